@@ -1,0 +1,220 @@
+"""Plain FP64 CPU oracle of the VLBM for MHD -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product path (the HIP library and its
+Python binding) never touches it, and it never touches the product path: the two
+share no code, header, table or constant.
+
+* ``vlbm_ref.c`` -- the lattice Boltzmann update of the paper (Sec. 2.2-2.3),
+  two-lattice push streaming, FP64, OpenMP over cells.
+* ``conv_ref.py`` -- the learned-correction network, restriction and gate in
+  FP64 numpy (plain shifted sums).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libvlbm_ref.so")
+
+KMAX = 26
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (-O2, IEEE semantics, OpenMP)."""
+    if force or not os.path.exists(_SO):
+        tmp = _SO + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
+             "-o", tmp, os.path.join(_HERE, "vlbm_ref.c"), "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+class Params(ctypes.Structure):
+    """Mirror of ``vref_params`` in ``vlbm_ref.h``."""
+
+    _fields_ = [
+        ("dim", ctypes.c_int32),
+        ("nx", ctypes.c_int32),
+        ("ny", ctypes.c_int32),
+        ("nz", ctypes.c_int32),
+        ("model", ctypes.c_int32),
+        ("powell", ctypes.c_int32),
+        ("divb_mode", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("gamma", ctypes.c_double),
+        ("s", ctypes.c_double),
+        ("w0", ctypes.c_double),
+        ("tau", ctypes.c_double * KMAX),
+        ("dt", ctypes.c_double),
+        ("mu", ctypes.c_double),
+        ("eta0", ctypes.c_double),
+        ("j_c", ctypes.c_double),
+        ("tau_M", ctypes.c_double),
+        ("tau_H", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build(force=True)
+        L = ctypes.CDLL(_SO)
+        P = ctypes.POINTER(Params)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.vref_nvars.argtypes = [P]
+        L.vref_ndirs.argtypes = [P]
+        L.vref_flux_source.argtypes = [P, dp, dp, dp, dp, dp]
+        L.vref_equilibrium.argtypes = [P, dp, dp]
+        L.vref_equilibrium.restype = None
+        L.vref_collide.argtypes = [P, dp, dp, dp]
+        L.vref_init.argtypes = [P, dp, dp]
+        L.vref_run.argtypes = [P, dp, dp, ctypes.c_int]
+        L.vref_moments.argtypes = [P, dp, dp, dp, dp]
+        _lib = L
+    return _lib
+
+
+class use_library:
+    """Temporarily route every call of this module through another build of the
+    oracle (used by the tests that plant a mistake in a copy of the oracle source
+    and check that the pins catch it)."""
+
+    def __init__(self, path):
+        self.path = path
+        self.saved = None
+
+    def __enter__(self):
+        global _lib, _SO
+        self.saved = (_lib, _SO)
+        _lib, _SO = None, self.path
+        return lib()
+
+    def __exit__(self, *exc):
+        global _lib, _SO
+        _lib, _SO = self.saved
+        return False
+
+
+def compile_variant(src_text: str, out_path: str) -> str:
+    """Compile a (modified) copy of the oracle source to ``out_path``."""
+    src = out_path + ".c"
+    with open(src, "w") as fh:
+        fh.write(src_text)
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                           "-I", _HERE, "-o", out_path, src, "-lm"])
+    return out_path
+
+
+def source_text() -> str:
+    with open(os.path.join(_HERE, "vlbm_ref.c")) as fh:
+        return fh.read()
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def make_params(dim=2, shape=(64, 64, 1), model=0, gamma=5.0 / 3.0, s=0.2, w0=None,
+                tau=0.6, powell=1, divb_mode=0, dt=0.0, mu=0.0, eta0=0.0, j_c=0.0,
+                tau_M=1.0, tau_H=1.0) -> Params:
+    p = Params()
+    p.dim = dim
+    p.nx, p.ny, p.nz = shape
+    p.model = model
+    p.powell = powell
+    p.divb_mode = divb_mode
+    p.gamma = gamma
+    p.s = s
+    p.w0 = (1.0 / 3.0 if dim == 2 else 0.25) if w0 is None else w0
+    if np.ndim(tau) == 0:
+        taus = np.full(KMAX, float(tau))
+    else:
+        t = [float(v) for v in tau]
+        taus = np.array(t + [t[-1]] * (KMAX - len(t)))
+    for k in range(KMAX):
+        p.tau[k] = float(taus[k])
+    p.dt, p.mu, p.eta0, p.j_c, p.tau_M, p.tau_H = dt, mu, eta0, j_c, tau_M, tau_H
+    return p
+
+
+def nvars(p):
+    return 26 if p.model == 1 else 8
+
+
+def ndirs(p):
+    return 2 * p.dim + 1
+
+
+def ncells(p):
+    return p.nx * p.ny * p.nz
+
+
+def init(p, Q):
+    """f := f^eq(Q); Q is [K, nz, ny, nx] or [K, N]; returns f [K, Q, N]."""
+    K, NQ, N = nvars(p), ndirs(p), ncells(p)
+    Q = np.ascontiguousarray(np.asarray(Q, np.float64).reshape(K, N))
+    f = np.empty((K, NQ, N), np.float64)
+    lib().vref_init(ctypes.byref(p), _ptr(Q), _ptr(f))
+    return f
+
+
+def run(p, f, nsteps):
+    """Advance populations f [K, Q, N] in place by nsteps; returns #unphysical cell-steps."""
+    assert f.dtype == np.float64 and f.flags["C_CONTIGUOUS"]
+    work = np.empty_like(f)
+    return lib().vref_run(ctypes.byref(p), _ptr(f), _ptr(work), int(nsteps))
+
+
+def moments(p, f):
+    """Returns (Q [K, N], dlat [N], totals [K+5])."""
+    K, N = nvars(p), ncells(p)
+    Q = np.empty((K, N), np.float64)
+    d = np.empty(N, np.float64)
+    t = np.empty(K + 5, np.float64)
+    lib().vref_moments(ctypes.byref(p), _ptr(np.ascontiguousarray(f)), _ptr(Q), _ptr(d), _ptr(t))
+    return Q, d, t
+
+
+def collide(p, fcell):
+    """One-cell collision: fcell [K, Q] -> (fstar [K, Q], dlat, bad)."""
+    fcell = np.ascontiguousarray(fcell, np.float64)
+    out = np.empty_like(fcell)
+    dl = ctypes.c_double(0.0)
+    bad = lib().vref_collide(ctypes.byref(p), _ptr(fcell), _ptr(out), ctypes.byref(dl))
+    return out, dl.value, bad
+
+
+def equilibrium(p, Qcell):
+    Qcell = np.ascontiguousarray(Qcell, np.float64)
+    out = np.empty((nvars(p), ndirs(p)), np.float64)
+    lib().vref_equilibrium(ctypes.byref(p), _ptr(Qcell), _ptr(out))
+    return out
+
+
+def flux_source(p, Qcell, J=None):
+    K = nvars(p)
+    Qcell = np.ascontiguousarray(Qcell, np.float64)
+    J = np.zeros((K, 3)) if J is None else np.ascontiguousarray(J, np.float64)
+    Phi = np.empty((K, 3))
+    S = np.empty(K)
+    dl = ctypes.c_double(0.0)
+    bad = lib().vref_flux_source(ctypes.byref(p), _ptr(Qcell), _ptr(J), _ptr(Phi), _ptr(S),
+                                 ctypes.byref(dl))
+    return Phi, S, dl.value, bad
+
+
+def num_threads():
+    return lib().vref_num_threads()

@@ -1,0 +1,320 @@
+/*
+ * Plain FP64 CPU oracle of the VLBM for MHD.  TEST INFRASTRUCTURE ONLY: it is
+ * loaded by the tests, the smoke check and the CPU-baseline leg of the
+ * benchmark, never by the product path.  See vlbm_ref.h for layout and ABI.
+ *
+ * Every function follows the paper ("Lattice Boltzmann Methods for Compressible
+ * (Magneto)hydrodynamics") in its own order and notation; readings of points the
+ * paper leaves open are marked READING and are the ones listed in the design notes.
+ */
+#include "vlbm_ref.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+int vref_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+int vref_nvars(const vref_params* p) { return p->model == 1 ? 26 : 8; }
+int vref_ndirs(const vref_params* p) { return 2 * p->dim + 1; }
+
+/* Lattice (Sec. 2.2; the paper's lattice table is not printed).
+ * READING: D2Q5/D3Q7 with rest weight w0 and w_i = (1-w0)/(2 dim) for the 2 dim
+ * moving directions, so that sum_i w_i = 1 and sum_i w_i e_i e_i = c_s^2 I with
+ * c_s^2 = (1-w0)/dim. */
+static double weight(const vref_params* p, int i) {
+  return i == 0 ? p->w0 : (1.0 - p->w0) / (2.0 * p->dim);
+}
+static double cs2(const vref_params* p) { return (1.0 - p->w0) / p->dim; }
+/* component a of direction i */
+static int edir(int i, int a) {
+  if (i == 0) return 0;
+  int axis = (i - 1) / 2;
+  if (axis != a) return 0;
+  return (i % 2 == 1) ? 1 : -1;
+}
+
+/* Sec. 2.3: state Q = (rho, rho u, e_tot, B [, G, H]) and its physical flux.
+ * Ideal part: Phi_rho = rho u; Phi_m = rho u (x) u + p_tot I - B (x) B;
+ * Phi_E = (e_tot + p_tot) u - B (u.B); Phi_B = u (x) B - B (x) u, written per
+ * component as Phi[B_a][b] = u_b B_a - B_b u_a so that d_t B_a + d_b Phi[B_a][b]
+ * is the induction equation.  Equation of state: p = (gamma-1)(e_tot - rho|u|^2/2
+ * - |B|^2/2), p_tot = p + |B|^2/2.
+ * Resistive part (Sec. 2.2.1 and the expanded state of Sec. 2.3): G_ab ~ tau_M d_a B_b
+ * and H_ab ~ tau_H d_a u_b are transported with fluxes G (x) u - I (x) B and
+ * H (x) u - I (x) u and relaxed by -G/tau_M, -H/tau_H.
+ * READING (garbled stress): viscous stress tau_v = mu (grad u + grad u^T), whose
+ * divergence is mu Lap u for a solenoidal flow; heat flux q = 0;
+ * eta(j) = eta0 (1 + (|j|/j_c)^2) (constant eta0 when j_c <= 0);
+ * j = curl B; the induction flux gains -eta d_b B_a. */
+int vref_flux_source(const vref_params* p, const double* Q, const double* J,
+                     double* Phi, double* S, double* dlat) {
+  const int K = vref_nvars(p);
+  const int d = p->dim;
+  const double g = p->gamma;
+  const double rho = Q[0];
+  const double m[3] = {Q[1], Q[2], Q[3]};
+  const double E = Q[4];
+  const double B[3] = {Q[5], Q[6], Q[7]};
+  double u[3];
+  for (int a = 0; a < 3; ++a) u[a] = m[a] / rho;
+  double uu = 0.0, BB = 0.0, uB = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    uu += u[a] * u[a];
+    BB += B[a] * B[a];
+    uB += u[a] * B[a];
+  }
+  const double pres = (g - 1.0) * (E - 0.5 * rho * uu - 0.5 * BB);
+  const double ptot = pres + 0.5 * BB;
+
+  for (int k = 0; k < K; ++k) {
+    S[k] = 0.0;
+    for (int b = 0; b < 3; ++b) Phi[3 * k + b] = 0.0;
+  }
+  for (int b = 0; b < 3; ++b) {
+    Phi[3 * 0 + b] = m[b];
+    for (int a = 0; a < 3; ++a)
+      Phi[3 * (1 + a) + b] = m[a] * u[b] + (a == b ? ptot : 0.0) - B[a] * B[b];
+    Phi[3 * 4 + b] = (E + ptot) * u[b] - B[b] * uB;
+    for (int a = 0; a < 3; ++a) Phi[3 * (5 + a) + b] = u[b] * B[a] - B[b] * u[a];
+  }
+
+  double divB_lat; /* lattice-unit divergence of B used by the Powell source */
+  if (p->model == 1) {
+    const double* G = Q + 8;  /* G[3a+b] ~ tau_M d_a B_b */
+    const double* H = Q + 17; /* H[3a+b] ~ tau_H d_a u_b */
+    double dB[3][3], du[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        dB[a][b] = G[3 * a + b] / p->tau_M;
+        du[a][b] = H[3 * a + b] / p->tau_H;
+      }
+    const double jc[3] = {dB[1][2] - dB[2][1], dB[2][0] - dB[0][2], dB[0][1] - dB[1][0]};
+    double eta = p->eta0;
+    if (p->j_c > 0.0) {
+      const double jj = jc[0] * jc[0] + jc[1] * jc[1] + jc[2] * jc[2];
+      eta = p->eta0 * (1.0 + jj / (p->j_c * p->j_c));
+    }
+    const double jxB[3] = {jc[1] * B[2] - jc[2] * B[1], jc[2] * B[0] - jc[0] * B[2],
+                           jc[0] * B[1] - jc[1] * B[0]};
+    double tv[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) tv[a][b] = p->mu * (du[a][b] + du[b][a]);
+    for (int b = 0; b < 3; ++b) {
+      for (int a = 0; a < 3; ++a) Phi[3 * (1 + a) + b] -= tv[a][b];
+      double utv = 0.0;
+      for (int a = 0; a < 3; ++a) utv += u[a] * tv[a][b];
+      Phi[3 * 4 + b] += -utv + eta * jxB[b];
+      for (int a = 0; a < 3; ++a) Phi[3 * (5 + a) + b] -= eta * dB[b][a];
+    }
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b)
+        for (int c = 0; c < 3; ++c) {
+          Phi[3 * (8 + 3 * a + b) + c] = G[3 * a + b] * u[c] - (c == a ? B[b] : 0.0);
+          Phi[3 * (17 + 3 * a + b) + c] = H[3 * a + b] * u[c] - (c == a ? u[b] : 0.0);
+        }
+    /* relaxation sources of the transported gradients, times the time step */
+    for (int q = 0; q < 9; ++q) {
+      S[8 + q] = -G[q] * p->dt / p->tau_M;
+      S[17 + q] = -H[q] * p->dt / p->tau_H;
+    }
+    if (p->divb_mode == 1) {
+      double tr = 0.0;
+      for (int a = 0; a < d; ++a) tr += dB[a][a];
+      divB_lat = tr * (p->dt / p->s); /* physical divergence times dx */
+    } else {
+      divB_lat = 0.0;
+      for (int a = 0; a < d; ++a) divB_lat += J[3 * (5 + a) + a] / p->tau[5 + a];
+      divB_lat *= -1.0 / cs2(p);
+    }
+  } else {
+    /* READING (div B for the 8-variable system): local non-equilibrium estimate.
+     * The first moment of the B_a set deviates from its equilibrium value s Phi[B_a]
+     * by about -tau c_s^2 grad B_a, and Phi[B_a][a] = 0, so
+     * div B ~ -(1/c_s^2) sum_a J[B_a][a] / tau_{B_a}. */
+    divB_lat = 0.0;
+    for (int a = 0; a < d; ++a) divB_lat += J[3 * (5 + a) + a] / p->tau[5 + a];
+    divB_lat *= -1.0 / cs2(p);
+  }
+  *dlat = divB_lat;
+
+  /* Powell source S = -(div B) (0, B, u.B, u) (Sec. 2.3); on the lattice the
+   * physical divergence is divB_lat / dx and the source is multiplied by dt. */
+  if (p->powell) {
+    const double c = -p->s * divB_lat;
+    for (int a = 0; a < 3; ++a) {
+      S[1 + a] += c * B[a];
+      S[5 + a] += c * u[a];
+    }
+    S[4] += c * uB;
+  }
+  int bad = !(rho > 0.0) || !(pres >= 0.0);
+  for (int k = 0; k < K; ++k)
+    if (!isfinite(Q[k])) bad = 1;
+  return bad;
+}
+
+/* Sec. 2.2: linear vector equilibrium f^eq_{k,i} = w_i (Q_k + c_i . Phi_k / c_s^2),
+ * with the lattice flux s Phi. */
+static void equilibrium_from_flux(const vref_params* p, const double* Q, const double* Phi,
+                                  double* feq) {
+  const int K = vref_nvars(p), NQ = vref_ndirs(p), d = p->dim;
+  const double c2 = cs2(p);
+  for (int k = 0; k < K; ++k)
+    for (int i = 0; i < NQ; ++i) {
+      double ephi = 0.0;
+      for (int a = 0; a < d; ++a) ephi += edir(i, a) * p->s * Phi[3 * k + a];
+      feq[k * NQ + i] = weight(p, i) * (Q[k] + ephi / c2);
+    }
+}
+
+void vref_equilibrium(const vref_params* p, const double* Q, double* feq) {
+  double Phi[VREF_KMAX * 3], S[VREF_KMAX], J[VREF_KMAX * 3], dl;
+  memset(J, 0, sizeof J);
+  vref_flux_source(p, Q, J, Phi, S, &dl);
+  equilibrium_from_flux(p, Q, Phi, feq);
+}
+
+/* Sec. 2.2 update with BGK collision and direct source injection (Sec. 3 intro):
+ * zeroth and first moments Q_k = sum_i f_{k,i}, J_k = sum_i e_i f_{k,i};
+ * fluxes and source from Q (and J for the div B estimate);
+ * f*_{k,i} = f_{k,i} - (f_{k,i} - f^eq_{k,i}) / tau_k + w_i S~_k. */
+int vref_collide(const vref_params* p, const double* f, double* fstar, double* dlat) {
+  const int K = vref_nvars(p), NQ = vref_ndirs(p), d = p->dim;
+  double Q[VREF_KMAX], J[VREF_KMAX * 3], Phi[VREF_KMAX * 3], S[VREF_KMAX];
+  double feq[VREF_KMAX * 7];
+  for (int k = 0; k < K; ++k) {
+    Q[k] = 0.0;
+    for (int a = 0; a < 3; ++a) J[3 * k + a] = 0.0;
+    for (int i = 0; i < NQ; ++i) {
+      Q[k] += f[k * NQ + i];
+      for (int a = 0; a < d; ++a) J[3 * k + a] += edir(i, a) * f[k * NQ + i];
+    }
+  }
+  double dl;
+  const int bad = vref_flux_source(p, Q, J, Phi, S, &dl);
+  equilibrium_from_flux(p, Q, Phi, feq);
+  for (int k = 0; k < K; ++k)
+    for (int i = 0; i < NQ; ++i) {
+      const double fo = f[k * NQ + i];
+      fstar[k * NQ + i] = fo - (fo - feq[k * NQ + i]) / p->tau[k] + weight(p, i) * S[k];
+    }
+  if (dlat) *dlat = dl;
+  return bad;
+}
+
+static long ncells(const vref_params* p) { return (long)p->nx * p->ny * p->nz; }
+
+/* periodic neighbour of cell (x,y,z) along direction i */
+static long neighbour(const vref_params* p, int x, int y, int z, int i) {
+  int c[3] = {x, y, z};
+  const int n[3] = {p->nx, p->ny, p->nz};
+  for (int a = 0; a < p->dim; ++a) c[a] = ((c[a] + edir(i, a)) % n[a] + n[a]) % n[a];
+  return (long)c[0] + (long)p->nx * ((long)c[1] + (long)p->ny * c[2]);
+}
+
+int vref_init(const vref_params* p, const double* Q, double* f) {
+  const int K = vref_nvars(p), NQ = vref_ndirs(p);
+  const long N = ncells(p);
+#pragma omp parallel for schedule(static)
+  for (long c = 0; c < N; ++c) {
+    double q[VREF_KMAX], feq[VREF_KMAX * 7];
+    for (int k = 0; k < K; ++k) q[k] = Q[k * N + c];
+    vref_equilibrium(p, q, feq);
+    for (int k = 0; k < K; ++k)
+      for (int i = 0; i < NQ; ++i) f[((long)k * NQ + i) * N + c] = feq[k * NQ + i];
+  }
+  return 0;
+}
+
+/* Sec. 2.2 update: collide every cell, then push f*_{k,i}(x) to x + e_i (periodic). */
+int vref_run(const vref_params* p, double* f, double* work, int nsteps) {
+  const int K = vref_nvars(p), NQ = vref_ndirs(p);
+  const long N = ncells(p);
+  int nbad = 0;
+  for (int step = 0; step < nsteps; ++step) {
+#pragma omp parallel for collapse(2) schedule(static) reduction(+ : nbad)
+    for (int z = 0; z < p->nz; ++z)
+      for (int y = 0; y < p->ny; ++y)
+        for (int x = 0; x < p->nx; ++x) {
+          const long c = (long)x + (long)p->nx * ((long)y + (long)p->ny * z);
+          double fc[VREF_KMAX * 7], fs[VREF_KMAX * 7];
+          for (int k = 0; k < K; ++k)
+            for (int i = 0; i < NQ; ++i) fc[k * NQ + i] = f[((long)k * NQ + i) * N + c];
+          nbad += vref_collide(p, fc, fs, NULL);
+          for (int i = 0; i < NQ; ++i) {
+            const long t = neighbour(p, x, y, z, i);
+            for (int k = 0; k < K; ++k) work[((long)k * NQ + i) * N + t] = fs[k * NQ + i];
+          }
+        }
+    memcpy(f, work, sizeof(double) * (size_t)K * NQ * N);
+  }
+  return nbad;
+}
+
+int vref_moments(const vref_params* p, const double* f, double* Q_out, double* dlat,
+                 double* totals) {
+  const int K = vref_nvars(p), NQ = vref_ndirs(p), d = p->dim;
+  const long N = ncells(p);
+  double* Qall = (double*)malloc(sizeof(double) * (size_t)K * N);
+  double* dall = (double*)malloc(sizeof(double) * (size_t)N);
+  if (!Qall || !dall) {
+    free(Qall);
+    free(dall);
+    return -1;
+  }
+  int nbad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : nbad)
+  for (long c = 0; c < N; ++c) {
+    double q[VREF_KMAX], J[VREF_KMAX * 3], Phi[VREF_KMAX * 3], S[VREF_KMAX], dl;
+    for (int k = 0; k < K; ++k) {
+      q[k] = 0.0;
+      for (int a = 0; a < 3; ++a) J[3 * k + a] = 0.0;
+      for (int i = 0; i < NQ; ++i) {
+        const double v = f[((long)k * NQ + i) * N + c];
+        q[k] += v;
+        for (int a = 0; a < d; ++a) J[3 * k + a] += edir(i, a) * v;
+      }
+      Qall[(long)k * N + c] = q[k];
+    }
+    nbad += vref_flux_source(p, q, J, Phi, S, &dl);
+    dall[c] = dl;
+  }
+  if (totals) {
+    for (int k = 0; k < K + 5; ++k) totals[k] = 0.0;
+    for (int k = 0; k < K; ++k)
+      for (long c = 0; c < N; ++c) totals[k] += Qall[(long)k * N + c];
+    for (long c = 0; c < N; ++c) {
+      totals[K] += dall[c];
+      totals[K + 1] += dall[c] * dall[c];
+      if (fabs(dall[c]) > totals[K + 2]) totals[K + 2] = fabs(dall[c]);
+    }
+    /* central-difference divergence of the moment field B, lattice units */
+    for (int z = 0; z < p->nz; ++z)
+      for (int y = 0; y < p->ny; ++y)
+        for (int x = 0; x < p->nx; ++x) {
+          double dv = 0.0;
+          for (int a = 0; a < d; ++a) {
+            const long cp = neighbour(p, x, y, z, 2 * a + 1);
+            const long cm = neighbour(p, x, y, z, 2 * a + 2);
+            dv += 0.5 * (Qall[(long)(5 + a) * N + cp] - Qall[(long)(5 + a) * N + cm]);
+          }
+          totals[K + 3] += dv * dv;
+        }
+    totals[K + 4] = nbad;
+  }
+  if (Q_out) memcpy(Q_out, Qall, sizeof(double) * (size_t)K * N);
+  if (dlat) memcpy(dlat, dall, sizeof(double) * (size_t)N);
+  free(Qall);
+  free(dall);
+  return nbad;
+}

@@ -1,0 +1,80 @@
+/*
+ * Plain FP64 CPU oracle of the vectorial lattice Boltzmann method (VLBM) for
+ * ideal compressible and resistive MHD.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load this library.  It shares no code,
+ * header, table or constant with the GPU library; it is written straight from
+ * the paper, in the paper's order, with plain loops and two-lattice push
+ * streaming (not the in-place scheme the GPU uses).
+ *
+ * Paper: "Lattice Boltzmann Methods for Compressible (Magneto)hydrodynamics",
+ * Sec. 2.2 (VLBM update, linear vector equilibrium, moments), Sec. 2.2.1
+ * (local moments evolution), Sec. 2.3 (MHD state, fluxes, equation of state,
+ * Powell source), Sec. 3 intro (BGK collision + direct source injection).
+ *
+ * Layout: moments Q[k][cell]; populations f[k][i][cell]; cell = x + nx*(y + ny*z).
+ * Directions: i = 0 rest, i = 2a+1 is +e_a, i = 2a+2 is -e_a (a = 0..dim-1).
+ */
+#ifndef VLBM_REF_H
+#define VLBM_REF_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VREF_KMAX 26
+
+typedef struct {
+  int32_t dim;        /* 2: D2Q5, 3: D3Q7 */
+  int32_t nx, ny, nz; /* nz must be 1 when dim == 2 */
+  int32_t model;      /* 0: ideal MHD (K = 8); 1: resistive MHD with G, H (K = 26) */
+  int32_t powell;     /* 1: Powell source injected, 0: off */
+  int32_t divb_mode;  /* 0: local non-equilibrium estimate of div B; 1: trace of G / tau_M */
+  int32_t reserved;
+  double gamma;       /* adiabatic index */
+  double s;           /* flux scale dt/dx: lattice flux = s * physical flux */
+  double w0;          /* rest weight; w_i = (1-w0)/(2 dim), c_s^2 = (1-w0)/dim */
+  double tau[VREF_KMAX]; /* lattice relaxation time per variable (> 0.5) */
+  double dt;          /* physical time step (resistive model sources) */
+  double mu, eta0, j_c, tau_M, tau_H; /* resistive model; j_c <= 0: constant eta */
+} vref_params;
+
+/* number of variables K and of directions Q */
+int vref_nvars(const vref_params* p);
+int vref_ndirs(const vref_params* p);
+
+/* Physical flux Phi[k][beta] (beta = 0..2) and lattice source S~[k] (Powell and,
+ * for the resistive model, the relaxation of G and H) of one cell.
+ * J[k][a] = first moment sum_i e_ia f_{k,i} of the cell's populations (used by the
+ * local div B estimate).  Writes the lattice div B estimate to *dlat.  Returns 0, or
+ * 1 if the cell is unphysical (rho <= 0, p < 0 or a non-finite value). */
+int vref_flux_source(const vref_params* p, const double* Q, const double* J,
+                     double* Phi /*[K][3]*/, double* S /*[K]*/, double* dlat);
+
+/* f^eq_{k,i} = w_i (Q_k + s e_i . Phi_k / c_s^2) at one cell. */
+void vref_equilibrium(const vref_params* p, const double* Q, double* feq /*[K][Q]*/);
+
+/* One BGK collision with direct source injection at one cell:
+ * fstar_{k,i} = f_{k,i} - (f_{k,i} - f^eq_{k,i}) / tau_k + w_i S~_k. */
+int vref_collide(const vref_params* p, const double* f /*[K][Q]*/, double* fstar, double* dlat);
+
+/* f := f^eq(Q) everywhere. Q is [K][N], f is [K][Q][N]. */
+int vref_init(const vref_params* p, const double* Q, double* f);
+
+/* nsteps collide + push-stream steps (periodic). work has the size of f. */
+int vref_run(const vref_params* p, double* f, double* work, int nsteps);
+
+/* Moments of f: Q_out [K][N] (may be NULL), dlat [N] (may be NULL), totals (may be
+ * NULL): [0..K-1] sum_x Q_k, [K] sum d, [K+1] sum d^2, [K+2] max |d|,
+ * [K+3] sum_x (central div B)^2, [K+4] number of unphysical cells. */
+int vref_moments(const vref_params* p, const double* f, double* Q_out, double* dlat,
+                 double* totals);
+
+int vref_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,171 @@
+"""Seeded synthetic inputs for the VLBM MHD workloads.
+
+This module is shared by the oracle tests and the GPU path.  It holds none of the
+lattice Boltzmann arithmetic: it only draws random fields and assembles the
+conserved state Q = (rho, rho u, e_tot, B [, G, H]) from primitive fields, using
+the definition of the total energy (internal + kinetic + magnetic).
+
+Layout of every returned state: float64 array [K, nz, ny, nx], x fastest.
+Variable order: 0 rho, 1-3 rho u, 4 e_tot, 5-7 B, 8-16 G (G[3a+b] ~ tau_M d_a B_b),
+17-25 H (H[3a+b] ~ tau_H d_a u_b).
+
+Workloads (sizes and statistics follow the workload definitions; no public
+dataset is involved):
+* ``fourier_2d``: 2D ideal MHD, rho = 1, p = 0.6, u and B sums of random
+  Fourier modes with integer wave vectors 1 <= |k| <= kmax, seeded phases, u
+  scaled to max |u| = amp, B the discrete central curl of a random vector
+  potential scaled to max |B| = amp (so the central divergence of B vanishes).
+* ``turbulence_3d``: 3D random solenoidal u and B, complex Gaussian modes with
+  1 <= |k| <= kmax, projected perpendicular to k, |u_k| ~ k^-2 (shell energy
+  ~ k^-2), normalised to given rms values; G and H set to their relaxed values
+  tau_M grad B, tau_H grad u (spectral derivatives).
+* ``planar_discontinuity_3d``: a slab with a seeded periodic normal separating
+  seeded left/right states, tanh-smoothed over 2 cells.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def conserved_from_primitive(rho, u, p, B, gamma):
+    """Q = (rho, rho u, e_tot, B) with e_tot = p/(gamma-1) + rho|u|^2/2 + |B|^2/2."""
+    rho = np.asarray(rho, np.float64)
+    u = np.asarray(u, np.float64)
+    B = np.asarray(B, np.float64)
+    shape = np.broadcast_shapes(rho.shape, u.shape[1:], np.shape(p), B.shape[1:])
+    Q = np.empty((8,) + shape, np.float64)
+    Q[0] = rho
+    Q[1:4] = rho * u
+    Q[4] = np.asarray(p) / (gamma - 1.0) + 0.5 * rho * (u * u).sum(0) + 0.5 * (B * B).sum(0)
+    Q[5:8] = B
+    return Q
+
+
+def _random_mode_field(rng, shape2d, kmax, ncomp):
+    """Sum of unit-amplitude Fourier modes 1 <= |k| <= kmax (half plane), random phases."""
+    ny, nx = shape2d
+    y, x = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    modes = []
+    for ky in range(0, kmax + 1):
+        for kx in range(-kmax, kmax + 1):
+            if ky == 0 and kx <= 0:
+                continue
+            if 1 <= kx * kx + ky * ky <= kmax * kmax:
+                modes.append((kx, ky))
+    out = np.zeros((ncomp, ny, nx))
+    for c in range(ncomp):
+        phases = rng.uniform(0.0, 2.0 * np.pi, size=len(modes))
+        for (kx, ky), ph in zip(modes, phases):
+            out[c] += np.cos(2.0 * np.pi * (kx * x / nx + ky * y / ny) + ph)
+    return out
+
+
+def _central_curl_2d(A):
+    """Discrete central curl of A(x, y) (3 components, d/dz = 0), periodic."""
+    def dx(f):
+        return 0.5 * (np.roll(f, -1, axis=1) - np.roll(f, 1, axis=1))
+
+    def dy(f):
+        return 0.5 * (np.roll(f, -1, axis=0) - np.roll(f, 1, axis=0))
+
+    return np.stack([dy(A[2]), -dx(A[2]), dx(A[1]) - dy(A[0])])
+
+
+def fourier_2d(n=64, seed=0, kmax=4, amp=0.1, rho0=1.0, p0=0.6, gamma=5.0 / 3.0):
+    """2D ideal-MHD state [8, 1, n, n] (random Fourier modes, central div B = 0)."""
+    rng = np.random.default_rng(seed)
+    u = _random_mode_field(rng, (n, n), kmax, 3)
+    u *= amp / np.sqrt((u * u).sum(0)).max()
+    A = _random_mode_field(rng, (n, n), kmax, 3)
+    B = _central_curl_2d(A)
+    B *= amp / np.sqrt((B * B).sum(0)).max()
+    rho = np.full((n, n), rho0)
+    Q = conserved_from_primitive(rho, u, p0, B, gamma)
+    return Q[:, None, :, :].copy()
+
+
+def _solenoidal_spectral(rng, n, kmax, rms):
+    k1 = np.fft.fftfreq(n, d=1.0 / n)
+    kz, ky, kx = np.meshgrid(k1, k1, k1, indexing="ij")
+    kk = np.sqrt(kx * kx + ky * ky + kz * kz)
+    mask = (kk >= 1.0) & (kk <= kmax)
+    amp = np.zeros_like(kk)
+    amp[mask] = kk[mask] ** -2.0
+    vec = (rng.standard_normal((3, n, n, n)) + 1j * rng.standard_normal((3, n, n, n))) * amp
+    kvec = np.stack([kx, ky, kz])
+    k2 = np.where(kk > 0, kk * kk, 1.0)
+    kdotv = (kvec * vec).sum(0)
+    vec = vec - kvec * kdotv / k2
+    field = np.real(np.fft.ifftn(vec, axes=(1, 2, 3)))
+    field *= rms / np.sqrt((field * field).sum(0).mean())
+    fhat = np.fft.fftn(field, axes=(1, 2, 3))
+    # spectral gradient grad[a][b] = d_a field_b on the domain [0, 2 pi)^3
+    grad = np.empty((3, 3, n, n, n))
+    for a, ka in enumerate((kx, ky, kz)):
+        for b in range(3):
+            grad[a, b] = np.real(np.fft.ifftn(1j * ka * fhat[b]))
+    return field, grad
+
+
+def turbulence_3d(n=256, seed=1, kmax=8, u_rms=0.05, b_rms=0.05, rho0=1.0, p0=0.6,
+                  gamma=5.0 / 3.0, tau_M=0.01, tau_H=0.01, dtype=np.float64):
+    """3D resistive-MHD state [26, n, n, n] on [0, 2 pi)^3 (random solenoidal u, B)."""
+    rng = np.random.default_rng(seed)
+    u, gu = _solenoidal_spectral(rng, n, kmax, u_rms)
+    B, gB = _solenoidal_spectral(rng, n, kmax, b_rms)
+    Q = np.empty((26, n, n, n), dtype)
+    Q[:8] = conserved_from_primitive(np.full((n, n, n), rho0), u, p0, B, gamma)
+    Q[8:17] = (tau_M * gB).reshape(9, n, n, n)
+    Q[17:26] = (tau_H * gu).reshape(9, n, n, n)
+    return Q
+
+
+def planar_discontinuity_3d(n=512, seed=2, width=2.0, gamma=5.0 / 3.0, dtype=np.float64,
+                            shape=None):
+    """3D ideal-MHD slab: seeded integer normal k in {-2..2}^3 \\ 0, slab
+    frac(k.x/n) in [1/4, 3/4), rho, p ~ U[0.1, 1], |B| ~ U[0, 1] with seeded
+    directions on either side, u = 0, tanh profile of the given width."""
+    rng = np.random.default_rng(seed)
+    while True:
+        kvec = rng.integers(-2, 3, size=3)
+        if np.any(kvec != 0):
+            break
+    rhoL, rhoR = rng.uniform(0.1, 1.0, 2)
+    pL, pR = rng.uniform(0.1, 1.0, 2)
+    bL, bR = rng.uniform(0.0, 1.0, 2)
+    dL = rng.standard_normal(3)
+    dR = rng.standard_normal(3)
+    BL = bL * dL / np.linalg.norm(dL)
+    BR = bR * dR / np.linalg.norm(dR)
+    nz, ny, nx = (n, n, n) if shape is None else shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    # phase along the normal in units of one period; the slab is phase in [1/4, 3/4)
+    phase = kvec[0] * x / nx + kvec[1] * y / ny + kvec[2] * z / nz
+    xi = phase - np.floor(phase)
+    # distance (in cells) to the two interfaces along the normal direction
+    period = 1.0 / np.sqrt((kvec[0] / nx) ** 2 + (kvec[1] / ny) ** 2 + (kvec[2] / nz) ** 2)
+    d1 = (xi - 0.25) * period
+    d2 = (0.75 - xi) * period
+    inside = 0.25 * (1 + np.tanh(d1 / width)) * (1 + np.tanh(d2 / width))
+    w = inside  # 1 inside the slab (right state), 0 outside (left state)
+    rho = rhoL + (rhoR - rhoL) * w
+    p = pL + (pR - pL) * w
+    B = np.stack([BL[a] + (BR[a] - BL[a]) * w for a in range(3)])
+    u = np.zeros_like(B)
+    Q = conserved_from_primitive(rho, u, p, B, gamma).astype(dtype)
+    info = dict(k=kvec.tolist(), rho=(rhoL, rhoR), p=(pL, pR), BL=BL.tolist(), BR=BR.tolist())
+    return Q, info
+
+
+def uniform_state(shape, rho=1.0, u=(0.0, 0.0, 0.0), p=0.6, B=(0.0, 0.0, 0.0),
+                  gamma=5.0 / 3.0, K=8):
+    """Spatially uniform state [K, nz, ny, nx] (G = H = 0 for K = 26)."""
+    nz, ny, nx = shape
+    one = np.ones((nz, ny, nx))
+    Q8 = conserved_from_primitive(rho * one, np.array(u)[:, None, None, None] * one, p,
+                                  np.array(B)[:, None, None, None] * one, gamma)
+    if K == 8:
+        return Q8
+    Q = np.zeros((K, nz, ny, nx))
+    Q[:8] = Q8
+    return Q
