@@ -1,0 +1,170 @@
+/*
+ * vlbm.h -- C ABI of the MI355X (gfx950) library of the vectorial lattice
+ * Boltzmann method (VLBM) for ideal compressible and resistive MHD.
+ *
+ * Method (paper: "Lattice Boltzmann Methods for Compressible (Magneto)hydrodynamics"):
+ *   every conserved variable Q_k has its own population set f_{k,i} on a D2Q5 or
+ *   D3Q7 lattice (Sec. 2.2, VLBM update); each set is relaxed by BGK toward the
+ *   linear vector equilibrium f^eq_{k,i} = w_i (Q_k + c_i . Phi_k / c_s^2) whose
+ *   first moment carries the physical flux Phi_k (Sec. 2.2, equilibrium and
+ *   moments); the Powell source S = -(div B)(0, B, u.B, u) is injected directly
+ *   (Sec. 2.3, Powell correction; Sec. 3 intro, BGK with direct injection); the
+ *   populations then stream to the neighbour along c_i.  The ideal system carries
+ *   Q = (rho, rho u, e_tot, B) (Sec. 2.3, ideal MHD); the resistive system adds the
+ *   transported gradient tensors G ~ tau_M grad B and H ~ tau_H grad u
+ *   (Sec. 2.2.1 local moments evolution; Sec. 2.3 expanded state and resistive MHD).
+ *
+ * Conventions
+ *   - Every function returns a vlbm_status; errors are negative.  No exception or
+ *     abort crosses the ABI.  vlbm_last_error() gives the context's last message.
+ *   - Lattice units: dx = dt = 1 on the lattice; the lattice flux is s * Phi with
+ *     s = flux_scale = dt/dx in the caller's physical units; sources are multiplied
+ *     by the physical dt (Powell: by s times the lattice divergence).
+ *   - Moment fields are SoA [K][nz][ny][nx] (x fastest).  Variable order k:
+ *     0 rho; 1-3 rho u; 4 e_tot; 5-7 B; resistive only: 8-16 G (G[3a+b] ~ tau_M d_a B_b),
+ *     17-25 H (H[3a+b] ~ tau_H d_a u_b).
+ *   - Direction order i: 0 rest, then +x, -x, +y, -y (, +z, -z).
+ *   - Device pointers are HIP device addresses on the current device; host
+ *     pointers are ordinary memory.  The caller owns every buffer it passes,
+ *     including a borrowed population buffer; the context owns everything else.
+ *   - vlbm_step is asynchronous on the context's stream (no host sync).
+ *     vlbm_moments, vlbm_gather_cells, vlbm_get_populations and
+ *     vlbm_set_populations synchronise that stream.
+ *   - One context must not be used from two host threads at once.
+ */
+#ifndef VLBM_H
+#define VLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vlbm_ctx vlbm_ctx;
+
+typedef enum {
+  VLBM_OK = 0,
+  VLBM_ERR_ARG = -1,       /* invalid argument or parameter */
+  VLBM_ERR_OOM = -2,       /* device allocation failed */
+  VLBM_ERR_HIP = -3,       /* a HIP runtime call failed */
+  VLBM_ERR_STATE = -4,     /* call out of order (e.g. step before init) */
+  VLBM_ERR_NONFINITE = -5  /* moments found rho <= 0, p < 0 or a non-finite value */
+} vlbm_status;
+
+typedef enum { VLBM_D2Q5 = 0, VLBM_D3Q7 = 1 } vlbm_lattice;
+typedef enum { VLBM_IDEAL = 0, VLBM_RESISTIVE = 1 } vlbm_model; /* K = 8 or 26 */
+
+/* Population storage in HBM.  F64 and F32 store f itself (F64 computes in FP64,
+ * F32 in FP32).  F16DEV and BF16DEV store h = (f - f_rest[k][i]) / (w_i sigma_k),
+ * rounded to nearest even, and collide in FP32; f_rest = f^eq(Q_rest). */
+typedef enum { VLBM_F64 = 0, VLBM_F32 = 1, VLBM_F16DEV = 2, VLBM_BF16DEV = 3 } vlbm_storage;
+
+/* Boundary kind per domain face (x-, x+, y-, y+, z-, z+).  PERIODIC wraps; the
+ * equilibrium boundaries of Sec. 2.4 (static boundaries) assign f := f^eq of a
+ * Dirichlet state (INFLOW_EQ, the inflow_Q state) or of the state copied from the
+ * next cell inward along the face normal (ZERO_GRAD).  Non-periodic faces are
+ * accepted only by the D3Q7 ideal model. */
+typedef enum { VLBM_BC_PERIODIC = 0, VLBM_BC_INFLOW_EQ = 1, VLBM_BC_ZERO_GRAD = 2 } vlbm_bc;
+
+#define VLBM_KMAX 26
+#define VLBM_PARAMS_VERSION 1
+
+typedef struct {
+  uint32_t struct_size;   /* sizeof(vlbm_params); checked for ABI versioning */
+  int32_t lattice;        /* vlbm_lattice */
+  int32_t nx, ny, nz;     /* lattice extent; nz = 1 for D2Q5; each >= 1 */
+  int32_t model;          /* vlbm_model (resistive requires D3Q7) */
+  int32_t storage;        /* vlbm_storage */
+  int32_t powell;         /* 1: inject the Powell source (Sec. 2.3), 0: off */
+  int32_t divb_mode;      /* div B used by the Powell source: 0 local non-equilibrium
+                             estimate -(1/c_s^2) sum_a J[B_a][a] / tau_{B_a};
+                             1 (resistive only) trace of G / tau_M */
+  double gamma;           /* adiabatic index of the equation of state (Sec. 2.3) */
+  double flux_scale;      /* s = dt/dx (> 0) */
+  double w0;              /* rest weight; w_i = (1 - w0)/(2 dim), c_s^2 = (1 - w0)/dim;
+                             0 selects 1/3 (D2Q5) or 1/4 (D3Q7) */
+  double tau[VLBM_KMAX];  /* lattice relaxation time per variable, each > 0.5 */
+  double dt;              /* physical time step (resistive sources) */
+  double mu, eta0, j_c, tau_M, tau_H; /* resistive: viscosity, resistivity
+                             eta = eta0 (1 + (|j|/j_c)^2) (j_c <= 0: constant),
+                             relaxation times of G and H (> 0) */
+  int32_t bc[6];          /* vlbm_bc per face; all PERIODIC for the periodic configs */
+  double inflow_Q[8];     /* Dirichlet state of INFLOW_EQ faces (conserved variables) */
+  const double* rest_Q;   /* host, K values: Q_rest of the FP16/BF16 codec; NULL: the
+                             domain mean of the Q given to vlbm_init_fields, with
+                             rho u (and G, H) set to zero */
+  double scale[VLBM_KMAX];/* codec sigma_k (> 0); 0: smallest power of two >=
+                             max |Q_k - Q_rest,k| over the initial field (1 if 0) */
+  void* pop_buffer;       /* optional borrowed device buffer for the populations */
+  size_t pop_bytes;       /* its size in bytes (>= vlbm_population_bytes()) */
+  void* stream;           /* hipStream_t for all work; NULL: the null stream */
+  int32_t block_x;        /* threads per block along x for the sweep; 0: default */
+  int32_t reserved;
+} vlbm_params;
+
+/* Fill *p with defaults (periodic, F32, gamma 5/3, s 0.2, tau 0.6, Powell on). */
+vlbm_status vlbm_params_default(vlbm_params* p);
+
+/* Bytes of the population buffer for these parameters (K*Q padded planes). */
+vlbm_status vlbm_population_bytes(const vlbm_params* p, size_t* bytes);
+
+/* Create a context: validate p, allocate (or adopt) the population buffer and the
+ * small FP64 reduction buffers.  No kernel runs.  *out is NULL on error. */
+vlbm_status vlbm_create(const vlbm_params* p, vlbm_ctx** out);
+
+/* f := f^eq(Q) in every cell (natural layout), step counter := 0.  Q is SoA
+ * [K][nz][ny][nx], FP64 (q_is_f32 = 0) or FP32 (q_is_f32 = 1), on the device
+ * (q_on_device = 1) or the host.  Also fixes the FP16/BF16 codec tables (see
+ * vlbm_params.rest_Q / scale).  Synchronises. */
+vlbm_status vlbm_init_fields(vlbm_ctx* c, const void* Q, int q_on_device, int q_is_f32);
+
+/* Advance n >= 0 steps: per cell, gather the populations (in-place AA pattern),
+ * moments, equation of state, fluxes, div B estimate, Powell source, BGK with
+ * direct injection, scatter (Sec. 2.2-2.3).  Asynchronous on the context stream. */
+vlbm_status vlbm_step(vlbm_ctx* c, int32_t n);
+
+/* Moments of the current populations: Q_out SoA [K][nz][ny][nx] (FP64 or FP32,
+ * host or device; may be NULL) and totals (host, may be NULL, K + 5 doubles):
+ * [0..K-1] sum_x Q_k; [K] sum_x d; [K+1] sum_x d^2; [K+2] max_x |d|, with d the
+ * lattice-unit div B estimate of the Powell source; [K+3] sum_x (central-difference
+ * div B of the moment field)^2; [K+4] number of cells with rho <= 0, p < 0 or a
+ * non-finite moment.  Accumulated in FP64.  Synchronises.  Returns
+ * VLBM_ERR_NONFINITE (after filling the outputs) if [K+4] > 0 or a total is not finite. */
+vlbm_status vlbm_moments(vlbm_ctx* c, void* Q_out, int out_on_device, int out_is_f32,
+                         double* totals);
+
+/* Decoded pre-collision populations f_{k,i} at the given cells (host arrays):
+ * cells[n] linear indices x + nx (y + ny z); out[n][K][Q] FP64.  Synchronises. */
+vlbm_status vlbm_gather_cells(vlbm_ctx* c, const int64_t* cells, int64_t n, double* out);
+
+/* Raw population buffer (storage type, internal padded layout) to / from host
+ * memory, with the in-place pattern's parity and the step counter: a bitwise
+ * checkpoint.  bytes must equal vlbm_population_bytes(). */
+vlbm_status vlbm_get_populations(vlbm_ctx* c, void* dst, size_t bytes, int32_t* parity,
+                                 int64_t* step);
+vlbm_status vlbm_set_populations(vlbm_ctx* c, const void* src, size_t bytes, int32_t parity,
+                                 int64_t step);
+
+/* The codec reference state and scales in use (host arrays of K doubles). */
+vlbm_status vlbm_get_codec(const vlbm_ctx* c, double* rest_Q, double* scale);
+
+/* Number of steps taken since vlbm_init_fields. */
+vlbm_status vlbm_get_step(const vlbm_ctx* c, int64_t* step);
+
+/* Free everything the context owns (never a borrowed buffer).  NULL-safe. */
+void vlbm_destroy(vlbm_ctx* c);
+
+/* Last error message of the context ("" if none); NULL context: last create error. */
+const char* vlbm_last_error(const vlbm_ctx* c);
+
+/* Plain device-to-device copy of `bytes` bytes (multiple of 16, 16-byte aligned
+ * device pointers) with the library's streaming copy kernel, on `stream`: the
+ * measured-bandwidth denominator of the roofline.  Asynchronous. */
+vlbm_status vlbm_copy_kernel(void* dst, const void* src, size_t bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VLBM_H */

@@ -77,6 +77,7 @@ def lib():
         L.vref_equilibrium.argtypes = [P, dp, dp]
         L.vref_equilibrium.restype = None
         L.vref_collide.argtypes = [P, dp, dp, dp]
+        L.vref_collide_many.argtypes = [P, ctypes.c_long, dp, dp]
         L.vref_init.argtypes = [P, dp, dp]
         L.vref_run.argtypes = [P, dp, dp, ctypes.c_int]
         L.vref_moments.argtypes = [P, dp, dp, dp, dp]
@@ -195,6 +196,14 @@ def collide(p, fcell):
     dl = ctypes.c_double(0.0)
     bad = lib().vref_collide(ctypes.byref(p), _ptr(fcell), _ptr(out), ctypes.byref(dl))
     return out, dl.value, bad
+
+
+def collide_many(p, fcells):
+    """Collision of n independent cells: fcells [n, K, Q] -> fstar [n, K, Q]."""
+    fcells = np.ascontiguousarray(fcells, np.float64)
+    out = np.empty_like(fcells)
+    lib().vref_collide_many(ctypes.byref(p), fcells.shape[0], _ptr(fcells), _ptr(out))
+    return out
 
 
 def equilibrium(p, Qcell):

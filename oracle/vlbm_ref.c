@@ -212,6 +212,15 @@ int vref_collide(const vref_params* p, const double* f, double* fstar, double* d
   return bad;
 }
 
+/* vref_collide on n independent cells: f and fstar are [n][K][Q]. */
+int vref_collide_many(const vref_params* p, long n, const double* f, double* fstar) {
+  const int KQ = vref_nvars(p) * vref_ndirs(p);
+  int nbad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : nbad)
+  for (long j = 0; j < n; ++j) nbad += vref_collide(p, f + j * KQ, fstar + j * KQ, NULL);
+  return nbad;
+}
+
 static long ncells(const vref_params* p) { return (long)p->nx * p->ny * p->nz; }
 
 /* periodic neighbour of cell (x,y,z) along direction i */

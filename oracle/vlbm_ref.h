@@ -60,6 +60,9 @@ void vref_equilibrium(const vref_params* p, const double* Q, double* feq /*[K][Q
  * fstar_{k,i} = f_{k,i} - (f_{k,i} - f^eq_{k,i}) / tau_k + w_i S~_k. */
 int vref_collide(const vref_params* p, const double* f /*[K][Q]*/, double* fstar, double* dlat);
 
+/* vref_collide on n independent cells; f and fstar are [n][K][Q]. */
+int vref_collide_many(const vref_params* p, long n, const double* f, double* fstar);
+
 /* f := f^eq(Q) everywhere. Q is [K][N], f is [K][Q][N]. */
 int vref_init(const vref_params* p, const double* Q, double* f);
 

@@ -1,0 +1,484 @@
+// C ABI of the VLBM MHD library (include/vlbm.h): parameter validation, context
+// and buffer ownership, codec set-up, and stream-ordered launches of the kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "vlbm.h"
+#include "vlbm_kernels.h"
+
+using namespace vlbm;
+
+struct vlbm_ctx {
+  vlbm_params p{};
+  int D = 0, K = 0, NQ = 0, esize = 0;
+  long long N = 0, stride = 0;
+  size_t pop_bytes = 0;
+  void* f = nullptr;
+  bool owned = false;
+  hipStream_t stream = nullptr;
+  Phys ph{};
+  Codec cd{};
+  Grid g{};
+  Launch L{};
+  double rest_Q[KMAX] = {};
+  double scale[KMAX] = {};
+  bool rest_given = false;
+  int nblk = 0;
+  double* d_partial = nullptr;   // [nblk][K+5]
+  double* d_partial2 = nullptr;  // [nblk]
+  double* d_totals = nullptr;    // [K+5] totals, then 2 x KMAX codec scratch
+  double* d_Q = nullptr;         // [K][N] moments scratch (lazy)
+  long long step = 0;
+  bool initialized = false;
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+vlbm_status fail(vlbm_ctx* c, vlbm_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c)
+    c->err = buf;
+  else
+    g_create_err = buf;
+  return s;
+}
+
+vlbm_status hip_fail(vlbm_ctx* c, hipError_t e, const char* what) {
+  return fail(c, e == hipErrorOutOfMemory ? VLBM_ERR_OOM : VLBM_ERR_HIP, "%s: %s", what,
+              hipGetErrorString(e));
+}
+
+#define VLBM_HIP(c, call)                              \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return hip_fail(c, e_, #call); \
+  } while (0)
+
+int dim_of(int lattice) { return lattice == VLBM_D3Q7 ? 3 : 2; }
+int nvars_of(int model) { return model == VLBM_RESISTIVE ? 26 : 8; }
+int esize_of(int storage) {
+  switch (storage) {
+    case VLBM_F64: return 8;
+    case VLBM_F32: return 4;
+    default: return 2;
+  }
+}
+
+// plane stride in elements: whole planes rounded up to 256-byte multiples
+long long plane_stride(long long N, int esize) {
+  const long long bytes = (N * esize + 255) / 256 * 256;
+  return bytes / esize;
+}
+
+vlbm_status validate(const vlbm_params* p) {
+  if (!p) return fail(nullptr, VLBM_ERR_ARG, "params is NULL");
+  if (p->struct_size != sizeof(vlbm_params))
+    return fail(nullptr, VLBM_ERR_ARG, "params.struct_size %u != %zu (ABI mismatch)", p->struct_size,
+                sizeof(vlbm_params));
+  if (p->lattice != VLBM_D2Q5 && p->lattice != VLBM_D3Q7)
+    return fail(nullptr, VLBM_ERR_ARG, "unknown lattice %d", p->lattice);
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1)
+    return fail(nullptr, VLBM_ERR_ARG, "lattice extent %d x %d x %d", p->nx, p->ny, p->nz);
+  if (p->lattice == VLBM_D2Q5 && p->nz != 1) return fail(nullptr, VLBM_ERR_ARG, "D2Q5 needs nz == 1");
+  const long long N = (long long)p->nx * p->ny * p->nz;
+  if (N >= (1LL << 31)) return fail(nullptr, VLBM_ERR_ARG, "%lld cells exceed 2^31 - 1", N);
+  if (plane_stride(N, esize_of(p->storage)) * esize_of(p->storage) >= (1LL << 32))
+    return fail(nullptr, VLBM_ERR_ARG, "one population plane would exceed 4 GiB");
+  if (p->model != VLBM_IDEAL && p->model != VLBM_RESISTIVE)
+    return fail(nullptr, VLBM_ERR_ARG, "unknown model %d", p->model);
+  if (p->model == VLBM_RESISTIVE && p->lattice != VLBM_D3Q7)
+    return fail(nullptr, VLBM_ERR_ARG, "the resistive model needs D3Q7");
+  if (p->storage < VLBM_F64 || p->storage > VLBM_BF16DEV)
+    return fail(nullptr, VLBM_ERR_ARG, "unknown storage %d", p->storage);
+  if (!(p->gamma > 1.0) || !std::isfinite(p->gamma)) return fail(nullptr, VLBM_ERR_ARG, "gamma must be > 1");
+  if (!(p->flux_scale > 0.0) || !std::isfinite(p->flux_scale))
+    return fail(nullptr, VLBM_ERR_ARG, "flux_scale must be > 0");
+  if (!(p->w0 >= 0.0 && p->w0 < 1.0)) return fail(nullptr, VLBM_ERR_ARG, "w0 must be in [0, 1)");
+  const int K = nvars_of(p->model);
+  for (int k = 0; k < K; ++k)
+    if (!(p->tau[k] > 0.5) || !std::isfinite(p->tau[k]))
+      return fail(nullptr, VLBM_ERR_ARG, "tau[%d] = %g must be > 0.5", k, p->tau[k]);
+  if (p->powell != 0 && p->powell != 1) return fail(nullptr, VLBM_ERR_ARG, "powell must be 0 or 1");
+  if (p->divb_mode != 0 && !(p->divb_mode == 1 && p->model == VLBM_RESISTIVE))
+    return fail(nullptr, VLBM_ERR_ARG, "divb_mode %d not valid for this model", p->divb_mode);
+  if (p->model == VLBM_RESISTIVE) {
+    if (!(p->tau_M > 0.0) || !(p->tau_H > 0.0) || !(p->dt > 0.0))
+      return fail(nullptr, VLBM_ERR_ARG, "resistive model needs dt, tau_M, tau_H > 0");
+    if (!(p->mu >= 0.0) || !(p->eta0 >= 0.0)) return fail(nullptr, VLBM_ERR_ARG, "mu, eta0 must be >= 0");
+  }
+  for (int f = 0; f < 6; ++f)
+    if (p->bc[f] != VLBM_BC_PERIODIC)
+      return fail(nullptr, VLBM_ERR_ARG, "face %d: only periodic boundaries are handled by this sweep", f);
+  if (p->block_x != 0 && (p->block_x < 64 || p->block_x > 256 || p->block_x % 64 != 0))
+    return fail(nullptr, VLBM_ERR_ARG, "block_x must be 64, 128, 192 or 256");
+  if (p->rest_Q)
+    for (int k = 0; k < K; ++k)
+      if (!std::isfinite(p->rest_Q[k])) return fail(nullptr, VLBM_ERR_ARG, "rest_Q[%d] not finite", k);
+  for (int k = 0; k < K; ++k)
+    if (!(p->scale[k] >= 0.0) || !std::isfinite(p->scale[k]))
+      return fail(nullptr, VLBM_ERR_ARG, "scale[%d] must be >= 0", k);
+  return VLBM_OK;
+}
+
+// smallest power of two >= v (1 for v == 0)
+double pow2_at_least(double v) {
+  if (!(v > 0.0)) return 1.0;
+  int e;
+  const double m = std::frexp(v, &e);  // v = m 2^e, m in [0.5, 1)
+  return m == 0.5 ? std::ldexp(1.0, e - 1) : std::ldexp(1.0, e);
+}
+
+// FP16/BF16 codec table: f_rest = f^eq(Q_rest), scale w_i sigma_k.
+void build_codec(vlbm_ctx* c) {
+  std::memset(&c->cd, 0, sizeof c->cd);
+  if (c->p.storage != VLBM_F16DEV && c->p.storage != VLBM_BF16DEV) return;
+  double P[KMAX][3], S[KMAX], dl, Jb[3] = {0, 0, 0};
+  if (c->D == 2)
+    flux_source<double, 2, 0>(c->rest_Q, Jb, c->ph, P, S, dl);
+  else if (c->p.model == VLBM_RESISTIVE)
+    flux_source<double, 3, 1>(c->rest_Q, Jb, c->ph, P, S, dl);
+  else
+    flux_source<double, 3, 0>(c->rest_Q, Jb, c->ph, P, S, dl);
+  for (int k = 0; k < c->K; ++k)
+    for (int i = 0; i < c->NQ; ++i) {
+      const double w = i == 0 ? c->ph.w0 : c->ph.wi;
+      double fr;
+      if (c->D == 2)
+        fr = feq_dir<double, 2>(c->rest_Q[k], P[k], i, c->ph.w0, c->ph.wi);
+      else
+        fr = feq_dir<double, 3>(c->rest_Q[k], P[k], i, c->ph.w0, c->ph.wi);
+      c->cd.rest[k * c->NQ + i] = (float)fr;
+      c->cd.sc[k * c->NQ + i] = (float)(w * c->scale[k]);
+      c->cd.isc[k * c->NQ + i] = (float)(1.0 / (w * c->scale[k]));
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+vlbm_status vlbm_params_default(vlbm_params* p) {
+  if (!p) return VLBM_ERR_ARG;
+  std::memset(p, 0, sizeof *p);
+  p->struct_size = sizeof(vlbm_params);
+  p->lattice = VLBM_D2Q5;
+  p->nx = p->ny = 64;
+  p->nz = 1;
+  p->model = VLBM_IDEAL;
+  p->storage = VLBM_F32;
+  p->powell = 1;
+  p->gamma = 5.0 / 3.0;
+  p->flux_scale = 0.2;
+  for (int k = 0; k < VLBM_KMAX; ++k) p->tau[k] = 0.6;
+  p->tau_M = p->tau_H = 1.0;
+  return VLBM_OK;
+}
+
+vlbm_status vlbm_population_bytes(const vlbm_params* p, size_t* bytes) {
+  vlbm_status s = validate(p);
+  if (s != VLBM_OK) return s;
+  if (!bytes) return VLBM_ERR_ARG;
+  const int D = dim_of(p->lattice), K = nvars_of(p->model), es = esize_of(p->storage);
+  const long long N = (long long)p->nx * p->ny * p->nz;
+  *bytes = (size_t)K * (2 * D + 1) * plane_stride(N, es) * es;
+  return VLBM_OK;
+}
+
+vlbm_status vlbm_create(const vlbm_params* p, vlbm_ctx** out) {
+  if (!out) return fail(nullptr, VLBM_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  vlbm_status s = validate(p);
+  if (s != VLBM_OK) return s;
+  vlbm_ctx* c = new (std::nothrow) vlbm_ctx();
+  if (!c) return fail(nullptr, VLBM_ERR_OOM, "host allocation failed");
+  c->p = *p;
+  c->p.rest_Q = nullptr;
+  c->D = dim_of(p->lattice);
+  c->K = nvars_of(p->model);
+  c->NQ = 2 * c->D + 1;
+  c->esize = esize_of(p->storage);
+  c->N = (long long)p->nx * p->ny * p->nz;
+  c->stride = plane_stride(c->N, c->esize);
+  c->pop_bytes = (size_t)c->K * c->NQ * c->stride * c->esize;
+  c->stream = static_cast<hipStream_t>(p->stream);
+  if (p->rest_Q) {
+    for (int k = 0; k < c->K; ++k) c->rest_Q[k] = p->rest_Q[k];
+    c->rest_given = true;
+  }
+  for (int k = 0; k < c->K; ++k) c->scale[k] = p->scale[k];
+
+  const double w0 = p->w0 > 0.0 ? p->w0 : (c->D == 2 ? 1.0 / 3.0 : 0.25);
+  Phys& ph = c->ph;
+  ph.s = p->flux_scale;
+  ph.gm1 = p->gamma - 1.0;
+  ph.inv_cs2 = c->D / (1.0 - w0);
+  ph.w0 = w0;
+  ph.wi = (1.0 - w0) / (2.0 * c->D);
+  for (int k = 0; k < KMAX; ++k) ph.omega[k] = k < c->K ? 1.0 / p->tau[k] : 0.0;
+  for (int a = 0; a < 3; ++a) ph.inv_tauB[a] = 1.0 / p->tau[5 + a];
+  if (p->model == VLBM_RESISTIVE) {
+    ph.dt_over_tauM = p->dt / p->tau_M;
+    ph.dt_over_tauH = p->dt / p->tau_H;
+    ph.inv_tauM = 1.0 / p->tau_M;
+    ph.inv_tauH = 1.0 / p->tau_H;
+    ph.mu = p->mu;
+    ph.eta0 = p->eta0;
+    ph.inv_jc2 = p->j_c > 0.0 ? 1.0 / (p->j_c * p->j_c) : 0.0;
+    ph.divb_scale = p->dt / p->flux_scale;
+  }
+  ph.powell = p->powell;
+  ph.divb_mode = p->divb_mode;
+
+  if (p->pop_buffer) {
+    if (p->pop_bytes < c->pop_bytes) {
+      delete c;
+      return fail(nullptr, VLBM_ERR_ARG, "pop_bytes %zu < required %zu", p->pop_bytes, c->pop_bytes);
+    }
+    c->f = p->pop_buffer;
+    c->owned = false;
+  } else {
+    hipError_t e = hipMalloc(&c->f, c->pop_bytes);
+    if (e != hipSuccess) {
+      const size_t want = c->pop_bytes;
+      delete c;
+      return fail(nullptr, e == hipErrorOutOfMemory ? VLBM_ERR_OOM : VLBM_ERR_HIP,
+                  "hipMalloc of %zu population bytes: %s", want, hipGetErrorString(e));
+    }
+    c->owned = true;
+  }
+  c->nblk = (int)std::min<long long>(1024, (c->N + 255) / 256);
+  const int NT = c->K + 5;
+  hipError_t e = hipMalloc(&c->d_partial, sizeof(double) * (size_t)c->nblk * NT);
+  if (e == hipSuccess) e = hipMalloc(&c->d_partial2, sizeof(double) * (size_t)c->nblk);
+  if (e == hipSuccess) e = hipMalloc(&c->d_totals, sizeof(double) * (size_t)(NT + 2 * KMAX));
+  if (e != hipSuccess) {
+    vlbm_destroy(c);
+    return fail(nullptr, VLBM_ERR_OOM, "hipMalloc of reduction buffers: %s", hipGetErrorString(e));
+  }
+  c->g.f = c->f;
+  c->g.stride = c->stride;
+  c->g.nx = p->nx;
+  c->g.ny = p->ny;
+  c->g.nz = p->nz;
+  for (int f = 0; f < 6; ++f) c->g.bc[f] = p->bc[f];
+  c->L.storage = p->storage;
+  c->L.dim = c->D;
+  c->L.model = p->model;
+  c->L.block_x = p->block_x ? p->block_x : (p->nx >= 256 ? 256 : (p->nx >= 128 ? 128 : 64));
+  c->L.stream = c->stream;
+  *out = c;
+  return VLBM_OK;
+}
+
+vlbm_status vlbm_init_fields(vlbm_ctx* c, const void* Q, int q_on_device, int q_is_f32) {
+  if (!c) return VLBM_ERR_ARG;
+  if (!Q) return fail(c, VLBM_ERR_ARG, "Q is NULL");
+  const size_t qbytes = (size_t)c->K * c->N * (q_is_f32 ? 4 : 8);
+  const void* dQ = Q;
+  void* tmp = nullptr;
+  if (!q_on_device) {
+    VLBM_HIP(c, hipMalloc(&tmp, qbytes));
+    hipError_t e = hipMemcpyAsync(tmp, Q, qbytes, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+      (void)hipFree(tmp);
+      return hip_fail(c, e, "copy of Q to the device");
+    }
+    dQ = tmp;
+  }
+  vlbm_status st = VLBM_OK;
+  hipError_t e = hipSuccess;
+  const bool codec = c->p.storage == VLBM_F16DEV || c->p.storage == VLBM_BF16DEV;
+  if (codec) {
+    double* d_aux = c->d_totals + (c->K + 5);  // KMAX doubles after the totals
+    if (!c->rest_given) {
+      // Q_rest: domain mean with rho u (and G, H) set to zero
+      e = launch_field_reduce(c->L, c->N, c->K, dQ, q_is_f32, 0, nullptr, c->d_partial, c->nblk, d_aux);
+      double mean[KMAX];
+      if (e == hipSuccess) e = hipMemcpyAsync(mean, d_aux, sizeof(double) * c->K, hipMemcpyDeviceToHost, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      if (e == hipSuccess)
+        for (int k = 0; k < c->K; ++k)
+          c->rest_Q[k] = (k >= 1 && k <= 3) || k >= 8 ? 0.0 : mean[k] / (double)c->N;
+    }
+    bool need_scale = false;
+    for (int k = 0; k < c->K; ++k) need_scale |= !(c->p.scale[k] > 0.0);
+    if (e == hipSuccess && need_scale) {
+      double* d_rest = d_aux + KMAX;
+      double* d_dev = d_aux;
+      double dev[KMAX];
+      e = hipMemcpyAsync(d_rest, c->rest_Q, sizeof(double) * c->K, hipMemcpyHostToDevice, c->stream);
+      if (e == hipSuccess)
+        e = launch_field_reduce(c->L, c->N, c->K, dQ, q_is_f32, 1, d_rest, c->d_partial, c->nblk, d_dev);
+      if (e == hipSuccess) e = hipMemcpyAsync(dev, d_dev, sizeof(double) * c->K, hipMemcpyDeviceToHost, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      if (e == hipSuccess)
+        for (int k = 0; k < c->K; ++k)
+          if (!(c->p.scale[k] > 0.0)) c->scale[k] = pow2_at_least(dev[k]);
+    }
+    if (e == hipSuccess) build_codec(c);
+  }
+  if (e == hipSuccess) e = launch_init(c->L, c->g, c->ph, c->cd, dQ, q_is_f32);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (tmp) (void)hipFree(tmp);
+  if (e != hipSuccess) st = hip_fail(c, e, "init_fields");
+  if (st == VLBM_OK) {
+    c->step = 0;
+    c->initialized = true;
+  }
+  return st;
+}
+
+vlbm_status vlbm_step(vlbm_ctx* c, int32_t n) {
+  if (!c) return VLBM_ERR_ARG;
+  if (n < 0) return fail(c, VLBM_ERR_ARG, "n = %d < 0", n);
+  if (!c->initialized) return fail(c, VLBM_ERR_STATE, "vlbm_step before vlbm_init_fields");
+  for (int32_t j = 0; j < n; ++j) {
+    const hipError_t e = launch_sweep(c->L, c->g, c->ph, c->cd, (int)(c->step & 1));
+    if (e != hipSuccess) return hip_fail(c, e, "sweep launch");
+    ++c->step;
+  }
+  return VLBM_OK;
+}
+
+vlbm_status vlbm_moments(vlbm_ctx* c, void* Q_out, int out_on_device, int out_is_f32, double* totals) {
+  if (!c) return VLBM_ERR_ARG;
+  if (!c->initialized) return fail(c, VLBM_ERR_STATE, "vlbm_moments before vlbm_init_fields");
+  const size_t nq = (size_t)c->K * c->N;
+  double* Qd;
+  if (Q_out && out_on_device && !out_is_f32) {
+    Qd = static_cast<double*>(Q_out);
+  } else {
+    if (!c->d_Q) VLBM_HIP(c, hipMalloc(&c->d_Q, sizeof(double) * nq));
+    Qd = c->d_Q;
+  }
+  const int NT = c->K + 5;
+  const int par = (int)(c->step & 1);
+  VLBM_HIP(c, launch_moments(c->L, c->g, c->ph, c->cd, par, Qd, c->d_partial, c->nblk));
+  VLBM_HIP(c, launch_divc(c->L, c->g, Qd, c->d_partial2, c->nblk));
+  VLBM_HIP(c, launch_reduce(c->L, NT, c->d_partial, c->nblk, 1u << (c->K + 2), c->d_totals));
+  VLBM_HIP(c, launch_reduce(c->L, 1, c->d_partial2, c->nblk, 0u, c->d_totals + c->K + 3));
+  double tot[KMAX + 5];
+  VLBM_HIP(c, hipMemcpyAsync(tot, c->d_totals, sizeof(double) * NT, hipMemcpyDeviceToHost, c->stream));
+  if (Q_out && Qd != Q_out) {
+    if (out_is_f32) {
+      if (out_on_device) {
+        VLBM_HIP(c, launch_to_f32(c->stream, Qd, static_cast<float*>(Q_out), (long long)nq));
+      } else {
+        std::vector<double> h(nq);
+        VLBM_HIP(c, hipMemcpyAsync(h.data(), Qd, sizeof(double) * nq, hipMemcpyDeviceToHost, c->stream));
+        VLBM_HIP(c, hipStreamSynchronize(c->stream));
+        float* o = static_cast<float*>(Q_out);
+        for (size_t j = 0; j < nq; ++j) o[j] = (float)h[j];
+      }
+    } else {
+      VLBM_HIP(c, hipMemcpyAsync(Q_out, Qd, sizeof(double) * nq,
+                                 out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    }
+  }
+  VLBM_HIP(c, hipStreamSynchronize(c->stream));
+  if (totals) std::memcpy(totals, tot, sizeof(double) * NT);
+  bool finite = true;
+  for (int j = 0; j < NT; ++j) finite = finite && std::isfinite(tot[j]);
+  if (!finite || tot[c->K + 4] > 0.0)
+    return fail(c, VLBM_ERR_NONFINITE, "%g unphysical cells (rho <= 0, p < 0 or non-finite)", tot[c->K + 4]);
+  return VLBM_OK;
+}
+
+vlbm_status vlbm_gather_cells(vlbm_ctx* c, const int64_t* cells, int64_t n, double* out) {
+  if (!c) return VLBM_ERR_ARG;
+  if (!c->initialized) return fail(c, VLBM_ERR_STATE, "gather before vlbm_init_fields");
+  if (n < 0 || (n > 0 && (!cells || !out))) return fail(c, VLBM_ERR_ARG, "bad cell list");
+  if (n == 0) return VLBM_OK;
+  for (int64_t j = 0; j < n; ++j)
+    if (cells[j] < 0 || cells[j] >= c->N) return fail(c, VLBM_ERR_ARG, "cell %lld out of range", (long long)cells[j]);
+  long long* d_cells = nullptr;
+  double* d_out = nullptr;
+  const size_t nout = (size_t)n * c->K * c->NQ;
+  VLBM_HIP(c, hipMalloc(&d_cells, sizeof(long long) * n));
+  hipError_t e = hipMalloc(&d_out, sizeof(double) * nout);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_cells, cells, sizeof(long long) * n, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = launch_gather(c->L, c->g, c->cd, (int)(c->step & 1), c->K, d_cells, n, d_out);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, d_out, sizeof(double) * nout, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(d_cells);
+  if (d_out) (void)hipFree(d_out);
+  if (e != hipSuccess) return hip_fail(c, e, "gather_cells");
+  return VLBM_OK;
+}
+
+vlbm_status vlbm_get_populations(vlbm_ctx* c, void* dst, size_t bytes, int32_t* parity, int64_t* step) {
+  if (!c) return VLBM_ERR_ARG;
+  if (!dst || bytes != c->pop_bytes) return fail(c, VLBM_ERR_ARG, "need %zu bytes", c->pop_bytes);
+  VLBM_HIP(c, hipMemcpyAsync(dst, c->f, bytes, hipMemcpyDeviceToHost, c->stream));
+  VLBM_HIP(c, hipStreamSynchronize(c->stream));
+  if (parity) *parity = (int32_t)(c->step & 1);
+  if (step) *step = c->step;
+  return VLBM_OK;
+}
+
+vlbm_status vlbm_set_populations(vlbm_ctx* c, const void* src, size_t bytes, int32_t parity, int64_t step) {
+  if (!c) return VLBM_ERR_ARG;
+  if (!src || bytes != c->pop_bytes) return fail(c, VLBM_ERR_ARG, "need %zu bytes", c->pop_bytes);
+  if (step < 0 || (step & 1) != parity) return fail(c, VLBM_ERR_ARG, "parity must equal step & 1");
+  if ((c->p.storage == VLBM_F16DEV || c->p.storage == VLBM_BF16DEV) && !c->initialized && !c->rest_given)
+    return fail(c, VLBM_ERR_STATE, "FP16/BF16 restore needs rest_Q and scale in the params (or a prior init)");
+  if (!c->initialized) build_codec(c);
+  VLBM_HIP(c, hipMemcpyAsync(c->f, src, bytes, hipMemcpyHostToDevice, c->stream));
+  VLBM_HIP(c, hipStreamSynchronize(c->stream));
+  c->step = step;
+  c->initialized = true;
+  return VLBM_OK;
+}
+
+vlbm_status vlbm_get_codec(const vlbm_ctx* c, double* rest_Q, double* scale) {
+  if (!c) return VLBM_ERR_ARG;
+  for (int k = 0; k < c->K; ++k) {
+    if (rest_Q) rest_Q[k] = c->rest_Q[k];
+    if (scale) scale[k] = c->scale[k];
+  }
+  return VLBM_OK;
+}
+
+vlbm_status vlbm_get_step(const vlbm_ctx* c, int64_t* step) {
+  if (!c || !step) return VLBM_ERR_ARG;
+  *step = c->step;
+  return VLBM_OK;
+}
+
+void vlbm_destroy(vlbm_ctx* c) {
+  if (!c) return;
+  if (c->owned && c->f) (void)hipFree(c->f);
+  if (c->d_partial) (void)hipFree(c->d_partial);
+  if (c->d_partial2) (void)hipFree(c->d_partial2);
+  if (c->d_totals) (void)hipFree(c->d_totals);
+  if (c->d_Q) (void)hipFree(c->d_Q);
+  delete c;
+}
+
+const char* vlbm_last_error(const vlbm_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+vlbm_status vlbm_copy_kernel(void* dst, const void* src, size_t bytes, void* stream) {
+  if (!dst || !src || bytes % 16 != 0 || (reinterpret_cast<uintptr_t>(dst) & 15) ||
+      (reinterpret_cast<uintptr_t>(src) & 15))
+    return fail(nullptr, VLBM_ERR_ARG, "copy needs 16-byte aligned pointers and size");
+  const hipError_t e = launch_copy(static_cast<hipStream_t>(stream), dst, src, bytes);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "copy kernel");
+  return VLBM_OK;
+}
+
+}  // extern "C"

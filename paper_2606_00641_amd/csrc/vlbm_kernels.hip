@@ -1,0 +1,547 @@
+// HIP kernels (gfx950) of the VLBM MHD sweep and its diagnostics.
+//
+// Data layout in HBM: one population buffer, SoA planes indexed (k*Q + i) of
+// `stride` elements, cell index c = x + nx (y + ny z) with x fastest, so a
+// wavefront touches 64 consecutive cells of one plane per access.
+//
+// Streaming is the in-place AA pattern: a step at parity 0 reads slot i of its
+// own cell and writes the post-collision value of direction i to slot opposite(i)
+// of the same cell; a step at parity 1 reads slot opposite(i) of cell x - e_i and
+// writes slot i of cell x + e_i.  Every slot is read and written by one thread
+// only, so one buffer suffices and there is no race.  After a parity-0 step the
+// pre-collision population f_i(x) sits at slot opposite(i) of cell x - e_i; after
+// a parity-1 step the layout is natural again.
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "vlbm_kernels.h"
+
+namespace vlbm {
+namespace {
+
+constexpr int kReduceThreads = 256;
+
+// ---------------------------------------------------------------------------
+// storage codecs
+// ---------------------------------------------------------------------------
+template <int ST>
+struct Store;
+
+template <>
+struct Store<ST_F64> {
+  using T = double;
+  using R = double;
+  static __device__ __forceinline__ R dec(T v, const Codec&, int) { return v; }
+  static __device__ __forceinline__ T enc(R v, const Codec&, int) { return v; }
+  static __device__ __forceinline__ double dec64(T v, const Codec&, int) { return v; }
+};
+
+template <>
+struct Store<ST_F32> {
+  using T = float;
+  using R = float;
+  static __device__ __forceinline__ R dec(T v, const Codec&, int) { return v; }
+  static __device__ __forceinline__ T enc(R v, const Codec&, int) { return v; }
+  static __device__ __forceinline__ double dec64(T v, const Codec&, int) { return v; }
+};
+
+template <>
+struct Store<ST_F16> {
+  using T = unsigned short;
+  using R = float;
+  static __device__ __forceinline__ float h2f(T v) { return __half2float(__ushort_as_half(v)); }
+  static __device__ __forceinline__ R dec(T v, const Codec& cd, int j) {
+    return fmaf(cd.sc[j], h2f(v), cd.rest[j]);
+  }
+  static __device__ __forceinline__ T enc(R v, const Codec& cd, int j) {
+    float h = (v - cd.rest[j]) * cd.isc[j];
+    h = fminf(fmaxf(h, -65504.0f), 65504.0f);  // saturate instead of overflowing to inf
+    return __half_as_ushort(__float2half_rn(h));
+  }
+  static __device__ __forceinline__ double dec64(T v, const Codec& cd, int j) {
+    return (double)cd.rest[j] + (double)cd.sc[j] * (double)h2f(v);
+  }
+};
+
+template <>
+struct Store<ST_BF16> {
+  using T = unsigned short;
+  using R = float;
+  static __device__ __forceinline__ float b2f(T v) { return __uint_as_float((unsigned)v << 16); }
+  static __device__ __forceinline__ R dec(T v, const Codec& cd, int j) {
+    return fmaf(cd.sc[j], b2f(v), cd.rest[j]);
+  }
+  static __device__ __forceinline__ T enc(R v, const Codec& cd, int j) {
+    const float h = (v - cd.rest[j]) * cd.isc[j];
+    // round to nearest even on the upper 16 bits (finite inputs)
+    const unsigned u = __float_as_uint(h);
+    return (T)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+  }
+  static __device__ __forceinline__ double dec64(T v, const Codec& cd, int j) {
+    return (double)cd.rest[j] + (double)cd.sc[j] * (double)b2f(v);
+  }
+};
+
+// Neighbour linear indices of cell (x, y, z) along +e_a (np) and -e_a (nm),
+// periodic.  32-bit: every supported lattice has fewer than 2^31 cells.
+template <int D>
+__device__ __forceinline__ void neighbours(const Grid& g, int x, int y, int z, unsigned c,
+                                           unsigned (&np)[3], unsigned (&nm)[3]) {
+  const unsigned nx = g.nx, pl = (unsigned)g.nx * (unsigned)g.ny;
+  np[0] = (x + 1 == g.nx) ? c + 1 - nx : c + 1;
+  nm[0] = (x == 0) ? c + nx - 1 : c - 1;
+  np[1] = (y + 1 == g.ny) ? c - (unsigned)(g.ny - 1) * nx : c + nx;
+  nm[1] = (y == 0) ? c + (unsigned)(g.ny - 1) * nx : c - nx;
+  if constexpr (D == 3) {
+    np[2] = (z + 1 == g.nz) ? c - (unsigned)(g.nz - 1) * pl : c + pl;
+    nm[2] = (z == 0) ? c + (unsigned)(g.nz - 1) * pl : c - pl;
+  } else {
+    np[2] = nm[2] = c;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// the sweep: gather, decode, collide (moments, EOS, fluxes, div B, Powell, BGK +
+// injection), encode, scatter
+// ---------------------------------------------------------------------------
+// Plane addressing: the base of plane (k*Q + i) is wavefront-uniform, the per-lane
+// part is a 32-bit byte offset, so loads and stores use the scalar-base +
+// vector-offset form and keep no 64-bit address per population in registers.
+// (The library rejects lattices whose plane exceeds 4 GiB.)
+#define VLBM_GLOBAL __attribute__((address_space(1)))
+
+__device__ __forceinline__ VLBM_GLOBAL char* plane_base(void* base, size_t plane_bytes, int plane) {
+  // The base is the same for every lane; reading it through readfirstlane keeps it
+  // an opaque scalar value, so the backend cannot first fold the lane offset into
+  // it (which would cost a 64-bit VGPR address per load), and the global address
+  // space lets it use the scalar-base form of the load.
+  const unsigned long long a = reinterpret_cast<unsigned long long>(base) + plane_bytes * plane;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
+  return (VLBM_GLOBAL char*)(((unsigned long long)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ T ld(void* base, size_t plane_bytes, int plane, unsigned off) {
+  return *(const VLBM_GLOBAL T*)(plane_base(base, plane_bytes, plane) + off);
+}
+template <typename T>
+__device__ __forceinline__ void st(void* base, size_t plane_bytes, int plane, unsigned off, T v) {
+  *(VLBM_GLOBAL T*)(plane_base(base, plane_bytes, plane) + off) = v;
+}
+
+template <int ST, int D, int MODEL, int PAR>
+__global__ __launch_bounds__(256) void k_sweep(const Grid g, const Phys ph, const Codec cd) {
+  using S = Store<ST>;
+  using T = typename S::T;
+  using R = typename S::R;
+  constexpr int NQ = 2 * D + 1;
+  constexpr int K = MODEL ? 26 : 8;
+  constexpr unsigned ES = sizeof(T);
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= g.nx) return;
+  const int y = blockIdx.y, z = blockIdx.z;
+  const unsigned c = (unsigned)x + (unsigned)g.nx * ((unsigned)y + (unsigned)g.ny * (unsigned)z);
+  void* const F = g.f;
+  const size_t pb = (size_t)g.stride * ES;
+
+  // byte offsets of this cell and of its neighbours x + e_a (np), x - e_a (nm)
+  unsigned np[3], nm[3];
+  if constexpr (PAR == 1) {
+    neighbours<D>(g, x, y, z, c, np, nm);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      np[a] *= ES;
+      nm[a] *= ES;
+    }
+  }
+  const unsigned co = c * ES;
+
+  R f[K][NQ];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      T v;
+      if constexpr (PAR == 0) {
+        v = ld<T>(F, pb, k * NQ + i, co);
+      } else {
+        // f_i(x) was written by cell x - e_i into its slot opposite(i)
+        const unsigned src = (i == 0) ? co : ((i & 1) ? nm[(i - 1) >> 1] : np[(i - 1) >> 1]);
+        v = ld<T>(F, pb, k * NQ + opposite(i), src);
+      }
+      f[k][i] = S::dec(v, cd, k * NQ + i);
+    }
+  }
+
+  R dl;
+  collide<R, D, MODEL>(f, ph, dl);
+
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const T v = S::enc(f[k][i], cd, k * NQ + i);
+      if constexpr (PAR == 0) {
+        st<T>(F, pb, k * NQ + opposite(i), co, v);
+      } else {
+        const unsigned dst = (i == 0) ? co : ((i & 1) ? np[(i - 1) >> 1] : nm[(i - 1) >> 1]);
+        st<T>(F, pb, k * NQ + i, dst, v);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// init: f := f^eq(Q), natural layout
+// ---------------------------------------------------------------------------
+template <int ST, int D, int MODEL, typename QT>
+__global__ __launch_bounds__(256) void k_init(const Grid g, const Phys ph, const Codec cd,
+                                              const QT* __restrict__ Qin) {
+  using S = Store<ST>;
+  using T = typename S::T;
+  using R = typename S::R;
+  constexpr int NQ = 2 * D + 1;
+  constexpr int K = MODEL ? 26 : 8;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= g.nx) return;
+  const unsigned c = (unsigned)x + (unsigned)g.nx * (blockIdx.y + (unsigned)g.ny * blockIdx.z);
+  const size_t N = (size_t)g.nx * g.ny * g.nz;
+  T* __restrict__ F = static_cast<T*>(g.f);
+  R Q[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) Q[k] = (R)Qin[(size_t)k * N + c];
+  R Jb[3] = {R(0), R(0), R(0)};
+  R P[K][3], Sv[K], dl;
+  flux_source<R, D, MODEL>(Q, Jb, ph, P, Sv, dl);
+  const R wi = R(ph.wi);
+  const R w0 = rest_weight<R, D>(wi);
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int i = 0; i < NQ; ++i)
+      F[(size_t)(k * NQ + i) * g.stride + c] = S::enc(feq_dir<R, D>(Q[k], P[k], i, w0, wi), cd, k * NQ + i);
+}
+
+// ---------------------------------------------------------------------------
+// reductions (FP64)
+// ---------------------------------------------------------------------------
+// Reduce v[0..n) over the block (slots in maxmask take the max, others the sum) and
+// let thread j < n write the block result of slot j to out[j].  All threads call it.
+template <int NMAX>
+__device__ void block_reduce(double (&v)[NMAX], int n, unsigned maxmask, double* out) {
+  __shared__ double sh[kReduceThreads / 64][NMAX];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int j = 0; j < n; ++j) {
+    const bool mx = (maxmask >> j) & 1u;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(v[j], off);
+      v[j] = mx ? fmax(v[j], o) : v[j] + o;
+    }
+    if (lane == 0) sh[wv][j] = v[j];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < n) {
+    const int j = threadIdx.x;
+    const bool mx = (maxmask >> j) & 1u;
+    double r = sh[0][j];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = mx ? fmax(r, sh[w][j]) : r + sh[w][j];
+    out[j] = r;
+  }
+}
+
+template <int ST, int D, int MODEL>
+__global__ __launch_bounds__(kReduceThreads) void k_moments(const Grid g, const Phys ph,
+                                                            const Codec cd, int parity,
+                                                            double* __restrict__ Qout,
+                                                            double* __restrict__ partial) {
+  using S = Store<ST>;
+  using T = typename S::T;
+  constexpr int NQ = 2 * D + 1;
+  constexpr int K = MODEL ? 26 : 8;
+  constexpr int NT = K + 5;
+  const T* __restrict__ F = static_cast<const T*>(g.f);
+  const size_t N = (size_t)g.nx * g.ny * g.nz;
+  double acc[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) acc[j] = 0.0;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < N;
+       c += (size_t)gridDim.x * blockDim.x) {
+    const int x = (int)(c % g.nx);
+    const int y = (int)((c / g.nx) % g.ny);
+    const int z = (int)(c / ((size_t)g.nx * g.ny));
+    unsigned np[3], nm[3];
+    neighbours<D>(g, x, y, z, (unsigned)c, np, nm);
+    double Q[K];
+    double Jb[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double q = 0.0;
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) {
+        const unsigned src = (parity == 0 || i == 0) ? (unsigned)c
+                             : ((i & 1) ? nm[(i - 1) >> 1] : np[(i - 1) >> 1]);
+        const int slot = parity == 0 ? i : opposite(i);
+        const double v = S::dec64(F[(size_t)(k * NQ + slot) * g.stride + src], cd, k * NQ + i);
+        q += v;
+        if (k >= 5 && k < 5 + D && i > 0 && ((i - 1) >> 1) == k - 5) Jb[k - 5] += (i & 1) ? v : -v;
+      }
+      Q[k] = q;
+      Qout[(size_t)k * N + c] = q;
+    }
+    double P[K][3], Sv[K], dl;
+    const bool bad = flux_source<double, D, MODEL>(Q, Jb, ph, P, Sv, dl);
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] += Q[k];
+    acc[K] += dl;
+    acc[K + 1] += dl * dl;
+    acc[K + 2] = fmax(acc[K + 2], fabs(dl));
+    acc[K + 4] += bad ? 1.0 : 0.0;
+  }
+  block_reduce<NT>(acc, NT, 1u << (K + 2), partial + (size_t)blockIdx.x * NT);
+}
+
+template <int D>
+__global__ __launch_bounds__(kReduceThreads) void k_divc(const Grid g, const double* __restrict__ Qm,
+                                                         double* __restrict__ partial) {
+  const size_t N = (size_t)g.nx * g.ny * g.nz;
+  double acc[1] = {0.0};
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < N;
+       c += (size_t)gridDim.x * blockDim.x) {
+    const int x = (int)(c % g.nx);
+    const int y = (int)((c / g.nx) % g.ny);
+    const int z = (int)(c / ((size_t)g.nx * g.ny));
+    unsigned np[3], nm[3];
+    neighbours<D>(g, x, y, z, (unsigned)c, np, nm);
+    double dv = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) dv += 0.5 * (Qm[(size_t)(5 + a) * N + np[a]] - Qm[(size_t)(5 + a) * N + nm[a]]);
+    acc[0] += dv * dv;
+  }
+  block_reduce<1>(acc, 1, 0u, partial + blockIdx.x);
+}
+
+template <int NMAX>
+__global__ __launch_bounds__(kReduceThreads) void k_reduce(int n, const double* __restrict__ partial,
+                                                           int nblk, unsigned maxmask,
+                                                           double* __restrict__ out) {
+  double acc[NMAX];
+#pragma unroll
+  for (int j = 0; j < NMAX; ++j) acc[j] = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+    for (int j = 0; j < n; ++j) {
+      const double v = partial[(size_t)b * n + j];
+      acc[j] = ((maxmask >> j) & 1u) ? fmax(acc[j], v) : acc[j] + v;
+    }
+  block_reduce<NMAX>(acc, n, maxmask, out);
+}
+
+// per-variable sum (mode 0) or max |Q_k - rest_k| (mode 1) over the field
+template <int NMAX, typename QT>
+__global__ __launch_bounds__(kReduceThreads) void k_field_reduce(const QT* __restrict__ Q, long long N,
+                                                                 int K, int mode,
+                                                                 const double* __restrict__ rest,
+                                                                 double* __restrict__ partial) {
+  double acc[NMAX];
+#pragma unroll
+  for (int j = 0; j < NMAX; ++j) acc[j] = 0.0;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N;
+       c += (long long)gridDim.x * blockDim.x)
+    for (int k = 0; k < K; ++k) {
+      const double v = (double)Q[(size_t)k * N + c];
+      acc[k] = mode == 0 ? acc[k] + v : fmax(acc[k], fabs(v - rest[k]));
+    }
+  block_reduce<NMAX>(acc, K, mode == 0 ? 0u : 0xffffffffu, partial + (size_t)blockIdx.x * K);
+}
+
+template <int ST, int D>
+__global__ void k_gather(const Grid g, const Codec cd, int parity, int K,
+                         const long long* __restrict__ cells, long long n, double* __restrict__ out) {
+  using S = Store<ST>;
+  using T = typename S::T;
+  constexpr int NQ = 2 * D + 1;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * K * NQ) return;
+  const int i = (int)(t % NQ);
+  const int k = (int)((t / NQ) % K);
+  const long long c = cells[t / ((long long)NQ * K)];
+  const int x = (int)(c % g.nx);
+  const int y = (int)((c / g.nx) % g.ny);
+  const int z = (int)(c / ((long long)g.nx * g.ny));
+  unsigned np[3], nm[3];
+  neighbours<D>(g, x, y, z, (unsigned)c, np, nm);
+  const unsigned src = (parity == 0 || i == 0) ? (unsigned)c : ((i & 1) ? nm[(i - 1) >> 1] : np[(i - 1) >> 1]);
+  const int slot = parity == 0 ? i : opposite(i);
+  const T* F = static_cast<const T*>(g.f);
+  out[t] = S::dec64(F[(size_t)(k * NQ + slot) * g.stride + src], cd, k * NQ + i);
+}
+
+__global__ void k_to_f32(const double* __restrict__ in, float* __restrict__ out, long long n) {
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (long long)gridDim.x * blockDim.x)
+    out[t] = (float)in[t];
+}
+
+__global__ __launch_bounds__(256) void k_copy(uint4* __restrict__ dst, const uint4* __restrict__ src,
+                                              size_t n) {
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (size_t)gridDim.x * blockDim.x)
+    dst[t] = src[t];
+}
+
+// ---------------------------------------------------------------------------
+// launch helpers
+// ---------------------------------------------------------------------------
+dim3 cell_grid(const Grid& g, int bx) { return dim3((g.nx + bx - 1) / bx, g.ny, g.nz); }
+
+template <int ST, int D, int MODEL>
+hipError_t sweep_t(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity) {
+  const dim3 grd = cell_grid(g, L.block_x), blk(L.block_x);
+  if (parity == 0)
+    hipLaunchKernelGGL((k_sweep<ST, D, MODEL, 0>), grd, blk, 0, L.stream, g, ph, cd);
+  else
+    hipLaunchKernelGGL((k_sweep<ST, D, MODEL, 1>), grd, blk, 0, L.stream, g, ph, cd);
+  return hipGetLastError();
+}
+
+template <int ST, int D, int MODEL>
+hipError_t init_t(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, const void* Q,
+                  int f32) {
+  const dim3 grd = cell_grid(g, L.block_x), blk(L.block_x);
+  if (f32)
+    hipLaunchKernelGGL((k_init<ST, D, MODEL, float>), grd, blk, 0, L.stream, g, ph, cd,
+                       static_cast<const float*>(Q));
+  else
+    hipLaunchKernelGGL((k_init<ST, D, MODEL, double>), grd, blk, 0, L.stream, g, ph, cd,
+                       static_cast<const double*>(Q));
+  return hipGetLastError();
+}
+
+template <int ST, int D, int MODEL>
+hipError_t moments_t(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
+                     double* Qout, double* partial, int nblk) {
+  hipLaunchKernelGGL((k_moments<ST, D, MODEL>), dim3(nblk), dim3(kReduceThreads), 0, L.stream, g,
+                     ph, cd, parity, Qout, partial);
+  return hipGetLastError();
+}
+
+template <int ST>
+hipError_t gather_t(const Launch& L, const Grid& g, const Codec& cd, int parity, int K,
+                    const long long* cells, long long n, double* out) {
+  const long long tot = n * K * (2 * L.dim + 1);
+  const dim3 grd((unsigned)((tot + 255) / 256)), blk(256);
+  if (L.dim == 2)
+    hipLaunchKernelGGL((k_gather<ST, 2>), grd, blk, 0, L.stream, g, cd, parity, K, cells, n, out);
+  else
+    hipLaunchKernelGGL((k_gather<ST, 3>), grd, blk, 0, L.stream, g, cd, parity, K, cells, n, out);
+  return hipGetLastError();
+}
+
+// dispatch on (storage, dim, model) for functions templated <ST, D, MODEL>
+template <template <int, int, int> class Fn, typename... A>
+hipError_t dispatch(const Launch& L, A&&... args) {
+  const int key = L.storage * 100 + L.dim * 10 + L.model;
+  switch (key) {
+#define VLBM_CASE(ST, D, M) \
+  case ST * 100 + D * 10 + M: return Fn<ST, D, M>::run(L, args...);
+    VLBM_CASE(0, 2, 0) VLBM_CASE(0, 3, 0) VLBM_CASE(0, 3, 1)
+    VLBM_CASE(1, 2, 0) VLBM_CASE(1, 3, 0) VLBM_CASE(1, 3, 1)
+    VLBM_CASE(2, 2, 0) VLBM_CASE(2, 3, 0) VLBM_CASE(2, 3, 1)
+    VLBM_CASE(3, 2, 0) VLBM_CASE(3, 3, 0) VLBM_CASE(3, 3, 1)
+#undef VLBM_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int ST, int D, int M>
+struct SweepFn {
+  static hipError_t run(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int par) {
+    return sweep_t<ST, D, M>(L, g, ph, cd, par);
+  }
+};
+template <int ST, int D, int M>
+struct InitFn {
+  static hipError_t run(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd,
+                        const void* Q, int f32) {
+    return init_t<ST, D, M>(L, g, ph, cd, Q, f32);
+  }
+};
+template <int ST, int D, int M>
+struct MomentsFn {
+  static hipError_t run(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int par,
+                        double* Qout, double* partial, int nblk) {
+    return moments_t<ST, D, M>(L, g, ph, cd, par, Qout, partial, nblk);
+  }
+};
+
+}  // namespace
+
+hipError_t launch_sweep(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity) {
+  return dispatch<SweepFn>(L, g, ph, cd, parity);
+}
+
+hipError_t launch_init(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd,
+                       const void* Q, int q_is_f32) {
+  return dispatch<InitFn>(L, g, ph, cd, Q, q_is_f32);
+}
+
+hipError_t launch_moments(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd,
+                          int parity, double* Qout, double* partial, int nblk) {
+  return dispatch<MomentsFn>(L, g, ph, cd, parity, Qout, partial, nblk);
+}
+
+hipError_t launch_divc(const Launch& L, const Grid& g, const double* Qout, double* partial, int nblk) {
+  if (L.dim == 2)
+    hipLaunchKernelGGL((k_divc<2>), dim3(nblk), dim3(kReduceThreads), 0, L.stream, g, Qout, partial);
+  else
+    hipLaunchKernelGGL((k_divc<3>), dim3(nblk), dim3(kReduceThreads), 0, L.stream, g, Qout, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const Launch& L, int n, const double* partial, int nblk, unsigned maxmask,
+                         double* out) {
+  if (n > 32) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_reduce<32>), dim3(1), dim3(kReduceThreads), 0, L.stream, n, partial, nblk,
+                     maxmask, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const Launch& L, const Grid& g, const Codec& cd, int parity, int K,
+                         const long long* cells, long long n, double* out) {
+  switch (L.storage) {
+    case ST_F64: return gather_t<ST_F64>(L, g, cd, parity, K, cells, n, out);
+    case ST_F32: return gather_t<ST_F32>(L, g, cd, parity, K, cells, n, out);
+    case ST_F16: return gather_t<ST_F16>(L, g, cd, parity, K, cells, n, out);
+    case ST_BF16: return gather_t<ST_BF16>(L, g, cd, parity, K, cells, n, out);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_field_reduce(const Launch& L, long long N, int K, const void* Q, int q_is_f32,
+                               int mode, const double* rest, double* partial, int nblk, double* out) {
+  if (K > 32) return hipErrorInvalidValue;
+  if (q_is_f32)
+    hipLaunchKernelGGL((k_field_reduce<32, float>), dim3(nblk), dim3(kReduceThreads), 0, L.stream,
+                       static_cast<const float*>(Q), N, K, mode, rest, partial);
+  else
+    hipLaunchKernelGGL((k_field_reduce<32, double>), dim3(nblk), dim3(kReduceThreads), 0, L.stream,
+                       static_cast<const double*>(Q), N, K, mode, rest, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_reduce(L, K, partial, nblk, mode == 0 ? 0u : 0xffffffffu, out);
+}
+
+hipError_t launch_to_f32(hipStream_t s, const double* in, float* out, long long n) {
+  hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, s, in, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(hipStream_t s, void* dst, const void* src, size_t bytes) {
+  const size_t n = bytes / 16;
+  hipLaunchKernelGGL(k_copy, dim3(8192), dim3(256), 0, s, static_cast<uint4*>(dst),
+                     static_cast<const uint4*>(src), n);
+  return hipGetLastError();
+}
+
+}  // namespace vlbm

@@ -1,0 +1,217 @@
+// Per-cell physics of the VLBM MHD sweep: state -> flux, sources, div B estimate,
+// and the BGK collision with direct source injection.  Host and device.
+//
+// Paper: "Lattice Boltzmann Methods for Compressible (Magneto)hydrodynamics".
+//  - Sec. 2.2: update f_{k,i}(x + c_i, t + 1) = f_{k,i} + Omega^C + Omega^S, linear
+//    vector equilibrium f^eq_{k,i} = w_i (Q_k + c_i . Phi_k / c_s^2), moments
+//    Q_k = sum_i f_{k,i}.
+//  - Sec. 2.3: ideal MHD state/flux, equation of state, Powell source; the expanded
+//    resistive state with transported gradients (Sec. 2.2.1).
+//  - Sec. 3 intro: BGK collision, direct injection of the source.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace vlbm {
+
+constexpr int KMAX = 26;
+
+// Direction i: 0 rest, 2a+1 is +e_a, 2a+2 is -e_a.
+__host__ __device__ constexpr int opposite(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+// Model constants, converted to the compute type R by the kernel.
+struct Phys {
+  double s;          // flux scale dt/dx
+  double gm1;        // gamma - 1
+  double inv_cs2;    // 1 / c_s^2
+  double w0, wi;     // rest and moving weights
+  double omega[KMAX];// 1 / tau_k
+  double inv_tauB[3];// 1 / tau of the B_x, B_y, B_z sets (div B estimate)
+  double dt_over_tauM, dt_over_tauH;
+  double mu, eta0, inv_jc2, inv_tauM, inv_tauH;
+  double divb_scale; // divb_mode 1: dx = dt / s (lattice units of tr G / tau_M)
+  int powell, divb_mode;
+};
+
+// Scaled lattice flux P[k][a] = (s / c_s^2) Phi[k][a] for the D lattice axes, lattice
+// source S[k] and the lattice div B estimate.  Jb[a] = first moment along axis a of
+// the B_a population set (only used by divb_mode 0).  Returns true if the cell is
+// unphysical (rho <= 0, p < 0, or a non-finite value).
+template <typename R, int D, int MODEL>
+__host__ __device__ inline bool flux_source(const R* Q, const R* Jb, const Phys& ph,
+                                            R (*P)[3], R* S, R& dlat) {
+  constexpr int K = MODEL ? 26 : 8;
+  const R rho = Q[0];
+  const R ir = R(1) / rho;
+  const R m0 = Q[1], m1 = Q[2], m2 = Q[3];
+  const R E = Q[4];
+  const R b0 = Q[5], b1 = Q[6], b2 = Q[7];
+  const R u0 = m0 * ir, u1 = m1 * ir, u2 = m2 * ir;
+  const R mu_ = m0 * u0 + m1 * u1 + m2 * u2;  // rho |u|^2
+  const R bb = b0 * b0 + b1 * b1 + b2 * b2;
+  const R ub = u0 * b0 + u1 * b1 + u2 * b2;
+  const R pres = R(ph.gm1) * (E - R(0.5) * mu_ - R(0.5) * bb);
+  const R pt = pres + R(0.5) * bb;
+  const R c = R(ph.s * ph.inv_cs2);
+  const R u[3] = {u0, u1, u2};
+  const R m[3] = {m0, m1, m2};
+  const R B[3] = {b0, b1, b2};
+  const R Ept = E + pt;
+
+  // physical fluxes along the lattice axes a (Sec. 2.3, ideal MHD)
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    P[0][a] = m[a];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) P[1 + b][a] = m[b] * u[a] - B[b] * B[a] + (a == b ? pt : R(0));
+    P[4][a] = Ept * u[a] - B[a] * ub;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) P[5 + b][a] = u[a] * B[b] - B[a] * u[b];
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) S[k] = R(0);
+
+  R divb;
+  if constexpr (MODEL == 1) {
+    // expanded state: G ~ tau_M grad B, H ~ tau_H grad u (Sec. 2.2.1, Sec. 2.3)
+    const R* G = Q + 8;
+    const R* H = Q + 17;
+    const R itm = R(ph.inv_tauM), ith = R(ph.inv_tauH);
+    R dB[3][3], du[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        dB[a][b] = G[3 * a + b] * itm;
+        du[a][b] = H[3 * a + b] * ith;
+      }
+    const R j0 = dB[1][2] - dB[2][1], j1 = dB[2][0] - dB[0][2], j2 = dB[0][1] - dB[1][0];
+    R eta = R(ph.eta0);
+    if (ph.inv_jc2 > 0.0) eta = eta * (R(1) + (j0 * j0 + j1 * j1 + j2 * j2) * R(ph.inv_jc2));
+    const R jxb[3] = {j1 * b2 - j2 * b1, j2 * b0 - j0 * b2, j0 * b1 - j1 * b0};
+    const R muv = R(ph.mu);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      R utv = R(0);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const R tv = muv * (du[b][a] + du[a][b]);  // viscous stress, symmetric
+        P[1 + b][a] -= tv;
+        utv += u[b] * tv;
+        P[5 + b][a] -= eta * dB[a][b];           // -eta d_a B_b in the flux of B_b
+      }
+      P[4][a] += eta * jxb[a] - utv;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        const int ga = q / 3, gb = q % 3;
+        P[8 + q][a] = G[q] * u[a] - (a == ga ? B[gb] : R(0));
+        P[17 + q][a] = H[q] * u[a] - (a == ga ? u[gb] : R(0));
+      }
+    }
+    const R sg = R(-ph.dt_over_tauM), sh = R(-ph.dt_over_tauH);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      S[8 + q] = G[q] * sg;
+      S[17 + q] = H[q] * sh;
+    }
+    if (ph.divb_mode == 1) {
+      R tr = R(0);
+#pragma unroll
+      for (int a = 0; a < D; ++a) tr += dB[a][a];
+      divb = tr * R(ph.divb_scale);
+    } else {
+      R acc = R(0);
+#pragma unroll
+      for (int a = 0; a < D; ++a) acc += Jb[a] * R(ph.inv_tauB[a]);
+      divb = -acc * R(ph.inv_cs2);
+    }
+  } else {
+    // local non-equilibrium estimate of div B from the B sets' first moments
+    R acc = R(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) acc += Jb[a] * R(ph.inv_tauB[a]);
+    divb = -acc * R(ph.inv_cs2);
+  }
+  dlat = divb;
+
+  // Powell source -(div B)(0, B, u.B, u), times dt (= s times lattice divergence)
+  if (ph.powell) {
+    const R cp = -R(ph.s) * divb;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      S[1 + b] += cp * B[b];
+      S[5 + b] += cp * u[b];
+    }
+    S[4] += cp * ub;
+  }
+  // scale the fluxes to c_i . Phi / c_s^2 units of the equilibrium
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int a = 0; a < D; ++a) P[k][a] *= c;
+
+  bool bad = !(rho > R(0)) || !(pres >= R(0));
+#pragma unroll
+  for (int k = 0; k < K; ++k) bad = bad || !(Q[k] - Q[k] == R(0));  // NaN or Inf
+  return bad;
+}
+
+// Rest weight derived in the compute type as 1 - 2 D w_i, so that the weights sum
+// to exactly one in that type: with w0 and w_i rounded independently (1/3 and 1/6
+// in FP32 sum to 1 + 3e-8) the equilibrium would create mass every step.
+template <typename R, int D>
+__host__ __device__ inline R rest_weight(R wi) {
+  return R(1) - R(2 * D) * wi;
+}
+
+// Equilibrium of one variable: f^eq_i = w_i (Q + c_i . P) with P already scaled.
+template <typename R, int D>
+__host__ __device__ inline R feq_dir(R Qk, const R* Pk, int i, R w0, R wi) {
+  if (i == 0) return w0 * Qk;
+  const int a = (i - 1) >> 1;
+  return (i & 1) ? wi * (Qk + Pk[a]) : wi * (Qk - Pk[a]);
+}
+
+// BGK + direct injection, in place: f_{k,i} += omega_k (f^eq_{k,i} - f_{k,i}) + w_i S_k.
+// Returns the unphysical flag and writes the div B estimate.
+template <typename R, int D, int MODEL>
+__device__ __forceinline__ bool collide(R (*f)[2 * D + 1], const Phys& ph, R& dlat) {
+  constexpr int NQ = 2 * D + 1;
+  constexpr int K = MODEL ? 26 : 8;
+  // Zeroth moments, opposite directions paired first: f_{+a} + f_{-a} cancels the
+  // flux part c_a . Phi / c_s^2 the two carry with opposite signs before it is
+  // accumulated, which keeps small variables (G, H, a momentum at rest) accurate
+  // in FP32.
+  R Q[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    R acc = f[k][0];
+#pragma unroll
+    for (int a = 0; a < D; ++a) acc += f[k][2 * a + 1] + f[k][2 * a + 2];
+    Q[k] = acc;
+  }
+  R Jb[3] = {R(0), R(0), R(0)};
+#pragma unroll
+  for (int a = 0; a < D; ++a) Jb[a] = f[5 + a][2 * a + 1] - f[5 + a][2 * a + 2];
+  R P[K][3];
+  R S[K];
+  const bool bad = flux_source<R, D, MODEL>(Q, Jb, ph, P, S, dlat);
+  const R wi = R(ph.wi);
+  const R w0 = rest_weight<R, D>(wi);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const R om = R(ph.omega[k]);
+    const R sw0 = w0 * S[k], swi = wi * S[k];
+    f[k][0] += om * (w0 * Q[k] - f[k][0]) + sw0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const R ep = wi * (Q[k] + P[k][a]);
+      const R em = wi * (Q[k] - P[k][a]);
+      f[k][2 * a + 1] += om * (ep - f[k][2 * a + 1]) + swi;
+      f[k][2 * a + 2] += om * (em - f[k][2 * a + 2]) + swi;
+    }
+  }
+  return bad;
+}
+
+}  // namespace vlbm

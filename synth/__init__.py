@@ -24,7 +24,10 @@ dataset is involved):
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
+import scipy.fft as sfft
 
 
 def conserved_from_primitive(rho, u, p, B, gamma):
@@ -84,39 +87,50 @@ def fourier_2d(n=64, seed=0, kmax=4, amp=0.1, rho0=1.0, p0=0.6, gamma=5.0 / 3.0)
     return Q[:, None, :, :].copy()
 
 
-def _solenoidal_spectral(rng, n, kmax, rms):
-    k1 = np.fft.fftfreq(n, d=1.0 / n)
-    kz, ky, kx = np.meshgrid(k1, k1, k1, indexing="ij")
+def _fft_workers():
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def _solenoidal_spectral(rng, shape, dx, kmax, rms):
+    """Random solenoidal vector field on a periodic box of nz x ny x nx cells of
+    size dx, and its gradient grad[a][b] = d_a field_b (spectral)."""
+    nz, ny, nx = shape
+    kz, ky, kx = np.meshgrid(2 * np.pi * np.fft.fftfreq(nz, d=dx), 2 * np.pi * np.fft.fftfreq(ny, d=dx),
+                             2 * np.pi * np.fft.fftfreq(nx, d=dx), indexing="ij")
     kk = np.sqrt(kx * kx + ky * ky + kz * kz)
-    mask = (kk >= 1.0) & (kk <= kmax)
+    mask = (kk >= 1.0 - 1e-9) & (kk <= kmax + 1e-9)
     amp = np.zeros_like(kk)
     amp[mask] = kk[mask] ** -2.0
-    vec = (rng.standard_normal((3, n, n, n)) + 1j * rng.standard_normal((3, n, n, n))) * amp
+    vec = (rng.standard_normal((3,) + shape) + 1j * rng.standard_normal((3,) + shape)) * amp
     kvec = np.stack([kx, ky, kz])
     k2 = np.where(kk > 0, kk * kk, 1.0)
     kdotv = (kvec * vec).sum(0)
     vec = vec - kvec * kdotv / k2
-    field = np.real(np.fft.ifftn(vec, axes=(1, 2, 3)))
+    W = _fft_workers()
+    field = np.real(sfft.ifftn(vec, axes=(1, 2, 3), workers=W))
+    del vec
     field *= rms / np.sqrt((field * field).sum(0).mean())
-    fhat = np.fft.fftn(field, axes=(1, 2, 3))
-    # spectral gradient grad[a][b] = d_a field_b on the domain [0, 2 pi)^3
-    grad = np.empty((3, 3, n, n, n))
+    fhat = sfft.fftn(field, axes=(1, 2, 3), workers=W)
+    grad = np.empty((3, 3) + shape)
     for a, ka in enumerate((kx, ky, kz)):
         for b in range(3):
-            grad[a, b] = np.real(np.fft.ifftn(1j * ka * fhat[b]))
+            grad[a, b] = np.real(sfft.ifftn(1j * ka * fhat[b], workers=W))
     return field, grad
 
 
 def turbulence_3d(n=256, seed=1, kmax=8, u_rms=0.05, b_rms=0.05, rho0=1.0, p0=0.6,
-                  gamma=5.0 / 3.0, tau_M=0.01, tau_H=0.01, dtype=np.float64):
-    """3D resistive-MHD state [26, n, n, n] on [0, 2 pi)^3 (random solenoidal u, B)."""
+                  gamma=5.0 / 3.0, tau_M=0.01, tau_H=0.01, dtype=np.float64, shape=None):
+    """3D resistive-MHD state [26, nz, ny, nx] with cells of size 2 pi / n (the cube
+    [0, 2 pi)^3 when shape is None); random solenoidal u and B."""
     rng = np.random.default_rng(seed)
-    u, gu = _solenoidal_spectral(rng, n, kmax, u_rms)
-    B, gB = _solenoidal_spectral(rng, n, kmax, b_rms)
-    Q = np.empty((26, n, n, n), dtype)
-    Q[:8] = conserved_from_primitive(np.full((n, n, n), rho0), u, p0, B, gamma)
-    Q[8:17] = (tau_M * gB).reshape(9, n, n, n)
-    Q[17:26] = (tau_H * gu).reshape(9, n, n, n)
+    shape = (n, n, n) if shape is None else tuple(shape)
+    dx = 2.0 * np.pi / n
+    u, gu = _solenoidal_spectral(rng, shape, dx, kmax, u_rms)
+    B, gB = _solenoidal_spectral(rng, shape, dx, kmax, b_rms)
+    Q = np.empty((26,) + shape, dtype)
+    Q[:8] = conserved_from_primitive(np.full(shape, rho0), u, p0, B, gamma)
+    Q[8:17] = (tau_M * gB).reshape((9,) + shape)
+    Q[17:26] = (tau_H * gu).reshape((9,) + shape)
     return Q
 
 
@@ -138,21 +152,29 @@ def planar_discontinuity_3d(n=512, seed=2, width=2.0, gamma=5.0 / 3.0, dtype=np.
     BL = bL * dL / np.linalg.norm(dL)
     BR = bR * dR / np.linalg.norm(dR)
     nz, ny, nx = (n, n, n) if shape is None else shape
-    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    z = np.arange(nz, dtype=np.float64)[:, None, None]
+    y = np.arange(ny, dtype=np.float64)[None, :, None]
+    x = np.arange(nx, dtype=np.float64)[None, None, :]
     # phase along the normal in units of one period; the slab is phase in [1/4, 3/4)
-    phase = kvec[0] * x / nx + kvec[1] * y / ny + kvec[2] * z / nz
-    xi = phase - np.floor(phase)
+    xi = kvec[0] * x / nx + kvec[1] * y / ny + kvec[2] * z / nz
+    xi -= np.floor(xi)
     # distance (in cells) to the two interfaces along the normal direction
     period = 1.0 / np.sqrt((kvec[0] / nx) ** 2 + (kvec[1] / ny) ** 2 + (kvec[2] / nz) ** 2)
-    d1 = (xi - 0.25) * period
-    d2 = (0.75 - xi) * period
-    inside = 0.25 * (1 + np.tanh(d1 / width)) * (1 + np.tanh(d2 / width))
-    w = inside  # 1 inside the slab (right state), 0 outside (left state)
-    rho = rhoL + (rhoR - rhoL) * w
-    p = pL + (pR - pL) * w
-    B = np.stack([BL[a] + (BR[a] - BL[a]) * w for a in range(3)])
-    u = np.zeros_like(B)
-    Q = conserved_from_primitive(rho, u, p, B, gamma).astype(dtype)
+    w = np.tanh((xi - 0.25) * (period / width))
+    w += 1.0
+    w *= 1.0 + np.tanh((0.75 - xi) * (period / width))
+    w *= 0.25  # 1 inside the slab (right state), 0 outside (left state)
+    del xi
+    w = w.astype(dtype)
+    rho = (rhoL + (rhoR - rhoL) * w).astype(dtype)
+    p = (pL + (pR - pL) * w).astype(dtype)
+    B = np.stack([(BL[a] + (BR[a] - BL[a]) * w).astype(dtype) for a in range(3)])
+    u = np.zeros((3, 1, 1, 1), dtype)
+    Q = np.empty((8, nz, ny, nx), dtype)
+    Q[0] = rho
+    Q[1:4] = 0.0
+    Q[4] = p / (gamma - 1.0) + 0.5 * (B * B).sum(0)
+    Q[5:8] = B
     info = dict(k=kvec.tolist(), rho=(rhoL, rhoR), p=(pL, pR), BL=BL.tolist(), BR=BR.tolist())
     return Q, info
 
@@ -169,3 +191,39 @@ def uniform_state(shape, rho=1.0, u=(0.0, 0.0, 0.0), p=0.6, B=(0.0, 0.0, 0.0),
     Q = np.zeros((K, nz, ny, nx))
     Q[:8] = Q8
     return Q
+
+
+# ---------------------------------------------------------------------------
+# workload parameter sets (the numbers of each synthetic workload; each side maps
+# them onto its own parameter structure)
+# ---------------------------------------------------------------------------
+
+def workload_fourier_2d(n=64, steps=200):
+    """2D ideal MHD, D2Q5 x 8 variables, periodic, tau = 0.6, flux scale 0.2."""
+    return dict(dim=2, shape=(n, n, 1), model=0, s=0.2, gamma=5.0 / 3.0, tau=0.6, powell=1,
+                divb_mode=0, steps=steps, dt=0.0, mu=0.0, eta0=0.0, tau_M=1.0, tau_H=1.0)
+
+
+def workload_resistive_3d(n=256, steps=1000, re=400.0, u_rms=0.05, s=0.2, tau_M=0.01,
+                          dt_over_tau_M=None):
+    """3D resistive MHD, D3Q7 x 26 variables on [0, 2 pi)^3, Re = Rm = re with
+    reference length 1 and velocity u_rms; tau_M = tau_H = 0.01 (physical time), or
+    dt / dt_over_tau_M when given (reduced lattices keep the 256^3 ratio 0.49);
+    lattice relaxation time 1/2 plus a stabilising diffusion of 5 % of the viscosity."""
+    dx = 2.0 * np.pi / n
+    dt = s * dx
+    if dt_over_tau_M is not None:
+        tau_M = dt / dt_over_tau_M
+    nu = u_rms * 1.0 / re
+    nu_lat = nu * dt / dx ** 2
+    cs2 = 0.25
+    tau_lb = 0.5 + 0.05 * nu_lat / cs2
+    return dict(dim=3, shape=(n, n, n), model=1, s=s, gamma=5.0 / 3.0, tau=tau_lb, powell=1,
+                divb_mode=1, steps=steps, dt=dt, mu=nu, eta0=nu, tau_M=tau_M, tau_H=tau_M)
+
+
+def workload_slab_3d(n=512, steps=2000):
+    """3D ideal MHD, D3Q7 x 8 variables, planar discontinuity, tau = 0.6, flux scale
+    0.04 (keeps s (|u| + c_fast) below c_s^2 at rho = 0.1, |B| = 1)."""
+    return dict(dim=3, shape=(n, n, n), model=0, s=0.04, gamma=5.0 / 3.0, tau=0.6, powell=1,
+                divb_mode=0, steps=steps, dt=0.0, mu=0.0, eta0=0.0, tau_M=1.0, tau_H=1.0)
