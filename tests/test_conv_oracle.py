@@ -1,0 +1,193 @@
+"""Pins of the learned-correction oracle (oracle/conv_ref.py), CPU only.
+
+Library routines stand in as independent references: scipy's periodic correlation
+and torch's conv2d with circular padding for the convolution, torch's exact GELU,
+torch's bfloat16 rounding and torch's Adam; the gradients are checked by central
+finite differences in FP64.  Planted mistakes in a copy of the module source must
+make one of the checks fail."""
+import importlib.util
+import os
+import types
+
+import numpy as np
+import pytest
+import scipy.ndimage as ndi
+import torch
+
+import oracle.conv_ref as C
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def rand_params(rng, cin, width, layers, scale=0.3):
+    return [(rng.normal(0, scale, Ws), rng.normal(0, 0.1, bs)) for Ws, bs in C.Net.shapes(cin, width, layers)]
+
+
+def chk_conv_vs_scipy(mod=C):
+    rng = np.random.default_rng(0)
+    a = rng.normal(size=(2, 3, 7, 6))
+    W = rng.normal(size=(4, 3, 3, 3))
+    b = rng.normal(size=4)
+    z = mod.conv3x3(a, W, b)
+    ref = np.zeros_like(z)
+    for bb in range(2):
+        for o in range(4):
+            ref[bb, o] = b[o] + sum(ndi.correlate(a[bb, c], W[o, c], mode="wrap") for c in range(3))
+    return np.abs(z - ref).max()
+
+
+def chk_conv_vs_torch(mod=C):
+    rng = np.random.default_rng(1)
+    a = rng.normal(size=(2, 5, 8, 9))
+    W = rng.normal(size=(3, 5, 3, 3))
+    b = rng.normal(size=3)
+    z = mod.conv3x3(a, W, b)
+    t = torch.nn.functional.pad(torch.tensor(a), (1, 1, 1, 1), mode="circular")
+    ref = torch.nn.functional.conv2d(t, torch.tensor(W), torch.tensor(b)).numpy()
+    return np.abs(z - ref).max()
+
+
+def chk_gradients_fd(mod=C):
+    """Central finite differences of the MSE loss w.r.t. every parameter of a small
+    3-layer net, FP64; returns the worst relative error."""
+    rng = np.random.default_rng(2)
+    params = rand_params(rng, 3, 4, 3)
+    x = rng.normal(size=(2, 3, 5, 6))
+    t = rng.normal(size=(2, 3, 5, 6))
+    net = mod.Net(params, cin=3, width=4, layers=3)
+    _, grads = net.loss_and_grads(x, t)
+    worst = 0.0
+    h = 1e-5
+    gscale = max(np.abs(g).max() for pair in grads for g in pair)
+    for l in range(3):
+        for j in range(2):
+            p = params[l][j]
+            g = grads[l][j]
+            for idx in [tuple(rng.integers(0, s) for s in p.shape) for _ in range(6)]:
+                old = p[idx]
+                p[idx] = old + h
+                lp, _ = mod.Net(params, cin=3, width=4, layers=3).loss_and_grads(x, t)
+                p[idx] = old - h
+                lm, _ = mod.Net(params, cin=3, width=4, layers=3).loss_and_grads(x, t)
+                p[idx] = old
+                fd = (lp - lm) / (2 * h)
+                worst = max(worst, abs(fd - g[idx]) / max(abs(fd), 1e-3 * gscale))
+    return worst
+
+
+def chk_gelu_vs_torch(mod=C):
+    z = np.linspace(-6, 6, 241)
+    ref = torch.nn.functional.gelu(torch.tensor(z)).numpy()  # exact (erf) GELU
+    zt = torch.tensor(z, requires_grad=True)
+    torch.nn.functional.gelu(zt).sum().backward()
+    return max(np.abs(mod.gelu(z) - ref).max(), np.abs(mod.gelu_grad(z) - zt.grad.numpy()).max())
+
+
+def chk_adam_vs_torch(mod=C):
+    rng = np.random.default_rng(3)
+    params = rand_params(rng, 2, 3, 2)
+    tparams = [torch.tensor(p.copy(), requires_grad=True) for pair in params for p in pair]
+    opt = torch.optim.Adam(tparams, lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    adam = mod.Adam(params, lr=1e-2)
+    cur = params
+    for _ in range(5):
+        grads = [(rng.normal(size=W.shape), rng.normal(size=b.shape)) for W, b in cur]
+        for tp, g in zip(tparams, [g for pair in grads for g in pair]):
+            tp.grad = torch.tensor(g)
+        opt.step()
+        cur = adam.step(cur, grads)
+    mine = [p for pair in cur for p in pair]
+    return max(np.abs(m - t.detach().numpy()).max() for m, t in zip(mine, tparams))
+
+
+def test_conv_matches_scipy_periodic_correlation():
+    assert chk_conv_vs_scipy() < 1e-12
+
+
+def test_conv_matches_torch_circular_conv2d():
+    assert chk_conv_vs_torch() < 1e-12
+
+
+def test_identity_kernel():
+    rng = np.random.default_rng(4)
+    a = rng.normal(size=(1, 4, 6, 5))
+    W = np.zeros((4, 4, 3, 3))
+    for c in range(4):
+        W[c, c, 1, 1] = 1.0
+    assert np.array_equal(C.conv3x3(a, W, np.zeros(4)), a)
+
+
+def test_gradients_finite_differences():
+    assert chk_gradients_fd() < 1e-7
+
+
+def test_gelu_matches_torch():
+    assert chk_gelu_vs_torch() < 1e-12
+
+
+def test_adam_matches_torch():
+    assert chk_adam_vs_torch() < 1e-12
+
+
+def test_bf16_rounding_matches_torch():
+    rng = np.random.default_rng(5)
+    a = np.concatenate([rng.normal(size=1000) * 10.0 ** rng.integers(-5, 5, 1000), [0.0, -0.0, 1.0]])
+    ref = torch.tensor(a, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(C.bf16_round(a), ref)
+
+
+def test_restriction_conserves_totals_and_constants():
+    rng = np.random.default_rng(6)
+    Q = rng.normal(size=(8, 1, 16, 12))
+    R = C.restrict(Q, 4)
+    assert R.shape == (8, 1, 4, 3)
+    assert np.allclose(R.sum(axis=(1, 2, 3)) * 16, Q.sum(axis=(1, 2, 3)), rtol=1e-13)
+    assert np.allclose(R[:, 0, 1, 2], Q[:, 0, 4:8, 8:12].mean(axis=(1, 2)))
+    Q3 = rng.normal(size=(8, 4, 4, 4))
+    assert np.allclose(C.restrict(Q3, 2).sum() * 8, Q3.sum())
+
+
+def test_gate_cases():
+    rng = np.random.default_rng(7)
+    Q = rng.normal(size=(8, 1, 8, 8))
+    dQ = 1e-3 * rng.normal(size=Q.shape)
+    big = np.full(8, 1e9)
+    assert C.gate(Q, np.zeros_like(Q), big, 0.1)
+    assert not C.gate(Q, dQ, np.zeros(8), 0.1)  # bound 0 always falls back
+    bad = dQ.copy()
+    bad[0, 0, 1, 1] = np.nan
+    assert not C.gate(Q, bad, big, 0.1)
+    # a correction that only adds divergence is rejected
+    div_only = np.zeros_like(Q)
+    div_only[5] = 10.0 * np.sin(2 * np.pi * np.arange(8) / 8)[None, None, :]
+    assert not C.gate(Q, div_only, big, 0.1)
+
+
+MUTATIONS = {
+    "conv_shift_sign": ("shifted = np.roll(a, shift=(-(ky - 1), -(kx - 1)), axis=(2, 3))  # a[y+ky-1, x+kx-1]",
+                        "shifted = np.roll(a, shift=((ky - 1), (kx - 1)), axis=(2, 3))  # a[y+ky-1, x+kx-1]"),
+    "backward_scatter_sign": ("da += np.roll(back, shift=(ky - 1, kx - 1), axis=(2, 3))",
+                              "da += np.roll(back, shift=(-(ky - 1), -(kx - 1)), axis=(2, 3))"),
+    "gelu_grad_pdf_dropped": ("return cdf + z * pdf", "return cdf"),
+    "loss_scale": ("dz = 2.0 * (y - t) / n", "dz = 1.0 * (y - t) / n"),
+    "adam_bias_correction": ("new.append(p - self.lr * (m / c1) / (np.sqrt(v / c2) + self.eps))",
+                             "new.append(p - self.lr * m / (np.sqrt(v) + self.eps))"),
+}
+
+
+def _load_variant(src):
+    mod = types.ModuleType("conv_ref_variant")
+    exec(compile(src, "conv_ref_variant", "exec"), mod.__dict__)
+    return mod
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_conv_pins_catch_planted_mistake(name):
+    old, new = MUTATIONS[name]
+    src = open(C.__file__).read()
+    assert src.count(old) == 1, name
+    mod = _load_variant(src.replace(old, new))
+    failed = (chk_conv_vs_scipy(mod) > 1e-12 or chk_conv_vs_torch(mod) > 1e-12
+              or chk_gradients_fd(mod) > 1e-7 or chk_gelu_vs_torch(mod) > 1e-12
+              or chk_adam_vs_torch(mod) > 1e-12)
+    assert failed, name
