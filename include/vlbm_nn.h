@@ -1,0 +1,103 @@
+/*
+ * vlbm_nn.h -- C ABI of the learned coarse-grid correction of the VLBM MHD library.
+ *
+ * This part is an extension of the paper's method (not described there): the
+ * method's own runs on a fine 2D lattice, restricted to a coarser one, train a small
+ * network that predicts, from the coarse moments at one step, the correction that
+ * takes the plain coarse VLBM step to the restricted fine solution.  The coarse run
+ * then injects that correction into the populations (f_{k,i} += w_i dQ_k, which
+ * shifts the zeroth moments by dQ_k) unless a gate falls back to the plain VLBM.
+ * The VLBM pieces it drives are those of include/vlbm.h (Sec. 2.2-2.3 of the paper:
+ * moments, equilibrium, BGK update with direct source injection).
+ *
+ * Network: `layers` 3x3 convolutions with periodic padding on an nx x ny lattice,
+ * channels cin -> width -> ... -> width -> cin, exact GELU between layers; operands
+ * in bfloat16, accumulation in FP32 on the matrix cores; FP32 master weights, Adam.
+ * Supported shapes: cin = 8 (the ideal-MHD moments), width = 32, nx and ny multiples
+ * of 16.
+ *
+ * Weight vector layout (FP32, host): for each layer l in order, W_l[o][c][ky][kx]
+ * (o output channel, c input channel, ky, kx in 0..2 for offsets -1..1), then b_l[o].
+ * The convolution is z[o,y,x] = b[o] + sum_{c,ky,kx} W[o,c,ky,kx] a[c, y+ky-1, x+kx-1]
+ * with periodic indices.
+ *
+ * Normalisation: inputs are standardised per channel, x = (X - in_mean)/in_std;
+ * the network output y is a standardised correction, dQ = out_mean + out_std * y.
+ *
+ * All device arrays are FP32, [batch][channel][ny][nx] (x fastest).  Every call is
+ * stream-ordered on the network's stream; calls that return host values
+ * synchronise it.  Errors as in vlbm.h; vlbm_nn_last_error() gives the message.
+ */
+#ifndef VLBM_NN_H
+#define VLBM_NN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "vlbm.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vlbm_nn vlbm_nn;
+
+/* Create a network (weights zero, normalisation identity, Adam state zero).
+ * stream: hipStream_t or NULL.  *out is NULL on error. */
+vlbm_status vlbm_nn_create(int32_t cin, int32_t width, int32_t layers, void* stream, vlbm_nn** out);
+void vlbm_nn_destroy(vlbm_nn* nn);                           /* NULL-safe */
+const char* vlbm_nn_last_error(const vlbm_nn* nn);            /* NULL: last create error */
+
+/* Number of FP32 parameters (weights and biases of all layers). */
+vlbm_status vlbm_nn_num_params(const vlbm_nn* nn, size_t* n);
+/* Host FP32 weight vector in the layout above; n must equal vlbm_nn_num_params.
+ * set_weights also resets the Adam state and step count. */
+vlbm_status vlbm_nn_set_weights(vlbm_nn* nn, const float* w, size_t n);
+vlbm_status vlbm_nn_get_weights(const vlbm_nn* nn, float* w, size_t n);
+/* Per-channel normalisation (host arrays of cin doubles; std > 0). */
+vlbm_status vlbm_nn_set_norm(vlbm_nn* nn, const double* in_mean, const double* in_std,
+                             const double* out_mean, const double* out_std);
+
+/* Inference: X (device, raw moments) -> dQ (device, raw correction). */
+vlbm_status vlbm_nn_forward(vlbm_nn* nn, const float* X, float* dQ, int32_t batch, int32_t nx,
+                            int32_t ny);
+
+/* Mean-squared error between the standardised output and the standardised target
+ * (T, device, raw correction) and its gradient.  loss (host) may be NULL; grad
+ * (host, vlbm_nn_num_params floats) may be NULL.  The gradient is kept on the
+ * device for vlbm_nn_adam_step.  Synchronises when loss or grad is requested. */
+vlbm_status vlbm_nn_loss_grad(vlbm_nn* nn, const float* X, const float* T, int32_t batch,
+                              int32_t nx, int32_t ny, double* loss, float* grad);
+
+/* One Adam update of the FP32 master weights with the last gradient
+ * (beta1 0.9, beta2 0.999, eps 1e-8 unless changed by vlbm_nn_adam_config). */
+vlbm_status vlbm_nn_adam_step(vlbm_nn* nn, float lr);
+vlbm_status vlbm_nn_adam_config(vlbm_nn* nn, float beta1, float beta2, float eps);
+
+/* loss_grad followed by adam_step (one training iteration, all on the device). */
+vlbm_status vlbm_nn_train_step(vlbm_nn* nn, const float* X, const float* T, int32_t batch,
+                               int32_t nx, int32_t ny, float lr, double* loss);
+
+/* Block mean of a moment field: Qf (device FP32 [K][nz][ny][nx]) -> Qc (device FP32
+ * [K][nz/rz][ny/r][nx/r]) with rz = r if nz > 1 else 1.  Accumulated in FP64.  Every
+ * extent must be divisible by its factor.  stream: hipStream_t or NULL. */
+vlbm_status vlbm_restrict(const float* Qf, int32_t K, int32_t nx, int32_t ny, int32_t nz,
+                          int32_t r, float* Qc, void* stream);
+
+/* n coarse steps with the learned correction.  Per step: the moments X of the
+ * current populations (including the pending correction), dQ = network(X), the gate
+ * (FP64: every ||dQ_k||_2 <= bound_corr[k], the central-difference div B L2 norm of
+ * X + dQ at most (1 + bound_divb) times that of X, all finite; otherwise dQ := 0 and
+ * the fallback counter is incremented), then the sweep, with the previous step's
+ * accepted dQ added as w_i dQ_k to the populations before the collision.  After the
+ * last step the pending dQ is added to the populations, so vlbm_moments sees the
+ * corrected state.  The context must be a 2D ideal-MHD context (K = cin = 8) whose
+ * extent the network supports.  bound_corr: host, K doubles.  *n_fallback (host, may
+ * be NULL) receives the number of fallbacks in this call.  Synchronises. */
+vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const double* bound_corr,
+                                double bound_divb, int64_t* n_fallback);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VLBM_NN_H */

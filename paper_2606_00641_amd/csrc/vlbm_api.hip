@@ -11,34 +11,10 @@
 #include <vector>
 
 #include "vlbm.h"
+#include "vlbm_ctx.h"
 #include "vlbm_kernels.h"
 
 using namespace vlbm;
-
-struct vlbm_ctx {
-  vlbm_params p{};
-  int D = 0, K = 0, NQ = 0, esize = 0;
-  long long N = 0, stride = 0;
-  size_t pop_bytes = 0;
-  void* f = nullptr;
-  bool owned = false;
-  hipStream_t stream = nullptr;
-  Phys ph{};
-  Codec cd{};
-  Grid g{};
-  Launch L{};
-  double rest_Q[KMAX] = {};
-  double scale[KMAX] = {};
-  bool rest_given = false;
-  int nblk = 0;
-  double* d_partial = nullptr;   // [nblk][K+5]
-  double* d_partial2 = nullptr;  // [nblk]
-  double* d_totals = nullptr;    // [K+5] totals, then 2 x KMAX codec scratch
-  double* d_Q = nullptr;         // [K][N] moments scratch (lazy)
-  long long step = 0;
-  bool initialized = false;
-  std::string err;
-};
 
 namespace {
 

@@ -1,0 +1,990 @@
+// Learned coarse-grid correction (include/vlbm_nn.h): BF16 MFMA convolution
+// kernels (forward, data gradient, weight gradient), loss, Adam, restriction, the
+// FP64 gate and the corrected coarse step.
+//
+// Convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16 (gfx950): one
+// workgroup (4 wavefronts) computes a 16 x 16 tile of output positions for every
+// output channel; the 18 x 18 input halo (periodic) is staged in LDS in
+// channels-last order so that one lane's A fragment (8 consecutive input channels
+// of one tap, or 8 taps' worth for 8-channel inputs) is a single 16-byte LDS read.
+// B fragments (weights) are packed once per weight update in the exact lane order
+// of the instruction and held in registers for the whole tile.
+//
+// MFMA 16x16x32 operand layout (verified on the device): lane l holds
+// A[i = l % 16][k = 8 (l / 16) + e] and B[k = 8 (l / 16) + e][j = l % 16] for
+// e = 0..7; the result D[i = 4 (l / 16) + r][j = l % 16] for r = 0..3.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "vlbm.h"
+#include "vlbm_ctx.h"
+#include "vlbm_kernels.h"
+#include "vlbm_nn.h"
+
+namespace {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+typedef unsigned short bf16_t;
+
+constexpr int TILE = 16;
+constexpr int HALO = TILE + 2;
+constexpr int kThreads = 256;
+constexpr int kMaxLayers = 8;
+constexpr int kGateThreads = 256;
+
+enum { MODE_HIDDEN = 0, MODE_LAST = 1, MODE_BWD = 2 };
+
+__host__ __device__ inline int ksteps(int cin) { return (9 * cin + 31) / 32; }
+__host__ __device__ inline int ntiles(int cout) { return (cout + 15) / 16; }
+
+__device__ __forceinline__ bf16_t f2bf(float f) {
+  const unsigned u = __float_as_uint(f);
+  return (bf16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);  // nearest even (finite)
+}
+__device__ __forceinline__ float bf2f(bf16_t b) { return __uint_as_float((unsigned)b << 16); }
+
+// exact GELU and its derivative (standard normal CDF via erf)
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float z) {
+  const float cdf = 0.5f * (1.0f + erff(z * 0.70710678118654752f));
+  const float pdf = 0.39894228040143268f * expf(-0.5f * z * z);
+  return cdf + z * pdf;
+}
+
+// ---------------------------------------------------------------------------
+// weight packing into B-fragment order
+// ---------------------------------------------------------------------------
+// Forward (flip = 0): B[k][n] = W[n][c][tap] with k = tap * CIN + c over this conv's
+// input channels CIN and outputs n < COUT.
+// Data gradient (flip = 1) of a layer with weights W[o][c][tap] (o < CO, c < CI): a
+// convolution of dZ (CI' = CO input channels) producing CO' = CI outputs with
+// B[k = tap' * CO + o][n = c] = W[o][c][8 - tap'] (taps mirrored: offset -> -offset).
+__global__ void k_pack(const float* __restrict__ W, int CI, int CO, int flip, bf16_t* __restrict__ out) {
+  const int cin = flip ? CO : CI;    // input channels of the packed convolution
+  const int cout = flip ? CI : CO;   // its output channels
+  const int KS = ksteps(cin), NT = ntiles(cout);
+  const int total = KS * NT * 64 * 8;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= total) return;
+  const int e = q & 7, lane = (q >> 3) & 63, st = q >> 9;
+  const int t = st % NT, s = st / NT;
+  const int k = 32 * s + 8 * (lane >> 4) + e;
+  const int n = 16 * t + (lane & 15);
+  const int tap = k / cin, c = k % cin;
+  float v = 0.0f;
+  if (tap < 9 && n < cout) {
+    if (!flip)
+      v = W[((size_t)n * CI + c) * 9 + tap];
+    else
+      v = W[((size_t)c * CI + n) * 9 + (8 - tap)];  // W[o = c][c_in = n][8 - tap]
+  }
+  out[q] = f2bf(v);
+}
+
+// ---------------------------------------------------------------------------
+// convolution (forward, and data gradient with the mirrored packed weights)
+// ---------------------------------------------------------------------------
+// act: BF16 NHWC [B][H][W][CIN].  Output, by MODE:
+//  HIDDEN: z = conv + bias; out_act (BF16 NHWC COUT) = GELU(z); out_z (FP32 NHWC, optional) = z
+//  LAST:   out_z (FP32 NCHW [B][COUT][H][W]) = (conv + bias) * oscale + oshift
+//  BWD:    out_act (BF16 NHWC COUT) = conv * GELU'(zprev), zprev FP32 NHWC COUT
+template <int CIN, int COUT, int MODE>
+__global__ __launch_bounds__(kThreads) void k_conv(const bf16_t* __restrict__ act, const bf16_t* __restrict__ wpack,
+                                                   const float* __restrict__ bias, int H, int W,
+                                                   bf16_t* __restrict__ out_act, float* __restrict__ out_z,
+                                                   const float* __restrict__ zprev,
+                                                   const float* __restrict__ oscale,
+                                                   const float* __restrict__ oshift) {
+  constexpr int KS = (9 * CIN + 31) / 32;
+  constexpr int NT = (COUT + 15) / 16;
+  constexpr int CH = CIN / 8;
+  __shared__ __attribute__((aligned(16))) bf16_t tile[HALO * HALO * CIN];
+  const int b = blockIdx.z, ty0 = blockIdx.y * TILE, tx0 = blockIdx.x * TILE;
+  for (int q = threadIdx.x; q < HALO * HALO * CH; q += kThreads) {
+    const int pix = q / CH, ch = q % CH;
+    const int hy = pix / HALO, hx = pix % HALO;
+    int gy = ty0 - 1 + hy;
+    int gx = tx0 - 1 + hx;
+    gy = gy < 0 ? gy + H : (gy >= H ? gy - H : gy);
+    gx = gx < 0 ? gx + W : (gx >= W ? gx - W : gx);
+    const uint4 v = *reinterpret_cast<const uint4*>(act + (((size_t)b * H + gy) * W + gx) * CIN + ch * 8);
+    *reinterpret_cast<uint4*>(tile + pix * CIN + ch * 8) = v;
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  bf16x8 bw[KS][NT];
+#pragma unroll
+  for (int s = 0; s < KS; ++s)
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      bw[s][t] = *reinterpret_cast<const bf16x8*>(wpack + ((size_t)(s * NT + t) * 64 + lane) * 8);
+  __syncthreads();
+
+  f32x4 acc[4][NT];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+
+  const int px = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int py = 4 * wv + m;
+      bf16x8 a;
+      if constexpr (CIN == 32) {
+        const int dy = s / 3, dx = s % 3;
+        a = *reinterpret_cast<const bf16x8*>(tile + ((py + dy) * HALO + px + dx) * CIN + 8 * g);
+      } else {
+        const int tap = 4 * s + g;  // 8 input channels: 4 taps per K step
+        if (tap < 9) {
+          const int dy = tap / 3, dx = tap % 3;
+          a = *reinterpret_cast<const bf16x8*>(tile + ((py + dy) * HALO + px + dx) * CIN);
+        } else {
+          a = bf16x8{};  // zero padding of K
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[s][t], acc[m][t], 0, 0, 0);
+    }
+  }
+
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int y = ty0 + 4 * wv + m;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int co = 16 * t + (lane & 15);
+      if (co >= COUT) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int x = tx0 + 4 * g + r;
+        const float v = acc[m][t][r];
+        const size_t nhwc = (((size_t)b * H + y) * W + x) * COUT + co;
+        if constexpr (MODE == MODE_HIDDEN) {
+          const float z = v + bias[co];
+          out_act[nhwc] = f2bf(gelu(z));
+          if (out_z) out_z[nhwc] = z;
+        } else if constexpr (MODE == MODE_LAST) {
+          const float z = v + bias[co];
+          out_z[(((size_t)b * COUT + co) * H + y) * W + x] = z * oscale[co] + oshift[co];
+        } else {
+          out_act[nhwc] = f2bf(v * gelu_grad(zprev[nhwc]));
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// weight gradient: dW[o][c][tap] = sum_{b,p} dZ[b,p,o] act[b, p + off(tap), c];
+// db[o] = sum dZ.  GEMM with M = o, N = (tap, c), K = positions; each workgroup
+// accumulates over a fixed set of tiles and writes one partial (reduced later in a
+// fixed order, so the result is deterministic).
+// ---------------------------------------------------------------------------
+template <int CIN, int COUT>
+__global__ __launch_bounds__(kThreads) void k_conv_bw(const bf16_t* __restrict__ act, const bf16_t* __restrict__ dz,
+                                                      int B, int H, int W, float* __restrict__ part_w,
+                                                      float* __restrict__ part_b) {
+  constexpr int NJ = 9 * CIN;
+  constexpr int NTJ = (NJ + 15) / 16;
+  constexpr int MT = (COUT + 15) / 16;
+  constexpr int NTW = (NTJ + 3) / 4;  // N tiles per wavefront
+  __shared__ __attribute__((aligned(16))) bf16_t aT[CIN * HALO * HALO];
+  __shared__ __attribute__((aligned(16))) bf16_t dzT[MT * 16 * TILE * TILE];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4;
+  f32x4 acc[MT][NTW];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int u = 0; u < NTW; ++u) acc[mt][u] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  float db = 0.0f;
+  const int tiles_x = W / TILE, tiles_y = H / TILE;
+  const int ntile = B * tiles_x * tiles_y;
+  for (int tid = blockIdx.x; tid < ntile; tid += gridDim.x) {
+    const int b = tid / (tiles_x * tiles_y);
+    const int rem = tid % (tiles_x * tiles_y);
+    const int ty0 = (rem / tiles_x) * TILE, tx0 = (rem % tiles_x) * TILE;
+    __syncthreads();  // previous tile fully consumed
+    for (int q = threadIdx.x; q < HALO * HALO * (CIN / 8); q += kThreads) {
+      const int pix = q / (CIN / 8), ch = q % (CIN / 8);
+      const int hy = pix / HALO, hx = pix % HALO;
+      int gy = ty0 - 1 + hy;
+      int gx = tx0 - 1 + hx;
+      gy = gy < 0 ? gy + H : (gy >= H ? gy - H : gy);
+      gx = gx < 0 ? gx + W : (gx >= W ? gx - W : gx);
+      const uint4 v = *reinterpret_cast<const uint4*>(act + (((size_t)b * H + gy) * W + gx) * CIN + ch * 8);
+      const bf16_t* e = reinterpret_cast<const bf16_t*>(&v);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) aT[((ch * 8 + j) * HALO + hy) * HALO + hx] = e[j];
+    }
+    for (int q = threadIdx.x; q < MT * 16 * TILE * TILE; q += kThreads) {
+      const int o = q / (TILE * TILE), p = q % (TILE * TILE);
+      const int y = ty0 + p / TILE, x = tx0 + p % TILE;
+      dzT[q] = o < COUT ? dz[(((size_t)b * H + y) * W + x) * COUT + o] : (bf16_t)0;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < COUT) {
+      float sacc = 0.0f;
+      for (int p = 0; p < TILE * TILE; ++p) sacc += bf2f(dzT[threadIdx.x * TILE * TILE + p]);
+      db += sacc;
+    }
+#pragma unroll
+    for (int s = 0; s < (TILE * TILE) / 32; ++s) {
+      bf16x8 afr[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+        afr[mt] = *reinterpret_cast<const bf16x8*>(dzT + (16 * mt + (lane & 15)) * TILE * TILE + 32 * s + 8 * g);
+      const int pos0 = 32 * s + 8 * g;  // 8 consecutive positions of one tile row
+      const int py = pos0 / TILE, px0 = pos0 % TILE;
+#pragma unroll
+      for (int u = 0; u < NTW; ++u) {
+        const int nt = wv + 4 * u;
+        if (nt >= NTJ) continue;
+        const int j = 16 * nt + (lane & 15);
+        bf16x8 bfr = bf16x8{};
+        if (j < NJ) {
+          const int tap = j / CIN, c = j % CIN;
+          const int dy = tap / 3, dx = tap % 3;
+          const bf16_t* src = aT + (c * HALO + py + dy) * HALO + px0 + dx;  // 8 positions, unaligned
+#pragma unroll
+          for (int e = 0; e < 8; ++e) bfr[e] = __builtin_bit_cast(__bf16, src[e]);
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+          acc[mt][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[mt], bfr, acc[mt][u], 0, 0, 0);
+      }
+    }
+  }
+  // partial results of this workgroup
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int u = 0; u < NTW; ++u) {
+      const int nt = wv + 4 * u;
+      if (nt >= NTJ) continue;
+      const int j = 16 * nt + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int o = 16 * mt + 4 * g + r;
+        if (o < COUT && j < NJ) part_w[((size_t)blockIdx.x * COUT + o) * NJ + j] = acc[mt][u][r];
+      }
+    }
+  if ((int)threadIdx.x < COUT) part_b[(size_t)blockIdx.x * COUT + threadIdx.x] = db;
+}
+
+// Sum the partials in block order into the master-layout gradient:
+// grad_W[o][c][tap] = sum_blk part_w[blk][o][tap * CIN + c]; grad_b[o] = sum part_b.
+__global__ void k_reduce_grads(const float* __restrict__ part_w, const float* __restrict__ part_b, int nblk,
+                               int CIN, int COUT, float* __restrict__ gW, float* __restrict__ gb) {
+  const int NJ = 9 * CIN;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < COUT * NJ) {
+    const int o = q / NJ, rem = q % NJ;  // rem = c * 9 + tap in master order
+    const int c = rem / 9, tap = rem % 9;
+    const int j = tap * CIN + c;
+    float s = 0.0f;
+    for (int blk = 0; blk < nblk; ++blk) s += part_w[((size_t)blk * COUT + o) * NJ + j];
+    gW[q] = s;
+  } else if (q < COUT * NJ + COUT) {
+    const int o = q - COUT * NJ;
+    float s = 0.0f;
+    for (int blk = 0; blk < nblk; ++blk) s += part_b[(size_t)blk * COUT + o];
+    gb[o] = s;
+  }
+}
+
+// raw moments X (FP32 NCHW [B][C][H][W]) -> standardised BF16 NHWC (C = 8)
+__global__ void k_prep(const float* __restrict__ X, int B, int C, int H, int W, const float* __restrict__ mean,
+                       const float* __restrict__ istd, bf16_t* __restrict__ out) {
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t HW = (size_t)H * W;
+  if (q >= (size_t)B * HW) return;
+  const size_t b = q / HW, p = q % HW;
+  for (int c = 0; c < C; ++c) out[q * C + c] = f2bf((X[(b * C + c) * HW + p] - mean[c]) * istd[c]);
+}
+
+// MSE on standardised outputs: y (FP32 NCHW), target T raw -> (T - mean) * istd.
+// dZ = 2 (y - t) / n as BF16 NHWC; per-block FP64 partial sums of (y - t)^2.
+__global__ __launch_bounds__(kThreads) void k_loss(const float* __restrict__ y, const float* __restrict__ T, int B,
+                                                   int C, int H, int W, const float* __restrict__ mean,
+                                                   const float* __restrict__ istd, bf16_t* __restrict__ dz,
+                                                   double* __restrict__ partial) {
+  __shared__ double sh[kThreads / 64];
+  const size_t HW = (size_t)H * W;
+  const size_t n = (size_t)B * C * HW;
+  const double inv_n = 1.0 / (double)n;
+  double acc = 0.0;
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
+    const size_t b = q / (C * HW), c = (q / HW) % C, p = q % HW;
+    const float t = (T[q] - mean[c]) * istd[c];
+    const float d = y[q] - t;
+    acc += (double)d * (double)d;
+    dz[(b * HW + p) * C + c] = f2bf((float)(2.0 * inv_n) * d);
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kThreads / 64; ++w) s += sh[w];
+    partial[blockIdx.x] = s * inv_n;
+  }
+}
+
+__global__ void k_sum_partials(const double* __restrict__ partial, int n, double* __restrict__ out) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) s += partial[j];
+    out[0] = s;
+  }
+}
+
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, size_t n, float lr, float b1, float b2, float eps, float c1,
+                       float c2) {
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const float gq = g[q];
+  const float mq = b1 * m[q] + (1.0f - b1) * gq;
+  const float vq = b2 * v[q] + (1.0f - b2) * gq * gq;
+  m[q] = mq;
+  v[q] = vq;
+  p[q] -= lr * (mq / c1) / (sqrtf(vq / c2) + eps);
+}
+
+// block mean of a moment field (FP64 accumulation)
+__global__ void k_restrict(const float* __restrict__ Qf, int K, int nx, int ny, int nz, int r, int rz,
+                           float* __restrict__ Qc) {
+  const int cx = nx / r, cy = ny / r, cz = nz / rz;
+  const size_t nc = (size_t)cx * cy * cz;
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nc * K) return;
+  const int k = (int)(q / nc);
+  const size_t c = q % nc;
+  const int x = (int)(c % cx), y = (int)((c / cx) % cy), z = (int)(c / ((size_t)cx * cy));
+  double s = 0.0;
+  for (int dz = 0; dz < rz; ++dz)
+    for (int dy = 0; dy < r; ++dy)
+      for (int dx = 0; dx < r; ++dx)
+        s += Qf[(size_t)k * nx * ny * nz + ((size_t)(z * rz + dz) * ny + (y * r + dy)) * nx + (x * r + dx)];
+  Qc[q] = (float)(s / (double)(r * r * rz));
+}
+
+// ---------------------------------------------------------------------------
+// corrected coarse stepping (2D, 8 variables)
+// ---------------------------------------------------------------------------
+template <int ST>
+struct Dec;
+template <>
+struct Dec<vlbm::ST_F64> {
+  using T = double;
+  static __device__ double get(T v, const vlbm::Codec&, int) { return v; }
+};
+template <>
+struct Dec<vlbm::ST_F32> {
+  using T = float;
+  static __device__ double get(T v, const vlbm::Codec&, int) { return v; }
+};
+
+// X = moments of the populations at the given parity (+ flag * pending dQ), FP32
+template <int ST>
+__global__ void k_moments_x(const vlbm::Grid g, const vlbm::Codec cd, int parity, const float* __restrict__ dq,
+                            const int* __restrict__ flag, float* __restrict__ X) {
+  using T = typename Dec<ST>::T;
+  constexpr int K = 8, NQ = 5;
+  const size_t N = (size_t)g.nx * g.ny;
+  const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  const int x = (int)(c % g.nx), y = (int)(c / g.nx);
+  const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x + 1 == g.nx ? 0 : x + 1;
+  const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y + 1 == g.ny ? 0 : y + 1;
+  // cell x - e_i for i = 0..4 (rest, +x, -x, +y, -y)
+  const size_t up[NQ] = {c, (size_t)y * g.nx + xm, (size_t)y * g.nx + xp, (size_t)ym * g.nx + x,
+                         (size_t)yp * g.nx + x};
+  const T* F = static_cast<const T*>(g.f);
+  const bool add = flag && *flag;
+  for (int k = 0; k < K; ++k) {
+    float q = 0.0f;
+    for (int i = 0; i < NQ; ++i) {
+      const int slot = parity == 0 ? i : vlbm::opposite(i);
+      const size_t src = parity == 0 ? c : up[i];
+      q += (float)Dec<ST>::get(F[(size_t)(k * NQ + slot) * g.stride + src], cd, k * NQ + i);
+    }
+    if (add) q += dq[(size_t)k * N + c];
+    X[(size_t)k * N + c] = q;
+  }
+}
+
+// add flag * w_i dQ_k to every population at the given parity (the last pending correction)
+template <int ST>
+__global__ void k_inject(const vlbm::Grid g, int parity, const float* __restrict__ dq, const int* __restrict__ flag,
+                         double wi_d) {
+  using T = typename Dec<ST>::T;
+  constexpr int K = 8, NQ = 5;
+  const size_t N = (size_t)g.nx * g.ny;
+  const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N || !*flag) return;
+  const int x = (int)(c % g.nx), y = (int)(c / g.nx);
+  const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x + 1 == g.nx ? 0 : x + 1;
+  const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y + 1 == g.ny ? 0 : y + 1;
+  const size_t up[NQ] = {c, (size_t)y * g.nx + xm, (size_t)y * g.nx + xp, (size_t)ym * g.nx + x,
+                         (size_t)yp * g.nx + x};
+  T* F = static_cast<T*>(g.f);
+  // same weights, in the same type, as the injecting sweep
+  const T wi = (T)wi_d;
+  const T w0 = vlbm::rest_weight<T, 2>(wi);
+  for (int k = 0; k < K; ++k) {
+    const T d = (T)dq[(size_t)k * N + c];
+    for (int i = 0; i < NQ; ++i) {
+      const int slot = parity == 0 ? i : vlbm::opposite(i);
+      const size_t dst = parity == 0 ? c : up[i];
+      T& v = F[(size_t)(k * NQ + slot) * g.stride + dst];
+      v += (i == 0 ? w0 : wi) * d;
+    }
+  }
+}
+
+struct GateBounds {
+  double corr[8];
+  double divb;
+};
+
+// per-block FP64 partials: [0..7] sum dQ_k^2, [8] sum divc(X)^2, [9] sum divc(X + dQ)^2,
+// [10] non-finite count
+__global__ __launch_bounds__(kGateThreads) void k_gate_partials(const float* __restrict__ X, const float* __restrict__ dq,
+                                                                int nx, int ny, double* __restrict__ partial) {
+  constexpr int NP = 11;
+  __shared__ double sh[kGateThreads / 64][NP];
+  const size_t N = (size_t)nx * ny;
+  double acc[NP];
+  for (int j = 0; j < NP; ++j) acc[j] = 0.0;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (size_t)gridDim.x * blockDim.x) {
+    const int x = (int)(c % nx), y = (int)(c / nx);
+    const size_t xp = (size_t)y * nx + (x + 1 == nx ? 0 : x + 1), xm = (size_t)y * nx + (x == 0 ? nx - 1 : x - 1);
+    const size_t yp = (size_t)(y + 1 == ny ? 0 : y + 1) * nx + x, ym = (size_t)(y == 0 ? ny - 1 : y - 1) * nx + x;
+    for (int k = 0; k < 8; ++k) {
+      const double d = dq[(size_t)k * N + c];
+      acc[k] += d * d;
+      if (!(d - d == 0.0)) acc[10] += 1.0;
+    }
+    const float* Bx = X + 5 * N;
+    const float* By = X + 6 * N;
+    const float* dBx = dq + 5 * N;
+    const float* dBy = dq + 6 * N;
+    const double dv = 0.5 * ((double)Bx[xp] - Bx[xm]) + 0.5 * ((double)By[yp] - By[ym]);
+    const double dv2 = dv + 0.5 * ((double)dBx[xp] - dBx[xm]) + 0.5 * ((double)dBy[yp] - dBy[ym]);
+    acc[8] += dv * dv;
+    acc[9] += dv2 * dv2;
+  }
+  for (int j = 0; j < NP; ++j) {
+    for (int off = 32; off > 0; off >>= 1) acc[j] += __shfl_xor(acc[j], off);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6][j] = acc[j];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < NP) {
+    double s = 0.0;
+    for (int w = 0; w < kGateThreads / 64; ++w) s += sh[w][threadIdx.x];
+    partial[(size_t)blockIdx.x * NP + threadIdx.x] = s;
+  }
+}
+
+__global__ void k_gate_final(const double* __restrict__ partial, int nblk, GateBounds gb, int* __restrict__ flag,
+                             long long* __restrict__ fallbacks) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  constexpr int NP = 11;
+  double t[NP];
+  for (int j = 0; j < NP; ++j) t[j] = 0.0;
+  for (int b = 0; b < nblk; ++b)
+    for (int j = 0; j < NP; ++j) t[j] += partial[(size_t)b * NP + j];
+  bool ok = t[10] == 0.0;
+  for (int k = 0; k < 8; ++k) ok = ok && sqrt(t[k]) <= gb.corr[k];
+  ok = ok && sqrt(t[9]) <= (1.0 + gb.divb) * sqrt(t[8]);
+  *flag = ok ? 1 : 0;
+  if (!ok) *fallbacks += 1;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+struct vlbm_nn {
+  int cin = 0, width = 0, layers = 0;
+  int ci[kMaxLayers] = {}, co[kMaxLayers] = {};
+  size_t woff[kMaxLayers] = {}, boff[kMaxLayers] = {};  // offsets into the flat parameter vector
+  size_t nparam = 0;
+  hipStream_t stream = nullptr;
+  float* d_param = nullptr;  // FP32 master
+  float* d_grad = nullptr;
+  float* d_m = nullptr;
+  float* d_v = nullptr;
+  bf16_t* d_wf[kMaxLayers] = {};  // packed forward B fragments
+  bf16_t* d_wb[kMaxLayers] = {};  // packed data-gradient B fragments (layers >= 1)
+  float* d_norm = nullptr;        // in_mean[8], in_istd[8], out_mean[8], out_std[8], ones[8], zeros[8], out_istd[8]
+  long long t = 0;
+  float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  // activation workspace (grown on demand)
+  size_t ws_positions = 0;
+  bf16_t* d_act[kMaxLayers + 1] = {};  // layer inputs, BF16 NHWC
+  float* d_z[kMaxLayers] = {};         // hidden pre-activations FP32 NHWC
+  float* d_y = nullptr;                // last layer output FP32 NCHW
+  bf16_t* d_dz[2] = {};                // data-gradient ping-pong, BF16 NHWC
+  float* d_part_w = nullptr;
+  float* d_part_b = nullptr;
+  double* d_part_loss = nullptr;
+  double* d_loss = nullptr;
+  int bw_blocks = 0;
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_nn_err;
+
+vlbm_status nfail(vlbm_nn* nn, vlbm_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (nn)
+    nn->err = buf;
+  else
+    g_nn_err = buf;
+  return s;
+}
+
+#define NN_HIP(nn, call)                                                                                   \
+  do {                                                                                                     \
+    hipError_t e_ = (call);                                                                                \
+    if (e_ != hipSuccess)                                                                                  \
+      return nfail(nn, e_ == hipErrorOutOfMemory ? VLBM_ERR_OOM : VLBM_ERR_HIP, "%s: %s", #call,           \
+                   hipGetErrorString(e_));                                                                 \
+  } while (0)
+
+size_t packed_elems(int cin, int cout) { return (size_t)ksteps(cin) * ntiles(cout) * 64 * 8; }
+
+hipError_t launch_conv(int cin, int cout, int mode, const bf16_t* act, const bf16_t* wpack, const float* bias,
+                       int B, int H, int W, bf16_t* out_act, float* out_z, const float* zprev,
+                       const float* oscale, const float* oshift, hipStream_t s) {
+  const dim3 grd(W / TILE, H / TILE, B), blk(kThreads);
+#define CONV_CASE(CI, CO, M)                                                                          \
+  if (cin == CI && cout == CO && mode == M) {                                                        \
+    hipLaunchKernelGGL((k_conv<CI, CO, M>), grd, blk, 0, s, act, wpack, bias, H, W, out_act, out_z, \
+                       zprev, oscale, oshift);                                                      \
+    return hipGetLastError();                                                                       \
+  }
+  CONV_CASE(8, 32, MODE_HIDDEN)
+  CONV_CASE(32, 32, MODE_HIDDEN)
+  CONV_CASE(32, 8, MODE_LAST)
+  CONV_CASE(8, 8, MODE_LAST)
+  CONV_CASE(8, 32, MODE_BWD)
+  CONV_CASE(32, 32, MODE_BWD)
+#undef CONV_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_conv_bw(int cin, int cout, const bf16_t* act, const bf16_t* dz, int B, int H, int W,
+                          float* part_w, float* part_b, int nblk, hipStream_t s) {
+  const dim3 grd(nblk), blk(kThreads);
+  if (cin == 8 && cout == 32) hipLaunchKernelGGL((k_conv_bw<8, 32>), grd, blk, 0, s, act, dz, B, H, W, part_w, part_b);
+  else if (cin == 32 && cout == 32) hipLaunchKernelGGL((k_conv_bw<32, 32>), grd, blk, 0, s, act, dz, B, H, W, part_w, part_b);
+  else if (cin == 32 && cout == 8) hipLaunchKernelGGL((k_conv_bw<32, 8>), grd, blk, 0, s, act, dz, B, H, W, part_w, part_b);
+  else if (cin == 8 && cout == 8) hipLaunchKernelGGL((k_conv_bw<8, 8>), grd, blk, 0, s, act, dz, B, H, W, part_w, part_b);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+vlbm_status repack(vlbm_nn* nn) {
+  for (int l = 0; l < nn->layers; ++l) {
+    const size_t nf = packed_elems(nn->ci[l], nn->co[l]);
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, nn->stream,
+                       nn->d_param + nn->woff[l], nn->ci[l], nn->co[l], 0, nn->d_wf[l]);
+    NN_HIP(nn, hipGetLastError());
+    if (l > 0) {
+      const size_t nb = packed_elems(nn->co[l], nn->ci[l]);
+      hipLaunchKernelGGL(k_pack, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, nn->stream,
+                         nn->d_param + nn->woff[l], nn->ci[l], nn->co[l], 1, nn->d_wb[l]);
+      NN_HIP(nn, hipGetLastError());
+    }
+  }
+  return VLBM_OK;
+}
+
+vlbm_status check_shape(vlbm_nn* nn, int batch, int nx, int ny) {
+  if (batch < 1 || nx < TILE || ny < TILE || nx % TILE || ny % TILE)
+    return nfail(nn, VLBM_ERR_ARG, "batch >= 1 and nx, ny positive multiples of %d required (got %d, %d, %d)",
+                 TILE, batch, nx, ny);
+  if ((size_t)batch * nx * ny > ((size_t)1 << 28)) return nfail(nn, VLBM_ERR_ARG, "batch * nx * ny too large");
+  return VLBM_OK;
+}
+
+vlbm_status ensure_workspace(vlbm_nn* nn, size_t positions) {
+  if (positions <= nn->ws_positions) return VLBM_OK;
+  for (int l = 0; l <= nn->layers; ++l)
+    if (nn->d_act[l]) (void)hipFree(nn->d_act[l]), nn->d_act[l] = nullptr;
+  for (int l = 0; l < nn->layers; ++l)
+    if (nn->d_z[l]) (void)hipFree(nn->d_z[l]), nn->d_z[l] = nullptr;
+  if (nn->d_y) (void)hipFree(nn->d_y), nn->d_y = nullptr;
+  for (int j = 0; j < 2; ++j)
+    if (nn->d_dz[j]) (void)hipFree(nn->d_dz[j]), nn->d_dz[j] = nullptr;
+  nn->ws_positions = 0;
+  NN_HIP(nn, hipMalloc(&nn->d_act[0], positions * nn->cin * sizeof(bf16_t)));
+  for (int l = 0; l < nn->layers; ++l) {
+    NN_HIP(nn, hipMalloc(&nn->d_act[l + 1], positions * nn->co[l] * sizeof(bf16_t)));
+    NN_HIP(nn, hipMalloc(&nn->d_z[l], positions * nn->co[l] * sizeof(float)));
+  }
+  NN_HIP(nn, hipMalloc(&nn->d_y, positions * nn->cin * sizeof(float)));
+  for (int j = 0; j < 2; ++j) NN_HIP(nn, hipMalloc(&nn->d_dz[j], positions * nn->width * sizeof(bf16_t)));
+  nn->ws_positions = positions;
+  return VLBM_OK;
+}
+
+// forward pass; mode_train keeps the pre-activations.  Writes nn->d_y (NCHW FP32),
+// scaled by oscale/oshift.
+vlbm_status forward(vlbm_nn* nn, const float* X, int B, int nx, int ny, bool train, const float* oscale,
+                    const float* oshift, float* yout, hipStream_t s) {
+  const size_t P = (size_t)B * nx * ny;
+  vlbm_status st = ensure_workspace(nn, P);
+  if (st != VLBM_OK) return st;
+  const float* norm = nn->d_norm;
+  hipLaunchKernelGGL(k_prep, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, X, B, nn->cin, ny, nx,
+                     norm + 0, norm + 8, nn->d_act[0]);
+  NN_HIP(nn, hipGetLastError());
+  for (int l = 0; l < nn->layers; ++l) {
+    const bool last = l == nn->layers - 1;
+    NN_HIP(nn, launch_conv(nn->ci[l], nn->co[l], last ? MODE_LAST : MODE_HIDDEN, nn->d_act[l], nn->d_wf[l],
+                           nn->d_param + nn->boff[l], B, ny, nx, last ? nullptr : nn->d_act[l + 1],
+                           last ? yout : (train ? nn->d_z[l] : nullptr), nullptr, oscale, oshift, s));
+  }
+  return VLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vlbm_status vlbm_nn_create(int32_t cin, int32_t width, int32_t layers, void* stream, vlbm_nn** out) {
+  if (!out) return nfail(nullptr, VLBM_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (cin != 8 || width != 32 || layers < 1 || layers > kMaxLayers)
+    return nfail(nullptr, VLBM_ERR_ARG, "supported: cin = 8, width = 32, 1 <= layers <= %d", kMaxLayers);
+  vlbm_nn* nn = new (std::nothrow) vlbm_nn();
+  if (!nn) return nfail(nullptr, VLBM_ERR_OOM, "host allocation failed");
+  nn->cin = cin;
+  nn->width = width;
+  nn->layers = layers;
+  nn->stream = static_cast<hipStream_t>(stream);
+  size_t off = 0;
+  for (int l = 0; l < layers; ++l) {
+    nn->ci[l] = l == 0 ? cin : width;
+    nn->co[l] = l == layers - 1 ? cin : width;
+    nn->woff[l] = off;
+    off += (size_t)nn->co[l] * nn->ci[l] * 9;
+    nn->boff[l] = off;
+    off += nn->co[l];
+  }
+  nn->nparam = off;
+  hipError_t e = hipMalloc(&nn->d_param, off * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&nn->d_grad, off * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&nn->d_m, off * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&nn->d_v, off * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&nn->d_norm, 7 * 8 * sizeof(float));
+  for (int l = 0; l < layers && e == hipSuccess; ++l) {
+    e = hipMalloc(&nn->d_wf[l], packed_elems(nn->ci[l], nn->co[l]) * sizeof(bf16_t));
+    if (e == hipSuccess && l > 0) e = hipMalloc(&nn->d_wb[l], packed_elems(nn->co[l], nn->ci[l]) * sizeof(bf16_t));
+  }
+  nn->bw_blocks = 512;
+  if (e == hipSuccess) e = hipMalloc(&nn->d_part_w, (size_t)nn->bw_blocks * width * 9 * width * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&nn->d_part_b, (size_t)nn->bw_blocks * width * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&nn->d_part_loss, 1024 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&nn->d_loss, sizeof(double));
+  if (e != hipSuccess) {
+    vlbm_nn_destroy(nn);
+    return nfail(nullptr, VLBM_ERR_OOM, "device allocation failed: %s", hipGetErrorString(e));
+  }
+  std::vector<float> zero(off, 0.0f);
+  e = hipMemcpy(nn->d_param, zero.data(), off * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(nn->d_m, zero.data(), off * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(nn->d_v, zero.data(), off * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(nn->d_grad, zero.data(), off * sizeof(float), hipMemcpyHostToDevice);
+  float norm[56];
+  for (int c = 0; c < 8; ++c) {
+    norm[c] = 0.0f;       // in_mean
+    norm[8 + c] = 1.0f;   // in_istd
+    norm[16 + c] = 0.0f;  // out_mean
+    norm[24 + c] = 1.0f;  // out_std
+    norm[32 + c] = 1.0f;  // ones
+    norm[40 + c] = 0.0f;  // zeros
+    norm[48 + c] = 1.0f;  // out_istd
+  }
+  if (e == hipSuccess) e = hipMemcpy(nn->d_norm, norm, sizeof norm, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    vlbm_nn_destroy(nn);
+    return nfail(nullptr, VLBM_ERR_HIP, "initialisation: %s", hipGetErrorString(e));
+  }
+  if (repack(nn) != VLBM_OK || hipStreamSynchronize(nn->stream) != hipSuccess) {
+    const std::string msg = nn->err;
+    vlbm_nn_destroy(nn);
+    return nfail(nullptr, VLBM_ERR_HIP, "weight packing: %s", msg.c_str());
+  }
+  *out = nn;
+  return VLBM_OK;
+}
+
+void vlbm_nn_destroy(vlbm_nn* nn) {
+  if (!nn) return;
+  float* fl[] = {nn->d_param, nn->d_grad, nn->d_m, nn->d_v, nn->d_norm, nn->d_y, nn->d_part_w, nn->d_part_b};
+  for (float* p : fl)
+    if (p) (void)hipFree(p);
+  for (int l = 0; l < kMaxLayers; ++l) {
+    if (nn->d_wf[l]) (void)hipFree(nn->d_wf[l]);
+    if (nn->d_wb[l]) (void)hipFree(nn->d_wb[l]);
+    if (nn->d_z[l]) (void)hipFree(nn->d_z[l]);
+  }
+  for (int l = 0; l <= kMaxLayers; ++l)
+    if (nn->d_act[l]) (void)hipFree(nn->d_act[l]);
+  for (int j = 0; j < 2; ++j)
+    if (nn->d_dz[j]) (void)hipFree(nn->d_dz[j]);
+  if (nn->d_part_loss) (void)hipFree(nn->d_part_loss);
+  if (nn->d_loss) (void)hipFree(nn->d_loss);
+  delete nn;
+}
+
+const char* vlbm_nn_last_error(const vlbm_nn* nn) { return nn ? nn->err.c_str() : g_nn_err.c_str(); }
+
+vlbm_status vlbm_nn_num_params(const vlbm_nn* nn, size_t* n) {
+  if (!nn || !n) return VLBM_ERR_ARG;
+  *n = nn->nparam;
+  return VLBM_OK;
+}
+
+vlbm_status vlbm_nn_set_weights(vlbm_nn* nn, const float* w, size_t n) {
+  if (!nn) return VLBM_ERR_ARG;
+  if (!w || n != nn->nparam) return nfail(nn, VLBM_ERR_ARG, "need %zu weights", nn->nparam);
+  for (size_t j = 0; j < n; ++j)
+    if (!std::isfinite(w[j])) return nfail(nn, VLBM_ERR_ARG, "weight %zu not finite", j);
+  NN_HIP(nn, hipMemcpyAsync(nn->d_param, w, n * sizeof(float), hipMemcpyHostToDevice, nn->stream));
+  NN_HIP(nn, hipMemsetAsync(nn->d_m, 0, n * sizeof(float), nn->stream));
+  NN_HIP(nn, hipMemsetAsync(nn->d_v, 0, n * sizeof(float), nn->stream));
+  nn->t = 0;
+  vlbm_status st = repack(nn);
+  if (st != VLBM_OK) return st;
+  NN_HIP(nn, hipStreamSynchronize(nn->stream));
+  return VLBM_OK;
+}
+
+vlbm_status vlbm_nn_get_weights(const vlbm_nn* nn_c, float* w, size_t n) {
+  vlbm_nn* nn = const_cast<vlbm_nn*>(nn_c);
+  if (!nn) return VLBM_ERR_ARG;
+  if (!w || n != nn->nparam) return nfail(nn, VLBM_ERR_ARG, "need %zu weights", nn->nparam);
+  NN_HIP(nn, hipMemcpyAsync(w, nn->d_param, n * sizeof(float), hipMemcpyDeviceToHost, nn->stream));
+  NN_HIP(nn, hipStreamSynchronize(nn->stream));
+  return VLBM_OK;
+}
+
+vlbm_status vlbm_nn_set_norm(vlbm_nn* nn, const double* in_mean, const double* in_std, const double* out_mean,
+                             const double* out_std) {
+  if (!nn) return VLBM_ERR_ARG;
+  if (!in_mean || !in_std || !out_mean || !out_std) return nfail(nn, VLBM_ERR_ARG, "NULL normalisation array");
+  float norm[56];
+  for (int c = 0; c < 8; ++c) {
+    if (!(in_std[c] > 0.0) || !(out_std[c] > 0.0) || !std::isfinite(in_mean[c]) || !std::isfinite(out_mean[c]))
+      return nfail(nn, VLBM_ERR_ARG, "channel %d: std must be > 0 and means finite", c);
+    norm[c] = (float)in_mean[c];
+    norm[8 + c] = (float)(1.0 / in_std[c]);
+    norm[16 + c] = (float)out_mean[c];
+    norm[24 + c] = (float)out_std[c];
+    norm[32 + c] = 1.0f;
+    norm[40 + c] = 0.0f;
+    norm[48 + c] = (float)(1.0 / out_std[c]);
+  }
+  NN_HIP(nn, hipMemcpyAsync(nn->d_norm, norm, sizeof norm, hipMemcpyHostToDevice, nn->stream));
+  NN_HIP(nn, hipStreamSynchronize(nn->stream));
+  return VLBM_OK;
+}
+
+vlbm_status vlbm_nn_forward(vlbm_nn* nn, const float* X, float* dQ, int32_t batch, int32_t nx, int32_t ny) {
+  if (!nn) return VLBM_ERR_ARG;
+  if (!X || !dQ) return nfail(nn, VLBM_ERR_ARG, "NULL array");
+  vlbm_status st = check_shape(nn, batch, nx, ny);
+  if (st != VLBM_OK) return st;
+  // dQ = out_mean + out_std * y
+  return forward(nn, X, batch, nx, ny, false, nn->d_norm + 24, nn->d_norm + 16, dQ, nn->stream);
+}
+
+vlbm_status vlbm_nn_loss_grad(vlbm_nn* nn, const float* X, const float* T, int32_t B, int32_t nx, int32_t ny,
+                              double* loss, float* grad) {
+  if (!nn) return VLBM_ERR_ARG;
+  if (!X || !T) return nfail(nn, VLBM_ERR_ARG, "NULL array");
+  vlbm_status st = check_shape(nn, B, nx, ny);
+  if (st != VLBM_OK) return st;
+  // forward in standardised units (scale 1, shift 0), output into the workspace
+  st = ensure_workspace(nn, (size_t)B * nx * ny);
+  if (st != VLBM_OK) return st;
+  st = forward(nn, X, B, nx, ny, true, nn->d_norm + 32, nn->d_norm + 40, nn->d_y, nn->stream);
+  if (st != VLBM_OK) return st;
+  const int L = nn->layers;
+  const int lblocks = 1024;
+  hipLaunchKernelGGL(k_loss, dim3(lblocks), dim3(kThreads), 0, nn->stream, nn->d_y, T, B, nn->cin, ny, nx,
+                     nn->d_norm + 16, nn->d_norm + 48, nn->d_dz[0], nn->d_part_loss);
+  NN_HIP(nn, hipGetLastError());
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, nn->stream, nn->d_part_loss, lblocks, nn->d_loss);
+  NN_HIP(nn, hipGetLastError());
+  // backward: dZ of layer l lives in d_dz[cur]
+  int cur = 0;
+  const int ntile = B * (nx / TILE) * (ny / TILE);
+  const int nblk = ntile < nn->bw_blocks ? ntile : nn->bw_blocks;
+  for (int l = L - 1; l >= 0; --l) {
+    NN_HIP(nn, launch_conv_bw(nn->ci[l], nn->co[l], nn->d_act[l], nn->d_dz[cur], B, ny, nx, nn->d_part_w,
+                              nn->d_part_b, nblk, nn->stream));
+    const int nred = nn->co[l] * nn->ci[l] * 9 + nn->co[l];
+    hipLaunchKernelGGL(k_reduce_grads, dim3((nred + 255) / 256), dim3(256), 0, nn->stream, nn->d_part_w,
+                       nn->d_part_b, nblk, nn->ci[l], nn->co[l], nn->d_grad + nn->woff[l], nn->d_grad + nn->boff[l]);
+    NN_HIP(nn, hipGetLastError());
+    if (l > 0) {
+      // dA_{l-1} = conv(dZ_l, mirrored W_l); dZ_{l-1} = dA_{l-1} * GELU'(z_{l-1})
+      NN_HIP(nn, launch_conv(nn->co[l], nn->ci[l], MODE_BWD, nn->d_dz[cur], nn->d_wb[l], nullptr, B, ny, nx,
+                             nn->d_dz[1 - cur], nullptr, nn->d_z[l - 1], nullptr, nullptr, nn->stream));
+      cur = 1 - cur;
+    }
+  }
+  if (loss) NN_HIP(nn, hipMemcpyAsync(loss, nn->d_loss, sizeof(double), hipMemcpyDeviceToHost, nn->stream));
+  if (grad)
+    NN_HIP(nn, hipMemcpyAsync(grad, nn->d_grad, nn->nparam * sizeof(float), hipMemcpyDeviceToHost, nn->stream));
+  if (loss || grad) NN_HIP(nn, hipStreamSynchronize(nn->stream));
+  return VLBM_OK;
+}
+
+vlbm_status vlbm_nn_adam_config(vlbm_nn* nn, float beta1, float beta2, float eps) {
+  if (!nn) return VLBM_ERR_ARG;
+  if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+    return nfail(nn, VLBM_ERR_ARG, "betas in [0, 1), eps > 0 required");
+  nn->b1 = beta1;
+  nn->b2 = beta2;
+  nn->eps = eps;
+  return VLBM_OK;
+}
+
+vlbm_status vlbm_nn_adam_step(vlbm_nn* nn, float lr) {
+  if (!nn) return VLBM_ERR_ARG;
+  if (!(lr >= 0.0f) || !std::isfinite(lr)) return nfail(nn, VLBM_ERR_ARG, "lr must be >= 0");
+  nn->t += 1;
+  const float c1 = (float)(1.0 - std::pow((double)nn->b1, (double)nn->t));
+  const float c2 = (float)(1.0 - std::pow((double)nn->b2, (double)nn->t));
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)((nn->nparam + 255) / 256)), dim3(256), 0, nn->stream, nn->d_param,
+                     nn->d_grad, nn->d_m, nn->d_v, nn->nparam, lr, nn->b1, nn->b2, nn->eps, c1, c2);
+  NN_HIP(nn, hipGetLastError());
+  return repack(nn);
+}
+
+vlbm_status vlbm_nn_train_step(vlbm_nn* nn, const float* X, const float* T, int32_t batch, int32_t nx, int32_t ny,
+                               float lr, double* loss) {
+  vlbm_status st = vlbm_nn_loss_grad(nn, X, T, batch, nx, ny, loss, nullptr);
+  if (st != VLBM_OK) return st;
+  return vlbm_nn_adam_step(nn, lr);
+}
+
+vlbm_status vlbm_restrict(const float* Qf, int32_t K, int32_t nx, int32_t ny, int32_t nz, int32_t r, float* Qc,
+                          void* stream) {
+  if (!Qf || !Qc || K < 1 || r < 1 || nx < 1 || ny < 1 || nz < 1) return VLBM_ERR_ARG;
+  const int rz = nz > 1 ? r : 1;
+  if (nx % r || ny % r || nz % rz) return VLBM_ERR_ARG;
+  const size_t n = (size_t)K * (nx / r) * (ny / r) * (nz / rz);
+  hipLaunchKernelGGL(k_restrict, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, static_cast<hipStream_t>(stream),
+                     Qf, K, nx, ny, nz, r, rz, Qc);
+  return hipGetLastError() == hipSuccess ? VLBM_OK : VLBM_ERR_HIP;
+}
+
+vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const double* bound_corr, double bound_divb,
+                                int64_t* n_fallback) {
+  if (!c || !nn) return VLBM_ERR_ARG;
+  if (!c->initialized) return VLBM_ERR_STATE;
+  if (n < 0 || !bound_corr) return nfail(nn, VLBM_ERR_ARG, "n >= 0 and bound_corr required");
+  if (c->D != 2 || c->K != 8 || c->p.model != VLBM_IDEAL || c->N > (1LL << 28) ||
+      (c->p.storage != VLBM_F32 && c->p.storage != VLBM_F64))
+    return nfail(nn, VLBM_ERR_ARG, "corrected stepping needs a 2D ideal-MHD context with FP32 or FP64 storage");
+  vlbm_status st = check_shape(nn, 1, c->p.nx, c->p.ny);
+  if (st != VLBM_OK) return st;
+  GateBounds gb;
+  for (int k = 0; k < 8; ++k) {
+    if (!(bound_corr[k] >= 0.0)) return nfail(nn, VLBM_ERR_ARG, "bound_corr[%d] must be >= 0", k);
+    gb.corr[k] = bound_corr[k];
+  }
+  if (!(bound_divb >= 0.0)) return nfail(nn, VLBM_ERR_ARG, "bound_divb must be >= 0");
+  gb.divb = bound_divb;
+  const size_t N = (size_t)c->N;
+  hipStream_t s = c->stream;
+  float *X = nullptr, *dq[2] = {nullptr, nullptr};
+  int* flag = nullptr;  // flag[0..1] ping-pong
+  long long* fb = nullptr;
+  double* gpart = nullptr;
+  const int gblk = (int)std::min<size_t>(256, (N + kGateThreads - 1) / kGateThreads);
+  auto cleanup = [&]() {
+    if (X) (void)hipFree(X);
+    for (int j = 0; j < 2; ++j)
+      if (dq[j]) (void)hipFree(dq[j]);
+    if (flag) (void)hipFree(flag);
+    if (fb) (void)hipFree(fb);
+    if (gpart) (void)hipFree(gpart);
+  };
+  hipError_t e = hipMalloc(&X, 8 * N * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&dq[0], 8 * N * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&dq[1], 8 * N * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&flag, 2 * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&fb, sizeof(long long));
+  if (e == hipSuccess) e = hipMalloc(&gpart, (size_t)gblk * 11 * sizeof(double));
+  if (e == hipSuccess) e = hipMemsetAsync(flag, 0, 2 * sizeof(int), s);
+  if (e == hipSuccess) e = hipMemsetAsync(fb, 0, sizeof(long long), s);
+  const dim3 cgrid((unsigned)((N + 255) / 256)), cblk(256);
+  int cur = 0;  // dq[cur], flag[cur]: the pending correction (not yet in the populations)
+  for (int32_t step = 0; step < n && e == hipSuccess; ++step) {
+    const int par = (int)(c->step & 1);
+    if (c->p.storage == VLBM_F32)
+      hipLaunchKernelGGL(k_moments_x<vlbm::ST_F32>, cgrid, cblk, 0, s, c->g, c->cd, par, dq[cur], flag + cur, X);
+    else
+      hipLaunchKernelGGL(k_moments_x<vlbm::ST_F64>, cgrid, cblk, 0, s, c->g, c->cd, par, dq[cur], flag + cur, X);
+    e = hipGetLastError();
+    if (e != hipSuccess) break;
+    st = forward(nn, X, 1, c->p.nx, c->p.ny, false, nn->d_norm + 24, nn->d_norm + 16, dq[1 - cur], s);
+    if (st != VLBM_OK) {
+      cleanup();
+      return st;
+    }
+    hipLaunchKernelGGL(k_gate_partials, dim3(gblk), dim3(kGateThreads), 0, s, X, dq[1 - cur], c->p.nx, c->p.ny, gpart);
+    hipLaunchKernelGGL(k_gate_final, dim3(1), dim3(1), 0, s, gpart, gblk, gb, flag + (1 - cur), fb);
+    e = hipGetLastError();
+    if (e != hipSuccess) break;
+    e = vlbm::launch_sweep_inj(c->L, c->g, c->ph, c->cd, par, dq[cur], flag + cur);
+    ++c->step;
+    cur = 1 - cur;
+  }
+  if (e == hipSuccess && n > 0) {
+    // the last accepted correction goes into the populations
+    const int par = (int)(c->step & 1);
+    if (c->p.storage == VLBM_F32)
+      hipLaunchKernelGGL(k_inject<vlbm::ST_F32>, cgrid, cblk, 0, s, c->g, par, dq[cur], flag + cur, c->ph.wi);
+    else
+      hipLaunchKernelGGL(k_inject<vlbm::ST_F64>, cgrid, cblk, 0, s, c->g, par, dq[cur], flag + cur, c->ph.wi);
+    e = hipGetLastError();
+  }
+  long long nfb = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&nfb, fb, sizeof nfb, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  cleanup();
+  if (e != hipSuccess)
+    return nfail(nn, e == hipErrorOutOfMemory ? VLBM_ERR_OOM : VLBM_ERR_HIP, "corrected step: %s", hipGetErrorString(e));
+  if (n_fallback) *n_fallback = nfb;
+  return VLBM_OK;
+}
+
+}  // extern "C"
