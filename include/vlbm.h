@@ -74,7 +74,8 @@ typedef enum { VLBM_BC_PERIODIC = 0, VLBM_BC_INFLOW_EQ = 1, VLBM_BC_ZERO_GRAD = 
 typedef struct {
   uint32_t struct_size;   /* sizeof(vlbm_params); checked for ABI versioning */
   int32_t lattice;        /* vlbm_lattice */
-  int32_t nx, ny, nz;     /* lattice extent; nz = 1 for D2Q5; each >= 1 */
+  int32_t nx, ny, nz;     /* lattice extent, each >= 1; for D2Q5, nz > 1 is a batch of nz
+                             independent periodic nx x ny lattices (no coupling along z) */
   int32_t model;          /* vlbm_model (resistive requires D3Q7) */
   int32_t storage;        /* vlbm_storage */
   int32_t powell;         /* 1: inject the Powell source (Sec. 2.3), 0: off */

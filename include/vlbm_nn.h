@@ -24,7 +24,9 @@
  * Normalisation: inputs are standardised per channel, x = (X - in_mean)/in_std;
  * the network output y is a standardised correction, dQ = out_mean + out_std * y.
  *
- * All device arrays are FP32, [batch][channel][ny][nx] (x fastest).  Every call is
+ * All device arrays are FP32, channel-major [channel][batch][ny][nx] (x fastest) --
+ * the layout of the moments of a batched 2D context (include/vlbm.h, D2Q5 with
+ * nz = batch), which the network reads directly.  Every call is
  * stream-ordered on the network's stream; calls that return host values
  * synchronise it.  Errors as in vlbm.h; vlbm_nn_last_error() gives the message.
  */
@@ -79,10 +81,12 @@ vlbm_status vlbm_nn_train_step(vlbm_nn* nn, const float* X, const float* T, int3
                                int32_t nx, int32_t ny, float lr, double* loss);
 
 /* Block mean of a moment field: Qf (device FP32 [K][nz][ny][nx]) -> Qc (device FP32
- * [K][nz/rz][ny/r][nx/r]) with rz = r if nz > 1 else 1.  Accumulated in FP64.  Every
- * extent must be divisible by its factor.  stream: hipStream_t or NULL. */
+ * [K][nz/rz][ny/r][nx/r]); rz = r restricts a 3D field, rz = 1 a batch of 2D fields.
+ * If minus (device, the shape of Qc) is not NULL it is subtracted (the target of a
+ * training pair: restricted fine state minus the plain coarse step).  Accumulated in
+ * FP64.  Every extent must be divisible by its factor.  stream: hipStream_t or NULL. */
 vlbm_status vlbm_restrict(const float* Qf, int32_t K, int32_t nx, int32_t ny, int32_t nz,
-                          int32_t r, float* Qc, void* stream);
+                          int32_t r, int32_t rz, const float* minus, float* Qc, void* stream);
 
 /* n coarse steps with the learned correction.  Per step: the moments X of the
  * current populations (including the pending correction), dQ = network(X), the gate
@@ -91,8 +95,9 @@ vlbm_status vlbm_restrict(const float* Qf, int32_t K, int32_t nx, int32_t ny, in
  * the fallback counter is incremented), then the sweep, with the previous step's
  * accepted dQ added as w_i dQ_k to the populations before the collision.  After the
  * last step the pending dQ is added to the populations, so vlbm_moments sees the
- * corrected state.  The context must be a 2D ideal-MHD context (K = cin = 8) whose
- * extent the network supports.  bound_corr: host, K doubles.  *n_fallback (host, may
+ * corrected state.  The context must be a 2D ideal-MHD context (K = cin = 8, FP32 or
+ * FP64 storage; nz = batch of independent lattices, gated together) whose extent the
+ * network supports.  bound_corr: host, K doubles.  *n_fallback (host, may
  * be NULL) receives the number of fallbacks in this call.  Synchronises. */
 vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const double* bound_corr,
                                 double bound_divb, int64_t* n_fallback);

@@ -125,9 +125,12 @@ template <typename T>
 __device__ __forceinline__ T ld(void* base, size_t plane_bytes, int plane, unsigned off) {
   return *(const VLBM_GLOBAL T*)(plane_base(base, plane_bytes, plane) + off);
 }
+// Stores are nontemporal: the written populations are not read again before the
+// next sweep, and keeping them out of the caches measurably raised the sweep's
+// bandwidth on gfx950.
 template <typename T>
 __device__ __forceinline__ void st(void* base, size_t plane_bytes, int plane, unsigned off, T v) {
-  *(VLBM_GLOBAL T*)(plane_base(base, plane_bytes, plane) + off) = v;
+  __builtin_nontemporal_store(v, (VLBM_GLOBAL T*)(plane_base(base, plane_bytes, plane) + off));
 }
 
 // INJ: before the collision add flag * w_i dq[k][c] to f_{k,i} (the learned coarse

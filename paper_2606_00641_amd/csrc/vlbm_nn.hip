@@ -94,7 +94,7 @@ __global__ void k_pack(const float* __restrict__ W, int CI, int CO, int flip, bf
 // ---------------------------------------------------------------------------
 // act: BF16 NHWC [B][H][W][CIN].  Output, by MODE:
 //  HIDDEN: z = conv + bias; out_act (BF16 NHWC COUT) = GELU(z); out_z (FP32 NHWC, optional) = z
-//  LAST:   out_z (FP32 NCHW [B][COUT][H][W]) = (conv + bias) * oscale + oshift
+//  LAST:   out_z (FP32 channel-major [COUT][B][H][W]) = (conv + bias) * oscale + oshift
 //  BWD:    out_act (BF16 NHWC COUT) = conv * GELU'(zprev), zprev FP32 NHWC COUT
 template <int CIN, int COUT, int MODE>
 __global__ __launch_bounds__(kThreads) void k_conv(const bf16_t* __restrict__ act, const bf16_t* __restrict__ wpack,
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(kThreads) void k_conv(const bf16_t* __restrict__ ac
           if (out_z) out_z[nhwc] = z;
         } else if constexpr (MODE == MODE_LAST) {
           const float z = v + bias[co];
-          out_z[(((size_t)b * COUT + co) * H + y) * W + x] = z * oscale[co] + oshift[co];
+          out_z[(((size_t)co * gridDim.z + b) * H + y) * W + x] = z * oscale[co] + oshift[co];
         } else {
           out_act[nhwc] = f2bf(v * gelu_grad(zprev[nhwc]));
         }
@@ -302,17 +302,16 @@ __global__ void k_reduce_grads(const float* __restrict__ part_w, const float* __
   }
 }
 
-// raw moments X (FP32 NCHW [B][C][H][W]) -> standardised BF16 NHWC (C = 8)
+// raw moments X (FP32 channel-major [C][B][H][W]) -> standardised BF16 NHWC (C = 8)
 __global__ void k_prep(const float* __restrict__ X, int B, int C, int H, int W, const float* __restrict__ mean,
                        const float* __restrict__ istd, bf16_t* __restrict__ out) {
-  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t HW = (size_t)H * W;
-  if (q >= (size_t)B * HW) return;
-  const size_t b = q / HW, p = q % HW;
-  for (int c = 0; c < C; ++c) out[q * C + c] = f2bf((X[(b * C + c) * HW + p] - mean[c]) * istd[c]);
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;  // = b * HW + p
+  const size_t BHW = (size_t)B * H * W;
+  if (q >= BHW) return;
+  for (int c = 0; c < C; ++c) out[q * C + c] = f2bf((X[(size_t)c * BHW + q] - mean[c]) * istd[c]);
 }
 
-// MSE on standardised outputs: y (FP32 NCHW), target T raw -> (T - mean) * istd.
+// MSE on standardised outputs: y (FP32 [C][B][H][W]), target T raw -> (T - mean) * istd.
 // dZ = 2 (y - t) / n as BF16 NHWC; per-block FP64 partial sums of (y - t)^2.
 __global__ __launch_bounds__(kThreads) void k_loss(const float* __restrict__ y, const float* __restrict__ T, int B,
                                                    int C, int H, int W, const float* __restrict__ mean,
@@ -324,11 +323,12 @@ __global__ __launch_bounds__(kThreads) void k_loss(const float* __restrict__ y, 
   const double inv_n = 1.0 / (double)n;
   double acc = 0.0;
   for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
-    const size_t b = q / (C * HW), c = (q / HW) % C, p = q % HW;
+    const size_t BHW = (size_t)B * HW;
+    const size_t c = q / BHW, bp = q % BHW;  // bp = b * HW + p
     const float t = (T[q] - mean[c]) * istd[c];
     const float d = y[q] - t;
     acc += (double)d * (double)d;
-    dz[(b * HW + p) * C + c] = f2bf((float)(2.0 * inv_n) * d);
+    dz[bp * C + c] = f2bf((float)(2.0 * inv_n) * d);
   }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
@@ -361,9 +361,9 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
   p[q] -= lr * (mq / c1) / (sqrtf(vq / c2) + eps);
 }
 
-// block mean of a moment field (FP64 accumulation)
+// block mean of a moment field (FP64 accumulation), minus an optional field
 __global__ void k_restrict(const float* __restrict__ Qf, int K, int nx, int ny, int nz, int r, int rz,
-                           float* __restrict__ Qc) {
+                           const float* __restrict__ minus, float* __restrict__ Qc) {
   const int cx = nx / r, cy = ny / r, cz = nz / rz;
   const size_t nc = (size_t)cx * cy * cz;
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -376,7 +376,9 @@ __global__ void k_restrict(const float* __restrict__ Qf, int K, int nx, int ny, 
     for (int dy = 0; dy < r; ++dy)
       for (int dx = 0; dx < r; ++dx)
         s += Qf[(size_t)k * nx * ny * nz + ((size_t)(z * rz + dz) * ny + (y * r + dy)) * nx + (x * r + dx)];
-  Qc[q] = (float)(s / (double)(r * r * rz));
+  double v = s / (double)(r * r * rz);
+  if (minus) v -= (double)minus[q];
+  Qc[q] = (float)v;
 }
 
 // ---------------------------------------------------------------------------
@@ -401,15 +403,17 @@ __global__ void k_moments_x(const vlbm::Grid g, const vlbm::Codec cd, int parity
                             const int* __restrict__ flag, float* __restrict__ X) {
   using T = typename Dec<ST>::T;
   constexpr int K = 8, NQ = 5;
-  const size_t N = (size_t)g.nx * g.ny;
+  const size_t N = (size_t)g.nx * g.ny * g.nz;
   const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= N) return;
-  const int x = (int)(c % g.nx), y = (int)(c / g.nx);
+  // batch of independent 2D lattices along z
+  const size_t sl = (c / ((size_t)g.nx * g.ny)) * g.nx * g.ny;
+  const int x = (int)(c % g.nx), y = (int)((c / g.nx) % g.ny);
   const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x + 1 == g.nx ? 0 : x + 1;
   const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y + 1 == g.ny ? 0 : y + 1;
   // cell x - e_i for i = 0..4 (rest, +x, -x, +y, -y)
-  const size_t up[NQ] = {c, (size_t)y * g.nx + xm, (size_t)y * g.nx + xp, (size_t)ym * g.nx + x,
-                         (size_t)yp * g.nx + x};
+  const size_t up[NQ] = {c, sl + (size_t)y * g.nx + xm, sl + (size_t)y * g.nx + xp, sl + (size_t)ym * g.nx + x,
+                         sl + (size_t)yp * g.nx + x};
   const T* F = static_cast<const T*>(g.f);
   const bool add = flag && *flag;
   for (int k = 0; k < K; ++k) {
@@ -430,14 +434,15 @@ __global__ void k_inject(const vlbm::Grid g, int parity, const float* __restrict
                          double wi_d) {
   using T = typename Dec<ST>::T;
   constexpr int K = 8, NQ = 5;
-  const size_t N = (size_t)g.nx * g.ny;
+  const size_t N = (size_t)g.nx * g.ny * g.nz;
   const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= N || !*flag) return;
-  const int x = (int)(c % g.nx), y = (int)(c / g.nx);
+  const size_t sl = (c / ((size_t)g.nx * g.ny)) * g.nx * g.ny;
+  const int x = (int)(c % g.nx), y = (int)((c / g.nx) % g.ny);
   const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x + 1 == g.nx ? 0 : x + 1;
   const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y + 1 == g.ny ? 0 : y + 1;
-  const size_t up[NQ] = {c, (size_t)y * g.nx + xm, (size_t)y * g.nx + xp, (size_t)ym * g.nx + x,
-                         (size_t)yp * g.nx + x};
+  const size_t up[NQ] = {c, sl + (size_t)y * g.nx + xm, sl + (size_t)y * g.nx + xp, sl + (size_t)ym * g.nx + x,
+                         sl + (size_t)yp * g.nx + x};
   T* F = static_cast<T*>(g.f);
   // same weights, in the same type, as the injecting sweep
   const T wi = (T)wi_d;
@@ -461,16 +466,17 @@ struct GateBounds {
 // per-block FP64 partials: [0..7] sum dQ_k^2, [8] sum divc(X)^2, [9] sum divc(X + dQ)^2,
 // [10] non-finite count
 __global__ __launch_bounds__(kGateThreads) void k_gate_partials(const float* __restrict__ X, const float* __restrict__ dq,
-                                                                int nx, int ny, double* __restrict__ partial) {
+                                                                int nx, int ny, int nb, double* __restrict__ partial) {
   constexpr int NP = 11;
   __shared__ double sh[kGateThreads / 64][NP];
-  const size_t N = (size_t)nx * ny;
+  const size_t N = (size_t)nx * ny * nb;
   double acc[NP];
   for (int j = 0; j < NP; ++j) acc[j] = 0.0;
   for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (size_t)gridDim.x * blockDim.x) {
-    const int x = (int)(c % nx), y = (int)(c / nx);
-    const size_t xp = (size_t)y * nx + (x + 1 == nx ? 0 : x + 1), xm = (size_t)y * nx + (x == 0 ? nx - 1 : x - 1);
-    const size_t yp = (size_t)(y + 1 == ny ? 0 : y + 1) * nx + x, ym = (size_t)(y == 0 ? ny - 1 : y - 1) * nx + x;
+    const size_t sl = (c / ((size_t)nx * ny)) * nx * ny;  // batch slice
+    const int x = (int)(c % nx), y = (int)((c / nx) % ny);
+    const size_t xp = sl + (size_t)y * nx + (x + 1 == nx ? 0 : x + 1), xm = sl + (size_t)y * nx + (x == 0 ? nx - 1 : x - 1);
+    const size_t yp = sl + (size_t)(y + 1 == ny ? 0 : y + 1) * nx + x, ym = sl + (size_t)(y == 0 ? ny - 1 : y - 1) * nx + x;
     for (int k = 0; k < 8; ++k) {
       const double d = dq[(size_t)k * N + c];
       acc[k] += d * d;
@@ -894,14 +900,13 @@ vlbm_status vlbm_nn_train_step(vlbm_nn* nn, const float* X, const float* T, int3
   return vlbm_nn_adam_step(nn, lr);
 }
 
-vlbm_status vlbm_restrict(const float* Qf, int32_t K, int32_t nx, int32_t ny, int32_t nz, int32_t r, float* Qc,
-                          void* stream) {
-  if (!Qf || !Qc || K < 1 || r < 1 || nx < 1 || ny < 1 || nz < 1) return VLBM_ERR_ARG;
-  const int rz = nz > 1 ? r : 1;
+vlbm_status vlbm_restrict(const float* Qf, int32_t K, int32_t nx, int32_t ny, int32_t nz, int32_t r, int32_t rz,
+                          const float* minus, float* Qc, void* stream) {
+  if (!Qf || !Qc || K < 1 || r < 1 || rz < 1 || nx < 1 || ny < 1 || nz < 1) return VLBM_ERR_ARG;
   if (nx % r || ny % r || nz % rz) return VLBM_ERR_ARG;
   const size_t n = (size_t)K * (nx / r) * (ny / r) * (nz / rz);
   hipLaunchKernelGGL(k_restrict, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, static_cast<hipStream_t>(stream),
-                     Qf, K, nx, ny, nz, r, rz, Qc);
+                     Qf, K, nx, ny, nz, r, rz, minus, Qc);
   return hipGetLastError() == hipSuccess ? VLBM_OK : VLBM_ERR_HIP;
 }
 
@@ -913,7 +918,7 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
   if (c->D != 2 || c->K != 8 || c->p.model != VLBM_IDEAL || c->N > (1LL << 28) ||
       (c->p.storage != VLBM_F32 && c->p.storage != VLBM_F64))
     return nfail(nn, VLBM_ERR_ARG, "corrected stepping needs a 2D ideal-MHD context with FP32 or FP64 storage");
-  vlbm_status st = check_shape(nn, 1, c->p.nx, c->p.ny);
+  vlbm_status st = check_shape(nn, c->p.nz, c->p.nx, c->p.ny);
   if (st != VLBM_OK) return st;
   GateBounds gb;
   for (int k = 0; k < 8; ++k) {
@@ -955,12 +960,13 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
       hipLaunchKernelGGL(k_moments_x<vlbm::ST_F64>, cgrid, cblk, 0, s, c->g, c->cd, par, dq[cur], flag + cur, X);
     e = hipGetLastError();
     if (e != hipSuccess) break;
-    st = forward(nn, X, 1, c->p.nx, c->p.ny, false, nn->d_norm + 24, nn->d_norm + 16, dq[1 - cur], s);
+    st = forward(nn, X, c->p.nz, c->p.nx, c->p.ny, false, nn->d_norm + 24, nn->d_norm + 16, dq[1 - cur], s);
     if (st != VLBM_OK) {
       cleanup();
       return st;
     }
-    hipLaunchKernelGGL(k_gate_partials, dim3(gblk), dim3(kGateThreads), 0, s, X, dq[1 - cur], c->p.nx, c->p.ny, gpart);
+    hipLaunchKernelGGL(k_gate_partials, dim3(gblk), dim3(kGateThreads), 0, s, X, dq[1 - cur], c->p.nx, c->p.ny,
+                       c->p.nz, gpart);
     hipLaunchKernelGGL(k_gate_final, dim3(1), dim3(1), 0, s, gpart, gblk, gb, flag + (1 - cur), fb);
     e = hipGetLastError();
     if (e != hipSuccess) break;

@@ -1,0 +1,201 @@
+"""Learned coarse-grid correction for 2D ideal MHD: pair generation, training and the
+gain evaluation, driven through the C ABI (include/vlbm.h, include/vlbm_nn.h).
+
+Every arithmetic step runs in the HIP library: fine and coarse sweeps, moments,
+restriction (block mean) and pair targets, network forward/backward/Adam, the gate
+and the corrected coarse step.  Python only allocates device buffers (torch),
+chooses indices and measures time.  The per-channel normalisation statistics are
+computed once on the host from a sample of the training pairs.
+
+Pairs (one coarse step = r fine steps, same flux scale and relaxation time):
+  X_n = R(Q_fine(t_n)),  Y_n = R(Q_fine(t_{n+1})) - C(X_n),
+where R is the r x r block mean and C one plain coarse step started from f^eq(X_n).
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import nn as N
+from . import vlbm as V
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def make_context(shape, batch, storage, workload, stream):
+    nx, ny = shape
+    return V.Vlbm(V.make_params(lattice="D2Q5", shape=(nx, ny, batch), model="ideal", storage=storage,
+                                gamma=workload["gamma"], flux_scale=workload["s"], tau=workload["tau"],
+                                powell=workload["powell"], stream=stream))
+
+
+def initial_batch(seeds, n, kmax, make_state):
+    """Stack the seeded initial states [8, 1, n, n] of each seed along z."""
+    Q = np.concatenate([make_state(n, seed=s, kmax=kmax) for s in seeds], axis=1)
+    return np.ascontiguousarray(Q, dtype=np.float32)
+
+
+def generate_pairs(seeds, n_fine, r, pairs_per_seed, workload, make_state, kmax=16, storage="f32", log=None):
+    """Returns (X, Y) device tensors [P, 8, B, nc, nc] (channel-major per pair)."""
+    torch = _torch()
+    s = torch.cuda.current_stream().cuda_stream
+    B, nc = len(seeds), n_fine // r
+    fine = make_context((n_fine, n_fine), B, storage, workload, s)
+    coarse = make_context((nc, nc), B, storage, workload, s)
+    fine.vlbm_init_fields(torch.from_numpy(initial_batch(seeds, n_fine, kmax, make_state)).cuda())
+    M = torch.empty((8, B, n_fine, n_fine), dtype=torch.float32, device="cuda")
+    Cst = torch.empty((8, B, nc, nc), dtype=torch.float32, device="cuda")
+    X = torch.empty((pairs_per_seed, 8, B, nc, nc), dtype=torch.float32, device="cuda")
+    Y = torch.empty_like(X)
+    nxt = torch.empty((8, B, nc, nc), dtype=torch.float32, device="cuda")
+    fine.vlbm_moments(out=M)
+    N.vlbm_restrict(M, r, X[0], rz=1, stream=s)
+    t0 = time.perf_counter()
+    for n in range(pairs_per_seed):
+        coarse.vlbm_init_fields(X[n])
+        coarse.vlbm_step(1)
+        coarse.vlbm_moments(out=Cst)
+        fine.vlbm_step(r)
+        fine.vlbm_moments(out=M)
+        N.vlbm_restrict(M, r, X[n + 1] if n + 1 < pairs_per_seed else nxt, rz=1, stream=s)
+        N.vlbm_restrict(M, r, Y[n], rz=1, minus=Cst, stream=s)
+        if log and (n + 1) % 100 == 0:
+            log(f"pairs: {n + 1}/{pairs_per_seed} steps x {B} seeds, {time.perf_counter() - t0:.1f} s")
+    torch.cuda.synchronize()
+    fine.vlbm_destroy()
+    coarse.vlbm_destroy()
+    return X, Y
+
+
+def normalisation(X, Y, sample=64, seed=0):
+    """Per-channel mean and standard deviation of inputs and targets (host, from up
+    to `sample` pairs), and the per-lattice RMS L2 norm of each target channel."""
+    rng = np.random.default_rng(seed)
+    P = X.shape[0]
+    idx = np.sort(rng.choice(P, size=min(sample, P), replace=False))
+    xs = X[idx].cpu().numpy().astype(np.float64)  # [S, 8, B, n, n]
+    ys = Y[idx].cpu().numpy().astype(np.float64)
+    in_mean = xs.mean(axis=(0, 2, 3, 4))
+    in_std = xs.std(axis=(0, 2, 3, 4))
+    out_mean = np.zeros(8)
+    out_std = ys.std(axis=(0, 2, 3, 4))
+    in_std = np.where(in_std > 1e-12, in_std, 1.0)
+    out_std = np.where(out_std > 1e-20, out_std, 1.0)
+    y_l2 = np.sqrt((ys ** 2).sum(axis=(3, 4)).mean(axis=(0, 2)))  # per channel, one lattice
+    return in_mean, in_std, out_mean, out_std, y_l2
+
+
+def init_weights(layers=4, cin=8, width=32, seed=0, last_scale=0.1):
+    """He-normal weights, zero biases; the last layer scaled down so training starts
+    near the plain coarse VLBM."""
+    rng = np.random.default_rng(seed)
+    dims = [cin] + [width] * (layers - 1) + [cin]
+    w = []
+    for l in range(layers):
+        W = rng.normal(0.0, np.sqrt(2.0 / (9 * dims[l])), (dims[l + 1], dims[l], 3, 3))
+        if l == layers - 1:
+            W *= last_scale
+        w += [W.ravel(), np.zeros(dims[l + 1])]
+    return np.concatenate(w).astype(np.float32)
+
+
+def train(net, X, Y, iters, lr, seed=0, log=None, log_every=200):
+    """Adam on randomly drawn pairs (each pair is a batch of all its seeds)."""
+    rng = np.random.default_rng(seed)
+    P = X.shape[0]
+    losses = []
+    t0 = time.perf_counter()
+    for it in range(iters):
+        n = int(rng.integers(P))
+        want = (it + 1) % log_every == 0 or it == 0
+        loss = net.vlbm_nn_train_step(X[n], Y[n], lr, want_loss=want)
+        if want:
+            losses.append((it + 1, loss))
+            if log:
+                log(f"train {it + 1}/{iters}: loss {loss:.4e} ({time.perf_counter() - t0:.1f} s)")
+    _torch().cuda.synchronize()
+    return losses, time.perf_counter() - t0
+
+
+def field_errors(Q, R):
+    """Per-field relative L2 (rho u and B as vectors), Q, R numpy [8, ...]."""
+    fam = {"rho": [0], "m": [1, 2, 3], "E": [4], "B": [5, 6, 7]}
+    out = {}
+    for name, ks in fam.items():
+        num = np.sqrt(sum(((Q[k] - R[k]) ** 2).sum() for k in ks))
+        den = np.sqrt(sum((R[k] ** 2).sum() for k in ks))
+        out[name] = float(num / den)
+    return out
+
+
+def evaluate(net, seeds, n_fine, r, coarse_steps, workload, make_state, bound_corr, bound_divb, kmax=16,
+             checkpoints=5, storage="f32", log=None):
+    """Coarse plain vs coarse learned, both scored against the restricted fine run."""
+    torch = _torch()
+    s = torch.cuda.current_stream().cuda_stream
+    B, nc = len(seeds), n_fine // r
+    fine = make_context((n_fine, n_fine), B, storage, workload, s)
+    plain = make_context((nc, nc), B, storage, workload, s)
+    learned = make_context((nc, nc), B, storage, workload, s)
+    fine.vlbm_init_fields(torch.from_numpy(initial_batch(seeds, n_fine, kmax, make_state)).cuda())
+    M = torch.empty((8, B, n_fine, n_fine), dtype=torch.float32, device="cuda")
+    Rf = torch.empty((8, B, nc, nc), dtype=torch.float32, device="cuda")
+    fine.vlbm_moments(out=M)
+    N.vlbm_restrict(M, r, Rf, rz=1, stream=s)
+    plain.vlbm_init_fields(Rf)
+    learned.vlbm_init_fields(Rf)
+    chunk = coarse_steps // checkpoints
+    hist, fallbacks = [], 0
+    for c in range(checkpoints):
+        fine.vlbm_step(r * chunk)
+        plain.vlbm_step(chunk)
+        fallbacks += N.vlbm_step_corrected(learned, net, chunk, bound_corr, bound_divb)
+        fine.vlbm_moments(out=M)
+        N.vlbm_restrict(M, r, Rf, rz=1, stream=s)
+        ref = Rf.cpu().numpy().astype(np.float64)
+        qp, _ = plain.vlbm_moments(raise_nonfinite=False)
+        ql, _ = learned.vlbm_moments(raise_nonfinite=False)
+        ep = field_errors(qp.reshape(ref.shape), ref)
+        el = field_errors(ql.reshape(ref.shape), ref)
+        hist.append(dict(coarse_step=(c + 1) * chunk, plain=ep, learned=el))
+        if log:
+            log(f"eval step {(c + 1) * chunk}: plain {ep} learned {el} fallbacks {fallbacks}")
+    for ctx in (fine, plain, learned):
+        ctx.vlbm_destroy()
+    return hist, fallbacks
+
+
+def time_runs(net, n_fine, r, coarse_steps, workload, make_state, bound_corr, bound_divb, kmax=16, seed=900,
+              storage="f32"):
+    """Wall time of the plain FP32 fine run (r * coarse_steps steps) and of the
+    corrected coarse run (coarse_steps steps), one lattice each, inputs resident."""
+    torch = _torch()
+    s = torch.cuda.current_stream().cuda_stream
+    nc = n_fine // r
+    fine = make_context((n_fine, n_fine), 1, storage, workload, s)
+    learned = make_context((nc, nc), 1, storage, workload, s)
+    Q0 = torch.from_numpy(initial_batch([seed], n_fine, kmax, make_state)).cuda()
+    fine.vlbm_init_fields(Q0)
+    M = torch.empty((8, 1, n_fine, n_fine), dtype=torch.float32, device="cuda")
+    Rf = torch.empty((8, 1, nc, nc), dtype=torch.float32, device="cuda")
+    fine.vlbm_moments(out=M)
+    N.vlbm_restrict(M, r, Rf, rz=1, stream=s)
+    learned.vlbm_init_fields(Rf)
+    fine.vlbm_step(r * 10)
+    N.vlbm_step_corrected(learned, net, 10, bound_corr, bound_divb)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fine.vlbm_step(r * coarse_steps)
+    torch.cuda.synchronize()
+    t_fine = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    nfb = N.vlbm_step_corrected(learned, net, coarse_steps, bound_corr, bound_divb)
+    torch.cuda.synchronize()
+    t_learned = time.perf_counter() - t0
+    fine.vlbm_destroy()
+    learned.vlbm_destroy()
+    return t_fine, t_learned, nfb

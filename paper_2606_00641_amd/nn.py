@@ -24,7 +24,8 @@ _sigs = {
     "vlbm_nn_adam_step": [_vp, ctypes.c_float],
     "vlbm_nn_adam_config": [_vp, ctypes.c_float, ctypes.c_float, ctypes.c_float],
     "vlbm_nn_train_step": [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, _dp],
-    "vlbm_restrict": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp],
+    "vlbm_restrict": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                      ctypes.c_int32, _vp, _vp, _vp],
     "vlbm_step_corrected": [_vp, _vp, ctypes.c_int32, _dp, ctypes.c_double, ctypes.POINTER(ctypes.c_int64)],
 }
 for _name, _args in _sigs.items():
@@ -80,13 +81,13 @@ class Net:
         _check(_lib.vlbm_nn_set_norm(self.h, *[p for _, p in arrs]), self.h)
 
     def vlbm_nn_forward(self, X, out):
-        """X, out: torch FP32 device tensors [batch, 8, ny, nx]."""
-        B, C, ny, nx = X.shape
+        """X, out: torch FP32 device tensors [8, batch, ny, nx] (channel-major)."""
+        C, B, ny, nx = X.shape
         _check(_lib.vlbm_nn_forward(self.h, _dev(X), _dev(out), B, nx, ny), self.h)
         return out
 
     def vlbm_nn_loss_grad(self, X, T, want_grad=True):
-        B, C, ny, nx = X.shape
+        C, B, ny, nx = X.shape
         loss = ctypes.c_double()
         g = np.empty(self.vlbm_nn_num_params(), np.float32) if want_grad else None
         _check(_lib.vlbm_nn_loss_grad(self.h, _dev(X), _dev(T), B, nx, ny, ctypes.byref(loss),
@@ -100,7 +101,7 @@ class Net:
         _check(_lib.vlbm_nn_adam_config(self.h, b1, b2, eps), self.h)
 
     def vlbm_nn_train_step(self, X, T, lr, want_loss=False):
-        B, C, ny, nx = X.shape
+        C, B, ny, nx = X.shape
         loss = ctypes.c_double()
         _check(_lib.vlbm_nn_train_step(self.h, _dev(X), _dev(T), B, nx, ny, lr,
                                        ctypes.byref(loss) if want_loss else None), self.h)
@@ -120,10 +121,14 @@ class Net:
             pass
 
 
-def vlbm_restrict(Qf, r, out, stream=None):
-    """Qf: torch FP32 device [K, nz, ny, nx]; out: [K, nz/rz, ny/r, nx/r]."""
+def vlbm_restrict(Qf, r, out, rz=None, minus=None, stream=None):
+    """Qf: torch FP32 device [K, nz, ny, nx]; out: [K, nz/rz, ny/r, nx/r].  rz defaults
+    to r for a 3D field (nz > 1 means 3D unless rz=1 is given for a 2D batch)."""
     K, nz, ny, nx = Qf.shape
-    st = _lib.vlbm_restrict(_dev(Qf), K, nx, ny, nz, r, _dev(out), stream)
+    if rz is None:
+        rz = r if nz > 1 else 1
+    st = _lib.vlbm_restrict(_dev(Qf), K, nx, ny, nz, r, rz, _dev(minus) if minus is not None else None,
+                            _dev(out), stream)
     if st != _v.VLBM_OK:
         raise _v.VlbmError(st, "vlbm_restrict: bad shapes")
     return out

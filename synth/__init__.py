@@ -45,9 +45,10 @@ def conserved_from_primitive(rho, u, p, B, gamma):
 
 
 def _random_mode_field(rng, shape2d, kmax, ncomp):
-    """Sum of unit-amplitude Fourier modes 1 <= |k| <= kmax (half plane), random phases."""
+    """Sum of unit-amplitude Fourier modes cos(2 pi (kx x/nx + ky y/ny) + phase) over
+    integer 1 <= |k| <= kmax in the half plane, seeded phases; synthesised with an
+    inverse FFT (the same sum, evaluated in O(n^2 log n))."""
     ny, nx = shape2d
-    y, x = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
     modes = []
     for ky in range(0, kmax + 1):
         for kx in range(-kmax, kmax + 1):
@@ -58,8 +59,10 @@ def _random_mode_field(rng, shape2d, kmax, ncomp):
     out = np.zeros((ncomp, ny, nx))
     for c in range(ncomp):
         phases = rng.uniform(0.0, 2.0 * np.pi, size=len(modes))
+        F = np.zeros((ny, nx), np.complex128)
         for (kx, ky), ph in zip(modes, phases):
-            out[c] += np.cos(2.0 * np.pi * (kx * x / nx + ky * y / ny) + ph)
+            F[ky % ny, kx % nx] += np.exp(1j * ph)
+        out[c] = np.real(np.fft.ifft2(F)) * (nx * ny)
     return out
 
 

@@ -1,0 +1,35 @@
+"""The learned coarse correction, end to end at a reduced size: pairs from batched
+fine runs (128^2 -> 32^2, r = 4), training on the GPU, and a held-out comparison
+against the restricted fine run, where the corrected coarse run must beat the plain
+coarse VLBM."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def test_learned_correction_beats_plain_coarse():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    from paper_2606_00641_amd import learned as Lr
+    from paper_2606_00641_amd import nn as N
+
+    w = synth.workload_fourier_2d()
+    print("case learned pipeline 128^2 -> 32^2", flush=True)
+    X, Y = Lr.generate_pairs(list(range(100, 108)), 128, 4, 80, w, synth.fourier_2d, kmax=8)
+    in_mean, in_std, out_mean, out_std, y_l2 = Lr.normalisation(X, Y)
+    net = N.Net(8, 32, 4, stream=torch.cuda.current_stream().cuda_stream)
+    net.vlbm_nn_set_weights(Lr.init_weights(seed=0))
+    net.vlbm_nn_set_norm(in_mean, in_std, out_mean, out_std)
+    losses, _ = Lr.train(net, X, Y, 600, 1e-3, seed=0)
+    assert losses[-1][1] < losses[0][1]
+    eval_seeds = [900, 901, 902, 903]
+    bound = 5.0 * y_l2 * np.sqrt(len(eval_seeds))
+    hist, nfb = Lr.evaluate(net, eval_seeds, 128, 4, 200, w, synth.fourier_2d, bound, 0.1, kmax=8, checkpoints=2)
+    plain = sum(hist[-1]["plain"].values())
+    learned = sum(hist[-1]["learned"].values())
+    print("plain", hist[-1]["plain"], "learned", hist[-1]["learned"], "fallbacks", nfb, flush=True)
+    assert learned < plain

@@ -49,6 +49,16 @@ def rand_params(rng, layers, bf16=True):
     return ps
 
 
+def cm(torch, a):
+    """Batch-major [B, C, H, W] numpy -> channel-major [C, B, H, W] FP32 device tensor."""
+    return torch.tensor(np.ascontiguousarray(np.swapaxes(a, 0, 1)), dtype=torch.float32, device="cuda")
+
+
+def bm(t):
+    """Channel-major device tensor -> batch-major numpy."""
+    return np.swapaxes(t.cpu().numpy(), 0, 1)
+
+
 def rel_l2(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
 
@@ -66,10 +76,10 @@ def test_single_conv_forward_exact(env):
     params = rand_params(rng, 1)
     X = C.bf16_round(rng.normal(size=(2, 8, 32, 48)))
     net = make_net(env, 1, params)
-    Y = torch.empty((2, 8, 32, 48), dtype=torch.float32, device="cuda")
-    net.vlbm_nn_forward(torch.tensor(X, dtype=torch.float32, device="cuda"), Y)
+    Y = torch.empty((8, 2, 32, 48), dtype=torch.float32, device="cuda")
+    net.vlbm_nn_forward(cm(torch, X), Y)
     want = C.Net(params, layers=1).forward(X)
-    assert rel_l2(Y.cpu().numpy(), want) < 1e-5
+    assert rel_l2(bm(Y), want) < 1e-5
 
 
 def test_full_forward_matches_quantised_oracle(env):
@@ -78,10 +88,10 @@ def test_full_forward_matches_quantised_oracle(env):
     params = rand_params(rng, 4)
     X = rng.normal(size=(2, 8, 32, 32))
     net = make_net(env, 4, params)
-    Y = torch.empty((2, 8, 32, 32), dtype=torch.float32, device="cuda")
-    net.vlbm_nn_forward(torch.tensor(X, dtype=torch.float32, device="cuda"), Y)
+    Y = torch.empty((8, 2, 32, 32), dtype=torch.float32, device="cuda")
+    net.vlbm_nn_forward(cm(torch, X), Y)
     want = C.Net(params, layers=4, quantize=True).forward(X)
-    assert rel_l2(Y.cpu().numpy(), want) < 1e-2
+    assert rel_l2(bm(Y), want) < 1e-2
 
 
 def test_normalisation(env):
@@ -95,11 +105,11 @@ def test_normalisation(env):
     X = Xs * sd_in[None, :, None, None] + mu_in[None, :, None, None]
     net = make_net(env, 1, params)
     net.vlbm_nn_set_norm(mu_in, sd_in, mu_out, sd_out)
-    Y = torch.empty((1, 8, 16, 16), dtype=torch.float32, device="cuda")
-    net.vlbm_nn_forward(torch.tensor(X, dtype=torch.float32, device="cuda"), Y)
+    Y = torch.empty((8, 1, 16, 16), dtype=torch.float32, device="cuda")
+    net.vlbm_nn_forward(cm(torch, X), Y)
     want = C.Net(params, layers=1, quantize=True).forward((X - mu_in[None, :, None, None]) / sd_in[None, :, None, None])
     want = want * sd_out[None, :, None, None] + mu_out[None, :, None, None]
-    assert rel_l2(Y.cpu().numpy(), want) < 1e-2
+    assert rel_l2(bm(Y), want) < 1e-2
 
 
 @pytest.mark.parametrize("layers", [1, 2, 4])
@@ -110,8 +120,7 @@ def test_gradients_match_oracle(env, layers):
     X = rng.normal(size=(2, 8, 32, 32))
     T = rng.normal(size=(2, 8, 32, 32))
     net = make_net(env, layers, params)
-    loss, g = net.vlbm_nn_loss_grad(torch.tensor(X, dtype=torch.float32, device="cuda"),
-                                    torch.tensor(T, dtype=torch.float32, device="cuda"))
+    loss, g = net.vlbm_nn_loss_grad(cm(torch, X), cm(torch, T))
     oloss, ograds = C.Net(params, layers=layers, quantize=True).loss_and_grads(X, T)
     assert abs(loss - oloss) <= 1e-2 * oloss
     gp = unflat(g, layers)
@@ -124,8 +133,8 @@ def test_adam_step_matches_oracle(env):
     torch = env[0]
     rng = np.random.default_rng(9)
     params = rand_params(rng, 2, bf16=False)
-    X = torch.tensor(rng.normal(size=(1, 8, 16, 16)), dtype=torch.float32, device="cuda")
-    T = torch.tensor(rng.normal(size=(1, 8, 16, 16)), dtype=torch.float32, device="cuda")
+    X = cm(torch, rng.normal(size=(1, 8, 16, 16)))
+    T = cm(torch, rng.normal(size=(1, 8, 16, 16)))
     net = make_net(env, 2, params)
     w0 = net.vlbm_nn_get_weights()
     ad = C.Adam(unflat(w0, 2), lr=1e-3)
@@ -147,8 +156,8 @@ def test_training_reduces_loss(env):
     X = rng.normal(size=(4, 8, 32, 32))
     T = 0.5 * np.roll(X, 1, axis=3) - 0.3 * X  # a learnable local linear map
     net = make_net(env, 4, params)
-    Xt = torch.tensor(X, dtype=torch.float32, device="cuda")
-    Tt = torch.tensor(T, dtype=torch.float32, device="cuda")
+    Xt = cm(torch, X)
+    Tt = cm(torch, T)
     l0, _ = net.vlbm_nn_loss_grad(Xt, Tt, want_grad=False)
     for _ in range(150):
         net.vlbm_nn_train_step(Xt, Tt, 3e-3)
@@ -168,6 +177,13 @@ def test_restriction_matches_oracle(env):
     out3 = torch.empty((8, 4, 4, 8), dtype=torch.float32, device="cuda")
     nn.vlbm_restrict(torch.tensor(Q3, device="cuda"), 2, out3)
     assert np.allclose(out3.cpu().numpy(), C.restrict(Q3.astype(np.float64), 2), rtol=1e-6, atol=1e-7)
+    # a batch of 2D fields (rz = 1) minus a field
+    Qb = rng.normal(size=(8, 3, 32, 16)).astype(np.float32)
+    mn = rng.normal(size=(8, 3, 8, 4)).astype(np.float32)
+    outb = torch.empty((8, 3, 8, 4), dtype=torch.float32, device="cuda")
+    nn.vlbm_restrict(torch.tensor(Qb, device="cuda"), 4, outb, rz=1, minus=torch.tensor(mn, device="cuda"))
+    want = np.stack([C.restrict(Qb[:, j:j + 1].astype(np.float64), 4)[:, 0] for j in range(3)], axis=1) - mn
+    assert np.allclose(outb.cpu().numpy(), want, rtol=1e-6, atol=1e-6)
 
 
 # --- corrected coarse stepping ----------------------------------------------------
