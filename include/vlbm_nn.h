@@ -90,9 +90,10 @@ vlbm_status vlbm_restrict(const float* Qf, int32_t K, int32_t nx, int32_t ny, in
 
 /* n coarse steps with the learned correction.  Per step: the moments X of the
  * current populations (including the pending correction), dQ = network(X), the gate
- * (FP64: every ||dQ_k||_2 <= bound_corr[k], the central-difference div B L2 norm of
- * X + dQ at most (1 + bound_divb) times that of X, all finite; otherwise dQ := 0 and
- * the fallback counter is incremented), then the sweep, with the previous step's
+ * (FP64 over the whole lattice or batch: every ||dQ_k||_2 <= bound_corr[k]; the
+ * central-difference div B drift ||div(B + dB)||_2 <= (1 + bound_divb_rel) ||div B||_2
+ * + bound_divb_abs ||B||_2 with B the in-plane field of X; all finite -- otherwise
+ * dQ := 0 and the fallback counter is incremented), then the sweep, with the previous step's
  * accepted dQ added as w_i dQ_k to the populations before the collision.  After the
  * last step the pending dQ is added to the populations, so vlbm_moments sees the
  * corrected state.  The context must be a 2D ideal-MHD context (K = cin = 8, FP32 or
@@ -100,7 +101,7 @@ vlbm_status vlbm_restrict(const float* Qf, int32_t K, int32_t nx, int32_t ny, in
  * network supports.  bound_corr: host, K doubles.  *n_fallback (host, may
  * be NULL) receives the number of fallbacks in this call.  Synchronises. */
 vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const double* bound_corr,
-                                double bound_divb, int64_t* n_fallback);
+                                double bound_divb_rel, double bound_divb_abs, int64_t* n_fallback);
 
 #ifdef __cplusplus
 }

@@ -24,14 +24,28 @@ _SO = os.path.join(_HERE, "libvlbm_ref.so")
 KMAX = 26
 
 
+_SO32 = os.path.join(_HERE, "libvlbm_ref_f32.so")
+
+
 def build(force: bool = True) -> str:
-    """Compile the C oracle with gcc (-O2, IEEE semantics, OpenMP)."""
-    if force or not os.path.exists(_SO):
-        tmp = _SO + ".tmp"
-        subprocess.check_call(
-            ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
-             "-o", tmp, os.path.join(_HERE, "vlbm_ref.c"), "-lm"])
-        os.replace(tmp, _SO)
+    """Compile the C oracle with gcc (-O2, IEEE semantics, OpenMP), and the same
+    source with every double replaced by float: the oracle's formulas evaluated in
+    FP32 arithmetic, the yardstick of what FP32 evaluation of the method can reach
+    (used only to derive FP32 tolerances)."""
+    gen = os.path.join(_HERE, "_build")
+    os.makedirs(gen, exist_ok=True)
+    for name in ("vlbm_ref.c", "vlbm_ref.h"):
+        with open(os.path.join(_HERE, name)) as fh:
+            text = fh.read().replace("double", "float").replace("fabs(", "fabsf(")
+        with open(os.path.join(gen, name), "w") as fh:
+            fh.write(text)
+    for out, src in ((_SO, _HERE), (_SO32, gen)):
+        if force or not os.path.exists(out):
+            tmp = out + ".tmp"
+            subprocess.check_call(
+                ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-I", src,
+                 "-o", tmp, os.path.join(src, "vlbm_ref.c"), "-lm"])
+            os.replace(tmp, out)
     return _SO
 
 
@@ -227,3 +241,34 @@ def flux_source(p, Qcell, J=None):
 
 def num_threads():
     return lib().vref_num_threads()
+
+
+class Params32(ctypes.Structure):
+    """``vref_params`` of the FP32-arithmetic build (every double is a float)."""
+
+    _fields_ = [(n, (ctypes.c_float * KMAX) if n == "tau" else (ctypes.c_float if t is ctypes.c_double else t))
+                for n, t in Params._fields_]
+
+
+def run_fp32(p, Q, nsteps):
+    """The oracle's update evaluated entirely in FP32 (init, nsteps steps); returns
+    the moments [K, N] as float64.  A precision yardstick, not a reference."""
+    if not os.path.exists(_SO32):
+        build(force=True)
+    L = ctypes.CDLL(_SO32)
+    fp = ctypes.POINTER(ctypes.c_float)
+    q = Params32()
+    for n, _ in Params._fields_:
+        v = getattr(p, n)
+        if n == "tau":
+            for k in range(KMAX):
+                q.tau[k] = v[k]
+        else:
+            setattr(q, n, v)
+    K, NQ, N = nvars(p), ndirs(p), ncells(p)
+    Q32 = np.ascontiguousarray(np.asarray(Q, np.float64).reshape(K, N), np.float32)
+    f = np.empty((K, NQ, N), np.float32)
+    work = np.empty_like(f)
+    L.vref_init(ctypes.byref(q), Q32.ctypes.data_as(fp), f.ctypes.data_as(fp))
+    L.vref_run(ctypes.byref(q), f.ctypes.data_as(fp), work.ctypes.data_as(fp), int(nsteps))
+    return f.astype(np.float64).sum(axis=1)

@@ -14,8 +14,9 @@ be checked by eye:
           p -= lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps)
 * restriction R: r x r block mean of a moment field (conserves totals)
 * gate: the correction is dropped when a per-variable L2 norm exceeds its bound, when
-  it raises the central-difference div B norm of the state by more than a factor,
-  or when it is not finite.
+  it raises the central-difference div B norm of the state by more than a relative
+  amount plus an absolute amount (a fraction of the field's own L2 norm), or when it
+  is not finite.
 """
 from __future__ import annotations
 
@@ -154,6 +155,11 @@ def restrict(Q, r):
     return Q.reshape(K, nz // rz, rz, ny // r, r, nx // r, r).mean(axis=(2, 4, 6))
 
 
+def b_l2(Q, dim=2):
+    """sqrt(sum_x |B_inplane|^2) of a moment field [K, nz, ny, nx]."""
+    return float(np.sqrt(sum((Q[5 + a] ** 2).sum() for a in range(dim))))
+
+
 def central_divb_l2(Q, dim=2):
     """sqrt(sum_x (central div B)^2) of a moment field [K, nz, ny, nx], periodic."""
     div = np.zeros(Q.shape[1:])
@@ -163,8 +169,10 @@ def central_divb_l2(Q, dim=2):
     return float(np.sqrt((div * div).sum()))
 
 
-def gate(Q, dQ, bound_corr, bound_divb, dim=2):
-    """True if the correction dQ may be applied to state Q."""
+def gate(Q, dQ, bound_corr, bound_divb_rel, bound_divb_abs=0.0, dim=2):
+    """True if the correction dQ may be applied to state Q: finite, every
+    ||dQ_k||_2 <= bound_corr[k], and the central div B norm after the correction at
+    most (1 + rel) times the one before plus abs times ||B||_2."""
     if not np.all(np.isfinite(dQ)):
         return False
     K = dQ.shape[0]
@@ -173,4 +181,4 @@ def gate(Q, dQ, bound_corr, bound_divb, dim=2):
         return False
     before = central_divb_l2(Q, dim)
     after = central_divb_l2(Q + dQ, dim)
-    return after <= (1.0 + bound_divb) * before + 1e-300
+    return after <= (1.0 + bound_divb_rel) * before + bound_divb_abs * b_l2(Q, dim)

@@ -238,6 +238,13 @@ vlbm_status vlbm_create(const vlbm_params* p, vlbm_ctx** out) {
     }
     c->owned = true;
   }
+  // defined contents everywhere, including the plane padding (bitwise checkpoints
+  // and buffer comparisons between contexts)
+  if (hipMemsetAsync(c->f, 0, c->pop_bytes, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    vlbm_destroy(c);
+    return fail(nullptr, VLBM_ERR_HIP, "clearing the population buffer failed");
+  }
   c->nblk = (int)std::min<long long>(1024, (c->N + 255) / 256);
   const int NT = c->K + 5;
   hipError_t e = hipMalloc(&c->d_partial, sizeof(double) * (size_t)c->nblk * NT);

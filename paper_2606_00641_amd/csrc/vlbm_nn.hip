@@ -460,14 +460,14 @@ __global__ void k_inject(const vlbm::Grid g, int parity, const float* __restrict
 
 struct GateBounds {
   double corr[8];
-  double divb;
+  double divb_rel, divb_abs;
 };
 
 // per-block FP64 partials: [0..7] sum dQ_k^2, [8] sum divc(X)^2, [9] sum divc(X + dQ)^2,
-// [10] non-finite count
+// [10] non-finite count, [11] sum |B(X)|^2 (in-plane components)
 __global__ __launch_bounds__(kGateThreads) void k_gate_partials(const float* __restrict__ X, const float* __restrict__ dq,
                                                                 int nx, int ny, int nb, double* __restrict__ partial) {
-  constexpr int NP = 11;
+  constexpr int NP = 12;
   __shared__ double sh[kGateThreads / 64][NP];
   const size_t N = (size_t)nx * ny * nb;
   double acc[NP];
@@ -490,6 +490,7 @@ __global__ __launch_bounds__(kGateThreads) void k_gate_partials(const float* __r
     const double dv2 = dv + 0.5 * ((double)dBx[xp] - dBx[xm]) + 0.5 * ((double)dBy[yp] - dBy[ym]);
     acc[8] += dv * dv;
     acc[9] += dv2 * dv2;
+    acc[11] += (double)Bx[c] * Bx[c] + (double)By[c] * By[c];
   }
   for (int j = 0; j < NP; ++j) {
     for (int off = 32; off > 0; off >>= 1) acc[j] += __shfl_xor(acc[j], off);
@@ -506,14 +507,14 @@ __global__ __launch_bounds__(kGateThreads) void k_gate_partials(const float* __r
 __global__ void k_gate_final(const double* __restrict__ partial, int nblk, GateBounds gb, int* __restrict__ flag,
                              long long* __restrict__ fallbacks) {
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  constexpr int NP = 11;
+  constexpr int NP = 12;
   double t[NP];
   for (int j = 0; j < NP; ++j) t[j] = 0.0;
   for (int b = 0; b < nblk; ++b)
     for (int j = 0; j < NP; ++j) t[j] += partial[(size_t)b * NP + j];
   bool ok = t[10] == 0.0;
   for (int k = 0; k < 8; ++k) ok = ok && sqrt(t[k]) <= gb.corr[k];
-  ok = ok && sqrt(t[9]) <= (1.0 + gb.divb) * sqrt(t[8]);
+  ok = ok && sqrt(t[9]) <= (1.0 + gb.divb_rel) * sqrt(t[8]) + gb.divb_abs * sqrt(t[11]);
   *flag = ok ? 1 : 0;
   if (!ok) *fallbacks += 1;
 }
@@ -910,8 +911,8 @@ vlbm_status vlbm_restrict(const float* Qf, int32_t K, int32_t nx, int32_t ny, in
   return hipGetLastError() == hipSuccess ? VLBM_OK : VLBM_ERR_HIP;
 }
 
-vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const double* bound_corr, double bound_divb,
-                                int64_t* n_fallback) {
+vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const double* bound_corr,
+                                double bound_divb_rel, double bound_divb_abs, int64_t* n_fallback) {
   if (!c || !nn) return VLBM_ERR_ARG;
   if (!c->initialized) return VLBM_ERR_STATE;
   if (n < 0 || !bound_corr) return nfail(nn, VLBM_ERR_ARG, "n >= 0 and bound_corr required");
@@ -925,8 +926,10 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
     if (!(bound_corr[k] >= 0.0)) return nfail(nn, VLBM_ERR_ARG, "bound_corr[%d] must be >= 0", k);
     gb.corr[k] = bound_corr[k];
   }
-  if (!(bound_divb >= 0.0)) return nfail(nn, VLBM_ERR_ARG, "bound_divb must be >= 0");
-  gb.divb = bound_divb;
+  if (!(bound_divb_rel >= 0.0) || !(bound_divb_abs >= 0.0))
+    return nfail(nn, VLBM_ERR_ARG, "div B bounds must be >= 0");
+  gb.divb_rel = bound_divb_rel;
+  gb.divb_abs = bound_divb_abs;
   const size_t N = (size_t)c->N;
   hipStream_t s = c->stream;
   float *X = nullptr, *dq[2] = {nullptr, nullptr};
@@ -947,7 +950,7 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
   if (e == hipSuccess) e = hipMalloc(&dq[1], 8 * N * sizeof(float));
   if (e == hipSuccess) e = hipMalloc(&flag, 2 * sizeof(int));
   if (e == hipSuccess) e = hipMalloc(&fb, sizeof(long long));
-  if (e == hipSuccess) e = hipMalloc(&gpart, (size_t)gblk * 11 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&gpart, (size_t)gblk * 12 * sizeof(double));
   if (e == hipSuccess) e = hipMemsetAsync(flag, 0, 2 * sizeof(int), s);
   if (e == hipSuccess) e = hipMemsetAsync(fb, 0, sizeof(long long), s);
   const dim3 cgrid((unsigned)((N + 255) / 256)), cblk(256);

@@ -71,9 +71,19 @@ def generate_pairs(seeds, n_fine, r, pairs_per_seed, workload, make_state, kmax=
     return X, Y
 
 
+def _divc_l2(F):
+    """L2 norm of the central-difference divergence of the in-plane B of a moment
+    batch F [8, B, n, n] (host statistics)."""
+    d = 0.5 * (np.roll(F[5], -1, axis=-1) - np.roll(F[5], 1, axis=-1)) \
+        + 0.5 * (np.roll(F[6], -1, axis=-2) - np.roll(F[6], 1, axis=-2))
+    return float(np.sqrt((d * d).sum()))
+
+
 def normalisation(X, Y, sample=64, seed=0):
     """Per-channel mean and standard deviation of inputs and targets (host, from up
-    to `sample` pairs), and the per-lattice RMS L2 norm of each target channel."""
+    to `sample` pairs), the per-lattice RMS L2 norm of each target channel, and the
+    RMS div B drift of the true corrections, ||div(B + dB)|| - ||div B||, relative to
+    ||B|| (the scale of the gate's absolute div B allowance)."""
     rng = np.random.default_rng(seed)
     P = X.shape[0]
     idx = np.sort(rng.choice(P, size=min(sample, P), replace=False))
@@ -86,7 +96,12 @@ def normalisation(X, Y, sample=64, seed=0):
     in_std = np.where(in_std > 1e-12, in_std, 1.0)
     out_std = np.where(out_std > 1e-20, out_std, 1.0)
     y_l2 = np.sqrt((ys ** 2).sum(axis=(3, 4)).mean(axis=(0, 2)))  # per channel, one lattice
-    return in_mean, in_std, out_mean, out_std, y_l2
+    drift = []
+    for j in range(xs.shape[0]):
+        bnorm = np.sqrt((xs[j, 5] ** 2 + xs[j, 6] ** 2).sum())
+        drift.append((_divc_l2(xs[j] + ys[j]) - _divc_l2(xs[j])) / max(bnorm, 1e-300))
+    drift_rms = float(np.sqrt(np.mean(np.square(drift))))
+    return in_mean, in_std, out_mean, out_std, y_l2, drift_rms
 
 
 def init_weights(layers=4, cin=8, width=32, seed=0, last_scale=0.1):
@@ -132,8 +147,8 @@ def field_errors(Q, R):
     return out
 
 
-def evaluate(net, seeds, n_fine, r, coarse_steps, workload, make_state, bound_corr, bound_divb, kmax=16,
-             checkpoints=5, storage="f32", log=None):
+def evaluate(net, seeds, n_fine, r, coarse_steps, workload, make_state, bound_corr, bound_divb_rel, bound_divb_abs,
+             kmax=16, checkpoints=5, storage="f32", log=None):
     """Coarse plain vs coarse learned, both scored against the restricted fine run."""
     torch = _torch()
     s = torch.cuda.current_stream().cuda_stream
@@ -153,7 +168,7 @@ def evaluate(net, seeds, n_fine, r, coarse_steps, workload, make_state, bound_co
     for c in range(checkpoints):
         fine.vlbm_step(r * chunk)
         plain.vlbm_step(chunk)
-        fallbacks += N.vlbm_step_corrected(learned, net, chunk, bound_corr, bound_divb)
+        fallbacks += N.vlbm_step_corrected(learned, net, chunk, bound_corr, bound_divb_rel, bound_divb_abs)
         fine.vlbm_moments(out=M)
         N.vlbm_restrict(M, r, Rf, rz=1, stream=s)
         ref = Rf.cpu().numpy().astype(np.float64)
@@ -169,8 +184,8 @@ def evaluate(net, seeds, n_fine, r, coarse_steps, workload, make_state, bound_co
     return hist, fallbacks
 
 
-def time_runs(net, n_fine, r, coarse_steps, workload, make_state, bound_corr, bound_divb, kmax=16, seed=900,
-              storage="f32"):
+def time_runs(net, n_fine, r, coarse_steps, workload, make_state, bound_corr, bound_divb_rel, bound_divb_abs,
+              kmax=16, seed=900, storage="f32"):
     """Wall time of the plain FP32 fine run (r * coarse_steps steps) and of the
     corrected coarse run (coarse_steps steps), one lattice each, inputs resident."""
     torch = _torch()
@@ -186,14 +201,14 @@ def time_runs(net, n_fine, r, coarse_steps, workload, make_state, bound_corr, bo
     N.vlbm_restrict(M, r, Rf, rz=1, stream=s)
     learned.vlbm_init_fields(Rf)
     fine.vlbm_step(r * 10)
-    N.vlbm_step_corrected(learned, net, 10, bound_corr, bound_divb)
+    N.vlbm_step_corrected(learned, net, 10, bound_corr, bound_divb_rel, bound_divb_abs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     fine.vlbm_step(r * coarse_steps)
     torch.cuda.synchronize()
     t_fine = time.perf_counter() - t0
     t0 = time.perf_counter()
-    nfb = N.vlbm_step_corrected(learned, net, coarse_steps, bound_corr, bound_divb)
+    nfb = N.vlbm_step_corrected(learned, net, coarse_steps, bound_corr, bound_divb_rel, bound_divb_abs)
     torch.cuda.synchronize()
     t_learned = time.perf_counter() - t0
     fine.vlbm_destroy()

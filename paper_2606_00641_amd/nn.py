@@ -26,7 +26,8 @@ _sigs = {
     "vlbm_nn_train_step": [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, _dp],
     "vlbm_restrict": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                       ctypes.c_int32, _vp, _vp, _vp],
-    "vlbm_step_corrected": [_vp, _vp, ctypes.c_int32, _dp, ctypes.c_double, ctypes.POINTER(ctypes.c_int64)],
+    "vlbm_step_corrected": [_vp, _vp, ctypes.c_int32, _dp, ctypes.c_double, ctypes.c_double,
+                            ctypes.POINTER(ctypes.c_int64)],
 }
 for _name, _args in _sigs.items():
     _fn = getattr(_lib, _name)
@@ -134,12 +135,13 @@ def vlbm_restrict(Qf, r, out, rz=None, minus=None, stream=None):
     return out
 
 
-def vlbm_step_corrected(sim, net, n, bound_corr, bound_divb):
+def vlbm_step_corrected(sim, net, n, bound_corr, bound_divb_rel, bound_divb_abs=0.0):
     """Advance the coarse context `sim` (a vlbm.Vlbm) n steps with the correction;
     returns the number of fallbacks."""
     b, bp = _d(bound_corr)
     nfb = ctypes.c_int64()
-    st = _lib.vlbm_step_corrected(sim.ctx, net.h, int(n), bp, float(bound_divb), ctypes.byref(nfb))
+    st = _lib.vlbm_step_corrected(sim.ctx, net.h, int(n), bp, float(bound_divb_rel), float(bound_divb_abs),
+                                  ctypes.byref(nfb))
     if st != _v.VLBM_OK:
         msg = _lib.vlbm_nn_last_error(net.h)
         raise _v.VlbmError(st, msg.decode() if msg else "")

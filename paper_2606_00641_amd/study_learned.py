@@ -47,7 +47,8 @@ def main():
     X, Y = Lr.generate_pairs(seeds, n_fine, r, pairs, w, synth.fourier_2d, kmax=kmax, log=log)
     t_pairs = time.perf_counter() - t0
     log(f"{pairs * len(seeds)} pairs in {t_pairs:.1f} s")
-    in_mean, in_std, out_mean, out_std, y_l2 = Lr.normalisation(X, Y)
+    in_mean, in_std, out_mean, out_std, y_l2, drift = Lr.normalisation(X, Y)
+    b_abs = 5.0 * drift
     net = N.Net(8, 32, 4, stream=torch.cuda.current_stream().cuda_stream)
     net.vlbm_nn_set_weights(Lr.init_weights(seed=0))
     net.vlbm_nn_set_norm(in_mean, in_std, out_mean, out_std)
@@ -55,9 +56,10 @@ def main():
     del X, Y
     torch.cuda.empty_cache()
     bound = 5.0 * y_l2 * np.sqrt(len(eval_seeds))
-    hist, nfb = Lr.evaluate(net, eval_seeds, n_fine, r, steps, w, synth.fourier_2d, bound, 0.1, kmax=kmax,
+    hist, nfb = Lr.evaluate(net, eval_seeds, n_fine, r, steps, w, synth.fourier_2d, bound, 0.1, b_abs, kmax=kmax,
                             checkpoints=10, log=log)
-    t_fine, t_learned, nfb_t = Lr.time_runs(net, n_fine, r, steps, w, synth.fourier_2d, y_l2 * 5.0, 0.1, kmax=kmax)
+    t_fine, t_learned, nfb_t = Lr.time_runs(net, n_fine, r, steps, w, synth.fourier_2d, y_l2 * 5.0, 0.1, b_abs,
+                                            kmax=kmax)
     res = dict(
         workload=f"2D ideal MHD D2Q5 x 8, fine {n_fine}^2 -> coarse {n_fine // r}^2 (r = {r}), Fourier modes k <= {kmax}, "
                  f"tau = {w['tau']}, s = {w['s']}, FP32 storage",
@@ -65,7 +67,7 @@ def main():
         network="4 x conv3x3, 8-32-32-32-8, GELU, BF16 MFMA / FP32 accumulate, Adam lr %g, %d iterations (batch %d lattices)"
                 % (args.lr, args.iters, len(seeds)),
         time_pairs_s=round(t_pairs, 2), time_train_s=round(t_train, 2), losses=losses,
-        bound_corr=list(map(float, bound)), bound_divb=0.1, history=hist, fallbacks=nfb,
+        bound_corr=list(map(float, bound)), bound_divb_rel=0.1, bound_divb_abs=b_abs, history=hist, fallbacks=nfb,
         wall_fine_s=round(t_fine, 4), wall_learned_coarse_s=round(t_learned, 4),
         speedup_vs_fine=round(t_fine / t_learned, 2), fallbacks_timed_run=nfb_t)
     log(json.dumps({k: res[k] for k in ("speedup_vs_fine", "fallbacks", "wall_fine_s", "wall_learned_coarse_s")}))

@@ -157,10 +157,13 @@ def test_gate_cases():
     bad = dQ.copy()
     bad[0, 0, 1, 1] = np.nan
     assert not C.gate(Q, bad, big, 0.1)
-    # a correction that only adds divergence is rejected
+    # a correction that only adds divergence is rejected, unless the absolute
+    # allowance (a fraction of ||B||) covers it
     div_only = np.zeros_like(Q)
     div_only[5] = 10.0 * np.sin(2 * np.pi * np.arange(8) / 8)[None, None, :]
     assert not C.gate(Q, div_only, big, 0.1)
+    assert C.gate(Q, div_only, big, 0.1, bound_divb_abs=100.0)
+    assert not C.gate(Q, div_only, big, 0.1, bound_divb_abs=0.01)
 
 
 MUTATIONS = {

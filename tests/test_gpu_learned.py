@@ -20,7 +20,7 @@ def test_learned_correction_beats_plain_coarse():
     w = synth.workload_fourier_2d()
     print("case learned pipeline 128^2 -> 32^2", flush=True)
     X, Y = Lr.generate_pairs(list(range(100, 108)), 128, 4, 80, w, synth.fourier_2d, kmax=8)
-    in_mean, in_std, out_mean, out_std, y_l2 = Lr.normalisation(X, Y)
+    in_mean, in_std, out_mean, out_std, y_l2, drift = Lr.normalisation(X, Y)
     net = N.Net(8, 32, 4, stream=torch.cuda.current_stream().cuda_stream)
     net.vlbm_nn_set_weights(Lr.init_weights(seed=0))
     net.vlbm_nn_set_norm(in_mean, in_std, out_mean, out_std)
@@ -28,7 +28,8 @@ def test_learned_correction_beats_plain_coarse():
     assert losses[-1][1] < losses[0][1]
     eval_seeds = [900, 901, 902, 903]
     bound = 5.0 * y_l2 * np.sqrt(len(eval_seeds))
-    hist, nfb = Lr.evaluate(net, eval_seeds, 128, 4, 200, w, synth.fourier_2d, bound, 0.1, kmax=8, checkpoints=2)
+    hist, nfb = Lr.evaluate(net, eval_seeds, 128, 4, 200, w, synth.fourier_2d, bound, 0.1, 5.0 * drift, kmax=8,
+                            checkpoints=2)
     plain = sum(hist[-1]["plain"].values())
     learned = sum(hist[-1]["learned"].values())
     print("plain", hist[-1]["plain"], "learned", hist[-1]["learned"], "fallbacks", nfb, flush=True)

@@ -162,6 +162,11 @@ def test_d3q7_slab_at_rest_fp32(vb):
 
 @pytest.mark.parametrize("storage,tol", [("f64", 1e-10), ("f32", 1e-5)])
 def test_d3q7_resistive_parity(vb, storage, tol):
+    """FP32: every field within 1e-5, except where the method's own formulas evaluated
+    in FP32 arithmetic (the oracle compiled with float) already miss it -- the small
+    transported gradients G, H ride on populations carrying an O(u) flux term, so
+    FP32 rounding of those populations sets their accuracy.  There the GPU must be
+    within 1.5x of that FP32 evaluation."""
     w = synth.workload_resistive_3d(n=16, dt_over_tau_M=0.49)
     w["shape"] = (12, 10, 8)
     Q0 = small_resistive()
@@ -169,7 +174,13 @@ def test_d3q7_resistive_parity(vb, storage, tol):
     _, Qg, _ = run_gpu(vb, w, Q0, steps, storage)
     Qo, _ = run_oracle(w, Q0, steps)
     err = rel_l2(Qg, Qo, 26)
-    assert max(err.values()) <= tol, err
+    if storage == "f64":
+        assert max(err.values()) <= tol, err
+        return
+    yard = rel_l2(oracle.run_fp32(oracle_params(w), Q0, steps), Qo, 26)
+    for name, e in err.items():
+        assert e <= max(tol, 1.5 * yard[name]), (name, e, yard[name])
+    assert max(err[k] for k in ("rho", "m", "E", "B")) <= tol, err
 
 
 # --- FP16 / BF16 deviation storage: one step at a time vs the oracle ------------
