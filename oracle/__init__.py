@@ -71,6 +71,17 @@ class Params(ctypes.Structure):
         ("j_c", ctypes.c_double),
         ("tau_M", ctypes.c_double),
         ("tau_H", ctypes.c_double),
+        ("bc", ctypes.c_int32 * 6),
+        ("body", ctypes.c_int32),
+        ("inflow_Q", ctypes.c_double * 8),
+        ("body_c0", ctypes.c_double * 3),
+        ("body_v", ctypes.c_double * 3),
+        ("body_R0", ctypes.c_double),
+        ("body_a", ctypes.c_double * 4),
+        ("body_d", (ctypes.c_double * 3) * 4),
+        ("body_b", ctypes.c_double * 4),
+        ("body_e", (ctypes.c_double * 3) * 4),
+        ("body_m", ctypes.c_double * 3),
     ]
 
 
@@ -95,6 +106,8 @@ def lib():
         L.vref_init.argtypes = [P, dp, dp]
         L.vref_run.argtypes = [P, dp, dp, ctypes.c_int]
         L.vref_moments.argtypes = [P, dp, dp, dp, dp]
+        L.vref_run_bc.argtypes = [P, dp, dp, ctypes.c_int, ctypes.c_int]
+        L.vref_solid.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double]
         _lib = L
     return _lib
 
@@ -193,6 +206,48 @@ def run(p, f, nsteps):
     return lib().vref_run(ctypes.byref(p), _ptr(f), _ptr(work), int(nsteps))
 
 
+def set_boundaries(p, bc=None, inflow_Q=None, body=None):
+    """bc: 6 face kinds (0 periodic, 1 inflow, 2 zero gradient); body: dict with c0, v,
+    R0, a[4], d[4][3], b[4], e[4][3], m[3] (or None)."""
+    if bc is not None:
+        for j in range(6):
+            p.bc[j] = int(bc[j])
+    if inflow_Q is not None:
+        for k in range(8):
+            p.inflow_Q[k] = float(inflow_Q[k])
+    p.body = 0
+    if body is not None:
+        p.body = 1
+        for a in range(3):
+            p.body_c0[a] = body["c0"][a]
+            p.body_v[a] = body["v"][a]
+            p.body_m[a] = body["m"][a]
+        p.body_R0 = body["R0"]
+        for j in range(4):
+            p.body_a[j] = body["a"][j]
+            p.body_b[j] = body["b"][j]
+            for a in range(3):
+                p.body_d[j][a] = body["d"][j][a]
+                p.body_e[j][a] = body["e"][j][a]
+    return p
+
+
+def run_bc(p, f, nsteps, t0=0):
+    """Advance f in place with the boundary kinds / body of p; returns #bad cell-steps."""
+    assert f.dtype == np.float64 and f.flags["C_CONTIGUOUS"]
+    work = np.empty_like(f)
+    return lib().vref_run_bc(ctypes.byref(p), _ptr(f), _ptr(work), int(nsteps), int(t0))
+
+
+def solid_mask(p, t):
+    m = np.zeros((p.nz, p.ny, p.nx), np.uint8)
+    for z in range(p.nz):
+        for y in range(p.ny):
+            for x in range(p.nx):
+                m[z, y, x] = lib().vref_solid(ctypes.byref(p), x, y, z, float(t))
+    return m
+
+
 def moments(p, f):
     """Returns (Q [K, N], dlat [N], totals [K+5])."""
     K, N = nvars(p), ncells(p)
@@ -243,11 +298,34 @@ def num_threads():
     return lib().vref_num_threads()
 
 
+def _as_f32(t):
+    if t is ctypes.c_double:
+        return ctypes.c_float
+    if hasattr(t, "_length_"):
+        return _as_f32(t._type_) * t._length_
+    return t
+
+
 class Params32(ctypes.Structure):
     """``vref_params`` of the FP32-arithmetic build (every double is a float)."""
 
-    _fields_ = [(n, (ctypes.c_float * KMAX) if n == "tau" else (ctypes.c_float if t is ctypes.c_double else t))
-                for n, t in Params._fields_]
+    _fields_ = [(n, _as_f32(t)) for n, t in Params._fields_]
+
+
+def _copy_struct(src, dst):
+    """Field-by-field copy between the FP64 and FP32 parameter mirrors."""
+    def cp(a, b):
+        for j in range(len(a)):
+            if hasattr(a[j], "__len__"):
+                cp(a[j], b[j])
+            else:
+                b[j] = a[j]
+    for n, _ in Params._fields_:
+        v = getattr(src, n)
+        if hasattr(v, "__len__"):
+            cp(v, getattr(dst, n))
+        else:
+            setattr(dst, n, v)
 
 
 def run_fp32(p, Q, nsteps):
@@ -258,13 +336,7 @@ def run_fp32(p, Q, nsteps):
     L = ctypes.CDLL(_SO32)
     fp = ctypes.POINTER(ctypes.c_float)
     q = Params32()
-    for n, _ in Params._fields_:
-        v = getattr(p, n)
-        if n == "tau":
-            for k in range(KMAX):
-                q.tau[k] = v[k]
-        else:
-            setattr(q, n, v)
+    _copy_struct(p, q)
     K, NQ, N = nvars(p), ndirs(p), ncells(p)
     Q32 = np.ascontiguousarray(np.asarray(Q, np.float64).reshape(K, N), np.float32)
     f = np.empty((K, NQ, N), np.float32)

@@ -327,3 +327,219 @@ int vref_moments(const vref_params* p, const double* f, double* Q_out, double* d
   free(dall);
   return nbad;
 }
+
+/* ------------------------------------------------------------------------- */
+/* boundaries (Sec. 2.4) and the moving body                                 */
+/* ------------------------------------------------------------------------- */
+
+/* READING (body, not in the paper -- the paper uses a homogenised body): a rough
+ * sphere given by its surface radius along each direction; solid = cell centre
+ * strictly inside. */
+int vref_solid(const vref_params* p, int x, int y, int z, double t) {
+  if (!p->body) return 0;
+  const double r[3] = {x - (p->body_c0[0] + t * p->body_v[0]), y - (p->body_c0[1] + t * p->body_v[1]),
+                       z - (p->body_c0[2] + t * p->body_v[2])};
+  const double rr = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  if (rr == 0.0) return 1;
+  double delta = 0.0;
+  for (int j = 0; j < 4; ++j) {
+    double dn = 0.0, en = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      dn += p->body_d[j][a] * r[a] / rr;
+      en += p->body_e[j][a] * r[a] / rr;
+    }
+    delta += p->body_a[j] * dn + p->body_b[j] * (en * en - 1.0 / 3.0);
+  }
+  return rr < p->body_R0 * (1.0 + delta);
+}
+
+/* dipole field of the body at point q (absolute cell coordinates), time t */
+static void dipole_field(const vref_params* p, const double* q, double t, double* B) {
+  double r[3];
+  for (int a = 0; a < 3; ++a) r[a] = q[a] - (p->body_c0[a] + t * p->body_v[a]);
+  const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+  const double r5 = r2 * r2 * sqrt(r2);
+  const double mr = p->body_m[0] * r[0] + p->body_m[1] * r[1] + p->body_m[2] * r[2];
+  for (int a = 0; a < 3; ++a) B[a] = (3.0 * mr * r[a] - p->body_m[a] * r2) / r5;
+}
+
+/* 1 if the cell lies on a non-periodic face; *inflow set if on an inflow face */
+static int face_node(const vref_params* p, const int c[3], int* inflow) {
+  const int n[3] = {p->nx, p->ny, p->nz};
+  int on = 0;
+  *inflow = 0;
+  for (int a = 0; a < p->dim; ++a) {
+    if (c[a] == 0 && p->bc[2 * a] != 0) {
+      on = 1;
+      if (p->bc[2 * a] == 1) *inflow = 1;
+    }
+    if (c[a] == n[a] - 1 && p->bc[2 * a + 1] != 0) {
+      on = 1;
+      if (p->bc[2 * a + 1] == 1) *inflow = 1;
+    }
+  }
+  return on;
+}
+
+static void cell_moments(const vref_params* p, const double* f, long N, long cell, double* Q) {
+  const int K = vref_nvars(p), NQ = vref_ndirs(p);
+  for (int k = 0; k < K; ++k) {
+    Q[k] = 0.0;
+    for (int i = 0; i < NQ; ++i) Q[k] += f[((long)k * NQ + i) * N + cell];
+  }
+}
+
+static long cell_index(const vref_params* p, const int c[3]) {
+  return (long)c[0] + (long)p->nx * ((long)c[1] + (long)p->ny * c[2]);
+}
+
+int vref_run_bc(const vref_params* p, double* f, double* work, int nsteps, int t0) {
+  const int K = vref_nvars(p), NQ = vref_ndirs(p), d = p->dim;
+  const long N = ncells(p);
+  const int n[3] = {p->nx, p->ny, p->nz};
+  const double c2 = cs2(p), wi = weight(p, 1);
+  unsigned char* solid = (unsigned char*)malloc((size_t)N);
+  unsigned char* solid_next = (unsigned char*)malloc((size_t)N);
+  double* qbc = (double*)malloc(sizeof(double) * (size_t)VREF_KMAX * N);
+  if (!solid || !solid_next || !qbc) {
+    free(solid);
+    free(solid_next);
+    free(qbc);
+    return -1;
+  }
+  int nbad = 0;
+  for (long c = 0; c < N; ++c) {
+    const int x = (int)(c % p->nx), y = (int)((c / p->nx) % p->ny), z = (int)(c / ((long)p->nx * p->ny));
+    solid[c] = (unsigned char)vref_solid(p, x, y, z, (double)t0);
+  }
+  for (int step = 0; step < nsteps; ++step) {
+    const double t = (double)(t0 + step);
+    /* Sec. 2.4 static boundaries: every node on a non-periodic face takes the
+     * equilibrium of its boundary state -- the Dirichlet state on an inflow face,
+     * otherwise (zero gradient) the moments of the nearest interior cell along the
+     * face normals.  All boundary states are read first, then written. */
+    for (long cell = 0; cell < N; ++cell) {
+      const int cc[3] = {(int)(cell % p->nx), (int)((cell / p->nx) % p->ny), (int)(cell / ((long)p->nx * p->ny))};
+      int inflow;
+      if (!face_node(p, cc, &inflow)) continue;
+      double* Q = qbc + (long)VREF_KMAX * cell;
+      if (inflow) {
+        for (int k = 0; k < K; ++k) Q[k] = k < 8 ? p->inflow_Q[k] : 0.0;
+      } else {
+        int ic[3] = {cc[0], cc[1], cc[2]};
+        for (int a = 0; a < d; ++a)
+          if (p->bc[2 * a] != 0 || p->bc[2 * a + 1] != 0) {
+            if (ic[a] < 1) ic[a] = 1;
+            if (ic[a] > n[a] - 2) ic[a] = n[a] - 2;
+          }
+        cell_moments(p, f, N, cell_index(p, ic), Q);
+      }
+    }
+    for (long cell = 0; cell < N; ++cell) {
+      const int cc[3] = {(int)(cell % p->nx), (int)((cell / p->nx) % p->ny), (int)(cell / ((long)p->nx * p->ny))};
+      int inflow;
+      if (!face_node(p, cc, &inflow)) continue;
+      double feq[VREF_KMAX * 7];
+      vref_equilibrium(p, qbc + (long)VREF_KMAX * cell, feq);
+      for (int k = 0; k < K; ++k)
+        for (int i = 0; i < NQ; ++i) f[((long)k * NQ + i) * N + cell] = feq[k * NQ + i];
+    }
+    memset(work, 0, sizeof(double) * (size_t)K * NQ * N);
+#pragma omp parallel for schedule(static) reduction(+ : nbad)
+    for (long cell = 0; cell < N; ++cell) {
+      if (solid[cell]) continue;
+      const int cc[3] = {(int)(cell % p->nx), (int)((cell / p->nx) % p->ny), (int)(cell / ((long)p->nx * p->ny))};
+      double fc[VREF_KMAX * 7], fs[VREF_KMAX * 7], Q[VREF_KMAX];
+      for (int k = 0; k < K; ++k)
+        for (int i = 0; i < NQ; ++i) fc[k * NQ + i] = f[((long)k * NQ + i) * N + cell];
+      nbad += vref_collide(p, fc, fs, NULL);
+      cell_moments(p, f, N, cell, Q);
+      for (int k = 0; k < K; ++k) work[((long)k * NQ + 0) * N + cell] = fs[k * NQ + 0];
+      for (int i = 1; i < NQ; ++i) {
+        /* streaming with periodic addressing: what leaves through a non-periodic
+         * face lands on a node of the opposite face, which the next step overwrites */
+        const long tgt = neighbour(p, cc[0], cc[1], cc[2], i);
+        const int ib = (i % 2 == 1) ? i + 1 : i - 1; /* opposite direction */
+        if (solid[tgt]) {
+          /* READING (body boundary): bounce back into the opposite direction of the
+           * same cell.  rho, e_tot: halfway bounce-back with the moving-wall flux
+           * correction -2 w_i c_i . s Phi_w / c_s^2 (Phi_w: the cell's flux with the
+           * wall velocity); rho u, B: anti-bounce-back -f* + 2 w_i Q_w to the wall
+           * values rho u_w and the dipole field at the link midpoint. */
+          const double* uw = p->body_v;
+          double q[3], Bw[3];
+          for (int a = 0; a < 3; ++a) q[a] = cc[a] + 0.5 * (a < d ? edir(i, a) : 0);
+          dipole_field(p, q, t, Bw);
+          const double rho = Q[0], E = Q[4];
+          const double B[3] = {Q[5], Q[6], Q[7]};
+          double uu = 0.0, BB = 0.0;
+          for (int a = 0; a < 3; ++a) {
+            const double u = Q[1 + a] / rho;
+            uu += u * u;
+            BB += B[a] * B[a];
+          }
+          const double pcell = (p->gamma - 1.0) * (E - 0.5 * rho * uu - 0.5 * BB);
+          const double ptcell = pcell + 0.5 * BB;
+          const double uB = uw[0] * B[0] + uw[1] * B[1] + uw[2] * B[2];
+          double ephi_rho = 0.0, ephi_E = 0.0;
+          for (int a = 0; a < d; ++a) {
+            ephi_rho += edir(i, a) * p->s * rho * uw[a];
+            ephi_E += edir(i, a) * p->s * ((E + ptcell) * uw[a] - B[a] * uB);
+          }
+          for (int k = 0; k < K; ++k) {
+            const double v = fs[k * NQ + i];
+            double out;
+            if (k == 0)
+              out = v - 2.0 * wi * ephi_rho / c2;
+            else if (k == 4)
+              out = v - 2.0 * wi * ephi_E / c2;
+            else if (k >= 1 && k <= 3)
+              out = -v + 2.0 * wi * rho * uw[k - 1];
+            else if (k >= 5 && k <= 7)
+              out = -v + 2.0 * wi * Bw[k - 5];
+            else
+              out = v;
+            work[((long)k * NQ + ib) * N + cell] = out;
+          }
+        } else {
+          for (int k = 0; k < K; ++k) work[((long)k * NQ + i) * N + tgt] = fs[k * NQ + i];
+        }
+      }
+    }
+    memcpy(f, work, sizeof(double) * (size_t)K * NQ * N);
+    /* body moves: cells it uncovers get f^eq of the mean moments of the neighbours
+     * that are fluid before and after the move */
+    for (long c = 0; c < N; ++c) {
+      const int x = (int)(c % p->nx), y = (int)((c / p->nx) % p->ny), z = (int)(c / ((long)p->nx * p->ny));
+      solid_next[c] = (unsigned char)vref_solid(p, x, y, z, t + 1.0);
+    }
+    for (long c = 0; c < N; ++c) {
+      if (!(solid[c] && !solid_next[c])) continue;
+      const int cc[3] = {(int)(c % p->nx), (int)((c / p->nx) % p->ny), (int)(c / ((long)p->nx * p->ny))};
+      double Qm[VREF_KMAX], Qn[VREF_KMAX];
+      int cnt = 0;
+      for (int k = 0; k < K; ++k) Qm[k] = 0.0;
+      for (int i = 1; i < NQ; ++i) {
+        const long nb = neighbour(p, cc[0], cc[1], cc[2], i);
+        if (solid[nb] || solid_next[nb]) continue;
+        cell_moments(p, f, N, nb, Qn);
+        for (int k = 0; k < K; ++k) Qm[k] += Qn[k];
+        ++cnt;
+      }
+      if (cnt == 0) {
+        for (int k = 0; k < K; ++k) Qm[k] = k < 8 ? p->inflow_Q[k] : 0.0;
+      } else {
+        for (int k = 0; k < K; ++k) Qm[k] /= cnt;
+      }
+      double feq[VREF_KMAX * 7];
+      vref_equilibrium(p, Qm, feq);
+      for (int k = 0; k < K; ++k)
+        for (int i = 0; i < NQ; ++i) f[((long)k * NQ + i) * N + c] = feq[k * NQ + i];
+    }
+    memcpy(solid, solid_next, (size_t)N);
+  }
+  free(solid);
+  free(solid_next);
+  free(qbc);
+  return nbad;
+}

@@ -39,6 +39,18 @@ typedef struct {
   double tau[VREF_KMAX]; /* lattice relaxation time per variable (> 0.5) */
   double dt;          /* physical time step (resistive model sources) */
   double mu, eta0, j_c, tau_M, tau_H; /* resistive model; j_c <= 0: constant eta */
+  /* boundaries (vref_run_bc only): per face x-, x+, y-, y+, z-, z+:
+   * 0 periodic, 1 inflow (equilibrium of inflow_Q), 2 zero gradient (equilibrium of
+   * the moments of the nearest interior cell) */
+  int32_t bc[6];
+  int32_t body;       /* 1: moving rough sphere with a dipole field */
+  double inflow_Q[8];
+  /* body: centre c(t) = c0 + t v (cell units, time in steps); surface radius along
+   * the unit direction n: R0 (1 + sum_j a_j (d_j . n) + sum_j b_j ((e_j . n)^2 - 1/3));
+   * dipole moment m at the centre: B(r) = (3 (m . r) r - m |r|^2) / |r|^5 */
+  double body_c0[3], body_v[3], body_R0;
+  double body_a[4], body_d[4][3], body_b[4], body_e[4][3];
+  double body_m[3];
 } vref_params;
 
 /* number of variables K and of directions Q */
@@ -74,6 +86,18 @@ int vref_run(const vref_params* p, double* f, double* work, int nsteps);
  * [K+3] sum_x (central div B)^2, [K+4] number of unphysical cells. */
 int vref_moments(const vref_params* p, const double* f, double* Q_out, double* dlat,
                  double* totals);
+
+/* Sec. 2.4 static boundaries and a moving body: nsteps steps with the face kinds
+ * of p->bc and, if p->body, the moving rough sphere.  t0 = time (steps) of the
+ * state in f.  Face nodes emit f^eq of their boundary state instead of colliding;
+ * links from a fluid cell into the body bounce back (rho, e_tot: halfway bounce-back
+ * with the moving-wall flux correction; rho u, B: anti-bounce-back to the wall
+ * values rho u_w and the dipole field); cells the body uncovers are refilled with
+ * f^eq of the mean moments of their fluid neighbours.  work has the size of f. */
+int vref_run_bc(const vref_params* p, double* f, double* work, int nsteps, int t0);
+
+/* 1 if cell (x, y, z) is inside the body at time t (steps). */
+int vref_solid(const vref_params* p, int x, int y, int z, double t);
 
 int vref_num_threads(void);
 

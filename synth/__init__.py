@@ -230,3 +230,73 @@ def workload_slab_3d(n=512, steps=2000):
     0.04 (keeps s (|u| + c_fast) below c_s^2 at rho = 0.1, |B| = 1)."""
     return dict(dim=3, shape=(n, n, n), model=0, s=0.04, gamma=5.0 / 3.0, tau=0.6, powell=1,
                 divb_mode=0, steps=steps, dt=0.0, mu=0.0, eta0=0.0, tau_M=1.0, tau_H=1.0)
+
+
+def workload_body_3d(shape=(768, 384, 384), steps=4000, tau=0.6, s=0.05):
+    """3D ideal MHD past a moving body, D3Q7 x 8 variables: inflow at x-, zero-gradient
+    elsewhere; flux scale 0.05 keeps s (|u| + c_fast) <= c_s^2 at Mach 3."""
+    return dict(dim=3, shape=tuple(shape), model=0, s=s, gamma=5.0 / 3.0, tau=tau, powell=1, divb_mode=0,
+                steps=steps, dt=0.0, mu=0.0, eta0=0.0, tau_M=1.0, tau_H=1.0, bc=(1, 2, 2, 2, 2, 2))
+
+
+def inflow_state(mach=3.0, alfven_mach=8.0, angle_deg=30.0, rho=1.0, p=0.6, gamma=5.0 / 3.0):
+    """Uniform inflow along +x: sound speed sqrt(gamma p / rho) = 1 for the defaults,
+    |u| = mach * c, |B| = |u| sqrt(rho) / alfven_mach at `angle_deg` in the x-y plane."""
+    c = np.sqrt(gamma * p / rho)
+    u = np.array([mach * c, 0.0, 0.0])
+    b = u[0] * np.sqrt(rho) / alfven_mach
+    a = np.deg2rad(angle_deg)
+    B = np.array([b * np.cos(a), b * np.sin(a), 0.0])
+    return conserved_from_primitive(rho, u, p, B, gamma), dict(u=u, B=B, rho=rho, p=p)
+
+
+def body_params(shape=(768, 384, 384), seed=4, R0=48.0, speed=0.02, rough=0.05, dipole_ratio=10.0,
+                B_in=0.375):
+    """Seeded rough sphere: centre at (nx/4, 5 ny/12, nz/2) moving along +y at `speed`
+    cells per step; surface radius R0 (1 + delta(n)) with delta a seeded sum of
+    degree-1 and degree-2 terms, |delta| <= rough; a dipole along a seeded direction
+    whose equatorial surface field is dipole_ratio |B_in|."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = shape
+    d = rng.standard_normal((4, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    e = rng.standard_normal((4, 3))
+    e /= np.linalg.norm(e, axis=1, keepdims=True)
+    a = rng.uniform(-1, 1, 4)
+    b = rng.uniform(-1, 1, 4)
+    # |a.(d.n)| <= |a|, |b ((e.n)^2 - 1/3)| <= 2/3 |b|
+    scale = rough / (np.abs(a).sum() + (2.0 / 3.0) * np.abs(b).sum())
+    md = rng.standard_normal(3)
+    md /= np.linalg.norm(md)
+    m = md * dipole_ratio * B_in * R0 ** 3
+    return dict(c0=[nx / 4.0, 5.0 * ny / 12.0, nz / 2.0], v=[0.0, speed, 0.0], R0=float(R0),
+                a=list(a * scale), d=d.tolist(), b=list(b * scale), e=e.tolist(), m=m.tolist())
+
+
+def body_initial_state(shape, body, mach=3.0, alfven_mach=8.0, angle_deg=30.0, rho=1.0, p=0.6,
+                       gamma=5.0 / 3.0, dtype=np.float64):
+    """Inflow state everywhere with the body's dipole field superposed on the inflow
+    field (outside a core of radius R0/2 around the centre, where the dipole is
+    singular), e_tot from that field; [8, nz, ny, nx]."""
+    nx, ny, nz = shape
+    _, info = inflow_state(mach, alfven_mach, angle_deg, rho, p, gamma)
+    z = np.arange(nz, dtype=np.float64)[:, None, None] - body["c0"][2]
+    y = np.arange(ny, dtype=np.float64)[None, :, None] - body["c0"][1]
+    x = np.arange(nx, dtype=np.float64)[None, None, :] - body["c0"][0]
+    r2 = x * x + y * y + z * z
+    r2 = np.maximum(r2, (0.5 * body["R0"]) ** 2)
+    m = body["m"]
+    mr = m[0] * x + m[1] * y + m[2] * z
+    r5 = r2 * r2 * np.sqrt(r2)
+    Q = np.empty((8, nz, ny, nx), dtype)
+    Bsq = np.zeros((nz, ny, nx))
+    for a, ra in enumerate((x, y, z)):
+        Ba = info["B"][a] + (3.0 * mr * ra - m[a] * r2) / r5
+        Q[5 + a] = Ba
+        Bsq = Bsq + Ba * Ba
+    u = info["u"]
+    Q[0] = rho
+    for a in range(3):
+        Q[1 + a] = rho * u[a]
+    Q[4] = p / (gamma - 1.0) + 0.5 * rho * (u @ u) + 0.5 * Bsq
+    return Q
