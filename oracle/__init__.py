@@ -39,8 +39,9 @@ def build(force: bool = True) -> str:
             text = fh.read().replace("double", "float").replace("fabs(", "fabsf(")
         with open(os.path.join(gen, name), "w") as fh:
             fh.write(text)
+    newest = max(os.path.getmtime(os.path.join(_HERE, n)) for n in ("vlbm_ref.c", "vlbm_ref.h"))
     for out, src in ((_SO, _HERE), (_SO32, gen)):
-        if force or not os.path.exists(out):
+        if force or not os.path.exists(out) or os.path.getmtime(out) < newest:
             tmp = out + ".tmp"
             subprocess.check_call(
                 ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-I", src,
@@ -108,6 +109,8 @@ def lib():
         L.vref_moments.argtypes = [P, dp, dp, dp, dp]
         L.vref_run_bc.argtypes = [P, dp, dp, ctypes.c_int, ctypes.c_int]
         L.vref_solid.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double]
+        L.vref_porosity.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double]
+        L.vref_porosity.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -206,9 +209,10 @@ def run(p, f, nsteps):
     return lib().vref_run(ctypes.byref(p), _ptr(f), _ptr(work), int(nsteps))
 
 
-def set_boundaries(p, bc=None, inflow_Q=None, body=None):
+def set_boundaries(p, bc=None, inflow_Q=None, body=None, body_mode=1):
     """bc: 6 face kinds (0 periodic, 1 inflow, 2 zero gradient); body: dict with c0, v,
-    R0, a[4], d[4][3], b[4], e[4][3], m[3] (or None)."""
+    R0, a[4], d[4][3], b[4], e[4][3], m[3] (or None); body_mode 1 bounce-back,
+    2 homogenized."""
     if bc is not None:
         for j in range(6):
             p.bc[j] = int(bc[j])
@@ -217,7 +221,7 @@ def set_boundaries(p, bc=None, inflow_Q=None, body=None):
             p.inflow_Q[k] = float(inflow_Q[k])
     p.body = 0
     if body is not None:
-        p.body = 1
+        p.body = int(body_mode)
         for a in range(3):
             p.body_c0[a] = body["c0"][a]
             p.body_v[a] = body["v"][a]
@@ -246,6 +250,17 @@ def solid_mask(p, t):
             for x in range(p.nx):
                 m[z, y, x] = lib().vref_solid(ctypes.byref(p), x, y, z, float(t))
     return m
+
+
+def porosity(p, t):
+    """Lattice porosity d [nz, ny, nx] of the homogenized body at time t."""
+    L = lib()
+    d = np.empty((p.nz, p.ny, p.nx))
+    for z in range(p.nz):
+        for y in range(p.ny):
+            for x in range(p.nx):
+                d[z, y, x] = L.vref_porosity(ctypes.byref(p), x, y, z, float(t))
+    return d
 
 
 def moments(p, f):

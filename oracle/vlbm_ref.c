@@ -188,7 +188,12 @@ void vref_equilibrium(const vref_params* p, const double* Q, double* feq) {
  * zeroth and first moments Q_k = sum_i f_{k,i}, J_k = sum_i e_i f_{k,i};
  * fluxes and source from Q (and J for the div B estimate);
  * f*_{k,i} = f_{k,i} - (f_{k,i} - f^eq_{k,i}) / tau_k + w_i S~_k. */
-int vref_collide(const vref_params* p, const double* f, double* fstar, double* dlat) {
+static void homogenize(const vref_params* p, const int cell[3], double t, double* Q);
+
+/* cell == NULL: plain collision; else the cell's coordinates, and the target state
+ * of the collision is homogenized with the body (Sec. 2.4) at time t. */
+static int collide_cell(const vref_params* p, const double* f, double* fstar, double* dlat,
+                        const int* cell, double t) {
   const int K = vref_nvars(p), NQ = vref_ndirs(p), d = p->dim;
   double Q[VREF_KMAX], J[VREF_KMAX * 3], Phi[VREF_KMAX * 3], S[VREF_KMAX];
   double feq[VREF_KMAX * 7];
@@ -200,6 +205,7 @@ int vref_collide(const vref_params* p, const double* f, double* fstar, double* d
       for (int a = 0; a < d; ++a) J[3 * k + a] += edir(i, a) * f[k * NQ + i];
     }
   }
+  if (cell) homogenize(p, cell, t, Q);
   double dl;
   const int bad = vref_flux_source(p, Q, J, Phi, S, &dl);
   equilibrium_from_flux(p, Q, Phi, feq);
@@ -210,6 +216,10 @@ int vref_collide(const vref_params* p, const double* f, double* fstar, double* d
     }
   if (dlat) *dlat = dl;
   return bad;
+}
+
+int vref_collide(const vref_params* p, const double* f, double* fstar, double* dlat) {
+  return collide_cell(p, f, fstar, dlat, NULL, 0.0);
 }
 
 /* vref_collide on n independent cells: f and fstar are [n][K][Q]. */
@@ -335,22 +345,98 @@ int vref_moments(const vref_params* p, const double* f, double* Q_out, double* d
 /* READING (body, not in the paper -- the paper uses a homogenised body): a rough
  * sphere given by its surface radius along each direction; solid = cell centre
  * strictly inside. */
-int vref_solid(const vref_params* p, int x, int y, int z, double t) {
-  if (!p->body) return 0;
-  const double r[3] = {x - (p->body_c0[0] + t * p->body_v[0]), y - (p->body_c0[1] + t * p->body_v[1]),
-                       z - (p->body_c0[2] + t * p->body_v[2])};
-  const double rr = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-  if (rr == 0.0) return 1;
+/* Offset r of cell (x, y, z) from the body centre at time t, its length, and the
+ * surface radius R0 (1 + delta(n)) along n = r / |r| (R0 at the centre). */
+static double surface_radius(const vref_params* p, int x, int y, int z, double t, double r[3], double* rr) {
+  r[0] = x - (p->body_c0[0] + t * p->body_v[0]);
+  r[1] = y - (p->body_c0[1] + t * p->body_v[1]);
+  r[2] = z - (p->body_c0[2] + t * p->body_v[2]);
+  *rr = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  if (*rr == 0.0) return p->body_R0;
   double delta = 0.0;
   for (int j = 0; j < 4; ++j) {
     double dn = 0.0, en = 0.0;
     for (int a = 0; a < 3; ++a) {
-      dn += p->body_d[j][a] * r[a] / rr;
-      en += p->body_e[j][a] * r[a] / rr;
+      dn += p->body_d[j][a] * r[a] / *rr;
+      en += p->body_e[j][a] * r[a] / *rr;
     }
     delta += p->body_a[j] * dn + p->body_b[j] * (en * en - 1.0 / 3.0);
   }
-  return rr < p->body_R0 * (1.0 + delta);
+  return p->body_R0 * (1.0 + delta);
+}
+
+int vref_solid(const vref_params* p, int x, int y, int z, double t) {
+  if (!p->body) return 0;
+  double r[3], rr;
+  const double R = surface_radius(p, x, y, z, t, r, &rr);
+  return rr == 0.0 || rr < R;
+}
+
+/* Sec. 2.4 homogenization: lattice porosity d from the signed distance phi to the
+ * surface (positive in the fluid) with the linear transition of width eps_h:
+ * d = 0 for phi <= -eps_h/2, phi/eps_h + 1/2 inside, 1 for phi >= eps_h/2.
+ * READING: eps_h = one cell (the paper's single-cell transition); phi = |r| - R(n),
+ * the radial distance to the surface (exact for a sphere). */
+double vref_porosity(const vref_params* p, int x, int y, int z, double t) {
+  if (!p->body) return 1.0;
+  double r[3], rr;
+  const double R = surface_radius(p, x, y, z, t, r, &rr);
+  const double phi = rr - R, eps = 1.0;
+  if (phi <= -0.5 * eps) return 0.0;
+  if (phi >= 0.5 * eps) return 1.0;
+  return phi / eps + 0.5;
+}
+
+/* Field of the body at cell (x, y, z), time t.  READING (the paper gives the body a
+ * prescribed field B^B without a formula): a sphere of radius R0 magnetised
+ * uniformly with moment m -- the dipole field (3 (m.r) r - m |r|^2) / |r|^5
+ * outside R0 and the uniform 2 m / R0^3 inside, which join with continuous normal
+ * component, so that B^B is divergence free. */
+static void body_field(const vref_params* p, int x, int y, int z, double t, double B[3]) {
+  double r[3];
+  r[0] = x - (p->body_c0[0] + t * p->body_v[0]);
+  r[1] = y - (p->body_c0[1] + t * p->body_v[1]);
+  r[2] = z - (p->body_c0[2] + t * p->body_v[2]);
+  const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+  const double R0 = p->body_R0;
+  if (r2 < R0 * R0) {
+    for (int a = 0; a < 3; ++a) B[a] = 2.0 * p->body_m[a] / (R0 * R0 * R0);
+    return;
+  }
+  const double r5 = r2 * r2 * sqrt(r2);
+  const double mr = p->body_m[0] * r[0] + p->body_m[1] * r[1] + p->body_m[2] * r[2];
+  for (int a = 0; a < 3; ++a) B[a] = (3.0 * mr * r[a] - p->body_m[a] * r2) / r5;
+}
+
+/* Sec. 2.4 homogenized target state of a cell: u^ = d u + (1 - d) u^B and
+ * B^ = d B + (1 - d) B^B replace u and B in the equilibrium and the flux (and, as
+ * a READING, in the Powell source evaluated with them).  READING: the homogenized
+ * state keeps rho and the fluid's pressure, so e_tot^ = p/(gamma-1) + rho|u^|^2/2 +
+ * |B^|^2/2.  u^B: the body's velocity in flux units, body_v / s (a velocity u moves
+ * u s cells per step). */
+static void homogenize(const vref_params* p, const int cell[3], double t, double* Q) {
+  const double d = vref_porosity(p, cell[0], cell[1], cell[2], t);
+  if (d >= 1.0) return;
+  double Bb[3];
+  body_field(p, cell[0], cell[1], cell[2], t, Bb);
+  const double rho = Q[0], gm1 = p->gamma - 1.0;
+  double u[3], uu = 0.0, BB = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    u[a] = Q[1 + a] / rho;
+    uu += u[a] * u[a];
+    BB += Q[5 + a] * Q[5 + a];
+  }
+  const double pres = gm1 * (Q[4] - 0.5 * rho * uu - 0.5 * BB);
+  double uh2 = 0.0, Bh2 = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    const double uh = d * u[a] + (1.0 - d) * p->body_v[a] / p->s;
+    const double Bh = d * Q[5 + a] + (1.0 - d) * Bb[a];
+    Q[1 + a] = rho * uh;
+    Q[5 + a] = Bh;
+    uh2 += uh * uh;
+    Bh2 += Bh * Bh;
+  }
+  Q[4] = pres / gm1 + 0.5 * rho * uh2 + 0.5 * Bh2;
 }
 
 /* dipole field of the body at point q (absolute cell coordinates), time t */
@@ -410,7 +496,7 @@ int vref_run_bc(const vref_params* p, double* f, double* work, int nsteps, int t
   int nbad = 0;
   for (long c = 0; c < N; ++c) {
     const int x = (int)(c % p->nx), y = (int)((c / p->nx) % p->ny), z = (int)(c / ((long)p->nx * p->ny));
-    solid[c] = (unsigned char)vref_solid(p, x, y, z, (double)t0);
+    solid[c] = (unsigned char)(p->body == 1 && vref_solid(p, x, y, z, (double)t0));
   }
   for (int step = 0; step < nsteps; ++step) {
     const double t = (double)(t0 + step);
@@ -452,7 +538,7 @@ int vref_run_bc(const vref_params* p, double* f, double* work, int nsteps, int t
       double fc[VREF_KMAX * 7], fs[VREF_KMAX * 7], Q[VREF_KMAX];
       for (int k = 0; k < K; ++k)
         for (int i = 0; i < NQ; ++i) fc[k * NQ + i] = f[((long)k * NQ + i) * N + cell];
-      nbad += vref_collide(p, fc, fs, NULL);
+      nbad += collide_cell(p, fc, fs, NULL, p->body == 2 ? cc : NULL, t);
       cell_moments(p, f, N, cell, Q);
       for (int k = 0; k < K; ++k) work[((long)k * NQ + 0) * N + cell] = fs[k * NQ + 0];
       for (int i = 1; i < NQ; ++i) {
@@ -466,7 +552,9 @@ int vref_run_bc(const vref_params* p, double* f, double* work, int nsteps, int t
            * correction -2 w_i c_i . s Phi_w / c_s^2 (Phi_w: the cell's flux with the
            * wall velocity); rho u, B: anti-bounce-back -f* + 2 w_i Q_w to the wall
            * values rho u_w and the dipole field at the link midpoint. */
-          const double* uw = p->body_v;
+          /* wall velocity in flux units: the body moves body_v cells per step,
+           * a velocity u moves u s cells per step (s = dt/dx) */
+          const double uw[3] = {p->body_v[0] / p->s, p->body_v[1] / p->s, p->body_v[2] / p->s};
           double q[3], Bw[3];
           for (int a = 0; a < 3; ++a) q[a] = cc[a] + 0.5 * (a < d ? edir(i, a) : 0);
           dipole_field(p, q, t, Bw);
@@ -511,7 +599,7 @@ int vref_run_bc(const vref_params* p, double* f, double* work, int nsteps, int t
      * that are fluid before and after the move */
     for (long c = 0; c < N; ++c) {
       const int x = (int)(c % p->nx), y = (int)((c / p->nx) % p->ny), z = (int)(c / ((long)p->nx * p->ny));
-      solid_next[c] = (unsigned char)vref_solid(p, x, y, z, t + 1.0);
+      solid_next[c] = (unsigned char)(p->body == 1 && vref_solid(p, x, y, z, t + 1.0));
     }
     for (long c = 0; c < N; ++c) {
       if (!(solid[c] && !solid_next[c])) continue;

@@ -43,7 +43,8 @@ typedef struct {
    * 0 periodic, 1 inflow (equilibrium of inflow_Q), 2 zero gradient (equilibrium of
    * the moments of the nearest interior cell) */
   int32_t bc[6];
-  int32_t body;       /* 1: moving rough sphere with a dipole field */
+  int32_t body;       /* moving rough sphere with a dipole field: 0 none, 1 bounce-back,
+                         2 homogenized (porosity blending of Sec. 2.4) */
   double inflow_Q[8];
   /* body: centre c(t) = c0 + t v (cell units, time in steps); surface radius along
    * the unit direction n: R0 (1 + sum_j a_j (d_j . n) + sum_j b_j ((e_j . n)^2 - 1/3));
@@ -90,14 +91,19 @@ int vref_moments(const vref_params* p, const double* f, double* Q_out, double* d
 /* Sec. 2.4 static boundaries and a moving body: nsteps steps with the face kinds
  * of p->bc and, if p->body, the moving rough sphere.  t0 = time (steps) of the
  * state in f.  Face nodes emit f^eq of their boundary state instead of colliding;
- * links from a fluid cell into the body bounce back (rho, e_tot: halfway bounce-back
- * with the moving-wall flux correction; rho u, B: anti-bounce-back to the wall
- * values rho u_w and the dipole field); cells the body uncovers are refilled with
- * f^eq of the mean moments of their fluid neighbours.  work has the size of f. */
+ * body 1: links from a fluid cell into the body bounce back (rho, e_tot: halfway
+ * bounce-back with the moving-wall flux correction; rho u, B: anti-bounce-back to
+ * the wall values rho u_w and the dipole field); cells the body uncovers are
+ * refilled with f^eq of the mean moments of their fluid neighbours.
+ * body 2: every cell collides toward its homogenized state (porosity blending of
+ * u and B with the body's velocity and field).  work has the size of f. */
 int vref_run_bc(const vref_params* p, double* f, double* work, int nsteps, int t0);
 
 /* 1 if cell (x, y, z) is inside the body at time t (steps). */
 int vref_solid(const vref_params* p, int x, int y, int z, double t);
+
+/* Lattice porosity d in [0, 1] of the homogenized body at cell (x, y, z), time t. */
+double vref_porosity(const vref_params* p, int x, int y, int z, double t);
 
 int vref_num_threads(void);
 

@@ -300,3 +300,42 @@ def body_initial_state(shape, body, mach=3.0, alfven_mach=8.0, angle_deg=30.0, r
         Q[1 + a] = rho * u[a]
     Q[4] = p / (gamma - 1.0) + 0.5 * rho * (u @ u) + 0.5 * Bsq
     return Q
+
+
+def smooth_box_state(shape, seed, amp=0.1, rho=1.0, p=0.6, B0=0.3, gamma=5.0 / 3.0):
+    """Smooth, non-periodic random state [8, nz, ny, nx]: each primitive field is a
+    seeded sum of one sine or cosine per axis of the normalised cell coordinates,
+    amplitude amp, around rho, u = 0, p and a uniform B0 in every component."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz) / nz, np.arange(ny) / ny, np.arange(nx) / nx, indexing="ij")
+
+    def fld():
+        a = rng.uniform(-1, 1, 6)
+        return a[0] * np.sin(2.1 * x + a[1]) + a[2] * np.cos(1.7 * y + a[3]) + a[4] * np.sin(2.3 * z + a[5])
+
+    r = rho + amp * fld()
+    u = amp * np.stack([fld(), fld(), fld()])
+    pr = p + amp * fld()
+    B = B0 + amp * np.stack([fld(), fld(), fld()])
+    return conserved_from_primitive(r, u, pr, B, gamma)
+
+
+def rough_body(c0, v, R0, m=(0.0, 0.0, 0.0), rough=0.0, seed=1):
+    """Body description (the dict the boundary code takes) of a sphere of radius R0
+    centred at c0 moving at v, with seeded roughness sum_j |a_j| + |b_j| = rough
+    (0: a smooth sphere) and dipole moment m."""
+    rng = np.random.default_rng(seed)
+    d = rng.standard_normal((4, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    e = rng.standard_normal((4, 3))
+    e /= np.linalg.norm(e, axis=1, keepdims=True)
+    a = rng.uniform(-1, 1, 4)
+    b = rng.uniform(-1, 1, 4)
+    if rough > 0:
+        scale = rough / (np.abs(a).sum() + np.abs(b).sum())
+        a, b = a * scale, b * scale
+    else:
+        a, b = np.zeros(4), np.zeros(4)
+    return dict(c0=[float(c) for c in c0], v=[float(c) for c in v], R0=float(R0), a=list(a), d=d.tolist(),
+                b=list(b), e=e.tolist(), m=[float(c) for c in m])

@@ -61,6 +61,12 @@ def _status(vb, **kw):
     return st, msg, ctx
 
 
+_QIN = [1.0, 3.0, 0.0, 0.0, 10.0, 0.3, 0.1, 0.0]
+_BODY_OK = dict(c0=[4, 4, 4], v=[0, 0, 0], R0=2.0, a=[0] * 4, d=[[1, 0, 0]] * 4, b=[0] * 4, e=[[1, 0, 0]] * 4,
+                m=[0, 0, 0])
+_BODY_NEG = dict(_BODY_OK, R0=-1.0)
+
+
 @pytest.mark.parametrize("kw,needle", [
     (dict(tau=0.5), "tau"),
     (dict(tau=float("nan")), "tau"),
@@ -73,6 +79,15 @@ def _status(vb, **kw):
     (dict(divb_mode=1), "divb_mode"),
     (dict(block_x=100), "block_x"),
     (dict(shape=(2048, 2048, 1024), lattice="D3Q7"), "2^31"),
+    (dict(lattice="D3Q7", shape=(8, 8, 8), bc=(1, 0, 0, 0, 0, 0), inflow_Q=_QIN), "neither"),
+    (dict(lattice="D3Q7", shape=(8, 8, 8), bc=(3, 3, 0, 0, 0, 0), inflow_Q=_QIN), "vlbm_bc"),
+    (dict(bc=(1, 2, 0, 0, 0, 0), inflow_Q=_QIN), "D3Q7 ideal"),
+    (dict(lattice="D3Q7", shape=(8, 8, 8), model="resistive", dt=0.1, bc=(1, 2, 0, 0, 0, 0), inflow_Q=_QIN),
+     "D3Q7 ideal"),
+    (dict(lattice="D3Q7", shape=(2, 8, 8), bc=(1, 2, 0, 0, 0, 0), inflow_Q=_QIN), ">= 3"),
+    (dict(lattice="D3Q7", shape=(8, 8, 8), bc=(1, 2, 0, 0, 0, 0), inflow_Q=[0.0] * 8), "density"),
+    (dict(lattice="D3Q7", shape=(8, 8, 8), body=_BODY_NEG), "body_R0"),
+    (dict(body=_BODY_OK), "D3Q7 ideal"),
 ])
 def test_create_rejects_bad_parameters(vb, kw, needle):
     st, msg, ctx = _status(vb, **kw)

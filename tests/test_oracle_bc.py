@@ -19,6 +19,15 @@ Facts used (none re-calls the oracle's boundary code to produce an expected valu
   is 2 w_i times the textbook dipole field (3 (m.r) r - m r^2) / r^5 at the link
   midpoints, summed over the cut links;
 * a smooth body (no roughness) is the set of cell centres strictly inside R0.
+Homogenized body (Sec. 2.4 porosity blending):
+* a uniform flow moving with an unmagnetised body stays exactly uniform;
+* deep inside the body (porosity 0) a uniform state relaxes geometrically,
+  rho u - rho u^B and B - B^B shrinking by (1 - 1/tau) per step, with u^B the body's
+  velocity and B^B the uniform interior field 2 m / R0^3 of a magnetised sphere;
+* one step at tau = 1 without the Powell source: every population is the
+  equilibrium of its source cell's homogenized state, assembled here from the
+  definition (porosity from the radial signed distance, linear transition of one
+  cell; blended u and B; rho and pressure kept).
 """
 import numpy as np
 import pytest
@@ -30,21 +39,7 @@ G53 = 5.0 / 3.0
 
 
 def _smooth_state(shape, seed, amp=0.1):
-    """Smooth random primitive fields (rho, u, p, B) on [nz, ny, nx], non-periodic
-    (plain polynomials and sines of the cell coordinates)."""
-    rng = np.random.default_rng(seed)
-    nz, ny, nx = shape
-    z, y, x = np.meshgrid(np.arange(nz) / nz, np.arange(ny) / ny, np.arange(nx) / nx, indexing="ij")
-
-    def fld():
-        a = rng.uniform(-1, 1, 6)
-        return (a[0] * np.sin(2.1 * x + a[1]) + a[2] * np.cos(1.7 * y + a[3]) + a[4] * np.sin(2.3 * z + a[5]))
-
-    rho = 1.0 + amp * fld()
-    u = amp * np.stack([fld(), fld(), fld()])
-    p = 0.6 + amp * fld()
-    B = 0.3 + amp * np.stack([fld(), fld(), fld()])
-    return synth.conserved_from_primitive(rho, u, p, B, G53)
+    return synth.smooth_box_state(shape, seed, amp)
 
 
 def _cell_Q(p, f):
@@ -53,19 +48,7 @@ def _cell_Q(p, f):
 
 
 def _body(c0, v, R0, m=(0.0, 0.0, 0.0), rough=0.0, seed=1):
-    rng = np.random.default_rng(seed)
-    d = rng.standard_normal((4, 3))
-    d /= np.linalg.norm(d, axis=1, keepdims=True)
-    e = rng.standard_normal((4, 3))
-    e /= np.linalg.norm(e, axis=1, keepdims=True)
-    a = rng.uniform(-1, 1, 4)
-    b = rng.uniform(-1, 1, 4)
-    if rough > 0:
-        scale = rough / (np.abs(a).sum() + np.abs(b).sum())
-        a, b = a * scale, b * scale
-    else:
-        a, b = np.zeros(4), np.zeros(4)
-    return dict(c0=list(c0), v=list(v), R0=float(R0), a=list(a), d=d.tolist(), b=list(b), e=e.tolist(), m=list(m))
+    return synth.rough_body(c0, v, R0, m, rough, seed)
 
 
 # ----------------------------------------------------------------------------
@@ -163,14 +146,15 @@ def chk_static_body_rest(nsteps=20, rough=0.15):
     return float(np.abs(Qe - Q)[:, fluid].max())
 
 
-def chk_comoving_uniform(nsteps=12):
+def chk_comoving_uniform(nsteps=20):
     shape = (16, 18, 14)
-    v = (0.35, 0.25, -0.15)
+    s = 0.15
+    v = (0.06, 0.04, -0.025)  # cells per step; the fluid velocity v / s moves with it
     body = _body((6.2, 7.1, 6.8), v, 3.8, rough=0.1, seed=2)
-    p = oracle.make_params(dim=3, shape=shape[::-1], tau=0.8, s=0.15)
+    p = oracle.make_params(dim=3, shape=shape[::-1], tau=0.8, s=s)
     oracle.set_boundaries(p, bc=(0,) * 6, inflow_Q=synth.uniform_state((1, 1, 1), rho=2.0, p=1.0)[:, 0, 0, 0],
                           body=body)
-    Q = synth.uniform_state(shape, rho=1.0, u=v, p=0.6)
+    Q = synth.uniform_state(shape, rho=1.0, u=tuple(c / s for c in v), p=0.6)
     f = oracle.init(p, Q)
     oracle.run_bc(p, f, nsteps)
     s0, s1 = oracle.solid_mask(p, 0), oracle.solid_mask(p, nsteps)
@@ -239,6 +223,94 @@ def chk_smooth_body_geometry():
     return int((oracle.solid_mask(p, t) != want).sum())
 
 
+def chk_hlbm_comoving_uniform(nsteps=15):
+    shape = (14, 12, 13)
+    s = 0.12
+    v = (0.05, -0.03, 0.02)
+    body = _body((6.1, 5.8, 6.4), v, 3.3, rough=0.1, seed=8)
+    p = oracle.make_params(dim=3, shape=shape[::-1], tau=0.7, s=s)
+    oracle.set_boundaries(p, bc=(0,) * 6, inflow_Q=np.zeros(8), body=body, body_mode=2)
+    Q = synth.uniform_state(shape, rho=1.0, u=tuple(c / s for c in v), p=0.6)
+    f = oracle.init(p, Q)
+    oracle.run_bc(p, f, nsteps)
+    return float(np.abs(_cell_Q(p, f) - Q).max())
+
+
+def chk_hlbm_interior_relaxation(nsteps=5, tau=0.8):
+    shape = (5, 6, 4)
+    s = 0.1
+    v = np.array([0.02, -0.01, 0.015])
+    m = np.array([300.0, -200.0, 500.0])
+    R0 = 60.0
+    body = _body((2.0, 3.0, 2.5), v, R0, m=m)
+    p = oracle.make_params(dim=3, shape=shape[::-1], tau=tau, s=s)
+    oracle.set_boundaries(p, bc=(0,) * 6, inflow_Q=np.zeros(8), body=body, body_mode=2)
+    u0, B0 = np.array([0.3, 0.1, -0.2]), np.array([0.2, -0.1, 0.3])
+    Q = synth.uniform_state(shape, rho=1.3, u=tuple(u0), p=0.7, B=tuple(B0))
+    f = oracle.init(p, Q)
+    oracle.run_bc(p, f, nsteps)
+    Qe = _cell_Q(p, f).reshape(8, -1)
+    g = (1.0 - 1.0 / tau) ** nsteps
+    mb, Bb = 1.3 * v / s, 2.0 * m / R0 ** 3
+    want_m = mb + g * (1.3 * u0 - mb)
+    want_B = Bb + g * (B0 - Bb)
+    return float(max(np.abs(Qe[1:4] - want_m[:, None]).max(), np.abs(Qe[5:8] - want_B[:, None]).max(),
+                     np.abs(Qe[0] - 1.3).max()))
+
+
+def _hlbm_state(Q, body, s, gamma, t):
+    """Homogenized state of every cell, from the definition (numpy)."""
+    nz, ny, nx = Q.shape[1:]
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    c = np.array(body["c0"]) + t * np.array(body["v"])
+    r = np.stack([x - c[0], y - c[1], z - c[2]]).astype(np.float64)
+    rr = np.sqrt((r * r).sum(0))
+    n = r / np.where(rr > 0, rr, 1.0)
+    dd, ee = np.array(body["d"]), np.array(body["e"])
+    delta = sum(body["a"][j] * np.tensordot(dd[j], n, 1) + body["b"][j] * (np.tensordot(ee[j], n, 1) ** 2 - 1 / 3)
+                for j in range(4))
+    phi = rr - body["R0"] * (1.0 + delta)
+    d = np.clip(phi + 0.5, 0.0, 1.0)
+    m = np.array(body["m"])[:, None, None, None]
+    r2 = rr ** 2
+    Bdip = (3.0 * (m * r).sum(0) * r - m * r2) / np.where(r2 > 0, r2, 1.0) ** 2.5
+    Bb = np.where(rr < body["R0"], 2.0 * m / body["R0"] ** 3, Bdip)
+    ub = (np.array(body["v"]) / s)[:, None, None, None]
+    rho = Q[0]
+    u = Q[1:4] / rho
+    B = Q[5:8]
+    pres = (gamma - 1.0) * (Q[4] - 0.5 * rho * (u * u).sum(0) - 0.5 * (B * B).sum(0))
+    uh = d * u + (1.0 - d) * ub
+    Bh = d * B + (1.0 - d) * Bb
+    out = Q.copy()
+    out[1:4] = rho * uh
+    out[5:8] = Bh
+    out[4] = pres / (gamma - 1.0) + 0.5 * rho * (uh * uh).sum(0) + 0.5 * (Bh * Bh).sum(0)
+    return np.where(d[None] < 1.0, out, Q), d
+
+
+def chk_hlbm_one_step_definition():
+    shape = (9, 10, 12)
+    s = 0.15
+    body = _body((5.7, 4.6, 4.2), (0.04, 0.02, -0.03), 3.1, m=(2.0, -1.0, 1.5), rough=0.15, seed=9)
+    Q = _smooth_state(shape, 13)
+    p = oracle.make_params(dim=3, shape=shape[::-1], tau=1.0, s=s, powell=0)
+    oracle.set_boundaries(p, bc=(0,) * 6, inflow_Q=np.zeros(8), body=body, body_mode=2)
+    f = oracle.init(p, Q)
+    oracle.run_bc(p, f, 1)
+    Qh, d = _hlbm_state(Q, body, s, G53, 0.0)
+    assert (d == 0).sum() > 20 and ((d > 0) & (d < 1)).sum() > 20
+    nz, ny, nx = shape
+    N = nx * ny * nz
+    flat = Qh.reshape(8, N)
+    feq = np.stack([oracle.equilibrium(p, flat[:, c]) for c in range(N)], axis=-1).reshape(8, 7, nz, ny, nx)
+    want = feq[:, 0].copy()
+    for i in range(1, 7):
+        a, sgn = (i - 1) // 2, (1 if i % 2 == 1 else -1)
+        want += np.roll(feq[:, i], sgn, axis=3 - a)
+    return float(np.abs(_cell_Q(p, f) - want).max() / np.abs(want).max())
+
+
 # ----------------------------------------------------------------------------
 # tests
 # ----------------------------------------------------------------------------
@@ -273,6 +345,18 @@ def test_wall_field_is_the_dipole_at_link_midpoints():
     assert chk_dipole_wall_field() < 1e-13
 
 
+def test_hlbm_flow_moving_with_the_body_stays_uniform():
+    assert chk_hlbm_comoving_uniform() < 1e-14
+
+
+def test_hlbm_interior_relaxes_to_body_velocity_and_field():
+    assert chk_hlbm_interior_relaxation() < 1e-13
+
+
+def test_hlbm_one_step_follows_the_definition():
+    assert chk_hlbm_one_step_definition() < 1e-14
+
+
 def test_smooth_body_is_a_sphere():
     assert chk_smooth_body_geometry() == 0
 
@@ -280,6 +364,7 @@ def test_smooth_body_is_a_sphere():
 # planted mistakes in the boundary code: each must make a check fail
 MUTATIONS = {
     "bb_momentum_sign": ("out = -v + 2.0 * wi * rho * uw[k - 1];", "out = v + 2.0 * wi * rho * uw[k - 1];"),
+    "bb_wall_velocity_units": ("p->body_v[1] / p->s, p->body_v[2] / p->s};", "p->body_v[1], p->body_v[2]};"),
     "bb_rho_wall_flux_dropped": ("out = v - 2.0 * wi * ephi_rho / c2;", "out = v;"),
     "bb_energy_wall_flux_dropped": ("out = v - 2.0 * wi * ephi_E / c2;", "out = v;"),
     "bb_field_weight": ("out = -v + 2.0 * wi * Bw[k - 5];", "out = -v + wi * Bw[k - 5];"),
@@ -289,6 +374,13 @@ MUTATIONS = {
     "face_inflow_edges": ("if (p->bc[2 * a] == 1) *inflow = 1;", ";"),
     "refill_uses_uncovered": ("if (solid[nb] || solid_next[nb]) continue;", "if (solid_next[nb]) continue;"),
     "solid_roughness_sign": ("delta += p->body_a[j] * dn", "delta -= p->body_a[j] * dn"),
+    "hlbm_porosity_offset": ("return phi / eps + 0.5;", "return phi / eps;"),
+    "hlbm_blend_swapped": ("const double uh = d * u[a] + (1.0 - d) * p->body_v[a] / p->s;",
+                           "const double uh = (1.0 - d) * u[a] + d * p->body_v[a] / p->s;"),
+    "hlbm_velocity_units": ("(1.0 - d) * p->body_v[a] / p->s;", "(1.0 - d) * p->body_v[a];"),
+    "hlbm_inner_field": ("B[a] = 2.0 * p->body_m[a] / (R0 * R0 * R0);", "B[a] = p->body_m[a] / (R0 * R0 * R0);"),
+    "hlbm_energy_kept": ("Q[4] = pres / gm1 + 0.5 * rho * uh2 + 0.5 * Bh2;", "(void)uh2; (void)Bh2;"),
+    "hlbm_field_blend": ("const double Bh = d * Q[5 + a] + (1.0 - d) * Bb[a];", "const double Bh = Q[5 + a];"),
 }
 
 
@@ -301,6 +393,9 @@ def _fails(name):
         lambda: chk_comoving_uniform() > 1e-13,
         lambda: chk_static_body_conservation() > 1e-13,
         lambda: chk_dipole_wall_field() > 1e-13,
+        lambda: chk_hlbm_comoving_uniform() > 1e-14,
+        lambda: chk_hlbm_interior_relaxation() > 1e-13,
+        lambda: chk_hlbm_one_step_definition() > 1e-14,
     ]
     if name == "solid_roughness_sign":
         # the roughness enters only the solid test; compare with an independent
