@@ -35,13 +35,16 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+SWEEP_SOURCES = ("vlbm_kernels.h", "vlbm_kernels.hip", "vlbm_physics.h")
+
+
 def kernel_source_hash():
+    """Hash of the sources the sweep kernel is built from."""
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".h")):
-            with open(os.path.join(CSRC, name), "rb") as fh:
-                h.update(name.encode())
-                h.update(fh.read())
+    for name in SWEEP_SOURCES:
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 

@@ -62,10 +62,12 @@ typedef enum { VLBM_IDEAL = 0, VLBM_RESISTIVE = 1 } vlbm_model; /* K = 8 or 26 *
 typedef enum { VLBM_F64 = 0, VLBM_F32 = 1, VLBM_F16DEV = 2, VLBM_BF16DEV = 3 } vlbm_storage;
 
 /* Boundary kind per domain face (x-, x+, y-, y+, z-, z+).  PERIODIC wraps; the
- * equilibrium boundaries of Sec. 2.4 (static boundaries) assign f := f^eq of a
- * Dirichlet state (INFLOW_EQ, the inflow_Q state) or of the state copied from the
- * next cell inward along the face normal (ZERO_GRAD).  Non-periodic faces are
- * accepted only by the D3Q7 ideal model. */
+ * equilibrium boundaries of Sec. 2.4 (static boundaries): at the start of every step
+ * each node of a non-periodic face takes f := f^eq of its boundary state -- the
+ * Dirichlet state inflow_Q if it lies on an INFLOW_EQ face, else (ZERO_GRAD) the
+ * moments of the nearest interior cell along the face normals -- and then collides
+ * and streams like any node.  Both faces of an axis are periodic or neither is; a
+ * non-periodic axis needs at least 3 cells.  Accepted by the D3Q7 ideal model only. */
 typedef enum { VLBM_BC_PERIODIC = 0, VLBM_BC_INFLOW_EQ = 1, VLBM_BC_ZERO_GRAD = 2 } vlbm_bc;
 
 #define VLBM_KMAX 26
@@ -102,7 +104,30 @@ typedef struct {
   size_t pop_bytes;       /* its size in bytes (>= vlbm_population_bytes()) */
   void* stream;           /* hipStream_t for all work; NULL: the null stream */
   int32_t block_x;        /* threads per block along x for the sweep; 0: default */
-  int32_t reserved;
+  int32_t body;           /* moving rough sphere with a dipole field (D3Q7 ideal):
+                             0 none, 1 bounce-back, 2 homogenized (Sec. 2.4) */
+  /* Body (an extension; the paper's moving bodies are homogenised, Sec. 2.4): centre
+   * c(t) = body_c0 + t body_v (cell units, t in steps); solid where the distance of a
+   * cell centre to c(t) is below R0 (1 + sum_j a_j (d_j . n) + sum_j b_j ((e_j . n)^2
+   * - 1/3)), n the unit direction; dipole moment body_m at the centre, field
+   * (3 (m . r) r - m |r|^2) / |r|^5.  A link from a fluid cell into the body bounces
+   * back: rho and e_tot halfway with the moving-wall flux correction
+   * -2 w_i c_i . s Phi(u_w) / c_s^2, rho u and B anti-bounce-back -f* + 2 w_i Q_w to
+   * rho u_w and the dipole field at the link midpoint, u_w = body_v / flux_scale (the
+   * velocity that moves body_v cells per step); cells the body uncovers take f^eq of
+   * the mean moments of their neighbours that are fluid before and after the move
+   * (inflow_Q if there is none).  Solid cells report zero moments.
+   * body = 2, the paper's homogenized LBM (Sec. 2.4): every cell collides toward
+   * its homogenized state -- porosity d = clamp(phi + 1/2, 0, 1) from the radial
+   * signed distance phi = |r| - R(n) (a transition one cell wide), u^ = d u +
+   * (1 - d) u_w and B^ = d B + (1 - d) B_b replace u and B in the equilibrium, the
+   * flux and the Powell source, rho and the pressure are kept (e_tot follows);
+   * B_b is the dipole field outside R0 and the uniform 2 m / R0^3 inside (a
+   * uniformly magnetised sphere).  No mask, no refill; all cells report moments.
+   * The body must stay clear of the domain faces (it does not wrap). */
+  double body_c0[3], body_v[3], body_R0;
+  double body_a[4], body_d[4][3], body_b[4], body_e[4][3];
+  double body_m[3];
 } vlbm_params;
 
 /* Fill *p with defaults (periodic, F32, gamma 5/3, s 0.2, tau 0.6, Powell on). */

@@ -2,6 +2,7 @@
 // and buffer ownership, codec set-up, and stream-ordered launches of the kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -98,9 +99,34 @@ vlbm_status validate(const vlbm_params* p) {
       return fail(nullptr, VLBM_ERR_ARG, "resistive model needs dt, tau_M, tau_H > 0");
     if (!(p->mu >= 0.0) || !(p->eta0 >= 0.0)) return fail(nullptr, VLBM_ERR_ARG, "mu, eta0 must be >= 0");
   }
-  for (int f = 0; f < 6; ++f)
-    if (p->bc[f] != VLBM_BC_PERIODIC)
-      return fail(nullptr, VLBM_ERR_ARG, "face %d: only periodic boundaries are handled by this sweep", f);
+  bool faces = false;
+  const int32_t ext[3] = {p->nx, p->ny, p->nz};
+  for (int f = 0; f < 6; ++f) {
+    if (p->bc[f] < VLBM_BC_PERIODIC || p->bc[f] > VLBM_BC_ZERO_GRAD)
+      return fail(nullptr, VLBM_ERR_ARG, "bc[%d] = %d is not a vlbm_bc", f, p->bc[f]);
+    if ((p->bc[f] == VLBM_BC_PERIODIC) != (p->bc[f ^ 1] == VLBM_BC_PERIODIC))
+      return fail(nullptr, VLBM_ERR_ARG, "faces %d and %d: both periodic or neither", f & ~1, f | 1);
+    if (p->bc[f] != VLBM_BC_PERIODIC) {
+      faces = true;
+      if (ext[f >> 1] < 3) return fail(nullptr, VLBM_ERR_ARG, "non-periodic axis %d needs >= 3 cells", f >> 1);
+    }
+  }
+  if (p->body < 0 || p->body > 2) return fail(nullptr, VLBM_ERR_ARG, "body must be 0, 1 or 2");
+  if ((faces || p->body) && (p->lattice != VLBM_D3Q7 || p->model != VLBM_IDEAL))
+    return fail(nullptr, VLBM_ERR_ARG, "non-periodic faces and the body need the D3Q7 ideal model");
+  if (faces || p->body)
+    for (int k = 0; k < 8; ++k)
+      if (!std::isfinite(p->inflow_Q[k])) return fail(nullptr, VLBM_ERR_ARG, "inflow_Q[%d] not finite", k);
+  if (faces && !(p->inflow_Q[0] > 0.0)) return fail(nullptr, VLBM_ERR_ARG, "inflow_Q[0] (density) must be > 0");
+  if (p->body) {
+    if (!(p->body_R0 > 0.0) || !std::isfinite(p->body_R0)) return fail(nullptr, VLBM_ERR_ARG, "body_R0 must be > 0");
+    const double* vals[] = {p->body_c0, p->body_v, p->body_a, &p->body_d[0][0], p->body_b, &p->body_e[0][0],
+                            p->body_m};
+    const int cnt[] = {3, 3, 4, 12, 4, 12, 3};
+    for (int j = 0; j < 7; ++j)
+      for (int q = 0; q < cnt[j]; ++q)
+        if (!std::isfinite(vals[j][q])) return fail(nullptr, VLBM_ERR_ARG, "body parameters must be finite");
+  }
   if (p->block_x != 0 && (p->block_x < 64 || p->block_x > 256 || p->block_x % 64 != 0))
     return fail(nullptr, VLBM_ERR_ARG, "block_x must be 64, 128, 192 or 256");
   if (p->rest_Q)
@@ -121,6 +147,33 @@ double pow2_at_least(double v) {
 }
 
 // FP16/BF16 codec table: f_rest = f^eq(Q_rest), scale w_i sigma_k.
+// Cells whose mask can change when the body moves from time t0 to t1 (t0 <= t1):
+// the bounding box of both positions, widened by the surface-radius bound and two
+// cells (the link bits of the neighbours), clipped to the domain.
+void body_box(vlbm_ctx* c, double t0, double t1, int (&box)[6]) {
+  const int n[3] = {c->p.nx, c->p.ny, c->p.nz};
+  for (int a = 0; a < 3; ++a) {
+    const double p0 = c->body.c0[a] + t0 * c->body.v[a], p1 = c->body.c0[a] + t1 * c->body.v[a];
+    const double lo = std::floor(std::min(p0, p1) - c->body_rmax) - 2.0;
+    const double hi = std::ceil(std::max(p0, p1) + c->body_rmax) + 3.0;
+    box[2 * a] = (int)std::max(0.0, std::min((double)n[a], lo));
+    box[2 * a + 1] = (int)std::max(0.0, std::min((double)n[a], hi));
+  }
+}
+
+// Mask of the whole lattice at the current step (after init or a restore).
+hipError_t body_mask_full(vlbm_ctx* c) {
+  Body b = c->body;
+  b.t = (double)c->step;
+  b.box[0] = b.box[2] = b.box[4] = 0;
+  b.box[1] = c->p.nx;
+  b.box[3] = c->p.ny;
+  b.box[5] = c->p.nz;
+  hipError_t e = launch_mask(c->L, c->g, b, 0, 1);
+  if (e == hipSuccess) e = launch_mask(c->L, c->g, b, 1, 0);
+  return e;
+}
+
 void build_codec(vlbm_ctx* c) {
   std::memset(&c->cd, 0, sizeof c->cd);
   if (c->p.storage != VLBM_F16DEV && c->p.storage != VLBM_BF16DEV) return;
@@ -259,7 +312,44 @@ vlbm_status vlbm_create(const vlbm_params* p, vlbm_ctx** out) {
   c->g.nx = p->nx;
   c->g.ny = p->ny;
   c->g.nz = p->nz;
-  for (int f = 0; f < 6; ++f) c->g.bc[f] = p->bc[f];
+  for (int f = 0; f < 6; ++f) {
+    c->g.bc[f] = p->bc[f];
+    c->has_faces |= p->bc[f] != VLBM_BC_PERIODIC;
+  }
+  for (int k = 0; k < 8; ++k) c->inflow.q[k] = p->inflow_Q[k];
+  if (p->body) {
+    Body& b = c->body;
+    double delta = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      b.c0[a] = p->body_c0[a];
+      b.v[a] = p->body_v[a];
+      b.m[a] = p->body_m[a];
+    }
+    b.R0 = p->body_R0;
+    for (int j = 0; j < 4; ++j) {
+      b.a[j] = p->body_a[j];
+      b.b[j] = p->body_b[j];
+      double dd = 0.0, ee = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        b.d[j][a] = p->body_d[j][a];
+        b.e[j][a] = p->body_e[j][a];
+        dd += b.d[j][a] * b.d[j][a];
+        ee += b.e[j][a] * b.e[j][a];
+      }
+      // |d_j . n| <= |d_j|, |(e_j . n)^2 - 1/3| <= |e_j|^2 + 1/3
+      delta += std::fabs(b.a[j]) * std::sqrt(dd) + std::fabs(b.b[j]) * (ee + 1.0 / 3.0);
+    }
+    c->body_rmax = b.R0 * (1.0 + delta);
+    b.rmax = c->body_rmax;
+    if (p->body == 1) {  // bounce-back keeps a solid/link mask
+      if (hipMalloc(&c->d_mask, (size_t)c->N) != hipSuccess ||
+          hipMemsetAsync(c->d_mask, 0, (size_t)c->N, c->stream) != hipSuccess) {
+        vlbm_destroy(c);
+        return fail(nullptr, VLBM_ERR_OOM, "allocation of the body mask failed");
+      }
+      c->g.mask = c->d_mask;
+    }
+  }
   c->L.storage = p->storage;
   c->L.dim = c->D;
   c->L.model = p->model;
@@ -318,6 +408,10 @@ vlbm_status vlbm_init_fields(vlbm_ctx* c, const void* Q, int q_on_device, int q_
     if (e == hipSuccess) build_codec(c);
   }
   if (e == hipSuccess) e = launch_init(c->L, c->g, c->ph, c->cd, dQ, q_is_f32);
+  if (e == hipSuccess && c->p.body == 1) {
+    c->step = 0;
+    e = body_mask_full(c);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (tmp) (void)hipFree(tmp);
   if (e != hipSuccess) st = hip_fail(c, e, "init_fields");
@@ -333,9 +427,30 @@ vlbm_status vlbm_step(vlbm_ctx* c, int32_t n) {
   if (n < 0) return fail(c, VLBM_ERR_ARG, "n = %d < 0", n);
   if (!c->initialized) return fail(c, VLBM_ERR_STATE, "vlbm_step before vlbm_init_fields");
   for (int32_t j = 0; j < n; ++j) {
-    const hipError_t e = launch_sweep(c->L, c->g, c->ph, c->cd, (int)(c->step & 1));
+    const int par = (int)(c->step & 1);
+    if (c->has_faces) {
+      const hipError_t e = launch_faces(c->L, c->g, c->ph, c->cd, par, c->inflow);
+      if (e != hipSuccess) return hip_fail(c, e, "face launch");
+    }
+    if (!c->p.body) {
+      const hipError_t e = launch_sweep(c->L, c->g, c->ph, c->cd, par);
+      if (e != hipSuccess) return hip_fail(c, e, "sweep launch");
+      ++c->step;
+      continue;
+    }
+    Body b = c->body;
+    b.t = (double)c->step;
+    hipError_t e = launch_sweep_body(c->L, c->g, c->ph, c->cd, par, b, c->p.body);
     if (e != hipSuccess) return hip_fail(c, e, "sweep launch");
     ++c->step;
+    if (c->p.body == 2) continue;  // the homogenized body needs no mask
+    // the body moves to its position at the new step; uncovered cells are refilled
+    body_box(c, b.t, (double)c->step, b.box);
+    b.t = (double)c->step;
+    e = launch_mask(c->L, c->g, b, 0, 0);
+    if (e == hipSuccess) e = launch_mask(c->L, c->g, b, 1, 0);
+    if (e == hipSuccess) e = launch_refill(c->L, c->g, c->ph, c->cd, (int)(c->step & 1), b, c->inflow);
+    if (e != hipSuccess) return hip_fail(c, e, "body update");
   }
   return VLBM_OK;
 }
@@ -424,8 +539,9 @@ vlbm_status vlbm_set_populations(vlbm_ctx* c, const void* src, size_t bytes, int
     return fail(c, VLBM_ERR_STATE, "FP16/BF16 restore needs rest_Q and scale in the params (or a prior init)");
   if (!c->initialized) build_codec(c);
   VLBM_HIP(c, hipMemcpyAsync(c->f, src, bytes, hipMemcpyHostToDevice, c->stream));
-  VLBM_HIP(c, hipStreamSynchronize(c->stream));
   c->step = step;
+  if (c->p.body == 1) VLBM_HIP(c, body_mask_full(c));
+  VLBM_HIP(c, hipStreamSynchronize(c->stream));
   c->initialized = true;
   return VLBM_OK;
 }
@@ -452,6 +568,7 @@ void vlbm_destroy(vlbm_ctx* c) {
   if (c->d_partial2) (void)hipFree(c->d_partial2);
   if (c->d_totals) (void)hipFree(c->d_totals);
   if (c->d_Q) (void)hipFree(c->d_Q);
+  if (c->d_mask) (void)hipFree(c->d_mask);
   delete c;
 }
 

@@ -29,6 +29,11 @@ struct vlbm_ctx {
   double* d_partial2 = nullptr;  // [nblk]
   double* d_totals = nullptr;    // [K+5] totals, then 2 x KMAX codec scratch
   double* d_Q = nullptr;         // [K][N] moments scratch (lazy)
+  bool has_faces = false;         // some face is not periodic
+  vlbm::Inflow inflow{};
+  vlbm::Body body{};              // geometry; t and box set per launch
+  double body_rmax = 0.0;         // bound of the body's surface radius
+  unsigned char* d_mask = nullptr;  // [N] body mask (body only)
   long long step = 0;
   bool initialized = false;
   std::string err;

@@ -15,7 +15,28 @@ struct Grid {
   void* f;              // population buffer, planes (k*NQ + i) of `stride` elements
   long long stride;     // elements per plane
   int nx, ny, nz;
-  int bc[6];            // per face: 0 periodic (only kind handled by the periodic sweep)
+  int bc[6];            // per face: 0 periodic, 1 inflow, 2 zero gradient
+  unsigned char* mask;  // body mask per cell (NULL: no body), bits below
+};
+
+// Body mask bits: solid now, solid before the last move, and for i = 1..6 the
+// neighbour x + e_i is solid now (the link i is cut).
+constexpr unsigned kSolid = 0x80u, kWasSolid = 0x01u;
+__host__ __device__ constexpr unsigned link_bit(int i) { return 1u << i; }
+
+// Moving rough sphere with a dipole field (absolute cell coordinates, time in steps).
+struct Body {
+  double c0[3], v[3], R0;
+  double a[4], d[4][3], b[4], e[4][3];
+  double m[3];
+  double rmax;  // bound of the surface radius (cells)
+  double t;     // time of the state the kernel works on
+  int box[6];   // [x0, x1) x [y0, y1) x [z0, z1): the cells whose mask can change
+};
+
+// Boundary state of inflow faces (the first 8 conserved variables).
+struct Inflow {
+  double q[8];
 };
 
 // FP16/BF16 deviation codec: f = rest[k*NQ+i] + sc[k*NQ+i] * h,
@@ -36,10 +57,25 @@ struct Launch {
 // out; 1: swapped in, natural out).
 hipError_t launch_sweep(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity);
 
-// Sweep of a 2D ideal-MHD lattice (FP32 or FP64 storage) that first adds
-// *flag * w_i dq[k][c] to the gathered populations (dq FP32 [K][N], device).
-hipError_t launch_sweep_inj(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
-                            const float* dq, const int* flag);
+// Static faces (D3Q7 ideal model): every node of a non-periodic face takes
+// f := f^eq(Q_bc) at the given parity, Q_bc the inflow state on inflow faces, else
+// the moments of the nearest cell that lies on no non-periodic face.
+hipError_t launch_faces(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
+                        const Inflow& in);
+
+// Body mask in b.box at time b.t: pass 0 sets the solid bit (and keeps the old one
+// as kWasSolid unless `fresh`), pass 1 the link bits.
+hipError_t launch_mask(const Launch& L, const Grid& g, const Body& b, int pass, int fresh);
+// Cells of b.box uncovered by the last move take f^eq of the mean moments of their
+// neighbours that are fluid before and after it (the inflow state if none), at the
+// given parity.
+hipError_t launch_refill(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
+                         const Body& b, const Inflow& in);
+// Sweep of a D3Q7 ideal lattice with a body at time b.t.  mode 1: solid cells are
+// skipped and links into the body bounce back (moving wall, dipole field); mode 2:
+// every cell collides toward its homogenized state (porosity blending).
+hipError_t launch_sweep_body(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
+                             const Body& b, int mode);
 
 // f := f^eq(Q) in natural layout.  Q is device SoA [K][N], FP64 or FP32.
 hipError_t launch_init(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd,

@@ -39,7 +39,7 @@ struct Phys {
 // unphysical (rho <= 0, p < 0, or a non-finite value).
 template <typename R, int D, int MODEL>
 __host__ __device__ inline bool flux_source(const R* Q, const R* Jb, const Phys& ph,
-                                            R (*P)[3], R* S, R& dlat) {
+                                            R (*P)[3], R* S, R& dlat, R* pt_out = nullptr) {
   constexpr int K = MODEL ? 26 : 8;
   const R rho = Q[0];
   const R ir = R(1) / rho;
@@ -57,6 +57,7 @@ __host__ __device__ inline bool flux_source(const R* Q, const R* Jb, const Phys&
   const R m[3] = {m0, m1, m2};
   const R B[3] = {b0, b1, b2};
   const R Ept = E + pt;
+  if (pt_out) *pt_out = pt;
 
   // physical fluxes along the lattice axes a (Sec. 2.3, ideal MHD)
 #pragma unroll
@@ -172,17 +173,24 @@ __host__ __device__ inline R feq_dir(R Qk, const R* Pk, int i, R w0, R wi) {
   return (i & 1) ? wi * (Qk + Pk[a]) : wi * (Qk - Pk[a]);
 }
 
-// BGK + direct injection, in place: f_{k,i} += omega_k (f^eq_{k,i} - f_{k,i}) + w_i S_k.
-// Returns the unphysical flag and writes the div B estimate.
-template <typename R, int D, int MODEL>
-__device__ __forceinline__ bool collide(R (*f)[2 * D + 1], const Phys& ph, R& dlat) {
-  constexpr int NQ = 2 * D + 1;
+// Target of the collision: the state whose equilibrium, flux and source the
+// populations relax toward.  NoTarget keeps the cell's own moments.
+struct NoTarget {
+  template <typename R>
+  __device__ __forceinline__ void operator()(R*) const {}
+};
+
+// BGK + direct injection, in place: f_{k,i} += omega_k (f^eq_{k,i}(Q') - f_{k,i}) + w_i S_k(Q'),
+// Q' the moments Q after tgt.  Returns the unphysical flag and writes the div B
+// estimate, the pre-collision moments Q and the total pressure pt of Q'.
+template <typename R, int D, int MODEL, typename Tgt = NoTarget>
+__device__ __forceinline__ bool collide(R (*f)[2 * D + 1], const Phys& ph, R& dlat,
+                                        R (&Q)[MODEL ? 26 : 8], R& pt, const Tgt& tgt = Tgt{}) {
   constexpr int K = MODEL ? 26 : 8;
   // Zeroth moments, opposite directions paired first: f_{+a} + f_{-a} cancels the
   // flux part c_a . Phi / c_s^2 the two carry with opposite signs before it is
   // accumulated, which keeps small variables (G, H, a momentum at rest) accurate
   // in FP32.
-  R Q[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     R acc = f[k][0];
@@ -193,25 +201,36 @@ __device__ __forceinline__ bool collide(R (*f)[2 * D + 1], const Phys& ph, R& dl
   R Jb[3] = {R(0), R(0), R(0)};
 #pragma unroll
   for (int a = 0; a < D; ++a) Jb[a] = f[5 + a][2 * a + 1] - f[5 + a][2 * a + 2];
+  R Qt[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) Qt[k] = Q[k];
+  tgt(Qt);
   R P[K][3];
   R S[K];
-  const bool bad = flux_source<R, D, MODEL>(Q, Jb, ph, P, S, dlat);
+  const bool bad = flux_source<R, D, MODEL>(Qt, Jb, ph, P, S, dlat, &pt);
   const R wi = R(ph.wi);
   const R w0 = rest_weight<R, D>(wi);
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const R om = R(ph.omega[k]);
     const R sw0 = w0 * S[k], swi = wi * S[k];
-    f[k][0] += om * (w0 * Q[k] - f[k][0]) + sw0;
+    f[k][0] += om * (w0 * Qt[k] - f[k][0]) + sw0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      const R ep = wi * (Q[k] + P[k][a]);
-      const R em = wi * (Q[k] - P[k][a]);
+      const R ep = wi * (Qt[k] + P[k][a]);
+      const R em = wi * (Qt[k] - P[k][a]);
       f[k][2 * a + 1] += om * (ep - f[k][2 * a + 1]) + swi;
       f[k][2 * a + 2] += om * (em - f[k][2 * a + 2]) + swi;
     }
   }
   return bad;
+}
+
+template <typename R, int D, int MODEL>
+__device__ __forceinline__ bool collide(R (*f)[2 * D + 1], const Phys& ph, R& dlat) {
+  R Q[MODEL ? 26 : 8];
+  R pt;
+  return collide<R, D, MODEL>(f, ph, dlat, Q, pt);
 }
 
 }  // namespace vlbm

@@ -71,6 +71,40 @@ def generate_pairs(seeds, n_fine, r, pairs_per_seed, workload, make_state, kmax=
     return X, Y
 
 
+def rollout_pairs(net, X, m, workload, bound_corr, bound_divb_rel, bound_divb_abs, stride=1, storage="f32",
+                  log=None):
+    """Pairs taken on the corrected run's own states (so that the network also learns to
+    pull a drifted coarse state back toward the restricted fine trajectory): for
+    n = m, m + stride, ...: start a coarse run at X[n - m] (a restricted fine state),
+    take m corrected steps to Xt (its state at t_n, with the drift the run accumulates),
+    and set the target X[n + 1] - C(Xt).  X: [P, 8, B, nc, nc] device tensor of
+    consecutive restricted fine states.  Returns (Xr, Yr) of the same layout."""
+    torch = _torch()
+    s = torch.cuda.current_stream().cuda_stream
+    P, _, B, nc, _ = X.shape
+    a = make_context((nc, nc), B, storage, workload, s)
+    b = make_context((nc, nc), B, storage, workload, s)
+    idx = list(range(m, P - 1, stride))
+    Xr = torch.empty((len(idx), 8, B, nc, nc), dtype=torch.float32, device="cuda")
+    Yr = torch.empty_like(Xr)
+    Cst = torch.empty((8, B, nc, nc), dtype=torch.float32, device="cuda")
+    t0 = time.perf_counter()
+    for j, n in enumerate(idx):
+        a.vlbm_init_fields(X[n - m])
+        N.vlbm_step_corrected(a, net, m, bound_corr, bound_divb_rel, bound_divb_abs)
+        a.vlbm_moments(out=Xr[j])
+        b.vlbm_init_fields(Xr[j])
+        b.vlbm_step(1)
+        b.vlbm_moments(out=Cst)
+        N.vlbm_restrict(X[n + 1], 1, Yr[j], rz=1, minus=Cst, stream=s)  # r = 1: X[n+1] - C(Xt)
+        if log and (j + 1) % 100 == 0:
+            log(f"rollout pairs: {j + 1}/{len(idx)} ({time.perf_counter() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    a.vlbm_destroy()
+    b.vlbm_destroy()
+    return Xr, Yr
+
+
 def _divc_l2(F):
     """L2 norm of the central-difference divergence of the in-plane B of a moment
     batch F [8, B, n, n] (host statistics)."""
@@ -149,37 +183,43 @@ def field_errors(Q, R):
 
 def evaluate(net, seeds, n_fine, r, coarse_steps, workload, make_state, bound_corr, bound_divb_rel, bound_divb_abs,
              kmax=16, checkpoints=5, storage="f32", log=None):
-    """Coarse plain vs coarse learned, both scored against the restricted fine run."""
+    """Coarse plain VLBM, the corrected coarse run and its base operator alone (every
+    step restarted from the equilibrium of its moments, no correction), each scored
+    against the restricted fine run."""
     torch = _torch()
     s = torch.cuda.current_stream().cuda_stream
     B, nc = len(seeds), n_fine // r
     fine = make_context((n_fine, n_fine), B, storage, workload, s)
     plain = make_context((nc, nc), B, storage, workload, s)
     learned = make_context((nc, nc), B, storage, workload, s)
+    base = make_context((nc, nc), B, storage, workload, s)
     fine.vlbm_init_fields(torch.from_numpy(initial_batch(seeds, n_fine, kmax, make_state)).cuda())
     M = torch.empty((8, B, n_fine, n_fine), dtype=torch.float32, device="cuda")
     Rf = torch.empty((8, B, nc, nc), dtype=torch.float32, device="cuda")
     fine.vlbm_moments(out=M)
     N.vlbm_restrict(M, r, Rf, rz=1, stream=s)
-    plain.vlbm_init_fields(Rf)
-    learned.vlbm_init_fields(Rf)
+    for ctx in (plain, learned, base):
+        ctx.vlbm_init_fields(Rf)
     chunk = coarse_steps // checkpoints
     hist, fallbacks = [], 0
+    zero = np.zeros(8)
     for c in range(checkpoints):
         fine.vlbm_step(r * chunk)
         plain.vlbm_step(chunk)
         fallbacks += N.vlbm_step_corrected(learned, net, chunk, bound_corr, bound_divb_rel, bound_divb_abs)
+        N.vlbm_step_corrected(base, net, chunk, zero, 0.0, 0.0)
         fine.vlbm_moments(out=M)
         N.vlbm_restrict(M, r, Rf, rz=1, stream=s)
         ref = Rf.cpu().numpy().astype(np.float64)
-        qp, _ = plain.vlbm_moments(raise_nonfinite=False)
-        ql, _ = learned.vlbm_moments(raise_nonfinite=False)
-        ep = field_errors(qp.reshape(ref.shape), ref)
-        el = field_errors(ql.reshape(ref.shape), ref)
-        hist.append(dict(coarse_step=(c + 1) * chunk, plain=ep, learned=el))
+        err = {}
+        for name, ctx in (("plain", plain), ("learned", learned), ("base", base)):
+            q, _ = ctx.vlbm_moments(raise_nonfinite=False)
+            err[name] = field_errors(q.reshape(ref.shape), ref)
+        hist.append(dict(coarse_step=(c + 1) * chunk, **err))
         if log:
-            log(f"eval step {(c + 1) * chunk}: plain {ep} learned {el} fallbacks {fallbacks}")
-    for ctx in (fine, plain, learned):
+            log(f"eval step {(c + 1) * chunk}: plain {err['plain']} learned {err['learned']} "
+                f"base {err['base']} fallbacks {fallbacks}")
+    for ctx in (fine, plain, learned, base):
         ctx.vlbm_destroy()
     return hist, fallbacks
 

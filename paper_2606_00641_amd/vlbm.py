@@ -61,7 +61,15 @@ class vlbm_params(ctypes.Structure):
         ("pop_bytes", ctypes.c_size_t),
         ("stream", ctypes.c_void_p),
         ("block_x", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("body", ctypes.c_int32),
+        ("body_c0", ctypes.c_double * 3),
+        ("body_v", ctypes.c_double * 3),
+        ("body_R0", ctypes.c_double),
+        ("body_a", ctypes.c_double * 4),
+        ("body_d", (ctypes.c_double * 3) * 4),
+        ("body_b", ctypes.c_double * 4),
+        ("body_e", (ctypes.c_double * 3) * 4),
+        ("body_m", ctypes.c_double * 3),
     ]
 
 
@@ -125,7 +133,7 @@ def _is_torch(x):
 def make_params(lattice="D2Q5", shape=(64, 64, 1), model="ideal", storage="f32", gamma=5.0 / 3.0,
                 flux_scale=0.2, tau=0.6, powell=True, divb_mode=0, dt=0.0, mu=0.0, eta0=0.0,
                 j_c=0.0, tau_M=1.0, tau_H=1.0, w0=0.0, bc=None, inflow_Q=None, scale=None,
-                stream=None, block_x=0):
+                stream=None, block_x=0, body=None):
     p = vlbm_params()
     _check(_lib.vlbm_params_default(ctypes.byref(p)))
     p.lattice = VLBM_D3Q7 if str(lattice).upper() == "D3Q7" else VLBM_D2Q5
@@ -153,6 +161,19 @@ def make_params(lattice="D2Q5", shape=(64, 64, 1), model="ideal", storage="f32",
             p.scale[k] = float(v)
     p.stream = stream
     p.block_x = int(block_x)
+    if body is not None:
+        p.body = int(body.get("mode", 1))
+        for a in range(3):
+            p.body_c0[a] = body["c0"][a]
+            p.body_v[a] = body["v"][a]
+            p.body_m[a] = body["m"][a]
+        p.body_R0 = body["R0"]
+        for j in range(4):
+            p.body_a[j] = body["a"][j]
+            p.body_b[j] = body["b"][j]
+            for a in range(3):
+                p.body_d[j][a] = body["d"][j][a]
+                p.body_e[j][a] = body["e"][j][a]
     return p
 
 

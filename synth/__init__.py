@@ -250,12 +250,13 @@ def inflow_state(mach=3.0, alfven_mach=8.0, angle_deg=30.0, rho=1.0, p=0.6, gamm
     return conserved_from_primitive(rho, u, p, B, gamma), dict(u=u, B=B, rho=rho, p=p)
 
 
-def body_params(shape=(768, 384, 384), seed=4, R0=48.0, speed=0.02, rough=0.05, dipole_ratio=10.0,
-                B_in=0.375):
+def body_params(shape=(768, 384, 384), seed=4, R0=48.0, speed=0.02, rough=0.05, dipole_ratio=2.0,
+                B_in=0.375, mode=2):
     """Seeded rough sphere: centre at (nx/4, 5 ny/12, nz/2) moving along +y at `speed`
     cells per step; surface radius R0 (1 + delta(n)) with delta a seeded sum of
     degree-1 and degree-2 terms, |delta| <= rough; a dipole along a seeded direction
-    whose equatorial surface field is dipole_ratio |B_in|."""
+    whose equatorial surface field is dipole_ratio |B_in|; mode 2 the homogenized
+    body, 1 bounce-back."""
     rng = np.random.default_rng(seed)
     nx, ny, nz = shape
     d = rng.standard_normal((4, 3))
@@ -270,28 +271,31 @@ def body_params(shape=(768, 384, 384), seed=4, R0=48.0, speed=0.02, rough=0.05, 
     md /= np.linalg.norm(md)
     m = md * dipole_ratio * B_in * R0 ** 3
     return dict(c0=[nx / 4.0, 5.0 * ny / 12.0, nz / 2.0], v=[0.0, speed, 0.0], R0=float(R0),
-                a=list(a * scale), d=d.tolist(), b=list(b * scale), e=e.tolist(), m=m.tolist())
+                a=list(a * scale), d=d.tolist(), b=list(b * scale), e=e.tolist(), m=m.tolist(), mode=int(mode))
 
 
 def body_initial_state(shape, body, mach=3.0, alfven_mach=8.0, angle_deg=30.0, rho=1.0, p=0.6,
                        gamma=5.0 / 3.0, dtype=np.float64):
-    """Inflow state everywhere with the body's dipole field superposed on the inflow
-    field (outside a core of radius R0/2 around the centre, where the dipole is
-    singular), e_tot from that field; [8, nz, ny, nx]."""
+    """Inflow state everywhere with the field of a sphere of radius R0 magnetised
+    uniformly with the body's moment m superposed on the inflow field (the dipole
+    field outside R0, the uniform 2 m / R0^3 inside; divergence free), e_tot from
+    that field; [8, nz, ny, nx]."""
     nx, ny, nz = shape
     _, info = inflow_state(mach, alfven_mach, angle_deg, rho, p, gamma)
     z = np.arange(nz, dtype=np.float64)[:, None, None] - body["c0"][2]
     y = np.arange(ny, dtype=np.float64)[None, :, None] - body["c0"][1]
     x = np.arange(nx, dtype=np.float64)[None, None, :] - body["c0"][0]
+    R0 = body["R0"]
     r2 = x * x + y * y + z * z
-    r2 = np.maximum(r2, (0.5 * body["R0"]) ** 2)
+    inside = r2 < R0 * R0
+    r2 = np.maximum(r2, R0 * R0)
     m = body["m"]
     mr = m[0] * x + m[1] * y + m[2] * z
     r5 = r2 * r2 * np.sqrt(r2)
     Q = np.empty((8, nz, ny, nx), dtype)
     Bsq = np.zeros((nz, ny, nx))
     for a, ra in enumerate((x, y, z)):
-        Ba = info["B"][a] + (3.0 * mr * ra - m[a] * r2) / r5
+        Ba = info["B"][a] + np.where(inside, 2.0 * m[a] / R0 ** 3, (3.0 * mr * ra - m[a] * r2) / r5)
         Q[5 + a] = Ba
         Bsq = Bsq + Ba * Ba
     u = info["u"]

@@ -1,0 +1,163 @@
+"""GPU parity of the non-periodic faces (Sec. 2.4 static boundaries) and of the
+moving magnetised body against the oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from fieldcheck import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+BCS = [(1, 2, 2, 2, 2, 2), (2, 1, 1, 2, 0, 0), (0, 0, 2, 2, 1, 2)]
+
+
+@pytest.fixture(scope="module")
+def vb():
+    import torch
+    assert torch.cuda.is_available(), "GPU test on a machine without a GPU"
+    torch.cuda.set_device(0)
+    from paper_2606_00641_amd import vlbm
+    return vlbm
+
+
+def _stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _case(kind, mode=1):
+    """(shape (nx, ny, nz), Q0, inflow_Q, body, tau, s, steps); mode 1 bounce-back,
+    2 homogenized body."""
+    if kind == "faces":
+        shape = (20, 12, 10)
+        Q0 = synth.smooth_box_state(shape[::-1], seed=11)
+        Qin, _ = synth.inflow_state(mach=1.2, alfven_mach=4.0)
+        return shape, Q0, Qin, None, 0.7, 0.15, 30
+    shape = (30, 22, 20)
+    Qin, _ = synth.inflow_state(mach=0.8, alfven_mach=4.0)
+    Q0 = np.broadcast_to(Qin[:, None, None, None], (8,) + shape[::-1]).copy()
+    Q0 += 0.3 * (synth.smooth_box_state(shape[::-1], seed=12, amp=0.05, rho=0.0, p=0.0, B0=0.0))
+    body = synth.rough_body((9.3, 10.1, 9.7), (0.08, 0.04, 0.02), 4.6, m=(3.0, -2.0, 1.5), rough=0.12, seed=5)
+    body["mode"] = mode
+    return shape, Q0, Qin, body, 0.7, 0.1, 40
+
+
+def _run_pair(vb, kind, storage, bc, steps=None, mode=1):
+    shape, Q0, Qin, body, tau, s, n = _case(kind, mode)
+    n = steps or n
+    p = vb.make_params(lattice="D3Q7", shape=shape, model="ideal", storage=storage, flux_scale=s, tau=tau,
+                       bc=bc, inflow_Q=Qin, body=body, stream=_stream())
+    sim = vb.Vlbm(p)
+    sim.vlbm_init_fields(Q0)
+    sim.vlbm_step(n)
+    Qg, tot = sim.vlbm_moments()
+    op = oracle.make_params(dim=3, shape=shape, s=s, tau=tau)
+    oracle.set_boundaries(op, bc=bc, inflow_Q=Qin, body=body, body_mode=mode)
+    f = oracle.init(op, Q0)
+    oracle.run_bc(op, f, n)
+    Qo, _, _ = oracle.moments(op, f)
+    if body and mode == 1:
+        fluid = (oracle.solid_mask(op, n) == 0).reshape(-1)
+    else:
+        fluid = np.ones(np.prod(shape), bool)
+    return np.asarray(Qg).reshape(8, -1), Qo, fluid, tot
+
+
+@pytest.mark.parametrize("bc", BCS)
+def test_faces_fp64_parity(vb, bc):
+    Qg, Qo, fluid, _ = _run_pair(vb, "faces", "f64", bc)
+    err = rel_l2(Qg, Qo, 8)
+    assert max(err.values()) < 1e-10, err
+
+
+def test_faces_fp32_parity(vb):
+    Qg, Qo, fluid, _ = _run_pair(vb, "faces", "f32", BCS[0])
+    err = rel_l2(Qg, Qo, 8)
+    assert max(err.values()) < 1e-5, err
+
+
+@pytest.mark.parametrize("steps", [39, 40])
+def test_body_fp64_parity(vb, steps):
+    """Moving rough magnetised body with an inflow face and zero-gradient faces; the
+    fluid cells match the oracle, the solid ones report zero moments."""
+    Qg, Qo, fluid, tot = _run_pair(vb, "body", "f64", (1, 2, 2, 2, 2, 2), steps=steps)
+    err = rel_l2(Qg[:, fluid], Qo[:, fluid], 8)
+    assert max(err.values()) < 1e-10, err
+    assert np.all(Qg[:, ~fluid] == 0.0)
+    assert (~fluid).sum() > 300
+
+
+def test_body_fp32_parity(vb):
+    Qg, Qo, fluid, _ = _run_pair(vb, "body", "f32", (1, 2, 2, 2, 2, 2))
+    err = rel_l2(Qg[:, fluid], Qo[:, fluid], 8)
+    assert max(err.values()) < 1e-5, err
+
+
+@pytest.mark.parametrize("storage,tol", [("f16", 2e-3), ("bf16", 2e-2)])
+def test_body_low_precision(vb, storage, tol):
+    """FP16/BF16 deviation storage with the body: per-field error against the FP64
+    oracle after 40 steps, within the storage format's resolution."""
+    Qg, Qo, fluid, _ = _run_pair(vb, "body", storage, (1, 2, 2, 2, 2, 2))
+    err = rel_l2(Qg[:, fluid], Qo[:, fluid], 8)
+    print(storage, err)
+    assert max(err.values()) < tol, err
+
+
+@pytest.mark.parametrize("steps", [39, 40])
+def test_homogenized_body_fp64_parity(vb, steps):
+    """The paper's homogenized moving body (porosity blending), inflow and
+    zero-gradient faces: every cell matches the oracle."""
+    Qg, Qo, _, _ = _run_pair(vb, "body", "f64", (1, 2, 2, 2, 2, 2), steps=steps, mode=2)
+    err = rel_l2(Qg, Qo, 8)
+    assert max(err.values()) < 1e-10, err
+
+
+def test_homogenized_body_fp32_parity(vb):
+    Qg, Qo, _, _ = _run_pair(vb, "body", "f32", (1, 2, 2, 2, 2, 2), mode=2)
+    err = rel_l2(Qg, Qo, 8)
+    assert max(err.values()) < 1e-5, err
+
+
+@pytest.mark.parametrize("storage,tol", [("f16", 2e-3), ("bf16", 2e-2)])
+def test_homogenized_body_low_precision(vb, storage, tol):
+    Qg, Qo, _, _ = _run_pair(vb, "body", storage, (1, 2, 2, 2, 2, 2), mode=2)
+    err = rel_l2(Qg, Qo, 8)
+    print(storage, err)
+    assert max(err.values()) < tol, err
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-14), ("f32", 2e-6), ("f16", 2e-3), ("bf16", 2e-2)])
+def test_uniform_inflow_stays_uniform_with_faces(vb, storage, tol):
+    """The Mach-3 inflow state everywhere stays that state (face nodes re-set to its
+    equilibrium, the interior at its fixed point), within the storage's rounding."""
+    Qin, _ = synth.inflow_state()
+    shape = (17, 9, 8)
+    p = vb.make_params(lattice="D3Q7", shape=shape, model="ideal", storage=storage, flux_scale=0.05, tau=1.0,
+                       bc=(1, 2, 2, 2, 2, 2), inflow_Q=Qin, stream=_stream())
+    sim = vb.Vlbm(p)
+    sim.vlbm_init_fields(np.broadcast_to(Qin[:, None, None, None], (8,) + shape[::-1]).copy())
+    sim.vlbm_step(9)
+    Q, _ = sim.vlbm_moments()
+    err = np.abs(np.asarray(Q).reshape(8, -1) - Qin[:, None]).max() / np.abs(Qin).max()
+    assert err < tol, err
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_checkpoint_restart_with_body(vb, mode):
+    """A restored context continues bit for bit (the bounce-back body recomputes its
+    mask for the restored step)."""
+    shape, Q0, Qin, body, tau, s, _ = _case("body", mode)
+    mk = lambda: vb.Vlbm(vb.make_params(lattice="D3Q7", shape=shape, model="ideal", storage="f32", flux_scale=s,
+                                        tau=tau, bc=(1, 2, 2, 2, 2, 2), inflow_Q=Qin, body=body, stream=_stream()))
+    a = mk()
+    a.vlbm_init_fields(Q0)
+    a.vlbm_step(13)
+    buf, par, step = a.vlbm_get_populations()
+    a.vlbm_step(14)
+    b = mk()
+    b.vlbm_set_populations(buf, par, step)
+    b.vlbm_step(14)
+    qa, _ = a.vlbm_moments()
+    qb, _ = b.vlbm_moments()
+    assert np.array_equal(np.asarray(qa), np.asarray(qb))
