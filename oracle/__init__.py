@@ -83,6 +83,9 @@ class Params(ctypes.Structure):
         ("body_b", ctypes.c_double * 4),
         ("body_e", (ctypes.c_double * 3) * 4),
         ("body_m", ctypes.c_double * 3),
+        ("collision", ctypes.c_int32),
+        ("reserved2", ctypes.c_int32),
+        ("trt_magic", ctypes.c_double),
     ]
 
 
@@ -160,7 +163,7 @@ def _ptr(a):
 
 def make_params(dim=2, shape=(64, 64, 1), model=0, gamma=5.0 / 3.0, s=0.2, w0=None,
                 tau=0.6, powell=1, divb_mode=0, dt=0.0, mu=0.0, eta0=0.0, j_c=0.0,
-                tau_M=1.0, tau_H=1.0) -> Params:
+                tau_M=1.0, tau_H=1.0, collision=0, trt_magic=0.25) -> Params:
     p = Params()
     p.dim = dim
     p.nx, p.ny, p.nz = shape
@@ -178,6 +181,8 @@ def make_params(dim=2, shape=(64, 64, 1), model=0, gamma=5.0 / 3.0, s=0.2, w0=No
     for k in range(KMAX):
         p.tau[k] = float(taus[k])
     p.dt, p.mu, p.eta0, p.j_c, p.tau_M, p.tau_H = dt, mu, eta0, j_c, tau_M, tau_H
+    p.collision = int(collision)
+    p.trt_magic = float(trt_magic)
     return p
 
 

@@ -209,11 +209,48 @@ static int collide_cell(const vref_params* p, const double* f, double* fstar, do
   double dl;
   const int bad = vref_flux_source(p, Q, J, Phi, S, &dl);
   equilibrium_from_flux(p, Q, Phi, feq);
-  for (int k = 0; k < K; ++k)
-    for (int i = 0; i < NQ; ++i) {
-      const double fo = f[k * NQ + i];
-      fstar[k * NQ + i] = fo - (fo - feq[k * NQ + i]) / p->tau[k] + weight(p, i) * S[k];
+  if (p->collision == 0) {
+    for (int k = 0; k < K; ++k)
+      for (int i = 0; i < NQ; ++i) {
+        const double fo = f[k * NQ + i];
+        fstar[k * NQ + i] = fo - (fo - feq[k * NQ + i]) / p->tau[k] + weight(p, i) * S[k];
+      }
+  } else if (p->collision == 1) {
+    /* Sec. 2.2 names TRT among the admissible collisions.  READING: the
+     * antisymmetric parts f^-_i = (f_i - f_ibar)/2 relax with 1/tau_k (they carry the
+     * first moment, so tau_k keeps setting the transport), the symmetric parts
+     * f^+_i = (f_i + f_ibar)/2 with 1/tau+_k, tau+ fixed by the magic parameter
+     * Lambda = (tau+ - 1/2)(tau_k - 1/2). */
+    for (int k = 0; k < K; ++k) {
+      const double om_a = 1.0 / p->tau[k];
+      const double om_s = 1.0 / (0.5 + p->trt_magic / (p->tau[k] - 0.5));
+      for (int i = 0; i < NQ; ++i) {
+        const int ib = i == 0 ? 0 : ((i % 2 == 1) ? i + 1 : i - 1);
+        const double fp = 0.5 * (f[k * NQ + i] + f[k * NQ + ib]);
+        const double fm = 0.5 * (f[k * NQ + i] - f[k * NQ + ib]);
+        const double ep = 0.5 * (feq[k * NQ + i] + feq[k * NQ + ib]);
+        const double em = 0.5 * (feq[k * NQ + i] - feq[k * NQ + ib]);
+        fstar[k * NQ + i] = f[k * NQ + i] - om_s * (fp - ep) - om_a * (fm - em) + weight(p, i) * S[k];
+      }
     }
+  } else {
+    /* Sec. 2.2 names the regularized BGK (RLB) among the admissible collisions: the
+     * non-equilibrium part is replaced by its projection on the first-order Hermite
+     * term, f^neq_i -> w_i e_i . J^neq / c_s^2 with J^neq = sum_i e_i (f_i - f^eq_i),
+     * then relaxed: f* = f^eq + (1 - 1/tau_k) f^neq_reg + w_i S~_k. */
+    const double c2 = cs2(p);
+    for (int k = 0; k < K; ++k) {
+      double Jn[3] = {0.0, 0.0, 0.0};
+      for (int i = 0; i < NQ; ++i)
+        for (int a = 0; a < d; ++a) Jn[a] += edir(i, a) * (f[k * NQ + i] - feq[k * NQ + i]);
+      for (int i = 0; i < NQ; ++i) {
+        double eJ = 0.0;
+        for (int a = 0; a < d; ++a) eJ += edir(i, a) * Jn[a];
+        const double fneq = weight(p, i) * eJ / c2;
+        fstar[k * NQ + i] = feq[k * NQ + i] + (1.0 - 1.0 / p->tau[k]) * fneq + weight(p, i) * S[k];
+      }
+    }
+  }
   if (dlat) *dlat = dl;
   return bad;
 }

@@ -52,6 +52,11 @@ typedef struct {
   double body_c0[3], body_v[3], body_R0;
   double body_a[4], body_d[4][3], body_b[4], body_e[4][3];
   double body_m[3];
+  /* collision (Sec. 2.2 admits several): 0 BGK, 1 TRT with magic parameter
+   * trt_magic, 2 regularized BGK */
+  int32_t collision;
+  int32_t reserved2;
+  double trt_magic;
 } vref_params;
 
 /* number of variables K and of directions Q */
@@ -69,8 +74,9 @@ int vref_flux_source(const vref_params* p, const double* Q, const double* J,
 /* f^eq_{k,i} = w_i (Q_k + s e_i . Phi_k / c_s^2) at one cell. */
 void vref_equilibrium(const vref_params* p, const double* Q, double* feq /*[K][Q]*/);
 
-/* One BGK collision with direct source injection at one cell:
- * fstar_{k,i} = f_{k,i} - (f_{k,i} - f^eq_{k,i}) / tau_k + w_i S~_k. */
+/* One collision with direct source injection at one cell; BGK:
+ * fstar_{k,i} = f_{k,i} - (f_{k,i} - f^eq_{k,i}) / tau_k + w_i S~_k (TRT and RLB as
+ * selected by p->collision). */
 int vref_collide(const vref_params* p, const double* f /*[K][Q]*/, double* fstar, double* dlat);
 
 /* vref_collide on n independent cells; f and fstar are [n][K][Q]. */

@@ -232,9 +232,10 @@ def workload_slab_3d(n=512, steps=2000):
                 divb_mode=0, steps=steps, dt=0.0, mu=0.0, eta0=0.0, tau_M=1.0, tau_H=1.0)
 
 
-def workload_body_3d(shape=(768, 384, 384), steps=4000, tau=0.6, s=0.05):
+def workload_body_3d(shape=(768, 384, 384), steps=4000, tau=1.0, s=0.05):
     """3D ideal MHD past a moving body, D3Q7 x 8 variables: inflow at x-, zero-gradient
-    elsewhere; flux scale 0.05 keeps s (|u| + c_fast) <= c_s^2 at Mach 3."""
+    elsewhere; flux scale 0.05 keeps s (|u| + c_fast) <= c_s^2 at Mach 3; tau = 1 (the
+    Mach-3 wake with tau = 0.6 or 0.8 loses positivity within 500 steps at this size)."""
     return dict(dim=3, shape=tuple(shape), model=0, s=s, gamma=5.0 / 3.0, tau=tau, powell=1, divb_mode=0,
                 steps=steps, dt=0.0, mu=0.0, eta0=0.0, tau_M=1.0, tau_H=1.0, bc=(1, 2, 2, 2, 2, 2))
 
@@ -343,3 +344,30 @@ def rough_body(c0, v, R0, m=(0.0, 0.0, 0.0), rough=0.0, seed=1):
         a, b = np.zeros(4), np.zeros(4)
     return dict(c0=[float(c) for c in c0], v=[float(c) for c in v], R0=float(R0), a=list(a), d=d.tolist(),
                 b=list(b), e=e.tolist(), m=[float(c) for c in m])
+
+
+def orszag_tang_2d(n=64, gamma=5.0 / 3.0):
+    """Compressible Orszag-Tang vortex (Sec. 3.4) on the periodic unit square with n
+    cells per side: rho = 25/(36 pi), p = 5/(12 pi), u = (-sin 2 pi y, sin 2 pi x),
+    B = B0 (-sin 2 pi y, sin 4 pi x), B0 = 1/sqrt(4 pi); cell centres at (i + 1/2)/n.
+    Returns [8, 1, n, n]."""
+    c = (np.arange(n) + 0.5) / n
+    y, x = np.meshgrid(c, c, indexing="ij")
+    b0 = 1.0 / np.sqrt(4.0 * np.pi)
+    u = np.stack([-np.sin(2 * np.pi * y), np.sin(2 * np.pi * x), np.zeros_like(x)])
+    B = np.stack([-b0 * np.sin(2 * np.pi * y), b0 * np.sin(4 * np.pi * x), np.zeros_like(x)])
+    Q = conserved_from_primitive(25.0 / (36.0 * np.pi) * np.ones_like(x), u, 5.0 / (12.0 * np.pi), B, gamma)
+    return Q[:, None]
+
+
+def workload_orszag_tang_2d(n=4000, tau=None):
+    """Lattice parameters of the compressible Orszag-Tang run: acoustic scaling with
+    CFL 0.1 (s = 0.1 at sound speed 1); the stabilisation diffusivity 2.5e-5 at
+    n = 1000, decreasing linearly with the cell size, is D = c_s^2 (tau - 1/2) dx / s,
+    i.e. tau = 1/2 + 2.5e-5 * 1000 * s / c_s^2 = 0.5075 at every n (D2Q5, c_s^2 = 1/3)."""
+    s = 0.1
+    if tau is None:
+        tau = 0.5 + 2.5e-5 * 1000.0 * s / (1.0 / 3.0)
+    return dict(dim=2, shape=(n, n, 1), model=0, s=s, gamma=5.0 / 3.0, tau=tau, powell=1, divb_mode=0,
+                steps=int(round(0.5 / (s / n))), dt=0.0, mu=0.0, eta0=0.0, tau_M=1.0, tau_H=1.0)
+

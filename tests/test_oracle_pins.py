@@ -95,10 +95,16 @@ def chk_flux_textbook():
     return err
 
 
-def chk_pulse_fourier(nsteps=40):
+def chk_pulse_fourier(nsteps=40, collision=0, magic=0.25):
     """Density pulse on a uniform (u0, p0, B0) background.  The rho set then obeys
-    the linear scalar scheme f_i(x + e_i, t+1) = (1-w) f_i + w W_i sum_j f_j with
-    W_i = w_i (1 + s e_i.u0 / c_s^2), w = 1/tau, solved exactly per Fourier mode."""
+    the linear scalar scheme f(x + e_i, t+1) = M0 f, solved exactly per Fourier mode,
+    with M0 built by hand from the collision's definition (W_i = w_i (1 + s e_i.u0 /
+    c_s^2), the equilibrium W sum_j f_j):
+    BGK  M0 = (1 - w) I + w W 1^T, w = 1/tau;
+    TRT  M0 = I - w+ P+ (I - W 1^T) - w- P- (I - W 1^T), P+/P- the symmetric and
+         antisymmetric halves over opposite directions, w- = 1/tau,
+         w+ = 1/(1/2 + Lambda/(tau - 1/2));
+    RLB  M0 = W 1^T + (1 - w) R (I - W 1^T), R_ij = w_i e_i.e_j / c_s^2."""
     nx, ny = 32, 16
     s, tau = 0.2, 0.6
     u0 = np.array([0.05, -0.03, 0.02])
@@ -108,7 +114,7 @@ def chk_pulse_fourier(nsteps=40):
                         + 0.3 * np.sin(2 * np.pi * 3 * y / ny + 0.4))
     Q = synth.conserved_from_primitive(rho, u0[:, None, None] * np.ones_like(rho), 0.6,
                                        B0[:, None, None] * np.ones_like(rho), G53)[:, None]
-    p = oracle.make_params(dim=2, shape=(nx, ny, 1), s=s, tau=tau)
+    p = oracle.make_params(dim=2, shape=(nx, ny, 1), s=s, tau=tau, collision=collision, trt_magic=magic)
     f = oracle.init(p, Q)
     oracle.run(p, f, nsteps)
     Qn, _, _ = oracle.moments(p, f)
@@ -118,11 +124,22 @@ def chk_pulse_fourier(nsteps=40):
     e = np.array([[0, 0], [1, 0], [-1, 0], [0, 1], [0, -1]], float)
     W = w * (1 + s * (e @ u0[:2]) / cs2)
     om = 1.0 / tau
+    A = np.eye(5) - np.outer(W, np.ones(5))  # f - f^eq as a linear map of f
+    if collision == 1:
+        opp = [0, 2, 1, 4, 3]
+        Pb = np.eye(5)[opp]  # (Pb f)_i = f_ibar
+        Pp, Pm = 0.5 * (np.eye(5) + Pb), 0.5 * (np.eye(5) - Pb)
+        om_p = 1.0 / (0.5 + magic / (tau - 0.5))
+        M0 = np.eye(5) - om_p * Pp @ A - om * Pm @ A
+    elif collision == 2:
+        Rg = w[:, None] * (e @ e.T) / cs2
+        M0 = np.outer(W, np.ones(5)) + (1 - om) * Rg @ A
+    else:
+        M0 = (1 - om) * np.eye(5) + om * np.outer(W, np.ones(5))
     kx = 2 * np.pi * np.fft.fftfreq(nx)
     ky = 2 * np.pi * np.fft.fftfreq(ny)
     rho_hat = np.fft.fft2(rho)  # [ny, nx]
     fh = W[:, None, None] * rho_hat[None]
-    M0 = (1 - om) * np.eye(5) + om * np.outer(W, np.ones(5))
     KY, KX = np.meshgrid(ky, kx, indexing="ij")
     shift = np.exp(-1j * (e[:, 0, None, None] * KX[None] + e[:, 1, None, None] * KY[None]))
     for _ in range(nsteps):
@@ -322,6 +339,37 @@ def test_totals_exact_without_powell(dim):
 
 def test_pulse_exact_fourier_evolution():
     assert chk_pulse_fourier() < 1e-13
+
+
+@pytest.mark.parametrize("collision,magic", [(1, 0.25), (1, 1.0 / 12.0), (2, 0.25)])
+def test_pulse_exact_fourier_evolution_trt_rlb(collision, magic):
+    assert chk_pulse_fourier(collision=collision, magic=magic) < 1e-13
+
+
+def chk_collision_identities(nsteps=6):
+    """TRT with Lambda = (tau - 1/2)^2 relaxes both halves at 1/tau: it is BGK.  On
+    lattices whose equilibrium has only zeroth- and first-order parts (D2Q5, D3Q7), the
+    regularized BGK equals TRT whose symmetric half relaxes at 1 (Lambda = (tau -
+    1/2)/2): both keep f^eq_i + (1 - 1/tau) times the antisymmetric non-equilibrium part.
+    Full nonlinear MHD, Powell on, 2D and 3D."""
+    err = 0.0
+    for dim, shape, Q in ((2, (24, 24, 1), synth.fourier_2d(24, seed=3)),
+                          (3, (10, 9, 8), synth.smooth_box_state((8, 9, 10), seed=2))):
+        tau = 0.7
+        runs = {}
+        for name, coll, magic in (("bgk", 0, 0.0), ("trt_bgk", 1, (tau - 0.5) ** 2), ("rlb", 2, 0.0),
+                                  ("trt_rlb", 1, 0.5 * (tau - 0.5))):
+            p = oracle.make_params(dim=dim, shape=shape, tau=tau, collision=coll, trt_magic=magic, s=0.1)
+            f = oracle.init(p, Q)
+            oracle.run(p, f, nsteps)
+            runs[name] = f
+        err = max(err, np.abs(runs["bgk"] - runs["trt_bgk"]).max(), np.abs(runs["rlb"] - runs["trt_rlb"]).max())
+        assert np.abs(runs["bgk"] - runs["rlb"]).max() > 1e-8  # the two are different schemes
+    return err
+
+
+def test_collision_identities():
+    assert chk_collision_identities() < 1e-14
 
 
 def test_linear_wave_speeds_second_order():
@@ -528,6 +576,10 @@ MUTATIONS = {
     "resistive_G_flux_sign": ("- (c == a ? B[b] : 0.0);", "+ (c == a ? B[b] : 0.0);"),
     "ohmic_flux_sign": ("Phi[3 * 4 + b] += -utv + eta * jxB[b];", "Phi[3 * 4 + b] += -utv - eta * jxB[b];"),
     "viscous_transpose_dropped": ("p->mu * (du[a][b] + du[b][a])", "p->mu * (du[a][b] + du[a][b])"),
+    "trt_rates_swapped": ("- om_s * (fp - ep) - om_a * (fm - em)", "- om_a * (fp - ep) - om_s * (fm - em)"),
+    "trt_magic_inverted": ("1.0 / (0.5 + p->trt_magic / (p->tau[k] - 0.5))", "1.0 / (0.5 + (p->tau[k] - 0.5) / p->trt_magic)"),
+    "rlb_projection_scale": ("const double fneq = weight(p, i) * eJ / c2;", "const double fneq = weight(p, i) * eJ;"),
+    "rlb_relaxation": ("feq[k * NQ + i] + (1.0 - 1.0 / p->tau[k]) * fneq", "feq[k * NQ + i] + (1.0 / p->tau[k]) * fneq"),
 }
 
 
@@ -544,6 +596,9 @@ def _fails(name):
         return dp_on > 3e-4
     if name == "divb_estimate_scale":
         return chk_divb_estimator_tau1() > 1e-12
+    if name.startswith("trt") or name.startswith("rlb"):
+        return (chk_pulse_fourier(collision=1, magic=1.0 / 12.0) > 1e-13
+                or chk_pulse_fourier(collision=2) > 1e-13 or chk_collision_identities() > 1e-14)
     checks = [
         lambda: chk_equilibrium_moments() > 1e-14,
         lambda: chk_flux_textbook() > 1e-14,
