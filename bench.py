@@ -53,7 +53,8 @@ def params_for(vlbm, w, storage, stream):
                             model="resistive" if w["model"] else "ideal", storage=storage,
                             gamma=w["gamma"], flux_scale=w["s"], tau=w["tau"], powell=w["powell"],
                             divb_mode=w["divb_mode"], dt=w["dt"], mu=w["mu"], eta0=w["eta0"],
-                            tau_M=w["tau_M"], tau_H=w["tau_H"], stream=stream)
+                            tau_M=w["tau_M"], tau_H=w["tau_H"], bc=w.get("bc"), inflow_Q=w.get("inflow_Q"),
+                            body=w.get("body"), stream=stream)
 
 
 def time_sweep(vlbm, torch, w, Q_dev, storage, steps, warmup):
@@ -198,6 +199,29 @@ def main():
         for st in ("f16", "bf16"):
             forms[st]["speedup_vs_f32"] = round(forms[st]["mlups"] / forms["f32"]["mlups"], 3)
 
+    body_forms = {}
+    if not args.no_forms:
+        # flow past the moving magnetised body: 768 x 384 x 384, inflow / zero-gradient
+        # faces, homogenized body, FP16 deviation storage next to FP32
+        shape = (768, 384, 384)
+        wb = synth.workload_body_3d(shape=shape)
+        Qin, info = synth.inflow_state()
+        wb["inflow_Q"] = Qin
+        wb["body"] = synth.body_params(shape=shape, B_in=float(np.linalg.norm(info["B"])))
+        log("generating the 768 x 384 x 384 body workload")
+        Qb = torch.from_numpy(synth.body_initial_state(shape, wb["body"], dtype=np.float32)).cuda()
+        for st in ("f16", "f32"):
+            rr = time_sweep(vlbm, torch, wb, Qb, st, args.form_steps, 5)
+            m = rr["ncell"] * args.form_steps / rr["wall_s"] / 1e6
+            gb = rr["bytes_per_cell"] * rr["ncell"] / (rr["kernel_ms"] * 1e-3) / 1e9
+            body_forms[st] = dict(mlups=round(m, 1), step_ms=round(rr["kernel_ms"], 4),
+                                  bytes_per_cell=rr["bytes_per_cell"], achieved_GBps=round(gb, 1),
+                                  frac_of_peak=round(gb / HBM_PEAK_GBPS, 4), finite=rr["finite"])
+            log(f"body 768x384x384 {st}: {m:.1f} MLUPS, {gb:.0f} GB/s")
+        body_forms["f16"]["speedup_vs_f32"] = round(body_forms["f16"]["mlups"] / body_forms["f32"]["mlups"], 3)
+        del Qb
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
@@ -237,6 +261,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "forms_slab_512": forms or None,
+        "forms_body_768x384x384": body_forms or None,
         "finite": r["finite"],
     }
     print(json.dumps(out), flush=True)

@@ -128,9 +128,16 @@ typedef struct {
   double body_c0[3], body_v[3], body_R0;
   double body_a[4], body_d[4][3], body_b[4], body_e[4][3];
   double body_m[3];
+  /* Collision (Sec. 2.2 admits several): 0 BGK; 1 TRT -- the antisymmetric halves
+   * (f_i - f_ibar)/2, which carry the first moment, relax with 1/tau_k and the
+   * symmetric halves with 1/tau+_k, (tau+_k - 1/2)(tau_k - 1/2) = trt_magic (> 0);
+   * 2 regularized BGK -- f* = f^eq + (1 - 1/tau_k) w_i e_i . J^neq / c_s^2 + w_i S~. */
+  int32_t collision;
+  double trt_magic;
 } vlbm_params;
 
-/* Fill *p with defaults (periodic, F32, gamma 5/3, s 0.2, tau 0.6, Powell on). */
+/* Fill *p with defaults (periodic, F32, gamma 5/3, s 0.2, tau 0.6, Powell on, BGK,
+ * trt_magic 1/4). */
 vlbm_status vlbm_params_default(vlbm_params* p);
 
 /* Bytes of the population buffer for these parameters (K*Q padded planes). */

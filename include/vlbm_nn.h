@@ -5,8 +5,11 @@
  * method's own runs on a fine 2D lattice, restricted to a coarser one, train a small
  * network that predicts, from the coarse moments at one step, the correction that
  * takes the plain coarse VLBM step to the restricted fine solution.  The coarse run
- * then adds that correction to the moments after each plain coarse step unless a
- * gate falls back to the plain step.
+ * then injects that correction into the populations (f_{k,i} += w_i dQ_k, which
+ * shifts the zeroth moments by dQ_k) after each plain coarse step, unless a gate
+ * falls back to the plain VLBM.  The training pairs come from a teacher-forced coarse
+ * run that takes exactly these steps with the true corrections, so the network is
+ * trained against the operator it is applied to.
  * The VLBM pieces it drives are those of include/vlbm.h (Sec. 2.2-2.3 of the paper:
  * moments, equilibrium, BGK update with direct source injection).
  *
@@ -88,18 +91,23 @@ vlbm_status vlbm_nn_train_step(vlbm_nn* nn, const float* X, const float* T, int3
 vlbm_status vlbm_restrict(const float* Qf, int32_t K, int32_t nx, int32_t ny, int32_t nz,
                           int32_t r, int32_t rz, const float* minus, float* Qc, void* stream);
 
-/* n coarse steps with the learned correction: Q_{n+1} = C(Q_n) + dQ_n, where C is
- * one plain VLBM step started from f^eq(Q_n) -- the step the training targets are
- * taken against -- and dQ_n = network(Q_n).  Per step: the moments X of the current
- * populations plus the pending correction, dQ = network(X), the gate (FP64 over the
- * whole lattice or batch: every ||dQ_k||_2 <= bound_corr[k]; the central-difference
- * div B drift ||div(B + dB)||_2 <= (1 + bound_divb_rel) ||div B||_2 + bound_divb_abs
- * ||B||_2 with B the in-plane field of X; all finite -- otherwise dQ := 0, i.e. the
- * plain step C, and the fallback counter is incremented), f := f^eq(X), the sweep,
- * and dQ becomes the pending correction.  After the last step the pending dQ is added
- * to the populations (f_{k,i} += w_i dQ_k), so vlbm_moments sees the corrected state.  The context must be a 2D ideal-MHD context (K = cin = 8, FP32 or
- * FP64 storage; nz = batch of independent lattices, gated together) whose extent the
- * network supports.  bound_corr: host, K doubles.  *n_fallback (host, may
+/* f_{k,i} += w_i dQ_k at the context's current step (shifts the zeroth moments by
+ * dQ): the teacher-forced coarse run of the training pairs takes each target this
+ * way.  dQ: device FP32 [8][N] in the context's moment layout.  2D ideal-MHD context,
+ * FP32 or FP64 storage.  Stream-ordered, no synchronisation. */
+vlbm_status vlbm_inject(vlbm_ctx* c, const float* dQ);
+
+/* n coarse steps with the learned correction.  Per step: the moments X of the
+ * current populations (including the pending correction), dQ = network(X), the gate
+ * (FP64 over the whole lattice or batch: every ||dQ_k||_2 <= bound_corr[k]; the
+ * central-difference div B drift ||div(B + dB)||_2 <= (1 + bound_divb_rel) ||div B||_2
+ * + bound_divb_abs ||B||_2 with B the in-plane field of X; all finite -- otherwise
+ * dQ := 0, i.e. the plain coarse VLBM step, and the fallback counter is incremented),
+ * then the sweep, with the previous step's accepted dQ added as w_i dQ_k to the
+ * populations before the collision.  After the last step the pending dQ is added to
+ * the populations, so vlbm_moments sees the corrected state.  The context must be a
+ * 2D ideal-MHD BGK context (K = cin = 8, FP32 or FP64 storage; nz = batch of
+ * independent lattices, gated together) whose extent the network supports.  bound_corr: host, K doubles.  *n_fallback (host, may
  * be NULL) receives the number of fallbacks in this call.  Synchronises. */
 vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const double* bound_corr,
                                 double bound_divb_rel, double bound_divb_abs, int64_t* n_fallback);

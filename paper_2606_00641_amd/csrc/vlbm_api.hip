@@ -112,6 +112,9 @@ vlbm_status validate(const vlbm_params* p) {
     }
   }
   if (p->body < 0 || p->body > 2) return fail(nullptr, VLBM_ERR_ARG, "body must be 0, 1 or 2");
+  if (p->collision < 0 || p->collision > 2) return fail(nullptr, VLBM_ERR_ARG, "collision must be 0, 1 or 2");
+  if (p->collision == 1 && !(p->trt_magic > 0.0 && std::isfinite(p->trt_magic)))
+    return fail(nullptr, VLBM_ERR_ARG, "trt_magic must be > 0");
   if ((faces || p->body) && (p->lattice != VLBM_D3Q7 || p->model != VLBM_IDEAL))
     return fail(nullptr, VLBM_ERR_ARG, "non-periodic faces and the body need the D3Q7 ideal model");
   if (faces || p->body)
@@ -216,6 +219,7 @@ vlbm_status vlbm_params_default(vlbm_params* p) {
   p->flux_scale = 0.2;
   for (int k = 0; k < VLBM_KMAX; ++k) p->tau[k] = 0.6;
   p->tau_M = p->tau_H = 1.0;
+  p->trt_magic = 0.25;
   return VLBM_OK;
 }
 
@@ -273,6 +277,13 @@ vlbm_status vlbm_create(const vlbm_params* p, vlbm_ctx** out) {
   }
   ph.powell = p->powell;
   ph.divb_mode = p->divb_mode;
+  ph.collision = p->collision;
+  for (int k = 0; k < KMAX; ++k) {
+    const double tau = k < c->K ? p->tau[k] : 1.0;
+    ph.omega_s[k] = p->collision == 1 ? 1.0 / (0.5 + p->trt_magic / (tau - 0.5))
+                    : p->collision == 2 ? 1.0
+                                        : ph.omega[k];
+  }
 
   if (p->pop_buffer) {
     if (p->pop_bytes < c->pop_bytes) {

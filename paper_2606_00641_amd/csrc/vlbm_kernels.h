@@ -77,6 +77,11 @@ hipError_t launch_refill(const Launch& L, const Grid& g, const Phys& ph, const C
 hipError_t launch_sweep_body(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
                              const Body& b, int mode);
 
+// Sweep of a 2D ideal-MHD BGK lattice (FP32 or FP64 storage) that first adds
+// *flag * w_i dq[k][c] to the gathered populations (dq FP32 [K][N], device).
+hipError_t launch_sweep_inj(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
+                            const float* dq, const int* flag);
+
 // f := f^eq(Q) in natural layout.  Q is device SoA [K][N], FP64 or FP32.
 hipError_t launch_init(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd,
                        const void* Q, int q_is_f32);

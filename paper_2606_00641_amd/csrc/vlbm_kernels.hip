@@ -251,9 +251,12 @@ struct HlbmTarget {
 // rho u and B.  In the AA layout that population belongs at slot i of cell x + e_i
 // after a parity-0 step and at slot opposite(i) of x after a parity-1 step, places
 // no other thread writes because the solid cell runs no update.
-template <int ST, int D, int MODEL, int PAR, int BODY = 0>
+// INJ: before the collision add *dqflag * w_i dq[k][c] to f_{k,i} (the pending learned
+// coarse correction, which shifts the zeroth moments by dq); dq is FP32 [K][N].
+template <int ST, int D, int MODEL, int PAR, int BODY = 0, int COLL = 0, bool INJ = false>
 __global__ __launch_bounds__(256) void k_sweep(const Grid g, const Phys ph, const Codec cd,
-                                               const Body bd = Body{}) {
+                                               const Body bd = Body{}, const float* __restrict__ dq = nullptr,
+                                               const int* __restrict__ dqflag = nullptr) {
   using S = Store<ST>;
   using T = typename S::T;
   using R = typename S::R;
@@ -301,15 +304,29 @@ __global__ __launch_bounds__(256) void k_sweep(const Grid g, const Phys ph, cons
     }
   }
 
+  if constexpr (INJ) {
+    if (*dqflag) {
+      const size_t N = (size_t)g.nx * g.ny * g.nz;
+      const R wi = R(ph.wi);
+      const R w0 = rest_weight<R, D>(wi);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const R d = (R)dq[(size_t)k * N + c];
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) f[k][i] += (i == 0 ? w0 : wi) * d;
+      }
+    }
+  }
+
   R dl;
   if constexpr (BODY != 1) {
     if constexpr (BODY == 2) {
       static_assert(D == 3 && MODEL == 0, "homogenized body: D3Q7 ideal MHD");
       R Q[K], pt;
       const bool near = HlbmTarget::near_body(bd, x, y, z);
-      collide<R, D, MODEL>(f, ph, dl, Q, pt, HlbmTarget{&bd, x, y, z, near, ph.s, ph.gm1});
+      collide<R, D, MODEL, COLL>(f, ph, dl, Q, pt, HlbmTarget{&bd, x, y, z, near, ph.s, ph.gm1});
     } else {
-      collide<R, D, MODEL>(f, ph, dl);
+      collide<R, D, MODEL, COLL>(f, ph, dl);
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -327,7 +344,7 @@ __global__ __launch_bounds__(256) void k_sweep(const Grid g, const Phys ph, cons
   } else {
     static_assert(D == 3 && MODEL == 0, "body bounce-back: D3Q7 ideal MHD");
     R Q[K], pt;
-    collide<R, D, MODEL>(f, ph, dl, Q, pt);
+    collide<R, D, MODEL, COLL>(f, ph, dl, Q, pt);
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
       const unsigned dst = (i == 0) ? co : ((i & 1) ? np[(i - 1) >> 1] : nm[(i - 1) >> 1]);
@@ -750,10 +767,23 @@ dim3 cell_grid(const Grid& g, int bx) { return dim3((g.nx + bx - 1) / bx, g.ny, 
 template <int ST, int D, int MODEL>
 hipError_t sweep_t(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity) {
   const dim3 grd = cell_grid(g, L.block_x), blk(L.block_x);
+  switch ((ph.collision ? 2 : 0) + parity) {
+    case 0: hipLaunchKernelGGL((k_sweep<ST, D, MODEL, 0, 0, 0>), grd, blk, 0, L.stream, g, ph, cd); break;
+    case 1: hipLaunchKernelGGL((k_sweep<ST, D, MODEL, 1, 0, 0>), grd, blk, 0, L.stream, g, ph, cd); break;
+    case 2: hipLaunchKernelGGL((k_sweep<ST, D, MODEL, 0, 0, 1>), grd, blk, 0, L.stream, g, ph, cd); break;
+    default: hipLaunchKernelGGL((k_sweep<ST, D, MODEL, 1, 0, 1>), grd, blk, 0, L.stream, g, ph, cd); break;
+  }
+  return hipGetLastError();
+}
+
+template <int ST>
+hipError_t sweep_inj_t(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
+                       const float* dq, const int* flag) {
+  const dim3 grd = cell_grid(g, L.block_x), blk(L.block_x);
   if (parity == 0)
-    hipLaunchKernelGGL((k_sweep<ST, D, MODEL, 0>), grd, blk, 0, L.stream, g, ph, cd);
+    hipLaunchKernelGGL((k_sweep<ST, 2, 0, 0, 0, 0, true>), grd, blk, 0, L.stream, g, ph, cd, Body{}, dq, flag);
   else
-    hipLaunchKernelGGL((k_sweep<ST, D, MODEL, 1>), grd, blk, 0, L.stream, g, ph, cd);
+    hipLaunchKernelGGL((k_sweep<ST, 2, 0, 1, 0, 0, true>), grd, blk, 0, L.stream, g, ph, cd, Body{}, dq, flag);
   return hipGetLastError();
 }
 
@@ -764,18 +794,19 @@ hipError_t boundary_t(const Launch& L, const Grid& g, const Phys& ph, const Code
     const long long area = std::max({(long long)g.ny * g.nz, (long long)g.nx * g.nz, (long long)g.nx * g.ny});
     hipLaunchKernelGGL((k_faces<ST>), dim3((unsigned)((area + 255) / 256), 1, 6), dim3(256), 0, L.stream, g, ph,
                        cd, parity, *in);
-  } else if (what == 1) {  // sweep with the bounce-back body
+  } else if (what == 1 || what == 3) {  // sweep with the bounce-back (1) or homogenized (3) body
     const dim3 grd = cell_grid(g, L.block_x), blk(L.block_x);
-    if (parity == 0)
-      hipLaunchKernelGGL((k_sweep<ST, 3, 0, 0, 1>), grd, blk, 0, L.stream, g, ph, cd, *b);
-    else
-      hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 1>), grd, blk, 0, L.stream, g, ph, cd, *b);
-  } else if (what == 3) {  // sweep with the homogenized body
-    const dim3 grd = cell_grid(g, L.block_x), blk(L.block_x);
-    if (parity == 0)
-      hipLaunchKernelGGL((k_sweep<ST, 3, 0, 0, 2>), grd, blk, 0, L.stream, g, ph, cd, *b);
-    else
-      hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 2>), grd, blk, 0, L.stream, g, ph, cd, *b);
+    const int key = (what == 3 ? 4 : 0) + (ph.collision ? 2 : 0) + parity;
+    switch (key) {
+      case 0: hipLaunchKernelGGL((k_sweep<ST, 3, 0, 0, 1, 0>), grd, blk, 0, L.stream, g, ph, cd, *b); break;
+      case 1: hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 1, 0>), grd, blk, 0, L.stream, g, ph, cd, *b); break;
+      case 2: hipLaunchKernelGGL((k_sweep<ST, 3, 0, 0, 1, 1>), grd, blk, 0, L.stream, g, ph, cd, *b); break;
+      case 3: hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 1, 1>), grd, blk, 0, L.stream, g, ph, cd, *b); break;
+      case 4: hipLaunchKernelGGL((k_sweep<ST, 3, 0, 0, 2, 0>), grd, blk, 0, L.stream, g, ph, cd, *b); break;
+      case 5: hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 2, 0>), grd, blk, 0, L.stream, g, ph, cd, *b); break;
+      case 6: hipLaunchKernelGGL((k_sweep<ST, 3, 0, 0, 2, 1>), grd, blk, 0, L.stream, g, ph, cd, *b); break;
+      default: hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 2, 1>), grd, blk, 0, L.stream, g, ph, cd, *b); break;
+    }
   } else {  // refill
     const long long n = (long long)(b->box[1] - b->box[0]) * (b->box[3] - b->box[2]) * (b->box[5] - b->box[4]);
     if (n <= 0) return hipSuccess;
@@ -876,6 +907,14 @@ hipError_t launch_sweep(const Launch& L, const Grid& g, const Phys& ph, const Co
 hipError_t launch_init(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd,
                        const void* Q, int q_is_f32) {
   return dispatch<InitFn>(L, g, ph, cd, Q, q_is_f32);
+}
+
+hipError_t launch_sweep_inj(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
+                            const float* dq, const int* flag) {
+  if (L.dim != 2 || L.model != 0 || ph.collision != 0) return hipErrorInvalidValue;
+  if (L.storage == ST_F32) return sweep_inj_t<ST_F32>(L, g, ph, cd, parity, dq, flag);
+  if (L.storage == ST_F64) return sweep_inj_t<ST_F64>(L, g, ph, cd, parity, dq, flag);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_faces(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,

@@ -429,7 +429,7 @@ __global__ void k_moments_x(const vlbm::Grid g, const vlbm::Codec cd, int parity
   }
 }
 
-// add flag * w_i dQ_k to every population at the given parity (the last pending correction)
+// add w_i dQ_k to every population at the given parity, if *flag (or flag is NULL)
 template <int ST>
 __global__ void k_inject(const vlbm::Grid g, int parity, const float* __restrict__ dq, const int* __restrict__ flag,
                          double wi_d) {
@@ -437,7 +437,7 @@ __global__ void k_inject(const vlbm::Grid g, int parity, const float* __restrict
   constexpr int K = 8, NQ = 5;
   const size_t N = (size_t)g.nx * g.ny * g.nz;
   const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= N || !*flag) return;
+  if (c >= N || (flag && !*flag)) return;
   const size_t sl = (c / ((size_t)g.nx * g.ny)) * g.nx * g.ny;
   const int x = (int)(c % g.nx), y = (int)((c / g.nx) % g.ny);
   const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x + 1 == g.nx ? 0 : x + 1;
@@ -457,52 +457,6 @@ __global__ void k_inject(const vlbm::Grid g, int parity, const float* __restrict
       v += (i == 0 ? w0 : wi) * d;
     }
   }
-}
-
-// f := f^eq(Q) in the layout of the given parity, Q the moments of the cell's own
-// populations plus flag * dq (the pending correction), accumulated in FP64 in direction
-// order like vlbm_moments, then taken to the storage type: every step of a corrected
-// coarse run starts from the equilibrium of its moments, like the plain coarse step
-// the training targets are taken against.  Each thread reads and writes only the
-// population slots of its own cell.
-template <int ST>
-__global__ void k_feq_x(const vlbm::Grid g, const vlbm::Phys ph, const vlbm::Codec cd, int parity,
-                        const float* __restrict__ dq, const int* __restrict__ flag) {
-  using T = typename Dec<ST>::T;
-  constexpr int K = 8, NQ = 5;
-  const size_t N = (size_t)g.nx * g.ny * g.nz;
-  const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= N) return;
-  const size_t sl = (c / ((size_t)g.nx * g.ny)) * g.nx * g.ny;
-  const int x = (int)(c % g.nx), y = (int)((c / g.nx) % g.ny);
-  const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x + 1 == g.nx ? 0 : x + 1;
-  const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y + 1 == g.ny ? 0 : y + 1;
-  const size_t up[NQ] = {c, sl + (size_t)y * g.nx + xm, sl + (size_t)y * g.nx + xp, sl + (size_t)ym * g.nx + x,
-                         sl + (size_t)yp * g.nx + x};
-  T* F = static_cast<T*>(g.f);
-  const bool add = flag && *flag;
-  T Q[K];
-  for (int k = 0; k < K; ++k) {
-    double q = 0.0;
-    for (int i = 0; i < NQ; ++i) {
-      const int slot = parity == 0 ? i : vlbm::opposite(i);
-      const size_t src = parity == 0 ? c : up[i];
-      q += Dec<ST>::get(F[(size_t)(k * NQ + slot) * g.stride + src], cd, k * NQ + i);
-    }
-    if (add) q += (double)dq[(size_t)k * N + c];
-    Q[k] = (T)q;
-  }
-  T Jb[3] = {T(0), T(0), T(0)};
-  T P[K][3], Sv[K], dl;
-  vlbm::flux_source<T, 2, 0>(Q, Jb, ph, P, Sv, dl);
-  const T wi = (T)ph.wi;
-  const T w0 = vlbm::rest_weight<T, 2>(wi);
-  for (int k = 0; k < K; ++k)
-    for (int i = 0; i < NQ; ++i) {
-      const int slot = parity == 0 ? i : vlbm::opposite(i);
-      const size_t dst = parity == 0 ? c : up[i];
-      F[(size_t)(k * NQ + slot) * g.stride + dst] = vlbm::feq_dir<T, 2>(Q[k], P[k], i, w0, wi);
-    }
 }
 
 struct GateBounds {
@@ -958,14 +912,30 @@ vlbm_status vlbm_restrict(const float* Qf, int32_t K, int32_t nx, int32_t ny, in
   return hipGetLastError() == hipSuccess ? VLBM_OK : VLBM_ERR_HIP;
 }
 
+vlbm_status vlbm_inject(vlbm_ctx* c, const float* dQ) {
+  if (!c || !dQ) return VLBM_ERR_ARG;
+  if (!c->initialized) return VLBM_ERR_STATE;
+  if (c->D != 2 || c->K != 8 || c->p.model != VLBM_IDEAL || (c->p.storage != VLBM_F32 && c->p.storage != VLBM_F64))
+    return VLBM_ERR_ARG;
+  const size_t N = (size_t)c->N;
+  const dim3 cgrid((unsigned)((N + 255) / 256)), cblk(256);
+  const int par = (int)(c->step & 1);
+  if (c->p.storage == VLBM_F32)
+    hipLaunchKernelGGL(k_inject<vlbm::ST_F32>, cgrid, cblk, 0, c->stream, c->g, par, dQ, nullptr, c->ph.wi);
+  else
+    hipLaunchKernelGGL(k_inject<vlbm::ST_F64>, cgrid, cblk, 0, c->stream, c->g, par, dQ, nullptr, c->ph.wi);
+  return hipGetLastError() == hipSuccess ? VLBM_OK : VLBM_ERR_HIP;
+}
+
 vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const double* bound_corr,
                                 double bound_divb_rel, double bound_divb_abs, int64_t* n_fallback) {
   if (!c || !nn) return VLBM_ERR_ARG;
   if (!c->initialized) return VLBM_ERR_STATE;
   if (n < 0 || !bound_corr) return nfail(nn, VLBM_ERR_ARG, "n >= 0 and bound_corr required");
-  if (c->D != 2 || c->K != 8 || c->p.model != VLBM_IDEAL || c->N > (1LL << 28) ||
+  if (c->D != 2 || c->K != 8 || c->p.model != VLBM_IDEAL || c->N > (1LL << 28) || c->p.collision != 0 ||
       (c->p.storage != VLBM_F32 && c->p.storage != VLBM_F64))
-    return nfail(nn, VLBM_ERR_ARG, "corrected stepping needs a 2D ideal-MHD context with FP32 or FP64 storage");
+    return nfail(nn, VLBM_ERR_ARG,
+                 "corrected stepping needs a 2D ideal-MHD BGK context with FP32 or FP64 storage");
   vlbm_status st = check_shape(nn, c->p.nz, c->p.nx, c->p.ny);
   if (st != VLBM_OK) return st;
   GateBounds gb;
@@ -1018,13 +988,9 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
     hipLaunchKernelGGL(k_gate_partials, dim3(gblk), dim3(kGateThreads), 0, s, X, dq[1 - cur], c->p.nx, c->p.ny,
                        c->p.nz, gpart);
     hipLaunchKernelGGL(k_gate_final, dim3(1), dim3(1), 0, s, gpart, gblk, gb, flag + (1 - cur), fb);
-    if (c->p.storage == VLBM_F32)
-      hipLaunchKernelGGL(k_feq_x<vlbm::ST_F32>, cgrid, cblk, 0, s, c->g, c->ph, c->cd, par, dq[cur], flag + cur);
-    else
-      hipLaunchKernelGGL(k_feq_x<vlbm::ST_F64>, cgrid, cblk, 0, s, c->g, c->ph, c->cd, par, dq[cur], flag + cur);
     e = hipGetLastError();
     if (e != hipSuccess) break;
-    e = vlbm::launch_sweep(c->L, c->g, c->ph, c->cd, par);
+    e = vlbm::launch_sweep_inj(c->L, c->g, c->ph, c->cd, par, dq[cur], flag + cur);
     ++c->step;
     cur = 1 - cur;
   }

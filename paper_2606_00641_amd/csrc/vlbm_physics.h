@@ -31,6 +31,8 @@ struct Phys {
   double mu, eta0, inv_jc2, inv_tauM, inv_tauH;
   double divb_scale; // divb_mode 1: dx = dt / s (lattice units of tr G / tau_M)
   int powell, divb_mode;
+  int collision;     // 0 BGK; else two rates: antisymmetric halves at omega, symmetric at omega_s
+  double omega_s[KMAX];
 };
 
 // Scaled lattice flux P[k][a] = (s / c_s^2) Phi[k][a] for the D lattice axes, lattice
@@ -183,7 +185,9 @@ struct NoTarget {
 // BGK + direct injection, in place: f_{k,i} += omega_k (f^eq_{k,i}(Q') - f_{k,i}) + w_i S_k(Q'),
 // Q' the moments Q after tgt.  Returns the unphysical flag and writes the div B
 // estimate, the pre-collision moments Q and the total pressure pt of Q'.
-template <typename R, int D, int MODEL, typename Tgt = NoTarget>
+// COLL 0: BGK; 1: two relaxation rates (TRT, and the regularized BGK as its case
+// omega_s = 1) -- a template parameter, so that the BGK sweep keeps its registers.
+template <typename R, int D, int MODEL, int COLL = 0, typename Tgt = NoTarget>
 __device__ __forceinline__ bool collide(R (*f)[2 * D + 1], const Phys& ph, R& dlat,
                                         R (&Q)[MODEL ? 26 : 8], R& pt, const Tgt& tgt = Tgt{}) {
   constexpr int K = MODEL ? 26 : 8;
@@ -210,27 +214,48 @@ __device__ __forceinline__ bool collide(R (*f)[2 * D + 1], const Phys& ph, R& dl
   const bool bad = flux_source<R, D, MODEL>(Qt, Jb, ph, P, S, dlat, &pt);
   const R wi = R(ph.wi);
   const R w0 = rest_weight<R, D>(wi);
+  if constexpr (COLL == 0) {
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const R om = R(ph.omega[k]);
-    const R sw0 = w0 * S[k], swi = wi * S[k];
-    f[k][0] += om * (w0 * Qt[k] - f[k][0]) + sw0;
+    for (int k = 0; k < K; ++k) {
+      const R om = R(ph.omega[k]);
+      const R sw0 = w0 * S[k], swi = wi * S[k];
+      f[k][0] += om * (w0 * Qt[k] - f[k][0]) + sw0;
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-      const R ep = wi * (Qt[k] + P[k][a]);
-      const R em = wi * (Qt[k] - P[k][a]);
-      f[k][2 * a + 1] += om * (ep - f[k][2 * a + 1]) + swi;
-      f[k][2 * a + 2] += om * (em - f[k][2 * a + 2]) + swi;
+      for (int a = 0; a < D; ++a) {
+        const R ep = wi * (Qt[k] + P[k][a]);
+        const R em = wi * (Qt[k] - P[k][a]);
+        f[k][2 * a + 1] += om * (ep - f[k][2 * a + 1]) + swi;
+        f[k][2 * a + 2] += om * (em - f[k][2 * a + 2]) + swi;
+      }
+    }
+  } else {
+    // two relaxation rates over each opposite pair: the symmetric half (f_+ + f_-)/2
+    // toward w_i Q at omega_s, the antisymmetric half (f_+ - f_-)/2 toward w_i P at
+    // omega; the rest population is symmetric.  The regularized BGK of these
+    // first-order lattices is the case omega_s = 1.
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const R oa = R(ph.omega[k]), os = R(ph.omega_s[k]);
+      const R sw0 = w0 * S[k], swi = wi * S[k];
+      f[k][0] += os * (w0 * Qt[k] - f[k][0]) + sw0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const R fp = f[k][2 * a + 1], fm = f[k][2 * a + 2];
+        const R ds = os * (R(0.5) * (fp + fm) - wi * Qt[k]);
+        const R da = oa * (R(0.5) * (fp - fm) - wi * P[k][a]);
+        f[k][2 * a + 1] = fp - ds - da + swi;
+        f[k][2 * a + 2] = fm - ds + da + swi;
+      }
     }
   }
   return bad;
 }
 
-template <typename R, int D, int MODEL>
+template <typename R, int D, int MODEL, int COLL = 0>
 __device__ __forceinline__ bool collide(R (*f)[2 * D + 1], const Phys& ph, R& dlat) {
   R Q[MODEL ? 26 : 8];
   R pt;
-  return collide<R, D, MODEL>(f, ph, dlat, Q, pt);
+  return collide<R, D, MODEL, COLL>(f, ph, dlat, Q, pt);
 }
 
 }  // namespace vlbm

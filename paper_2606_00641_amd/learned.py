@@ -8,8 +8,12 @@ chooses indices and measures time.  The per-channel normalisation statistics are
 computed once on the host from a sample of the training pairs.
 
 Pairs (one coarse step = r fine steps, same flux scale and relaxation time):
-  X_n = R(Q_fine(t_n)),  Y_n = R(Q_fine(t_{n+1})) - C(X_n),
-where R is the r x r block mean and C one plain coarse step started from f^eq(X_n).
+  X_n = R(Q_fine(t_n)),  Y_n = R(Q_fine(t_{n+1})) - P(f_n),
+where R is the r x r block mean and P one plain coarse VLBM step of a teacher-forced
+coarse run: it starts from f^eq(X_0) and after each step takes the true correction,
+f_{n+1} = P(f_n) + w_i Y_n, so its moments follow R(Q_fine) while its populations
+carry the coarse run's own non-equilibrium part -- the state and the operator the
+corrected run applies the network to.
 """
 from __future__ import annotations
 
@@ -54,55 +58,22 @@ def generate_pairs(seeds, n_fine, r, pairs_per_seed, workload, make_state, kmax=
     nxt = torch.empty((8, B, nc, nc), dtype=torch.float32, device="cuda")
     fine.vlbm_moments(out=M)
     N.vlbm_restrict(M, r, X[0], rz=1, stream=s)
+    coarse.vlbm_init_fields(X[0])
     t0 = time.perf_counter()
     for n in range(pairs_per_seed):
-        coarse.vlbm_init_fields(X[n])
         coarse.vlbm_step(1)
         coarse.vlbm_moments(out=Cst)
         fine.vlbm_step(r)
         fine.vlbm_moments(out=M)
         N.vlbm_restrict(M, r, X[n + 1] if n + 1 < pairs_per_seed else nxt, rz=1, stream=s)
         N.vlbm_restrict(M, r, Y[n], rz=1, minus=Cst, stream=s)
+        N.vlbm_inject(coarse, Y[n])  # teacher forcing: the coarse moments become X[n + 1]
         if log and (n + 1) % 100 == 0:
             log(f"pairs: {n + 1}/{pairs_per_seed} steps x {B} seeds, {time.perf_counter() - t0:.1f} s")
     torch.cuda.synchronize()
     fine.vlbm_destroy()
     coarse.vlbm_destroy()
     return X, Y
-
-
-def rollout_pairs(net, X, m, workload, bound_corr, bound_divb_rel, bound_divb_abs, stride=1, storage="f32",
-                  log=None):
-    """Pairs taken on the corrected run's own states (so that the network also learns to
-    pull a drifted coarse state back toward the restricted fine trajectory): for
-    n = m, m + stride, ...: start a coarse run at X[n - m] (a restricted fine state),
-    take m corrected steps to Xt (its state at t_n, with the drift the run accumulates),
-    and set the target X[n + 1] - C(Xt).  X: [P, 8, B, nc, nc] device tensor of
-    consecutive restricted fine states.  Returns (Xr, Yr) of the same layout."""
-    torch = _torch()
-    s = torch.cuda.current_stream().cuda_stream
-    P, _, B, nc, _ = X.shape
-    a = make_context((nc, nc), B, storage, workload, s)
-    b = make_context((nc, nc), B, storage, workload, s)
-    idx = list(range(m, P - 1, stride))
-    Xr = torch.empty((len(idx), 8, B, nc, nc), dtype=torch.float32, device="cuda")
-    Yr = torch.empty_like(Xr)
-    Cst = torch.empty((8, B, nc, nc), dtype=torch.float32, device="cuda")
-    t0 = time.perf_counter()
-    for j, n in enumerate(idx):
-        a.vlbm_init_fields(X[n - m])
-        N.vlbm_step_corrected(a, net, m, bound_corr, bound_divb_rel, bound_divb_abs)
-        a.vlbm_moments(out=Xr[j])
-        b.vlbm_init_fields(Xr[j])
-        b.vlbm_step(1)
-        b.vlbm_moments(out=Cst)
-        N.vlbm_restrict(X[n + 1], 1, Yr[j], rz=1, minus=Cst, stream=s)  # r = 1: X[n+1] - C(Xt)
-        if log and (j + 1) % 100 == 0:
-            log(f"rollout pairs: {j + 1}/{len(idx)} ({time.perf_counter() - t0:.1f} s)")
-    torch.cuda.synchronize()
-    a.vlbm_destroy()
-    b.vlbm_destroy()
-    return Xr, Yr
 
 
 def _divc_l2(F):
@@ -183,43 +154,38 @@ def field_errors(Q, R):
 
 def evaluate(net, seeds, n_fine, r, coarse_steps, workload, make_state, bound_corr, bound_divb_rel, bound_divb_abs,
              kmax=16, checkpoints=5, storage="f32", log=None):
-    """Coarse plain VLBM, the corrected coarse run and its base operator alone (every
-    step restarted from the equilibrium of its moments, no correction), each scored
-    against the restricted fine run."""
+    """Coarse plain VLBM vs the corrected coarse run, both scored against the restricted
+    fine run."""
     torch = _torch()
     s = torch.cuda.current_stream().cuda_stream
     B, nc = len(seeds), n_fine // r
     fine = make_context((n_fine, n_fine), B, storage, workload, s)
     plain = make_context((nc, nc), B, storage, workload, s)
     learned = make_context((nc, nc), B, storage, workload, s)
-    base = make_context((nc, nc), B, storage, workload, s)
     fine.vlbm_init_fields(torch.from_numpy(initial_batch(seeds, n_fine, kmax, make_state)).cuda())
     M = torch.empty((8, B, n_fine, n_fine), dtype=torch.float32, device="cuda")
     Rf = torch.empty((8, B, nc, nc), dtype=torch.float32, device="cuda")
     fine.vlbm_moments(out=M)
     N.vlbm_restrict(M, r, Rf, rz=1, stream=s)
-    for ctx in (plain, learned, base):
+    for ctx in (plain, learned):
         ctx.vlbm_init_fields(Rf)
     chunk = coarse_steps // checkpoints
     hist, fallbacks = [], 0
-    zero = np.zeros(8)
     for c in range(checkpoints):
         fine.vlbm_step(r * chunk)
         plain.vlbm_step(chunk)
         fallbacks += N.vlbm_step_corrected(learned, net, chunk, bound_corr, bound_divb_rel, bound_divb_abs)
-        N.vlbm_step_corrected(base, net, chunk, zero, 0.0, 0.0)
         fine.vlbm_moments(out=M)
         N.vlbm_restrict(M, r, Rf, rz=1, stream=s)
         ref = Rf.cpu().numpy().astype(np.float64)
         err = {}
-        for name, ctx in (("plain", plain), ("learned", learned), ("base", base)):
+        for name, ctx in (("plain", plain), ("learned", learned)):
             q, _ = ctx.vlbm_moments(raise_nonfinite=False)
             err[name] = field_errors(q.reshape(ref.shape), ref)
         hist.append(dict(coarse_step=(c + 1) * chunk, **err))
         if log:
-            log(f"eval step {(c + 1) * chunk}: plain {err['plain']} learned {err['learned']} "
-                f"base {err['base']} fallbacks {fallbacks}")
-    for ctx in (fine, plain, learned, base):
+            log(f"eval step {(c + 1) * chunk}: plain {err['plain']} learned {err['learned']} fallbacks {fallbacks}")
+    for ctx in (fine, plain, learned):
         ctx.vlbm_destroy()
     return hist, fallbacks
 

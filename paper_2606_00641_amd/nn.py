@@ -28,6 +28,7 @@ _sigs = {
                       ctypes.c_int32, _vp, _vp, _vp],
     "vlbm_step_corrected": [_vp, _vp, ctypes.c_int32, _dp, ctypes.c_double, ctypes.c_double,
                             ctypes.POINTER(ctypes.c_int64)],
+    "vlbm_inject": [_vp, _vp],
 }
 for _name, _args in _sigs.items():
     _fn = getattr(_lib, _name)
@@ -146,3 +147,12 @@ def vlbm_step_corrected(sim, net, n, bound_corr, bound_divb_rel, bound_divb_abs=
         msg = _lib.vlbm_nn_last_error(net.h)
         raise _v.VlbmError(st, msg.decode() if msg else "")
     return nfb.value
+
+
+def vlbm_inject(sim, dQ):
+    """f += w_i dQ_k on the context `sim` (a vlbm.Vlbm) at its current step; dQ: torch
+    FP32 device tensor [8, nz, ny, nx]."""
+    st = _lib.vlbm_inject(sim.ctx, _dev(dQ))
+    if st != _v.VLBM_OK:
+        raise _v.VlbmError(st, "vlbm_inject: needs an initialised 2D ideal-MHD FP32/FP64 context")
+

@@ -30,10 +30,6 @@ def main():
     ap.add_argument("--iters", type=int, default=3000)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--quick", action="store_true", help="small sizes (smoke)")
-    ap.add_argument("--rollout", type=int, nargs="*", default=[4, 16],
-                    help="corrected steps of each rollout-pair round")
-    ap.add_argument("--rollout-stride", type=int, default=2)
-    ap.add_argument("--iters-rollout", type=int, default=1500)
     args = ap.parse_args()
     import torch
     import synth
@@ -57,17 +53,6 @@ def main():
     net.vlbm_nn_set_weights(Lr.init_weights(seed=0))
     net.vlbm_nn_set_norm(in_mean, in_std, out_mean, out_std)
     losses, t_train = Lr.train(net, X, Y, args.iters, args.lr, seed=0, log=log)
-    bound_train = 5.0 * y_l2 * np.sqrt(len(seeds))
-    for rnd, m in enumerate(args.rollout):
-        # pairs on the corrected run's own drifted states, added to the training set
-        t0 = time.perf_counter()
-        Xr, Yr = Lr.rollout_pairs(net, X, m, w, bound_train, 0.1, b_abs, stride=args.rollout_stride, log=log)
-        X, Y = torch.cat([X, Xr]), torch.cat([Y, Yr])
-        del Xr, Yr
-        log(f"rollout round {rnd + 1} (m = {m}): {X.shape[0]} pairs, {time.perf_counter() - t0:.1f} s")
-        more, t_more = Lr.train(net, X, Y, args.iters_rollout, args.lr * 0.5, seed=rnd + 1, log=log)
-        losses += [(args.iters + rnd * args.iters_rollout + it, l) for it, l in more]
-        t_train += t_more + time.perf_counter() - t0
     del X, Y
     torch.cuda.empty_cache()
     bound = 5.0 * y_l2 * np.sqrt(len(eval_seeds))
@@ -81,7 +66,6 @@ def main():
         train_seeds=[seeds[0], seeds[-1]], pairs=pairs * len(seeds), eval_seeds=eval_seeds, coarse_steps=steps,
         network="4 x conv3x3, 8-32-32-32-8, GELU, BF16 MFMA / FP32 accumulate, Adam lr %g, %d iterations (batch %d lattices)"
                 % (args.lr, args.iters, len(seeds)),
-        rollout_rounds=dict(m=args.rollout, stride=args.rollout_stride, iters=args.iters_rollout, lr=args.lr * 0.5),
         time_pairs_s=round(t_pairs, 2), time_train_s=round(t_train, 2), losses=losses,
         bound_corr=list(map(float, bound)), bound_divb_rel=0.1, bound_divb_abs=b_abs, history=hist, fallbacks=nfb,
         wall_fine_s=round(t_fine, 4), wall_learned_coarse_s=round(t_learned, 4),

@@ -70,6 +70,8 @@ class vlbm_params(ctypes.Structure):
         ("body_b", ctypes.c_double * 4),
         ("body_e", (ctypes.c_double * 3) * 4),
         ("body_m", ctypes.c_double * 3),
+        ("collision", ctypes.c_int32),
+        ("trt_magic", ctypes.c_double),
     ]
 
 
@@ -133,7 +135,7 @@ def _is_torch(x):
 def make_params(lattice="D2Q5", shape=(64, 64, 1), model="ideal", storage="f32", gamma=5.0 / 3.0,
                 flux_scale=0.2, tau=0.6, powell=True, divb_mode=0, dt=0.0, mu=0.0, eta0=0.0,
                 j_c=0.0, tau_M=1.0, tau_H=1.0, w0=0.0, bc=None, inflow_Q=None, scale=None,
-                stream=None, block_x=0, body=None):
+                stream=None, block_x=0, body=None, collision="bgk", trt_magic=0.25):
     p = vlbm_params()
     _check(_lib.vlbm_params_default(ctypes.byref(p)))
     p.lattice = VLBM_D3Q7 if str(lattice).upper() == "D3Q7" else VLBM_D2Q5
@@ -161,6 +163,8 @@ def make_params(lattice="D2Q5", shape=(64, 64, 1), model="ideal", storage="f32",
             p.scale[k] = float(v)
     p.stream = stream
     p.block_x = int(block_x)
+    p.collision = {"bgk": 0, "trt": 1, "rlb": 2}[collision] if isinstance(collision, str) else int(collision)
+    p.trt_magic = float(trt_magic)
     if body is not None:
         p.body = int(body.get("mode", 1))
         for a in range(3):
