@@ -164,6 +164,18 @@ void body_box(vlbm_ctx* c, double t0, double t1, int (&box)[6]) {
   }
 }
 
+// Homogenized body at time t: the box of cells within the surface-radius bound plus
+// one cell (porosity below 1 possible only there), clipped to the domain.
+void hlbm_box(vlbm_ctx* c, double t, int (&box)[6]) {
+  const int n[3] = {c->p.nx, c->p.ny, c->p.nz};
+  for (int a = 0; a < 3; ++a) {
+    const double p0 = c->body.c0[a] + t * c->body.v[a];
+    const double lo = std::floor(p0 - c->body_rmax) - 1.0, hi = std::ceil(p0 + c->body_rmax) + 2.0;
+    box[2 * a] = (int)std::max(0.0, std::min((double)n[a], lo));
+    box[2 * a + 1] = (int)std::max(0.0, std::min((double)n[a], hi));
+  }
+}
+
 // Mask of the whole lattice at the current step (after init or a restore).
 hipError_t body_mask_full(vlbm_ctx* c) {
   Body b = c->body;
@@ -451,6 +463,7 @@ vlbm_status vlbm_step(vlbm_ctx* c, int32_t n) {
     }
     Body b = c->body;
     b.t = (double)c->step;
+    if (c->p.body == 2) hlbm_box(c, b.t, b.box);
     hipError_t e = launch_sweep_body(c->L, c->g, c->ph, c->cd, par, b, c->p.body);
     if (e != hipSuccess) return hip_fail(c, e, "sweep launch");
     ++c->step;

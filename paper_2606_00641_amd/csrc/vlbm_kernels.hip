@@ -123,13 +123,14 @@ __device__ __forceinline__ VLBM_GLOBAL char* plane_base(void* base, size_t plane
   const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
   return (VLBM_GLOBAL char*)(((unsigned long long)hi << 32) | lo);
 }
+// Loads and stores are nontemporal: every population is read once and written once
+// per sweep, and keeping the streams out of the caches measurably raised the sweep's
+// bandwidth on gfx950 (stores: +3 %; loads, on top: +4 % on the 26-variable FP32
+// sweep, +7 % FP32 / +14 % FP16 on the 8-variable sweep).
 template <typename T>
 __device__ __forceinline__ T ld(void* base, size_t plane_bytes, int plane, unsigned off) {
-  return *(const VLBM_GLOBAL T*)(plane_base(base, plane_bytes, plane) + off);
+  return __builtin_nontemporal_load((const VLBM_GLOBAL T*)(plane_base(base, plane_bytes, plane) + off));
 }
-// Stores are nontemporal: the written populations are not read again before the
-// next sweep, and keeping them out of the caches measurably raised the sweep's
-// bandwidth on gfx950.
 template <typename T>
 __device__ __forceinline__ void st(void* base, size_t plane_bytes, int plane, unsigned off, T v) {
   __builtin_nontemporal_store(v, (VLBM_GLOBAL T*)(plane_base(base, plane_bytes, plane) + off));
@@ -263,9 +264,21 @@ __global__ __launch_bounds__(256) void k_sweep(const Grid g, const Phys ph, cons
   constexpr int NQ = 2 * D + 1;
   constexpr int K = MODEL ? 26 : 8;
   constexpr unsigned ES = sizeof(T);
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= g.nx) return;
-  const int y = blockIdx.y, z = blockIdx.z;
+  // BODY 2 runs over the body's box only (grid = box extent, offset by its corner);
+  // BODY 3 is the plain sweep of every other cell.
+  int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+  if constexpr (BODY == 2) {
+    x += bd.box[0];
+    y += bd.box[2];
+    z += bd.box[4];
+    if (x >= bd.box[1]) return;
+  } else {
+    if (x >= g.nx) return;
+  }
+  if constexpr (BODY == 3) {
+    if (x >= bd.box[0] && x < bd.box[1] && y >= bd.box[2] && y < bd.box[3] && z >= bd.box[4] && z < bd.box[5])
+      return;
+  }
   const unsigned c = (unsigned)x + (unsigned)g.nx * ((unsigned)y + (unsigned)g.ny * (unsigned)z);
   void* const F = g.f;
   const size_t pb = (size_t)g.stride * ES;
@@ -794,18 +807,38 @@ hipError_t boundary_t(const Launch& L, const Grid& g, const Phys& ph, const Code
     const long long area = std::max({(long long)g.ny * g.nz, (long long)g.nx * g.nz, (long long)g.nx * g.ny});
     hipLaunchKernelGGL((k_faces<ST>), dim3((unsigned)((area + 255) / 256), 1, 6), dim3(256), 0, L.stream, g, ph,
                        cd, parity, *in);
-  } else if (what == 1 || what == 3) {  // sweep with the bounce-back (1) or homogenized (3) body
+  } else if (what == 1) {  // sweep with the bounce-back body
     const dim3 grd = cell_grid(g, L.block_x), blk(L.block_x);
-    const int key = (what == 3 ? 4 : 0) + (ph.collision ? 2 : 0) + parity;
-    switch (key) {
+    switch ((ph.collision ? 2 : 0) + parity) {
       case 0: hipLaunchKernelGGL((k_sweep<ST, 3, 0, 0, 1, 0>), grd, blk, 0, L.stream, g, ph, cd, *b); break;
       case 1: hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 1, 0>), grd, blk, 0, L.stream, g, ph, cd, *b); break;
       case 2: hipLaunchKernelGGL((k_sweep<ST, 3, 0, 0, 1, 1>), grd, blk, 0, L.stream, g, ph, cd, *b); break;
-      case 3: hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 1, 1>), grd, blk, 0, L.stream, g, ph, cd, *b); break;
-      case 4: hipLaunchKernelGGL((k_sweep<ST, 3, 0, 0, 2, 0>), grd, blk, 0, L.stream, g, ph, cd, *b); break;
-      case 5: hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 2, 0>), grd, blk, 0, L.stream, g, ph, cd, *b); break;
-      case 6: hipLaunchKernelGGL((k_sweep<ST, 3, 0, 0, 2, 1>), grd, blk, 0, L.stream, g, ph, cd, *b); break;
-      default: hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 2, 1>), grd, blk, 0, L.stream, g, ph, cd, *b); break;
+      default: hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 1, 1>), grd, blk, 0, L.stream, g, ph, cd, *b); break;
+    }
+  } else if (what == 3) {
+    // homogenized body: the plain sweep outside the body's box, then the homogenized
+    // sweep of the box; the two update disjoint cells, each cell exactly once
+    const dim3 grd = cell_grid(g, L.block_x), blk(L.block_x);
+    const int bx = b->box[1] - b->box[0], by = b->box[3] - b->box[2], bz = b->box[5] - b->box[4];
+    const bool box = bx > 0 && by > 0 && bz > 0;
+    const dim3 bgrd((unsigned)((bx + L.block_x - 1) / L.block_x), (unsigned)by, (unsigned)bz);
+    switch ((ph.collision ? 2 : 0) + parity) {
+      case 0:
+        hipLaunchKernelGGL((k_sweep<ST, 3, 0, 0, 3, 0>), grd, blk, 0, L.stream, g, ph, cd, *b);
+        if (box) hipLaunchKernelGGL((k_sweep<ST, 3, 0, 0, 2, 0>), bgrd, blk, 0, L.stream, g, ph, cd, *b);
+        break;
+      case 1:
+        hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 3, 0>), grd, blk, 0, L.stream, g, ph, cd, *b);
+        if (box) hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 2, 0>), bgrd, blk, 0, L.stream, g, ph, cd, *b);
+        break;
+      case 2:
+        hipLaunchKernelGGL((k_sweep<ST, 3, 0, 0, 3, 1>), grd, blk, 0, L.stream, g, ph, cd, *b);
+        if (box) hipLaunchKernelGGL((k_sweep<ST, 3, 0, 0, 2, 1>), bgrd, blk, 0, L.stream, g, ph, cd, *b);
+        break;
+      default:
+        hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 3, 1>), grd, blk, 0, L.stream, g, ph, cd, *b);
+        if (box) hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 2, 1>), bgrd, blk, 0, L.stream, g, ph, cd, *b);
+        break;
     }
   } else {  // refill
     const long long n = (long long)(b->box[1] - b->box[0]) * (b->box[3] - b->box[2]) * (b->box[5] - b->box[4]);

@@ -10,7 +10,8 @@ Cases:
         CFL 0.1 and tau = 0.5075, to t = 0.5 (20000 steps), checkpoints at t = 0.125,
         0.25, 0.5.
 
-Usage: python -m paper_2606_00641_amd.study_precision --case slab|ot [--n N] [--out FILE]
+Usage: python -m paper_2606_00641_amd.study_precision --case slab|ot [--n N] [--collision bgk|trt|rlb]
+       [--tau TAU] [--out FILE]
 """
 import argparse
 import json
@@ -48,6 +49,8 @@ def main():
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--collision", choices=("bgk", "trt", "rlb"), default="bgk")
+    ap.add_argument("--tau", type=float, default=None)
     args = ap.parse_args()
     import torch
     import synth
@@ -65,19 +68,20 @@ def main():
         desc = f"3D ideal MHD slab (planar discontinuity, seed 2), {n}^3 periodic, D3Q7 x 8, s = {w['s']}, tau = {w['tau']}"
     else:
         n = args.n or 4000
-        w = synth.workload_orszag_tang_2d(n)
+        w = synth.workload_orszag_tang_2d(n, tau=args.tau)
         steps = args.steps or w["steps"]
         marks = [steps // 4, steps // 2, steps]
         Q0 = synth.orszag_tang_2d(n)
         lattice, shape = "D2Q5", (n, n, 1)
-        desc = f"compressible Orszag-Tang vortex, {n}^2 periodic, D2Q5 x 8, s = {w['s']}, tau = {w['tau']}"
+        desc = (f"compressible Orszag-Tang vortex, {n}^2 periodic, D2Q5 x 8, s = {w['s']}, tau = {w['tau']}, "
+                f"{args.collision.upper()} collision")
     log(desc)
     Qd = torch.from_numpy(np.ascontiguousarray(Q0)).cuda()
     del Q0
     sims = {}
     for st in FORMS:
         p = V.make_params(lattice=lattice, shape=shape, model="ideal", storage=st, gamma=w["gamma"], flux_scale=w["s"],
-                          tau=w["tau"], powell=w["powell"], stream=stream.cuda_stream)
+                          tau=w["tau"], powell=w["powell"], collision=args.collision, stream=stream.cuda_stream)
         sims[st] = V.Vlbm(p)
         sims[st].vlbm_init_fields(Qd)
     del Qd
@@ -116,7 +120,7 @@ def main():
     log(json.dumps(perf))
     res = dict(case=args.case, workload=desc, steps=steps, checkpoints=hist, throughput=perf,
                note="errors are per-field relative L2 against the FP64 GPU run of the same workload")
-    out = args.out or os.path.join(ROOT, "gpurun_out", f"precision_{args.case}.json")
+    out = args.out or os.path.join(ROOT, "gpurun_out", f"precision_{args.case}_{args.collision}.json")
     os.makedirs(os.path.dirname(out), exist_ok=True)
     with open(out, "w") as fh:
         json.dump(res, fh, indent=1)
