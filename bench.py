@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0  # dense BF16 matrix-core peak
 CSRC = os.path.join(ROOT, "paper_2606_00641_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
 
@@ -222,6 +223,17 @@ def main():
         del Qb
         torch.cuda.empty_cache()
 
+    network = None
+    if not args.no_forms:
+        # the learned correction's network (4 x conv3x3, 8-32-32-32-8) on its coarse
+        # training batch: 40 lattices of 256^2, BF16 MFMA with FP32 accumulation
+        from paper_2606_00641_amd import learned
+        network = learned.time_network(batch=40, n=256)
+        for k in network:
+            network[k]["frac_of_bf16_peak"] = round(network[k]["tflops"] / BF16_PEAK_TFLOPS, 4)
+        network["peak_TFLOPs_bf16_dense"] = BF16_PEAK_TFLOPS
+        log(f"network forward {network['forward']['tflops']} TFLOP/s, train step {network['train_step']['tflops']} TFLOP/s")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
@@ -262,6 +274,7 @@ def main():
         "cpu_baseline": cpu,
         "forms_slab_512": forms or None,
         "forms_body_768x384x384": body_forms or None,
+        "learned_network_40x256x256": network,
         "finite": r["finite"],
     }
     print(json.dumps(out), flush=True)

@@ -953,14 +953,22 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
   int* flag = nullptr;  // flag[0..1] ping-pong
   long long* fb = nullptr;
   double* gpart = nullptr;
+  hipStream_t cs = nullptr;  // the loop runs on its own stream, ordered after and before s
+  hipEvent_t ev = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
   const int gblk = (int)std::min<size_t>(256, (N + kGateThreads - 1) / kGateThreads);
   auto cleanup = [&]() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
     if (X) (void)hipFree(X);
     for (int j = 0; j < 2; ++j)
       if (dq[j]) (void)hipFree(dq[j]);
     if (flag) (void)hipFree(flag);
     if (fb) (void)hipFree(fb);
     if (gpart) (void)hipFree(gpart);
+    if (ev) (void)hipEventDestroy(ev);
+    if (cs) (void)hipStreamDestroy(cs);
   };
   hipError_t e = hipMalloc(&X, 8 * N * sizeof(float));
   if (e == hipSuccess) e = hipMalloc(&dq[0], 8 * N * sizeof(float));
@@ -968,44 +976,85 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
   if (e == hipSuccess) e = hipMalloc(&flag, 2 * sizeof(int));
   if (e == hipSuccess) e = hipMalloc(&fb, sizeof(long long));
   if (e == hipSuccess) e = hipMalloc(&gpart, (size_t)gblk * 12 * sizeof(double));
-  if (e == hipSuccess) e = hipMemsetAsync(flag, 0, 2 * sizeof(int), s);
-  if (e == hipSuccess) e = hipMemsetAsync(fb, 0, sizeof(long long), s);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(ev, s);
+  if (e == hipSuccess) e = hipStreamWaitEvent(cs, ev, 0);
+  if (e == hipSuccess) e = hipMemsetAsync(flag, 0, 2 * sizeof(int), cs);
+  if (e == hipSuccess) e = hipMemsetAsync(fb, 0, sizeof(long long), cs);
+  vlbm::Launch L = c->L;
+  L.stream = cs;
   const dim3 cgrid((unsigned)((N + 255) / 256)), cblk(256);
   int cur = 0;  // dq[cur], flag[cur]: the pending correction (not yet in the populations)
-  for (int32_t step = 0; step < n && e == hipSuccess; ++step) {
+  // one corrected step: moments (with the pending correction), network, gate, sweep
+  // injecting the pending correction.  Kernels only, so that it can be captured.
+  auto step = [&]() -> vlbm_status {
     const int par = (int)(c->step & 1);
     if (c->p.storage == VLBM_F32)
-      hipLaunchKernelGGL(k_moments_x<vlbm::ST_F32>, cgrid, cblk, 0, s, c->g, c->cd, par, dq[cur], flag + cur, X);
+      hipLaunchKernelGGL(k_moments_x<vlbm::ST_F32>, cgrid, cblk, 0, cs, c->g, c->cd, par, dq[cur], flag + cur, X);
     else
-      hipLaunchKernelGGL(k_moments_x<vlbm::ST_F64>, cgrid, cblk, 0, s, c->g, c->cd, par, dq[cur], flag + cur, X);
+      hipLaunchKernelGGL(k_moments_x<vlbm::ST_F64>, cgrid, cblk, 0, cs, c->g, c->cd, par, dq[cur], flag + cur, X);
     e = hipGetLastError();
-    if (e != hipSuccess) break;
-    st = forward(nn, X, c->p.nz, c->p.nx, c->p.ny, false, nn->d_norm + 24, nn->d_norm + 16, dq[1 - cur], s);
-    if (st != VLBM_OK) {
-      cleanup();
-      return st;
-    }
-    hipLaunchKernelGGL(k_gate_partials, dim3(gblk), dim3(kGateThreads), 0, s, X, dq[1 - cur], c->p.nx, c->p.ny,
+    if (e != hipSuccess) return VLBM_ERR_HIP;
+    vlbm_status fs = forward(nn, X, c->p.nz, c->p.nx, c->p.ny, false, nn->d_norm + 24, nn->d_norm + 16, dq[1 - cur], cs);
+    if (fs != VLBM_OK) return fs;
+    hipLaunchKernelGGL(k_gate_partials, dim3(gblk), dim3(kGateThreads), 0, cs, X, dq[1 - cur], c->p.nx, c->p.ny,
                        c->p.nz, gpart);
-    hipLaunchKernelGGL(k_gate_final, dim3(1), dim3(1), 0, s, gpart, gblk, gb, flag + (1 - cur), fb);
+    hipLaunchKernelGGL(k_gate_final, dim3(1), dim3(1), 0, cs, gpart, gblk, gb, flag + (1 - cur), fb);
     e = hipGetLastError();
-    if (e != hipSuccess) break;
-    e = vlbm::launch_sweep_inj(c->L, c->g, c->ph, c->cd, par, dq[cur], flag + cur);
+    if (e == hipSuccess) e = vlbm::launch_sweep_inj(L, c->g, c->ph, c->cd, par, dq[cur], flag + cur);
+    if (e != hipSuccess) return VLBM_ERR_HIP;
     ++c->step;
     cur = 1 - cur;
+    return VLBM_OK;
+  };
+  int32_t done = 0;
+  // two steps eagerly (they also size the network's workspace), then pairs of steps
+  // replayed from a captured graph: a pair returns parity and ping-pong slot to where
+  // they started, so one captured pair serves every later pair
+  for (; done < n && done < 2 && e == hipSuccess; ++done) {
+    st = step();
+    if (st != VLBM_OK) break;
+  }
+  if (st == VLBM_OK && e == hipSuccess && n - done >= 4) {
+    const long long step0 = c->step;
+    const int cur0 = cur;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+      const vlbm_status s1 = step();
+      const vlbm_status s2 = s1 == VLBM_OK ? step() : s1;
+      const hipError_t ce = hipStreamEndCapture(cs, &graph);
+      c->step = step0;  // the captured steps have not run
+      cur = cur0;
+      if (s2 == VLBM_OK && ce == hipSuccess && graph &&
+          hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+        exec = nullptr;
+      (void)hipGetLastError();  // a failed capture leaves the eager path below
+      e = hipSuccess;
+    }
+    if (exec)
+      for (; n - done >= 2; done += 2) {
+        e = hipGraphLaunch(exec, cs);
+        if (e != hipSuccess) break;
+        c->step += 2;
+      }
+  }
+  for (; st == VLBM_OK && done < n && e == hipSuccess; ++done) st = step();
+  if (st != VLBM_OK && e == hipSuccess) {
+    cleanup();
+    return st;
   }
   if (e == hipSuccess && n > 0) {
     // the last accepted correction goes into the populations
     const int par = (int)(c->step & 1);
     if (c->p.storage == VLBM_F32)
-      hipLaunchKernelGGL(k_inject<vlbm::ST_F32>, cgrid, cblk, 0, s, c->g, par, dq[cur], flag + cur, c->ph.wi);
+      hipLaunchKernelGGL(k_inject<vlbm::ST_F32>, cgrid, cblk, 0, cs, c->g, par, dq[cur], flag + cur, c->ph.wi);
     else
-      hipLaunchKernelGGL(k_inject<vlbm::ST_F64>, cgrid, cblk, 0, s, c->g, par, dq[cur], flag + cur, c->ph.wi);
+      hipLaunchKernelGGL(k_inject<vlbm::ST_F64>, cgrid, cblk, 0, cs, c->g, par, dq[cur], flag + cur, c->ph.wi);
     e = hipGetLastError();
   }
   long long nfb = 0;
-  if (e == hipSuccess) e = hipMemcpyAsync(&nfb, fb, sizeof nfb, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&nfb, fb, sizeof nfb, hipMemcpyDeviceToHost, cs);
+  if (e == hipSuccess) e = hipStreamSynchronize(cs);
   cleanup();
   if (e != hipSuccess)
     return nfail(nn, e == hipErrorOutOfMemory ? VLBM_ERR_OOM : VLBM_ERR_HIP, "corrected step: %s", hipGetErrorString(e));

@@ -220,3 +220,41 @@ def time_runs(net, n_fine, r, coarse_steps, workload, make_state, bound_corr, bo
     fine.vlbm_destroy()
     learned.vlbm_destroy()
     return t_fine, t_learned, nfb
+
+
+# flops per output pixel of the 8-32-32-32-8 network with 3x3 kernels
+FWD_FLOPS_PER_PIXEL = 2 * 9 * (8 * 32 + 32 * 32 + 32 * 32 + 32 * 8)
+# one training step: forward, input gradients of layers 2-4, weight gradients of all
+TRAIN_FLOPS_PER_PIXEL = 2 * FWD_FLOPS_PER_PIXEL + 2 * 9 * (32 * 32 + 32 * 32 + 32 * 8)
+
+
+def time_network(batch=40, n=256, reps=20, seed=0):
+    """Mean time of the network's forward pass and of one training step (loss,
+    gradients, Adam) on a batch of n x n lattices, from HIP events on the network's
+    stream; returns dict with ms and TFLOP/s (algorithmic flops of the 3x3 layers)."""
+    torch = _torch()
+    stream = torch.cuda.current_stream()
+    net = N.Net(8, 32, 4, stream=stream.cuda_stream)
+    net.vlbm_nn_set_weights(init_weights(seed=seed))
+    net.vlbm_nn_set_norm(np.zeros(8), np.ones(8), np.zeros(8), np.ones(8))
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    X = torch.randn((8, batch, n, n), generator=g, device="cuda", dtype=torch.float32)
+    T = torch.randn((8, batch, n, n), generator=g, device="cuda", dtype=torch.float32)
+    Y = torch.empty_like(X)
+    out = {}
+    for name, fn, fl in (("forward", lambda: net.vlbm_nn_forward(X, Y), FWD_FLOPS_PER_PIXEL),
+                         ("train_step", lambda: net.vlbm_nn_train_step(X, T, 1e-4), TRAIN_FLOPS_PER_PIXEL)):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = dict(ms=round(ms, 4), tflops=round(fl * batch * n * n / (ms * 1e-3) / 1e12, 2))
+    net.vlbm_nn_destroy()
+    return out
+
