@@ -136,25 +136,6 @@ __device__ __forceinline__ void st(void* base, size_t plane_bytes, int plane, un
   __builtin_nontemporal_store(v, (VLBM_GLOBAL T*)(plane_base(base, plane_bytes, plane) + off));
 }
 
-// Value of the lane below / above in the wavefront (64 lanes).  Only lanes whose
-// neighbour lane is a valid cell of the same row use the result.
-template <typename T>
-__device__ __forceinline__ T lane_up(T v) {
-  if constexpr (sizeof(T) == 2) {
-    return (T)__shfl_up((int)v, 1, 64);
-  } else {
-    return __shfl_up(v, 1, 64);
-  }
-}
-template <typename T>
-__device__ __forceinline__ T lane_down(T v) {
-  if constexpr (sizeof(T) == 2) {
-    return (T)__shfl_down((int)v, 1, 64);
-  } else {
-    return __shfl_down(v, 1, 64);
-  }
-}
-
 // Dipole field of the body at point q (cell coordinates) and time t.
 __device__ inline void dipole_at(const Body& b, const double (&q)[3], double t, double (&B)[3]) {
   double r[3];
@@ -285,35 +266,19 @@ __global__ __launch_bounds__(256) void k_sweep(const Grid g, const Phys ph, cons
   constexpr unsigned ES = sizeof(T);
   // BODY 2 runs over the body's box only (grid = box extent, offset by its corner);
   // BODY 3 is the plain sweep of every other cell.
-  //
-  // XSH (parity 1 without the link-wise body): the +-x populations are read from the
-  // neighbouring cells' slots and written into them, one element off the wavefront's
-  // alignment.  Instead each lane loads and stores the aligned element of its own
-  // cell and passes it to the lane that needs it; the lanes at the ends of a
-  // wavefront's run of cells load/store the one element beyond it themselves.  Every
-  // cell of the run therefore stays in the wavefront through the exchanges: a cell
-  // whose update belongs to the other kernel (BODY 3: inside the body's box) still
-  // takes part but stores nothing of its own (own = false).
-  constexpr bool XSH = PAR == 1 && BODY != 1;
-  const int lane = threadIdx.x & 63;
   int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
-  int xend = g.nx;  // end of the row's run of cells in this launch
   if constexpr (BODY == 2) {
     x += bd.box[0];
     y += bd.box[2];
     z += bd.box[4];
-    xend = bd.box[1];
+    if (x >= bd.box[1]) return;
+  } else {
+    if (x >= g.nx) return;
   }
-  if (x >= xend) return;
-  bool own = true;
   if constexpr (BODY == 3) {
-    own = !(x >= bd.box[0] && x < bd.box[1] && y >= bd.box[2] && y < bd.box[3] && z >= bd.box[4] && z < bd.box[5]);
-    if constexpr (!XSH) {
-      if (!own) return;
-    }
+    if (x >= bd.box[0] && x < bd.box[1] && y >= bd.box[2] && y < bd.box[3] && z >= bd.box[4] && z < bd.box[5])
+      return;
   }
-  // last cell of the wavefront's run in this row (the next lane is not a cell of it)
-  const bool run_end = lane == 63 || x + 1 >= xend;
   const unsigned c = (unsigned)x + (unsigned)g.nx * ((unsigned)y + (unsigned)g.ny * (unsigned)z);
   void* const F = g.f;
   const size_t pb = (size_t)g.stride * ES;
@@ -343,16 +308,6 @@ __global__ __launch_bounds__(256) void k_sweep(const Grid g, const Phys ph, cons
       T v;
       if constexpr (PAR == 0) {
         v = ld<T>(F, pb, k * NQ + i, co);
-      } else if (XSH && i == 1) {
-        // f_+x(x) sits in slot -x of cell x - 1: the lane below's aligned element
-        const T own_el = ld<T>(F, pb, k * NQ + 2, co);
-        v = lane_up(own_el);
-        if (lane == 0) v = ld<T>(F, pb, k * NQ + 2, nm[0]);
-      } else if (XSH && i == 2) {
-        // f_-x(x) sits in slot +x of cell x + 1: the lane above's aligned element
-        const T own_el = ld<T>(F, pb, k * NQ + 1, co);
-        v = lane_down(own_el);
-        if (run_end) v = ld<T>(F, pb, k * NQ + 1, np[0]);
       } else {
         // f_i(x) was written by cell x - e_i into its slot opposite(i)
         const unsigned src = (i == 0) ? co : ((i & 1) ? nm[(i - 1) >> 1] : np[(i - 1) >> 1]);
@@ -386,8 +341,6 @@ __global__ __launch_bounds__(256) void k_sweep(const Grid g, const Phys ph, cons
     } else {
       collide<R, D, MODEL, COLL>(f, ph, dl);
     }
-    const bool own_below = XSH ? (bool)__shfl_up((int)own, 1, 64) : true;
-    const bool own_above = XSH ? (bool)__shfl_down((int)own, 1, 64) : true;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
 #pragma unroll
@@ -395,17 +348,7 @@ __global__ __launch_bounds__(256) void k_sweep(const Grid g, const Phys ph, cons
         const T v = S::enc(f[k][i], cd, k * NQ + i);
         if constexpr (PAR == 0) {
           st<T>(F, pb, k * NQ + opposite(i), co, v);
-        } else if (XSH && i == 1) {
-          // f*_+x goes to slot +x of cell x + 1: the lane above stores it aligned
-          const T w = lane_up(v);
-          if (lane > 0 && own_below) st<T>(F, pb, k * NQ + 1, co, w);
-          if (own && run_end) st<T>(F, pb, k * NQ + 1, np[0], v);
-        } else if (XSH && i == 2) {
-          // f*_-x goes to slot -x of cell x - 1: the lane below stores it aligned
-          const T w = lane_down(v);
-          if (!run_end && own_above) st<T>(F, pb, k * NQ + 2, co, w);
-          if (own && lane == 0) st<T>(F, pb, k * NQ + 2, nm[0], v);
-        } else if (own) {
+        } else {
           const unsigned dst = (i == 0) ? co : ((i & 1) ? np[(i - 1) >> 1] : nm[(i - 1) >> 1]);
           st<T>(F, pb, k * NQ + i, dst, v);
         }
