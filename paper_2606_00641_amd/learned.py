@@ -43,8 +43,11 @@ def initial_batch(seeds, n, kmax, make_state):
     return np.ascontiguousarray(Q, dtype=np.float32)
 
 
-def generate_pairs(seeds, n_fine, r, pairs_per_seed, workload, make_state, kmax=16, storage="f32", log=None):
-    """Returns (X, Y) device tensors [P, 8, B, nc, nc] (channel-major per pair)."""
+def generate_pairs(seeds, n_fine, r, pairs_per_seed, workload, make_state, kmax=16, storage="f32", stride=1,
+                   log=None):
+    """Returns (X, Y) device tensors [P, 8, B, nc, nc] (channel-major per pair): every
+    `stride`-th pair of a run of pairs_per_seed * stride coarse steps, so that the
+    pairs span the horizon the corrected run is used over."""
     torch = _torch()
     s = torch.cuda.current_stream().cuda_stream
     B, nc = len(seeds), n_fine // r
@@ -55,21 +58,28 @@ def generate_pairs(seeds, n_fine, r, pairs_per_seed, workload, make_state, kmax=
     Cst = torch.empty((8, B, nc, nc), dtype=torch.float32, device="cuda")
     X = torch.empty((pairs_per_seed, 8, B, nc, nc), dtype=torch.float32, device="cuda")
     Y = torch.empty_like(X)
-    nxt = torch.empty((8, B, nc, nc), dtype=torch.float32, device="cuda")
+    cur = torch.empty((8, B, nc, nc), dtype=torch.float32, device="cuda")
+    nxt = torch.empty_like(cur)
+    tgt = torch.empty_like(cur)
     fine.vlbm_moments(out=M)
-    N.vlbm_restrict(M, r, X[0], rz=1, stream=s)
-    coarse.vlbm_init_fields(X[0])
+    N.vlbm_restrict(M, r, cur, rz=1, stream=s)
+    coarse.vlbm_init_fields(cur)
     t0 = time.perf_counter()
-    for n in range(pairs_per_seed):
+    for n in range(pairs_per_seed * stride):
         coarse.vlbm_step(1)
         coarse.vlbm_moments(out=Cst)
         fine.vlbm_step(r)
         fine.vlbm_moments(out=M)
-        N.vlbm_restrict(M, r, X[n + 1] if n + 1 < pairs_per_seed else nxt, rz=1, stream=s)
-        N.vlbm_restrict(M, r, Y[n], rz=1, minus=Cst, stream=s)
-        N.vlbm_inject(coarse, Y[n])  # teacher forcing: the coarse moments become X[n + 1]
-        if log and (n + 1) % 100 == 0:
-            log(f"pairs: {n + 1}/{pairs_per_seed} steps x {B} seeds, {time.perf_counter() - t0:.1f} s")
+        N.vlbm_restrict(M, r, nxt, rz=1, stream=s)
+        N.vlbm_restrict(M, r, tgt, rz=1, minus=Cst, stream=s)
+        N.vlbm_inject(coarse, tgt)  # teacher forcing: the coarse moments become nxt
+        if n % stride == 0:
+            X[n // stride].copy_(cur)
+            Y[n // stride].copy_(tgt)
+        cur, nxt = nxt, cur
+        if log and (n + 1) % (100 * stride) == 0:
+            log(f"pairs: {(n + 1) // stride}/{pairs_per_seed} ({n + 1} coarse steps) x {B} seeds, "
+                f"{time.perf_counter() - t0:.1f} s")
     torch.cuda.synchronize()
     fine.vlbm_destroy()
     coarse.vlbm_destroy()

@@ -19,7 +19,7 @@ def test_learned_correction_beats_plain_coarse():
 
     w = synth.workload_fourier_2d()
     print("case learned pipeline 128^2 -> 32^2", flush=True)
-    X, Y = Lr.generate_pairs(list(range(100, 108)), 128, 4, 80, w, synth.fourier_2d, kmax=4)
+    X, Y = Lr.generate_pairs(list(range(100, 108)), 128, 4, 80, w, synth.fourier_2d, kmax=4, stride=3)
     in_mean, in_std, out_mean, out_std, y_l2, drift = Lr.normalisation(X, Y)
     net = N.Net(8, 32, 4, stream=torch.cuda.current_stream().cuda_stream)
     net.vlbm_nn_set_weights(Lr.init_weights(seed=0))
