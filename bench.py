@@ -145,14 +145,74 @@ def traffic_for(workload_key, storage):
     return rec["bytes_per_launch"]
 
 
+def run_slab(vlbm, torch, synth, form_steps):
+    """512^3 ideal-MHD slab in FP32, FP16 and BF16 storage."""
+    forms = {}
+    ws = synth.workload_slab_3d(n=512)
+    log("generating the 512^3 slab workload")
+    Qs = torch.from_numpy(synth.planar_discontinuity_3d(n=512, seed=2, dtype=np.float32)[0]).cuda()
+    for st in ("f32", "f16", "bf16"):
+        rr = time_sweep(vlbm, torch, ws, Qs, st, form_steps, 5)
+        m = rr["ncell"] * form_steps / rr["wall_s"] / 1e6
+        gb = rr["bytes_per_cell"] * rr["ncell"] / (rr["kernel_ms"] * 1e-3) / 1e9
+        forms[st] = dict(mlups=round(m, 1), kernel_ms=round(rr["kernel_ms"], 4),
+                         bytes_per_cell=rr["bytes_per_cell"], achieved_GBps=round(gb, 1),
+                         frac_of_peak=round(gb / HBM_PEAK_GBPS, 4), finite=rr["finite"])
+        log(f"slab 512^3 {st}: {m:.1f} MLUPS, {gb:.0f} GB/s")
+    del Qs
+    torch.cuda.empty_cache()
+    for st in ("f16", "bf16"):
+        forms[st]["speedup_vs_f32"] = round(forms[st]["mlups"] / forms["f32"]["mlups"], 3)
+    return forms
+
+
+def run_body(vlbm, torch, synth, form_steps):
+    """Flow past the moving magnetised body: 768 x 384 x 384, inflow / zero-gradient
+    faces, homogenized body, FP16 deviation storage next to FP32."""
+    body_forms = {}
+    shape = (768, 384, 384)
+    wb = synth.workload_body_3d(shape=shape)
+    Qin, info = synth.inflow_state()
+    wb["inflow_Q"] = Qin
+    wb["body"] = synth.body_params(shape=shape, B_in=float(np.linalg.norm(info["B"])))
+    log("generating the 768 x 384 x 384 body workload")
+    Qb = torch.from_numpy(synth.body_initial_state(shape, wb["body"], dtype=np.float32)).cuda()
+    for st in ("f16", "f32"):
+        rr = time_sweep(vlbm, torch, wb, Qb, st, form_steps, 5)
+        m = rr["ncell"] * form_steps / rr["wall_s"] / 1e6
+        gb = rr["bytes_per_cell"] * rr["ncell"] / (rr["kernel_ms"] * 1e-3) / 1e9
+        body_forms[st] = dict(mlups=round(m, 1), step_ms=round(rr["kernel_ms"], 4),
+                              bytes_per_cell=rr["bytes_per_cell"], achieved_GBps=round(gb, 1),
+                              frac_of_peak=round(gb / HBM_PEAK_GBPS, 4), finite=rr["finite"])
+        log(f"body 768x384x384 {st}: {m:.1f} MLUPS, {gb:.0f} GB/s")
+    body_forms["f16"]["speedup_vs_f32"] = round(body_forms["f16"]["mlups"] / body_forms["f32"]["mlups"], 3)
+    del Qb
+    torch.cuda.empty_cache()
+    return body_forms
+
+
+def run_network():
+    """The learned correction's network (4 x conv3x3, 8-32-32-32-8) on its coarse
+    training batch: 40 lattices of 256^2, BF16 MFMA with FP32 accumulation."""
+    from paper_2606_00641_amd import learned
+    network = learned.time_network(batch=40, n=256)
+    for k in network:
+        network[k]["frac_of_bf16_peak"] = round(network[k]["tflops"] / BF16_PEAK_TFLOPS, 4)
+    network["peak_TFLOPs_bf16_dense"] = BF16_PEAK_TFLOPS
+    log(f"network forward {network['forward']['tflops']} TFLOP/s, train step {network['train_step']['tflops']} TFLOP/s")
+    return network
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-forms", action="store_true", help="skip the FP32/FP16/BF16 slab forms")
+    ap.add_argument("--no-forms", action="store_true", help="skip the slab and body forms and the network timing")
     ap.add_argument("--form-steps", type=int, default=50)
+    ap.add_argument("--only", choices=("slab", "body", "network"), default=None,
+                    help="run one secondary part alone and print its result (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU slab "
@@ -165,7 +225,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    res = {}
+    if args.only:
+        part = {"slab": lambda: run_slab(vlbm, torch, synth, args.form_steps),
+                "body": lambda: run_body(vlbm, torch, synth, args.form_steps),
+                "network": run_network}[args.only]()
+        print(json.dumps({args.only: part}), flush=True)
+        return
 
     # --- main workload: 3D resistive MHD, 256^3, D3Q7 x 26, FP32 ------------------
     w = synth.workload_resistive_3d(n=256)
@@ -182,57 +247,9 @@ def main():
     copy_gbps = copy_bandwidth(vlbm, torch)
     log(f"copy kernel: {copy_gbps:.0f} GB/s")
 
-    forms = {}
-    if not args.no_forms:
-        ws = synth.workload_slab_3d(n=512)
-        log("generating the 512^3 slab workload")
-        Qs = torch.from_numpy(synth.planar_discontinuity_3d(n=512, seed=2, dtype=np.float32)[0]).cuda()
-        for st in ("f32", "f16", "bf16"):
-            rr = time_sweep(vlbm, torch, ws, Qs, st, args.form_steps, 5)
-            m = rr["ncell"] * args.form_steps / rr["wall_s"] / 1e6
-            gb = rr["bytes_per_cell"] * rr["ncell"] / (rr["kernel_ms"] * 1e-3) / 1e9
-            forms[st] = dict(mlups=round(m, 1), kernel_ms=round(rr["kernel_ms"], 4),
-                             bytes_per_cell=rr["bytes_per_cell"], achieved_GBps=round(gb, 1),
-                             frac_of_peak=round(gb / HBM_PEAK_GBPS, 4), finite=rr["finite"])
-            log(f"slab 512^3 {st}: {m:.1f} MLUPS, {gb:.0f} GB/s")
-        del Qs
-        torch.cuda.empty_cache()
-        for st in ("f16", "bf16"):
-            forms[st]["speedup_vs_f32"] = round(forms[st]["mlups"] / forms["f32"]["mlups"], 3)
-
-    body_forms = {}
-    if not args.no_forms:
-        # flow past the moving magnetised body: 768 x 384 x 384, inflow / zero-gradient
-        # faces, homogenized body, FP16 deviation storage next to FP32
-        shape = (768, 384, 384)
-        wb = synth.workload_body_3d(shape=shape)
-        Qin, info = synth.inflow_state()
-        wb["inflow_Q"] = Qin
-        wb["body"] = synth.body_params(shape=shape, B_in=float(np.linalg.norm(info["B"])))
-        log("generating the 768 x 384 x 384 body workload")
-        Qb = torch.from_numpy(synth.body_initial_state(shape, wb["body"], dtype=np.float32)).cuda()
-        for st in ("f16", "f32"):
-            rr = time_sweep(vlbm, torch, wb, Qb, st, args.form_steps, 5)
-            m = rr["ncell"] * args.form_steps / rr["wall_s"] / 1e6
-            gb = rr["bytes_per_cell"] * rr["ncell"] / (rr["kernel_ms"] * 1e-3) / 1e9
-            body_forms[st] = dict(mlups=round(m, 1), step_ms=round(rr["kernel_ms"], 4),
-                                  bytes_per_cell=rr["bytes_per_cell"], achieved_GBps=round(gb, 1),
-                                  frac_of_peak=round(gb / HBM_PEAK_GBPS, 4), finite=rr["finite"])
-            log(f"body 768x384x384 {st}: {m:.1f} MLUPS, {gb:.0f} GB/s")
-        body_forms["f16"]["speedup_vs_f32"] = round(body_forms["f16"]["mlups"] / body_forms["f32"]["mlups"], 3)
-        del Qb
-        torch.cuda.empty_cache()
-
-    network = None
-    if not args.no_forms:
-        # the learned correction's network (4 x conv3x3, 8-32-32-32-8) on its coarse
-        # training batch: 40 lattices of 256^2, BF16 MFMA with FP32 accumulation
-        from paper_2606_00641_amd import learned
-        network = learned.time_network(batch=40, n=256)
-        for k in network:
-            network[k]["frac_of_bf16_peak"] = round(network[k]["tflops"] / BF16_PEAK_TFLOPS, 4)
-        network["peak_TFLOPs_bf16_dense"] = BF16_PEAK_TFLOPS
-        log(f"network forward {network['forward']['tflops']} TFLOP/s, train step {network['train_step']['tflops']} TFLOP/s")
+    forms = run_slab(vlbm, torch, synth, args.form_steps) if not args.no_forms else {}
+    body_forms = run_body(vlbm, torch, synth, args.form_steps) if not args.no_forms else {}
+    network = run_network() if not args.no_forms else None
 
     cpu = None
     if not args.no_cpu_baseline:

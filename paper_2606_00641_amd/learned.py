@@ -44,10 +44,14 @@ def initial_batch(seeds, n, kmax, make_state):
 
 
 def generate_pairs(seeds, n_fine, r, pairs_per_seed, workload, make_state, kmax=16, storage="f32", stride=1,
-                   log=None):
+                   noise=0.0, seed=0, log=None):
     """Returns (X, Y) device tensors [P, 8, B, nc, nc] (channel-major per pair): every
     `stride`-th pair of a run of pairs_per_seed * stride coarse steps, so that the
-    pairs span the horizon the corrected run is used over."""
+    pairs span the horizon the corrected run is used over.  noise > 0: before a
+    stored pair's coarse step the teacher-forced state is perturbed by Gaussian noise
+    of noise x the initial per-channel spread, and the target still leads to the
+    restricted fine state -- the network then also learns to pull a drifted coarse
+    state back (the coarse run continues from the true state)."""
     torch = _torch()
     s = torch.cuda.current_stream().cuda_stream
     B, nc = len(seeds), n_fine // r
@@ -64,8 +68,17 @@ def generate_pairs(seeds, n_fine, r, pairs_per_seed, workload, make_state, kmax=
     fine.vlbm_moments(out=M)
     N.vlbm_restrict(M, r, cur, rz=1, stream=s)
     coarse.vlbm_init_fields(cur)
+    spread = cur.std(dim=(1, 2, 3), keepdim=True)  # per channel, of the initial state
+    gen = torch.Generator(device="cuda").manual_seed(seed)
+    eps = torch.empty_like(cur)
     t0 = time.perf_counter()
     for n in range(pairs_per_seed * stride):
+        stored = n % stride == 0
+        if noise > 0.0 and stored:
+            torch.randn(eps.shape, generator=gen, device="cuda", out=eps)
+            eps.mul_(spread * noise)
+            N.vlbm_inject(coarse, eps)  # the coarse moments become cur + eps
+            cur.add_(eps)
         coarse.vlbm_step(1)
         coarse.vlbm_moments(out=Cst)
         fine.vlbm_step(r)
@@ -73,7 +86,7 @@ def generate_pairs(seeds, n_fine, r, pairs_per_seed, workload, make_state, kmax=
         N.vlbm_restrict(M, r, nxt, rz=1, stream=s)
         N.vlbm_restrict(M, r, tgt, rz=1, minus=Cst, stream=s)
         N.vlbm_inject(coarse, tgt)  # teacher forcing: the coarse moments become nxt
-        if n % stride == 0:
+        if stored:
             X[n // stride].copy_(cur)
             Y[n // stride].copy_(tgt)
         cur, nxt = nxt, cur

@@ -30,6 +30,8 @@ def main():
     ap.add_argument("--iters", type=int, default=3000)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--quick", action="store_true", help="small sizes (smoke)")
+    ap.add_argument("--noise", type=float, default=0.0, help="relative noise on the stored pairs' inputs")
+    ap.add_argument("--stride", type=int, default=1, help="store every stride-th pair of the teacher-forced run")
     args = ap.parse_args()
     import torch
     import synth
@@ -41,11 +43,12 @@ def main():
         n_fine, seeds, pairs, eval_seeds, steps, kmax = 256, list(range(100, 108)), 100, [900, 901], 500, 4
     else:
         n_fine, seeds, pairs, eval_seeds, steps, kmax = 1024, list(range(100, 140)), 500, list(range(900, 910)), 5000, 16
-    stride = steps // pairs  # the pairs span the evaluated horizon
+    stride = args.stride
     r = 4
     w = synth.workload_fourier_2d()
     t0 = time.perf_counter()
-    X, Y = Lr.generate_pairs(seeds, n_fine, r, pairs, w, synth.fourier_2d, kmax=kmax, stride=stride, log=log)
+    X, Y = Lr.generate_pairs(seeds, n_fine, r, pairs, w, synth.fourier_2d, kmax=kmax, stride=stride,
+                             noise=args.noise, log=log)
     t_pairs = time.perf_counter() - t0
     log(f"{pairs * len(seeds)} pairs in {t_pairs:.1f} s")
     in_mean, in_std, out_mean, out_std, y_l2, drift = Lr.normalisation(X, Y)
@@ -64,7 +67,8 @@ def main():
     res = dict(
         workload=f"2D ideal MHD D2Q5 x 8, fine {n_fine}^2 -> coarse {n_fine // r}^2 (r = {r}), Fourier modes k <= {kmax}, "
                  f"tau = {w['tau']}, s = {w['s']}, FP32 storage",
-        train_seeds=[seeds[0], seeds[-1]], pairs=pairs * len(seeds), pair_stride=stride, eval_seeds=eval_seeds,
+        train_seeds=[seeds[0], seeds[-1]], pairs=pairs * len(seeds), pair_stride=stride, pair_noise=args.noise,
+        eval_seeds=eval_seeds,
         coarse_steps=steps,
         network="4 x conv3x3, 8-32-32-32-8, GELU, BF16 MFMA / FP32 accumulate, Adam lr %g, %d iterations (batch %d lattices)"
                 % (args.lr, args.iters, len(seeds)),
