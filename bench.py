@@ -36,7 +36,7 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-SWEEP_SOURCES = ("vlbm_kernels.h", "vlbm_kernels.hip", "vlbm_physics.h")
+SWEEP_SOURCES = ("vlbm_device.h", "vlbm_kernels.h", "vlbm_physics.h", "vlbm_sweep.hip")
 
 
 def kernel_source_hash():

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 OUT = os.path.join(PKG, "libvlbm.so")
-SOURCES = ["vlbm_kernels.hip", "vlbm_api.hip", "vlbm_nn.hip"]
+SOURCES = ["vlbm_sweep.hip", "vlbm_kernels.hip", "vlbm_api.hip", "vlbm_nn.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -1,5 +1,5 @@
-// Internal interface between the C ABI (vlbm_api.hip) and the kernels
-// (vlbm_kernels.hip).  Not installed; the public ABI is include/vlbm.h.
+// Internal interface between the C ABI (vlbm_api.hip) and the kernels (vlbm_sweep.hip,
+// vlbm_kernels.hip).  Not installed; the public ABI is include/vlbm.h.
 #pragma once
 
 #include <hip/hip_runtime.h>
