@@ -15,7 +15,6 @@ on the 512^3 ideal-MHD slab workload next to FP32, and the FP64 CPU oracle's
 throughput on a bounded sample of the same workload.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -31,22 +30,11 @@ BF16_PEAK_TFLOPS = 2500.0  # dense BF16 matrix-core peak
 CSRC = os.path.join(ROOT, "paper_2606_00641_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
 
+from paper_2606_00641_amd.pmc_traffic import kernel_source_hash  # noqa: E402
+
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
-
-
-SWEEP_SOURCES = ("vlbm_device.h", "vlbm_kernels.h", "vlbm_physics.h", "vlbm_sweep.hip")
-
-
-def kernel_source_hash():
-    """Hash of the sources the sweep kernel is built from."""
-    h = hashlib.sha256()
-    for name in SWEEP_SOURCES:
-        with open(os.path.join(CSRC, name), "rb") as fh:
-            h.update(name.encode())
-            h.update(fh.read())
-    return h.hexdigest()[:16]
 
 
 def params_for(vlbm, w, storage, stream):

@@ -25,8 +25,11 @@ namespace {
 // no other thread writes because the solid cell runs no update.
 // INJ: before the collision add *dqflag * w_i dq[k][c] to f_{k,i} (the pending learned
 // coarse correction, which shifts the zeroth moments by dq); dq is FP32 [K][N].
+// Occupancy: the FP32 26-variable sweep needs 256 VGPRs + 26 AGPRs at parity 0,
+// one wavefront per SIMD; bounding it to two per SIMD costs 48 B of scratch per lane
+// and was measured 4-5 % faster (at parity 1 the bound spills more and is slower).
 template <int ST, int D, int MODEL, int PAR, int BODY = 0, int COLL = 0, bool INJ = false>
-__global__ __launch_bounds__(256) void k_sweep(const Grid g, const Phys ph, const Codec cd,
+__global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COLL == 0) ? 2 : 1) void k_sweep(const Grid g, const Phys ph, const Codec cd,
                                                const Body bd = Body{}, const float* __restrict__ dq = nullptr,
                                                const int* __restrict__ dqflag = nullptr) {
   using S = Store<ST>;

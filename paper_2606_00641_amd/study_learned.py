@@ -32,6 +32,9 @@ def main():
     ap.add_argument("--quick", action="store_true", help="small sizes (smoke)")
     ap.add_argument("--noise", type=float, default=0.0, help="relative noise on the stored pairs' inputs")
     ap.add_argument("--stride", type=int, default=1, help="store every stride-th pair of the teacher-forced run")
+    ap.add_argument("--bound-factor", type=float, default=5.0,
+                    help="gate: fall back when a channel's correction norm exceeds this many times the RMS "
+                         "norm of the training targets")
     args = ap.parse_args()
     import torch
     import synth
@@ -59,10 +62,10 @@ def main():
     losses, t_train = Lr.train(net, X, Y, args.iters, args.lr, seed=0, log=log)
     del X, Y
     torch.cuda.empty_cache()
-    bound = 5.0 * y_l2 * np.sqrt(len(eval_seeds))
+    bound = args.bound_factor * y_l2 * np.sqrt(len(eval_seeds))
     hist, nfb = Lr.evaluate(net, eval_seeds, n_fine, r, steps, w, synth.fourier_2d, bound, 0.1, b_abs, kmax=kmax,
                             checkpoints=10, log=log)
-    t_fine, t_learned, nfb_t = Lr.time_runs(net, n_fine, r, steps, w, synth.fourier_2d, y_l2 * 5.0, 0.1, b_abs,
+    t_fine, t_learned, nfb_t = Lr.time_runs(net, n_fine, r, steps, w, synth.fourier_2d, y_l2 * args.bound_factor, 0.1, b_abs,
                                             kmax=kmax)
     res = dict(
         workload=f"2D ideal MHD D2Q5 x 8, fine {n_fine}^2 -> coarse {n_fine // r}^2 (r = {r}), Fourier modes k <= {kmax}, "
@@ -73,7 +76,7 @@ def main():
         network="4 x conv3x3, 8-32-32-32-8, GELU, BF16 MFMA / FP32 accumulate, Adam lr %g, %d iterations (batch %d lattices)"
                 % (args.lr, args.iters, len(seeds)),
         time_pairs_s=round(t_pairs, 2), time_train_s=round(t_train, 2), losses=losses,
-        bound_corr=list(map(float, bound)), bound_divb_rel=0.1, bound_divb_abs=b_abs, history=hist, fallbacks=nfb,
+        bound_factor=args.bound_factor, bound_corr=list(map(float, bound)), bound_divb_rel=0.1, bound_divb_abs=b_abs, history=hist, fallbacks=nfb,
         wall_fine_s=round(t_fine, 4), wall_learned_coarse_s=round(t_learned, 4),
         speedup_vs_fine=round(t_fine / t_learned, 2), fallbacks_timed_run=nfb_t)
     log(json.dumps({k: res[k] for k in ("speedup_vs_fine", "fallbacks", "wall_fine_s", "wall_learned_coarse_s")}))
