@@ -16,6 +16,57 @@
 namespace vlbm {
 namespace {
 
+// Lane shifts across the 64-lane wavefront (DPP wave_shr:1 / wave_shl:1):
+// lane_up(e, v) gives lane l the v of lane l - 1 and lane 0 its own e; lane_dn(e, v)
+// gives lane l the v of lane l + 1 and lane 63 its own e.  A lane that is inactive
+// at the shift is read as out of range (its neighbour gets e), so the shifts run with
+// every lane of the wavefront active.
+__device__ __forceinline__ unsigned up1(unsigned e, unsigned v) {
+  return __builtin_amdgcn_update_dpp((int)e, (int)v, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ unsigned dn1(unsigned e, unsigned v) {
+  return __builtin_amdgcn_update_dpp((int)e, (int)v, 0x130, 0xf, 0xf, false);
+}
+template <bool UP, typename T>
+__device__ __forceinline__ T lane_shift(T e, T v) {
+  auto sh = [](unsigned ee, unsigned vv) { return UP ? up1(ee, vv) : dn1(ee, vv); };
+  if constexpr (sizeof(T) == 8) {
+    const unsigned long long ue = __builtin_bit_cast(unsigned long long, e);
+    const unsigned long long uv = __builtin_bit_cast(unsigned long long, v);
+    const unsigned long long r = (unsigned long long)sh((unsigned)ue, (unsigned)uv) |
+                                 ((unsigned long long)sh((unsigned)(ue >> 32), (unsigned)(uv >> 32)) << 32);
+    return __builtin_bit_cast(T, r);
+  } else if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, sh(__builtin_bit_cast(unsigned, e), __builtin_bit_cast(unsigned, v)));
+  } else {
+    return (T)sh((unsigned)e, (unsigned)v);
+  }
+}
+
+// Wavefront-edge values of the x planes, exchanged through LDS (a workgroup has at
+// most 256 threads, four wavefronts); separate arrays for the pre- and post-collision
+// exchange, so that a wavefront writing the second never overwrites a value another
+// wavefront has yet to read from the first.
+constexpr int kMaxWaves = 4;
+template <typename T, int K, bool ON>
+struct XchLds {
+  T lo[2][kMaxWaves][K];  // lane 0's value of each wavefront
+  T hi[2][kMaxWaves][K];  // lane 63's value
+};
+template <typename T, int K>
+struct XchLds<T, K, false> {};
+
+// XCH (parity 1, plain sweep, workgroups tiling every x row exactly): the +-x
+// populations are read and written at the cell's own, aligned slots and passed
+// between neighbouring lanes instead of being accessed one element off the
+// wavefront's alignment.  Cell x needs f_{+x}(x) = slot(-x) of x - 1 and f_{-x}(x) =
+// slot(+x) of x + 1: each lane loads its own slots(-x) and (+x) and takes the values
+// of lanes l - 1 and l + 1; the post-collision f_{+x}(x) belongs to slot(+x) of
+// x + 1 and f_{-x}(x) to slot(-x) of x - 1, so each lane stores the values of lanes
+// l - 1 and l + 1 at its own slots.  Between wavefronts the edge values go through
+// LDS; at the ends of a workgroup that spans a whole row they wrap around the row
+// (periodic), else the end lanes read and write the neighbouring workgroup's cell
+// directly, one element each.
 // BODY (D3Q7 ideal): solid cells are skipped; a link i whose neighbour x + e_i is
 // solid returns the post-collision population into direction opposite(i) of the
 // same cell -- halfway bounce-back with the moving-wall flux correction for rho and
@@ -28,7 +79,7 @@ namespace {
 // Occupancy: the FP32 26-variable sweep needs 256 VGPRs + 26 AGPRs at parity 0,
 // one wavefront per SIMD; bounding it to two per SIMD costs 48 B of scratch per lane
 // and was measured 4-5 % faster (at parity 1 the bound spills more and is slower).
-template <int ST, int D, int MODEL, int PAR, int BODY = 0, int COLL = 0, bool INJ = false>
+template <int ST, int D, int MODEL, int PAR, int BODY = 0, int COLL = 0, bool INJ = false, bool XCH = false>
 __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COLL == 0) ? 2 : 1) void k_sweep(const Grid g, const Phys ph, const Codec cd,
                                                const Body bd = Body{}, const float* __restrict__ dq = nullptr,
                                                const int* __restrict__ dqflag = nullptr) {
@@ -38,6 +89,8 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
   constexpr int NQ = 2 * D + 1;
   constexpr int K = MODEL ? 26 : 8;
   constexpr unsigned ES = sizeof(T);
+  static_assert(!XCH || (PAR == 1 && BODY == 0), "lane exchange: plain sweep at parity 1");
+  __shared__ XchLds<T, K, XCH> xl;
   // BODY 2 runs over the body's box only (grid = box extent, offset by its corner);
   // BODY 3 is the plain sweep of every other cell.
   int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
@@ -75,6 +128,8 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
   const unsigned co = c * ES;
 
   R f[K][NQ];
+  T raw[XCH ? K : 1][2];
+  (void)raw;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
 #pragma unroll
@@ -82,12 +137,63 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
       T v;
       if constexpr (PAR == 0) {
         v = ld<T>(F, pb, k * NQ + i, co);
+      } else if constexpr (XCH) {
+        // i = 1, 2: this cell's own slot opposite(i), handed to the neighbour lane below
+        const unsigned src = (i <= 2) ? co : ((i & 1) ? nm[(i - 1) >> 1] : np[(i - 1) >> 1]);
+        v = ld<T>(F, pb, k * NQ + opposite(i), src);
       } else {
         // f_i(x) was written by cell x - e_i into its slot opposite(i)
         const unsigned src = (i == 0) ? co : ((i & 1) ? nm[(i - 1) >> 1] : np[(i - 1) >> 1]);
         v = ld<T>(F, pb, k * NQ + opposite(i), src);
       }
+      if constexpr (XCH) {
+        if (i == 1 || i == 2) {
+          raw[k][i - 1] = v;
+          continue;
+        }
+      }
       f[k][i] = S::dec(v, cd, k * NQ + i);
+    }
+  }
+  if constexpr (XCH) {
+    // raw[k][0] = slot(-x) of x (f_{+x} of x + 1), raw[k][1] = slot(+x) of x (f_{-x} of x - 1)
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = (int)(blockDim.x >> 6);
+    const bool row = (int)blockDim.x == g.nx;
+    if (lane == 63) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) xl.hi[0][w][k] = raw[k][0];
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) xl.lo[0][w][k] = raw[k][1];
+    }
+    __syncthreads();
+    // what lane 0 needs from the left and lane 63 from the right: another wavefront's
+    // edge value, or (ends of a workgroup that does not span the row) the
+    // neighbouring workgroup's cell, at a wavefront-uniform address
+    const unsigned rowc = (unsigned)g.nx * ((unsigned)y + (unsigned)g.ny * (unsigned)z);
+    const unsigned x0 = blockIdx.x * blockDim.x, x1 = x0 + blockDim.x;
+    const unsigned cl = (rowc + (x0 == 0 ? (unsigned)g.nx - 1u : x0 - 1u)) * ES;
+    const unsigned cr = (rowc + (x1 == (unsigned)g.nx ? 0u : x1)) * ES;
+    T el[K], er[K];
+    if (w > 0 || row) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) el[k] = xl.hi[0][w > 0 ? w - 1 : nw - 1][k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) el[k] = ld<T>(F, pb, k * NQ + 2, cl);
+    }
+    if (w < nw - 1 || row) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) er[k] = xl.lo[0][w < nw - 1 ? w + 1 : 0][k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) er[k] = ld<T>(F, pb, k * NQ + 1, cr);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      f[k][1] = S::dec(lane_shift<true>(el[k], raw[k][0]), cd, k * NQ + 1);
+      f[k][2] = S::dec(lane_shift<false>(er[k], raw[k][1]), cd, k * NQ + 2);
     }
   }
 
@@ -119,6 +225,9 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
     for (int k = 0; k < K; ++k) {
 #pragma unroll
       for (int i = 0; i < NQ; ++i) {
+        if constexpr (XCH) {
+          if (i == 1 || i == 2) continue;
+        }
         const T v = S::enc(f[k][i], cd, k * NQ + i);
         if constexpr (PAR == 0) {
           st<T>(F, pb, k * NQ + opposite(i), co, v);
@@ -126,6 +235,52 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
           const unsigned dst = (i == 0) ? co : ((i & 1) ? np[(i - 1) >> 1] : nm[(i - 1) >> 1]);
           st<T>(F, pb, k * NQ + i, dst, v);
         }
+      }
+    }
+    if constexpr (XCH) {
+      // post-collision f_{+x}(x) -> slot(+x) of x + 1, f_{-x}(x) -> slot(-x) of x - 1,
+      // each stored by the lane of that cell
+      const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = (int)(blockDim.x >> 6);
+      const bool row = (int)blockDim.x == g.nx;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        raw[k][0] = S::enc(f[k][1], cd, k * NQ + 1);
+        raw[k][1] = S::enc(f[k][2], cd, k * NQ + 2);
+      }
+      if (lane == 63) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) xl.hi[1][w][k] = raw[k][0];
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) xl.lo[1][w][k] = raw[k][1];
+      }
+      __syncthreads();
+      const int wl = w > 0 ? w - 1 : nw - 1, wr = w < nw - 1 ? w + 1 : 0;
+      // ends of a workgroup that does not span the row: its last lane writes slot(+x)
+      // of the next workgroup's first cell and its first lane slot(-x) of the previous
+      // workgroup's last cell, whose own lanes skip those slots
+      if (!row && t == (int)blockDim.x - 1) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) st<T>(F, pb, k * NQ + 1, np[0], raw[k][0]);
+      }
+      if (!row && t == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) st<T>(F, pb, k * NQ + 2, nm[0], raw[k][1]);
+      }
+      // the lane shifts read every lane, so they run with all lanes active
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        raw[k][0] = lane_shift<true>(xl.hi[1][wl][k], raw[k][0]);
+        raw[k][1] = lane_shift<false>(xl.lo[1][wr][k], raw[k][1]);
+      }
+      if (row || t != 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) st<T>(F, pb, k * NQ + 1, co, raw[k][0]);
+      }
+      if (row || t != (int)blockDim.x - 1) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) st<T>(F, pb, k * NQ + 2, co, raw[k][1]);
       }
     }
   } else {
@@ -179,14 +334,35 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
   }
 }
 
+// The parity-1 lane exchange needs every workgroup to cover whole wavefronts of one
+// x row (no partial workgroup, so that every lane reaches the barriers).  It is used
+// for the 8-variable sweeps (measured on 512^3: parity 1 11-20 % faster in FP32,
+// 12 % FP16, 10 % BF16); the 26-variable sweep runs one wavefront per SIMD, where the
+// workgroup barrier leaves the CU idle, and was 16 % slower with it.
+inline bool lane_exchange(const Grid& g, int block_x, int model) {
+  return model == 0 && block_x % 64 == 0 && g.nx % block_x == 0;
+}
+
 template <int ST, int D, int MODEL>
 hipError_t sweep_t(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity) {
   const dim3 grd = cell_grid(g, L.block_x), blk(L.block_x);
+  constexpr bool kX = MODEL == 0;
+  const bool xch = lane_exchange(g, L.block_x, MODEL);
   switch ((ph.collision ? 2 : 0) + parity) {
     case 0: hipLaunchKernelGGL((k_sweep<ST, D, MODEL, 0, 0, 0>), grd, blk, 0, L.stream, g, ph, cd); break;
-    case 1: hipLaunchKernelGGL((k_sweep<ST, D, MODEL, 1, 0, 0>), grd, blk, 0, L.stream, g, ph, cd); break;
+    case 1:
+      if (xch)
+        hipLaunchKernelGGL((k_sweep<ST, D, MODEL, 1, 0, 0, false, kX>), grd, blk, 0, L.stream, g, ph, cd);
+      else
+        hipLaunchKernelGGL((k_sweep<ST, D, MODEL, 1, 0, 0>), grd, blk, 0, L.stream, g, ph, cd);
+      break;
     case 2: hipLaunchKernelGGL((k_sweep<ST, D, MODEL, 0, 0, 1>), grd, blk, 0, L.stream, g, ph, cd); break;
-    default: hipLaunchKernelGGL((k_sweep<ST, D, MODEL, 1, 0, 1>), grd, blk, 0, L.stream, g, ph, cd); break;
+    default:
+      if (xch)
+        hipLaunchKernelGGL((k_sweep<ST, D, MODEL, 1, 0, 1, false, kX>), grd, blk, 0, L.stream, g, ph, cd);
+      else
+        hipLaunchKernelGGL((k_sweep<ST, D, MODEL, 1, 0, 1>), grd, blk, 0, L.stream, g, ph, cd);
+      break;
   }
   return hipGetLastError();
 }
@@ -197,6 +373,8 @@ hipError_t sweep_inj_t(const Launch& L, const Grid& g, const Phys& ph, const Cod
   const dim3 grd = cell_grid(g, L.block_x), blk(L.block_x);
   if (parity == 0)
     hipLaunchKernelGGL((k_sweep<ST, 2, 0, 0, 0, 0, true>), grd, blk, 0, L.stream, g, ph, cd, Body{}, dq, flag);
+  else if (lane_exchange(g, L.block_x, 0))
+    hipLaunchKernelGGL((k_sweep<ST, 2, 0, 1, 0, 0, true, true>), grd, blk, 0, L.stream, g, ph, cd, Body{}, dq, flag);
   else
     hipLaunchKernelGGL((k_sweep<ST, 2, 0, 1, 0, 0, true>), grd, blk, 0, L.stream, g, ph, cd, Body{}, dq, flag);
   return hipGetLastError();

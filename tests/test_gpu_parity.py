@@ -193,6 +193,61 @@ def test_block_sizes_bitwise_equal(vb):
         assert np.array_equal(b, bufs[0])
 
 
+# exchange vs oracle (FP64, FP32) and exchange vs direct path (every storage: the
+# rounding of one fused multiply-add, through the storage format's rounding)
+LANE_TOL = {"f64": 1e-10, "f32": 1e-5}
+LANE_VS_DIRECT = {"f64": 1e-13, "f32": 1e-6, "f16": 1e-3, "bf16": 1e-2}
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+@pytest.mark.parametrize("case", ["2d", "3d_ideal", "3d_resistive"])
+def test_lane_exchange(vb, storage, case):
+    """x rows that the workgroups tile exactly take the parity-1 lane exchange in the
+    8-variable sweeps (one workgroup per row, or several with single-element accesses
+    at their ends); a block shape that does not tile the row, and the 26-variable
+    sweep, take the direct neighbour accesses.  Every
+    tiling of the exchange gives identical bits; the exchange and the direct path are
+    the same arithmetic compiled into different kernels (the compiler may fuse a
+    multiply-add in one and not the other): they agree to that rounding, and the
+    exchange meets the oracle at the FP64 and FP32 bars (the storage forms are held
+    to the oracle on the direct path by the low-precision tests)."""
+    if case == "2d":
+        w = synth.workload_fourier_2d()
+        w["shape"] = (256, 6, 2)
+        Q0 = np.concatenate([synth.fourier_2d(256, seed=s)[:, :, :6, :] for s in (7, 8)], axis=1)
+        blocks, K = (64, 128, 256, 192), 8
+    elif case == "3d_ideal":
+        w = synth.workload_slab_3d()
+        w["shape"] = (256, 5, 4)
+        Q0, _ = synth.planar_discontinuity_3d(seed=4, shape=(4, 5, 256))
+        Q0 = boosted(Q0, (0.3, -0.2, 0.25))
+        blocks, K = (64, 128, 256, 192), 8
+    else:
+        w = synth.workload_resistive_3d(n=16, dt_over_tau_M=0.49)
+        w["shape"] = (128, 4, 3)
+        Q0 = small_resistive(shape=(128, 4, 3), seed=6)
+        blocks, K = (64, 128, 192), 26
+    Q0 = np.ascontiguousarray(Q0)
+    steps = 9
+    print("case lane exchange", case, storage, flush=True)
+    Qo, _ = run_oracle(w, Q0, steps)
+    bufs, Qs = [], []
+    for bx in blocks:
+        sim, Qg, _ = run_gpu(vb, w, Q0, steps, storage, block_x=bx)
+        bufs.append(sim.vlbm_get_populations()[0])
+        Qs.append(Qg)
+        sim.vlbm_destroy()
+        if storage in LANE_TOL:
+            err = rel_l2(Qg, Qo, K)
+            fam = ("rho", "m", "E", "B") if K == 26 and storage != "f64" else tuple(err)
+            assert max(err[k] for k in fam) <= LANE_TOL[storage], (bx, err)
+    for bx, b in zip(blocks[1:-1], bufs[1:-1]):
+        assert np.array_equal(b, bufs[0]), bx
+    d = rel_l2(Qs[0], Qs[-1], K)
+    fam = ("rho", "m", "E", "B") if K == 26 and storage != "f64" else tuple(d)
+    assert max(d[k] for k in fam) <= LANE_VS_DIRECT[storage], d
+
+
 # --- D3Q7 ideal and resistive, ragged boxes -------------------------------------
 
 def boosted(Q, u0, gamma=5.0 / 3.0):
