@@ -89,7 +89,7 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
   constexpr int NQ = 2 * D + 1;
   constexpr int K = MODEL ? 26 : 8;
   constexpr unsigned ES = sizeof(T);
-  static_assert(!XCH || (PAR == 1 && BODY == 0), "lane exchange: plain sweep at parity 1");
+  static_assert(!XCH || (PAR == 1 && (BODY == 0 || BODY == 3)), "lane exchange: plain sweep at parity 1");
   __shared__ XchLds<T, K, XCH> xl;
   // BODY 2 runs over the body's box only (grid = box extent, offset by its corner);
   // BODY 3 is the plain sweep of every other cell.
@@ -102,10 +102,24 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
   } else {
     if (x >= g.nx) return;
   }
+  // with the lane exchange, a cell of the body's box still takes part (its lane
+  // relays its own x slots to the neighbour lanes) but updates nothing
+  bool own = true, own_l = true, own_r = true;
   if constexpr (BODY == 3) {
-    if (x >= bd.box[0] && x < bd.box[1] && y >= bd.box[2] && y < bd.box[3] && z >= bd.box[4] && z < bd.box[5])
-      return;
+    auto in_box = [&](int xx) {
+      return xx >= bd.box[0] && xx < bd.box[1] && y >= bd.box[2] && y < bd.box[3] && z >= bd.box[4] && z < bd.box[5];
+    };
+    if constexpr (XCH) {
+      own = !in_box(x);
+      own_l = !in_box(x == 0 ? g.nx - 1 : x - 1);
+      own_r = !in_box(x + 1 == g.nx ? 0 : x + 1);
+    } else {
+      if (in_box(x)) return;
+    }
   }
+  (void)own;
+  (void)own_l;
+  (void)own_r;
   const unsigned c = (unsigned)x + (unsigned)g.nx * ((unsigned)y + (unsigned)g.ny * (unsigned)z);
   void* const F = g.f;
   const size_t pb = (size_t)g.stride * ES;
@@ -226,7 +240,7 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
 #pragma unroll
       for (int i = 0; i < NQ; ++i) {
         if constexpr (XCH) {
-          if (i == 1 || i == 2) continue;
+          if (i == 1 || i == 2 || !own) continue;
         }
         const T v = S::enc(f[k][i], cd, k * NQ + i);
         if constexpr (PAR == 0) {
@@ -260,11 +274,11 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
       // ends of a workgroup that does not span the row: its last lane writes slot(+x)
       // of the next workgroup's first cell and its first lane slot(-x) of the previous
       // workgroup's last cell, whose own lanes skip those slots
-      if (!row && t == (int)blockDim.x - 1) {
+      if (!row && own && t == (int)blockDim.x - 1) {
 #pragma unroll
         for (int k = 0; k < K; ++k) st<T>(F, pb, k * NQ + 1, np[0], raw[k][0]);
       }
-      if (!row && t == 0) {
+      if (!row && own && t == 0) {
 #pragma unroll
         for (int k = 0; k < K; ++k) st<T>(F, pb, k * NQ + 2, nm[0], raw[k][1]);
       }
@@ -274,11 +288,13 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
         raw[k][0] = lane_shift<true>(xl.hi[1][wl][k], raw[k][0]);
         raw[k][1] = lane_shift<false>(xl.lo[1][wr][k], raw[k][1]);
       }
-      if (row || t != 0) {
+      // slot(+x) takes the left neighbour's value, slot(-x) the right one's: stored
+      // only where that neighbour was updated here
+      if ((row || t != 0) && own_l) {
 #pragma unroll
         for (int k = 0; k < K; ++k) st<T>(F, pb, k * NQ + 1, co, raw[k][0]);
       }
-      if (row || t != (int)blockDim.x - 1) {
+      if ((row || t != (int)blockDim.x - 1) && own_r) {
 #pragma unroll
         for (int k = 0; k < K; ++k) st<T>(F, pb, k * NQ + 2, co, raw[k][1]);
       }
@@ -399,13 +415,17 @@ hipError_t sweep_body_t(const Launch& L, const Grid& g, const Phys& ph, const Co
     const int bx = b->box[1] - b->box[0], by = b->box[3] - b->box[2], bz = b->box[5] - b->box[4];
     const bool box = bx > 0 && by > 0 && bz > 0;
     const dim3 bgrd((unsigned)((bx + L.block_x - 1) / L.block_x), (unsigned)by, (unsigned)bz);
+    const bool xch = lane_exchange(g, L.block_x, 0);
     switch ((ph.collision ? 2 : 0) + parity) {
       case 0:
         hipLaunchKernelGGL((k_sweep<ST, 3, 0, 0, 3, 0>), grd, blk, 0, L.stream, g, ph, cd, *b);
         if (box) hipLaunchKernelGGL((k_sweep<ST, 3, 0, 0, 2, 0>), bgrd, blk, 0, L.stream, g, ph, cd, *b);
         break;
       case 1:
-        hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 3, 0>), grd, blk, 0, L.stream, g, ph, cd, *b);
+        if (xch)
+          hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 3, 0, false, true>), grd, blk, 0, L.stream, g, ph, cd, *b);
+        else
+          hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 3, 0>), grd, blk, 0, L.stream, g, ph, cd, *b);
         if (box) hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 2, 0>), bgrd, blk, 0, L.stream, g, ph, cd, *b);
         break;
       case 2:
@@ -413,7 +433,10 @@ hipError_t sweep_body_t(const Launch& L, const Grid& g, const Phys& ph, const Co
         if (box) hipLaunchKernelGGL((k_sweep<ST, 3, 0, 0, 2, 1>), bgrd, blk, 0, L.stream, g, ph, cd, *b);
         break;
       default:
-        hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 3, 1>), grd, blk, 0, L.stream, g, ph, cd, *b);
+        if (xch)
+          hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 3, 1, false, true>), grd, blk, 0, L.stream, g, ph, cd, *b);
+        else
+          hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 3, 1>), grd, blk, 0, L.stream, g, ph, cd, *b);
         if (box) hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 2, 1>), bgrd, blk, 0, L.stream, g, ph, cd, *b);
         break;
     }

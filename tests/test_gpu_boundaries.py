@@ -26,15 +26,15 @@ def _stream():
     return torch.cuda.current_stream().cuda_stream
 
 
-def _case(kind, mode=1):
+def _case(kind, mode=1, nx=None):
     """(shape (nx, ny, nz), Q0, inflow_Q, body, tau, s, steps); mode 1 bounce-back,
-    2 homogenized body."""
+    2 homogenized body; nx overrides the body box's x extent."""
     if kind == "faces":
         shape = (20, 12, 10)
         Q0 = synth.smooth_box_state(shape[::-1], seed=11)
         Qin, _ = synth.inflow_state(mach=1.2, alfven_mach=4.0)
         return shape, Q0, Qin, None, 0.7, 0.15, 30
-    shape = (30, 22, 20)
+    shape = (nx or 30, 22, 20)
     Qin, _ = synth.inflow_state(mach=0.8, alfven_mach=4.0)
     Q0 = np.broadcast_to(Qin[:, None, None, None], (8,) + shape[::-1]).copy()
     Q0 += 0.3 * (synth.smooth_box_state(shape[::-1], seed=12, amp=0.05, rho=0.0, p=0.0, B0=0.0))
@@ -43,11 +43,11 @@ def _case(kind, mode=1):
     return shape, Q0, Qin, body, 0.7, 0.1, 40
 
 
-def _run_pair(vb, kind, storage, bc, steps=None, mode=1):
-    shape, Q0, Qin, body, tau, s, n = _case(kind, mode)
+def _run_pair(vb, kind, storage, bc, steps=None, mode=1, nx=None, block_x=0):
+    shape, Q0, Qin, body, tau, s, n = _case(kind, mode, nx)
     n = steps or n
     p = vb.make_params(lattice="D3Q7", shape=shape, model="ideal", storage=storage, flux_scale=s, tau=tau,
-                       bc=bc, inflow_Q=Qin, body=body, stream=_stream())
+                       bc=bc, inflow_Q=Qin, body=body, stream=_stream(), block_x=block_x)
     sim = vb.Vlbm(p)
     sim.vlbm_init_fields(Q0)
     sim.vlbm_step(n)
@@ -161,3 +161,18 @@ def test_checkpoint_restart_with_body(vb, mode):
     qa, _ = a.vlbm_moments()
     qb, _ = b.vlbm_moments()
     assert np.array_equal(np.asarray(qa), np.asarray(qb))
+
+
+@pytest.mark.parametrize("block_x", [64, 128, 256])
+def test_homogenized_body_lane_exchange(vb, block_x):
+    """x rows of 128 cells: workgroups of 64 (two per row) and 128 (one per row) take
+    the parity-1 lane exchange around the body's box, 256 the direct accesses; every
+    cell matches the oracle in FP64, and FP32 agrees across the two paths."""
+    print("case body lane exchange", block_x, flush=True)
+    Qg, Qo, _, _ = _run_pair(vb, "body", "f64", (1, 2, 2, 2, 2, 2), steps=41, mode=2, nx=128, block_x=block_x)
+    err = rel_l2(Qg, Qo, 8)
+    assert max(err.values()) < 1e-10, err
+    a, _, _, _ = _run_pair(vb, "body", "f32", (1, 2, 2, 2, 2, 2), steps=41, mode=2, nx=128, block_x=block_x)
+    b, _, _, _ = _run_pair(vb, "body", "f32", (1, 2, 2, 2, 2, 2), steps=41, mode=2, nx=128, block_x=256)
+    d = rel_l2(a, b, 8)
+    assert max(d.values()) < 1e-6, d
