@@ -456,7 +456,7 @@ vlbm_status vlbm_step(vlbm_ctx* c, int32_t n) {
       if (e != hipSuccess) return hip_fail(c, e, "face launch");
     }
     if (!c->p.body) {
-      const hipError_t e = launch_sweep(c->L, c->g, c->ph, c->cd, par);
+      const hipError_t e = launch_sweep(c->L, c->g, c->ph, c->cd, par, c->inflow);
       if (e != hipSuccess) return hip_fail(c, e, "sweep launch");
       ++c->step;
       continue;
@@ -464,7 +464,7 @@ vlbm_status vlbm_step(vlbm_ctx* c, int32_t n) {
     Body b = c->body;
     b.t = (double)c->step;
     if (c->p.body == 2) hlbm_box(c, b.t, b.box);
-    hipError_t e = launch_sweep_body(c->L, c->g, c->ph, c->cd, par, b, c->p.body);
+    hipError_t e = launch_sweep_body(c->L, c->g, c->ph, c->cd, par, b, c->p.body, c->inflow);
     if (e != hipSuccess) return hip_fail(c, e, "sweep launch");
     ++c->step;
     if (c->p.body == 2) continue;  // the homogenized body needs no mask

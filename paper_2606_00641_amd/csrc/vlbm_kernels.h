@@ -55,13 +55,20 @@ struct Launch {
 
 // One sweep (collide + stream) at the given parity (0: natural layout in, swapped
 // out; 1: swapped in, natural out).
-hipError_t launch_sweep(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity);
+hipError_t launch_sweep(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
+                        const Inflow& in);
 
 // Static faces (D3Q7 ideal model): every node of a non-periodic face takes
 // f := f^eq(Q_bc) at the given parity, Q_bc the inflow state on inflow faces, else
 // the moments of the nearest cell that lies on no non-periodic face.
 hipError_t launch_faces(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
                         const Inflow& in);
+
+// The sweep itself re-sets the nodes of non-periodic x faces that lie on no other
+// non-periodic face (D3Q7 ideal); it takes the zero-gradient state from the
+// neighbouring lane, which holds cell x = 1 (x = nx - 2) unless nx - 1 starts a new
+// wavefront.  The face pass then handles the y and z faces only.
+__host__ __device__ inline bool fuse_x_faces(const Grid& g) { return g.bc[0] != 0 && g.nx % 64 != 1; }
 
 // Body mask in b.box at time b.t: pass 0 sets the solid bit (and keeps the old one
 // as kWasSolid unless `fresh`), pass 1 the link bits.
@@ -75,7 +82,7 @@ hipError_t launch_refill(const Launch& L, const Grid& g, const Phys& ph, const C
 // skipped and links into the body bounce back (moving wall, dipole field); mode 2:
 // every cell collides toward its homogenized state (porosity blending).
 hipError_t launch_sweep_body(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
-                             const Body& b, int mode);
+                             const Body& b, int mode, const Inflow& in);
 
 // Sweep of a 2D ideal-MHD BGK lattice (FP32 or FP64 storage) that first adds
 // *flag * w_i dq[k][c] to the gathered populations (dq FP32 [K][N], device).

@@ -71,7 +71,9 @@ __device__ inline void write_feq3(const Grid& g, const Phys& ph, const Codec& cd
 }
 
 // Static faces.  blockIdx.z is the face (2a + side); a thread per node of it.  A node
-// on several non-periodic faces is handled by each of them with identical values;
+// on several non-periodic faces is handled by each of them with identical values (the
+// x faces by the sweep itself where it can, see fuse_x_faces; their edges with the y
+// and z faces still here);
 // the cells read (no non-periodic face) and the populations written (face nodes
 // only) are disjoint.
 template <int ST>
@@ -80,6 +82,7 @@ __global__ __launch_bounds__(256) void k_faces(const Grid g, const Phys ph, cons
   using R = typename Store<ST>::R;
   const int f = blockIdx.z, a = f >> 1;
   if (g.bc[f] == 0) return;
+  if (a == 0 && fuse_x_faces(g)) return;  // the sweep re-sets these nodes
   const int n[3] = {g.nx, g.ny, g.nz};
   // the two other axes in increasing order, so that consecutive threads walk along x
   // (consecutive addresses) on the y and z faces

@@ -79,10 +79,11 @@ struct XchLds<T, K, false> {};
 // Occupancy: the FP32 26-variable sweep needs 256 VGPRs + 26 AGPRs at parity 0,
 // one wavefront per SIMD; bounding it to two per SIMD costs 48 B of scratch per lane
 // and was measured 4-5 % faster (at parity 1 the bound spills more and is slower).
-template <int ST, int D, int MODEL, int PAR, int BODY = 0, int COLL = 0, bool INJ = false, bool XCH = false>
-__global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COLL == 0) ? 2 : 1) void k_sweep(const Grid g, const Phys ph, const Codec cd,
-                                               const Body bd = Body{}, const float* __restrict__ dq = nullptr,
-                                               const int* __restrict__ dqflag = nullptr) {
+template <int ST, int D, int MODEL, int PAR, int BODY = 0, int COLL = 0, bool INJ = false, bool XCH = false,
+          bool FX = false>
+__global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COLL == 0) ? 2 : 1) void k_sweep(
+    const Grid g, const Phys ph, const Codec cd, const Body bd, const float* __restrict__ dq,
+    const int* __restrict__ dqflag, const Inflow in) {
   using S = Store<ST>;
   using T = typename S::T;
   using R = typename S::R;
@@ -90,6 +91,7 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
   constexpr int K = MODEL ? 26 : 8;
   constexpr unsigned ES = sizeof(T);
   static_assert(!XCH || (PAR == 1 && (BODY == 0 || BODY == 3)), "lane exchange: plain sweep at parity 1");
+  static_assert(!FX || (D == 3 && MODEL == 0 && BODY != 2 && !INJ), "x faces: D3Q7 ideal MHD");
   __shared__ XchLds<T, K, XCH> xl;
   // BODY 2 runs over the body's box only (grid = box extent, offset by its corner);
   // BODY 3 is the plain sweep of every other cell.
@@ -208,6 +210,47 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
     for (int k = 0; k < K; ++k) {
       f[k][1] = S::dec(lane_shift<true>(el[k], raw[k][0]), cd, k * NQ + 1);
       f[k][2] = S::dec(lane_shift<false>(er[k], raw[k][1]), cd, k * NQ + 2);
+    }
+  }
+
+  if constexpr (FX) {
+    // Static x faces (Sec. 2.4) inside the sweep: a node of a non-periodic x face
+    // that lies on no other non-periodic face takes f := f^eq(Q_bc) before it
+    // collides -- Q_bc the inflow state, or (zero gradient) the moments of its
+    // neighbour x +- 1 in the same row, which the neighbour lane holds.  This is what
+    // the separate face pass computes (same moment order, same storage rounding of
+    // f^eq) without its one-element-per-row accesses; the y and z faces, edges
+    // included, stay with that pass.
+    R q[8], ql[8], qr[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      R a = R(0);
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) a += f[k][i];
+      q[k] = a;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      ql[k] = lane_shift<true>(q[k], q[k]);   // moments of x - 1
+      qr[k] = lane_shift<false>(q[k], q[k]);  // moments of x + 1
+    }
+    const bool yin = g.bc[2] == 0 || (y > 0 && y < g.ny - 1);
+    const bool zin = g.bc[4] == 0 || (z > 0 && z < g.nz - 1);
+    const int side = x == 0 ? 0 : (x == g.nx - 1 ? 1 : -1);
+    if (side >= 0 && g.bc[side] != 0 && yin && zin) {
+      R Qb[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) Qb[k] = g.bc[side] == 1 ? R(in.q[k]) : (side == 0 ? qr[k] : ql[k]);
+      R Jb[3] = {R(0), R(0), R(0)};
+      R P[8][3], Sv[8], dlb;
+      flux_source<R, 3, 0>(Qb, Jb, ph, P, Sv, dlb);
+      const R wi = R(ph.wi);
+      const R w0 = rest_weight<R, 3>(wi);
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int i = 0; i < NQ; ++i)
+          f[k][i] = S::dec(S::enc(feq_dir<R, 3>(Qb[k], P[k], i, w0, wi), cd, k * NQ + i), cd, k * NQ + i);
     }
   }
 
@@ -359,86 +402,76 @@ inline bool lane_exchange(const Grid& g, int block_x, int model) {
   return model == 0 && block_x % 64 == 0 && g.nx % block_x == 0;
 }
 
-template <int ST, int D, int MODEL>
-hipError_t sweep_t(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity) {
-  const dim3 grd = cell_grid(g, L.block_x), blk(L.block_x);
-  constexpr bool kX = MODEL == 0;
-  const bool xch = lane_exchange(g, L.block_x, MODEL);
-  switch ((ph.collision ? 2 : 0) + parity) {
-    case 0: hipLaunchKernelGGL((k_sweep<ST, D, MODEL, 0, 0, 0>), grd, blk, 0, L.stream, g, ph, cd); break;
-    case 1:
-      if (xch)
-        hipLaunchKernelGGL((k_sweep<ST, D, MODEL, 1, 0, 0, false, kX>), grd, blk, 0, L.stream, g, ph, cd);
-      else
-        hipLaunchKernelGGL((k_sweep<ST, D, MODEL, 1, 0, 0>), grd, blk, 0, L.stream, g, ph, cd);
-      break;
-    case 2: hipLaunchKernelGGL((k_sweep<ST, D, MODEL, 0, 0, 1>), grd, blk, 0, L.stream, g, ph, cd); break;
-    default:
-      if (xch)
-        hipLaunchKernelGGL((k_sweep<ST, D, MODEL, 1, 0, 1, false, kX>), grd, blk, 0, L.stream, g, ph, cd);
-      else
-        hipLaunchKernelGGL((k_sweep<ST, D, MODEL, 1, 0, 1>), grd, blk, 0, L.stream, g, ph, cd);
-      break;
+// One k_sweep launch with the template flags chosen at run time: parity, collision
+// (BGK or two-rate), lane exchange, x faces.  Only the combinations a caller can ask
+// for are instantiated.
+template <int ST, int D, int MODEL, int BODY, bool INJ>
+void launch_k(const Launch& L, dim3 grd, int parity, int coll, bool xch, bool fx, const Grid& g, const Phys& ph,
+              const Codec& cd, const Body& b, const float* dq, const int* flag, const Inflow& in) {
+  constexpr bool kX = MODEL == 0 && (BODY == 0 || BODY == 3);  // exchange possible
+  constexpr bool kF = D == 3 && MODEL == 0 && BODY != 2 && !INJ;  // x faces possible
+  constexpr bool kC = !INJ;                                      // two-rate collisions possible
+  auto go = [&](auto par_c, auto coll_c, auto xch_c, auto fx_c) {
+    constexpr int P = decltype(par_c)::value, C = decltype(coll_c)::value;
+    constexpr bool X = decltype(xch_c)::value, FXv = decltype(fx_c)::value;
+    hipLaunchKernelGGL((k_sweep<ST, D, MODEL, P, BODY, C, INJ, X, FXv>), grd, dim3(L.block_x), 0, L.stream, g, ph,
+                       cd, b, dq, flag, in);
+  };
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  using BF = std::false_type;
+  using BT = std::true_type;
+  auto with_fx = [&](auto par_c, auto coll_c, auto xch_c) {
+    if constexpr (kF) {
+      if (fx) return go(par_c, coll_c, xch_c, BT{});
+    }
+    go(par_c, coll_c, xch_c, BF{});
+  };
+  auto with_coll = [&](auto par_c, auto xch_c) {
+    if constexpr (kC) {
+      if (coll) return with_fx(par_c, I1{}, xch_c);
+    }
+    with_fx(par_c, I0{}, xch_c);
+  };
+  if (parity == 0) return with_coll(I0{}, BF{});
+  if constexpr (kX) {
+    if (xch) return with_coll(I1{}, BT{});
   }
+  with_coll(I1{}, BF{});
+}
+
+template <int ST, int D, int MODEL>
+hipError_t sweep_t(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity, const Inflow& in) {
+  launch_k<ST, D, MODEL, 0, false>(L, cell_grid(g, L.block_x), parity, ph.collision, lane_exchange(g, L.block_x, MODEL),
+                                   fuse_x_faces(g), g, ph, cd, Body{}, nullptr, nullptr, in);
   return hipGetLastError();
 }
 
 template <int ST>
 hipError_t sweep_inj_t(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
                        const float* dq, const int* flag) {
-  const dim3 grd = cell_grid(g, L.block_x), blk(L.block_x);
-  if (parity == 0)
-    hipLaunchKernelGGL((k_sweep<ST, 2, 0, 0, 0, 0, true>), grd, blk, 0, L.stream, g, ph, cd, Body{}, dq, flag);
-  else if (lane_exchange(g, L.block_x, 0))
-    hipLaunchKernelGGL((k_sweep<ST, 2, 0, 1, 0, 0, true, true>), grd, blk, 0, L.stream, g, ph, cd, Body{}, dq, flag);
-  else
-    hipLaunchKernelGGL((k_sweep<ST, 2, 0, 1, 0, 0, true>), grd, blk, 0, L.stream, g, ph, cd, Body{}, dq, flag);
+  launch_k<ST, 2, 0, 0, true>(L, cell_grid(g, L.block_x), parity, 0, lane_exchange(g, L.block_x, 0), false, g, ph,
+                              cd, Body{}, dq, flag, Inflow{});
   return hipGetLastError();
 }
 
 // what 1: the bounce-back body; 3: the homogenized body
 template <int ST>
 hipError_t sweep_body_t(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
-                        const Body* b, int what) {
+                        const Body* b, int what, const Inflow& in) {
+  const dim3 grd = cell_grid(g, L.block_x);
+  const bool fx = fuse_x_faces(g);
   if (what == 1) {
-    const dim3 grd = cell_grid(g, L.block_x), blk(L.block_x);
-    switch ((ph.collision ? 2 : 0) + parity) {
-      case 0: hipLaunchKernelGGL((k_sweep<ST, 3, 0, 0, 1, 0>), grd, blk, 0, L.stream, g, ph, cd, *b); break;
-      case 1: hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 1, 0>), grd, blk, 0, L.stream, g, ph, cd, *b); break;
-      case 2: hipLaunchKernelGGL((k_sweep<ST, 3, 0, 0, 1, 1>), grd, blk, 0, L.stream, g, ph, cd, *b); break;
-      default: hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 1, 1>), grd, blk, 0, L.stream, g, ph, cd, *b); break;
-    }
+    launch_k<ST, 3, 0, 1, false>(L, grd, parity, ph.collision, false, fx, g, ph, cd, *b, nullptr, nullptr, in);
   } else {
     // homogenized body: the plain sweep outside the body's box, then the homogenized
     // sweep of the box; the two update disjoint cells, each cell exactly once
-    const dim3 grd = cell_grid(g, L.block_x), blk(L.block_x);
     const int bx = b->box[1] - b->box[0], by = b->box[3] - b->box[2], bz = b->box[5] - b->box[4];
-    const bool box = bx > 0 && by > 0 && bz > 0;
-    const dim3 bgrd((unsigned)((bx + L.block_x - 1) / L.block_x), (unsigned)by, (unsigned)bz);
-    const bool xch = lane_exchange(g, L.block_x, 0);
-    switch ((ph.collision ? 2 : 0) + parity) {
-      case 0:
-        hipLaunchKernelGGL((k_sweep<ST, 3, 0, 0, 3, 0>), grd, blk, 0, L.stream, g, ph, cd, *b);
-        if (box) hipLaunchKernelGGL((k_sweep<ST, 3, 0, 0, 2, 0>), bgrd, blk, 0, L.stream, g, ph, cd, *b);
-        break;
-      case 1:
-        if (xch)
-          hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 3, 0, false, true>), grd, blk, 0, L.stream, g, ph, cd, *b);
-        else
-          hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 3, 0>), grd, blk, 0, L.stream, g, ph, cd, *b);
-        if (box) hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 2, 0>), bgrd, blk, 0, L.stream, g, ph, cd, *b);
-        break;
-      case 2:
-        hipLaunchKernelGGL((k_sweep<ST, 3, 0, 0, 3, 1>), grd, blk, 0, L.stream, g, ph, cd, *b);
-        if (box) hipLaunchKernelGGL((k_sweep<ST, 3, 0, 0, 2, 1>), bgrd, blk, 0, L.stream, g, ph, cd, *b);
-        break;
-      default:
-        if (xch)
-          hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 3, 1, false, true>), grd, blk, 0, L.stream, g, ph, cd, *b);
-        else
-          hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 3, 1>), grd, blk, 0, L.stream, g, ph, cd, *b);
-        if (box) hipLaunchKernelGGL((k_sweep<ST, 3, 0, 1, 2, 1>), bgrd, blk, 0, L.stream, g, ph, cd, *b);
-        break;
+    launch_k<ST, 3, 0, 3, false>(L, grd, parity, ph.collision, lane_exchange(g, L.block_x, 0), fx, g, ph, cd, *b,
+                                 nullptr, nullptr, in);
+    if (bx > 0 && by > 0 && bz > 0) {
+      const dim3 bgrd((unsigned)((bx + L.block_x - 1) / L.block_x), (unsigned)by, (unsigned)bz);
+      launch_k<ST, 3, 0, 2, false>(L, bgrd, parity, ph.collision, false, false, g, ph, cd, *b, nullptr, nullptr, in);
     }
   }
   return hipGetLastError();
@@ -446,15 +479,16 @@ hipError_t sweep_body_t(const Launch& L, const Grid& g, const Phys& ph, const Co
 
 template <int ST, int D, int M>
 struct SweepFn {
-  static hipError_t run(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int par) {
-    return sweep_t<ST, D, M>(L, g, ph, cd, par);
+  static hipError_t run(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int par, const Inflow& in) {
+    return sweep_t<ST, D, M>(L, g, ph, cd, par, in);
   }
 };
 
 }  // namespace
 
-hipError_t launch_sweep(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity) {
-  return dispatch<SweepFn>(L, g, ph, cd, parity);
+hipError_t launch_sweep(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
+                        const Inflow& in) {
+  return dispatch<SweepFn>(L, g, ph, cd, parity, in);
 }
 
 hipError_t launch_sweep_inj(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
@@ -466,15 +500,15 @@ hipError_t launch_sweep_inj(const Launch& L, const Grid& g, const Phys& ph, cons
 }
 
 hipError_t launch_sweep_body(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
-                             const Body& b, int mode) {
+                             const Body& b, int mode, const Inflow& in) {
   if (L.dim != 3 || L.model != 0) return hipErrorInvalidValue;
   if (mode != 2 && (mode != 1 || !g.mask)) return hipErrorInvalidValue;
   const int what = mode == 2 ? 3 : 1;
   switch (L.storage) {
-    case ST_F64: return sweep_body_t<ST_F64>(L, g, ph, cd, parity, &b, what);
-    case ST_F32: return sweep_body_t<ST_F32>(L, g, ph, cd, parity, &b, what);
-    case ST_F16: return sweep_body_t<ST_F16>(L, g, ph, cd, parity, &b, what);
-    case ST_BF16: return sweep_body_t<ST_BF16>(L, g, ph, cd, parity, &b, what);
+    case ST_F64: return sweep_body_t<ST_F64>(L, g, ph, cd, parity, &b, what, in);
+    case ST_F32: return sweep_body_t<ST_F32>(L, g, ph, cd, parity, &b, what, in);
+    case ST_F16: return sweep_body_t<ST_F16>(L, g, ph, cd, parity, &b, what, in);
+    case ST_BF16: return sweep_body_t<ST_BF16>(L, g, ph, cd, parity, &b, what, in);
     default: return hipErrorInvalidValue;
   }
 }
