@@ -43,18 +43,19 @@ def read_counter(path, counter):
     return rows
 
 
-SWEEP_RE = re.compile(r"k_sweep<(\d+), (\d+), (\d+), (\d+), (\d+), (\d+), (true|false)>")
+SWEEP_RE = re.compile(r"k_sweep<(\d+), (\d+), (\d+), (\d+), (\d+), (\d+)((?:, (?:true|false))*)>")
 
 
 def per_parity(rows, st, d, model):
-    """Mean KiB per dispatch of the plain periodic BGK sweep for each parity."""
+    """Mean KiB per dispatch of the plain periodic BGK sweep for each parity (no
+    injection, no face or exchange variant)."""
     acc = {}
     for name, v in rows:
         m = SWEEP_RE.search(name)
         if not m:
             continue
-        ST, D, MODEL, PAR, BODY, COLL, INJ = m.groups()
-        if (int(ST), int(D), int(MODEL), int(BODY), int(COLL), INJ) != (st, d, model, 0, 0, "false"):
+        ST, D, MODEL, PAR, BODY, COLL, flags = m.groups()
+        if (int(ST), int(D), int(MODEL), int(BODY), int(COLL)) != (st, d, model, 0, 0) or "true" in flags:
             continue
         acc.setdefault(int(PAR), []).append(v)
     return {p: sum(v) / len(v) for p, v in sorted(acc.items())}
