@@ -98,7 +98,11 @@ vlbm_status vlbm_restrict(const float* Qf, int32_t K, int32_t nx, int32_t ny, in
 vlbm_status vlbm_inject(vlbm_ctx* c, const float* dQ);
 
 /* n coarse steps with the learned correction.  Per step: the moments X of the
- * current populations (including the pending correction), dQ = network(X), the gate
+ * current populations (including the pending correction), dQ = network(X) -- if
+ * project_totals is nonzero, minus its mean over each lattice of the batch, channel by
+ * channel (the fine run, its restriction and the coarse VLBM all keep the lattice
+ * totals of rho, rho u, E and B up to the Powell source, so the true correction has a
+ * zero total, and a bias of the network cannot accumulate in the totals) -- the gate
  * (FP64 over the whole lattice or batch: every ||dQ_k||_2 <= bound_corr[k]; the
  * central-difference div B drift ||div(B + dB)||_2 <= (1 + bound_divb_rel) ||div B||_2
  * + bound_divb_abs ||B||_2 with B the in-plane field of X; all finite -- otherwise
@@ -110,7 +114,8 @@ vlbm_status vlbm_inject(vlbm_ctx* c, const float* dQ);
  * independent lattices, gated together) whose extent the network supports.  bound_corr: host, K doubles.  *n_fallback (host, may
  * be NULL) receives the number of fallbacks in this call.  Synchronises. */
 vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const double* bound_corr,
-                                double bound_divb_rel, double bound_divb_abs, int64_t* n_fallback);
+                                double bound_divb_rel, double bound_divb_abs, int32_t project_totals,
+                                int64_t* n_fallback);
 
 #ifdef __cplusplus
 }

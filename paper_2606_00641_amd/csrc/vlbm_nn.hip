@@ -464,6 +464,39 @@ struct GateBounds {
   double divb_rel, divb_abs;
 };
 
+// Zero lattice total per channel.  The fine run, its restriction and the coarse VLBM
+// all keep each lattice's totals of rho, rho u, E and B (up to the Powell source), so
+// the correction they define has zero total; projecting the prediction onto that keeps
+// a small bias of the network from accumulating in the totals over many steps.
+// Pass 1: FP64 partial sums of dq[k] over chunks of kCenterChunk cells of lattice b,
+// partial[(k * nb + b) * nchunk + chunk]; pass 2: every cell subtracts the mean of its
+// (k, b) from the partials.  No buffer needs clearing, so both passes can be captured.
+constexpr int kCenterChunk = 4096;
+__global__ __launch_bounds__(256) void k_center_sum(const float* __restrict__ dq, int nxy, int nb, long long N,
+                                                    double* __restrict__ partial) {
+  __shared__ double sh[4];
+  const int chunk = blockIdx.x, k = blockIdx.y, b = blockIdx.z, nchunk = gridDim.x;
+  const float* p = dq + (size_t)k * (size_t)N + (size_t)b * (size_t)nxy;
+  const int i0 = chunk * kCenterChunk, i1 = min(nxy, i0 + kCenterChunk);
+  double s = 0.0;
+  for (int i = i0 + (int)threadIdx.x; i < i1; i += 256) s += p[i];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[((size_t)k * nb + b) * nchunk + chunk] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+__global__ __launch_bounds__(256) void k_center_apply(float* __restrict__ dq, int nxy, int nb, long long N,
+                                                      int nchunk, const double* __restrict__ partial) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (c >= N) return;
+  const int b = (int)(c / nxy);
+  const double* q = partial + ((size_t)k * nb + b) * nchunk;
+  double s = 0.0;
+  for (int j = 0; j < nchunk; ++j) s += q[j];
+  dq[(size_t)k * (size_t)N + c] -= (float)(s / (double)nxy);
+}
+
 // per-block FP64 partials: [0..7] sum dQ_k^2, [8] sum divc(X)^2, [9] sum divc(X + dQ)^2,
 // [10] non-finite count, [11] sum |B(X)|^2 (in-plane components)
 __global__ __launch_bounds__(kGateThreads) void k_gate_partials(const float* __restrict__ X, const float* __restrict__ dq,
@@ -928,7 +961,8 @@ vlbm_status vlbm_inject(vlbm_ctx* c, const float* dQ) {
 }
 
 vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const double* bound_corr,
-                                double bound_divb_rel, double bound_divb_abs, int64_t* n_fallback) {
+                                double bound_divb_rel, double bound_divb_abs, int32_t project_totals,
+                                int64_t* n_fallback) {
   if (!c || !nn) return VLBM_ERR_ARG;
   if (!c->initialized) return VLBM_ERR_STATE;
   if (n < 0 || !bound_corr) return nfail(nn, VLBM_ERR_ARG, "n >= 0 and bound_corr required");
@@ -953,6 +987,8 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
   int* flag = nullptr;  // flag[0..1] ping-pong
   long long* fb = nullptr;
   double* gpart = nullptr;
+  double* cpart = nullptr;  // projection partials
+  const int nxy = c->p.nx * c->p.ny, nchunk = (nxy + kCenterChunk - 1) / kCenterChunk;
   hipStream_t cs = nullptr;  // the loop runs on its own stream, ordered after and before s
   hipEvent_t ev = nullptr;
   hipGraph_t graph = nullptr;
@@ -967,6 +1003,7 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
     if (flag) (void)hipFree(flag);
     if (fb) (void)hipFree(fb);
     if (gpart) (void)hipFree(gpart);
+    if (cpart) (void)hipFree(cpart);
     if (ev) (void)hipEventDestroy(ev);
     if (cs) (void)hipStreamDestroy(cs);
   };
@@ -976,6 +1013,7 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
   if (e == hipSuccess) e = hipMalloc(&flag, 2 * sizeof(int));
   if (e == hipSuccess) e = hipMalloc(&fb, sizeof(long long));
   if (e == hipSuccess) e = hipMalloc(&gpart, (size_t)gblk * 12 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&cpart, (size_t)8 * c->p.nz * nchunk * sizeof(double));
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventRecord(ev, s);
@@ -998,6 +1036,12 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
     if (e != hipSuccess) return VLBM_ERR_HIP;
     vlbm_status fs = forward(nn, X, c->p.nz, c->p.nx, c->p.ny, false, nn->d_norm + 24, nn->d_norm + 16, dq[1 - cur], cs);
     if (fs != VLBM_OK) return fs;
+    if (project_totals) {
+      hipLaunchKernelGGL(k_center_sum, dim3((unsigned)nchunk, 8, (unsigned)c->p.nz), dim3(256), 0, cs, dq[1 - cur],
+                         nxy, c->p.nz, (long long)N, cpart);
+      hipLaunchKernelGGL(k_center_apply, dim3((unsigned)((N + 255) / 256), 8), dim3(256), 0, cs, dq[1 - cur], nxy,
+                         c->p.nz, (long long)N, nchunk, cpart);
+    }
     hipLaunchKernelGGL(k_gate_partials, dim3(gblk), dim3(kGateThreads), 0, cs, X, dq[1 - cur], c->p.nx, c->p.ny,
                        c->p.nz, gpart);
     hipLaunchKernelGGL(k_gate_final, dim3(1), dim3(1), 0, cs, gpart, gblk, gb, flag + (1 - cur), fb);

@@ -176,7 +176,7 @@ def field_errors(Q, R):
 
 
 def evaluate(net, seeds, n_fine, r, coarse_steps, workload, make_state, bound_corr, bound_divb_rel, bound_divb_abs,
-             kmax=16, checkpoints=5, storage="f32", log=None):
+             kmax=16, checkpoints=5, storage="f32", log=None, project=True):
     """Coarse plain VLBM vs the corrected coarse run, both scored against the restricted
     fine run."""
     torch = _torch()
@@ -197,7 +197,8 @@ def evaluate(net, seeds, n_fine, r, coarse_steps, workload, make_state, bound_co
     for c in range(checkpoints):
         fine.vlbm_step(r * chunk)
         plain.vlbm_step(chunk)
-        fallbacks += N.vlbm_step_corrected(learned, net, chunk, bound_corr, bound_divb_rel, bound_divb_abs)
+        fallbacks += N.vlbm_step_corrected(learned, net, chunk, bound_corr, bound_divb_rel, bound_divb_abs,
+                                           project_totals=project)
         fine.vlbm_moments(out=M)
         N.vlbm_restrict(M, r, Rf, rz=1, stream=s)
         ref = Rf.cpu().numpy().astype(np.float64)
@@ -214,7 +215,7 @@ def evaluate(net, seeds, n_fine, r, coarse_steps, workload, make_state, bound_co
 
 
 def time_runs(net, n_fine, r, coarse_steps, workload, make_state, bound_corr, bound_divb_rel, bound_divb_abs,
-              kmax=16, seed=900, storage="f32"):
+              kmax=16, seed=900, storage="f32", project=True):
     """Wall time of the plain FP32 fine run (r * coarse_steps steps) and of the
     corrected coarse run (coarse_steps steps), one lattice each, inputs resident."""
     torch = _torch()
@@ -230,14 +231,15 @@ def time_runs(net, n_fine, r, coarse_steps, workload, make_state, bound_corr, bo
     N.vlbm_restrict(M, r, Rf, rz=1, stream=s)
     learned.vlbm_init_fields(Rf)
     fine.vlbm_step(r * 10)
-    N.vlbm_step_corrected(learned, net, 10, bound_corr, bound_divb_rel, bound_divb_abs)
+    N.vlbm_step_corrected(learned, net, 10, bound_corr, bound_divb_rel, bound_divb_abs, project_totals=project)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     fine.vlbm_step(r * coarse_steps)
     torch.cuda.synchronize()
     t_fine = time.perf_counter() - t0
     t0 = time.perf_counter()
-    nfb = N.vlbm_step_corrected(learned, net, coarse_steps, bound_corr, bound_divb_rel, bound_divb_abs)
+    nfb = N.vlbm_step_corrected(learned, net, coarse_steps, bound_corr, bound_divb_rel, bound_divb_abs,
+                                project_totals=project)
     torch.cuda.synchronize()
     t_learned = time.perf_counter() - t0
     fine.vlbm_destroy()

@@ -26,7 +26,7 @@ _sigs = {
     "vlbm_nn_train_step": [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, _dp],
     "vlbm_restrict": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                       ctypes.c_int32, _vp, _vp, _vp],
-    "vlbm_step_corrected": [_vp, _vp, ctypes.c_int32, _dp, ctypes.c_double, ctypes.c_double,
+    "vlbm_step_corrected": [_vp, _vp, ctypes.c_int32, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                             ctypes.POINTER(ctypes.c_int64)],
     "vlbm_inject": [_vp, _vp],
 }
@@ -136,13 +136,14 @@ def vlbm_restrict(Qf, r, out, rz=None, minus=None, stream=None):
     return out
 
 
-def vlbm_step_corrected(sim, net, n, bound_corr, bound_divb_rel, bound_divb_abs=0.0):
-    """Advance the coarse context `sim` (a vlbm.Vlbm) n steps with the correction;
-    returns the number of fallbacks."""
+def vlbm_step_corrected(sim, net, n, bound_corr, bound_divb_rel, bound_divb_abs=0.0, project_totals=True):
+    """Advance the coarse context `sim` (a vlbm.Vlbm) n steps with the correction
+    (projected to zero lattice totals unless project_totals is False); returns the
+    number of fallbacks."""
     b, bp = _d(bound_corr)
     nfb = ctypes.c_int64()
     st = _lib.vlbm_step_corrected(sim.ctx, net.h, int(n), bp, float(bound_divb_rel), float(bound_divb_abs),
-                                  ctypes.byref(nfb))
+                                  1 if project_totals else 0, ctypes.byref(nfb))
     if st != _v.VLBM_OK:
         msg = _lib.vlbm_nn_last_error(net.h)
         raise _v.VlbmError(st, msg.decode() if msg else "")

@@ -32,6 +32,8 @@ def main():
     ap.add_argument("--quick", action="store_true", help="small sizes (smoke)")
     ap.add_argument("--noise", type=float, default=0.0, help="relative noise on the stored pairs' inputs")
     ap.add_argument("--stride", type=int, default=1, help="store every stride-th pair of the teacher-forced run")
+    ap.add_argument("--no-project", action="store_true", help="do not project the correction to zero lattice totals")
+    ap.add_argument("--seed", type=int, default=0, help="seed of the initial weights and of the training order")
     ap.add_argument("--bound-factor", type=float, default=5.0,
                     help="gate: fall back when a channel's correction norm exceeds this many times the RMS "
                          "norm of the training targets")
@@ -57,20 +59,21 @@ def main():
     in_mean, in_std, out_mean, out_std, y_l2, drift = Lr.normalisation(X, Y)
     b_abs = 5.0 * drift
     net = N.Net(8, 32, 4, stream=torch.cuda.current_stream().cuda_stream)
-    net.vlbm_nn_set_weights(Lr.init_weights(seed=0))
+    net.vlbm_nn_set_weights(Lr.init_weights(seed=args.seed))
     net.vlbm_nn_set_norm(in_mean, in_std, out_mean, out_std)
-    losses, t_train = Lr.train(net, X, Y, args.iters, args.lr, seed=0, log=log)
+    losses, t_train = Lr.train(net, X, Y, args.iters, args.lr, seed=args.seed, log=log)
     del X, Y
     torch.cuda.empty_cache()
     bound = args.bound_factor * y_l2 * np.sqrt(len(eval_seeds))
     hist, nfb = Lr.evaluate(net, eval_seeds, n_fine, r, steps, w, synth.fourier_2d, bound, 0.1, b_abs, kmax=kmax,
-                            checkpoints=10, log=log)
+                            checkpoints=10, log=log, project=not args.no_project)
     t_fine, t_learned, nfb_t = Lr.time_runs(net, n_fine, r, steps, w, synth.fourier_2d, y_l2 * args.bound_factor, 0.1, b_abs,
-                                            kmax=kmax)
+                                            kmax=kmax, project=not args.no_project)
     res = dict(
         workload=f"2D ideal MHD D2Q5 x 8, fine {n_fine}^2 -> coarse {n_fine // r}^2 (r = {r}), Fourier modes k <= {kmax}, "
                  f"tau = {w['tau']}, s = {w['s']}, FP32 storage",
-        train_seeds=[seeds[0], seeds[-1]], pairs=pairs * len(seeds), pair_stride=stride, pair_noise=args.noise,
+        train_seeds=[seeds[0], seeds[-1]], pairs=pairs * len(seeds), pair_stride=stride, pair_noise=args.noise, seed=args.seed,
+        projected=not args.no_project,
         eval_seeds=eval_seeds,
         coarse_steps=steps,
         network="4 x conv3x3, 8-32-32-32-8, GELU, BF16 MFMA / FP32 accumulate, Adam lr %g, %d iterations (batch %d lattices)"

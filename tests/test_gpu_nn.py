@@ -241,7 +241,7 @@ def test_uniform_correction_matches_oracle_emulation(env):
     params[3] = (params[3][0], c.astype(np.float32).astype(np.float64))
     net = make_net(env, 4, params)
     sim = coarse_sim(env, "f64", n=n, powell=0)
-    nfb = nn.vlbm_step_corrected(sim, net, steps, np.full(8, 1.0), 0.1)
+    nfb = nn.vlbm_step_corrected(sim, net, steps, np.full(8, 1.0), 0.1, project_totals=False)
     assert nfb == 0
     Qg, tg = sim.vlbm_moments()
     w = synth.workload_fourier_2d(n=n)
@@ -256,6 +256,49 @@ def test_uniform_correction_matches_oracle_emulation(env):
     assert np.abs(Qg - Qo).max() <= 1e-10
     _, _, t0 = oracle.moments(op, oracle.init(op, synth.fourier_2d(n, seed=0)))
     assert np.allclose(tg[:8] - t0[:8], steps * n * n * cf, rtol=1e-6, atol=1e-9)
+
+
+def test_projected_uniform_correction_is_the_plain_run(env):
+    """Projected to zero lattice totals, a uniform correction vanishes exactly: the run
+    is bitwise the plain run."""
+    torch, vlbm, nn = env
+    c = np.array([1e-4, 2e-5, -1e-5, 3e-5, 2e-4, 1e-5, -2e-5, 1e-5])
+    params = [(np.zeros(Ws), np.zeros(bs)) for Ws, bs in C.Net.shapes(8, 32, 4)]
+    params[3] = (params[3][0], c.astype(np.float32).astype(np.float64))
+    net = make_net(env, 4, params)
+    a = coarse_sim(env, "f32", n=32)
+    b = coarse_sim(env, "f32", n=32)
+    assert nn.vlbm_step_corrected(a, net, 11, np.full(8, 1.0), 0.1) == 0
+    b.vlbm_step(11)
+    assert np.array_equal(a.vlbm_get_populations()[0], b.vlbm_get_populations()[0])
+
+
+def test_projection_keeps_each_lattice_total(env):
+    """A random network's correction, projected, leaves the total mass of every lattice
+    of the batch where the plain VLBM keeps it, up to the FP32 rounding of the
+    correction itself (|sum dQ| <= N 2^-24 max|dQ| per step: here below 1e-9 of the
+    mass after 13 steps), while the unprojected correction moves it by 1e-3."""
+    torch, vlbm, nn = env
+    rng = np.random.default_rng(31)
+    params = [(W * 0.05, b * 0.01) for W, b in rand_params(rng, 4)]
+    net = make_net(env, 4, params)
+    n, B = 32, 3
+    w = synth.workload_fourier_2d(n=n)
+    Q0 = np.concatenate([synth.fourier_2d(n, seed=40 + j) for j in range(B)], axis=1)
+
+    def lattice_mass(sim):
+        Q, _ = sim.vlbm_moments()
+        return np.asarray(Q).reshape(8, B, n * n)[0].sum(axis=1)
+
+    out = {}
+    for proj in (True, False):
+        sim = vlbm.Vlbm(gpu_params(vlbm, w, "f64", shape=(n, n, B)))
+        sim.vlbm_init_fields(Q0)
+        m0 = lattice_mass(sim)
+        nn.vlbm_step_corrected(sim, net, 13, np.full(8, 10.0), 10.0, 1.0, project_totals=proj)
+        out[proj] = np.abs(lattice_mass(sim) - m0).max() / np.abs(m0).max()
+    assert out[True] <= 1e-9, out
+    assert out[False] > 1e5 * max(out[True], 1e-16), out
 
 
 def test_replayed_steps_equal_single_steps(env):
