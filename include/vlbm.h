@@ -99,7 +99,9 @@ typedef struct {
                              domain mean of the Q given to vlbm_init_fields, with
                              rho u (and G, H) set to zero */
   double scale[VLBM_KMAX];/* codec sigma_k (> 0); 0: smallest power of two >=
-                             max |Q_k - Q_rest,k| over the initial field (1 if 0) */
+                             max |Q_k - Q_rest,k| over the initial field, or >= |Q_rest,k|
+                             if that spread is within 2^-20 |Q_rest,k| (a field uniform
+                             at the start; 1 if both are 0) */
   void* pop_buffer;       /* optional borrowed device buffer for the populations */
   size_t pop_bytes;       /* its size in bytes (>= vlbm_population_bytes()) */
   void* stream;           /* hipStream_t for all work; NULL: the null stream */

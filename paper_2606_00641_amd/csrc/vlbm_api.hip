@@ -425,8 +425,14 @@ vlbm_status vlbm_init_fields(vlbm_ctx* c, const void* Q, int q_on_device, int q_
       if (e == hipSuccess) e = hipMemcpyAsync(dev, d_dev, sizeof(double) * c->K, hipMemcpyDeviceToHost, c->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
       if (e == hipSuccess)
-        for (int k = 0; k < c->K; ++k)
-          if (!(c->p.scale[k] > 0.0)) c->scale[k] = pow2_at_least(dev[k]);
+        for (int k = 0; k < c->K; ++k) {
+          if (c->p.scale[k] > 0.0) continue;
+          // a field uniform at the start (its spread no more than the rounding of its
+          // mean) is scaled by its own magnitude: the spread it develops later is
+          // unknown, and a scale set by rounding noise would saturate FP16 at once
+          const double mag = std::fabs(c->rest_Q[k]);
+          c->scale[k] = pow2_at_least(dev[k] > std::ldexp(mag, -20) ? dev[k] : mag);
+        }
     }
     if (e == hipSuccess) build_codec(c);
   }
