@@ -538,14 +538,18 @@ __global__ __launch_bounds__(kGateThreads) void k_gate_partials(const float* __r
   }
 }
 
-__global__ void k_gate_final(const double* __restrict__ partial, int nblk, GateBounds gb, int* __restrict__ flag,
-                             long long* __restrict__ fallbacks) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+// One wavefront: lane l sums the partials of blocks l, l + 64, ...; a shuffle tree
+// combines the lanes, and lane 0 decides.
+__global__ __launch_bounds__(64) void k_gate_final(const double* __restrict__ partial, int nblk, GateBounds gb,
+                                                   int* __restrict__ flag, long long* __restrict__ fallbacks) {
   constexpr int NP = 12;
   double t[NP];
   for (int j = 0; j < NP; ++j) t[j] = 0.0;
-  for (int b = 0; b < nblk; ++b)
+  for (int b = (int)threadIdx.x; b < nblk; b += 64)
     for (int j = 0; j < NP; ++j) t[j] += partial[(size_t)b * NP + j];
+  for (int j = 0; j < NP; ++j)
+    for (int off = 32; off > 0; off >>= 1) t[j] += __shfl_xor(t[j], off);
+  if (threadIdx.x != 0) return;
   bool ok = t[10] == 0.0;
   for (int k = 0; k < 8; ++k) ok = ok && sqrt(t[k]) <= gb.corr[k];
   ok = ok && sqrt(t[9]) <= (1.0 + gb.divb_rel) * sqrt(t[8]) + gb.divb_abs * sqrt(t[11]);
@@ -1044,7 +1048,7 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
     }
     hipLaunchKernelGGL(k_gate_partials, dim3(gblk), dim3(kGateThreads), 0, cs, X, dq[1 - cur], c->p.nx, c->p.ny,
                        c->p.nz, gpart);
-    hipLaunchKernelGGL(k_gate_final, dim3(1), dim3(1), 0, cs, gpart, gblk, gb, flag + (1 - cur), fb);
+    hipLaunchKernelGGL(k_gate_final, dim3(1), dim3(64), 0, cs, gpart, gblk, gb, flag + (1 - cur), fb);
     e = hipGetLastError();
     if (e == hipSuccess) e = vlbm::launch_sweep_inj(L, c->g, c->ph, c->cd, par, dq[cur], flag + cur);
     if (e != hipSuccess) return VLBM_ERR_HIP;
