@@ -191,6 +191,32 @@ def run_network():
     return network
 
 
+def recorded_studies():
+    """Summaries of the committed study outputs under profiles/ (recorded by
+    study_precision.py and study_learned.py on the same GPU; not re-measured here)."""
+    out = {}
+    try:
+        with open(os.path.join(ROOT, "profiles", "precision_slab_512.json")) as fh:
+            d = json.load(fh)
+        last = d["checkpoints"][-1]
+        out["precision_slab_512"] = {
+            "source": "profiles/precision_slab_512.json", "steps": last["step"],
+            "rel_l2_vs_fp64": {st: {k: v for k, v in last[st].items() if k != "nbad"} for st in ("f32", "f16", "bf16")}}
+    except (OSError, ValueError, KeyError):
+        pass
+    try:
+        with open(os.path.join(ROOT, "profiles", "learned_coarse_2d.json")) as fh:
+            d = json.load(fh)
+        last = d["history"][-1]
+        out["learned_coarse_2d"] = {
+            "source": "profiles/learned_coarse_2d.json", "workload": d["workload"], "coarse_steps": d["coarse_steps"],
+            "speedup_vs_fine_fp32": d["speedup_vs_fine"], "rel_l2_vs_restricted_fine": {
+                "plain_coarse": last["plain"], "learned_coarse": last["learned"]}, "fallbacks": d["fallbacks"]}
+    except (OSError, ValueError, KeyError):
+        pass
+    return out or None
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -280,6 +306,7 @@ def main():
         "forms_slab_512": forms or None,
         "forms_body_768x384x384": body_forms or None,
         "learned_network_40x256x256": network,
+        "recorded_studies": recorded_studies(),
         "finite": r["finite"],
     }
     print(json.dumps(out), flush=True)
