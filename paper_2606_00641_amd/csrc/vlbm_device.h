@@ -128,6 +128,15 @@ template <typename T>
 __device__ __forceinline__ void st(void* base, size_t plane_bytes, int plane, unsigned off, T v) {
   __builtin_nontemporal_store(v, (VLBM_GLOBAL T*)(plane_base(base, plane_bytes, plane) + off));
 }
+// A store one element off the wavefront's alignment (the +-x populations on parity 1)
+// fills only part of its first and last cache lines; the neighbouring wavefront fills
+// the rest.  With the ordinary cache policy L2 merges the two halves before writing the
+// line back; the streaming policy sends the partial lines on (measured on the
+// 26-variable sweep: parity 1 8.6 % faster with this store for those two planes).
+template <typename T>
+__device__ __forceinline__ void st_shifted(void* base, size_t plane_bytes, int plane, unsigned off, T v) {
+  *(VLBM_GLOBAL T*)(plane_base(base, plane_bytes, plane) + off) = v;
+}
 
 // Dipole field of the body at point q (cell coordinates) and time t.
 __device__ inline void dipole_at(const Body& b, const double (&q)[3], double t, double (&B)[3]) {

@@ -290,7 +290,10 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
           st<T>(F, pb, k * NQ + opposite(i), co, v);
         } else {
           const unsigned dst = (i == 0) ? co : ((i & 1) ? np[(i - 1) >> 1] : nm[(i - 1) >> 1]);
-          st<T>(F, pb, k * NQ + i, dst, v);
+          if (i == 1 || i == 2)
+            st_shifted<T>(F, pb, k * NQ + i, dst, v);
+          else
+            st<T>(F, pb, k * NQ + i, dst, v);
         }
       }
     }
@@ -319,11 +322,11 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
       // workgroup's last cell, whose own lanes skip those slots
       if (!row && own && t == (int)blockDim.x - 1) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) st<T>(F, pb, k * NQ + 1, np[0], raw[k][0]);
+        for (int k = 0; k < K; ++k) st_shifted<T>(F, pb, k * NQ + 1, np[0], raw[k][0]);
       }
       if (!row && own && t == 0) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) st<T>(F, pb, k * NQ + 2, nm[0], raw[k][1]);
+        for (int k = 0; k < K; ++k) st_shifted<T>(F, pb, k * NQ + 2, nm[0], raw[k][1]);
       }
       // the lane shifts read every lane, so they run with all lanes active
 #pragma unroll
@@ -385,6 +388,8 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
           const T v = S::enc(f[k][i], cd, k * NQ + i);
           if constexpr (PAR == 0)
             st<T>(F, pb, k * NQ + opposite(i), co, v);
+          else if (i == 1 || i == 2)
+            st_shifted<T>(F, pb, k * NQ + i, dst, v);
           else
             st<T>(F, pb, k * NQ + i, dst, v);
         }
