@@ -188,6 +188,21 @@ vlbm_status vlbm_get_codec(const vlbm_ctx* c, double* rest_Q, double* scale);
 /* Number of steps taken since vlbm_init_fields. */
 vlbm_status vlbm_get_step(const vlbm_ctx* c, int64_t* step);
 
+/* Loads on the homogenized body (body = 2) for the context's next step -- the per-step
+ * surface integrals of the paper's moving-body showcase (Sec. 5: magnetic flux, force,
+ * torque, electromagnetic work) for the homogenization of Sec. 2.4.  The collision
+ * moves each cell's conserved variables by omega_k (Q^_k - Q_k) toward its
+ * homogenized state; the body receives the opposite.  loads (host, 8 doubles):
+ * [0..2] force = -sum omega_m rho (u^ - u) (momentum per step, cell volume 1, flux
+ * units); [3..5] torque = -sum (x - c(t)) x omega_m rho (u^ - u) about the body's
+ * centre c(t) = body_c0 + t body_v; [6] energy moved to the body per step, -sum
+ * omega_E (e^ - e_tot); [7] magnetic flux through the surface, 1/2 sum |B . r/|r||
+ * over the one-cell porosity ramp (the surface measure |grad d| dV).  omega_k =
+ * 1/tau_k (BGK), the symmetric rate (TRT), 1 (RLB).  Periodic, Powell off: the
+ * fluid's momentum and energy totals change in the step by exactly -force, -energy.
+ * Synchronises the stream.  VLBM_ERR_ARG without the homogenized body. */
+vlbm_status vlbm_body_loads(vlbm_ctx* c, double* loads);
+
 /* Free everything the context owns (never a borrowed buffer).  NULL-safe. */
 void vlbm_destroy(vlbm_ctx* c);
 

@@ -364,3 +364,62 @@ def run_fp32(p, Q, nsteps):
     L.vref_init(ctypes.byref(q), Q32.ctypes.data_as(fp), f.ctypes.data_as(fp))
     L.vref_run(ctypes.byref(q), f.ctypes.data_as(fp), work.ctypes.data_as(fp), int(nsteps))
     return f.astype(np.float64).sum(axis=1)
+
+
+def body_loads(p, f, t):
+    """What one homogenized step at time t moves from the fluid to the body, and the
+    magnetic flux through the body's surface -- the per-step integrals the paper's
+    showcase reports (Sec. 5: net magnetic flux, force, torque, electromagnetic work),
+    for the homogenized body of Sec. 2.4.
+
+    The collision relaxes every conserved variable toward its homogenized value, so a
+    cell's zeroth moments change by omega_k (Q^_k - Q_k): momentum by omega_m rho (u^ - u)
+    = omega_m rho (1 - d) (u^B - u), energy by omega_E (e^ - e_tot) (rho and p kept,
+    e^ = p/(gamma-1) + rho|u^|^2/2 + |B^|^2/2).  The body receives the opposite:
+    force = -sum omega_m rho (u^ - u), torque = -sum (x - c(t)) x omega_m rho (u^ - u)
+    about the body's centre, work = -sum omega_E (e^ - e_tot) (all per step, cell volume
+    1, flux units).  omega_k: 1/tau_k (BGK), 1/tau+_k (TRT: the zeroth moment is carried
+    by the symmetric halves), 1 (RLB: f* = f^eq(Q^) + ..., whose zeroth moment is Q^).
+    Flux: half the surface integral of |B . n|, the surface measure being |grad d| dV,
+    1 across the one-cell ramp 0 < d < 1 of the porosity: flux = 1/2 sum_ramp |B . r/|r||.
+    Returns dict(force [3], torque [3], work, flux)."""
+    K = nvars(p)
+    Q, _, _ = moments(p, f)
+    Q = Q.reshape(K, p.nz, p.ny, p.nx)
+    d = porosity(p, t)
+    c = np.array([p.body_c0[a] + t * p.body_v[a] for a in range(3)])
+    z, y, x = np.meshgrid(np.arange(p.nz), np.arange(p.ny), np.arange(p.nx), indexing="ij")
+    r = np.stack([x - c[0], y - c[1], z - c[2]]).astype(np.float64)
+    r2 = (r ** 2).sum(0)
+    m = np.array([p.body_m[a] for a in range(3)])
+    R0 = p.body_R0
+    with np.errstate(divide="ignore", invalid="ignore"):
+        mr = (m[:, None, None, None] * r).sum(0)
+        Bout = (3.0 * mr * r - m[:, None, None, None] * r2) / r2 ** 2.5
+    Bin = np.broadcast_to((2.0 * m / R0 ** 3)[:, None, None, None], r.shape)
+    BB = np.where(r2 < R0 * R0, Bin, Bout)
+    rho, E, B = Q[0], Q[4], Q[5:8]
+    u = Q[1:4] / rho
+    gm1 = p.gamma - 1.0
+    pres = gm1 * (E - 0.5 * rho * (u ** 2).sum(0) - 0.5 * (B ** 2).sum(0))
+    ub = np.array([p.body_v[a] for a in range(3)]) / p.s
+    uh = d * u + (1.0 - d) * ub[:, None, None, None]
+    Bh = d * B + np.where(d < 1.0, (1.0 - d) * BB, 0.0)
+    Eh = pres / gm1 + 0.5 * rho * (uh ** 2).sum(0) + 0.5 * (Bh ** 2).sum(0)
+    tau = np.array([p.tau[k] for k in range(K)])
+    if p.collision == 0:
+        om = 1.0 / tau
+    elif p.collision == 1:
+        om = 1.0 / (0.5 + p.trt_magic / (tau - 0.5))
+    else:
+        om = np.ones(K)
+    dM = om[1:4, None, None, None] * rho * (uh - u)
+    dM = np.where(d < 1.0, dM, 0.0)
+    dE = np.where(d < 1.0, om[4] * (Eh - E), 0.0)
+    force = -dM.reshape(3, -1).sum(1)
+    torque = -np.cross(r, dM, axis=0).reshape(3, -1).sum(1)
+    ramp = (d > 0.0) & (d < 1.0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        Bn = np.abs((B * r).sum(0)) / np.sqrt(r2)
+    flux = 0.5 * Bn[ramp].sum()
+    return dict(force=force, torque=torque, work=-dE.sum(), flux=flux)

@@ -591,6 +591,21 @@ vlbm_status vlbm_get_step(const vlbm_ctx* c, int64_t* step) {
   return VLBM_OK;
 }
 
+vlbm_status vlbm_body_loads(vlbm_ctx* c, double* loads) {
+  if (!c || !loads) return VLBM_ERR_ARG;
+  if (!c->initialized) return fail(c, VLBM_ERR_STATE, "body_loads before init_fields");
+  if (c->p.body != 2) return fail(c, VLBM_ERR_ARG, "body_loads needs the homogenized body (body = 2)");
+  Body b = c->body;
+  b.t = (double)c->step;
+  hlbm_box(c, b.t, b.box);
+  const int par = (int)(c->step & 1);
+  VLBM_HIP(c, launch_body_loads(c->L, c->g, c->ph, c->cd, par, b, c->d_partial, c->nblk));
+  VLBM_HIP(c, launch_reduce(c->L, 8, c->d_partial, c->nblk, 0u, c->d_totals));
+  VLBM_HIP(c, hipMemcpyAsync(loads, c->d_totals, 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  VLBM_HIP(c, hipStreamSynchronize(c->stream));
+  return VLBM_OK;
+}
+
 void vlbm_destroy(vlbm_ctx* c) {
   if (!c) return;
   if (c->owned && c->f) (void)hipFree(c->f);

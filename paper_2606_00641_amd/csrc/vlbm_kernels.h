@@ -102,6 +102,10 @@ hipError_t launch_divc(const Launch& L, const Grid& g, const double* Qout, doubl
                        int nblk);
 // Fixed-order reduction of per-block partials [nblk][n] into out[n] (device);
 // slots whose bit is set in maxmask take the max, the others the sum.
+// Loads on the homogenized body at time b.t over b.box: nblk block partials of
+// (force[3], torque[3], energy, magnetic flux), to be summed with launch_reduce.
+hipError_t launch_body_loads(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
+                             const Body& b, double* partial, int nblk);
 hipError_t launch_reduce(const Launch& L, int n, const double* partial, int nblk, unsigned maxmask,
                          double* out);
 

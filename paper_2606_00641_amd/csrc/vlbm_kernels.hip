@@ -291,6 +291,49 @@ __global__ __launch_bounds__(kReduceThreads) void k_moments(const Grid g, const 
   block_reduce<NT>(acc, NT, 1u << (K + 2), partial + (size_t)blockIdx.x * NT);
 }
 
+// Per-step loads on the homogenized body at time b.t (cells of b.box): what the
+// homogenized collision moves from the fluid to the body -- force (momentum), torque
+// about the body's centre, energy -- and the magnetic flux through its surface,
+// 1/2 sum |B . r/|r|| over the one-cell porosity ramp.  The cell's moments change by
+// omega_k (Q^_k - Q_k) in the collision; omega_k = 1/tau_k (BGK), the symmetric rate
+// (two-rate collisions carry the zeroth moment in the symmetric halves), 1 (RLB).
+// partial[block][8] = (F, T, W, flux).
+template <int ST>
+__global__ __launch_bounds__(kReduceThreads) void k_body_loads(const Grid g, const Phys ph, const Codec cd,
+                                                               int parity, const Body b,
+                                                               double* __restrict__ partial) {
+  using R = typename Store<ST>::R;
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const long long bx = b.box[1] - b.box[0], by = b.box[3] - b.box[2], bz = b.box[5] - b.box[4];
+  const long long nb = bx * by * bz;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < nb; t += (long long)gridDim.x * blockDim.x) {
+    const int x = b.box[0] + (int)(t % bx), y = b.box[2] + (int)((t / bx) % by), z = b.box[4] + (int)(t / (bx * by));
+    const HlbmTarget tg{&b, x, y, z, HlbmTarget::near_body(b, x, y, z), ph.s, ph.gm1};
+    if (!tg.near) continue;
+    double r[3], rr;
+    const double phi = tg.rr_minus_R(r, rr);
+    if (phi >= 0.5) continue;  // porosity 1: fluid, no exchange
+    const unsigned c = (unsigned)x + (unsigned)g.nx * ((unsigned)y + (unsigned)g.ny * (unsigned)z);
+    R Qr[8];
+    cell_moments3<ST>(g, cd, parity, c, Qr);
+    double Q[8], Qh[8];
+    for (int k = 0; k < 8; ++k) Q[k] = Qh[k] = (double)Qr[k];
+    tg(Qh);
+    double om[5];
+    for (int k = 1; k < 5; ++k) om[k] = ph.collision == 0 ? ph.omega[k] : (ph.collision == 1 ? ph.omega_s[k] : 1.0);
+    const double dM[3] = {om[1] * (Qh[1] - Q[1]), om[2] * (Qh[2] - Q[2]), om[3] * (Qh[3] - Q[3])};
+    acc[0] -= dM[0];
+    acc[1] -= dM[1];
+    acc[2] -= dM[2];
+    acc[3] -= r[1] * dM[2] - r[2] * dM[1];
+    acc[4] -= r[2] * dM[0] - r[0] * dM[2];
+    acc[5] -= r[0] * dM[1] - r[1] * dM[0];
+    acc[6] -= om[4] * (Qh[4] - Q[4]);
+    if (phi > -0.5 && rr > 0.0) acc[7] += 0.5 * fabs(Q[5] * r[0] + Q[6] * r[1] + Q[7] * r[2]) / rr;
+  }
+  block_reduce<8>(acc, 8, 0u, partial + (size_t)blockIdx.x * 8);
+}
+
 template <int D>
 __global__ __launch_bounds__(kReduceThreads) void k_divc(const Grid g, const double* __restrict__ Qm,
                                                          double* __restrict__ partial) {
@@ -496,6 +539,20 @@ hipError_t launch_divc(const Launch& L, const Grid& g, const double* Qout, doubl
     hipLaunchKernelGGL((k_divc<2>), dim3(nblk), dim3(kReduceThreads), 0, L.stream, g, Qout, partial);
   else
     hipLaunchKernelGGL((k_divc<3>), dim3(nblk), dim3(kReduceThreads), 0, L.stream, g, Qout, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_body_loads(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
+                             const Body& b, double* partial, int nblk) {
+  if (L.dim != 3 || L.model != 0) return hipErrorInvalidValue;
+  const dim3 grd(nblk), blk(kReduceThreads);
+  switch (L.storage) {
+    case ST_F64: hipLaunchKernelGGL(k_body_loads<ST_F64>, grd, blk, 0, L.stream, g, ph, cd, parity, b, partial); break;
+    case ST_F32: hipLaunchKernelGGL(k_body_loads<ST_F32>, grd, blk, 0, L.stream, g, ph, cd, parity, b, partial); break;
+    case ST_F16: hipLaunchKernelGGL(k_body_loads<ST_F16>, grd, blk, 0, L.stream, g, ph, cd, parity, b, partial); break;
+    case ST_BF16: hipLaunchKernelGGL(k_body_loads<ST_BF16>, grd, blk, 0, L.stream, g, ph, cd, parity, b, partial); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -98,6 +98,7 @@ def load_library(path: str = LIB_PATH):
         "vlbm_get_codec": [vp, dp, dp],
         "vlbm_get_step": [vp, ctypes.POINTER(ctypes.c_int64)],
         "vlbm_copy_kernel": [vp, vp, ctypes.c_size_t, vp],
+        "vlbm_body_loads": [vp, dp],
     }
     for name, argtypes in sigs.items():
         fn = getattr(L, name)
@@ -277,6 +278,13 @@ class Vlbm:
         s = ctypes.c_int64()
         _check(_lib.vlbm_get_step(self.ctx, ctypes.byref(s)), self.ctx)
         return s.value
+
+    def vlbm_body_loads(self):
+        """Loads on the homogenized body for the next step: dict(force [3], torque [3],
+        energy, flux) (include/vlbm.h)."""
+        out = np.zeros(8)
+        _check(_lib.vlbm_body_loads(self.ctx, _dptr(out)), self.ctx)
+        return dict(force=out[0:3].copy(), torque=out[3:6].copy(), energy=float(out[6]), flux=float(out[7]))
 
     def vlbm_destroy(self):
         if getattr(self, "ctx", None) is not None and self.ctx.value:

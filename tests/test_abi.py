@@ -122,3 +122,4 @@ def test_null_safety(vb):
     assert L.vlbm_step(None, 1) == vb.VLBM_ERR_ARG
     assert L.vlbm_create(None, None) == vb.VLBM_ERR_ARG
     assert L.vlbm_copy_kernel(None, None, 16, None) == vb.VLBM_ERR_ARG
+    assert L.vlbm_body_loads(None, None) == vb.VLBM_ERR_ARG

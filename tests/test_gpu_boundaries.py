@@ -176,3 +176,55 @@ def test_homogenized_body_lane_exchange(vb, block_x):
     b, _, _, _ = _run_pair(vb, "body", "f32", (1, 2, 2, 2, 2, 2), steps=41, mode=2, nx=128, block_x=256)
     d = rel_l2(a, b, 8)
     assert max(d.values()) < 1e-6, d
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-10), ("f32", 1e-5)])
+@pytest.mark.parametrize("steps", [13, 14])
+def test_body_loads_parity(vb, storage, tol, steps):
+    """Loads on the homogenized body (force, torque, energy, flux) after an even and an
+    odd number of steps match the oracle's, evaluated on the oracle's own run."""
+    shape, Q0, Qin, body, tau, s, _ = _case("body", 2)
+    bc = (1, 2, 2, 2, 2, 2)
+    p = vb.make_params(lattice="D3Q7", shape=shape, model="ideal", storage=storage, flux_scale=s, tau=tau,
+                       bc=bc, inflow_Q=Qin, body=body, stream=_stream())
+    sim = vb.Vlbm(p)
+    sim.vlbm_init_fields(Q0)
+    sim.vlbm_step(steps)
+    g = sim.vlbm_body_loads()
+    op = oracle.make_params(dim=3, shape=shape, s=s, tau=tau)
+    oracle.set_boundaries(op, bc=bc, inflow_Q=Qin, body=body, body_mode=2)
+    f = oracle.init(op, Q0)
+    oracle.run_bc(op, f, steps)
+    o = oracle.body_loads(op, f, steps)
+    print(storage, steps, g, o)
+    for a, b in ((g["force"], o["force"]), (g["torque"], o["torque"])):
+        assert np.abs(a - b).max() <= tol * np.abs(b).max(), (a, b)
+    assert abs(g["energy"] - o["work"]) <= tol * abs(o["work"])
+    assert abs(g["flux"] - o["flux"]) <= tol * o["flux"]
+
+
+def test_body_loads_balance_the_gpu_step(vb):
+    """Periodic, Powell off, FP64: the GPU step changes the fluid's momentum and energy
+    totals by minus the loads taken before it."""
+    shape, Q0, Qin, body, tau, s, _ = _case("body", 2)
+    p = vb.make_params(lattice="D3Q7", shape=shape, model="ideal", storage="f64", flux_scale=s, tau=tau,
+                       powell=False, body=body, stream=_stream())
+    sim = vb.Vlbm(p)
+    sim.vlbm_init_fields(Q0)
+    sim.vlbm_step(5)
+    L = sim.vlbm_body_loads()
+    _, t0 = sim.vlbm_moments()
+    sim.vlbm_step(1)
+    _, t1 = sim.vlbm_moments()
+    dM, dE = t1[1:4] - t0[1:4], t1[4] - t0[4]
+    assert np.abs(dM + L["force"]).max() <= 1e-10 * np.abs(L["force"]).max(), (dM, L)
+    assert abs(dE + L["energy"]) <= 1e-10 * abs(L["energy"]), (dE, L)
+
+
+def test_body_loads_need_the_homogenized_body(vb):
+    shape, Q0, Qin, body, tau, s, _ = _case("body", 1)
+    sim = vb.Vlbm(vb.make_params(lattice="D3Q7", shape=shape, model="ideal", storage="f32", flux_scale=s, tau=tau,
+                                 bc=(1, 2, 2, 2, 2, 2), inflow_Q=Qin, body=body, stream=_stream()))
+    sim.vlbm_init_fields(Q0)
+    with pytest.raises(vb.VlbmError):
+        sim.vlbm_body_loads()

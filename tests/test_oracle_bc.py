@@ -434,3 +434,68 @@ def test_boundary_pins_catch_planted_mistake(name, tmp_path):
     path = oracle.compile_variant(src.replace(old, new), str(tmp_path / f"mut_{name}.so"))
     with oracle.use_library(path):
         assert _fails(name), f"planted mistake '{name}' was not caught"
+
+
+# --- loads on the homogenized body (Sec. 5 per-step integrals, Sec. 2.4 body) ----
+
+def _uniform_state(shape, rho=1.0, p=0.6, u=(0.05, 0.0, 0.0), B=(0.3, -0.2, 0.1), gamma=5.0 / 3.0):
+    u, B = np.asarray(u, float), np.asarray(B, float)
+    Q = np.zeros((8,) + tuple(shape[::-1]))
+    Q[0] = rho
+    Q[1:4] = rho * u[:, None, None, None]
+    Q[5:8] = B[:, None, None, None]
+    Q[4] = p / (gamma - 1.0) + 0.5 * rho * (u @ u) + 0.5 * (B @ B)
+    return Q
+
+
+def _smooth_sphere(c, R0, v=(0.0, 0.0, 0.0), m=(0.0, 0.0, 0.0)):
+    return dict(c0=c, v=v, R0=R0, a=[0.0] * 4, d=[[1.0, 0.0, 0.0]] * 4, b=[0.0] * 4, e=[[1.0, 0.0, 0.0]] * 4, m=m)
+
+
+@pytest.mark.parametrize("collision", [0, 1, 2])
+def test_body_loads_balance_the_fluid(collision):
+    """Periodic domain, Powell off: in one step the fluid's momentum and energy totals
+    change by exactly minus the force and energy the loads assign to the body (the
+    homogenization is the only non-conservative part of the step), for every
+    collision operator; a moving rough magnetised body."""
+    shape = (24, 22, 20)
+    Qin, _ = synth.inflow_state(mach=0.8, alfven_mach=4.0)
+    Q0 = np.broadcast_to(Qin[:, None, None, None], (8,) + shape[::-1]).copy()
+    Q0 += 0.3 * synth.smooth_box_state(shape[::-1], seed=12, amp=0.05, rho=0.0, p=0.0, B0=0.0)
+    body = synth.rough_body((11.3, 10.1, 9.7), (0.08, 0.04, 0.02), 4.6, m=(3.0, -2.0, 1.5), rough=0.12, seed=5)
+    op = oracle.make_params(dim=3, shape=shape, s=0.1, tau=0.7, powell=0, collision=collision)
+    oracle.set_boundaries(op, bc=None, inflow_Q=Qin, body=body, body_mode=2)
+    f = oracle.init(op, Q0)
+    oracle.run_bc(op, f, 3)
+    L = oracle.body_loads(op, f, 3)
+    Qa, _, _ = oracle.moments(op, f)
+    oracle.run_bc(op, f, 1, t0=3)
+    Qb, _, _ = oracle.moments(op, f)
+    dM = Qb[1:4].sum(1) - Qa[1:4].sum(1)
+    dE = Qb[4].sum() - Qa[4].sum()
+    assert np.abs(dM + L["force"]).max() <= 1e-11 * np.abs(L["force"]).max(), (dM, L["force"])
+    assert abs(dE + L["work"]) <= 1e-11 * abs(L["work"]), (dE, L["work"])
+    assert np.abs(L["force"]).max() > 0.1 and abs(L["work"]) > 0.01
+
+
+@pytest.mark.parametrize("R0,c", [(6.0, (16, 16, 16)), (8.0, (16.3, 16.5, 15.8)), (10.0, (20, 20, 20))])
+def test_body_loads_closed_forms(R0, c):
+    """A uniform flow u0 x and field B0 around a smooth sphere at rest without a
+    moment: every cell of the body pulls the fluid toward rest, so the force is
+    omega rho u0 x (the body's porosity volume, sum (1 - d) = 4/3 pi R0^3 to the ramp's
+    resolution); the flux of the uniform field through the sphere is pi R0^2 |B0|
+    (half the integral of |B0 . n|); a sphere centred on a lattice point takes no
+    torque (mirror symmetry of the cells)."""
+    n = int(2 * np.ceil(max(c)))
+    shape = (n, n, n)
+    u0, B0, tau = 0.05, np.array([0.3, -0.2, 0.1]), 0.7
+    Q = _uniform_state(shape, u=(u0, 0.0, 0.0), B=B0)
+    op = oracle.make_params(dim=3, shape=shape, s=0.1, tau=tau, powell=0)
+    oracle.set_boundaries(op, bc=None, inflow_Q=Q[:, 0, 0, 0], body=_smooth_sphere(c, R0), body_mode=2)
+    L = oracle.body_loads(op, oracle.init(op, Q), 0)
+    vol = 4.0 / 3.0 * np.pi * R0 ** 3
+    assert abs(L["force"][0] / (u0 / tau * vol) - 1.0) < 0.01, L
+    assert np.abs(L["force"][1:]).max() <= 1e-12 * L["force"][0]
+    assert abs(L["flux"] / (np.pi * R0 ** 2 * np.linalg.norm(B0)) - 1.0) < 0.06, L
+    if all(float(x).is_integer() for x in c):
+        assert np.abs(L["torque"]).max() <= 1e-12 * L["force"][0] * R0, L
