@@ -54,7 +54,12 @@ typedef enum {
 } vlbm_status;
 
 typedef enum { VLBM_D2Q5 = 0, VLBM_D3Q7 = 1 } vlbm_lattice;
-typedef enum { VLBM_IDEAL = 0, VLBM_RESISTIVE = 1 } vlbm_model; /* K = 8 or 26 */
+/* IDEAL: ideal compressible MHD, K = 8 (rho, rho u, E, B; Sec. 2.3).  RESISTIVE:
+ * resistive incompressible MHD, K = 26 (+ G, H; D3Q7 only).  EULER: compressible
+ * Euler, K = 5 (rho, rho u, E) -- the ideal system without the field, the
+ * hydrodynamic limit the scheme covers (Sec. 1, Sec. 2.3): fluxes rho u,
+ * rho u u + p I, (E + p) u, p = (gamma - 1)(E - rho |u|^2 / 2), no source. */
+typedef enum { VLBM_IDEAL = 0, VLBM_RESISTIVE = 1, VLBM_EULER = 2 } vlbm_model;
 
 /* Population storage in HBM.  F64 and F32 store f itself (F64 computes in FP64,
  * F32 in FP32).  F16DEV and BF16DEV store h = (f - f_rest[k][i]) / (w_i sigma_k),

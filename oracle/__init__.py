@@ -187,7 +187,7 @@ def make_params(dim=2, shape=(64, 64, 1), model=0, gamma=5.0 / 3.0, s=0.2, w0=No
 
 
 def nvars(p):
-    return 26 if p.model == 1 else 8
+    return {1: 26, 2: 5}.get(p.model, 8)
 
 
 def ndirs(p):

@@ -24,7 +24,7 @@ int vref_num_threads(void) {
 #endif
 }
 
-int vref_nvars(const vref_params* p) { return p->model == 1 ? 26 : 8; }
+int vref_nvars(const vref_params* p) { return p->model == 1 ? 26 : (p->model == 2 ? 5 : 8); }
 int vref_ndirs(const vref_params* p) { return 2 * p->dim + 1; }
 
 /* Lattice (Sec. 2.2; the paper's lattice table is not printed).
@@ -56,8 +56,33 @@ static int edir(int i, int a) {
  * divergence is mu Lap u for a solenoidal flow; heat flux q = 0;
  * eta(j) = eta0 (1 + (|j|/j_c)^2) (constant eta0 when j_c <= 0);
  * j = curl B; the induction flux gains -eta d_b B_a. */
+/* Compressible Euler (model 2): the conservation laws of mass, momentum and energy
+ * without a field -- the hydrodynamic limit of the MHD system (Sec. 1, Sec. 2.3):
+ * Phi = (rho u, rho u u + p I, (E + p) u), p = (gamma - 1)(E - rho |u|^2 / 2), S = 0. */
+static int euler_flux(const vref_params* p, const double* Q, double* Phi, double* S, double* dlat) {
+  const double rho = Q[0], E = Q[4];
+  double u[3], uu = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    u[a] = Q[1 + a] / rho;
+    uu += u[a] * u[a];
+  }
+  const double pres = (p->gamma - 1.0) * (E - 0.5 * rho * uu);
+  for (int b = 0; b < 3; ++b) {
+    Phi[3 * 0 + b] = Q[1 + b];
+    for (int a = 0; a < 3; ++a) Phi[3 * (1 + a) + b] = Q[1 + a] * u[b] + (a == b ? pres : 0.0);
+    Phi[3 * 4 + b] = (E + pres) * u[b];
+  }
+  for (int k = 0; k < 5; ++k) S[k] = 0.0;
+  *dlat = 0.0;
+  int bad = !(rho > 0.0) || !(pres >= 0.0);
+  for (int k = 0; k < 5; ++k)
+    if (!isfinite(Q[k])) bad = 1;
+  return bad;
+}
+
 int vref_flux_source(const vref_params* p, const double* Q, const double* J,
                      double* Phi, double* S, double* dlat) {
+  if (p->model == 2) return euler_flux(p, Q, Phi, S, dlat);
   const int K = vref_nvars(p);
   const int d = p->dim;
   const double g = p->gamma;
@@ -355,7 +380,7 @@ int vref_moments(const vref_params* p, const double* f, double* Q_out, double* d
       if (fabs(dall[c]) > totals[K + 2]) totals[K + 2] = fabs(dall[c]);
     }
     /* central-difference divergence of the moment field B, lattice units */
-    for (int z = 0; z < p->nz; ++z)
+    for (int z = 0; z < (p->model == 2 ? 0 : p->nz); ++z)
       for (int y = 0; y < p->ny; ++y)
         for (int x = 0; x < p->nx; ++x) {
           double dv = 0.0;

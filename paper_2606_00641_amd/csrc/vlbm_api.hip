@@ -46,7 +46,7 @@ vlbm_status hip_fail(vlbm_ctx* c, hipError_t e, const char* what) {
   } while (0)
 
 int dim_of(int lattice) { return lattice == VLBM_D3Q7 ? 3 : 2; }
-int nvars_of(int model) { return model == VLBM_RESISTIVE ? 26 : 8; }
+int nvars_of(int model) { return model == VLBM_RESISTIVE ? 26 : (model == VLBM_EULER ? 5 : 8); }
 int esize_of(int storage) {
   switch (storage) {
     case VLBM_F64: return 8;
@@ -77,7 +77,7 @@ vlbm_status validate(const vlbm_params* p) {
   if (N >= (1LL << 31)) return fail(nullptr, VLBM_ERR_ARG, "%lld cells exceed 2^31 - 1", N);
   if (plane_stride(N, esize_of(p->storage)) * esize_of(p->storage) >= (1LL << 32))
     return fail(nullptr, VLBM_ERR_ARG, "one population plane would exceed 4 GiB");
-  if (p->model != VLBM_IDEAL && p->model != VLBM_RESISTIVE)
+  if (p->model != VLBM_IDEAL && p->model != VLBM_RESISTIVE && p->model != VLBM_EULER)
     return fail(nullptr, VLBM_ERR_ARG, "unknown model %d", p->model);
   if (p->model == VLBM_RESISTIVE && p->lattice != VLBM_D3Q7)
     return fail(nullptr, VLBM_ERR_ARG, "the resistive model needs D3Q7");
@@ -193,7 +193,11 @@ void build_codec(vlbm_ctx* c) {
   std::memset(&c->cd, 0, sizeof c->cd);
   if (c->p.storage != VLBM_F16DEV && c->p.storage != VLBM_BF16DEV) return;
   double P[KMAX][3], S[KMAX], dl, Jb[3] = {0, 0, 0};
-  if (c->D == 2)
+  if (c->p.model == VLBM_EULER && c->D == 2)
+    flux_source<double, 2, 2>(c->rest_Q, Jb, c->ph, P, S, dl);
+  else if (c->p.model == VLBM_EULER)
+    flux_source<double, 3, 2>(c->rest_Q, Jb, c->ph, P, S, dl);
+  else if (c->D == 2)
     flux_source<double, 2, 0>(c->rest_Q, Jb, c->ph, P, S, dl);
   else if (c->p.model == VLBM_RESISTIVE)
     flux_source<double, 3, 1>(c->rest_Q, Jb, c->ph, P, S, dl);
@@ -499,11 +503,14 @@ vlbm_status vlbm_moments(vlbm_ctx* c, void* Q_out, int out_on_device, int out_is
   const int NT = c->K + 5;
   const int par = (int)(c->step & 1);
   VLBM_HIP(c, launch_moments(c->L, c->g, c->ph, c->cd, par, Qd, c->d_partial, c->nblk));
-  VLBM_HIP(c, launch_divc(c->L, c->g, Qd, c->d_partial2, c->nblk));
+  const bool has_B = c->p.model != VLBM_EULER;
+  if (has_B) VLBM_HIP(c, launch_divc(c->L, c->g, Qd, c->d_partial2, c->nblk));
   VLBM_HIP(c, launch_reduce(c->L, NT, c->d_partial, c->nblk, 1u << (c->K + 2), c->d_totals));
-  VLBM_HIP(c, launch_reduce(c->L, 1, c->d_partial2, c->nblk, 0u, c->d_totals + c->K + 3));
+  if (has_B) VLBM_HIP(c, launch_reduce(c->L, 1, c->d_partial2, c->nblk, 0u, c->d_totals + c->K + 3));
   double tot[KMAX + 5];
   VLBM_HIP(c, hipMemcpyAsync(tot, c->d_totals, sizeof(double) * NT, hipMemcpyDeviceToHost, c->stream));
+  VLBM_HIP(c, hipStreamSynchronize(c->stream));
+  if (!has_B) tot[c->K + 3] = 0.0;  // no field, no divergence
   if (Q_out && Qd != Q_out) {
     if (out_is_f32) {
       if (out_on_device) {

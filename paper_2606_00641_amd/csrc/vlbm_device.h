@@ -256,10 +256,10 @@ hipError_t dispatch(const Launch& L, A&&... args) {
   switch (key) {
 #define VLBM_CASE(ST, D, M) \
   case ST * 100 + D * 10 + M: return Fn<ST, D, M>::run(L, args...);
-    VLBM_CASE(0, 2, 0) VLBM_CASE(0, 3, 0) VLBM_CASE(0, 3, 1)
-    VLBM_CASE(1, 2, 0) VLBM_CASE(1, 3, 0) VLBM_CASE(1, 3, 1)
-    VLBM_CASE(2, 2, 0) VLBM_CASE(2, 3, 0) VLBM_CASE(2, 3, 1)
-    VLBM_CASE(3, 2, 0) VLBM_CASE(3, 3, 0) VLBM_CASE(3, 3, 1)
+    VLBM_CASE(0, 2, 0) VLBM_CASE(0, 3, 0) VLBM_CASE(0, 3, 1) VLBM_CASE(0, 2, 2) VLBM_CASE(0, 3, 2)
+    VLBM_CASE(1, 2, 0) VLBM_CASE(1, 3, 0) VLBM_CASE(1, 3, 1) VLBM_CASE(1, 2, 2) VLBM_CASE(1, 3, 2)
+    VLBM_CASE(2, 2, 0) VLBM_CASE(2, 3, 0) VLBM_CASE(2, 3, 1) VLBM_CASE(2, 2, 2) VLBM_CASE(2, 3, 2)
+    VLBM_CASE(3, 2, 0) VLBM_CASE(3, 3, 0) VLBM_CASE(3, 3, 1) VLBM_CASE(3, 2, 2) VLBM_CASE(3, 3, 2)
 #undef VLBM_CASE
     default: return hipErrorInvalidValue;
   }

@@ -186,7 +186,7 @@ __global__ __launch_bounds__(256) void k_init(const Grid g, const Phys ph, const
   using T = typename S::T;
   using R = typename S::R;
   constexpr int NQ = 2 * D + 1;
-  constexpr int K = MODEL ? 26 : 8;
+  constexpr int K = kNVars<MODEL>;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= g.nx) return;
   const unsigned c = (unsigned)x + (unsigned)g.nx * (blockIdx.y + (unsigned)g.ny * blockIdx.z);
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_moments(const Grid g, const 
   using S = Store<ST>;
   using T = typename S::T;
   constexpr int NQ = 2 * D + 1;
-  constexpr int K = MODEL ? 26 : 8;
+  constexpr int K = kNVars<MODEL>;
   constexpr int NT = K + 5;
   const T* __restrict__ F = static_cast<const T*>(g.f);
   const size_t N = (size_t)g.nx * g.ny * g.nz;

@@ -35,6 +35,11 @@ struct Phys {
   double omega_s[KMAX];
 };
 
+// Number of conserved variables of a model: 8 ideal MHD (rho, rho u, E, B), 26
+// resistive MHD (+ G, H), 5 compressible Euler (rho, rho u, E).
+template <int MODEL>
+inline constexpr int kNVars = MODEL == 1 ? 26 : (MODEL == 2 ? 5 : 8);
+
 // Scaled lattice flux P[k][a] = (s / c_s^2) Phi[k][a] for the D lattice axes, lattice
 // source S[k] and the lattice div B estimate.  Jb[a] = first moment along axis a of
 // the B_a population set (only used by divb_mode 0).  Returns true if the cell is
@@ -42,7 +47,34 @@ struct Phys {
 template <typename R, int D, int MODEL>
 __host__ __device__ inline bool flux_source(const R* Q, const R* Jb, const Phys& ph,
                                             R (*P)[3], R* S, R& dlat, R* pt_out = nullptr) {
-  constexpr int K = MODEL ? 26 : 8;
+  constexpr int K = kNVars<MODEL>;
+  if constexpr (MODEL == 2) {
+    // compressible Euler: the ideal system without the field (the hydrodynamic limit
+    // the paper's scheme covers, Sec. 1 and Sec. 2.3): mass, momentum, energy fluxes
+    (void)Jb;
+    const R rho = Q[0];
+    const R ir = R(1) / rho;
+    const R m[3] = {Q[1], Q[2], Q[3]};
+    const R E = Q[4];
+    const R u[3] = {m[0] * ir, m[1] * ir, m[2] * ir};
+    const R pres = R(ph.gm1) * (E - R(0.5) * (m[0] * u[0] + m[1] * u[1] + m[2] * u[2]));
+    const R c = R(ph.s * ph.inv_cs2);
+    if (pt_out) *pt_out = pres;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      P[0][a] = c * m[a];
+#pragma unroll
+      for (int b = 0; b < 3; ++b) P[1 + b][a] = c * (m[b] * u[a] + (a == b ? pres : R(0)));
+      P[4][a] = c * ((E + pres) * u[a]);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) S[k] = R(0);
+    dlat = R(0);
+    bool bad = !(rho > R(0)) || !(pres >= R(0));
+#pragma unroll
+    for (int k = 0; k < K; ++k) bad = bad || !(Q[k] - Q[k] == R(0));
+    return bad;
+  } else {
   const R rho = Q[0];
   const R ir = R(1) / rho;
   const R m0 = Q[1], m1 = Q[2], m2 = Q[3];
@@ -157,6 +189,7 @@ __host__ __device__ inline bool flux_source(const R* Q, const R* Jb, const Phys&
 #pragma unroll
   for (int k = 0; k < K; ++k) bad = bad || !(Q[k] - Q[k] == R(0));  // NaN or Inf
   return bad;
+  }
 }
 
 // Rest weight derived in the compute type as 1 - 2 D w_i, so that the weights sum
@@ -189,8 +222,8 @@ struct NoTarget {
 // omega_s = 1) -- a template parameter, so that the BGK sweep keeps its registers.
 template <typename R, int D, int MODEL, int COLL = 0, typename Tgt = NoTarget>
 __device__ __forceinline__ bool collide(R (*f)[2 * D + 1], const Phys& ph, R& dlat,
-                                        R (&Q)[MODEL ? 26 : 8], R& pt, const Tgt& tgt = Tgt{}) {
-  constexpr int K = MODEL ? 26 : 8;
+                                        R (&Q)[kNVars<MODEL>], R& pt, const Tgt& tgt = Tgt{}) {
+  constexpr int K = kNVars<MODEL>;
   // Zeroth moments, opposite directions paired first: f_{+a} + f_{-a} cancels the
   // flux part c_a . Phi / c_s^2 the two carry with opposite signs before it is
   // accumulated, which keeps small variables (G, H, a momentum at rest) accurate
@@ -203,8 +236,10 @@ __device__ __forceinline__ bool collide(R (*f)[2 * D + 1], const Phys& ph, R& dl
     Q[k] = acc;
   }
   R Jb[3] = {R(0), R(0), R(0)};
+  if constexpr (MODEL != 2) {
 #pragma unroll
-  for (int a = 0; a < D; ++a) Jb[a] = f[5 + a][2 * a + 1] - f[5 + a][2 * a + 2];
+    for (int a = 0; a < D; ++a) Jb[a] = f[5 + a][2 * a + 1] - f[5 + a][2 * a + 2];
+  }
   R Qt[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) Qt[k] = Q[k];
@@ -253,7 +288,7 @@ __device__ __forceinline__ bool collide(R (*f)[2 * D + 1], const Phys& ph, R& dl
 
 template <typename R, int D, int MODEL, int COLL = 0>
 __device__ __forceinline__ bool collide(R (*f)[2 * D + 1], const Phys& ph, R& dlat) {
-  R Q[MODEL ? 26 : 8];
+  R Q[kNVars<MODEL>];
   R pt;
   return collide<R, D, MODEL, COLL>(f, ph, dlat, Q, pt);
 }

@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
   using T = typename S::T;
   using R = typename S::R;
   constexpr int NQ = 2 * D + 1;
-  constexpr int K = MODEL ? 26 : 8;
+  constexpr int K = kNVars<MODEL>;
   constexpr unsigned ES = sizeof(T);
   static_assert(!XCH || (PAR == 1 && (BODY == 0 || BODY == 3)), "lane exchange: plain sweep at parity 1");
   static_assert(!FX || (D == 3 && MODEL == 0 && BODY != 2 && !INJ), "x faces: D3Q7 ideal MHD");
@@ -400,11 +400,11 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
 
 // The parity-1 lane exchange needs every workgroup to cover whole wavefronts of one
 // x row (no partial workgroup, so that every lane reaches the barriers).  It is used
-// for the 8-variable sweeps (measured on 512^3: parity 1 11-20 % faster in FP32,
+// for the 8-variable (and 5-variable) sweeps (measured on 512^3: parity 1 11-20 % faster in FP32,
 // 12 % FP16, 10 % BF16); the 26-variable sweep runs one wavefront per SIMD, where the
 // workgroup barrier leaves the CU idle, and was 16 % slower with it.
 inline bool lane_exchange(const Grid& g, int block_x, int model) {
-  return model == 0 && block_x % 64 == 0 && g.nx % block_x == 0;
+  return model != 1 && block_x % 64 == 0 && g.nx % block_x == 0;
 }
 
 // One k_sweep launch with the template flags chosen at run time: parity, collision
@@ -413,7 +413,7 @@ inline bool lane_exchange(const Grid& g, int block_x, int model) {
 template <int ST, int D, int MODEL, int BODY, bool INJ>
 void launch_k(const Launch& L, dim3 grd, int parity, int coll, bool xch, bool fx, const Grid& g, const Phys& ph,
               const Codec& cd, const Body& b, const float* dq, const int* flag, const Inflow& in) {
-  constexpr bool kX = MODEL == 0 && (BODY == 0 || BODY == 3);  // exchange possible
+  constexpr bool kX = MODEL != 1 && (BODY == 0 || BODY == 3);  // exchange possible
   constexpr bool kF = D == 3 && MODEL == 0 && BODY != 2 && !INJ;  // x faces possible
   constexpr bool kC = !INJ;                                      // two-rate collisions possible
   auto go = [&](auto par_c, auto coll_c, auto xch_c, auto fx_c) {

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libvlbm.so")
 KMAX = 26
 VLBM_OK, VLBM_ERR_ARG, VLBM_ERR_OOM, VLBM_ERR_HIP, VLBM_ERR_STATE, VLBM_ERR_NONFINITE = 0, -1, -2, -3, -4, -5
 VLBM_D2Q5, VLBM_D3Q7 = 0, 1
-VLBM_IDEAL, VLBM_RESISTIVE = 0, 1
+VLBM_IDEAL, VLBM_RESISTIVE, VLBM_EULER = 0, 1, 2
 VLBM_F64, VLBM_F32, VLBM_F16DEV, VLBM_BF16DEV = 0, 1, 2, 3
 VLBM_BC_PERIODIC, VLBM_BC_INFLOW_EQ, VLBM_BC_ZERO_GRAD = 0, 1, 2
 STORAGE = {"f64": VLBM_F64, "f32": VLBM_F32, "f16": VLBM_F16DEV, "bf16": VLBM_BF16DEV}
@@ -141,7 +141,8 @@ def make_params(lattice="D2Q5", shape=(64, 64, 1), model="ideal", storage="f32",
     _check(_lib.vlbm_params_default(ctypes.byref(p)))
     p.lattice = VLBM_D3Q7 if str(lattice).upper() == "D3Q7" else VLBM_D2Q5
     p.nx, p.ny, p.nz = (int(v) for v in shape)
-    p.model = VLBM_RESISTIVE if model == "resistive" else VLBM_IDEAL
+    p.model = {"ideal": VLBM_IDEAL, "resistive": VLBM_RESISTIVE, "euler": VLBM_EULER}[model] if isinstance(model, str) \
+        else int(model)
     p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
     p.gamma = gamma
     p.flux_scale = flux_scale
@@ -195,7 +196,7 @@ class Vlbm:
         if pop_tensor is not None:
             params.pop_buffer = pop_tensor.data_ptr()
             params.pop_bytes = pop_tensor.numel() * pop_tensor.element_size()
-        self.K = 26 if params.model == VLBM_RESISTIVE else 8
+        self.K = {VLBM_RESISTIVE: 26, VLBM_EULER: 5}.get(params.model, 8)
         self.dim = 3 if params.lattice == VLBM_D3Q7 else 2
         self.Q = 2 * self.dim + 1
         self.shape = (params.nx, params.ny, params.nz)

@@ -44,6 +44,14 @@ def conserved_from_primitive(rho, u, p, B, gamma):
     return Q
 
 
+def without_field(Q):
+    """The compressible-Euler state [5, ...] of an ideal-MHD state Q [8, ...]: rho,
+    rho u, and the total energy without its magnetic part (same p and u)."""
+    Q = np.asarray(Q, np.float64)
+    E = Q[4] - 0.5 * (Q[5:8] ** 2).sum(0)
+    return np.concatenate([Q[:4], E[None]], axis=0)
+
+
 def _random_mode_field(rng, shape2d, kmax, ncomp):
     """Sum of unit-amplitude Fourier modes cos(2 pi (kx x/nx + ky y/ny) + phase) over
     integer 1 <= |k| <= kmax in the half plane, seeded phases; synthesised with an

@@ -6,8 +6,11 @@ FAMILIES_8 = {"rho": [0], "m": [1, 2, 3], "E": [4], "B": [5, 6, 7]}
 FAMILIES_26 = dict(FAMILIES_8, G=list(range(8, 17)), H=list(range(17, 26)))
 
 
+FAMILIES_5 = {"rho": [0], "m": [1, 2, 3], "E": [4]}
+
+
 def families(K):
-    return FAMILIES_26 if K == 26 else FAMILIES_8
+    return {26: FAMILIES_26, 5: FAMILIES_5}.get(K, FAMILIES_8)
 
 
 def rel_l2(a, b, K):

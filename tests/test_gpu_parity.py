@@ -33,7 +33,7 @@ def _stream():
 def gpu_params(vb, w, storage, block_x=0, shape=None):
     shape = shape or w["shape"]
     return vb.make_params(lattice="D3Q7" if w["dim"] == 3 else "D2Q5", shape=shape,
-                          model="resistive" if w["model"] else "ideal", storage=storage,
+                          model={0: "ideal", 1: "resistive", 2: "euler"}[w["model"]], storage=storage,
                           gamma=w["gamma"], flux_scale=w["s"], tau=w["tau"], powell=w["powell"],
                           divb_mode=w["divb_mode"], dt=w["dt"], mu=w["mu"], eta0=w["eta0"],
                           tau_M=w["tau_M"], tau_H=w["tau_H"], stream=_stream(), block_x=block_x)
@@ -482,3 +482,55 @@ def test_device_resident_fields_and_borrowed_buffer(vb):
     sim.vlbm_moments(out=out)
     ref = run_gpu(vb, w, Q0, 10, "f32")[1]
     assert np.allclose(out.cpu().numpy(), ref, rtol=1e-6, atol=1e-7)
+
+
+# --- compressible Euler (the ideal system without the field) --------------------
+
+def _euler(w):
+    w = dict(w)
+    w["model"] = 2
+    w["tau"] = w["tau"] if np.ndim(w["tau"]) == 0 else list(w["tau"])[:5]
+    return w
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-10), ("f32", 1e-5)])
+def test_euler_2d_parity_200_steps(vb, storage, tol):
+    w = _euler(synth.workload_fourier_2d())
+    Q0 = synth.without_field(synth.fourier_2d(64, seed=1))
+    _, Qg, _ = run_gpu(vb, w, Q0, 200, storage)
+    Qo, _ = run_oracle(w, Q0, 200)
+    err = rel_l2(Qg, Qo, 5)
+    assert max(err.values()) <= tol, err
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-10), ("f32", 1e-5), ("f16", 3e-3), ("bf16", 3e-2)])
+def test_euler_3d_parity(vb, storage, tol):
+    """Slab without field on a ragged box (70 x 20 x 12), with a drift so that every
+    field is O(1); 60 steps."""
+    w = _euler(synth.workload_slab_3d())
+    w["shape"] = (70, 20, 12)
+    Qm, _ = synth.planar_discontinuity_3d(seed=2, shape=(12, 20, 70))
+    Q0 = synth.without_field(boosted(Qm, (0.3, -0.2, 0.25)))
+    _, Qg, _ = run_gpu(vb, w, Q0, 60, storage)
+    Qo, _ = run_oracle(w, Q0, 60)
+    err = rel_l2(Qg, Qo, 5)
+    assert max(err.values()) <= tol, err
+
+
+def test_euler_lane_exchange(vb):
+    """Rows tiled by the workgroups take the parity-1 lane exchange in the Euler sweep
+    too: every tiling bitwise equal, held to the oracle and to the direct path."""
+    w = _euler(synth.workload_slab_3d())
+    w["shape"] = (256, 5, 4)
+    Qm, _ = synth.planar_discontinuity_3d(seed=4, shape=(4, 5, 256))
+    Q0 = synth.without_field(boosted(Qm, (0.3, -0.2, 0.25)))
+    Qo, _ = run_oracle(w, Q0, 9)
+    bufs, Qs = [], []
+    for bx in (64, 128, 256, 192):
+        sim, Qg, _ = run_gpu(vb, w, Q0, 9, "f64", block_x=bx)
+        bufs.append(sim.vlbm_get_populations()[0])
+        Qs.append(Qg)
+        sim.vlbm_destroy()
+        assert max(rel_l2(Qg, Qo, 5).values()) <= 1e-10
+    assert np.array_equal(bufs[1], bufs[0]) and np.array_equal(bufs[2], bufs[0])
+    assert max(rel_l2(Qs[0], Qs[-1], 5).values()) <= 1e-13

@@ -323,9 +323,89 @@ def chk_uniform(dim=2, model=0):
     return spread, drift
 
 
+def chk_euler_vs_mhd(dim, nsteps=40):
+    """Compressible Euler (model 2) against the ideal-MHD model run with B = 0 (to
+    which the MHD system reduces exactly: no Maxwell stress, no magnetic pressure or
+    energy, no induction, div B = 0): max relative difference of rho, rho u, E, and
+    the largest B the MHD run develops."""
+    if dim == 2:
+        Qm = synth.fourier_2d(24, seed=4)
+        shape = (24, 24, 1)
+    else:
+        Qm, _ = synth.planar_discontinuity_3d(seed=3, shape=(6, 7, 9))
+        shape = (9, 7, 6)
+    Qe = synth.without_field(Qm)
+    Qm0 = np.concatenate([Qe, np.zeros((3,) + Qe.shape[1:])], axis=0)
+    tau = [0.6, 0.7, 0.65, 0.8, 0.9, 0.6, 0.6, 0.6]
+    pe = oracle.make_params(dim=dim, shape=shape, model=2, tau=tau[:5])
+    pm = oracle.make_params(dim=dim, shape=shape, model=0, tau=tau)
+    fe, fm = oracle.init(pe, Qe), oracle.init(pm, Qm0)
+    oracle.run(pe, fe, nsteps)
+    oracle.run(pm, fm, nsteps)
+    Qen, _, _ = oracle.moments(pe, fe)
+    Qmn, _, _ = oracle.moments(pm, fm)
+    d = np.abs(Qen - Qmn[:5]).max() / np.abs(Qmn[:5]).max()
+    return d, np.abs(Qmn[5:]).max()
+
+
+def euler_sound_speed(N, rho=1.0, p=0.6, s=0.2, tau=0.6, eps=1e-6, travel=0.25, gamma=G53):
+    """Measured speed of a forward linear sound wave of the Euler model, one wavelength
+    across N cells, and the textbook speed sqrt(gamma p / rho)."""
+    c = np.sqrt(gamma * p / rho)
+    k = 2 * np.pi / N
+    x = np.arange(N)
+    sn = eps * np.sin(k * x)
+    # forward acoustic eigenvector: d rho = rho/c du, d p = rho c du
+    prim_rho, prim_u, prim_p = rho + rho / c * sn, sn, p + rho * c * sn
+    Qm = synth.conserved_from_primitive(prim_rho, np.stack([prim_u, 0 * sn, 0 * sn]), prim_p,
+                                        np.zeros((3, N)), gamma)
+    Q = synth.without_field(Qm)[:, None, None, :]
+    P = oracle.make_params(dim=2, shape=(N, 1, 1), model=2, s=s, tau=tau, gamma=gamma)
+    f = oracle.init(P, Q)
+    nsteps = int(round(travel * N / (s * c)))
+    oracle.run(P, f, nsteps)
+    Qn, _, _ = oracle.moments(P, f)
+    Qb = synth.without_field(synth.conserved_from_primitive(rho, np.zeros(3), p, np.zeros(3), gamma))
+    a0 = ((Q[:, 0, 0, :] - Qb[:, None]) * np.exp(-1j * k * x)).sum(1)
+    an = ((Qn - Qb[:, None]) * np.exp(-1j * k * x)).sum(1)
+    z = (np.conj(a0) * an).sum() / (np.conj(a0) * a0).sum()
+    return c, -np.angle(z) / (k * nsteps * s)
+
+
+def chk_euler_sound():
+    c, c32 = euler_sound_speed(32)
+    _, c64 = euler_sound_speed(64)
+    e32, e64 = abs(c32 - c) / c, abs(c64 - c) / c
+    return e64, e32 / max(e64, 1e-300)
+
+
 # ----------------------------------------------------------------------------
 # tests
 # ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_euler_is_mhd_without_field(dim):
+    d, bmax = chk_euler_vs_mhd(dim)
+    assert bmax == 0.0  # B stays exactly zero in the MHD run
+    assert d <= 1e-14, d
+
+
+def test_euler_sound_speed_second_order():
+    e64, ratio = chk_euler_sound()
+    assert e64 < 2e-3, e64
+    assert 3.0 < ratio < 5.0, ratio
+
+
+def test_euler_totals_exact():
+    Q = synth.without_field(synth.fourier_2d(32, seed=9))
+    p = oracle.make_params(dim=2, shape=(32, 32, 1), model=2)
+    f = oracle.init(p, Q)
+    _, _, t0 = oracle.moments(p, f)
+    oracle.run(p, f, 60)
+    _, _, t1 = oracle.moments(p, f)
+    scale = np.abs(Q).reshape(5, -1).sum(1)
+    assert np.all(np.abs(t1[:5] - t0[:5]) <= 1e-13 * scale)
+
 
 def test_equilibrium_moment_identities():
     assert chk_equilibrium_moments() < 1e-14
@@ -609,6 +689,9 @@ MUTATIONS = {
     "trt_magic_inverted": ("1.0 / (0.5 + p->trt_magic / (p->tau[k] - 0.5))", "1.0 / (0.5 + (p->tau[k] - 0.5) / p->trt_magic)"),
     "rlb_projection_scale": ("const double fneq = weight(p, i) * eJ / c2;", "const double fneq = weight(p, i) * eJ;"),
     "rlb_relaxation": ("feq[k * NQ + i] + (1.0 - 1.0 / p->tau[k]) * fneq", "feq[k * NQ + i] + (1.0 / p->tau[k]) * fneq"),
+    "euler_pressure_dropped": ("Phi[3 * (1 + a) + b] = Q[1 + a] * u[b] + (a == b ? pres : 0.0);",
+                               "Phi[3 * (1 + a) + b] = Q[1 + a] * u[b] + (a == b ? 0.0 : 0.0);"),
+    "euler_energy_flux": ("Phi[3 * 4 + b] = (E + pres) * u[b];", "Phi[3 * 4 + b] = E * u[b];"),
 }
 
 
@@ -625,6 +708,8 @@ def _fails(name):
         return dp_on > 3e-4
     if name == "divb_estimate_scale":
         return chk_divb_estimator_tau1() > 1e-12
+    if name.startswith("euler"):
+        return chk_euler_vs_mhd(2)[0] > 1e-14 or chk_euler_sound()[0] > 2e-3
     if name.startswith("trt") or name.startswith("rlb"):
         return (chk_pulse_fourier(collision=1, magic=1.0 / 12.0) > 1e-13
                 or chk_pulse_fourier(collision=2) > 1e-13 or chk_collision_identities() > 1e-14)
