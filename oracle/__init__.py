@@ -107,6 +107,7 @@ def lib():
         L.vref_equilibrium.restype = None
         L.vref_collide.argtypes = [P, dp, dp, dp]
         L.vref_collide_many.argtypes = [P, ctypes.c_long, dp, dp]
+        L.vref_collide_at.argtypes = [P, ctypes.c_long, dp, ctypes.POINTER(ctypes.c_int32), ctypes.c_double, dp]
         L.vref_init.argtypes = [P, dp, dp]
         L.vref_run.argtypes = [P, dp, dp, ctypes.c_int]
         L.vref_moments.argtypes = [P, dp, dp, dp, dp]
@@ -292,6 +293,17 @@ def collide_many(p, fcells):
     fcells = np.ascontiguousarray(fcells, np.float64)
     out = np.empty_like(fcells)
     lib().vref_collide_many(ctypes.byref(p), fcells.shape[0], _ptr(fcells), _ptr(out))
+    return out
+
+
+def collide_at(p, fcells, xyz, t):
+    """Collision of n cells fcells [n, K, Q] at coordinates xyz [n, 3] and time t
+    (homogenized toward the body if p.body == 2) -> fstar [n, K, Q]."""
+    fcells = np.ascontiguousarray(fcells, np.float64)
+    xyz = np.ascontiguousarray(xyz, np.int32)
+    out = np.empty_like(fcells)
+    lib().vref_collide_at(ctypes.byref(p), fcells.shape[0], _ptr(fcells),
+                          xyz.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), float(t), _ptr(out))
     return out
 
 

@@ -293,6 +293,15 @@ int vref_collide_many(const vref_params* p, long n, const double* f, double* fst
   return nbad;
 }
 
+int vref_collide_at(const vref_params* p, long n, const double* f, const int* xyz, double t, double* fstar) {
+  const int KQ = vref_nvars(p) * vref_ndirs(p);
+  int nbad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : nbad)
+  for (long j = 0; j < n; ++j)
+    nbad += collide_cell(p, f + j * KQ, fstar + j * KQ, NULL, p->body == 2 ? xyz + 3 * j : NULL, t);
+  return nbad;
+}
+
 static long ncells(const vref_params* p) { return (long)p->nx * p->ny * p->nz; }
 
 /* periodic neighbour of cell (x,y,z) along direction i */

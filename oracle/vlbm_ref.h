@@ -81,6 +81,9 @@ int vref_collide(const vref_params* p, const double* f /*[K][Q]*/, double* fstar
 
 /* vref_collide on n independent cells; f and fstar are [n][K][Q]. */
 int vref_collide_many(const vref_params* p, long n, const double* f, double* fstar);
+/* Collision of n cells at coordinates xyz [n][3] (time t): with the homogenized body
+ * (p->body == 2) each cell collides toward its homogenized state, else as above. */
+int vref_collide_at(const vref_params* p, long n, const double* f, const int* xyz, double t, double* fstar);
 
 /* f := f^eq(Q) everywhere. Q is [K][N], f is [K][Q][N]. */
 int vref_init(const vref_params* p, const double* Q, double* f);

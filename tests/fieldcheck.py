@@ -60,3 +60,21 @@ def oracle_one_step(oracle, op, pre_gather, cells, shape, dim):
     for i in range(NQ):
         out[:, :, i] = post[inv[:, i], :, i]
     return out
+
+
+def oracle_one_step_at(oracle, op, pre_gather, cells, shape, dim, t):
+    """As oracle_one_step, with each upstream cell collided at its own coordinates and
+    time t (the homogenized body's collision depends on where the cell is)."""
+    up = upstream_cells(cells, shape, dim)
+    uniq, inv = np.unique(up.ravel(), return_inverse=True)
+    pre = pre_gather(uniq)
+    nx, ny, _ = shape
+    xyz = np.stack([uniq % nx, (uniq // nx) % ny, uniq // (nx * ny)], axis=1)
+    post = oracle.collide_at(op, pre, xyz, t)
+    NQ = 2 * dim + 1
+    inv = inv.reshape(len(cells), NQ)
+    K = pre.shape[1]
+    out = np.empty((len(cells), K, NQ))
+    for i in range(NQ):
+        out[:, :, i] = post[inv[:, i], :, i]
+    return out
