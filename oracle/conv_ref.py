@@ -2,12 +2,14 @@
 (loaded by tests/, the smoke check and the CPU-baseline leg of the benchmark).
 
 The correction network is an extension of the method (it is not in the paper): a
-stack of 3x3 convolutions with periodic padding on the coarse moment field,
-GELU between layers, trained by mean-squared error with Adam.  Everything here is
-written as plain shifted sums over the 9 taps -- no blocking or fusion -- so it can
-be checked by eye:
+stack of 3x3 (2D lattices) or 3x3x3 (3D lattices) convolutions with periodic
+padding on the coarse moment field, GELU between layers, trained by mean-squared
+error with Adam.  Everything here is written as plain shifted sums over the 9 or 27
+taps -- no blocking or fusion -- so it can be checked by eye:
 
 * conv:   z[b,o,y,x] = bias[o] + sum_{c,ky,kx} W[o,c,ky,kx] a[b,c,(y+ky-1)%H,(x+kx-1)%W]
+* conv3:  z[b,o,z,y,x] = bias[o] + sum_{c,kz,ky,kx} W[o,c,kz,ky,kx] a[b,c,z+kz-1,y+ky-1,x+kx-1]
+          (every index periodic)
 * GELU:   g(z) = z Phi(z) (Phi the standard normal CDF), g'(z) = Phi(z) + z phi(z)
 * loss:   L = mean((y - t)^2)
 * Adam:   m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
@@ -75,24 +77,56 @@ def conv3x3_backward(a, W, dz):
     return da, dW, dz.sum(axis=(0, 2, 3))
 
 
+def conv3x3x3(a, W, bias):
+    """Periodic 3x3x3 convolution (cross-correlation).  a [B,C,D,H,W], W [O,C,3,3,3]."""
+    B, C, D, H, Wd = a.shape
+    O = W.shape[0]
+    z = np.zeros((B, O, D, H, Wd))
+    for kz in range(3):
+        for ky in range(3):
+            for kx in range(3):
+                # a[z+kz-1, y+ky-1, x+kx-1]
+                shifted = np.roll(a, shift=(-(kz - 1), -(ky - 1), -(kx - 1)), axis=(2, 3, 4))
+                z += np.einsum("oc,bczyx->bozyx", W[:, :, kz, ky, kx], shifted)
+    return z + bias[None, :, None, None, None]
+
+
+def conv3x3x3_backward(a, W, dz):
+    """Gradients of conv3x3x3: returns (da, dW, dbias)."""
+    dW = np.zeros_like(W)
+    da = np.zeros_like(a)
+    for kz in range(3):
+        for ky in range(3):
+            for kx in range(3):
+                off = (kz - 1, ky - 1, kx - 1)
+                shifted = np.roll(a, shift=tuple(-o for o in off), axis=(2, 3, 4))
+                dW[:, :, kz, ky, kx] = np.einsum("bozyx,bczyx->oc", dz, shifted)
+                back = np.einsum("oc,bozyx->bczyx", W[:, :, kz, ky, kx], dz)
+                da += np.roll(back, shift=off, axis=(2, 3, 4))  # opposite of the forward shift
+    return da, dW, dz.sum(axis=(0, 2, 3, 4))
+
+
 class Net:
-    """Layer widths cin -> width -> ... -> cout, `layers` convolutions.
+    """Layer widths cin -> width -> ... -> cout, `layers` convolutions; dim = 2
+    (3x3 kernels, fields [B,C,H,W]) or dim = 3 (3x3x3 kernels, fields [B,C,D,H,W]).
 
     quantize=True rounds the weights and every stored activation (network input,
     hidden activations) to bfloat16, as the GPU stores them; products and sums stay
     FP64."""
 
-    def __init__(self, params, cin=8, width=32, layers=4, cout=None, quantize=False):
+    def __init__(self, params, cin=8, width=32, layers=4, cout=None, quantize=False, dim=2):
         self.cin, self.width, self.layers = cin, width, layers
         self.cout = cin if cout is None else cout
         self.quantize = quantize
+        self.dim = dim
+        self.conv, self.conv_backward = (conv3x3, conv3x3_backward) if dim == 2 else (conv3x3x3, conv3x3x3_backward)
         self.params = [(np.asarray(W, np.float64), np.asarray(b, np.float64)) for W, b in params]
 
     @staticmethod
-    def shapes(cin=8, width=32, layers=4, cout=None):
+    def shapes(cin=8, width=32, layers=4, cout=None, dim=2):
         cout = cin if cout is None else cout
         dims = [cin] + [width] * (layers - 1) + [cout]
-        return [((dims[l + 1], dims[l], 3, 3), (dims[l + 1],)) for l in range(layers)]
+        return [((dims[l + 1], dims[l]) + (3,) * dim, (dims[l + 1],)) for l in range(layers)]
 
     def _q(self, a):
         return bf16_round(a) if self.quantize else a
@@ -101,7 +135,7 @@ class Net:
         a = self._q(x)
         cache = []
         for l, (W, b) in enumerate(self.params):
-            z = conv3x3(a, self._q(W), b)
+            z = self.conv(a, self._q(W), b)
             cache.append((a, z))
             if l < len(self.params) - 1:
                 a = self._q(gelu(z))
@@ -118,7 +152,7 @@ class Net:
         for l in range(len(self.params) - 1, -1, -1):
             a, z = cache[l]
             W, _ = self.params[l]
-            da, dW, db = conv3x3_backward(a, self._q(W), dz)
+            da, dW, db = self.conv_backward(a, self._q(W), dz)
             grads[l] = (dW, db)
             if l > 0:
                 _, zprev = cache[l - 1]

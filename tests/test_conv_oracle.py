@@ -1,7 +1,8 @@
 """Pins of the learned-correction oracle (oracle/conv_ref.py), CPU only.
 
 Library routines stand in as independent references: scipy's periodic correlation
-and torch's conv2d with circular padding for the convolution, torch's exact GELU,
+and torch's conv2d / conv3d with circular padding for the 3x3 and 3x3x3
+convolutions, torch's exact GELU,
 torch's bfloat16 rounding and torch's Adam; the gradients are checked by central
 finite differences in FP64.  Planted mistakes in a copy of the module source must
 make one of the checks fail."""
@@ -75,6 +76,56 @@ def chk_gradients_fd(mod=C):
     return worst
 
 
+def chk_conv3_vs_scipy(mod=C):
+    rng = np.random.default_rng(10)
+    a = rng.normal(size=(2, 3, 5, 4, 6))
+    W = rng.normal(size=(2, 3, 3, 3, 3))
+    b = rng.normal(size=2)
+    z = mod.conv3x3x3(a, W, b)
+    ref = np.zeros_like(z)
+    for bb in range(2):
+        for o in range(2):
+            ref[bb, o] = b[o] + sum(ndi.correlate(a[bb, c], W[o, c], mode="wrap") for c in range(3))
+    return np.abs(z - ref).max()
+
+
+def chk_conv3_vs_torch(mod=C):
+    rng = np.random.default_rng(11)
+    a = rng.normal(size=(2, 4, 3, 5, 7))
+    W = rng.normal(size=(3, 4, 3, 3, 3))
+    b = rng.normal(size=3)
+    z = mod.conv3x3x3(a, W, b)
+    t = torch.nn.functional.pad(torch.tensor(a), (1, 1, 1, 1, 1, 1), mode="circular")
+    ref = torch.nn.functional.conv3d(t, torch.tensor(W), torch.tensor(b)).numpy()
+    return np.abs(z - ref).max()
+
+
+def chk_gradients3_fd(mod=C):
+    """Central finite differences of the MSE loss of a small 2-layer 3D net."""
+    rng = np.random.default_rng(12)
+    params = [(rng.normal(0, 0.3, Ws), rng.normal(0, 0.1, bs)) for Ws, bs in C.Net.shapes(2, 3, 2, dim=3)]
+    x = rng.normal(size=(1, 2, 3, 4, 5))
+    t = rng.normal(size=(1, 2, 3, 4, 5))
+    _, grads = mod.Net(params, cin=2, width=3, layers=2, dim=3).loss_and_grads(x, t)
+    worst = 0.0
+    h = 1e-5
+    gscale = max(np.abs(g).max() for pair in grads for g in pair)
+    for l in range(2):
+        for j in range(2):
+            p = params[l][j]
+            g = grads[l][j]
+            for idx in [tuple(rng.integers(0, s) for s in p.shape) for _ in range(8)]:
+                old = p[idx]
+                p[idx] = old + h
+                lp, _ = mod.Net(params, cin=2, width=3, layers=2, dim=3).loss_and_grads(x, t)
+                p[idx] = old - h
+                lm, _ = mod.Net(params, cin=2, width=3, layers=2, dim=3).loss_and_grads(x, t)
+                p[idx] = old
+                fd = (lp - lm) / (2 * h)
+                worst = max(worst, abs(fd - g[idx]) / max(abs(fd), 1e-3 * gscale))
+    return worst
+
+
 def chk_gelu_vs_torch(mod=C):
     z = np.linspace(-6, 6, 241)
     ref = torch.nn.functional.gelu(torch.tensor(z)).numpy()  # exact (erf) GELU
@@ -115,6 +166,46 @@ def test_identity_kernel():
     for c in range(4):
         W[c, c, 1, 1] = 1.0
     assert np.array_equal(C.conv3x3(a, W, np.zeros(4)), a)
+
+
+def test_conv3_matches_scipy_periodic_correlation():
+    assert chk_conv3_vs_scipy() < 1e-12
+
+
+def test_conv3_matches_torch_circular_conv3d():
+    assert chk_conv3_vs_torch() < 1e-12
+
+
+def test_conv3_identity_kernel_and_planar_kernel():
+    """The centre tap as identity reproduces the input; a kernel confined to the
+    kz = 1 plane acts as the 2D convolution on every z-slice."""
+    rng = np.random.default_rng(13)
+    a = rng.normal(size=(2, 3, 4, 5, 6))
+    W = np.zeros((3, 3, 3, 3, 3))
+    for c in range(3):
+        W[c, c, 1, 1, 1] = 1.0
+    assert np.array_equal(C.conv3x3x3(a, W, np.zeros(3)), a)
+    W2 = rng.normal(size=(2, 3, 3, 3))
+    b = rng.normal(size=2)
+    W3 = np.zeros((2, 3, 3, 3, 3))
+    W3[:, :, 1] = W2
+    z3 = C.conv3x3x3(a, W3, b)
+    for zz in range(4):
+        assert np.abs(z3[:, :, zz] - C.conv3x3(a[:, :, zz], W2, b)).max() < 1e-12
+
+
+def test_conv3_translation_equivariance():
+    rng = np.random.default_rng(14)
+    a = rng.normal(size=(1, 2, 4, 5, 3))
+    W = rng.normal(size=(2, 2, 3, 3, 3))
+    b = rng.normal(size=2)
+    z = C.conv3x3x3(a, W, b)
+    zs = C.conv3x3x3(np.roll(a, (1, 2, -1), axis=(2, 3, 4)), W, b)
+    assert np.abs(zs - np.roll(z, (1, 2, -1), axis=(2, 3, 4))).max() < 1e-12
+
+
+def test_gradients3_finite_differences():
+    assert chk_gradients3_fd() < 1e-7
 
 
 def test_gradients_finite_differences():
@@ -171,6 +262,14 @@ MUTATIONS = {
                         "shifted = np.roll(a, shift=((ky - 1), (kx - 1)), axis=(2, 3))  # a[y+ky-1, x+kx-1]"),
     "backward_scatter_sign": ("da += np.roll(back, shift=(ky - 1, kx - 1), axis=(2, 3))",
                               "da += np.roll(back, shift=(-(ky - 1), -(kx - 1)), axis=(2, 3))"),
+    "conv3_shift_sign": ("shifted = np.roll(a, shift=(-(kz - 1), -(ky - 1), -(kx - 1)), axis=(2, 3, 4))",
+                         "shifted = np.roll(a, shift=(-(kz - 1), (ky - 1), -(kx - 1)), axis=(2, 3, 4))"),
+    "conv3_axes_swapped": ("z += np.einsum(\"oc,bczyx->bozyx\", W[:, :, kz, ky, kx], shifted)",
+                           "z += np.einsum(\"oc,bczyx->bozyx\", W[:, :, kx, ky, kz], shifted)"),
+    "backward3_scatter_sign": ("da += np.roll(back, shift=off, axis=(2, 3, 4))",
+                               "da += np.roll(back, shift=tuple(-o for o in off), axis=(2, 3, 4))"),
+    "backward3_weight_transposed": ("back = np.einsum(\"oc,bozyx->bczyx\", W[:, :, kz, ky, kx], dz)",
+                                    "back = np.einsum(\"oc,bozyx->bczyx\", W[:, :, 2 - kz, ky, kx], dz)"),
     "gelu_grad_pdf_dropped": ("return cdf + z * pdf", "return cdf"),
     "loss_scale": ("dz = 2.0 * (y - t) / n", "dz = 1.0 * (y - t) / n"),
     "adam_bias_correction": ("new.append(p - self.lr * (m / c1) / (np.sqrt(v / c2) + self.eps))",
@@ -191,6 +290,7 @@ def test_conv_pins_catch_planted_mistake(name):
     assert src.count(old) == 1, name
     mod = _load_variant(src.replace(old, new))
     failed = (chk_conv_vs_scipy(mod) > 1e-12 or chk_conv_vs_torch(mod) > 1e-12
-              or chk_gradients_fd(mod) > 1e-7 or chk_gelu_vs_torch(mod) > 1e-12
-              or chk_adam_vs_torch(mod) > 1e-12)
+              or chk_conv3_vs_scipy(mod) > 1e-12 or chk_conv3_vs_torch(mod) > 1e-12
+              or chk_gradients_fd(mod) > 1e-7 or chk_gradients3_fd(mod) > 1e-7
+              or chk_gelu_vs_torch(mod) > 1e-12 or chk_adam_vs_torch(mod) > 1e-12)
     assert failed, name
