@@ -66,25 +66,30 @@ __device__ __forceinline__ float gelu_grad(float z) {
 // input channels CIN and outputs n < COUT.
 // Data gradient (flip = 1) of a layer with weights W[o][c][tap] (o < CO, c < CI): a
 // convolution of dZ (CI' = CO input channels) producing CO' = CI outputs with
-// B[k = tap' * CO + o][n = c] = W[o][c][8 - tap'] (taps mirrored: offset -> -offset).
-__global__ void k_pack(const float* __restrict__ W, int CI, int CO, int flip, bf16_t* __restrict__ out) {
+// B[k = tap' * CO + o][n = c] = W[o][c][ntap - 1 - tap'] (taps mirrored: offset -> -offset).
+// ntap = 9 (3x3) or 27 (3x3x3, tap = 9 kz + 3 ky + kx): the 27 taps are packed as three
+// z-slabs of the 3x3 layout, slab kz at offset kz * ksteps * ntiles * 512.
+__global__ void k_pack(const float* __restrict__ W, int CI, int CO, int flip, int ntap, bf16_t* __restrict__ out) {
   const int cin = flip ? CO : CI;    // input channels of the packed convolution
   const int cout = flip ? CI : CO;   // its output channels
   const int KS = ksteps(cin), NT = ntiles(cout);
-  const int total = KS * NT * 64 * 8;
+  const int per_slab = KS * NT * 64 * 8;
+  const int total = (ntap / 9) * per_slab;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= total) return;
-  const int e = q & 7, lane = (q >> 3) & 63, st = q >> 9;
+  const int slab = q / per_slab, qs = q % per_slab;
+  const int e = qs & 7, lane = (qs >> 3) & 63, st = qs >> 9;
   const int t = st % NT, s = st / NT;
   const int k = 32 * s + 8 * (lane >> 4) + e;
   const int n = 16 * t + (lane & 15);
-  const int tap = k / cin, c = k % cin;
+  const int tap2 = k / cin, c = k % cin;
   float v = 0.0f;
-  if (tap < 9 && n < cout) {
+  if (tap2 < 9 && n < cout) {
+    const int tap = 9 * slab + tap2;
     if (!flip)
-      v = W[((size_t)n * CI + c) * 9 + tap];
+      v = W[((size_t)n * CI + c) * ntap + tap];
     else
-      v = W[((size_t)c * CI + n) * 9 + (8 - tap)];  // W[o = c][c_in = n][8 - tap]
+      v = W[((size_t)c * CI + n) * ntap + (ntap - 1 - tap)];  // W[o = c][c_in = n][mirrored tap]
   }
   out[q] = f2bf(v);
 }
@@ -92,13 +97,16 @@ __global__ void k_pack(const float* __restrict__ W, int CI, int CO, int flip, bf
 // ---------------------------------------------------------------------------
 // convolution (forward, and data gradient with the mirrored packed weights)
 // ---------------------------------------------------------------------------
-// act: BF16 NHWC [B][H][W][CIN].  Output, by MODE:
+// act: BF16 channels-last [S][H][W][CIN] over S = B * D slices (D = 1: a batch of 2D
+// lattices; D > 1: B 3D lattices of D slices each, periodic in z).  NZT = 1 for the
+// 3x3 kernel, 3 for the 3x3x3 kernel (the halos of slices z-1, z, z+1 are staged
+// and the packed weights of each z-slab are loaded in turn).  Output, by MODE:
 //  HIDDEN: z = conv + bias; out_act (BF16 NHWC COUT) = GELU(z); out_z (FP32 NHWC, optional) = z
 //  LAST:   out_z (FP32 channel-major [COUT][B][H][W]) = (conv + bias) * oscale + oshift
 //  BWD:    out_act (BF16 NHWC COUT) = conv * GELU'(zprev), zprev FP32 NHWC COUT
-template <int CIN, int COUT, int MODE>
+template <int CIN, int COUT, int MODE, int NZT>
 __global__ __launch_bounds__(kThreads) void k_conv(const bf16_t* __restrict__ act, const bf16_t* __restrict__ wpack,
-                                                   const float* __restrict__ bias, int H, int W,
+                                                   const float* __restrict__ bias, int D, int H, int W,
                                                    bf16_t* __restrict__ out_act, float* __restrict__ out_z,
                                                    const float* __restrict__ zprev,
                                                    const float* __restrict__ oscale,
@@ -106,17 +114,22 @@ __global__ __launch_bounds__(kThreads) void k_conv(const bf16_t* __restrict__ ac
   constexpr int KS = (9 * CIN + 31) / 32;
   constexpr int NT = (COUT + 15) / 16;
   constexpr int CH = CIN / 8;
-  __shared__ __attribute__((aligned(16))) bf16_t tile[HALO * HALO * CIN];
-  const int b = blockIdx.z, ty0 = blockIdx.y * TILE, tx0 = blockIdx.x * TILE;
-  for (int q = threadIdx.x; q < HALO * HALO * CH; q += kThreads) {
-    const int pix = q / CH, ch = q % CH;
+  __shared__ __attribute__((aligned(16))) bf16_t tile[NZT * HALO * HALO * CIN];
+  const int sl = blockIdx.z, ty0 = blockIdx.y * TILE, tx0 = blockIdx.x * TILE;
+  const int zl = sl % D, zbase = sl - zl;  // slice within its lattice, first slice of the lattice
+  for (int q = threadIdx.x; q < NZT * HALO * HALO * CH; q += kThreads) {
+    const int zs = q / (HALO * HALO * CH), r = q % (HALO * HALO * CH);
+    const int pix = r / CH, ch = r % CH;
     const int hy = pix / HALO, hx = pix % HALO;
+    int gz = zl + zs - NZT / 2;
     int gy = ty0 - 1 + hy;
     int gx = tx0 - 1 + hx;
+    gz = gz < 0 ? gz + D : (gz >= D ? gz - D : gz);
     gy = gy < 0 ? gy + H : (gy >= H ? gy - H : gy);
     gx = gx < 0 ? gx + W : (gx >= W ? gx - W : gx);
-    const uint4 v = *reinterpret_cast<const uint4*>(act + (((size_t)b * H + gy) * W + gx) * CIN + ch * 8);
-    *reinterpret_cast<uint4*>(tile + pix * CIN + ch * 8) = v;
+    const uint4 v =
+        *reinterpret_cast<const uint4*>(act + (((size_t)(zbase + gz) * H + gy) * W + gx) * CIN + ch * 8);
+    *reinterpret_cast<uint4*>(tile + (zs * HALO * HALO + pix) * CIN + ch * 8) = v;
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   bf16x8 bw[KS][NT];
@@ -134,26 +147,38 @@ __global__ __launch_bounds__(kThreads) void k_conv(const bf16_t* __restrict__ ac
     for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
   const int px = lane & 15, g = lane >> 4;
+#pragma unroll 1
+  for (int zs = 0; zs < NZT; ++zs) {
+    if (zs > 0) {  // weights of the next z-slab
 #pragma unroll
-  for (int s = 0; s < KS; ++s) {
+      for (int s = 0; s < KS; ++s)
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int py = 4 * wv + m;
-      bf16x8 a;
-      if constexpr (CIN == 32) {
-        const int dy = s / 3, dx = s % 3;
-        a = *reinterpret_cast<const bf16x8*>(tile + ((py + dy) * HALO + px + dx) * CIN + 8 * g);
-      } else {
-        const int tap = 4 * s + g;  // 8 input channels: 4 taps per K step
-        if (tap < 9) {
-          const int dy = tap / 3, dx = tap % 3;
-          a = *reinterpret_cast<const bf16x8*>(tile + ((py + dy) * HALO + px + dx) * CIN);
+        for (int t = 0; t < NT; ++t)
+          bw[s][t] = *reinterpret_cast<const bf16x8*>(wpack + ((size_t)((zs * KS + s) * NT + t) * 64 + lane) * 8);
+    }
+    const bf16_t* tz = tile + zs * HALO * HALO * CIN;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int py = 4 * wv + m;
+        bf16x8 a;
+        if constexpr (CIN == 32) {
+          const int dy = s / 3, dx = s % 3;
+          a = *reinterpret_cast<const bf16x8*>(tz + ((py + dy) * HALO + px + dx) * CIN + 8 * g);
         } else {
-          a = bf16x8{};  // zero padding of K
+          const int tap = 4 * s + g;  // 8 input channels: 4 taps per K step
+          if (tap < 9) {
+            const int dy = tap / 3, dx = tap % 3;
+            a = *reinterpret_cast<const bf16x8*>(tz + ((py + dy) * HALO + px + dx) * CIN);
+          } else {
+            a = bf16x8{};  // zero padding of K
+          }
         }
-      }
 #pragma unroll
-      for (int t = 0; t < NT; ++t) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[s][t], acc[m][t], 0, 0, 0);
+        for (int t = 0; t < NT; ++t)
+          acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[s][t], acc[m][t], 0, 0, 0);
+      }
     }
   }
 
@@ -168,14 +193,14 @@ __global__ __launch_bounds__(kThreads) void k_conv(const bf16_t* __restrict__ ac
       for (int r = 0; r < 4; ++r) {
         const int x = tx0 + 4 * g + r;
         const float v = acc[m][t][r];
-        const size_t nhwc = (((size_t)b * H + y) * W + x) * COUT + co;
+        const size_t nhwc = (((size_t)sl * H + y) * W + x) * COUT + co;
         if constexpr (MODE == MODE_HIDDEN) {
           const float z = v + bias[co];
           out_act[nhwc] = f2bf(gelu(z));
           if (out_z) out_z[nhwc] = z;
         } else if constexpr (MODE == MODE_LAST) {
           const float z = v + bias[co];
-          out_z[(((size_t)co * gridDim.z + b) * H + y) * W + x] = z * oscale[co] + oshift[co];
+          out_z[(((size_t)co * gridDim.z + sl) * H + y) * W + x] = z * oscale[co] + oshift[co];
         } else {
           out_act[nhwc] = f2bf(v * gelu_grad(zprev[nhwc]));
         }
@@ -188,13 +213,16 @@ __global__ __launch_bounds__(kThreads) void k_conv(const bf16_t* __restrict__ ac
 // weight gradient: dW[o][c][tap] = sum_{b,p} dZ[b,p,o] act[b, p + off(tap), c];
 // db[o] = sum dZ.  GEMM with M = o, N = (tap, c), K = positions; each workgroup
 // accumulates over a fixed set of tiles and writes one partial (reduced later in a
-// fixed order, so the result is deterministic).
+// fixed order, so the result is deterministic).  Positions run over S slices of
+// D-slice lattices (as k_conv); blockIdx.y selects the z-slab of a 3x3x3 kernel
+// (gridDim.y = 3; taps 9 kz + 3 ky + kx, columns of the partial tap * CIN + c over
+// all 27 taps) or is 0 for the 3x3 kernel (gridDim.y = 1).
 // ---------------------------------------------------------------------------
 template <int CIN, int COUT>
 __global__ __launch_bounds__(kThreads) void k_conv_bw(const bf16_t* __restrict__ act, const bf16_t* __restrict__ dz,
-                                                      int B, int H, int W, float* __restrict__ part_w,
+                                                      int S, int D, int H, int W, float* __restrict__ part_w,
                                                       float* __restrict__ part_b) {
-  constexpr int NJ = 9 * CIN;
+  constexpr int NJ = 9 * CIN;  // columns of this z-slab
   constexpr int NTJ = (NJ + 15) / 16;
   constexpr int MT = (COUT + 15) / 16;
   constexpr int NTW = (NTJ + 3) / 4;  // N tiles per wavefront
@@ -207,12 +235,17 @@ __global__ __launch_bounds__(kThreads) void k_conv_bw(const bf16_t* __restrict__
 #pragma unroll
     for (int u = 0; u < NTW; ++u) acc[mt][u] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   float db = 0.0f;
+  const int slab = blockIdx.y, nslab = gridDim.y;
   const int tiles_x = W / TILE, tiles_y = H / TILE;
-  const int ntile = B * tiles_x * tiles_y;
+  const int ntile = S * tiles_x * tiles_y;
   for (int tid = blockIdx.x; tid < ntile; tid += gridDim.x) {
-    const int b = tid / (tiles_x * tiles_y);
+    const int sl = tid / (tiles_x * tiles_y);
     const int rem = tid % (tiles_x * tiles_y);
     const int ty0 = (rem / tiles_x) * TILE, tx0 = (rem % tiles_x) * TILE;
+    const int zl = sl % D;
+    int gz = zl + slab - nslab / 2;
+    gz = gz < 0 ? gz + D : (gz >= D ? gz - D : gz);
+    const int asl = sl - zl + gz;  // input slice of this z-slab
     __syncthreads();  // previous tile fully consumed
     for (int q = threadIdx.x; q < HALO * HALO * (CIN / 8); q += kThreads) {
       const int pix = q / (CIN / 8), ch = q % (CIN / 8);
@@ -221,7 +254,7 @@ __global__ __launch_bounds__(kThreads) void k_conv_bw(const bf16_t* __restrict__
       int gx = tx0 - 1 + hx;
       gy = gy < 0 ? gy + H : (gy >= H ? gy - H : gy);
       gx = gx < 0 ? gx + W : (gx >= W ? gx - W : gx);
-      const uint4 v = *reinterpret_cast<const uint4*>(act + (((size_t)b * H + gy) * W + gx) * CIN + ch * 8);
+      const uint4 v = *reinterpret_cast<const uint4*>(act + (((size_t)asl * H + gy) * W + gx) * CIN + ch * 8);
       const bf16_t* e = reinterpret_cast<const bf16_t*>(&v);
 #pragma unroll
       for (int j = 0; j < 8; ++j) aT[((ch * 8 + j) * HALO + hy) * HALO + hx] = e[j];
@@ -229,10 +262,10 @@ __global__ __launch_bounds__(kThreads) void k_conv_bw(const bf16_t* __restrict__
     for (int q = threadIdx.x; q < MT * 16 * TILE * TILE; q += kThreads) {
       const int o = q / (TILE * TILE), p = q % (TILE * TILE);
       const int y = ty0 + p / TILE, x = tx0 + p % TILE;
-      dzT[q] = o < COUT ? dz[(((size_t)b * H + y) * W + x) * COUT + o] : (bf16_t)0;
+      dzT[q] = o < COUT ? dz[(((size_t)sl * H + y) * W + x) * COUT + o] : (bf16_t)0;
     }
     __syncthreads();
-    if ((int)threadIdx.x < COUT) {
+    if (slab == 0 && (int)threadIdx.x < COUT) {
       float sacc = 0.0f;
       for (int p = 0; p < TILE * TILE; ++p) sacc += bf2f(dzT[threadIdx.x * TILE * TILE + p]);
       db += sacc;
@@ -275,21 +308,23 @@ __global__ __launch_bounds__(kThreads) void k_conv_bw(const bf16_t* __restrict__
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int o = 16 * mt + 4 * g + r;
-        if (o < COUT && j < NJ) part_w[((size_t)blockIdx.x * COUT + o) * NJ + j] = acc[mt][u][r];
+        if (o < COUT && j < NJ)
+          part_w[((size_t)blockIdx.x * COUT + o) * (nslab * NJ) + slab * NJ + j] = acc[mt][u][r];
       }
     }
-  if ((int)threadIdx.x < COUT) part_b[(size_t)blockIdx.x * COUT + threadIdx.x] = db;
+  if (slab == 0 && (int)threadIdx.x < COUT) part_b[(size_t)blockIdx.x * COUT + threadIdx.x] = db;
 }
 
 // Sum the partials in block order into the master-layout gradient:
-// grad_W[o][c][tap] = sum_blk part_w[blk][o][tap * CIN + c]; grad_b[o] = sum part_b.
+// grad_W[o][c][tap] = sum_blk part_w[blk][o][tap * CIN + c]; grad_b[o] = sum part_b
+// (ntap = 9 or 27 taps).
 __global__ void k_reduce_grads(const float* __restrict__ part_w, const float* __restrict__ part_b, int nblk,
-                               int CIN, int COUT, float* __restrict__ gW, float* __restrict__ gb) {
-  const int NJ = 9 * CIN;
+                               int CIN, int COUT, int ntap, float* __restrict__ gW, float* __restrict__ gb) {
+  const int NJ = ntap * CIN;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q < COUT * NJ) {
-    const int o = q / NJ, rem = q % NJ;  // rem = c * 9 + tap in master order
-    const int c = rem / 9, tap = rem % 9;
+    const int o = q / NJ, rem = q % NJ;  // rem = c * ntap + tap in master order
+    const int c = rem / ntap, tap = rem % ntap;
     const int j = tap * CIN + c;
     float s = 0.0f;
     for (int blk = 0; blk < nblk; ++blk) s += part_w[((size_t)blk * COUT + o) * NJ + j];
@@ -397,23 +432,39 @@ struct Dec<vlbm::ST_F32> {
   static __device__ double get(T v, const vlbm::Codec&, int) { return v; }
 };
 
+// Cells x - e_i (periodic) for i = 0..2D (rest, +x, -x, +y, -y[, +z, -z]) of cell c.
+// D = 2: the grid is a batch of independent 2D lattices along z; D = 3: one 3D lattice.
+template <int D>
+__device__ inline void upwind_cells(const vlbm::Grid& g, size_t c, size_t* up) {
+  const size_t nxy = (size_t)g.nx * g.ny;
+  const int x = (int)(c % g.nx), y = (int)((c / g.nx) % g.ny), z = (int)(c / nxy);
+  const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x + 1 == g.nx ? 0 : x + 1;
+  const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y + 1 == g.ny ? 0 : y + 1;
+  const size_t sl = (size_t)z * nxy;
+  up[0] = c;
+  up[1] = sl + (size_t)y * g.nx + xm;
+  up[2] = sl + (size_t)y * g.nx + xp;
+  up[3] = sl + (size_t)ym * g.nx + x;
+  up[4] = sl + (size_t)yp * g.nx + x;
+  if constexpr (D == 3) {
+    const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z + 1 == g.nz ? 0 : z + 1;
+    const size_t r = (size_t)y * g.nx + x;
+    up[5] = (size_t)zm * nxy + r;
+    up[6] = (size_t)zp * nxy + r;
+  }
+}
+
 // X = moments of the populations at the given parity (+ flag * pending dQ), FP32
-template <int ST>
+template <int ST, int D>
 __global__ void k_moments_x(const vlbm::Grid g, const vlbm::Codec cd, int parity, const float* __restrict__ dq,
                             const int* __restrict__ flag, float* __restrict__ X) {
   using T = typename Dec<ST>::T;
-  constexpr int K = 8, NQ = 5;
+  constexpr int K = 8, NQ = 2 * D + 1;
   const size_t N = (size_t)g.nx * g.ny * g.nz;
   const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= N) return;
-  // batch of independent 2D lattices along z
-  const size_t sl = (c / ((size_t)g.nx * g.ny)) * g.nx * g.ny;
-  const int x = (int)(c % g.nx), y = (int)((c / g.nx) % g.ny);
-  const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x + 1 == g.nx ? 0 : x + 1;
-  const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y + 1 == g.ny ? 0 : y + 1;
-  // cell x - e_i for i = 0..4 (rest, +x, -x, +y, -y)
-  const size_t up[NQ] = {c, sl + (size_t)y * g.nx + xm, sl + (size_t)y * g.nx + xp, sl + (size_t)ym * g.nx + x,
-                         sl + (size_t)yp * g.nx + x};
+  size_t up[NQ];
+  upwind_cells<D>(g, c, up);
   const T* F = static_cast<const T*>(g.f);
   const bool add = flag && *flag;
   for (int k = 0; k < K; ++k) {
@@ -430,24 +481,20 @@ __global__ void k_moments_x(const vlbm::Grid g, const vlbm::Codec cd, int parity
 }
 
 // add w_i dQ_k to every population at the given parity, if *flag (or flag is NULL)
-template <int ST>
+template <int ST, int D>
 __global__ void k_inject(const vlbm::Grid g, int parity, const float* __restrict__ dq, const int* __restrict__ flag,
                          double wi_d) {
   using T = typename Dec<ST>::T;
-  constexpr int K = 8, NQ = 5;
+  constexpr int K = 8, NQ = 2 * D + 1;
   const size_t N = (size_t)g.nx * g.ny * g.nz;
   const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= N || (flag && !*flag)) return;
-  const size_t sl = (c / ((size_t)g.nx * g.ny)) * g.nx * g.ny;
-  const int x = (int)(c % g.nx), y = (int)((c / g.nx) % g.ny);
-  const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x + 1 == g.nx ? 0 : x + 1;
-  const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y + 1 == g.ny ? 0 : y + 1;
-  const size_t up[NQ] = {c, sl + (size_t)y * g.nx + xm, sl + (size_t)y * g.nx + xp, sl + (size_t)ym * g.nx + x,
-                         sl + (size_t)yp * g.nx + x};
+  size_t up[NQ];
+  upwind_cells<D>(g, c, up);
   T* F = static_cast<T*>(g.f);
   // same weights, in the same type, as the injecting sweep
   const T wi = (T)wi_d;
-  const T w0 = vlbm::rest_weight<T, 2>(wi);
+  const T w0 = vlbm::rest_weight<T, D>(wi);
   for (int k = 0; k < K; ++k) {
     const T d = (T)dq[(size_t)k * N + c];
     for (int i = 0; i < NQ; ++i) {
@@ -468,6 +515,8 @@ struct GateBounds {
 // all keep each lattice's totals of rho, rho u, E and B (up to the Powell source), so
 // the correction they define has zero total; projecting the prediction onto that keeps
 // a small bias of the network from accumulating in the totals over many steps.
+// nb lattices of nxy cells each (a batch of 2D lattices, or one 3D lattice: nb = 1,
+// nxy = all its cells).
 // Pass 1: FP64 partial sums of dq[k] over chunks of kCenterChunk cells of lattice b,
 // partial[(k * nb + b) * nchunk + chunk]; pass 2: every cell subtracts the mean of its
 // (k, b) from the partials.  No buffer needs clearing, so both passes can be captured.
@@ -498,16 +547,19 @@ __global__ __launch_bounds__(256) void k_center_apply(float* __restrict__ dq, in
 }
 
 // per-block FP64 partials: [0..7] sum dQ_k^2, [8] sum divc(X)^2, [9] sum divc(X + dQ)^2,
-// [10] non-finite count, [11] sum |B(X)|^2 (in-plane components)
+// [10] non-finite count, [11] sum |B(X)|^2 (the D components the divergence sees).
+// D = 2: nz lattices of nx x ny (divergence of the in-plane field); D = 3: one
+// nx x ny x nz lattice.
+template <int D>
 __global__ __launch_bounds__(kGateThreads) void k_gate_partials(const float* __restrict__ X, const float* __restrict__ dq,
-                                                                int nx, int ny, int nb, double* __restrict__ partial) {
+                                                                int nx, int ny, int nz, double* __restrict__ partial) {
   constexpr int NP = 12;
   __shared__ double sh[kGateThreads / 64][NP];
-  const size_t N = (size_t)nx * ny * nb;
+  const size_t N = (size_t)nx * ny * nz;
   double acc[NP];
   for (int j = 0; j < NP; ++j) acc[j] = 0.0;
   for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (size_t)gridDim.x * blockDim.x) {
-    const size_t sl = (c / ((size_t)nx * ny)) * nx * ny;  // batch slice
+    const size_t sl = (c / ((size_t)nx * ny)) * nx * ny;  // z-slice
     const int x = (int)(c % nx), y = (int)((c / nx) % ny);
     const size_t xp = sl + (size_t)y * nx + (x + 1 == nx ? 0 : x + 1), xm = sl + (size_t)y * nx + (x == 0 ? nx - 1 : x - 1);
     const size_t yp = sl + (size_t)(y + 1 == ny ? 0 : y + 1) * nx + x, ym = sl + (size_t)(y == 0 ? ny - 1 : y - 1) * nx + x;
@@ -520,11 +572,22 @@ __global__ __launch_bounds__(kGateThreads) void k_gate_partials(const float* __r
     const float* By = X + 6 * N;
     const float* dBx = dq + 5 * N;
     const float* dBy = dq + 6 * N;
-    const double dv = 0.5 * ((double)Bx[xp] - Bx[xm]) + 0.5 * ((double)By[yp] - By[ym]);
-    const double dv2 = dv + 0.5 * ((double)dBx[xp] - dBx[xm]) + 0.5 * ((double)dBy[yp] - dBy[ym]);
+    double dv = 0.5 * ((double)Bx[xp] - Bx[xm]) + 0.5 * ((double)By[yp] - By[ym]);
+    double ddv = 0.5 * ((double)dBx[xp] - dBx[xm]) + 0.5 * ((double)dBy[yp] - dBy[ym]);
+    double b2 = (double)Bx[c] * Bx[c] + (double)By[c] * By[c];
+    if constexpr (D == 3) {
+      const size_t nxy = (size_t)nx * ny, r = c - sl, z = c / nxy;
+      const size_t zp = (z + 1 == (size_t)nz ? 0 : z + 1) * nxy + r, zm = (z == 0 ? nz - 1 : z - 1) * nxy + r;
+      const float* Bz = X + 7 * N;
+      const float* dBz = dq + 7 * N;
+      dv += 0.5 * ((double)Bz[zp] - Bz[zm]);
+      ddv += 0.5 * ((double)dBz[zp] - dBz[zm]);
+      b2 += (double)Bz[c] * Bz[c];
+    }
+    const double dv2 = dv + ddv;
     acc[8] += dv * dv;
     acc[9] += dv2 * dv2;
-    acc[11] += (double)Bx[c] * Bx[c] + (double)By[c] * By[c];
+    acc[11] += b2;
   }
   for (int j = 0; j < NP; ++j) {
     for (int off = 32; off > 0; off >>= 1) acc[j] += __shfl_xor(acc[j], off);
@@ -563,6 +626,7 @@ __global__ __launch_bounds__(64) void k_gate_final(const double* __restrict__ pa
 // C ABI
 // ---------------------------------------------------------------------------
 struct vlbm_nn {
+  int dim = 2, ntap = 9, nzt = 1;  // 3x3 (dim 2) or 3x3x3 (dim 3) kernels; nzt = ntap / 9
   int cin = 0, width = 0, layers = 0;
   int ci[kMaxLayers] = {}, co[kMaxLayers] = {};
   size_t woff[kMaxLayers] = {}, boff[kMaxLayers] = {};  // offsets into the flat parameter vector
@@ -616,60 +680,75 @@ vlbm_status nfail(vlbm_nn* nn, vlbm_status s, const char* fmt, ...) {
                    hipGetErrorString(e_));                                                                 \
   } while (0)
 
-size_t packed_elems(int cin, int cout) { return (size_t)ksteps(cin) * ntiles(cout) * 64 * 8; }
+size_t packed_elems(int cin, int cout, int nzt) { return (size_t)nzt * ksteps(cin) * ntiles(cout) * 64 * 8; }
 
-hipError_t launch_conv(int cin, int cout, int mode, const bf16_t* act, const bf16_t* wpack, const float* bias,
-                       int B, int H, int W, bf16_t* out_act, float* out_z, const float* zprev,
-                       const float* oscale, const float* oshift, hipStream_t s) {
-  const dim3 grd(W / TILE, H / TILE, B), blk(kThreads);
-#define CONV_CASE(CI, CO, M)                                                                          \
-  if (cin == CI && cout == CO && mode == M) {                                                        \
-    hipLaunchKernelGGL((k_conv<CI, CO, M>), grd, blk, 0, s, act, wpack, bias, H, W, out_act, out_z, \
-                       zprev, oscale, oshift);                                                      \
-    return hipGetLastError();                                                                       \
+// S slices of D-slice lattices (D = 1 for 2D lattices); nzt = 1 (3x3) or 3 (3x3x3)
+hipError_t launch_conv(int cin, int cout, int mode, int nzt, const bf16_t* act, const bf16_t* wpack,
+                       const float* bias, int S, int D, int H, int W, bf16_t* out_act, float* out_z,
+                       const float* zprev, const float* oscale, const float* oshift, hipStream_t s) {
+  const dim3 grd(W / TILE, H / TILE, S), blk(kThreads);
+#define CONV_CASE(CI, CO, M, Z)                                                                          \
+  if (cin == CI && cout == CO && mode == M && nzt == Z) {                                               \
+    hipLaunchKernelGGL((k_conv<CI, CO, M, Z>), grd, blk, 0, s, act, wpack, bias, D, H, W, out_act, out_z, \
+                       zprev, oscale, oshift);                                                         \
+    return hipGetLastError();                                                                          \
   }
-  CONV_CASE(8, 32, MODE_HIDDEN)
-  CONV_CASE(32, 32, MODE_HIDDEN)
-  CONV_CASE(32, 8, MODE_LAST)
-  CONV_CASE(8, 8, MODE_LAST)
-  CONV_CASE(8, 32, MODE_BWD)
-  CONV_CASE(32, 32, MODE_BWD)
+#define CONV_CASES(Z)             \
+  CONV_CASE(8, 32, MODE_HIDDEN, Z)  \
+  CONV_CASE(32, 32, MODE_HIDDEN, Z) \
+  CONV_CASE(32, 8, MODE_LAST, Z)    \
+  CONV_CASE(8, 8, MODE_LAST, Z)     \
+  CONV_CASE(8, 32, MODE_BWD, Z)     \
+  CONV_CASE(32, 32, MODE_BWD, Z)
+  CONV_CASES(1)
+  CONV_CASES(3)
+#undef CONV_CASES
 #undef CONV_CASE
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_conv_bw(int cin, int cout, const bf16_t* act, const bf16_t* dz, int B, int H, int W,
-                          float* part_w, float* part_b, int nblk, hipStream_t s) {
-  const dim3 grd(nblk), blk(kThreads);
-  if (cin == 8 && cout == 32) hipLaunchKernelGGL((k_conv_bw<8, 32>), grd, blk, 0, s, act, dz, B, H, W, part_w, part_b);
-  else if (cin == 32 && cout == 32) hipLaunchKernelGGL((k_conv_bw<32, 32>), grd, blk, 0, s, act, dz, B, H, W, part_w, part_b);
-  else if (cin == 32 && cout == 8) hipLaunchKernelGGL((k_conv_bw<32, 8>), grd, blk, 0, s, act, dz, B, H, W, part_w, part_b);
-  else if (cin == 8 && cout == 8) hipLaunchKernelGGL((k_conv_bw<8, 8>), grd, blk, 0, s, act, dz, B, H, W, part_w, part_b);
-  else return hipErrorInvalidValue;
+hipError_t launch_conv_bw(int cin, int cout, int nzt, const bf16_t* act, const bf16_t* dz, int S, int D, int H,
+                          int W, float* part_w, float* part_b, int nblk, hipStream_t s) {
+  const dim3 grd(nblk, nzt), blk(kThreads);
+  if (cin == 8 && cout == 32)
+    hipLaunchKernelGGL((k_conv_bw<8, 32>), grd, blk, 0, s, act, dz, S, D, H, W, part_w, part_b);
+  else if (cin == 32 && cout == 32)
+    hipLaunchKernelGGL((k_conv_bw<32, 32>), grd, blk, 0, s, act, dz, S, D, H, W, part_w, part_b);
+  else if (cin == 32 && cout == 8)
+    hipLaunchKernelGGL((k_conv_bw<32, 8>), grd, blk, 0, s, act, dz, S, D, H, W, part_w, part_b);
+  else if (cin == 8 && cout == 8)
+    hipLaunchKernelGGL((k_conv_bw<8, 8>), grd, blk, 0, s, act, dz, S, D, H, W, part_w, part_b);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 vlbm_status repack(vlbm_nn* nn) {
   for (int l = 0; l < nn->layers; ++l) {
-    const size_t nf = packed_elems(nn->ci[l], nn->co[l]);
+    const size_t nf = packed_elems(nn->ci[l], nn->co[l], nn->nzt);
     hipLaunchKernelGGL(k_pack, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, nn->stream,
-                       nn->d_param + nn->woff[l], nn->ci[l], nn->co[l], 0, nn->d_wf[l]);
+                       nn->d_param + nn->woff[l], nn->ci[l], nn->co[l], 0, nn->ntap, nn->d_wf[l]);
     NN_HIP(nn, hipGetLastError());
     if (l > 0) {
-      const size_t nb = packed_elems(nn->co[l], nn->ci[l]);
+      const size_t nb = packed_elems(nn->co[l], nn->ci[l], nn->nzt);
       hipLaunchKernelGGL(k_pack, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, nn->stream,
-                         nn->d_param + nn->woff[l], nn->ci[l], nn->co[l], 1, nn->d_wb[l]);
+                         nn->d_param + nn->woff[l], nn->ci[l], nn->co[l], 1, nn->ntap, nn->d_wb[l]);
       NN_HIP(nn, hipGetLastError());
     }
   }
   return VLBM_OK;
 }
 
-vlbm_status check_shape(vlbm_nn* nn, int batch, int nx, int ny) {
+// batch lattices of nz x ny x nx (nz = 1 for a 3x3 network)
+vlbm_status check_shape(vlbm_nn* nn, int batch, int nx, int ny, int nz) {
   if (batch < 1 || nx < TILE || ny < TILE || nx % TILE || ny % TILE)
     return nfail(nn, VLBM_ERR_ARG, "batch >= 1 and nx, ny positive multiples of %d required (got %d, %d, %d)",
                  TILE, batch, nx, ny);
-  if ((size_t)batch * nx * ny > ((size_t)1 << 28)) return nfail(nn, VLBM_ERR_ARG, "batch * nx * ny too large");
+  if (nn->dim == 2 && nz != 1) return nfail(nn, VLBM_ERR_ARG, "a 3x3 network takes nz = 1 (got %d)", nz);
+  if (nz < 1) return nfail(nn, VLBM_ERR_ARG, "nz >= 1 required (got %d)", nz);
+  if ((size_t)batch * nz > 65535) return nfail(nn, VLBM_ERR_ARG, "batch * nz must not exceed 65535");
+  if ((size_t)batch * nz * nx * ny > ((size_t)1 << 28))
+    return nfail(nn, VLBM_ERR_ARG, "batch * nz * ny * nx too large");
   return VLBM_OK;
 }
 
@@ -696,20 +775,22 @@ vlbm_status ensure_workspace(vlbm_nn* nn, size_t positions) {
 
 // forward pass; mode_train keeps the pre-activations.  Writes nn->d_y (NCHW FP32),
 // scaled by oscale/oshift.
-vlbm_status forward(vlbm_nn* nn, const float* X, int B, int nx, int ny, bool train, const float* oscale,
+vlbm_status forward(vlbm_nn* nn, const float* X, int B, int nx, int ny, int nz, bool train, const float* oscale,
                     const float* oshift, float* yout, hipStream_t s) {
-  const size_t P = (size_t)B * nx * ny;
+  const int S = B * nz;  // slices
+  const size_t P = (size_t)S * nx * ny;
   vlbm_status st = ensure_workspace(nn, P);
   if (st != VLBM_OK) return st;
   const float* norm = nn->d_norm;
-  hipLaunchKernelGGL(k_prep, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, X, B, nn->cin, ny, nx,
+  hipLaunchKernelGGL(k_prep, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, X, S, nn->cin, ny, nx,
                      norm + 0, norm + 8, nn->d_act[0]);
   NN_HIP(nn, hipGetLastError());
   for (int l = 0; l < nn->layers; ++l) {
     const bool last = l == nn->layers - 1;
-    NN_HIP(nn, launch_conv(nn->ci[l], nn->co[l], last ? MODE_LAST : MODE_HIDDEN, nn->d_act[l], nn->d_wf[l],
-                           nn->d_param + nn->boff[l], B, ny, nx, last ? nullptr : nn->d_act[l + 1],
-                           last ? yout : (train ? nn->d_z[l] : nullptr), nullptr, oscale, oshift, s));
+    NN_HIP(nn, launch_conv(nn->ci[l], nn->co[l], last ? MODE_LAST : MODE_HIDDEN, nn->nzt, nn->d_act[l],
+                           nn->d_wf[l], nn->d_param + nn->boff[l], S, nz, ny, nx,
+                           last ? nullptr : nn->d_act[l + 1], last ? yout : (train ? nn->d_z[l] : nullptr),
+                           nullptr, oscale, oshift, s));
   }
   return VLBM_OK;
 }
@@ -718,13 +799,18 @@ vlbm_status forward(vlbm_nn* nn, const float* X, int B, int nx, int ny, bool tra
 
 extern "C" {
 
-vlbm_status vlbm_nn_create(int32_t cin, int32_t width, int32_t layers, void* stream, vlbm_nn** out) {
+vlbm_status vlbm_nn_create(int32_t dim, int32_t cin, int32_t width, int32_t layers, void* stream,
+                           vlbm_nn** out) {
   if (!out) return nfail(nullptr, VLBM_ERR_ARG, "out is NULL");
   *out = nullptr;
-  if (cin != 8 || width != 32 || layers < 1 || layers > kMaxLayers)
-    return nfail(nullptr, VLBM_ERR_ARG, "supported: cin = 8, width = 32, 1 <= layers <= %d", kMaxLayers);
+  if ((dim != 2 && dim != 3) || cin != 8 || width != 32 || layers < 1 || layers > kMaxLayers)
+    return nfail(nullptr, VLBM_ERR_ARG, "supported: dim = 2 or 3, cin = 8, width = 32, 1 <= layers <= %d",
+                 kMaxLayers);
   vlbm_nn* nn = new (std::nothrow) vlbm_nn();
   if (!nn) return nfail(nullptr, VLBM_ERR_OOM, "host allocation failed");
+  nn->dim = dim;
+  nn->ntap = dim == 2 ? 9 : 27;
+  nn->nzt = nn->ntap / 9;
   nn->cin = cin;
   nn->width = width;
   nn->layers = layers;
@@ -734,7 +820,7 @@ vlbm_status vlbm_nn_create(int32_t cin, int32_t width, int32_t layers, void* str
     nn->ci[l] = l == 0 ? cin : width;
     nn->co[l] = l == layers - 1 ? cin : width;
     nn->woff[l] = off;
-    off += (size_t)nn->co[l] * nn->ci[l] * 9;
+    off += (size_t)nn->co[l] * nn->ci[l] * nn->ntap;
     nn->boff[l] = off;
     off += nn->co[l];
   }
@@ -745,11 +831,13 @@ vlbm_status vlbm_nn_create(int32_t cin, int32_t width, int32_t layers, void* str
   if (e == hipSuccess) e = hipMalloc(&nn->d_v, off * sizeof(float));
   if (e == hipSuccess) e = hipMalloc(&nn->d_norm, 7 * 8 * sizeof(float));
   for (int l = 0; l < layers && e == hipSuccess; ++l) {
-    e = hipMalloc(&nn->d_wf[l], packed_elems(nn->ci[l], nn->co[l]) * sizeof(bf16_t));
-    if (e == hipSuccess && l > 0) e = hipMalloc(&nn->d_wb[l], packed_elems(nn->co[l], nn->ci[l]) * sizeof(bf16_t));
+    e = hipMalloc(&nn->d_wf[l], packed_elems(nn->ci[l], nn->co[l], nn->nzt) * sizeof(bf16_t));
+    if (e == hipSuccess && l > 0)
+      e = hipMalloc(&nn->d_wb[l], packed_elems(nn->co[l], nn->ci[l], nn->nzt) * sizeof(bf16_t));
   }
   nn->bw_blocks = 512;
-  if (e == hipSuccess) e = hipMalloc(&nn->d_part_w, (size_t)nn->bw_blocks * width * 9 * width * sizeof(float));
+  if (e == hipSuccess)
+    e = hipMalloc(&nn->d_part_w, (size_t)nn->bw_blocks * width * nn->ntap * width * sizeof(float));
   if (e == hipSuccess) e = hipMalloc(&nn->d_part_b, (size_t)nn->bw_blocks * width * sizeof(float));
   if (e == hipSuccess) e = hipMalloc(&nn->d_part_loss, 1024 * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&nn->d_loss, sizeof(double));
@@ -858,48 +946,51 @@ vlbm_status vlbm_nn_set_norm(vlbm_nn* nn, const double* in_mean, const double* i
   return VLBM_OK;
 }
 
-vlbm_status vlbm_nn_forward(vlbm_nn* nn, const float* X, float* dQ, int32_t batch, int32_t nx, int32_t ny) {
+vlbm_status vlbm_nn_forward(vlbm_nn* nn, const float* X, float* dQ, int32_t batch, int32_t nx, int32_t ny,
+                            int32_t nz) {
   if (!nn) return VLBM_ERR_ARG;
   if (!X || !dQ) return nfail(nn, VLBM_ERR_ARG, "NULL array");
-  vlbm_status st = check_shape(nn, batch, nx, ny);
+  vlbm_status st = check_shape(nn, batch, nx, ny, nz);
   if (st != VLBM_OK) return st;
   // dQ = out_mean + out_std * y
-  return forward(nn, X, batch, nx, ny, false, nn->d_norm + 24, nn->d_norm + 16, dQ, nn->stream);
+  return forward(nn, X, batch, nx, ny, nz, false, nn->d_norm + 24, nn->d_norm + 16, dQ, nn->stream);
 }
 
 vlbm_status vlbm_nn_loss_grad(vlbm_nn* nn, const float* X, const float* T, int32_t B, int32_t nx, int32_t ny,
-                              double* loss, float* grad) {
+                              int32_t nz, double* loss, float* grad) {
   if (!nn) return VLBM_ERR_ARG;
   if (!X || !T) return nfail(nn, VLBM_ERR_ARG, "NULL array");
-  vlbm_status st = check_shape(nn, B, nx, ny);
+  vlbm_status st = check_shape(nn, B, nx, ny, nz);
   if (st != VLBM_OK) return st;
+  const int S = B * nz;  // slices
   // forward in standardised units (scale 1, shift 0), output into the workspace
-  st = ensure_workspace(nn, (size_t)B * nx * ny);
+  st = ensure_workspace(nn, (size_t)S * nx * ny);
   if (st != VLBM_OK) return st;
-  st = forward(nn, X, B, nx, ny, true, nn->d_norm + 32, nn->d_norm + 40, nn->d_y, nn->stream);
+  st = forward(nn, X, B, nx, ny, nz, true, nn->d_norm + 32, nn->d_norm + 40, nn->d_y, nn->stream);
   if (st != VLBM_OK) return st;
   const int L = nn->layers;
   const int lblocks = 1024;
-  hipLaunchKernelGGL(k_loss, dim3(lblocks), dim3(kThreads), 0, nn->stream, nn->d_y, T, B, nn->cin, ny, nx,
+  hipLaunchKernelGGL(k_loss, dim3(lblocks), dim3(kThreads), 0, nn->stream, nn->d_y, T, S, nn->cin, ny, nx,
                      nn->d_norm + 16, nn->d_norm + 48, nn->d_dz[0], nn->d_part_loss);
   NN_HIP(nn, hipGetLastError());
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, nn->stream, nn->d_part_loss, lblocks, nn->d_loss);
   NN_HIP(nn, hipGetLastError());
   // backward: dZ of layer l lives in d_dz[cur]
   int cur = 0;
-  const int ntile = B * (nx / TILE) * (ny / TILE);
+  const int ntile = S * (nx / TILE) * (ny / TILE);
   const int nblk = ntile < nn->bw_blocks ? ntile : nn->bw_blocks;
   for (int l = L - 1; l >= 0; --l) {
-    NN_HIP(nn, launch_conv_bw(nn->ci[l], nn->co[l], nn->d_act[l], nn->d_dz[cur], B, ny, nx, nn->d_part_w,
-                              nn->d_part_b, nblk, nn->stream));
-    const int nred = nn->co[l] * nn->ci[l] * 9 + nn->co[l];
+    NN_HIP(nn, launch_conv_bw(nn->ci[l], nn->co[l], nn->nzt, nn->d_act[l], nn->d_dz[cur], S, nz, ny, nx,
+                              nn->d_part_w, nn->d_part_b, nblk, nn->stream));
+    const int nred = nn->co[l] * nn->ci[l] * nn->ntap + nn->co[l];
     hipLaunchKernelGGL(k_reduce_grads, dim3((nred + 255) / 256), dim3(256), 0, nn->stream, nn->d_part_w,
-                       nn->d_part_b, nblk, nn->ci[l], nn->co[l], nn->d_grad + nn->woff[l], nn->d_grad + nn->boff[l]);
+                       nn->d_part_b, nblk, nn->ci[l], nn->co[l], nn->ntap, nn->d_grad + nn->woff[l],
+                       nn->d_grad + nn->boff[l]);
     NN_HIP(nn, hipGetLastError());
     if (l > 0) {
       // dA_{l-1} = conv(dZ_l, mirrored W_l); dZ_{l-1} = dA_{l-1} * GELU'(z_{l-1})
-      NN_HIP(nn, launch_conv(nn->co[l], nn->ci[l], MODE_BWD, nn->d_dz[cur], nn->d_wb[l], nullptr, B, ny, nx,
-                             nn->d_dz[1 - cur], nullptr, nn->d_z[l - 1], nullptr, nullptr, nn->stream));
+      NN_HIP(nn, launch_conv(nn->co[l], nn->ci[l], MODE_BWD, nn->nzt, nn->d_dz[cur], nn->d_wb[l], nullptr, S, nz,
+                             ny, nx, nn->d_dz[1 - cur], nullptr, nn->d_z[l - 1], nullptr, nullptr, nn->stream));
       cur = 1 - cur;
     }
   }
@@ -933,8 +1024,8 @@ vlbm_status vlbm_nn_adam_step(vlbm_nn* nn, float lr) {
 }
 
 vlbm_status vlbm_nn_train_step(vlbm_nn* nn, const float* X, const float* T, int32_t batch, int32_t nx, int32_t ny,
-                               float lr, double* loss) {
-  vlbm_status st = vlbm_nn_loss_grad(nn, X, T, batch, nx, ny, loss, nullptr);
+                               int32_t nz, float lr, double* loss) {
+  vlbm_status st = vlbm_nn_loss_grad(nn, X, T, batch, nx, ny, nz, loss, nullptr);
   if (st != VLBM_OK) return st;
   return vlbm_nn_adam_step(nn, lr);
 }
@@ -949,18 +1040,43 @@ vlbm_status vlbm_restrict(const float* Qf, int32_t K, int32_t nx, int32_t ny, in
   return hipGetLastError() == hipSuccess ? VLBM_OK : VLBM_ERR_HIP;
 }
 
+namespace {
+// a periodic ideal-MHD context with FP32 or FP64 storage (2D batch or 3D lattice)
+bool correctable(const vlbm_ctx* c) {
+  return c->K == 8 && c->p.model == VLBM_IDEAL && !c->has_faces && c->p.body == 0 &&
+         (c->p.storage == VLBM_F32 || c->p.storage == VLBM_F64);
+}
+
+void launch_inject(const vlbm_ctx* c, int par, const float* dq, const int* flag, hipStream_t s) {
+  const dim3 cgrid((unsigned)(((size_t)c->N + 255) / 256)), cblk(256);
+  const bool f32 = c->p.storage == VLBM_F32;
+  if (c->D == 2) {
+    if (f32) hipLaunchKernelGGL((k_inject<vlbm::ST_F32, 2>), cgrid, cblk, 0, s, c->g, par, dq, flag, c->ph.wi);
+    else hipLaunchKernelGGL((k_inject<vlbm::ST_F64, 2>), cgrid, cblk, 0, s, c->g, par, dq, flag, c->ph.wi);
+  } else {
+    if (f32) hipLaunchKernelGGL((k_inject<vlbm::ST_F32, 3>), cgrid, cblk, 0, s, c->g, par, dq, flag, c->ph.wi);
+    else hipLaunchKernelGGL((k_inject<vlbm::ST_F64, 3>), cgrid, cblk, 0, s, c->g, par, dq, flag, c->ph.wi);
+  }
+}
+
+void launch_moments_x(const vlbm_ctx* c, int par, const float* dq, const int* flag, float* X, hipStream_t s) {
+  const dim3 cgrid((unsigned)(((size_t)c->N + 255) / 256)), cblk(256);
+  const bool f32 = c->p.storage == VLBM_F32;
+  if (c->D == 2) {
+    if (f32) hipLaunchKernelGGL((k_moments_x<vlbm::ST_F32, 2>), cgrid, cblk, 0, s, c->g, c->cd, par, dq, flag, X);
+    else hipLaunchKernelGGL((k_moments_x<vlbm::ST_F64, 2>), cgrid, cblk, 0, s, c->g, c->cd, par, dq, flag, X);
+  } else {
+    if (f32) hipLaunchKernelGGL((k_moments_x<vlbm::ST_F32, 3>), cgrid, cblk, 0, s, c->g, c->cd, par, dq, flag, X);
+    else hipLaunchKernelGGL((k_moments_x<vlbm::ST_F64, 3>), cgrid, cblk, 0, s, c->g, c->cd, par, dq, flag, X);
+  }
+}
+}  // namespace
+
 vlbm_status vlbm_inject(vlbm_ctx* c, const float* dQ) {
   if (!c || !dQ) return VLBM_ERR_ARG;
   if (!c->initialized) return VLBM_ERR_STATE;
-  if (c->D != 2 || c->K != 8 || c->p.model != VLBM_IDEAL || (c->p.storage != VLBM_F32 && c->p.storage != VLBM_F64))
-    return VLBM_ERR_ARG;
-  const size_t N = (size_t)c->N;
-  const dim3 cgrid((unsigned)((N + 255) / 256)), cblk(256);
-  const int par = (int)(c->step & 1);
-  if (c->p.storage == VLBM_F32)
-    hipLaunchKernelGGL(k_inject<vlbm::ST_F32>, cgrid, cblk, 0, c->stream, c->g, par, dQ, nullptr, c->ph.wi);
-  else
-    hipLaunchKernelGGL(k_inject<vlbm::ST_F64>, cgrid, cblk, 0, c->stream, c->g, par, dQ, nullptr, c->ph.wi);
+  if (!correctable(c)) return VLBM_ERR_ARG;
+  launch_inject(c, (int)(c->step & 1), dQ, nullptr, c->stream);
   return hipGetLastError() == hipSuccess ? VLBM_OK : VLBM_ERR_HIP;
 }
 
@@ -970,11 +1086,14 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
   if (!c || !nn) return VLBM_ERR_ARG;
   if (!c->initialized) return VLBM_ERR_STATE;
   if (n < 0 || !bound_corr) return nfail(nn, VLBM_ERR_ARG, "n >= 0 and bound_corr required");
-  if (c->D != 2 || c->K != 8 || c->p.model != VLBM_IDEAL || c->N > (1LL << 28) || c->p.collision != 0 ||
-      (c->p.storage != VLBM_F32 && c->p.storage != VLBM_F64))
+  if (!correctable(c) || c->N > (1LL << 28) || c->p.collision != 0)
     return nfail(nn, VLBM_ERR_ARG,
-                 "corrected stepping needs a 2D ideal-MHD BGK context with FP32 or FP64 storage");
-  vlbm_status st = check_shape(nn, c->p.nz, c->p.nx, c->p.ny);
+                 "corrected stepping needs a periodic ideal-MHD BGK context with FP32 or FP64 storage");
+  if (nn->dim != c->D)
+    return nfail(nn, VLBM_ERR_ARG, "a %dD context needs a network of dim %d (got %d)", c->D, c->D, nn->dim);
+  // 2D: the context's nz is a batch of lattices; 3D: one lattice of nz slices
+  const int nbatch = c->D == 2 ? c->p.nz : 1, nzl = c->D == 2 ? 1 : c->p.nz;
+  vlbm_status st = check_shape(nn, nbatch, c->p.nx, c->p.ny, nzl);
   if (st != VLBM_OK) return st;
   GateBounds gb;
   for (int k = 0; k < 8; ++k) {
@@ -992,7 +1111,8 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
   long long* fb = nullptr;
   double* gpart = nullptr;
   double* cpart = nullptr;  // projection partials
-  const int nxy = c->p.nx * c->p.ny, nchunk = (nxy + kCenterChunk - 1) / kCenterChunk;
+  // cells per lattice (the projection's unit)
+  const int nxy = (int)(N / (size_t)nbatch), nchunk = (nxy + kCenterChunk - 1) / kCenterChunk;
   hipStream_t cs = nullptr;  // the loop runs on its own stream, ordered after and before s
   hipEvent_t ev = nullptr;
   hipGraph_t graph = nullptr;
@@ -1017,7 +1137,7 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
   if (e == hipSuccess) e = hipMalloc(&flag, 2 * sizeof(int));
   if (e == hipSuccess) e = hipMalloc(&fb, sizeof(long long));
   if (e == hipSuccess) e = hipMalloc(&gpart, (size_t)gblk * 12 * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc(&cpart, (size_t)8 * c->p.nz * nchunk * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&cpart, (size_t)8 * nbatch * nchunk * sizeof(double));
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventRecord(ev, s);
@@ -1026,28 +1146,29 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
   if (e == hipSuccess) e = hipMemsetAsync(fb, 0, sizeof(long long), cs);
   vlbm::Launch L = c->L;
   L.stream = cs;
-  const dim3 cgrid((unsigned)((N + 255) / 256)), cblk(256);
   int cur = 0;  // dq[cur], flag[cur]: the pending correction (not yet in the populations)
   // one corrected step: moments (with the pending correction), network, gate, sweep
   // injecting the pending correction.  Kernels only, so that it can be captured.
   auto step = [&]() -> vlbm_status {
     const int par = (int)(c->step & 1);
-    if (c->p.storage == VLBM_F32)
-      hipLaunchKernelGGL(k_moments_x<vlbm::ST_F32>, cgrid, cblk, 0, cs, c->g, c->cd, par, dq[cur], flag + cur, X);
-    else
-      hipLaunchKernelGGL(k_moments_x<vlbm::ST_F64>, cgrid, cblk, 0, cs, c->g, c->cd, par, dq[cur], flag + cur, X);
+    launch_moments_x(c, par, dq[cur], flag + cur, X, cs);
     e = hipGetLastError();
     if (e != hipSuccess) return VLBM_ERR_HIP;
-    vlbm_status fs = forward(nn, X, c->p.nz, c->p.nx, c->p.ny, false, nn->d_norm + 24, nn->d_norm + 16, dq[1 - cur], cs);
+    vlbm_status fs = forward(nn, X, nbatch, c->p.nx, c->p.ny, nzl, false, nn->d_norm + 24, nn->d_norm + 16,
+                             dq[1 - cur], cs);
     if (fs != VLBM_OK) return fs;
     if (project_totals) {
-      hipLaunchKernelGGL(k_center_sum, dim3((unsigned)nchunk, 8, (unsigned)c->p.nz), dim3(256), 0, cs, dq[1 - cur],
-                         nxy, c->p.nz, (long long)N, cpart);
+      hipLaunchKernelGGL(k_center_sum, dim3((unsigned)nchunk, 8, (unsigned)nbatch), dim3(256), 0, cs, dq[1 - cur],
+                         nxy, nbatch, (long long)N, cpart);
       hipLaunchKernelGGL(k_center_apply, dim3((unsigned)((N + 255) / 256), 8), dim3(256), 0, cs, dq[1 - cur], nxy,
-                         c->p.nz, (long long)N, nchunk, cpart);
+                         nbatch, (long long)N, nchunk, cpart);
     }
-    hipLaunchKernelGGL(k_gate_partials, dim3(gblk), dim3(kGateThreads), 0, cs, X, dq[1 - cur], c->p.nx, c->p.ny,
-                       c->p.nz, gpart);
+    if (c->D == 2)
+      hipLaunchKernelGGL(k_gate_partials<2>, dim3(gblk), dim3(kGateThreads), 0, cs, X, dq[1 - cur], c->p.nx,
+                         c->p.ny, c->p.nz, gpart);
+    else
+      hipLaunchKernelGGL(k_gate_partials<3>, dim3(gblk), dim3(kGateThreads), 0, cs, X, dq[1 - cur], c->p.nx,
+                         c->p.ny, c->p.nz, gpart);
     hipLaunchKernelGGL(k_gate_final, dim3(1), dim3(64), 0, cs, gpart, gblk, gb, flag + (1 - cur), fb);
     e = hipGetLastError();
     if (e == hipSuccess) e = vlbm::launch_sweep_inj(L, c->g, c->ph, c->cd, par, dq[cur], flag + cur);
@@ -1093,11 +1214,7 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
   }
   if (e == hipSuccess && n > 0) {
     // the last accepted correction goes into the populations
-    const int par = (int)(c->step & 1);
-    if (c->p.storage == VLBM_F32)
-      hipLaunchKernelGGL(k_inject<vlbm::ST_F32>, cgrid, cblk, 0, cs, c->g, par, dq[cur], flag + cur, c->ph.wi);
-    else
-      hipLaunchKernelGGL(k_inject<vlbm::ST_F64>, cgrid, cblk, 0, cs, c->g, par, dq[cur], flag + cur, c->ph.wi);
+    launch_inject(c, (int)(c->step & 1), dq[cur], flag + cur, cs);
     e = hipGetLastError();
   }
   long long nfb = 0;

@@ -455,8 +455,12 @@ hipError_t sweep_t(const Launch& L, const Grid& g, const Phys& ph, const Codec& 
 template <int ST>
 hipError_t sweep_inj_t(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
                        const float* dq, const int* flag) {
-  launch_k<ST, 2, 0, 0, true>(L, cell_grid(g, L.block_x), parity, 0, lane_exchange(g, L.block_x, 0), false, g, ph,
-                              cd, Body{}, dq, flag, Inflow{});
+  if (L.dim == 2)
+    launch_k<ST, 2, 0, 0, true>(L, cell_grid(g, L.block_x), parity, 0, lane_exchange(g, L.block_x, 0), false, g, ph,
+                                cd, Body{}, dq, flag, Inflow{});
+  else
+    launch_k<ST, 3, 0, 0, true>(L, cell_grid(g, L.block_x), parity, 0, lane_exchange(g, L.block_x, 0), false, g, ph,
+                                cd, Body{}, dq, flag, Inflow{});
   return hipGetLastError();
 }
 
@@ -498,7 +502,8 @@ hipError_t launch_sweep(const Launch& L, const Grid& g, const Phys& ph, const Co
 
 hipError_t launch_sweep_inj(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
                             const float* dq, const int* flag) {
-  if (L.dim != 2 || L.model != 0 || ph.collision != 0) return hipErrorInvalidValue;
+  if ((L.dim != 2 && L.dim != 3) || L.model != 0 || ph.collision != 0) return hipErrorInvalidValue;
+  if (L.dim == 3 && (g.bc[0] || g.bc[2] || g.bc[4] || g.mask)) return hipErrorInvalidValue;  // periodic, no body
   if (L.storage == ST_F32) return sweep_inj_t<ST_F32>(L, g, ph, cd, parity, dq, flag);
   if (L.storage == ST_F64) return sweep_inj_t<ST_F64>(L, g, ph, cd, parity, dq, flag);
   return hipErrorInvalidValue;

@@ -132,14 +132,14 @@ def normalisation(X, Y, sample=64, seed=0):
     return in_mean, in_std, out_mean, out_std, y_l2, drift_rms
 
 
-def init_weights(layers=4, cin=8, width=32, seed=0, last_scale=0.1):
+def init_weights(layers=4, cin=8, width=32, seed=0, last_scale=0.1, dim=2):
     """He-normal weights, zero biases; the last layer scaled down so training starts
-    near the plain coarse VLBM."""
+    near the plain coarse VLBM.  dim = 3 gives 3x3x3 kernels."""
     rng = np.random.default_rng(seed)
     dims = [cin] + [width] * (layers - 1) + [cin]
     w = []
     for l in range(layers):
-        W = rng.normal(0.0, np.sqrt(2.0 / (9 * dims[l])), (dims[l + 1], dims[l], 3, 3))
+        W = rng.normal(0.0, np.sqrt(2.0 / (3 ** dim * dims[l])), (dims[l + 1], dims[l]) + (3,) * dim)
         if l == layers - 1:
             W *= last_scale
         w += [W.ravel(), np.zeros(dims[l + 1])]
@@ -253,19 +253,25 @@ FWD_FLOPS_PER_PIXEL = 2 * 9 * (8 * 32 + 32 * 32 + 32 * 32 + 32 * 8)
 TRAIN_FLOPS_PER_PIXEL = 2 * FWD_FLOPS_PER_PIXEL + 2 * 9 * (32 * 32 + 32 * 32 + 32 * 8)
 
 
-def time_network(batch=40, n=256, reps=20, seed=0):
+def time_network(batch=40, n=256, reps=20, seed=0, dim=2, nz=1, ny=None, nx=None):
     """Mean time of the network's forward pass and of one training step (loss,
-    gradients, Adam) on a batch of n x n lattices, from HIP events on the network's
-    stream; returns dict with ms and TFLOP/s (algorithmic flops of the 3x3 layers)."""
+    gradients, Adam) on a batch of lattices (n x n, or nz x ny x nx for dim = 3), from
+    HIP events on the network's stream; returns dict with ms and TFLOP/s (algorithmic
+    flops of the 3x3 or 3x3x3 layers)."""
     torch = _torch()
     stream = torch.cuda.current_stream()
-    net = N.Net(8, 32, 4, stream=stream.cuda_stream)
-    net.vlbm_nn_set_weights(init_weights(seed=seed))
+    ny = n if ny is None else ny
+    nx = n if nx is None else nx
+    net = N.Net(8, 32, 4, stream=stream.cuda_stream, dim=dim)
+    net.vlbm_nn_set_weights(init_weights(seed=seed, dim=dim))
     net.vlbm_nn_set_norm(np.zeros(8), np.ones(8), np.zeros(8), np.ones(8))
     g = torch.Generator(device="cuda").manual_seed(seed)
-    X = torch.randn((8, batch, n, n), generator=g, device="cuda", dtype=torch.float32)
-    T = torch.randn((8, batch, n, n), generator=g, device="cuda", dtype=torch.float32)
+    shape = (8, batch, ny, nx) if dim == 2 else (8, batch, nz, ny, nx)
+    X = torch.randn(shape, generator=g, device="cuda", dtype=torch.float32)
+    T = torch.randn(shape, generator=g, device="cuda", dtype=torch.float32)
     Y = torch.empty_like(X)
+    taps = 3 if dim == 3 else 1  # 27 taps = 3 x 9
+    npix = batch * (nz if dim == 3 else 1) * ny * nx
     out = {}
     for name, fn, fl in (("forward", lambda: net.vlbm_nn_forward(X, Y), FWD_FLOPS_PER_PIXEL),
                          ("train_step", lambda: net.vlbm_nn_train_step(X, T, 1e-4), TRAIN_FLOPS_PER_PIXEL)):
@@ -279,7 +285,7 @@ def time_network(batch=40, n=256, reps=20, seed=0):
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        out[name] = dict(ms=round(ms, 4), tflops=round(fl * batch * n * n / (ms * 1e-3) / 1e12, 2))
+        out[name] = dict(ms=round(ms, 4), tflops=round(taps * fl * npix / (ms * 1e-3) / 1e12, 2))
     net.vlbm_nn_destroy()
     return out
 

@@ -14,16 +14,17 @@ _dp = ctypes.POINTER(ctypes.c_double)
 _fp = ctypes.POINTER(ctypes.c_float)
 
 _sigs = {
-    "vlbm_nn_create": [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.POINTER(_vp)],
+    "vlbm_nn_create": [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.POINTER(_vp)],
     "vlbm_nn_num_params": [_vp, ctypes.POINTER(ctypes.c_size_t)],
     "vlbm_nn_set_weights": [_vp, _fp, ctypes.c_size_t],
     "vlbm_nn_get_weights": [_vp, _fp, ctypes.c_size_t],
     "vlbm_nn_set_norm": [_vp, _dp, _dp, _dp, _dp],
-    "vlbm_nn_forward": [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
-    "vlbm_nn_loss_grad": [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _dp, _fp],
+    "vlbm_nn_forward": [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
+    "vlbm_nn_loss_grad": [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _dp, _fp],
     "vlbm_nn_adam_step": [_vp, ctypes.c_float],
     "vlbm_nn_adam_config": [_vp, ctypes.c_float, ctypes.c_float, ctypes.c_float],
-    "vlbm_nn_train_step": [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, _dp],
+    "vlbm_nn_train_step": [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                           ctypes.c_float, _dp],
     "vlbm_restrict": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                       ctypes.c_int32, _vp, _vp, _vp],
     "vlbm_step_corrected": [_vp, _vp, ctypes.c_int32, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
@@ -56,13 +57,23 @@ def _d(a):
 
 
 class Net:
-    """Owns one ``vlbm_nn``; methods map one-to-one onto the C ABI."""
+    """Owns one ``vlbm_nn``; methods map one-to-one onto the C ABI.  dim = 2: 3x3
+    kernels, fields [C, batch, ny, nx]; dim = 3: 3x3x3 kernels, fields
+    [C, batch, nz, ny, nx] (torch FP32 device tensors, channel-major)."""
 
-    def __init__(self, cin=8, width=32, layers=4, stream=None):
+    def __init__(self, cin=8, width=32, layers=4, stream=None, dim=2):
         h = ctypes.c_void_p()
-        _check(_lib.vlbm_nn_create(cin, width, layers, stream, ctypes.byref(h)))
+        _check(_lib.vlbm_nn_create(dim, cin, width, layers, stream, ctypes.byref(h)))
         self.h = h
-        self.cin, self.width, self.layers = cin, width, layers
+        self.cin, self.width, self.layers, self.dim = cin, width, layers, dim
+
+    def _shape(self, X):
+        """(batch, nx, ny, nz) of a channel-major field."""
+        if self.dim == 2:
+            C, B, ny, nx = X.shape
+            return B, nx, ny, 1
+        C, B, nz, ny, nx = X.shape
+        return B, nx, ny, nz
 
     def vlbm_nn_num_params(self):
         n = ctypes.c_size_t()
@@ -83,16 +94,16 @@ class Net:
         _check(_lib.vlbm_nn_set_norm(self.h, *[p for _, p in arrs]), self.h)
 
     def vlbm_nn_forward(self, X, out):
-        """X, out: torch FP32 device tensors [8, batch, ny, nx] (channel-major)."""
-        C, B, ny, nx = X.shape
-        _check(_lib.vlbm_nn_forward(self.h, _dev(X), _dev(out), B, nx, ny), self.h)
+        """X, out: torch FP32 device tensors of the network's field shape."""
+        if tuple(out.shape) != tuple(X.shape):
+            raise ValueError("out must have the shape of X")
+        _check(_lib.vlbm_nn_forward(self.h, _dev(X), _dev(out), *self._shape(X)), self.h)
         return out
 
     def vlbm_nn_loss_grad(self, X, T, want_grad=True):
-        C, B, ny, nx = X.shape
         loss = ctypes.c_double()
         g = np.empty(self.vlbm_nn_num_params(), np.float32) if want_grad else None
-        _check(_lib.vlbm_nn_loss_grad(self.h, _dev(X), _dev(T), B, nx, ny, ctypes.byref(loss),
+        _check(_lib.vlbm_nn_loss_grad(self.h, _dev(X), _dev(T), *self._shape(X), ctypes.byref(loss),
                                       g.ctypes.data_as(_fp) if g is not None else None), self.h)
         return loss.value, g
 
@@ -103,9 +114,8 @@ class Net:
         _check(_lib.vlbm_nn_adam_config(self.h, b1, b2, eps), self.h)
 
     def vlbm_nn_train_step(self, X, T, lr, want_loss=False):
-        C, B, ny, nx = X.shape
         loss = ctypes.c_double()
-        _check(_lib.vlbm_nn_train_step(self.h, _dev(X), _dev(T), B, nx, ny, lr,
+        _check(_lib.vlbm_nn_train_step(self.h, _dev(X), _dev(T), *self._shape(X), lr,
                                        ctypes.byref(loss) if want_loss else None), self.h)
         return loss.value if want_loss else None
 
@@ -155,5 +165,5 @@ def vlbm_inject(sim, dQ):
     FP32 device tensor [8, nz, ny, nx]."""
     st = _lib.vlbm_inject(sim.ctx, _dev(dQ))
     if st != _v.VLBM_OK:
-        raise _v.VlbmError(st, "vlbm_inject: needs an initialised 2D ideal-MHD FP32/FP64 context")
+        raise _v.VlbmError(st, "vlbm_inject: needs an initialised periodic ideal-MHD FP32/FP64 context")
 

@@ -80,6 +80,10 @@ def load_library(path: str = LIB_PATH):
         raise ImportError(
             f"{path} is missing: build the HIP library first "
             "(python -c 'import __graft_entry__ as g; g.build()'); there is no CPU fallback")
+    # torch is imported first so that its HIP runtime is the one the library binds to:
+    # the process then holds a single runtime, shared by the library's calls and the
+    # torch tensors and streams handed to it
+    import torch  # noqa: F401
     L = ctypes.CDLL(path)
     P = ctypes.POINTER(vlbm_params)
     vp = ctypes.c_void_p

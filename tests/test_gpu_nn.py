@@ -30,19 +30,19 @@ def flat(params):
     return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in params]).astype(np.float32)
 
 
-def unflat(w, layers, cin=8, width=32):
+def unflat(w, layers, cin=8, width=32, dim=2):
     out, off = [], 0
-    for Ws, bs in C.Net.shapes(cin, width, layers):
+    for Ws, bs in C.Net.shapes(cin, width, layers, dim=dim):
         nW, nb = int(np.prod(Ws)), int(np.prod(bs))
         out.append((w[off:off + nW].reshape(Ws).astype(np.float64), w[off + nW:off + nW + nb].astype(np.float64)))
         off += nW + nb
     return out
 
 
-def rand_params(rng, layers, bf16=True):
+def rand_params(rng, layers, bf16=True, dim=2):
     ps = []
-    for Ws, bs in C.Net.shapes(8, 32, layers):
-        fan = Ws[1] * 9
+    for Ws, bs in C.Net.shapes(8, 32, layers, dim=dim):
+        fan = Ws[1] * 3 ** dim
         W = rng.normal(0, np.sqrt(2.0 / fan), Ws)
         b = rng.normal(0, 0.05, bs)
         ps.append((C.bf16_round(W) if bf16 else W, b.astype(np.float32).astype(np.float64)))
@@ -50,7 +50,7 @@ def rand_params(rng, layers, bf16=True):
 
 
 def cm(torch, a):
-    """Batch-major [B, C, H, W] numpy -> channel-major [C, B, H, W] FP32 device tensor."""
+    """Batch-major [B, C, (D,) H, W] numpy -> channel-major [C, B, (D,) H, W] FP32 device tensor."""
     return torch.tensor(np.ascontiguousarray(np.swapaxes(a, 0, 1)), dtype=torch.float32, device="cuda")
 
 
@@ -63,9 +63,9 @@ def rel_l2(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
 
 
-def make_net(env, layers, params):
+def make_net(env, layers, params, dim=2):
     torch, vlbm, nn = env
-    net = nn.Net(8, 32, layers, stream=torch.cuda.current_stream().cuda_stream)
+    net = nn.Net(8, 32, layers, stream=torch.cuda.current_stream().cuda_stream, dim=dim)
     net.vlbm_nn_set_weights(flat(params))
     return net
 
@@ -184,6 +184,109 @@ def test_restriction_matches_oracle(env):
     nn.vlbm_restrict(torch.tensor(Qb, device="cuda"), 4, outb, rz=1, minus=torch.tensor(mn, device="cuda"))
     want = np.stack([C.restrict(Qb[:, j:j + 1].astype(np.float64), 4)[:, 0] for j in range(3)], axis=1) - mn
     assert np.allclose(outb.cpu().numpy(), want, rtol=1e-6, atol=1e-6)
+
+
+# --- 3x3x3 network (3D lattices) -----------------------------------------------
+
+@pytest.mark.parametrize("nz", [1, 2, 5])
+def test_conv3_single_layer_forward_exact(env, nz):
+    """One 3x3x3 layer, BF16-exact inputs and weights: exact up to FP32 accumulation.
+    nz = 1 and 2 are the degenerate periodic cases (z-1 and z+1 the same slice)."""
+    torch = env[0]
+    rng = np.random.default_rng(20 + nz)
+    params = rand_params(rng, 1, dim=3)
+    X = C.bf16_round(rng.normal(size=(2, 8, nz, 16, 32)))
+    net = make_net(env, 1, params, dim=3)
+    Y = torch.empty((8, 2, nz, 16, 32), dtype=torch.float32, device="cuda")
+    net.vlbm_nn_forward(cm(torch, X), Y)
+    want = C.Net(params, layers=1, dim=3).forward(X)
+    assert rel_l2(bm(Y), want) < 1e-5
+
+
+def test_conv3_full_forward_matches_quantised_oracle(env):
+    torch = env[0]
+    rng = np.random.default_rng(24)
+    params = rand_params(rng, 4, dim=3)
+    X = rng.normal(size=(1, 8, 6, 16, 32))
+    net = make_net(env, 4, params, dim=3)
+    Y = torch.empty((8, 1, 6, 16, 32), dtype=torch.float32, device="cuda")
+    net.vlbm_nn_forward(cm(torch, X), Y)
+    want = C.Net(params, layers=4, quantize=True, dim=3).forward(X)
+    assert rel_l2(bm(Y), want) < 1e-2
+
+
+@pytest.mark.parametrize("layers", [1, 2, 4])
+def test_conv3_gradients_match_oracle(env, layers):
+    """Loss and every layer's weight and bias gradient (weight gradient over three
+    z-slabs, data gradient through the mirrored 27-tap weights) against the FP64
+    oracle on BF16-rounded activations."""
+    torch = env[0]
+    rng = np.random.default_rng(30 + layers)
+    params = rand_params(rng, layers, dim=3)
+    X = rng.normal(size=(2, 8, 3, 16, 16))
+    T = rng.normal(size=(2, 8, 3, 16, 16))
+    net = make_net(env, layers, params, dim=3)
+    loss, g = net.vlbm_nn_loss_grad(cm(torch, X), cm(torch, T))
+    oloss, ograds = C.Net(params, layers=layers, quantize=True, dim=3).loss_and_grads(X, T)
+    assert abs(loss - oloss) <= 1e-2 * oloss
+    gp = unflat(g, layers, dim=3)
+    for l in range(layers):
+        assert rel_l2(gp[l][0], ograds[l][0]) < 3e-2, (l, "W")
+        assert rel_l2(gp[l][1], ograds[l][1]) < 3e-2, (l, "b")
+
+
+def test_conv3_gradient_exact_single_layer(env):
+    """One layer on BF16-exact inputs and weights with a loss gradient that is
+    BF16-exact up to the FP32 rounding of the target (y - t a BF16 value times a
+    power of two): the weight gradient of every tap of all three z-slabs then agrees
+    to 1e-3, against 3e-2 where the activations are rounded."""
+    torch = env[0]
+    rng = np.random.default_rng(35)
+    params = rand_params(rng, 1, dim=3)
+    X = C.bf16_round(rng.normal(size=(1, 8, 4, 16, 16)))
+    Y = C.Net(params, layers=1, dim=3).forward(X)
+    n = Y.size  # dZ = 2 (y - t) / n: pick y - t = n/2 * BF16 values
+    D = C.bf16_round(rng.normal(size=Y.shape)) * (n / 2.0) * 2.0 ** -20
+    T = Y - D
+    net = make_net(env, 1, params, dim=3)
+    _, g = net.vlbm_nn_loss_grad(cm(torch, X), cm(torch, T))
+    _, ograds = C.Net(params, layers=1, dim=3).loss_and_grads(X, T)
+    gp = unflat(g, 1, dim=3)
+    # the GPU's y is the FP32 forward, so y - t differs from D by FP32 rounding of y
+    assert rel_l2(gp[0][0], ograds[0][0]) < 1e-3
+    assert rel_l2(gp[0][1], ograds[0][1]) < 1e-3
+
+
+def test_conv3_training_reduces_loss(env):
+    torch = env[0]
+    rng = np.random.default_rng(36)
+    params = rand_params(rng, 4, bf16=False, dim=3)
+    for l in range(4):
+        params[l] = (params[l][0] * (0.1 if l == 3 else 1.0), params[l][1] * 0)
+    X = rng.normal(size=(2, 8, 4, 16, 16))
+    T = 0.5 * np.roll(X, 1, axis=2) - 0.3 * X  # a local linear map along z
+    net = make_net(env, 4, params, dim=3)
+    Xt, Tt = cm(torch, X), cm(torch, T)
+    l0, _ = net.vlbm_nn_loss_grad(Xt, Tt, want_grad=False)
+    for _ in range(150):
+        net.vlbm_nn_train_step(Xt, Tt, 3e-3)
+    l1, _ = net.vlbm_nn_loss_grad(Xt, Tt, want_grad=False)
+    assert l1 < 0.3 * l0, (l0, l1)
+
+
+def test_network_dimension_checks(env):
+    torch, vlbm, nn = env
+    net2 = nn.Net(8, 32, 1, stream=torch.cuda.current_stream().cuda_stream)
+    X = torch.zeros((8, 1, 2, 16, 16), dtype=torch.float32, device="cuda")
+    with pytest.raises(vlbm.VlbmError):  # a 3x3 network takes nz = 1 only
+        nn._check(nn._lib.vlbm_nn_forward(net2.h, nn._dev(X), nn._dev(X), 1, 16, 16, 2), net2.h)
+    with pytest.raises(vlbm.VlbmError):
+        nn.Net(8, 32, 1, dim=4)
+    net3 = nn.Net(8, 32, 1, stream=torch.cuda.current_stream().cuda_stream, dim=3)
+    assert net3.vlbm_nn_num_params() == 8 * 8 * 27 + 8
+    sim = coarse_sim(env, "f32", n=32)
+    with pytest.raises(vlbm.VlbmError):  # corrected 2D stepping needs the 3x3 network
+        nn.vlbm_step_corrected(sim, net3, 1, np.full(8, 1e30), 0.1)
 
 
 # --- corrected coarse stepping ----------------------------------------------------
@@ -320,3 +423,120 @@ def test_replayed_steps_equal_single_steps(env):
     qa, _ = a.vlbm_moments()
     qb, _ = b.vlbm_moments()
     assert np.abs(qa - qb).max() <= 1e-5 * np.abs(qb).max()
+
+
+# --- corrected stepping of a 3D lattice (3x3x3 network) --------------------------
+
+SHAPE3 = (32, 16, 8)  # nx, ny, nz
+
+
+def sim3(env, storage="f64", powell=1, seed=1):
+    torch, vlbm, nn = env
+    w = synth.workload_slab_3d()
+    w["powell"] = powell
+    sim = vlbm.Vlbm(gpu_params(vlbm, w, storage, shape=SHAPE3))
+    sim.vlbm_init_fields(state3(seed))
+    return sim
+
+
+def state3(seed=1):
+    nx, ny, nz = SHAPE3
+    return synth.turbulence_3d(n=16, seed=seed, shape=(nz, ny, nx))[:8]
+
+
+def test_3d_zero_weights_corrected_run_is_the_plain_run(env):
+    """Zero network: every step is accepted and adds nothing, so the corrected run
+    (two eager steps, captured pairs, a last eager step) is bitwise the plain run."""
+    torch, vlbm, nn = env
+    a, b = sim3(env), sim3(env)
+    net = nn.Net(8, 32, 4, stream=torch.cuda.current_stream().cuda_stream, dim=3)
+    assert nn.vlbm_step_corrected(a, net, 9, np.full(8, 1e30), 0.1) == 0
+    b.vlbm_step(9)
+    assert np.array_equal(a.vlbm_get_populations()[0], b.vlbm_get_populations()[0])
+
+
+def test_3d_zero_bound_falls_back_every_step(env):
+    torch, vlbm, nn = env
+    rng = np.random.default_rng(40)
+    a, b = sim3(env, "f32"), sim3(env, "f32")
+    net = make_net(env, 4, rand_params(rng, 4, dim=3), dim=3)
+    assert nn.vlbm_step_corrected(a, net, 7, np.zeros(8), 0.1) == 7
+    b.vlbm_step(7)
+    assert np.array_equal(a.vlbm_get_populations()[0], b.vlbm_get_populations()[0])
+
+
+def test_3d_uniform_correction_matches_oracle_emulation(env):
+    """Only the last biases nonzero: a uniform correction c, so the corrected run is
+    the plain D3Q7 run with f_{k,i} += w_i c_k after every step (oracle, w_0 = 1/4,
+    w_i = 1/8), and the totals grow by N c_k per step."""
+    torch, vlbm, nn = env
+    steps = 8
+    c = np.array([1e-4, 2e-5, -1e-5, 3e-5, 2e-4, 1e-5, -2e-5, 1e-5])  # uniform: div B unchanged
+    params = [(np.zeros(Ws), np.zeros(bs)) for Ws, bs in C.Net.shapes(8, 32, 4, dim=3)]
+    params[3] = (params[3][0], c.astype(np.float32).astype(np.float64))
+    net = make_net(env, 4, params, dim=3)
+    sim = sim3(env, "f64", powell=0)
+    assert nn.vlbm_step_corrected(sim, net, steps, np.full(8, 1.0), 0.1, project_totals=False) == 0
+    Qg, tg = sim.vlbm_moments()
+    w = synth.workload_slab_3d()
+    op = oracle.make_params(dim=3, shape=SHAPE3, tau=w["tau"], s=w["s"], powell=0)
+    f = oracle.init(op, state3())
+    wts = np.array([1 / 4] + [1 / 8] * 6)
+    cf = c.astype(np.float32).astype(np.float64)
+    for _ in range(steps):
+        oracle.run(op, f, 1)
+        f += (cf[:, None] * wts[None, :])[:, :, None]
+    Qo, _, to = oracle.moments(op, f)
+    assert np.abs(Qg - Qo).max() <= 1e-10
+    _, _, t0 = oracle.moments(op, oracle.init(op, state3()))
+    N = int(np.prod(SHAPE3))
+    assert np.allclose(tg[:8] - t0[:8], steps * N * cf, rtol=1e-6, atol=1e-9)
+
+
+def test_3d_projection_removes_a_uniform_correction(env):
+    """Projected onto zero lattice totals (one 3D lattice), a uniform correction
+    vanishes exactly: the run is bitwise the plain run."""
+    torch, vlbm, nn = env
+    c = np.array([1e-4, 2e-5, -1e-5, 3e-5, 2e-4, 1e-5, -2e-5, 1e-5])
+    params = [(np.zeros(Ws), np.zeros(bs)) for Ws, bs in C.Net.shapes(8, 32, 4, dim=3)]
+    params[3] = (params[3][0], c.astype(np.float32).astype(np.float64))
+    net = make_net(env, 4, params, dim=3)
+    a, b = sim3(env, "f32"), sim3(env, "f32")
+    assert nn.vlbm_step_corrected(a, net, 6, np.full(8, 1.0), 0.1) == 0
+    b.vlbm_step(6)
+    assert np.array_equal(a.vlbm_get_populations()[0], b.vlbm_get_populations()[0])
+
+
+def test_3d_gate_sees_the_z_divergence(env):
+    """A one-layer network whose only taps map B_z to dB_z = a (B_z(z+1) - B_z(z-1)):
+    it changes div B only through d/dz.  The oracle gate rejects it in 3D and would
+    accept it if only the in-plane divergence were checked; the GPU gate falls back."""
+    torch, vlbm, nn = env
+    a = 0.25
+    W = np.zeros((8, 8, 3, 3, 3))
+    W[7, 7, 0, 1, 1], W[7, 7, 2, 1, 1] = -a, a
+    params = [(W, np.zeros(8))]
+    Q = state3()
+    dQ = C.Net(params, layers=1, quantize=True, dim=3).forward(Q[None])[0]
+    big = np.full(8, 1e30)
+    assert not C.gate(Q, dQ, big, 0.1, dim=3)
+    assert C.gate(Q, dQ, big, 0.1, dim=2)
+    net = make_net(env, 1, params, dim=3)
+    sim = sim3(env, "f64")
+    assert nn.vlbm_step_corrected(sim, net, 1, big, 0.1) == 1
+    # with the divergence allowance raised far enough the same correction is accepted
+    sim2 = sim3(env, "f64")
+    assert nn.vlbm_step_corrected(sim2, net, 1, big, 0.1, bound_divb_abs=1e3) == 0
+
+
+def test_3d_inject_matches_oracle(env):
+    """vlbm_inject on a 3D context adds w_i dQ_k to every population."""
+    torch, vlbm, nn = env
+    rng = np.random.default_rng(41)
+    sim = sim3(env, "f64")
+    sim.vlbm_step(3)
+    Q0, _ = sim.vlbm_moments()
+    dQ = rng.normal(0, 1e-3, (8,) + Q0.shape[1:])
+    nn.vlbm_inject(sim, torch.tensor(dQ, dtype=torch.float32, device="cuda"))
+    Q1, _ = sim.vlbm_moments()
+    assert np.abs(Q1 - Q0 - dQ.astype(np.float32)).max() <= 1e-12
