@@ -180,15 +180,19 @@ def run_body(vlbm, torch, synth, form_steps):
 
 
 def run_network():
-    """The learned correction's network (4 x conv3x3, 8-32-32-32-8) on its coarse
-    training batch: 40 lattices of 256^2, BF16 MFMA with FP32 accumulation."""
+    """The learned correction's networks (4 layers, 8-32-32-32-8, BF16 MFMA with FP32
+    accumulation): 3x3 on its coarse 2D training batch (40 lattices of 256^2) and
+    3x3x3 on the coarse grid of the body flow (384 x 192 x 192)."""
     from paper_2606_00641_amd import learned
-    network = learned.time_network(batch=40, n=256)
-    for k in network:
-        network[k]["frac_of_bf16_peak"] = round(network[k]["tflops"] / BF16_PEAK_TFLOPS, 4)
-    network["peak_TFLOPs_bf16_dense"] = BF16_PEAK_TFLOPS
-    log(f"network forward {network['forward']['tflops']} TFLOP/s, train step {network['train_step']['tflops']} TFLOP/s")
-    return network
+    nets = {"2d_3x3_40x256x256": learned.time_network(batch=40, n=256),
+            "3d_3x3x3_384x192x192": learned.time_network(batch=1, dim=3, nz=192, ny=192, nx=384, reps=5)}
+    for name, network in nets.items():
+        for k in network:
+            network[k]["frac_of_bf16_peak"] = round(network[k]["tflops"] / BF16_PEAK_TFLOPS, 4)
+        log(f"network {name}: forward {network['forward']['tflops']} TFLOP/s, "
+            f"train step {network['train_step']['tflops']} TFLOP/s")
+    nets["peak_TFLOPs_bf16_dense"] = BF16_PEAK_TFLOPS
+    return nets
 
 
 def recorded_studies():
@@ -305,7 +309,7 @@ def main():
         "cpu_baseline": cpu,
         "forms_slab_512": forms or None,
         "forms_body_768x384x384": body_forms or None,
-        "learned_network_40x256x256": network,
+        "learned_network": network,
         "recorded_studies": recorded_studies(),
         "finite": r["finite"],
     }
