@@ -197,7 +197,8 @@ def run_network():
 
 def recorded_studies():
     """Summaries of the committed study outputs under profiles/ (recorded by
-    study_precision.py and study_learned.py on the same GPU; not re-measured here)."""
+    study_precision.py, study_learned.py and study_learned_3d.py on the same GPU; not
+    re-measured here)."""
     out = {}
     try:
         with open(os.path.join(ROOT, "profiles", "precision_slab_512.json")) as fh:
@@ -208,16 +209,17 @@ def recorded_studies():
             "rel_l2_vs_fp64": {st: {k: v for k, v in last[st].items() if k != "nbad"} for st in ("f32", "f16", "bf16")}}
     except (OSError, ValueError, KeyError):
         pass
-    try:
-        with open(os.path.join(ROOT, "profiles", "learned_coarse_2d.json")) as fh:
-            d = json.load(fh)
-        last = d["history"][-1]
-        out["learned_coarse_2d"] = {
-            "source": "profiles/learned_coarse_2d.json", "workload": d["workload"], "coarse_steps": d["coarse_steps"],
-            "speedup_vs_fine_fp32": d["speedup_vs_fine"], "rel_l2_vs_restricted_fine": {
-                "plain_coarse": last["plain"], "learned_coarse": last["learned"]}, "fallbacks": d["fallbacks"]}
-    except (OSError, ValueError, KeyError):
-        pass
+    for key in ("learned_coarse_2d", "learned_coarse_3d"):
+        try:
+            with open(os.path.join(ROOT, "profiles", key + ".json")) as fh:
+                d = json.load(fh)
+            last = d["history"][-1]
+            out[key] = {
+                "source": f"profiles/{key}.json", "workload": d["workload"], "coarse_steps": d["coarse_steps"],
+                "speedup_vs_fine_fp32": d["speedup_vs_fine"], "rel_l2_vs_restricted_fine": {
+                    "plain_coarse": last["plain"], "learned_coarse": last["learned"]}, "fallbacks": d["fallbacks"]}
+        except (OSError, ValueError, KeyError):
+            pass
     return out or None
 
 

@@ -68,7 +68,7 @@ vlbm_status vlbm_nn_get_weights(const vlbm_nn* nn, float* w, size_t n);
 vlbm_status vlbm_nn_set_norm(vlbm_nn* nn, const double* in_mean, const double* in_std,
                              const double* out_mean, const double* out_std);
 
-/* Inference: X (device, raw moments) -> dQ (device, raw correction).  batch lattices
+/* Inference: X (device, raw moments) -> dQ (device, raw correction, 16-byte aligned).  batch lattices
  * of nz x ny x nx cells; nz must be 1 for a dim-2 network; batch * nz <= 65535 and
  * batch * nz * ny * nx <= 2^28. */
 vlbm_status vlbm_nn_forward(vlbm_nn* nn, const float* X, float* dQ, int32_t batch, int32_t nx,

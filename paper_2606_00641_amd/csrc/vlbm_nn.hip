@@ -17,6 +17,7 @@
 
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -114,7 +115,14 @@ __global__ __launch_bounds__(kThreads) void k_conv(const bf16_t* __restrict__ ac
   constexpr int KS = (9 * CIN + 31) / 32;
   constexpr int NT = (COUT + 15) / 16;
   constexpr int CH = CIN / 8;
-  __shared__ __attribute__((aligned(16))) bf16_t tile[NZT * HALO * HALO * CIN];
+  // The input halo, and after the products the FP32 results of the tile (HIDDEN and
+  // BWD), share one LDS buffer.  Result rows are padded by 4 floats so that the four
+  // lane groups of a store land in distinct banks.
+  constexpr int OS = COUT + 4;
+  constexpr int kTileBytes = NZT * HALO * HALO * CIN * 2;
+  constexpr int kOutBytes = MODE == MODE_LAST ? 0 : TILE * TILE * OS * 4;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[kTileBytes > kOutBytes ? kTileBytes : kOutBytes];
+  bf16_t* tile = reinterpret_cast<bf16_t*>(lds);
   const int sl = blockIdx.z, ty0 = blockIdx.y * TILE, tx0 = blockIdx.x * TILE;
   const int zl = sl % D, zbase = sl - zl;  // slice within its lattice, first slice of the lattice
   for (int q = threadIdx.x; q < NZT * HALO * HALO * CH; q += kThreads) {
@@ -182,29 +190,61 @@ __global__ __launch_bounds__(kThreads) void k_conv(const bf16_t* __restrict__ ac
     }
   }
 
+  if constexpr (MODE == MODE_LAST) {
+    // channel-major output: a lane's four results are four consecutive x of one channel
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const int y = ty0 + 4 * wv + m;
+    for (int m = 0; m < 4; ++m) {
+      const int y = ty0 + 4 * wv + m;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int co = 16 * t + (lane & 15);
-      if (co >= COUT) continue;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int x = tx0 + 4 * g + r;
-        const float v = acc[m][t][r];
-        const size_t nhwc = (((size_t)sl * H + y) * W + x) * COUT + co;
-        if constexpr (MODE == MODE_HIDDEN) {
-          const float z = v + bias[co];
-          out_act[nhwc] = f2bf(gelu(z));
-          if (out_z) out_z[nhwc] = z;
-        } else if constexpr (MODE == MODE_LAST) {
-          const float z = v + bias[co];
-          out_z[(((size_t)co * gridDim.z + sl) * H + y) * W + x] = z * oscale[co] + oshift[co];
-        } else {
-          out_act[nhwc] = f2bf(v * gelu_grad(zprev[nhwc]));
-        }
+      for (int t = 0; t < NT; ++t) {
+        const int co = 16 * t + (lane & 15);
+        if (co >= COUT) continue;
+        const float b = bias[co], sc = oscale[co], sh = oshift[co];
+        float4 o;
+        o.x = (acc[m][t][0] + b) * sc + sh;
+        o.y = (acc[m][t][1] + b) * sc + sh;
+        o.z = (acc[m][t][2] + b) * sc + sh;
+        o.w = (acc[m][t][3] + b) * sc + sh;
+        *reinterpret_cast<float4*>(out_z + (((size_t)co * gridDim.z + sl) * H + y) * W + tx0 + 4 * g) = o;
       }
+    }
+  } else {
+    // channels-last outputs: stage the tile's results [position][channel] in LDS, then
+    // every thread finishes four consecutive channels of a position with 16-byte loads
+    // and stores
+    float* ob = reinterpret_cast<float*>(lds);
+    __syncthreads();  // every wavefront is done with the halo
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int co = 16 * t + (lane & 15);
+        if (co >= COUT) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ob[((4 * wv + m) * TILE + 4 * g + r) * OS + co] = acc[m][t][r];
+      }
+    __syncthreads();
+    constexpr int C4 = COUT / 4;
+    for (int q = threadIdx.x; q < TILE * TILE * C4; q += kThreads) {
+      const int pos = q / C4, c0 = 4 * (q % C4);
+      const int y = ty0 + pos / TILE, x = tx0 + pos % TILE;
+      const size_t nhwc = (((size_t)sl * H + y) * W + x) * COUT + c0;
+      const float4 v = *reinterpret_cast<const float4*>(ob + pos * OS + c0);
+      float a[4];
+      if constexpr (MODE == MODE_HIDDEN) {
+        const float4 b = *reinterpret_cast<const float4*>(bias + c0);
+        const float4 z = make_float4(v.x + b.x, v.y + b.y, v.z + b.z, v.w + b.w);
+        a[0] = gelu(z.x), a[1] = gelu(z.y), a[2] = gelu(z.z), a[3] = gelu(z.w);
+        if (out_z) *reinterpret_cast<float4*>(out_z + nhwc) = z;
+      } else {
+        const float4 zp = *reinterpret_cast<const float4*>(zprev + nhwc);
+        a[0] = v.x * gelu_grad(zp.x), a[1] = v.y * gelu_grad(zp.y);
+        a[2] = v.z * gelu_grad(zp.z), a[3] = v.w * gelu_grad(zp.w);
+      }
+      uint2 packed;
+      packed.x = (unsigned)f2bf(a[0]) | ((unsigned)f2bf(a[1]) << 16);
+      packed.y = (unsigned)f2bf(a[2]) | ((unsigned)f2bf(a[3]) << 16);
+      *reinterpret_cast<uint2*>(out_act + nhwc) = packed;
     }
   }
 }
@@ -950,6 +990,7 @@ vlbm_status vlbm_nn_forward(vlbm_nn* nn, const float* X, float* dQ, int32_t batc
                             int32_t nz) {
   if (!nn) return VLBM_ERR_ARG;
   if (!X || !dQ) return nfail(nn, VLBM_ERR_ARG, "NULL array");
+  if (reinterpret_cast<uintptr_t>(dQ) % 16) return nfail(nn, VLBM_ERR_ARG, "dQ must be 16-byte aligned");
   vlbm_status st = check_shape(nn, batch, nx, ny, nz);
   if (st != VLBM_OK) return st;
   // dQ = out_mean + out_std * y

@@ -1,5 +1,6 @@
-"""Learned coarse-grid correction for 2D ideal MHD: pair generation, training and the
-gain evaluation, driven through the C ABI (include/vlbm.h, include/vlbm_nn.h).
+"""Learned coarse-grid correction for ideal MHD (2D batches and 3D lattices): pair
+generation, training and the gain evaluation, driven through the C ABI
+(include/vlbm.h, include/vlbm_nn.h).
 
 Every arithmetic step runs in the HIP library: fine and coarse sweeps, moments,
 restriction (block mean) and pair targets, network forward/backward/Adam, the gate
@@ -99,11 +100,14 @@ def generate_pairs(seeds, n_fine, r, pairs_per_seed, workload, make_state, kmax=
     return X, Y
 
 
-def _divc_l2(F):
-    """L2 norm of the central-difference divergence of the in-plane B of a moment
-    batch F [8, B, n, n] (host statistics)."""
-    d = 0.5 * (np.roll(F[5], -1, axis=-1) - np.roll(F[5], 1, axis=-1)) \
-        + 0.5 * (np.roll(F[6], -1, axis=-2) - np.roll(F[6], 1, axis=-2))
+def _divc_l2(F, dim=2):
+    """L2 norm of the central-difference divergence of B of a moment batch
+    F [8, B, (nz,) ny, nx] (host statistics): the in-plane field in 2D, all three
+    components in 3D."""
+    d = 0.0
+    for a in range(dim):
+        ax = -1 - a  # component a along its own axis (x is the last axis)
+        d = d + 0.5 * (np.roll(F[5 + a], -1, axis=ax) - np.roll(F[5 + a], 1, axis=ax))
     return float(np.sqrt((d * d).sum()))
 
 
@@ -114,20 +118,22 @@ def normalisation(X, Y, sample=64, seed=0):
     ||B|| (the scale of the gate's absolute div B allowance)."""
     rng = np.random.default_rng(seed)
     P = X.shape[0]
+    dim = X.dim() - 3  # X: [P, 8, B, (nz,) ny, nx]
+    space = tuple(range(3, 3 + dim))
     idx = np.sort(rng.choice(P, size=min(sample, P), replace=False))
-    xs = X[idx].cpu().numpy().astype(np.float64)  # [S, 8, B, n, n]
+    xs = X[idx].cpu().numpy().astype(np.float64)  # [S, 8, B, (nz,) ny, nx]
     ys = Y[idx].cpu().numpy().astype(np.float64)
-    in_mean = xs.mean(axis=(0, 2, 3, 4))
-    in_std = xs.std(axis=(0, 2, 3, 4))
+    in_mean = xs.mean(axis=(0, 2) + space)
+    in_std = xs.std(axis=(0, 2) + space)
     out_mean = np.zeros(8)
-    out_std = ys.std(axis=(0, 2, 3, 4))
+    out_std = ys.std(axis=(0, 2) + space)
     in_std = np.where(in_std > 1e-12, in_std, 1.0)
     out_std = np.where(out_std > 1e-20, out_std, 1.0)
-    y_l2 = np.sqrt((ys ** 2).sum(axis=(3, 4)).mean(axis=(0, 2)))  # per channel, one lattice
+    y_l2 = np.sqrt((ys ** 2).sum(axis=space).mean(axis=(0, 2)))  # per channel, one lattice
     drift = []
     for j in range(xs.shape[0]):
-        bnorm = np.sqrt((xs[j, 5] ** 2 + xs[j, 6] ** 2).sum())
-        drift.append((_divc_l2(xs[j] + ys[j]) - _divc_l2(xs[j])) / max(bnorm, 1e-300))
+        bnorm = np.sqrt(sum((xs[j, 5 + a] ** 2).sum() for a in range(dim)))
+        drift.append((_divc_l2(xs[j] + ys[j], dim) - _divc_l2(xs[j], dim)) / max(bnorm, 1e-300))
     drift_rms = float(np.sqrt(np.mean(np.square(drift))))
     return in_mean, in_std, out_mean, out_std, y_l2, drift_rms
 
@@ -289,3 +295,144 @@ def time_network(batch=40, n=256, reps=20, seed=0, dim=2, nz=1, ny=None, nx=None
     net.vlbm_nn_destroy()
     return out
 
+
+
+# --- 3D lattices: one periodic D3Q7 lattice per context -------------------------
+
+def make_context_3d(n, storage, workload, stream):
+    return V.Vlbm(V.make_params(lattice="D3Q7", shape=(n, n, n), model="ideal", storage=storage,
+                                gamma=workload["gamma"], flux_scale=workload["s"], tau=workload["tau"],
+                                powell=workload["powell"], stream=stream))
+
+
+def _state_3d(make_state, n, seed):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(make_state(n, seed=seed), dtype=np.float32)).cuda()
+
+
+def generate_pairs_3d(seeds, n_fine, r, pairs_per_seed, workload, make_state, storage="f32", log=None):
+    """The pairs of generate_pairs on n^3 lattices, one seed at a time (restriction
+    r x r x r): device tensors X, Y [P, 8, 1, nc, nc, nc], P = pairs_per_seed x seeds,
+    the pairs of seed j at [j * pairs_per_seed, (j + 1) * pairs_per_seed)."""
+    torch = _torch()
+    s = torch.cuda.current_stream().cuda_stream
+    nc = n_fine // r
+    P = pairs_per_seed * len(seeds)
+    X = torch.empty((P, 8, 1, nc, nc, nc), dtype=torch.float32, device="cuda")
+    Y = torch.empty_like(X)
+    M = torch.empty((8, n_fine, n_fine, n_fine), dtype=torch.float32, device="cuda")
+    Cst = torch.empty((8, nc, nc, nc), dtype=torch.float32, device="cuda")
+    cur = torch.empty_like(Cst)
+    nxt = torch.empty_like(Cst)
+    tgt = torch.empty_like(Cst)
+    t0 = time.perf_counter()
+    for j, sd in enumerate(seeds):
+        fine = make_context_3d(n_fine, storage, workload, s)
+        coarse = make_context_3d(nc, storage, workload, s)
+        fine.vlbm_init_fields(_state_3d(make_state, n_fine, sd))
+        fine.vlbm_moments(out=M)
+        N.vlbm_restrict(M, r, cur, stream=s)
+        coarse.vlbm_init_fields(cur)
+        for n in range(pairs_per_seed):
+            coarse.vlbm_step(1)
+            coarse.vlbm_moments(out=Cst)
+            fine.vlbm_step(r)
+            fine.vlbm_moments(out=M)
+            N.vlbm_restrict(M, r, nxt, stream=s)
+            N.vlbm_restrict(M, r, tgt, minus=Cst, stream=s)
+            N.vlbm_inject(coarse, tgt)  # teacher forcing
+            X[j * pairs_per_seed + n, :, 0].copy_(cur)
+            Y[j * pairs_per_seed + n, :, 0].copy_(tgt)
+            cur, nxt = nxt, cur
+        torch.cuda.synchronize()
+        fine.vlbm_destroy()
+        coarse.vlbm_destroy()
+        if log:
+            log(f"pairs: seed {sd} done ({(j + 1) * pairs_per_seed}/{P}), {time.perf_counter() - t0:.1f} s")
+    return X, Y
+
+
+def _family_sums(Q, R):
+    """Per field family (rho u and B as vectors): (sum (Q - R)^2, sum R^2)."""
+    fam = {"rho": [0], "m": [1, 2, 3], "E": [4], "B": [5, 6, 7]}
+    return {name: (sum(float(((Q[k] - R[k]) ** 2).sum()) for k in ks), sum(float((R[k] ** 2).sum()) for k in ks))
+            for name, ks in fam.items()}
+
+
+def evaluate_3d(net, seeds, n_fine, r, coarse_steps, workload, make_state, bound_corr, bound_divb_rel,
+                bound_divb_abs, checkpoints=5, storage="f32", log=None, project=True):
+    """evaluate on 3D lattices: per checkpoint, the per-field relative L2 of the plain
+    and of the corrected coarse run against the restricted fine run, over all seeds."""
+    torch = _torch()
+    s = torch.cuda.current_stream().cuda_stream
+    nc = n_fine // r
+    chunk = coarse_steps // checkpoints
+    sums = [{"plain": None, "learned": None} for _ in range(checkpoints)]
+    fallbacks = 0
+    M = torch.empty((8, n_fine, n_fine, n_fine), dtype=torch.float32, device="cuda")
+    Rf = torch.empty((8, nc, nc, nc), dtype=torch.float32, device="cuda")
+    for sd in seeds:
+        fine = make_context_3d(n_fine, storage, workload, s)
+        plain = make_context_3d(nc, storage, workload, s)
+        learned = make_context_3d(nc, storage, workload, s)
+        fine.vlbm_init_fields(_state_3d(make_state, n_fine, sd))
+        fine.vlbm_moments(out=M)
+        N.vlbm_restrict(M, r, Rf, stream=s)
+        for ctx in (plain, learned):
+            ctx.vlbm_init_fields(Rf)
+        for c in range(checkpoints):
+            fine.vlbm_step(r * chunk)
+            plain.vlbm_step(chunk)
+            fallbacks += N.vlbm_step_corrected(learned, net, chunk, bound_corr, bound_divb_rel, bound_divb_abs,
+                                               project_totals=project)
+            fine.vlbm_moments(out=M)
+            N.vlbm_restrict(M, r, Rf, stream=s)
+            ref = Rf.cpu().numpy().astype(np.float64)
+            for name, ctx in (("plain", plain), ("learned", learned)):
+                q, _ = ctx.vlbm_moments(raise_nonfinite=False)
+                fs = _family_sums(q.reshape(ref.shape), ref)
+                acc = sums[c][name]
+                sums[c][name] = fs if acc is None else {k: (acc[k][0] + fs[k][0], acc[k][1] + fs[k][1]) for k in fs}
+        for ctx in (fine, plain, learned):
+            ctx.vlbm_destroy()
+        if log:
+            log(f"eval seed {sd} done, fallbacks so far {fallbacks}")
+    hist = []
+    for c in range(checkpoints):
+        err = {name: {k: float(np.sqrt(a / b)) for k, (a, b) in sums[c][name].items()} for name in ("plain", "learned")}
+        hist.append(dict(coarse_step=(c + 1) * chunk, **err))
+        if log:
+            log(f"eval step {(c + 1) * chunk}: plain {err['plain']} learned {err['learned']}")
+    return hist, fallbacks
+
+
+def time_runs_3d(net, n_fine, r, coarse_steps, workload, make_state, bound_corr, bound_divb_rel, bound_divb_abs,
+                 seed=900, storage="f32", project=True):
+    """time_runs on 3D lattices: the plain FP32 fine run (r * coarse_steps steps) and
+    the corrected coarse run (coarse_steps steps), inputs resident."""
+    torch = _torch()
+    s = torch.cuda.current_stream().cuda_stream
+    nc = n_fine // r
+    fine = make_context_3d(n_fine, storage, workload, s)
+    learned = make_context_3d(nc, storage, workload, s)
+    fine.vlbm_init_fields(_state_3d(make_state, n_fine, seed))
+    M = torch.empty((8, n_fine, n_fine, n_fine), dtype=torch.float32, device="cuda")
+    Rf = torch.empty((8, nc, nc, nc), dtype=torch.float32, device="cuda")
+    fine.vlbm_moments(out=M)
+    N.vlbm_restrict(M, r, Rf, stream=s)
+    learned.vlbm_init_fields(Rf)
+    fine.vlbm_step(r * 10)
+    N.vlbm_step_corrected(learned, net, 10, bound_corr, bound_divb_rel, bound_divb_abs, project_totals=project)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fine.vlbm_step(r * coarse_steps)
+    torch.cuda.synchronize()
+    t_fine = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    nfb = N.vlbm_step_corrected(learned, net, coarse_steps, bound_corr, bound_divb_rel, bound_divb_abs,
+                                project_totals=project)
+    torch.cuda.synchronize()
+    t_learned = time.perf_counter() - t0
+    fine.vlbm_destroy()
+    learned.vlbm_destroy()
+    return t_fine, t_learned, nfb
