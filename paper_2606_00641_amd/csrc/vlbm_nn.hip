@@ -494,10 +494,13 @@ __device__ inline void upwind_cells(const vlbm::Grid& g, size_t c, size_t* up) {
   }
 }
 
-// X = moments of the populations at the given parity (+ flag * pending dQ), FP32
+// X = moments of the populations at the given parity (+ flag * pending dQ), FP32;
+// also the network's standardised BF16 channels-last input (as k_prep computes it
+// from X) when act0 is not NULL
 template <int ST, int D>
 __global__ void k_moments_x(const vlbm::Grid g, const vlbm::Codec cd, int parity, const float* __restrict__ dq,
-                            const int* __restrict__ flag, float* __restrict__ X) {
+                            const int* __restrict__ flag, float* __restrict__ X, const float* __restrict__ in_mean,
+                            const float* __restrict__ in_istd, bf16_t* __restrict__ act0) {
   using T = typename Dec<ST>::T;
   constexpr int K = 8, NQ = 2 * D + 1;
   const size_t N = (size_t)g.nx * g.ny * g.nz;
@@ -507,6 +510,7 @@ __global__ void k_moments_x(const vlbm::Grid g, const vlbm::Codec cd, int parity
   upwind_cells<D>(g, c, up);
   const T* F = static_cast<const T*>(g.f);
   const bool add = flag && *flag;
+  unsigned packed[K / 2];
   for (int k = 0; k < K; ++k) {
     // FP64 accumulation in direction order, as vlbm_moments
     double q = 0.0;
@@ -516,8 +520,12 @@ __global__ void k_moments_x(const vlbm::Grid g, const vlbm::Codec cd, int parity
       q += Dec<ST>::get(F[(size_t)(k * NQ + slot) * g.stride + src], cd, k * NQ + i);
     }
     if (add) q += (double)dq[(size_t)k * N + c];
-    X[(size_t)k * N + c] = (float)q;
+    const float xq = (float)q;
+    X[(size_t)k * N + c] = xq;
+    const unsigned h = f2bf((xq - in_mean[k]) * in_istd[k]);
+    packed[k / 2] = (k & 1) ? (packed[k / 2] | (h << 16)) : h;
   }
+  if (act0) *reinterpret_cast<uint4*>(act0 + c * K) = make_uint4(packed[0], packed[1], packed[2], packed[3]);
 }
 
 // add w_i dQ_k to every population at the given parity, if *flag (or flag is NULL)
@@ -558,8 +566,10 @@ struct GateBounds {
 // nb lattices of nxy cells each (a batch of 2D lattices, or one 3D lattice: nb = 1,
 // nxy = all its cells).
 // Pass 1: FP64 partial sums of dq[k] over chunks of kCenterChunk cells of lattice b,
-// partial[(k * nb + b) * nchunk + chunk]; pass 2: every cell subtracts the mean of its
-// (k, b) from the partials.  No buffer needs clearing, so both passes can be captured.
+// partial[(k * nb + b) * nchunk + chunk]; pass 2: each workgroup sums the partials of
+// its (k, b) in a fixed order (every workgroup of a lattice gets the same mean) and
+// subtracts the mean from its cells.  No buffer needs clearing, so both passes can be
+// captured.
 constexpr int kCenterChunk = 4096;
 __global__ __launch_bounds__(256) void k_center_sum(const float* __restrict__ dq, int nxy, int nb, long long N,
                                                     double* __restrict__ partial) {
@@ -574,16 +584,23 @@ __global__ __launch_bounds__(256) void k_center_sum(const float* __restrict__ dq
   __syncthreads();
   if (threadIdx.x == 0) partial[((size_t)k * nb + b) * nchunk + chunk] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
+// 256 threads per workgroup; nxy is a multiple of 256 (nx, ny multiples of 16), so
+// a workgroup's cells lie in one lattice.
 __global__ __launch_bounds__(256) void k_center_apply(float* __restrict__ dq, int nxy, int nb, long long N,
                                                       int nchunk, const double* __restrict__ partial) {
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double mean;
+  const long long c0 = (long long)blockIdx.x * blockDim.x;
   const int k = blockIdx.y;
-  if (c >= N) return;
-  const int b = (int)(c / nxy);
-  const double* q = partial + ((size_t)k * nb + b) * nchunk;
-  double s = 0.0;
-  for (int j = 0; j < nchunk; ++j) s += q[j];
-  dq[(size_t)k * (size_t)N + c] -= (float)(s / (double)nxy);
+  if (threadIdx.x < 64) {
+    const double* q = partial + ((size_t)k * nb + (size_t)(c0 / nxy)) * nchunk;
+    double s = 0.0;
+    for (int j = (int)threadIdx.x; j < nchunk; j += 64) s += q[j];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (threadIdx.x == 0) mean = s / (double)nxy;
+  }
+  __syncthreads();
+  const long long c = c0 + threadIdx.x;
+  if (c < N) dq[(size_t)k * (size_t)N + c] -= (float)mean;
 }
 
 // per-block FP64 partials: [0..7] sum dQ_k^2, [8] sum divc(X)^2, [9] sum divc(X + dQ)^2,
@@ -815,6 +832,7 @@ vlbm_status ensure_workspace(vlbm_nn* nn, size_t positions) {
 
 // forward pass; mode_train keeps the pre-activations.  Writes nn->d_y (NCHW FP32),
 // scaled by oscale/oshift.
+// X == NULL: the first layer's input is already in nn->d_act[0].
 vlbm_status forward(vlbm_nn* nn, const float* X, int B, int nx, int ny, int nz, bool train, const float* oscale,
                     const float* oshift, float* yout, hipStream_t s) {
   const int S = B * nz;  // slices
@@ -822,9 +840,11 @@ vlbm_status forward(vlbm_nn* nn, const float* X, int B, int nx, int ny, int nz, 
   vlbm_status st = ensure_workspace(nn, P);
   if (st != VLBM_OK) return st;
   const float* norm = nn->d_norm;
-  hipLaunchKernelGGL(k_prep, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, X, S, nn->cin, ny, nx,
-                     norm + 0, norm + 8, nn->d_act[0]);
-  NN_HIP(nn, hipGetLastError());
+  if (X) {
+    hipLaunchKernelGGL(k_prep, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, X, S, nn->cin, ny, nx,
+                       norm + 0, norm + 8, nn->d_act[0]);
+    NN_HIP(nn, hipGetLastError());
+  }
   for (int l = 0; l < nn->layers; ++l) {
     const bool last = l == nn->layers - 1;
     NN_HIP(nn, launch_conv(nn->ci[l], nn->co[l], last ? MODE_LAST : MODE_HIDDEN, nn->nzt, nn->d_act[l],
@@ -1100,16 +1120,22 @@ void launch_inject(const vlbm_ctx* c, int par, const float* dq, const int* flag,
   }
 }
 
-void launch_moments_x(const vlbm_ctx* c, int par, const float* dq, const int* flag, float* X, hipStream_t s) {
+// X, and the network's first-layer input (standardised with in_mean, in_istd) in act0
+void launch_moments_x(const vlbm_ctx* c, int par, const float* dq, const int* flag, float* X, const float* in_mean,
+                      const float* in_istd, bf16_t* act0, hipStream_t s) {
   const dim3 cgrid((unsigned)(((size_t)c->N + 255) / 256)), cblk(256);
   const bool f32 = c->p.storage == VLBM_F32;
+#define MX_LAUNCH(ST, D)                                                                                   \
+  hipLaunchKernelGGL((k_moments_x<ST, D>), cgrid, cblk, 0, s, c->g, c->cd, par, dq, flag, X, in_mean, in_istd, \
+                     act0)
   if (c->D == 2) {
-    if (f32) hipLaunchKernelGGL((k_moments_x<vlbm::ST_F32, 2>), cgrid, cblk, 0, s, c->g, c->cd, par, dq, flag, X);
-    else hipLaunchKernelGGL((k_moments_x<vlbm::ST_F64, 2>), cgrid, cblk, 0, s, c->g, c->cd, par, dq, flag, X);
+    if (f32) MX_LAUNCH(vlbm::ST_F32, 2);
+    else MX_LAUNCH(vlbm::ST_F64, 2);
   } else {
-    if (f32) hipLaunchKernelGGL((k_moments_x<vlbm::ST_F32, 3>), cgrid, cblk, 0, s, c->g, c->cd, par, dq, flag, X);
-    else hipLaunchKernelGGL((k_moments_x<vlbm::ST_F64, 3>), cgrid, cblk, 0, s, c->g, c->cd, par, dq, flag, X);
+    if (f32) MX_LAUNCH(vlbm::ST_F32, 3);
+    else MX_LAUNCH(vlbm::ST_F64, 3);
   }
+#undef MX_LAUNCH
 }
 }  // namespace
 
@@ -1158,7 +1184,7 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
   hipEvent_t ev = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  const int gblk = (int)std::min<size_t>(256, (N + kGateThreads - 1) / kGateThreads);
+  const int gblk = (int)std::min<size_t>(1024, (N + kGateThreads - 1) / kGateThreads);
   auto cleanup = [&]() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -1192,11 +1218,14 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
   // injecting the pending correction.  Kernels only, so that it can be captured.
   auto step = [&]() -> vlbm_status {
     const int par = (int)(c->step & 1);
-    launch_moments_x(c, par, dq[cur], flag + cur, X, cs);
+    // the network's workspace is sized by the first (eager) step, never under capture
+    vlbm_status fs = ensure_workspace(nn, N);
+    if (fs != VLBM_OK) return fs;
+    launch_moments_x(c, par, dq[cur], flag + cur, X, nn->d_norm + 0, nn->d_norm + 8, nn->d_act[0], cs);
     e = hipGetLastError();
     if (e != hipSuccess) return VLBM_ERR_HIP;
-    vlbm_status fs = forward(nn, X, nbatch, c->p.nx, c->p.ny, nzl, false, nn->d_norm + 24, nn->d_norm + 16,
-                             dq[1 - cur], cs);
+    fs = forward(nn, nullptr, nbatch, c->p.nx, c->p.ny, nzl, false, nn->d_norm + 24, nn->d_norm + 16, dq[1 - cur],
+                 cs);
     if (fs != VLBM_OK) return fs;
     if (project_totals) {
       hipLaunchKernelGGL(k_center_sum, dim3((unsigned)nchunk, 8, (unsigned)nbatch), dim3(256), 0, cs, dq[1 - cur],
