@@ -529,6 +529,27 @@ def test_3d_gate_sees_the_z_divergence(env):
     assert nn.vlbm_step_corrected(sim2, net, 1, big, 0.1, bound_divb_abs=1e3) == 0
 
 
+def test_3d_corrected_step_rejects_open_lattices_and_2d_networks(env):
+    """The corrected 3D step needs a periodic lattice without a body and a dim-3
+    network; vlbm_inject likewise refuses a lattice with faces."""
+    torch, vlbm, nn = env
+    w = synth.workload_slab_3d()
+    Q = state3()
+    Qin = Q[:, 0, 0, 0].astype(np.float64)
+    opened = vlbm.Vlbm(vlbm.make_params(lattice="D3Q7", shape=SHAPE3, model="ideal", storage="f32", gamma=w["gamma"],
+                                        flux_scale=w["s"], tau=w["tau"], bc=(1, 2, 0, 0, 0, 0), inflow_Q=Qin,
+                                        stream=torch.cuda.current_stream().cuda_stream))
+    opened.vlbm_init_fields(Q)
+    net3 = nn.Net(8, 32, 1, stream=torch.cuda.current_stream().cuda_stream, dim=3)
+    with pytest.raises(vlbm.VlbmError):
+        nn.vlbm_step_corrected(opened, net3, 1, np.full(8, 1e30), 0.1)
+    with pytest.raises(vlbm.VlbmError):
+        nn.vlbm_inject(opened, torch.zeros((8, int(np.prod(SHAPE3))), dtype=torch.float32, device="cuda"))
+    net2 = nn.Net(8, 32, 1, stream=torch.cuda.current_stream().cuda_stream)
+    with pytest.raises(vlbm.VlbmError):
+        nn.vlbm_step_corrected(sim3(env, "f32"), net2, 1, np.full(8, 1e30), 0.1)
+
+
 def test_3d_inject_matches_oracle(env):
     """vlbm_inject on a 3D context adds w_i dQ_k to every population."""
     torch, vlbm, nn = env
