@@ -101,8 +101,8 @@ vlbm_status vlbm_restrict(const float* Qf, int32_t K, int32_t nx, int32_t ny, in
 /* f_{k,i} += w_i dQ_k at the context's current step (shifts the zeroth moments by
  * dQ): the teacher-forced coarse run of the training pairs takes each target this
  * way.  dQ: device FP32 [8][N] in the context's moment layout.  Periodic ideal-MHD
- * context (2D or 3D, no body), FP32 or FP64 storage.  Stream-ordered, no
- * synchronisation. */
+ * context (2D or 3D, no body), any storage form (FP16/BF16 deviations are decoded,
+ * incremented in FP32 and encoded again).  Stream-ordered, no synchronisation. */
 vlbm_status vlbm_inject(vlbm_ctx* c, const float* dQ);
 
 /* n coarse steps with the learned correction.  Per step: the moments X of the
@@ -119,7 +119,7 @@ vlbm_status vlbm_inject(vlbm_ctx* c, const float* dQ);
  * then the sweep, with the previous step's accepted dQ added as w_i dQ_k to the
  * populations before the collision.  After the last step the pending dQ is added to
  * the populations, so vlbm_moments sees the corrected state.  The context must be a
- * periodic ideal-MHD BGK context (K = cin = 8, FP32 or FP64 storage, no body) whose
+ * periodic ideal-MHD BGK context (K = cin = 8, any storage form, no body) whose
  * extent the network supports: 2D (nz = batch of independent lattices, gated
  * together and projected one by one) with a dim-2 network, or 3D (one lattice) with a
  * dim-3 network.  bound_corr: host, K doubles.  *n_fallback (host, may be NULL)

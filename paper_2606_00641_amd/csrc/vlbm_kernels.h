@@ -84,8 +84,8 @@ hipError_t launch_refill(const Launch& L, const Grid& g, const Phys& ph, const C
 hipError_t launch_sweep_body(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
                              const Body& b, int mode, const Inflow& in);
 
-// Sweep of a periodic 2D or 3D ideal-MHD BGK lattice (FP32 or FP64 storage) that
-// first adds *flag * w_i dq[k][c] to the gathered populations (dq FP32 [K][N], device).
+// Sweep of a periodic 2D or 3D ideal-MHD BGK lattice (any storage form) that first
+// adds *flag * w_i dq[k][c] to the gathered, decoded populations (dq FP32 [K][N], device).
 hipError_t launch_sweep_inj(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
                             const float* dq, const int* flag);
 

@@ -26,6 +26,7 @@
 
 #include "vlbm.h"
 #include "vlbm_ctx.h"
+#include "vlbm_device.h"
 #include "vlbm_kernels.h"
 #include "vlbm_nn.h"
 
@@ -459,18 +460,6 @@ __global__ void k_restrict(const float* __restrict__ Qf, int K, int nx, int ny, 
 // ---------------------------------------------------------------------------
 // corrected coarse stepping (2D, 8 variables)
 // ---------------------------------------------------------------------------
-template <int ST>
-struct Dec;
-template <>
-struct Dec<vlbm::ST_F64> {
-  using T = double;
-  static __device__ double get(T v, const vlbm::Codec&, int) { return v; }
-};
-template <>
-struct Dec<vlbm::ST_F32> {
-  using T = float;
-  static __device__ double get(T v, const vlbm::Codec&, int) { return v; }
-};
 
 // Cells x - e_i (periodic) for i = 0..2D (rest, +x, -x, +y, -y[, +z, -z]) of cell c.
 // D = 2: the grid is a batch of independent 2D lattices along z; D = 3: one 3D lattice.
@@ -501,7 +490,8 @@ template <int ST, int D>
 __global__ void k_moments_x(const vlbm::Grid g, const vlbm::Codec cd, int parity, const float* __restrict__ dq,
                             const int* __restrict__ flag, float* __restrict__ X, const float* __restrict__ in_mean,
                             const float* __restrict__ in_istd, bf16_t* __restrict__ act0) {
-  using T = typename Dec<ST>::T;
+  using S = vlbm::Store<ST>;
+  using T = typename S::T;
   constexpr int K = 8, NQ = 2 * D + 1;
   const size_t N = (size_t)g.nx * g.ny * g.nz;
   const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -517,7 +507,7 @@ __global__ void k_moments_x(const vlbm::Grid g, const vlbm::Codec cd, int parity
     for (int i = 0; i < NQ; ++i) {
       const int slot = parity == 0 ? i : vlbm::opposite(i);
       const size_t src = parity == 0 ? c : up[i];
-      q += Dec<ST>::get(F[(size_t)(k * NQ + slot) * g.stride + src], cd, k * NQ + i);
+      q += S::dec64(F[(size_t)(k * NQ + slot) * g.stride + src], cd, k * NQ + i);
     }
     if (add) q += (double)dq[(size_t)k * N + c];
     const float xq = (float)q;
@@ -528,11 +518,14 @@ __global__ void k_moments_x(const vlbm::Grid g, const vlbm::Codec cd, int parity
   if (act0) *reinterpret_cast<uint4*>(act0 + c * K) = make_uint4(packed[0], packed[1], packed[2], packed[3]);
 }
 
-// add w_i dQ_k to every population at the given parity, if *flag (or flag is NULL)
+// add w_i dQ_k to every population at the given parity, if *flag (or flag is NULL);
+// FP16/BF16 deviations are decoded, incremented in FP32 and encoded again
 template <int ST, int D>
-__global__ void k_inject(const vlbm::Grid g, int parity, const float* __restrict__ dq, const int* __restrict__ flag,
-                         double wi_d) {
-  using T = typename Dec<ST>::T;
+__global__ void k_inject(const vlbm::Grid g, const vlbm::Codec cd, int parity, const float* __restrict__ dq,
+                         const int* __restrict__ flag, double wi_d) {
+  using S = vlbm::Store<ST>;
+  using T = typename S::T;
+  using R = typename S::R;
   constexpr int K = 8, NQ = 2 * D + 1;
   const size_t N = (size_t)g.nx * g.ny * g.nz;
   const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -541,15 +534,16 @@ __global__ void k_inject(const vlbm::Grid g, int parity, const float* __restrict
   upwind_cells<D>(g, c, up);
   T* F = static_cast<T*>(g.f);
   // same weights, in the same type, as the injecting sweep
-  const T wi = (T)wi_d;
-  const T w0 = vlbm::rest_weight<T, D>(wi);
+  const R wi = (R)wi_d;
+  const R w0 = vlbm::rest_weight<R, D>(wi);
   for (int k = 0; k < K; ++k) {
-    const T d = (T)dq[(size_t)k * N + c];
+    const R d = (R)dq[(size_t)k * N + c];
+    if (d == R(0)) continue;  // nothing to add: the stored values stay as they are
     for (int i = 0; i < NQ; ++i) {
       const int slot = parity == 0 ? i : vlbm::opposite(i);
       const size_t dst = parity == 0 ? c : up[i];
       T& v = F[(size_t)(k * NQ + slot) * g.stride + dst];
-      v += (i == 0 ? w0 : wi) * d;
+      v = S::enc(S::dec(v, cd, k * NQ + i) + (i == 0 ? w0 : wi) * d, cd, k * NQ + i);
     }
   }
 }
@@ -1102,21 +1096,24 @@ vlbm_status vlbm_restrict(const float* Qf, int32_t K, int32_t nx, int32_t ny, in
 }
 
 namespace {
-// a periodic ideal-MHD context with FP32 or FP64 storage (2D batch or 3D lattice)
+// a periodic ideal-MHD context (2D batch or 3D lattice, any storage form)
 bool correctable(const vlbm_ctx* c) {
-  return c->K == 8 && c->p.model == VLBM_IDEAL && !c->has_faces && c->p.body == 0 &&
-         (c->p.storage == VLBM_F32 || c->p.storage == VLBM_F64);
+  return c->K == 8 && c->p.model == VLBM_IDEAL && !c->has_faces && c->p.body == 0;
 }
 
+// The launchers below index by storage * 2 + (dimension - 2): the storage codes of
+// vlbm.h and of the kernels agree.
 void launch_inject(const vlbm_ctx* c, int par, const float* dq, const int* flag, hipStream_t s) {
   const dim3 cgrid((unsigned)(((size_t)c->N + 255) / 256)), cblk(256);
-  const bool f32 = c->p.storage == VLBM_F32;
-  if (c->D == 2) {
-    if (f32) hipLaunchKernelGGL((k_inject<vlbm::ST_F32, 2>), cgrid, cblk, 0, s, c->g, par, dq, flag, c->ph.wi);
-    else hipLaunchKernelGGL((k_inject<vlbm::ST_F64, 2>), cgrid, cblk, 0, s, c->g, par, dq, flag, c->ph.wi);
-  } else {
-    if (f32) hipLaunchKernelGGL((k_inject<vlbm::ST_F32, 3>), cgrid, cblk, 0, s, c->g, par, dq, flag, c->ph.wi);
-    else hipLaunchKernelGGL((k_inject<vlbm::ST_F64, 3>), cgrid, cblk, 0, s, c->g, par, dq, flag, c->ph.wi);
+  switch (c->p.storage * 2 + (c->D - 2)) {
+#define INJ_CASE(ST, D)                                                                                   \
+  case ST * 2 + (D - 2):                                                                                  \
+    hipLaunchKernelGGL((k_inject<ST, D>), cgrid, cblk, 0, s, c->g, c->cd, par, dq, flag, c->ph.wi);       \
+    break;
+    INJ_CASE(vlbm::ST_F64, 2) INJ_CASE(vlbm::ST_F64, 3) INJ_CASE(vlbm::ST_F32, 2) INJ_CASE(vlbm::ST_F32, 3)
+    INJ_CASE(vlbm::ST_F16, 2) INJ_CASE(vlbm::ST_F16, 3) INJ_CASE(vlbm::ST_BF16, 2) INJ_CASE(vlbm::ST_BF16, 3)
+#undef INJ_CASE
+    default: break;
   }
 }
 
@@ -1124,18 +1121,17 @@ void launch_inject(const vlbm_ctx* c, int par, const float* dq, const int* flag,
 void launch_moments_x(const vlbm_ctx* c, int par, const float* dq, const int* flag, float* X, const float* in_mean,
                       const float* in_istd, bf16_t* act0, hipStream_t s) {
   const dim3 cgrid((unsigned)(((size_t)c->N + 255) / 256)), cblk(256);
-  const bool f32 = c->p.storage == VLBM_F32;
-#define MX_LAUNCH(ST, D)                                                                                   \
-  hipLaunchKernelGGL((k_moments_x<ST, D>), cgrid, cblk, 0, s, c->g, c->cd, par, dq, flag, X, in_mean, in_istd, \
-                     act0)
-  if (c->D == 2) {
-    if (f32) MX_LAUNCH(vlbm::ST_F32, 2);
-    else MX_LAUNCH(vlbm::ST_F64, 2);
-  } else {
-    if (f32) MX_LAUNCH(vlbm::ST_F32, 3);
-    else MX_LAUNCH(vlbm::ST_F64, 3);
+  switch (c->p.storage * 2 + (c->D - 2)) {
+#define MX_CASE(ST, D)                                                                                       \
+  case ST * 2 + (D - 2):                                                                                     \
+    hipLaunchKernelGGL((k_moments_x<ST, D>), cgrid, cblk, 0, s, c->g, c->cd, par, dq, flag, X, in_mean, in_istd, \
+                       act0);                                                                                \
+    break;
+    MX_CASE(vlbm::ST_F64, 2) MX_CASE(vlbm::ST_F64, 3) MX_CASE(vlbm::ST_F32, 2) MX_CASE(vlbm::ST_F32, 3)
+    MX_CASE(vlbm::ST_F16, 2) MX_CASE(vlbm::ST_F16, 3) MX_CASE(vlbm::ST_BF16, 2) MX_CASE(vlbm::ST_BF16, 3)
+#undef MX_CASE
+    default: break;
   }
-#undef MX_LAUNCH
 }
 }  // namespace
 
@@ -1155,7 +1151,7 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
   if (n < 0 || !bound_corr) return nfail(nn, VLBM_ERR_ARG, "n >= 0 and bound_corr required");
   if (!correctable(c) || c->N > (1LL << 28) || c->p.collision != 0)
     return nfail(nn, VLBM_ERR_ARG,
-                 "corrected stepping needs a periodic ideal-MHD BGK context with FP32 or FP64 storage");
+                 "corrected stepping needs a periodic ideal-MHD BGK context without a body");
   if (nn->dim != c->D)
     return nfail(nn, VLBM_ERR_ARG, "a %dD context needs a network of dim %d (got %d)", c->D, c->D, nn->dim);
   // 2D: the context's nz is a batch of lattices; 3D: one lattice of nz slices

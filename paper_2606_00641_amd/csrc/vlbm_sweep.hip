@@ -504,9 +504,13 @@ hipError_t launch_sweep_inj(const Launch& L, const Grid& g, const Phys& ph, cons
                             const float* dq, const int* flag) {
   if ((L.dim != 2 && L.dim != 3) || L.model != 0 || ph.collision != 0) return hipErrorInvalidValue;
   if (L.dim == 3 && (g.bc[0] || g.bc[2] || g.bc[4] || g.mask)) return hipErrorInvalidValue;  // periodic, no body
-  if (L.storage == ST_F32) return sweep_inj_t<ST_F32>(L, g, ph, cd, parity, dq, flag);
-  if (L.storage == ST_F64) return sweep_inj_t<ST_F64>(L, g, ph, cd, parity, dq, flag);
-  return hipErrorInvalidValue;
+  switch (L.storage) {
+    case ST_F64: return sweep_inj_t<ST_F64>(L, g, ph, cd, parity, dq, flag);
+    case ST_F32: return sweep_inj_t<ST_F32>(L, g, ph, cd, parity, dq, flag);
+    case ST_F16: return sweep_inj_t<ST_F16>(L, g, ph, cd, parity, dq, flag);
+    case ST_BF16: return sweep_inj_t<ST_BF16>(L, g, ph, cd, parity, dq, flag);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_sweep_body(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,

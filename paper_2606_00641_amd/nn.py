@@ -165,5 +165,5 @@ def vlbm_inject(sim, dQ):
     FP32 device tensor [8, nz, ny, nx]."""
     st = _lib.vlbm_inject(sim.ctx, _dev(dQ))
     if st != _v.VLBM_OK:
-        raise _v.VlbmError(st, "vlbm_inject: needs an initialised periodic ideal-MHD FP32/FP64 context")
+        raise _v.VlbmError(st, "vlbm_inject: needs an initialised periodic ideal-MHD context without a body")
 

@@ -550,6 +550,44 @@ def test_3d_corrected_step_rejects_open_lattices_and_2d_networks(env):
         nn.vlbm_step_corrected(sim3(env, "f32"), net2, 1, np.full(8, 1e30), 0.1)
 
 
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_low_precision_zero_weights_corrected_run_is_the_plain_run(env, storage, dim):
+    """FP16/BF16 deviation storage: a zero network adds nothing (the injecting sweep
+    adds zero to the decoded populations; the last injection leaves the stored values
+    as they are), so the corrected run is bitwise the plain run."""
+    torch, vlbm, nn = env
+    if dim == 2:
+        a, b = coarse_sim(env, storage, n=32), coarse_sim(env, storage, n=32)
+    else:
+        a, b = sim3(env, storage), sim3(env, storage)
+    net = nn.Net(8, 32, 2, stream=torch.cuda.current_stream().cuda_stream, dim=dim)
+    assert nn.vlbm_step_corrected(a, net, 9, np.full(8, 1e30), 0.1) == 0
+    b.vlbm_step(9)
+    assert np.array_equal(a.vlbm_get_populations()[0], b.vlbm_get_populations()[0])
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_low_precision_uniform_correction_moves_the_totals(env, storage):
+    """FP16/BF16 storage, a uniform correction c (last biases only): after n steps the
+    totals exceed those of the plain run of the same storage by n N c, up to the
+    storage's rounding of the populations (2 % here, against 100 % for a missing or
+    doubled injection); no step falls back."""
+    torch, vlbm, nn = env
+    steps = 8
+    c = np.full(8, 1e-3)
+    params = [(np.zeros(Ws), np.zeros(bs)) for Ws, bs in C.Net.shapes(8, 32, 2, dim=3)]
+    params[1] = (params[1][0], c.astype(np.float32).astype(np.float64))
+    net = make_net(env, 2, params, dim=3)
+    a, b = sim3(env, storage, powell=0), sim3(env, storage, powell=0)
+    assert nn.vlbm_step_corrected(a, net, steps, np.full(8, 1.0), 0.1, project_totals=False) == 0
+    b.vlbm_step(steps)
+    _, ta = a.vlbm_moments()
+    _, tb = b.vlbm_moments()
+    N = int(np.prod(SHAPE3))
+    assert np.allclose(ta[:8] - tb[:8], steps * N * c.astype(np.float32), rtol=2e-2)
+
+
 def test_3d_inject_matches_oracle(env):
     """vlbm_inject on a 3D context adds w_i dQ_k to every population."""
     torch, vlbm, nn = env
