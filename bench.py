@@ -209,7 +209,7 @@ def recorded_studies():
             "rel_l2_vs_fp64": {st: {k: v for k, v in last[st].items() if k != "nbad"} for st in ("f32", "f16", "bf16")}}
     except (OSError, ValueError, KeyError):
         pass
-    for key in ("learned_coarse_2d", "learned_coarse_3d"):
+    for key in ("learned_coarse_2d", "learned_coarse_3d", "learned_coarse_3d_f16", "learned_coarse_3d_bf16"):
         try:
             with open(os.path.join(ROOT, "profiles", key + ".json")) as fh:
                 d = json.load(fh)

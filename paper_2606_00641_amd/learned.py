@@ -360,9 +360,11 @@ def _family_sums(Q, R):
 
 
 def evaluate_3d(net, seeds, n_fine, r, coarse_steps, workload, make_state, bound_corr, bound_divb_rel,
-                bound_divb_abs, checkpoints=5, storage="f32", log=None, project=True):
+                bound_divb_abs, checkpoints=5, storage="f32", log=None, project=True, coarse_storage=None):
     """evaluate on 3D lattices: per checkpoint, the per-field relative L2 of the plain
-    and of the corrected coarse run against the restricted fine run, over all seeds."""
+    and of the corrected coarse run (storage form coarse_storage, default storage)
+    against the restricted fine run, over all seeds."""
+    coarse_storage = coarse_storage or storage
     torch = _torch()
     s = torch.cuda.current_stream().cuda_stream
     nc = n_fine // r
@@ -373,8 +375,8 @@ def evaluate_3d(net, seeds, n_fine, r, coarse_steps, workload, make_state, bound
     Rf = torch.empty((8, nc, nc, nc), dtype=torch.float32, device="cuda")
     for sd in seeds:
         fine = make_context_3d(n_fine, storage, workload, s)
-        plain = make_context_3d(nc, storage, workload, s)
-        learned = make_context_3d(nc, storage, workload, s)
+        plain = make_context_3d(nc, coarse_storage, workload, s)
+        learned = make_context_3d(nc, coarse_storage, workload, s)
         fine.vlbm_init_fields(_state_3d(make_state, n_fine, sd))
         fine.vlbm_moments(out=M)
         N.vlbm_restrict(M, r, Rf, stream=s)
@@ -407,14 +409,15 @@ def evaluate_3d(net, seeds, n_fine, r, coarse_steps, workload, make_state, bound
 
 
 def time_runs_3d(net, n_fine, r, coarse_steps, workload, make_state, bound_corr, bound_divb_rel, bound_divb_abs,
-                 seed=900, storage="f32", project=True):
-    """time_runs on 3D lattices: the plain FP32 fine run (r * coarse_steps steps) and
-    the corrected coarse run (coarse_steps steps), inputs resident."""
+                 seed=900, storage="f32", project=True, coarse_storage=None):
+    """time_runs on 3D lattices: the plain fine run (r * coarse_steps steps, storage
+    form storage) and the corrected coarse run (coarse_steps steps, coarse_storage,
+    default storage), inputs resident."""
     torch = _torch()
     s = torch.cuda.current_stream().cuda_stream
     nc = n_fine // r
     fine = make_context_3d(n_fine, storage, workload, s)
-    learned = make_context_3d(nc, storage, workload, s)
+    learned = make_context_3d(nc, coarse_storage or storage, workload, s)
     fine.vlbm_init_fields(_state_3d(make_state, n_fine, seed))
     M = torch.empty((8, n_fine, n_fine, n_fine), dtype=torch.float32, device="cuda")
     Rf = torch.empty((8, nc, nc, nc), dtype=torch.float32, device="cuda")

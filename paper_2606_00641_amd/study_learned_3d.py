@@ -3,9 +3,11 @@
 training pairs of a 4-layer 3x3x3 network with 32 channels; the corrected 64^3 run
 is scored against the restricted fine run on held-out seeds next to the plain coarse
 run, and the wall time of the plain FP32 fine run is compared with that of the
-corrected coarse run.
+corrected coarse run.  --coarse-storage f16 / bf16 runs the plain and corrected coarse
+lattices with FP16/BF16 deviation storage (the network is trained on FP32 pairs).
 
 Usage: python -m paper_2606_00641_amd.study_learned_3d [--out FILE] [--iters N] [--quick]
+       [--coarse-storage f32|f16|bf16]
 """
 import argparse
 import json
@@ -38,6 +40,9 @@ def main():
     ap.add_argument("--quick", action="store_true", help="small sizes (smoke)")
     ap.add_argument("--seed", type=int, default=0, help="seed of the initial weights and of the training order")
     ap.add_argument("--tau", type=float, default=0.55)
+    ap.add_argument("--coarse-storage", default="f32", choices=["f64", "f32", "f16", "bf16"],
+                    help="storage form of the plain and corrected coarse runs (pairs, training and the "
+                         "fine reference stay FP32)")
     ap.add_argument("--bound-factor", type=float, default=5.0,
                     help="gate: fall back when a channel's correction norm exceeds this many times the RMS "
                          "norm of the training targets")
@@ -71,13 +76,17 @@ def main():
     del X, Y
     torch.cuda.empty_cache()
     bound = args.bound_factor * y_l2  # one lattice per context
+    cst = args.coarse_storage
     hist, nfb = Lr.evaluate_3d(net, eval_seeds, n_fine, r, steps, w, make_state, bound, 0.1, b_abs, checkpoints=10,
-                               log=log)
-    t_fine, t_learned, nfb_t = Lr.time_runs_3d(net, n_fine, r, steps, w, make_state, bound, 0.1, b_abs)
+                               log=log, coarse_storage=cst)
+    t_fine, t_learned, nfb_t = Lr.time_runs_3d(net, n_fine, r, steps, w, make_state, bound, 0.1, b_abs,
+                                               coarse_storage=cst)
     nc = n_fine // r
     res = dict(
         workload=f"3D ideal MHD D3Q7 x 8, periodic turbulence (u_rms = B_rms = 0.05, modes 1 <= |k| <= 8), "
-                 f"fine {n_fine}^3 -> coarse {nc}^3 (r = {r}), tau = {w['tau']}, s = {w['s']}, FP32 storage",
+                 f"fine {n_fine}^3 -> coarse {nc}^3 (r = {r}), tau = {w['tau']}, s = {w['s']}, fine run FP32 "
+                 f"storage, coarse runs {cst.upper()} storage",
+        coarse_storage=cst,
         train_seeds=[seeds[0], seeds[-1]], pairs=pairs * len(seeds), seed=args.seed, projected=True,
         eval_seeds=eval_seeds, coarse_steps=steps,
         network="4 x conv3x3x3, 8-32-32-32-8, GELU, BF16 MFMA / FP32 accumulate, Adam lr %g, %d iterations "
