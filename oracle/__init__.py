@@ -86,6 +86,9 @@ class Params(ctypes.Structure):
         ("collision", ctypes.c_int32),
         ("reserved2", ctypes.c_int32),
         ("trt_magic", ctypes.c_double),
+        ("lame_lambda", ctypes.c_double),
+        ("lame_mu", ctypes.c_double),
+        ("rho0", ctypes.c_double),
     ]
 
 
@@ -164,7 +167,8 @@ def _ptr(a):
 
 def make_params(dim=2, shape=(64, 64, 1), model=0, gamma=5.0 / 3.0, s=0.2, w0=None,
                 tau=0.6, powell=1, divb_mode=0, dt=0.0, mu=0.0, eta0=0.0, j_c=0.0,
-                tau_M=1.0, tau_H=1.0, collision=0, trt_magic=0.25) -> Params:
+                tau_M=1.0, tau_H=1.0, collision=0, trt_magic=0.25, lame_lambda=1.0, lame_mu=1.0,
+                rho0=1.0) -> Params:
     p = Params()
     p.dim = dim
     p.nx, p.ny, p.nz = shape
@@ -184,11 +188,12 @@ def make_params(dim=2, shape=(64, 64, 1), model=0, gamma=5.0 / 3.0, s=0.2, w0=No
     p.dt, p.mu, p.eta0, p.j_c, p.tau_M, p.tau_H = dt, mu, eta0, j_c, tau_M, tau_H
     p.collision = int(collision)
     p.trt_magic = float(trt_magic)
+    p.lame_lambda, p.lame_mu, p.rho0 = float(lame_lambda), float(lame_mu), float(rho0)
     return p
 
 
 def nvars(p):
-    return {1: 26, 2: 5}.get(p.model, 8)
+    return {1: 26, 2: 5, 3: 9}.get(p.model, 8)
 
 
 def ndirs(p):

@@ -24,7 +24,9 @@ int vref_num_threads(void) {
 #endif
 }
 
-int vref_nvars(const vref_params* p) { return p->model == 1 ? 26 : (p->model == 2 ? 5 : 8); }
+int vref_nvars(const vref_params* p) {
+  return p->model == 1 ? 26 : (p->model == 2 ? 5 : (p->model == 3 ? 9 : 8));
+}
 int vref_ndirs(const vref_params* p) { return 2 * p->dim + 1; }
 
 /* Lattice (Sec. 2.2; the paper's lattice table is not printed).
@@ -80,9 +82,39 @@ static int euler_flux(const vref_params* p, const double* Q, double* Phi, double
   return bad;
 }
 
+/* Linear Navier-Cauchy (model 3), which Sec. 1 and Sec. 2.2 name among the equations
+ * the (Q, Phi, S) form covers, written as a first-order system in the momentum
+ * density m = rho0 v and the Cauchy stress sigma (symmetric; stored xx, yy, zz, xy,
+ * xz, yz):
+ *   d_t m_b     = d_a sigma_ba
+ *   d_t sigma_bc = lambda delta_bc d_a v_a + mu (d_b v_c + d_c v_b)
+ * so Phi[m_b][a] = -sigma_ba and Phi[sigma_bc][a] = -(lambda delta_bc v_a +
+ * mu (delta_ab v_c + delta_ac v_b)); no source.  The displacement form
+ * rho0 d_t^2 u = mu Lap u + (lambda + mu) grad div u follows for v = d_t u. */
+static const int kSigIdx[3][3] = {{3, 6, 7}, {6, 4, 8}, {7, 8, 5}};
+
+static int elastic_flux(const vref_params* p, const double* Q, double* Phi, double* S, double* dlat) {
+  const double lam = p->lame_lambda, mu = p->lame_mu;
+  double v[3];
+  for (int a = 0; a < 3; ++a) v[a] = Q[a] / p->rho0;
+  for (int a = 0; a < 3; ++a) {
+    for (int b = 0; b < 3; ++b) Phi[3 * b + a] = -Q[kSigIdx[b][a]];
+    for (int b = 0; b < 3; ++b)
+      for (int c = b; c < 3; ++c)
+        Phi[3 * kSigIdx[b][c] + a] = -((b == c ? lam * v[a] : 0.0) + mu * ((a == b ? v[c] : 0.0) + (a == c ? v[b] : 0.0)));
+  }
+  for (int k = 0; k < 9; ++k) S[k] = 0.0;
+  *dlat = 0.0;
+  int bad = 0;
+  for (int k = 0; k < 9; ++k)
+    if (!isfinite(Q[k])) bad = 1;
+  return bad;
+}
+
 int vref_flux_source(const vref_params* p, const double* Q, const double* J,
                      double* Phi, double* S, double* dlat) {
   if (p->model == 2) return euler_flux(p, Q, Phi, S, dlat);
+  if (p->model == 3) return elastic_flux(p, Q, Phi, S, dlat);
   const int K = vref_nvars(p);
   const int d = p->dim;
   const double g = p->gamma;
@@ -389,7 +421,7 @@ int vref_moments(const vref_params* p, const double* f, double* Q_out, double* d
       if (fabs(dall[c]) > totals[K + 2]) totals[K + 2] = fabs(dall[c]);
     }
     /* central-difference divergence of the moment field B, lattice units */
-    for (int z = 0; z < (p->model == 2 ? 0 : p->nz); ++z)
+    for (int z = 0; z < (p->model == 2 || p->model == 3 ? 0 : p->nz); ++z)
       for (int y = 0; y < p->ny; ++y)
         for (int x = 0; x < p->nx; ++x) {
           double dv = 0.0;

@@ -29,7 +29,9 @@ extern "C" {
 typedef struct {
   int32_t dim;        /* 2: D2Q5, 3: D3Q7 */
   int32_t nx, ny, nz; /* nz must be 1 when dim == 2 */
-  int32_t model;      /* 0: ideal MHD (K = 8); 1: resistive MHD with G, H (K = 26) */
+  int32_t model;      /* 0: ideal MHD (K = 8); 1: resistive MHD with G, H (K = 26);
+                         2: compressible Euler (K = 5); 3: linear elastodynamics
+                         (Navier-Cauchy) in velocity-stress form (K = 9) */
   int32_t powell;     /* 1: Powell source injected, 0: off */
   int32_t divb_mode;  /* 0: local non-equilibrium estimate of div B; 1: trace of G / tau_M */
   int32_t reserved;
@@ -57,6 +59,8 @@ typedef struct {
   int32_t collision;
   int32_t reserved2;
   double trt_magic;
+  /* model 3: Lame constants and density of the elastic medium */
+  double lame_lambda, lame_mu, rho0;
 } vref_params;
 
 /* number of variables K and of directions Q */

@@ -257,6 +257,28 @@ def test_conv3_gradient_exact_single_layer(env):
     assert rel_l2(gp[0][1], ograds[0][1]) < 1e-3
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_weight_gradient_exact_on_bf16_exact_operands(env, dim):
+    """One layer with zero weights and biases: the output is exactly 0 on both sides,
+    so the loss gradient dZ = -2 T / n is BF16-exact for T a BF16 value times n / 2 and
+    a power of two, and the inputs are BF16-exact: the weight and bias gradients are
+    then exact up to the FP32 accumulation (<= 1e-5), every tap of every slab."""
+    torch = env[0]
+    rng = np.random.default_rng(37 + dim)
+    shape = (2, 8, 16, 32) if dim == 2 else (1, 8, 3, 16, 16)
+    params = [(np.zeros(Ws), np.zeros(bs)) for Ws, bs in C.Net.shapes(8, 32, 1, dim=dim)]
+    X = C.bf16_round(rng.normal(size=shape))
+    n = int(np.prod(shape))
+    T = C.bf16_round(rng.normal(size=shape)) * (n / 2.0) * 2.0 ** -12
+    net = make_net(env, 1, params, dim=dim)
+    loss, g = net.vlbm_nn_loss_grad(cm(torch, X), cm(torch, T))
+    oloss, ograds = C.Net(params, layers=1, dim=dim).loss_and_grads(X, T)
+    assert abs(loss - oloss) <= 1e-6 * oloss
+    gp = unflat(g, 1, dim=dim)
+    assert rel_l2(gp[0][0], ograds[0][0]) < 1e-5
+    assert rel_l2(gp[0][1], ograds[0][1]) < 1e-5
+
+
 def test_conv3_training_reduces_loss(env):
     torch = env[0]
     rng = np.random.default_rng(36)

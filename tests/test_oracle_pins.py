@@ -379,6 +379,61 @@ def chk_euler_sound():
     return e64, e32 / max(e64, 1e-300)
 
 
+LAME = dict(lam=1.0, mu=0.5, rho0=1.0)  # c_p = sqrt(2), c_s = sqrt(1/2)
+
+
+def elastic_wave(N, kind, dim=2, s=0.1, tau=0.6, eps=1e-6, travel=0.25, lam=1.0, mu=0.5, rho0=1.0):
+    """Forward plane wave along x of the linear Navier-Cauchy model, one wavelength
+    across N cells: kind 'p' (v_x, sigma_xx = -rho0 c_p v_x and the lateral stress
+    sigma_yy = sigma_zz = -lambda v_x / c_p) or 's' (v_y, sigma_xy = -rho0 c_s v_y).
+    Returns (textbook speed, measured speed, the evolved Fourier amplitudes)."""
+    c = np.sqrt((lam + 2 * mu) / rho0) if kind == "p" else np.sqrt(mu / rho0)
+    k = 2 * np.pi / N
+    x = np.arange(N)
+    sn = eps * np.sin(k * x)
+    Q = np.zeros((9, N))
+    if kind == "p":
+        Q[0] = rho0 * sn
+        Q[3] = -rho0 * c * sn
+        Q[4] = Q[5] = -lam / c * sn
+    else:
+        Q[1] = rho0 * sn
+        Q[6] = -rho0 * c * sn
+    shape = (N, 1, 1)
+    Q4 = Q[:, None, None, :]
+    P = oracle.make_params(dim=dim, shape=shape, model=3, s=s, tau=tau, lame_lambda=lam, lame_mu=mu, rho0=rho0)
+    f = oracle.init(P, Q4)
+    nsteps = int(round(travel * N / (s * c)))
+    oracle.run(P, f, nsteps)
+    Qn, _, _ = oracle.moments(P, f)
+    a0 = (Q * np.exp(-1j * k * x)).sum(1)
+    an = (Qn * np.exp(-1j * k * x)).sum(1)
+    z = (np.conj(a0) * an).sum() / (np.conj(a0) * a0).sum()
+    return c, -np.angle(z) / (k * nsteps * s), an
+
+
+def chk_elastic_speeds():
+    """Worst relative speed error at N = 64 over both waves, and the smallest
+    error ratio N = 32 over N = 64 (4 for second order)."""
+    worst, ratio = 0.0, np.inf
+    for kind in ("p", "s"):
+        c, c32, _ = elastic_wave(32, kind, **LAME)
+        _, c64, _ = elastic_wave(64, kind, **LAME)
+        e32, e64 = abs(c32 - c) / c, abs(c64 - c) / c
+        worst = max(worst, e64)
+        ratio = min(ratio, e32 / max(e64, 1e-300))
+    return worst, ratio
+
+
+def chk_elastic_lateral_stress():
+    """Relative error of the P wave's lateral stress to momentum ratio after its
+    travel against -lambda / (rho0 c_p)."""
+    c, _, an = elastic_wave(64, "p", **LAME)
+    want = -LAME["lam"] / (LAME["rho0"] * c)
+    got = an[4] / an[0]
+    return abs(got - want) / abs(want)
+
+
 # ----------------------------------------------------------------------------
 # tests
 # ----------------------------------------------------------------------------
@@ -394,6 +449,35 @@ def test_euler_sound_speed_second_order():
     e64, ratio = chk_euler_sound()
     assert e64 < 2e-3, e64
     assert 3.0 < ratio < 5.0, ratio
+
+
+def test_elastic_wave_speeds_second_order():
+    """Navier-Cauchy P and S waves travel at sqrt((lambda + 2 mu) / rho0) and
+    sqrt(mu / rho0), the error falling at second order in the cell size."""
+    worst, ratio = chk_elastic_speeds()
+    assert worst < 1e-4, worst
+    assert 3.0 < ratio < 5.0, ratio
+
+
+def test_elastic_lateral_stress_of_the_p_wave():
+    """The P wave carries sigma_yy = -lambda v_x / c_p (the scheme keeps the ratio of
+    this eigenvector to rounding): pins the lambda coupling."""
+    assert chk_elastic_lateral_stress() < 1e-9
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_elastic_totals_exact(dim):
+    """No source: every total (momentum and stress) is kept to rounding."""
+    rng = np.random.default_rng(21)
+    shape = (12, 10, 1) if dim == 2 else (8, 6, 5)
+    nx, ny, nz = shape
+    Q = 1e-3 * rng.normal(size=(9, nz, ny, nx))
+    p = oracle.make_params(dim=dim, shape=shape, model=3, s=0.1, lame_lambda=1.0, lame_mu=0.5, rho0=1.0)
+    f = oracle.init(p, Q)
+    _, _, t0 = oracle.moments(p, f)
+    oracle.run(p, f, 30)
+    _, _, t1 = oracle.moments(p, f)
+    assert np.abs(t1[:9] - t0[:9]).max() <= 1e-15
 
 
 def test_euler_totals_exact():
@@ -692,6 +776,10 @@ MUTATIONS = {
     "euler_pressure_dropped": ("Phi[3 * (1 + a) + b] = Q[1 + a] * u[b] + (a == b ? pres : 0.0);",
                                "Phi[3 * (1 + a) + b] = Q[1 + a] * u[b] + (a == b ? 0.0 : 0.0);"),
     "euler_energy_flux": ("Phi[3 * 4 + b] = (E + pres) * u[b];", "Phi[3 * 4 + b] = E * u[b];"),
+    "elastic_stress_sign": ("for (int b = 0; b < 3; ++b) Phi[3 * b + a] = -Q[kSigIdx[b][a]];",
+                            "for (int b = 0; b < 3; ++b) Phi[3 * b + a] = Q[kSigIdx[b][a]];"),
+    "elastic_lambda_dropped": ("-((b == c ? lam * v[a] : 0.0) +", "-((b == c ? 0.0 * v[a] : 0.0) +"),
+    "elastic_shear_half": ("mu * ((a == b ? v[c] : 0.0) + (a == c ? v[b] : 0.0))", "mu * ((a == b ? v[c] : 0.0))"),
 }
 
 
@@ -708,6 +796,8 @@ def _fails(name):
         return dp_on > 3e-4
     if name == "divb_estimate_scale":
         return chk_divb_estimator_tau1() > 1e-12
+    if name.startswith("elastic"):
+        return chk_elastic_speeds()[0] > 1e-4 or chk_elastic_lateral_stress() > 1e-9
     if name.startswith("euler"):
         return chk_euler_vs_mhd(2)[0] > 1e-14 or chk_euler_sound()[0] > 2e-3
     if name.startswith("trt") or name.startswith("rlb"):
