@@ -59,7 +59,14 @@ typedef enum { VLBM_D2Q5 = 0, VLBM_D3Q7 = 1 } vlbm_lattice;
  * Euler, K = 5 (rho, rho u, E) -- the ideal system without the field, the
  * hydrodynamic limit the scheme covers (Sec. 1, Sec. 2.3): fluxes rho u,
  * rho u u + p I, (E + p) u, p = (gamma - 1)(E - rho |u|^2 / 2), no source. */
-typedef enum { VLBM_IDEAL = 0, VLBM_RESISTIVE = 1, VLBM_EULER = 2 } vlbm_model;
+/* NAVIER_CAUCHY: linear elastodynamics (the Navier-Cauchy equation, which Sec. 1 and
+ * Sec. 2.2 name among the equations the scheme covers), K = 9, in first-order
+ * velocity-stress form: momentum density m = rho0 v (k = 0..2) and the symmetric Cauchy
+ * stress sigma_xx, yy, zz, xy, xz, yz (k = 3..8); fluxes Phi[m_b][a] = -sigma_ba,
+ * Phi[sigma_bc][a] = -(lame_lambda delta_bc v_a + lame_mu (delta_ab v_c + delta_ac v_b)),
+ * no source.  P and S waves travel at sqrt((lambda + 2 mu) / rho0) and sqrt(mu / rho0);
+ * s times the P speed must stay below c_s^2. */
+typedef enum { VLBM_IDEAL = 0, VLBM_RESISTIVE = 1, VLBM_EULER = 2, VLBM_NAVIER_CAUCHY = 3 } vlbm_model;
 
 /* Population storage in HBM.  F64 and F32 store f itself (F64 computes in FP64,
  * F32 in FP32).  F16DEV and BF16DEV store h = (f - f_rest[k][i]) / (w_i sigma_k),
@@ -141,6 +148,9 @@ typedef struct {
    * 2 regularized BGK -- f* = f^eq + (1 - 1/tau_k) w_i e_i . J^neq / c_s^2 + w_i S~. */
   int32_t collision;
   double trt_magic;
+  /* NAVIER_CAUCHY only: Lame constants (lame_mu > 0, lame_lambda + 2 lame_mu > 0) and
+   * density (rho0 > 0) of the elastic medium; defaults 1, 1, 1. */
+  double lame_lambda, lame_mu, rho0;
 } vlbm_params;
 
 /* Fill *p with defaults (periodic, F32, gamma 5/3, s 0.2, tau 0.6, Powell on, BGK,

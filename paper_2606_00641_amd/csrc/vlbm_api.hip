@@ -46,7 +46,9 @@ vlbm_status hip_fail(vlbm_ctx* c, hipError_t e, const char* what) {
   } while (0)
 
 int dim_of(int lattice) { return lattice == VLBM_D3Q7 ? 3 : 2; }
-int nvars_of(int model) { return model == VLBM_RESISTIVE ? 26 : (model == VLBM_EULER ? 5 : 8); }
+int nvars_of(int model) {
+  return model == VLBM_RESISTIVE ? 26 : (model == VLBM_EULER ? 5 : (model == VLBM_NAVIER_CAUCHY ? 9 : 8));
+}
 int esize_of(int storage) {
   switch (storage) {
     case VLBM_F64: return 8;
@@ -77,8 +79,13 @@ vlbm_status validate(const vlbm_params* p) {
   if (N >= (1LL << 31)) return fail(nullptr, VLBM_ERR_ARG, "%lld cells exceed 2^31 - 1", N);
   if (plane_stride(N, esize_of(p->storage)) * esize_of(p->storage) >= (1LL << 32))
     return fail(nullptr, VLBM_ERR_ARG, "one population plane would exceed 4 GiB");
-  if (p->model != VLBM_IDEAL && p->model != VLBM_RESISTIVE && p->model != VLBM_EULER)
+  if (p->model != VLBM_IDEAL && p->model != VLBM_RESISTIVE && p->model != VLBM_EULER &&
+      p->model != VLBM_NAVIER_CAUCHY)
     return fail(nullptr, VLBM_ERR_ARG, "unknown model %d", p->model);
+  if (p->model == VLBM_NAVIER_CAUCHY &&
+      (!(p->lame_mu > 0.0) || !(p->rho0 > 0.0) || !(p->lame_lambda + 2.0 * p->lame_mu > 0.0) ||
+       !std::isfinite(p->lame_lambda) || !std::isfinite(p->lame_mu) || !std::isfinite(p->rho0)))
+    return fail(nullptr, VLBM_ERR_ARG, "Navier-Cauchy needs lame_mu > 0, rho0 > 0, lame_lambda + 2 lame_mu > 0");
   if (p->model == VLBM_RESISTIVE && p->lattice != VLBM_D3Q7)
     return fail(nullptr, VLBM_ERR_ARG, "the resistive model needs D3Q7");
   if (p->storage < VLBM_F64 || p->storage > VLBM_BF16DEV)
@@ -193,7 +200,11 @@ void build_codec(vlbm_ctx* c) {
   std::memset(&c->cd, 0, sizeof c->cd);
   if (c->p.storage != VLBM_F16DEV && c->p.storage != VLBM_BF16DEV) return;
   double P[KMAX][3], S[KMAX], dl, Jb[3] = {0, 0, 0};
-  if (c->p.model == VLBM_EULER && c->D == 2)
+  if (c->p.model == VLBM_NAVIER_CAUCHY && c->D == 2)
+    flux_source<double, 2, 3>(c->rest_Q, Jb, c->ph, P, S, dl);
+  else if (c->p.model == VLBM_NAVIER_CAUCHY)
+    flux_source<double, 3, 3>(c->rest_Q, Jb, c->ph, P, S, dl);
+  else if (c->p.model == VLBM_EULER && c->D == 2)
     flux_source<double, 2, 2>(c->rest_Q, Jb, c->ph, P, S, dl);
   else if (c->p.model == VLBM_EULER)
     flux_source<double, 3, 2>(c->rest_Q, Jb, c->ph, P, S, dl);
@@ -236,6 +247,7 @@ vlbm_status vlbm_params_default(vlbm_params* p) {
   for (int k = 0; k < VLBM_KMAX; ++k) p->tau[k] = 0.6;
   p->tau_M = p->tau_H = 1.0;
   p->trt_magic = 0.25;
+  p->lame_lambda = p->lame_mu = p->rho0 = 1.0;
   return VLBM_OK;
 }
 
@@ -291,6 +303,9 @@ vlbm_status vlbm_create(const vlbm_params* p, vlbm_ctx** out) {
     ph.inv_jc2 = p->j_c > 0.0 ? 1.0 / (p->j_c * p->j_c) : 0.0;
     ph.divb_scale = p->dt / p->flux_scale;
   }
+  ph.lame_lambda = p->lame_lambda;
+  ph.lame_mu = p->lame_mu;
+  ph.inv_rho0 = p->rho0 > 0.0 ? 1.0 / p->rho0 : 0.0;
   ph.powell = p->powell;
   ph.divb_mode = p->divb_mode;
   ph.collision = p->collision;
@@ -415,7 +430,9 @@ vlbm_status vlbm_init_fields(vlbm_ctx* c, const void* Q, int q_on_device, int q_
       if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
       if (e == hipSuccess)
         for (int k = 0; k < c->K; ++k)
-          c->rest_Q[k] = (k >= 1 && k <= 3) || k >= 8 ? 0.0 : mean[k] / (double)c->N;
+          c->rest_Q[k] = c->p.model == VLBM_NAVIER_CAUCHY
+                             ? (k <= 2 ? 0.0 : mean[k] / (double)c->N)  // momentum at rest, mean stress
+                             : ((k >= 1 && k <= 3) || k >= 8 ? 0.0 : mean[k] / (double)c->N);
     }
     bool need_scale = false;
     for (int k = 0; k < c->K; ++k) need_scale |= !(c->p.scale[k] > 0.0);
@@ -503,7 +520,7 @@ vlbm_status vlbm_moments(vlbm_ctx* c, void* Q_out, int out_on_device, int out_is
   const int NT = c->K + 5;
   const int par = (int)(c->step & 1);
   VLBM_HIP(c, launch_moments(c->L, c->g, c->ph, c->cd, par, Qd, c->d_partial, c->nblk));
-  const bool has_B = c->p.model != VLBM_EULER;
+  const bool has_B = c->p.model == VLBM_IDEAL || c->p.model == VLBM_RESISTIVE;
   if (has_B) VLBM_HIP(c, launch_divc(c->L, c->g, Qd, c->d_partial2, c->nblk));
   VLBM_HIP(c, launch_reduce(c->L, NT, c->d_partial, c->nblk, 1u << (c->K + 2), c->d_totals));
   if (has_B) VLBM_HIP(c, launch_reduce(c->L, 1, c->d_partial2, c->nblk, 0u, c->d_totals + c->K + 3));

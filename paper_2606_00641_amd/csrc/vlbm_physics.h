@@ -33,12 +33,19 @@ struct Phys {
   int powell, divb_mode;
   int collision;     // 0 BGK; else two rates: antisymmetric halves at omega, symmetric at omega_s
   double omega_s[KMAX];
+  double lame_lambda, lame_mu, inv_rho0;  // Navier-Cauchy medium
 };
 
 // Number of conserved variables of a model: 8 ideal MHD (rho, rho u, E, B), 26
-// resistive MHD (+ G, H), 5 compressible Euler (rho, rho u, E).
+// resistive MHD (+ G, H), 5 compressible Euler (rho, rho u, E), 9 Navier-Cauchy
+// (rho0 v, sigma_xx, yy, zz, xy, xz, yz).
 template <int MODEL>
-inline constexpr int kNVars = MODEL == 1 ? 26 : (MODEL == 2 ? 5 : 8);
+inline constexpr int kNVars = MODEL == 1 ? 26 : (MODEL == 2 ? 5 : (MODEL == 3 ? 9 : 8));
+
+// Index of sigma_bc in the Navier-Cauchy variables (symmetric, xx yy zz xy xz yz).
+__host__ __device__ constexpr int sigma_index(int b, int c) {
+  return b == c ? 3 + b : (b + c == 1 ? 6 : (b + c == 2 ? 7 : 8));
+}
 
 // Scaled lattice flux P[k][a] = (s / c_s^2) Phi[k][a] for the D lattice axes, lattice
 // source S[k] and the lattice div B estimate.  Jb[a] = first moment along axis a of
@@ -48,7 +55,34 @@ template <typename R, int D, int MODEL>
 __host__ __device__ inline bool flux_source(const R* Q, const R* Jb, const Phys& ph,
                                             R (*P)[3], R* S, R& dlat, R* pt_out = nullptr) {
   constexpr int K = kNVars<MODEL>;
-  if constexpr (MODEL == 2) {
+  if constexpr (MODEL == 3) {
+    // linear Navier-Cauchy in velocity-stress form: the momentum flux is minus the
+    // stress, the stress flux minus the isotropic (lambda) and shear (mu) rates of v
+    (void)Jb;
+    const R ir0 = R(ph.inv_rho0);
+    const R v[3] = {Q[0] * ir0, Q[1] * ir0, Q[2] * ir0};
+    const R lam = R(ph.lame_lambda), mu = R(ph.lame_mu);
+    const R c = R(ph.s * ph.inv_cs2);
+    if (pt_out) *pt_out = R(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+#pragma unroll
+      for (int b = 0; b < 3; ++b) P[b][a] = -c * Q[sigma_index(b, a)];
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int cc = b; cc < 3; ++cc)
+          P[sigma_index(b, cc)][a] = -c * ((b == cc ? lam * v[a] : R(0)) +
+                                           mu * ((a == b ? v[cc] : R(0)) + (a == cc ? v[b] : R(0))));
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) S[k] = R(0);
+    dlat = R(0);
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < K; ++k) bad = bad || !(Q[k] - Q[k] == R(0));
+    return bad;
+  } else if constexpr (MODEL == 2) {
     // compressible Euler: the ideal system without the field (the hydrodynamic limit
     // the paper's scheme covers, Sec. 1 and Sec. 2.3): mass, momentum, energy fluxes
     (void)Jb;
@@ -236,7 +270,7 @@ __device__ __forceinline__ bool collide(R (*f)[2 * D + 1], const Phys& ph, R& dl
     Q[k] = acc;
   }
   R Jb[3] = {R(0), R(0), R(0)};
-  if constexpr (MODEL != 2) {
+  if constexpr (MODEL == 0 || MODEL == 1) {
 #pragma unroll
     for (int a = 0; a < D; ++a) Jb[a] = f[5 + a][2 * a + 1] - f[5 + a][2 * a + 2];
   }

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libvlbm.so")
 KMAX = 26
 VLBM_OK, VLBM_ERR_ARG, VLBM_ERR_OOM, VLBM_ERR_HIP, VLBM_ERR_STATE, VLBM_ERR_NONFINITE = 0, -1, -2, -3, -4, -5
 VLBM_D2Q5, VLBM_D3Q7 = 0, 1
-VLBM_IDEAL, VLBM_RESISTIVE, VLBM_EULER = 0, 1, 2
+VLBM_IDEAL, VLBM_RESISTIVE, VLBM_EULER, VLBM_NAVIER_CAUCHY = 0, 1, 2, 3
 VLBM_F64, VLBM_F32, VLBM_F16DEV, VLBM_BF16DEV = 0, 1, 2, 3
 VLBM_BC_PERIODIC, VLBM_BC_INFLOW_EQ, VLBM_BC_ZERO_GRAD = 0, 1, 2
 STORAGE = {"f64": VLBM_F64, "f32": VLBM_F32, "f16": VLBM_F16DEV, "bf16": VLBM_BF16DEV}
@@ -72,6 +72,9 @@ class vlbm_params(ctypes.Structure):
         ("body_m", ctypes.c_double * 3),
         ("collision", ctypes.c_int32),
         ("trt_magic", ctypes.c_double),
+        ("lame_lambda", ctypes.c_double),
+        ("lame_mu", ctypes.c_double),
+        ("rho0", ctypes.c_double),
     ]
 
 
@@ -140,12 +143,14 @@ def _is_torch(x):
 def make_params(lattice="D2Q5", shape=(64, 64, 1), model="ideal", storage="f32", gamma=5.0 / 3.0,
                 flux_scale=0.2, tau=0.6, powell=True, divb_mode=0, dt=0.0, mu=0.0, eta0=0.0,
                 j_c=0.0, tau_M=1.0, tau_H=1.0, w0=0.0, bc=None, inflow_Q=None, scale=None,
-                stream=None, block_x=0, body=None, collision="bgk", trt_magic=0.25):
+                stream=None, block_x=0, body=None, collision="bgk", trt_magic=0.25, lame_lambda=1.0, lame_mu=1.0,
+                rho0=1.0):
     p = vlbm_params()
     _check(_lib.vlbm_params_default(ctypes.byref(p)))
     p.lattice = VLBM_D3Q7 if str(lattice).upper() == "D3Q7" else VLBM_D2Q5
     p.nx, p.ny, p.nz = (int(v) for v in shape)
-    p.model = {"ideal": VLBM_IDEAL, "resistive": VLBM_RESISTIVE, "euler": VLBM_EULER}[model] if isinstance(model, str) \
+    p.model = {"ideal": VLBM_IDEAL, "resistive": VLBM_RESISTIVE, "euler": VLBM_EULER,
+               "navier_cauchy": VLBM_NAVIER_CAUCHY}[model] if isinstance(model, str) \
         else int(model)
     p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
     p.gamma = gamma
@@ -171,6 +176,7 @@ def make_params(lattice="D2Q5", shape=(64, 64, 1), model="ideal", storage="f32",
     p.block_x = int(block_x)
     p.collision = {"bgk": 0, "trt": 1, "rlb": 2}[collision] if isinstance(collision, str) else int(collision)
     p.trt_magic = float(trt_magic)
+    p.lame_lambda, p.lame_mu, p.rho0 = float(lame_lambda), float(lame_mu), float(rho0)
     if body is not None:
         p.body = int(body.get("mode", 1))
         for a in range(3):
@@ -200,7 +206,7 @@ class Vlbm:
         if pop_tensor is not None:
             params.pop_buffer = pop_tensor.data_ptr()
             params.pop_bytes = pop_tensor.numel() * pop_tensor.element_size()
-        self.K = {VLBM_RESISTIVE: 26, VLBM_EULER: 5}.get(params.model, 8)
+        self.K = {VLBM_RESISTIVE: 26, VLBM_EULER: 5, VLBM_NAVIER_CAUCHY: 9}.get(params.model, 8)
         self.dim = 3 if params.lattice == VLBM_D3Q7 else 2
         self.Q = 2 * self.dim + 1
         self.shape = (params.nx, params.ny, params.nz)

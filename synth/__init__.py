@@ -209,6 +209,34 @@ def uniform_state(shape, rho=1.0, u=(0.0, 0.0, 0.0), p=0.6, B=(0.0, 0.0, 0.0),
 # them onto its own parameter structure)
 # ---------------------------------------------------------------------------
 
+def elastic_state(shape, seed=0, kmax=3, amp=1e-2, sigma0=(-0.1, -0.1, -0.1, 0.02, 0.0, -0.01)):
+    """Linear-elastic state [9, nz, ny, nx] on a periodic box (shape = (nx, ny, nz)):
+    momentum density and stress (xx, yy, zz, xy, xz, yz) as sums of seeded Fourier
+    modes with integer wavenumbers |k_a| <= kmax (no z-modes when nz = 1), scaled to
+    max |.| = amp per component, on a uniform pre-stress sigma0."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    Q = np.zeros((9, nz, ny, nx))
+    for k in range(9):
+        f = np.zeros((nz, ny, nx))
+        for _ in range(4):
+            kx, ky = rng.integers(-kmax, kmax + 1, 2)
+            kz = rng.integers(-kmax, kmax + 1) if nz > 1 else 0
+            ph = rng.uniform(0.0, 2.0 * np.pi)
+            f += np.cos(2 * np.pi * (kx * x / nx + ky * y / ny + kz * z / nz) + ph)
+        f *= amp / max(np.abs(f).max(), 1e-300)
+        Q[k] = f + (sigma0[k - 3] if k >= 3 else 0.0)
+    return Q
+
+
+def workload_elastic(dim=2, shape=(64, 64, 1), steps=200):
+    """Linear Navier-Cauchy, lambda = mu = rho0 = 1 (P speed sqrt(3), S speed 1), flux
+    scale 0.1 (s c_p = 0.17 below c_s^2 = 1/3 or 1/4), tau = 0.6."""
+    return dict(dim=dim, shape=shape, model=3, s=0.1, gamma=5.0 / 3.0, tau=0.6, powell=0, divb_mode=0, steps=steps,
+                dt=0.0, mu=0.0, eta0=0.0, tau_M=1.0, tau_H=1.0)
+
+
 def workload_fourier_2d(n=64, steps=200):
     """2D ideal MHD, D2Q5 x 8 variables, periodic, tau = 0.6, flux scale 0.2."""
     return dict(dim=2, shape=(n, n, 1), model=0, s=0.2, gamma=5.0 / 3.0, tau=0.6, powell=1,
