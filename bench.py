@@ -37,9 +37,13 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+MODEL_NAMES = {0: "ideal", 1: "resistive", 2: "euler", 3: "navier_cauchy"}
+MODEL_K = {0: 8, 1: 26, 2: 5, 3: 9}
+
+
 def params_for(vlbm, w, storage, stream):
     return vlbm.make_params(lattice="D3Q7" if w["dim"] == 3 else "D2Q5", shape=w["shape"],
-                            model="resistive" if w["model"] else "ideal", storage=storage,
+                            model=MODEL_NAMES[w["model"]], storage=storage,
                             gamma=w["gamma"], flux_scale=w["s"], tau=w["tau"], powell=w["powell"],
                             divb_mode=w["divb_mode"], dt=w["dt"], mu=w["mu"], eta0=w["eta0"],
                             tau_M=w["tau_M"], tau_H=w["tau_H"], bc=w.get("bc"), inflow_Q=w.get("inflow_Q"),
@@ -64,7 +68,7 @@ def time_sweep(vlbm, torch, w, Q_dev, storage, steps, warmup):
     kernel_ms = e0.elapsed_time(e1) / steps
     _, tot = sim.vlbm_moments(with_field=False, raise_nonfinite=False)
     ncell = int(np.prod(w["shape"]))
-    K = 26 if w["model"] else 8
+    K = MODEL_K[w["model"]]
     Qd = 2 * w["dim"] + 1
     esize = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[storage]
     sim.vlbm_destroy()
@@ -154,6 +158,31 @@ def run_slab(vlbm, torch, synth, form_steps):
     return forms
 
 
+def run_models(vlbm, torch, synth, form_steps):
+    """The other PDEs through the same sweep, 256^3 periodic, FP32: compressible Euler
+    (K = 5, the resistive workload's state without its field) and linear Navier-Cauchy
+    elastodynamics (K = 9, seeded Fourier momentum and stress on a pre-stress)."""
+    out = {}
+    n = 256
+    Qe = synth.without_field(synth.turbulence_3d(n=n, seed=1)[:8]).astype(np.float32)
+    we = dict(dim=3, shape=(n, n, n), model=2, s=0.1, gamma=5.0 / 3.0, tau=0.6, powell=0, divb_mode=0,
+              dt=0.0, mu=0.0, eta0=0.0, tau_M=1.0, tau_H=1.0)
+    wn = synth.workload_elastic(dim=3, shape=(n, n, n))
+    log("generating the 256^3 Euler and Navier-Cauchy states")
+    Qn = synth.elastic_state((n, n, n), seed=5).astype(np.float32)
+    for name, w, Qh in (("euler_256", we, Qe), ("navier_cauchy_256", wn, Qn)):
+        Qd = torch.from_numpy(Qh).cuda()
+        rr = time_sweep(vlbm, torch, w, Qd, "f32", form_steps, 5)
+        del Qd
+        torch.cuda.empty_cache()
+        m = rr["ncell"] * form_steps / rr["wall_s"] / 1e6
+        gb = rr["bytes_per_cell"] * rr["ncell"] / (rr["kernel_ms"] * 1e-3) / 1e9
+        out[name] = dict(mlups=round(m, 1), kernel_ms=round(rr["kernel_ms"], 4), bytes_per_cell=rr["bytes_per_cell"],
+                         achieved_GBps=round(gb, 1), frac_of_peak=round(gb / HBM_PEAK_GBPS, 4), finite=rr["finite"])
+        log(f"{name} f32: {m:.1f} MLUPS, {gb:.0f} GB/s")
+    return out
+
+
 def run_body(vlbm, torch, synth, form_steps):
     """Flow past the moving magnetised body: 768 x 384 x 384, inflow / zero-gradient
     faces, homogenized body, FP16 deviation storage next to FP32."""
@@ -231,7 +260,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the slab and body forms and the network timing")
     ap.add_argument("--form-steps", type=int, default=50)
-    ap.add_argument("--only", choices=("slab", "body", "network"), default=None,
+    ap.add_argument("--only", choices=("slab", "body", "models", "network"), default=None,
                     help="run one secondary part alone and print its result (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -248,6 +277,7 @@ def main():
     if args.only:
         part = {"slab": lambda: run_slab(vlbm, torch, synth, args.form_steps),
                 "body": lambda: run_body(vlbm, torch, synth, args.form_steps),
+                "models": lambda: run_models(vlbm, torch, synth, args.form_steps),
                 "network": run_network}[args.only]()
         print(json.dumps({args.only: part}), flush=True)
         return
@@ -269,6 +299,7 @@ def main():
 
     forms = run_slab(vlbm, torch, synth, args.form_steps) if not args.no_forms else {}
     body_forms = run_body(vlbm, torch, synth, args.form_steps) if not args.no_forms else {}
+    models = run_models(vlbm, torch, synth, args.form_steps) if not args.no_forms else {}
     network = run_network() if not args.no_forms else None
 
     cpu = None
@@ -311,6 +342,7 @@ def main():
         "cpu_baseline": cpu,
         "forms_slab_512": forms or None,
         "forms_body_768x384x384": body_forms or None,
+        "forms_other_models_256": models or None,
         "learned_network": network,
         "recorded_studies": recorded_studies(),
         "finite": r["finite"],

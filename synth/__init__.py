@@ -216,7 +216,10 @@ def elastic_state(shape, seed=0, kmax=3, amp=1e-2, sigma0=(-0.1, -0.1, -0.1, 0.0
     max |.| = amp per component, on a uniform pre-stress sigma0."""
     rng = np.random.default_rng(seed)
     nx, ny, nz = shape
-    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+
+    def wave(kk, n):  # exp(2 pi i k x / n) along one axis
+        return np.exp(2j * np.pi * kk * np.arange(n) / n)
+
     Q = np.zeros((9, nz, ny, nx))
     for k in range(9):
         f = np.zeros((nz, ny, nx))
@@ -224,7 +227,9 @@ def elastic_state(shape, seed=0, kmax=3, amp=1e-2, sigma0=(-0.1, -0.1, -0.1, 0.0
             kx, ky = rng.integers(-kmax, kmax + 1, 2)
             kz = rng.integers(-kmax, kmax + 1) if nz > 1 else 0
             ph = rng.uniform(0.0, 2.0 * np.pi)
-            f += np.cos(2 * np.pi * (kx * x / nx + ky * y / ny + kz * z / nz) + ph)
+            # cos(2 pi (kx x / nx + ky y / ny + kz z / nz) + ph) as a product of axis waves
+            f += ((np.exp(1j * ph) * wave(kz, nz))[:, None, None] * wave(ky, ny)[None, :, None]
+                  * wave(kx, nx)[None, None, :]).real
         f *= amp / max(np.abs(f).max(), 1e-300)
         Q[k] = f + (sigma0[k - 3] if k >= 3 else 0.0)
     return Q
