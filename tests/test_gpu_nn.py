@@ -610,6 +610,32 @@ def test_low_precision_uniform_correction_moves_the_totals(env, storage):
     assert np.allclose(ta[:8] - tb[:8], steps * N * c.astype(np.float32), rtol=2e-2)
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_3d_replayed_steps_equal_single_steps(env, storage):
+    """3D lattice: a long call (captured pairs replayed) against the same steps taken
+    one call at a time."""
+    torch, vlbm, nn = env
+    rng = np.random.default_rng(42)
+    params = [(W * 0.05, b * 0.01) for W, b in rand_params(rng, 4, dim=3)]
+    net = make_net(env, 4, params, dim=3)
+    a, b = sim3(env, storage), sim3(env, storage)
+    # a bound well above the corrections' norms on the initial state
+    q0 = torch.tensor(state3(), dtype=torch.float32, device="cuda").reshape(8, 1, 8, 16, 32)
+    out = torch.empty_like(q0)
+    net.vlbm_nn_forward(q0, out)
+    bound = 4.0 * torch.linalg.vector_norm(out.reshape(8, -1), dim=1).cpu().numpy().astype(np.float64)
+    nfa = nn.vlbm_step_corrected(a, net, 13, bound, 10.0, 1.0)
+    nfb = sum(nn.vlbm_step_corrected(b, net, 1, bound, 10.0, 1.0) for _ in range(13))
+    assert a.vlbm_get_step() == b.vlbm_get_step() == 13
+    assert nfa == nfb == 0
+    # single calls inject their correction at the end of each call rather than before
+    # the next collision: compare the moments, to the storage's rounding
+    qa, _ = a.vlbm_moments()
+    qb, _ = b.vlbm_moments()
+    tol = 1e-5 if storage == "f32" else 2e-3
+    assert np.abs(qa - qb).max() <= tol * np.abs(qb).max()
+
+
 def test_3d_inject_matches_oracle(env):
     """vlbm_inject on a 3D context adds w_i dQ_k to every population."""
     torch, vlbm, nn = env
