@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kThreads) void k_conv(const bf16_t* __restrict__ ac
                                                    bf16_t* __restrict__ out_act, float* __restrict__ out_z,
                                                    const float* __restrict__ zprev,
                                                    const float* __restrict__ oscale,
-                                                   const float* __restrict__ oshift) {
+                                                   const float* __restrict__ oshift, double* __restrict__ tsum) {
   constexpr int KS = (9 * CIN + 31) / 32;
   constexpr int NT = (COUT + 15) / 16;
   constexpr int CH = CIN / 8;
@@ -193,6 +193,9 @@ __global__ __launch_bounds__(kThreads) void k_conv(const bf16_t* __restrict__ ac
 
   if constexpr (MODE == MODE_LAST) {
     // channel-major output: a lane's four results are four consecutive x of one channel
+    double ts[NT];  // FP64 sums of this lane's outputs per channel (tsum != NULL)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) ts[t] = 0.0;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       const int y = ty0 + 4 * wv + m;
@@ -207,6 +210,29 @@ __global__ __launch_bounds__(kThreads) void k_conv(const bf16_t* __restrict__ ac
         o.z = (acc[m][t][2] + b) * sc + sh;
         o.w = (acc[m][t][3] + b) * sc + sh;
         *reinterpret_cast<float4*>(out_z + (((size_t)co * gridDim.z + sl) * H + y) * W + tx0 + 4 * g) = o;
+        ts[t] += ((double)o.x + (double)o.y) + ((double)o.z + (double)o.w);
+      }
+    }
+    if (tsum) {
+      // per-channel sum of the tile, tsum[co][tile] (tiles in launch order, so the
+      // tiles of one lattice are contiguous); a fixed order, so every run agrees
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {  // lanes l, l ^ 16, l ^ 32, l ^ 48 share a channel
+        ts[t] += __shfl_xor(ts[t], 16);
+        ts[t] += __shfl_xor(ts[t], 32);
+      }
+      double* wsum = reinterpret_cast<double*>(lds);  // [wavefront][16 NT]
+      __syncthreads();  // every wavefront is done with the halo
+      if (lane < 16)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) wsum[wv * 16 * NT + 16 * t + lane] = ts[t];
+      __syncthreads();
+      if ((int)threadIdx.x < COUT) {
+        const int co = threadIdx.x;
+        const double tot = (wsum[co] + wsum[16 * NT + co]) + (wsum[32 * NT + co] + wsum[48 * NT + co]);
+        const size_t ntile = (size_t)gridDim.x * gridDim.y * gridDim.z;
+        const size_t tile = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        tsum[(size_t)co * ntile + tile] = tot;
       }
     }
   } else {
@@ -553,86 +579,75 @@ struct GateBounds {
   double divb_rel, divb_abs;
 };
 
-// Zero lattice total per channel.  The fine run, its restriction and the coarse VLBM
-// all keep each lattice's totals of rho, rho u, E and B (up to the Powell source), so
-// the correction they define has zero total; projecting the prediction onto that keeps
-// a small bias of the network from accumulating in the totals over many steps.
-// nb lattices of nxy cells each (a batch of 2D lattices, or one 3D lattice: nb = 1,
-// nxy = all its cells).
-// Pass 1: FP64 partial sums of dq[k] over chunks of kCenterChunk cells of lattice b,
-// partial[(k * nb + b) * nchunk + chunk]; pass 2: each workgroup sums the partials of
-// its (k, b) in a fixed order (every workgroup of a lattice gets the same mean) and
-// subtracts the mean from its cells.  No buffer needs clearing, so both passes can be
-// captured.
-constexpr int kCenterChunk = 4096;
-__global__ __launch_bounds__(256) void k_center_sum(const float* __restrict__ dq, int nxy, int nb, long long N,
-                                                    double* __restrict__ partial) {
-  __shared__ double sh[4];
-  const int chunk = blockIdx.x, k = blockIdx.y, b = blockIdx.z, nchunk = gridDim.x;
-  const float* p = dq + (size_t)k * (size_t)N + (size_t)b * (size_t)nxy;
-  const int i0 = chunk * kCenterChunk, i1 = min(nxy, i0 + kCenterChunk);
-  double s = 0.0;
-  for (int i = i0 + (int)threadIdx.x; i < i1; i += 256) s += p[i];
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) partial[((size_t)k * nb + b) * nchunk + chunk] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-}
-// 256 threads per workgroup; nxy is a multiple of 256 (nx, ny multiples of 16), so
-// a workgroup's cells lie in one lattice.
-__global__ __launch_bounds__(256) void k_center_apply(float* __restrict__ dq, int nxy, int nb, long long N,
-                                                      int nchunk, const double* __restrict__ partial) {
-  __shared__ double mean;
-  const long long c0 = (long long)blockIdx.x * blockDim.x;
-  const int k = blockIdx.y;
-  if (threadIdx.x < 64) {
-    const double* q = partial + ((size_t)k * nb + (size_t)(c0 / nxy)) * nchunk;
-    double s = 0.0;
-    for (int j = (int)threadIdx.x; j < nchunk; j += 64) s += q[j];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (threadIdx.x == 0) mean = s / (double)nxy;
-  }
-  __syncthreads();
-  const long long c = c0 + threadIdx.x;
-  if (c < N) dq[(size_t)k * (size_t)N + c] -= (float)mean;
-}
-
-// per-block FP64 partials: [0..7] sum dQ_k^2, [8] sum divc(X)^2, [9] sum divc(X + dQ)^2,
+// Gate statistics of the network's correction, after its projection onto zero lattice
+// totals.  The fine run, its restriction and the coarse VLBM all keep each lattice's
+// totals of rho, rho u, E and B (up to the Powell source), so the correction they
+// define has zero total; projecting the prediction onto that keeps a small bias of the
+// network from accumulating in the totals over many steps.
+// raw: the network's output; tsum (NULL: no projection): its per-channel tile sums
+// from the last convolution, tsum[k][tile], the ntl tiles of lattice b at
+// [b ntl, (b + 1) ntl).  Every workgroup works inside one lattice (blockIdx.y): it sums
+// that lattice's tile sums in a fixed order (all its workgroups get the same means),
+// writes dq = raw - mean (FP32, as stored) and accumulates over its cells the FP64
+// partials: [0..7] sum dQ_k^2, [8] sum divc(X)^2, [9] sum divc(X + dQ)^2,
 // [10] non-finite count, [11] sum |B(X)|^2 (the D components the divergence sees).
 // D = 2: nz lattices of nx x ny (divergence of the in-plane field); D = 3: one
-// nx x ny x nz lattice.
+// nx x ny x nz lattice.  raw and dq are distinct buffers (neighbours are read from raw
+// and projected on the fly).
 template <int D>
-__global__ __launch_bounds__(kGateThreads) void k_gate_partials(const float* __restrict__ X, const float* __restrict__ dq,
-                                                                int nx, int ny, int nz, double* __restrict__ partial) {
+__global__ __launch_bounds__(kGateThreads) void k_gate_partials(const float* __restrict__ X, const float* __restrict__ raw,
+                                                                float* __restrict__ dq, const double* __restrict__ tsum,
+                                                                int ntl, int nx, int ny, int nz,
+                                                                double* __restrict__ partial) {
   constexpr int NP = 12;
   __shared__ double sh[kGateThreads / 64][NP];
+  __shared__ float mean[8];
   const size_t N = (size_t)nx * ny * nz;
+  const int nb = gridDim.y, b = blockIdx.y;
+  const size_t ncl = N / (size_t)nb;  // cells per lattice
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int k = wv; k < 8; k += kGateThreads / 64) {
+    double t = 0.0;
+    if (tsum) {
+      const double* q = tsum + (size_t)k * nb * ntl + (size_t)b * ntl;
+      for (int j = lane; j < ntl; j += 64) t += q[j];
+      for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+    }
+    if (lane == 0) mean[k] = (float)(t / (double)ncl);
+  }
+  __syncthreads();
+  float mk[8];
+  for (int k = 0; k < 8; ++k) mk[k] = mean[k];
   double acc[NP];
   for (int j = 0; j < NP; ++j) acc[j] = 0.0;
-  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (size_t)gridDim.x * blockDim.x) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < ncl; i += (size_t)gridDim.x * blockDim.x) {
+    const size_t c = (size_t)b * ncl + i;
     const size_t sl = (c / ((size_t)nx * ny)) * nx * ny;  // z-slice
     const int x = (int)(c % nx), y = (int)((c / nx) % ny);
     const size_t xp = sl + (size_t)y * nx + (x + 1 == nx ? 0 : x + 1), xm = sl + (size_t)y * nx + (x == 0 ? nx - 1 : x - 1);
     const size_t yp = sl + (size_t)(y + 1 == ny ? 0 : y + 1) * nx + x, ym = sl + (size_t)(y == 0 ? ny - 1 : y - 1) * nx + x;
     for (int k = 0; k < 8; ++k) {
-      const double d = dq[(size_t)k * N + c];
+      const float v = raw[(size_t)k * N + c] - mk[k];
+      dq[(size_t)k * N + c] = v;
+      const double d = v;
       acc[k] += d * d;
       if (!(d - d == 0.0)) acc[10] += 1.0;
     }
     const float* Bx = X + 5 * N;
     const float* By = X + 6 * N;
-    const float* dBx = dq + 5 * N;
-    const float* dBy = dq + 6 * N;
+    const float* rBx = raw + 5 * N;
+    const float* rBy = raw + 6 * N;
     double dv = 0.5 * ((double)Bx[xp] - Bx[xm]) + 0.5 * ((double)By[yp] - By[ym]);
-    double ddv = 0.5 * ((double)dBx[xp] - dBx[xm]) + 0.5 * ((double)dBy[yp] - dBy[ym]);
+    double ddv = 0.5 * ((double)(rBx[xp] - mk[5]) - (double)(rBx[xm] - mk[5])) +
+                 0.5 * ((double)(rBy[yp] - mk[6]) - (double)(rBy[ym] - mk[6]));
     double b2 = (double)Bx[c] * Bx[c] + (double)By[c] * By[c];
     if constexpr (D == 3) {
       const size_t nxy = (size_t)nx * ny, r = c - sl, z = c / nxy;
       const size_t zp = (z + 1 == (size_t)nz ? 0 : z + 1) * nxy + r, zm = (z == 0 ? nz - 1 : z - 1) * nxy + r;
       const float* Bz = X + 7 * N;
-      const float* dBz = dq + 7 * N;
+      const float* rBz = raw + 7 * N;
       dv += 0.5 * ((double)Bz[zp] - Bz[zm]);
-      ddv += 0.5 * ((double)dBz[zp] - dBz[zm]);
+      ddv += 0.5 * ((double)(rBz[zp] - mk[7]) - (double)(rBz[zm] - mk[7]));
       b2 += (double)Bz[c] * Bz[c];
     }
     const double dv2 = dv + ddv;
@@ -642,13 +657,13 @@ __global__ __launch_bounds__(kGateThreads) void k_gate_partials(const float* __r
   }
   for (int j = 0; j < NP; ++j) {
     for (int off = 32; off > 0; off >>= 1) acc[j] += __shfl_xor(acc[j], off);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6][j] = acc[j];
+    if (lane == 0) sh[wv][j] = acc[j];
   }
   __syncthreads();
   if ((int)threadIdx.x < NP) {
-    double s = 0.0;
-    for (int w = 0; w < kGateThreads / 64; ++w) s += sh[w][threadIdx.x];
-    partial[(size_t)blockIdx.x * NP + threadIdx.x] = s;
+    double sum = 0.0;
+    for (int w = 0; w < kGateThreads / 64; ++w) sum += sh[w][threadIdx.x];
+    partial[((size_t)b * gridDim.x + blockIdx.x) * NP + threadIdx.x] = sum;
   }
 }
 
@@ -736,12 +751,13 @@ size_t packed_elems(int cin, int cout, int nzt) { return (size_t)nzt * ksteps(ci
 // S slices of D-slice lattices (D = 1 for 2D lattices); nzt = 1 (3x3) or 3 (3x3x3)
 hipError_t launch_conv(int cin, int cout, int mode, int nzt, const bf16_t* act, const bf16_t* wpack,
                        const float* bias, int S, int D, int H, int W, bf16_t* out_act, float* out_z,
-                       const float* zprev, const float* oscale, const float* oshift, hipStream_t s) {
+                       const float* zprev, const float* oscale, const float* oshift, hipStream_t s,
+                       double* tsum = nullptr) {
   const dim3 grd(W / TILE, H / TILE, S), blk(kThreads);
 #define CONV_CASE(CI, CO, M, Z)                                                                          \
   if (cin == CI && cout == CO && mode == M && nzt == Z) {                                               \
     hipLaunchKernelGGL((k_conv<CI, CO, M, Z>), grd, blk, 0, s, act, wpack, bias, D, H, W, out_act, out_z, \
-                       zprev, oscale, oshift);                                                         \
+                       zprev, oscale, oshift, tsum);                                                   \
     return hipGetLastError();                                                                          \
   }
 #define CONV_CASES(Z)             \
@@ -826,9 +842,10 @@ vlbm_status ensure_workspace(vlbm_nn* nn, size_t positions) {
 
 // forward pass; mode_train keeps the pre-activations.  Writes nn->d_y (NCHW FP32),
 // scaled by oscale/oshift.
-// X == NULL: the first layer's input is already in nn->d_act[0].
+// X == NULL: the first layer's input is already in nn->d_act[0].  tsum != NULL: the
+// last layer also writes its per-channel tile sums there (k_conv).
 vlbm_status forward(vlbm_nn* nn, const float* X, int B, int nx, int ny, int nz, bool train, const float* oscale,
-                    const float* oshift, float* yout, hipStream_t s) {
+                    const float* oshift, float* yout, hipStream_t s, double* tsum = nullptr) {
   const int S = B * nz;  // slices
   const size_t P = (size_t)S * nx * ny;
   vlbm_status st = ensure_workspace(nn, P);
@@ -844,7 +861,7 @@ vlbm_status forward(vlbm_nn* nn, const float* X, int B, int nx, int ny, int nz, 
     NN_HIP(nn, launch_conv(nn->ci[l], nn->co[l], last ? MODE_LAST : MODE_HIDDEN, nn->nzt, nn->d_act[l],
                            nn->d_wf[l], nn->d_param + nn->boff[l], S, nz, ny, nx,
                            last ? nullptr : nn->d_act[l + 1], last ? yout : (train ? nn->d_z[l] : nullptr),
-                           nullptr, oscale, oshift, s));
+                           nullptr, oscale, oshift, s, last ? tsum : nullptr));
   }
   return VLBM_OK;
 }
@@ -1173,14 +1190,20 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
   int* flag = nullptr;  // flag[0..1] ping-pong
   long long* fb = nullptr;
   double* gpart = nullptr;
-  double* cpart = nullptr;  // projection partials
+  float* raw = nullptr;     // the network's output before the projection
+  double* ctsum = nullptr;  // its per-channel tile sums
   // cells per lattice (the projection's unit)
-  const int nxy = (int)(N / (size_t)nbatch), nchunk = (nxy + kCenterChunk - 1) / kCenterChunk;
+  // cells per lattice, conv tiles (16 x 16 cells of one slice) in all and per lattice
+  const size_t ncl = N / (size_t)nbatch, ntile = N / (TILE * TILE);
+  const int ntl = (int)(ntile / (size_t)nbatch);
   hipStream_t cs = nullptr;  // the loop runs on its own stream, ordered after and before s
   hipEvent_t ev = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  const int gblk = (int)std::min<size_t>(1024, (N + kGateThreads - 1) / kGateThreads);
+  // gate workgroups per lattice, about 1024 in all
+  const int gbpl = (int)std::max<size_t>(
+      1, std::min<size_t>((ncl + kGateThreads - 1) / kGateThreads, std::max<size_t>(1, 1024 / (size_t)nbatch)));
+  const int gblk = gbpl * nbatch;
   auto cleanup = [&]() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -1190,7 +1213,8 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
     if (flag) (void)hipFree(flag);
     if (fb) (void)hipFree(fb);
     if (gpart) (void)hipFree(gpart);
-    if (cpart) (void)hipFree(cpart);
+    if (raw) (void)hipFree(raw);
+    if (ctsum) (void)hipFree(ctsum);
     if (ev) (void)hipEventDestroy(ev);
     if (cs) (void)hipStreamDestroy(cs);
   };
@@ -1200,7 +1224,8 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
   if (e == hipSuccess) e = hipMalloc(&flag, 2 * sizeof(int));
   if (e == hipSuccess) e = hipMalloc(&fb, sizeof(long long));
   if (e == hipSuccess) e = hipMalloc(&gpart, (size_t)gblk * 12 * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc(&cpart, (size_t)8 * nbatch * nchunk * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&raw, 8 * N * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&ctsum, 8 * ntile * sizeof(double));
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventRecord(ev, s);
@@ -1220,21 +1245,17 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
     launch_moments_x(c, par, dq[cur], flag + cur, X, nn->d_norm + 0, nn->d_norm + 8, nn->d_act[0], cs);
     e = hipGetLastError();
     if (e != hipSuccess) return VLBM_ERR_HIP;
-    fs = forward(nn, nullptr, nbatch, c->p.nx, c->p.ny, nzl, false, nn->d_norm + 24, nn->d_norm + 16, dq[1 - cur],
-                 cs);
+    fs = forward(nn, nullptr, nbatch, c->p.nx, c->p.ny, nzl, false, nn->d_norm + 24, nn->d_norm + 16, raw, cs,
+                 project_totals ? ctsum : nullptr);
     if (fs != VLBM_OK) return fs;
-    if (project_totals) {
-      hipLaunchKernelGGL(k_center_sum, dim3((unsigned)nchunk, 8, (unsigned)nbatch), dim3(256), 0, cs, dq[1 - cur],
-                         nxy, nbatch, (long long)N, cpart);
-      hipLaunchKernelGGL(k_center_apply, dim3((unsigned)((N + 255) / 256), 8), dim3(256), 0, cs, dq[1 - cur], nxy,
-                         nbatch, (long long)N, nchunk, cpart);
-    }
+    // projection (when asked for) and gate statistics; the projected correction lands in dq
+    const dim3 ggrid((unsigned)gbpl, (unsigned)nbatch);
     if (c->D == 2)
-      hipLaunchKernelGGL(k_gate_partials<2>, dim3(gblk), dim3(kGateThreads), 0, cs, X, dq[1 - cur], c->p.nx,
-                         c->p.ny, c->p.nz, gpart);
+      hipLaunchKernelGGL(k_gate_partials<2>, ggrid, dim3(kGateThreads), 0, cs, X, raw, dq[1 - cur],
+                         project_totals ? ctsum : nullptr, ntl, c->p.nx, c->p.ny, c->p.nz, gpart);
     else
-      hipLaunchKernelGGL(k_gate_partials<3>, dim3(gblk), dim3(kGateThreads), 0, cs, X, dq[1 - cur], c->p.nx,
-                         c->p.ny, c->p.nz, gpart);
+      hipLaunchKernelGGL(k_gate_partials<3>, ggrid, dim3(kGateThreads), 0, cs, X, raw, dq[1 - cur],
+                         project_totals ? ctsum : nullptr, ntl, c->p.nx, c->p.ny, c->p.nz, gpart);
     hipLaunchKernelGGL(k_gate_final, dim3(1), dim3(64), 0, cs, gpart, gblk, gb, flag + (1 - cur), fb);
     e = hipGetLastError();
     if (e == hipSuccess) e = vlbm::launch_sweep_inj(L, c->g, c->ph, c->cd, par, dq[cur], flag + cur);
