@@ -39,6 +39,17 @@ struct Inflow {
   double q[8];
 };
 
+// Optional outputs of the injecting sweep (learned correction): the pre-collision
+// moments of every cell after the injection, FP32 [8][N] in x, and the network's
+// standardised input, BF16 channels-last [N][8] in act ((x - mean[k]) * istd[k],
+// rounded to nearest even).  x == NULL: none.
+struct MomentsOut {
+  float* x;
+  unsigned short* act;
+  const float* mean;
+  const float* istd;
+};
+
 // FP16/BF16 deviation codec: f = rest[k*NQ+i] + sc[k*NQ+i] * h,
 // h = round((f - rest) * isc).  Index i is the population's direction.
 struct Codec {
@@ -87,7 +98,7 @@ hipError_t launch_sweep_body(const Launch& L, const Grid& g, const Phys& ph, con
 // Sweep of a periodic 2D or 3D ideal-MHD BGK lattice (any storage form) that first
 // adds *flag * w_i dq[k][c] to the gathered, decoded populations (dq FP32 [K][N], device).
 hipError_t launch_sweep_inj(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
-                            const float* dq, const int* flag);
+                            const float* dq, const int* flag, const MomentsOut& mo);
 
 // f := f^eq(Q) in natural layout.  Q is device SoA [K][N], FP64 or FP32.
 hipError_t launch_init(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd,

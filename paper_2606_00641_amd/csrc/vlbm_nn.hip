@@ -518,41 +518,6 @@ __device__ inline void upwind_cells(const vlbm::Grid& g, size_t c, size_t* up) {
   }
 }
 
-// X = moments of the populations at the given parity (+ flag * pending dQ), FP32;
-// also the network's standardised BF16 channels-last input (as k_prep computes it
-// from X) when act0 is not NULL
-template <int ST, int D>
-__global__ void k_moments_x(const vlbm::Grid g, const vlbm::Codec cd, int parity, const float* __restrict__ dq,
-                            const int* __restrict__ flag, float* __restrict__ X, const float* __restrict__ in_mean,
-                            const float* __restrict__ in_istd, bf16_t* __restrict__ act0) {
-  using S = vlbm::Store<ST>;
-  using T = typename S::T;
-  constexpr int K = 8, NQ = 2 * D + 1;
-  const size_t N = (size_t)g.nx * g.ny * g.nz;
-  const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= N) return;
-  size_t up[NQ];
-  upwind_cells<D>(g, c, up);
-  const T* F = static_cast<const T*>(g.f);
-  const bool add = flag && *flag;
-  unsigned packed[K / 2];
-  for (int k = 0; k < K; ++k) {
-    // FP64 accumulation in direction order, as vlbm_moments
-    double q = 0.0;
-    for (int i = 0; i < NQ; ++i) {
-      const int slot = parity == 0 ? i : vlbm::opposite(i);
-      const size_t src = parity == 0 ? c : up[i];
-      q += S::dec64(F[(size_t)(k * NQ + slot) * g.stride + src], cd, k * NQ + i);
-    }
-    if (add) q += (double)dq[(size_t)k * N + c];
-    const float xq = (float)q;
-    X[(size_t)k * N + c] = xq;
-    const unsigned h = f2bf((xq - in_mean[k]) * in_istd[k]);
-    packed[k / 2] = (k & 1) ? (packed[k / 2] | (h << 16)) : h;
-  }
-  if (act0) *reinterpret_cast<uint4*>(act0 + c * K) = make_uint4(packed[0], packed[1], packed[2], packed[3]);
-}
-
 // add w_i dQ_k to every population at the given parity, if *flag (or flag is NULL);
 // FP16/BF16 deviations are decoded, incremented in FP32 and encoded again
 template <int ST, int D>
@@ -1143,22 +1108,6 @@ void launch_inject(const vlbm_ctx* c, int par, const float* dq, const int* flag,
   }
 }
 
-// X, and the network's first-layer input (standardised with in_mean, in_istd) in act0
-void launch_moments_x(const vlbm_ctx* c, int par, const float* dq, const int* flag, float* X, const float* in_mean,
-                      const float* in_istd, bf16_t* act0, hipStream_t s) {
-  const dim3 cgrid((unsigned)(((size_t)c->N + 255) / 256)), cblk(256);
-  switch (c->p.storage * 2 + (c->D - 2)) {
-#define MX_CASE(ST, D)                                                                                       \
-  case ST * 2 + (D - 2):                                                                                     \
-    hipLaunchKernelGGL((k_moments_x<ST, D>), cgrid, cblk, 0, s, c->g, c->cd, par, dq, flag, X, in_mean, in_istd, \
-                       act0);                                                                                \
-    break;
-    MX_CASE(vlbm::ST_F64, 2) MX_CASE(vlbm::ST_F64, 3) MX_CASE(vlbm::ST_F32, 2) MX_CASE(vlbm::ST_F32, 3)
-    MX_CASE(vlbm::ST_F16, 2) MX_CASE(vlbm::ST_F16, 3) MX_CASE(vlbm::ST_BF16, 2) MX_CASE(vlbm::ST_BF16, 3)
-#undef MX_CASE
-    default: break;
-  }
-}
 }  // namespace
 
 vlbm_status vlbm_inject(vlbm_ctx* c, const float* dQ) {
@@ -1244,15 +1193,20 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
   vlbm::Launch L = c->L;
   L.stream = cs;
   int cur = 0;  // dq[cur], flag[cur]: the pending correction (not yet in the populations)
-  // one corrected step: moments (with the pending correction), network, gate, sweep
-  // injecting the pending correction.  Kernels only, so that it can be captured.
+  // one corrected step: the sweep injecting the pending correction (it also writes the
+  // moments it collides with), the network on those moments, projection and gate of
+  // its correction (pending until the next sweep).  Kernels only, so that it can be
+  // captured.
   auto step = [&]() -> vlbm_status {
     const int par = (int)(c->step & 1);
     // the network's workspace is sized by the first (eager) step, never under capture
     vlbm_status fs = ensure_workspace(nn, N);
     if (fs != VLBM_OK) return fs;
-    launch_moments_x(c, par, dq[cur], flag + cur, X, nn->d_norm + 0, nn->d_norm + 8, nn->d_act[0], cs);
-    e = hipGetLastError();
+    // the sweep injects the pending correction and writes the moments it collides with
+    // (this step's network input, X and its standardised BF16 form); the network's
+    // correction for them is injected by the next sweep
+    const vlbm::MomentsOut mo{X, nn->d_act[0], nn->d_norm + 0, nn->d_norm + 8};
+    e = vlbm::launch_sweep_inj(L, c->g, c->ph, c->cd, par, dq[cur], flag + cur, mo);
     if (e != hipSuccess) return VLBM_ERR_HIP;
     fs = forward(nn, nullptr, nbatch, c->p.nx, c->p.ny, nzl, false, nn->d_norm + 24, nn->d_norm + 16, raw, cs,
                  project_totals ? ctsum : nullptr);
@@ -1267,7 +1221,6 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
                          project_totals ? ctsum : nullptr, ntl, c->p.nx, c->p.ny, c->p.nz, gpart);
     hipLaunchKernelGGL(k_gate_final, dim3(1), dim3(64), 0, cs, gpart, gblk, gb, flag + (1 - cur), fb);
     e = hipGetLastError();
-    if (e == hipSuccess) e = vlbm::launch_sweep_inj(L, c->g, c->ph, c->cd, par, dq[cur], flag + cur);
     if (e != hipSuccess) return VLBM_ERR_HIP;
     ++c->step;
     cur = 1 - cur;

@@ -83,7 +83,7 @@ template <int ST, int D, int MODEL, int PAR, int BODY = 0, int COLL = 0, bool IN
           bool FX = false>
 __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COLL == 0) ? 2 : 1) void k_sweep(
     const Grid g, const Phys ph, const Codec cd, const Body bd, const float* __restrict__ dq,
-    const int* __restrict__ dqflag, const Inflow in) {
+    const int* __restrict__ dqflag, const Inflow in, const MomentsOut mo) {
   using S = Store<ST>;
   using T = typename S::T;
   using R = typename S::R;
@@ -275,6 +275,22 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
       R Q[K], pt;
       const bool near = HlbmTarget::near_body(bd, x, y, z);
       collide<R, D, MODEL, COLL>(f, ph, dl, Q, pt, HlbmTarget{&bd, x, y, z, near, ph.s, ph.gm1});
+    } else if constexpr (INJ && MODEL == 0) {
+      R Q[K], pt;
+      collide<R, D, MODEL, COLL>(f, ph, dl, Q, pt);
+      if (mo.x) {  // the moments the next network evaluation takes
+        const size_t N = (size_t)g.nx * g.ny * g.nz;
+        unsigned h[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const float xq = (float)Q[k];
+          mo.x[(size_t)k * N + c] = xq;
+          const unsigned u = __float_as_uint((xq - mo.mean[k]) * mo.istd[k]);
+          h[k] = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;  // BF16, nearest even
+        }
+        *reinterpret_cast<uint4*>(mo.act + (size_t)c * K) =
+            make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+      }
     } else {
       collide<R, D, MODEL, COLL>(f, ph, dl);
     }
@@ -412,7 +428,8 @@ inline bool lane_exchange(const Grid& g, int block_x, int model) {
 // for are instantiated.
 template <int ST, int D, int MODEL, int BODY, bool INJ>
 void launch_k(const Launch& L, dim3 grd, int parity, int coll, bool xch, bool fx, const Grid& g, const Phys& ph,
-              const Codec& cd, const Body& b, const float* dq, const int* flag, const Inflow& in) {
+              const Codec& cd, const Body& b, const float* dq, const int* flag, const Inflow& in,
+              const MomentsOut& mo = MomentsOut{}) {
   constexpr bool kX = MODEL != 1 && (BODY == 0 || BODY == 3);  // exchange possible
   constexpr bool kF = D == 3 && MODEL == 0 && BODY != 2 && !INJ;  // x faces possible
   constexpr bool kC = !INJ;                                      // two-rate collisions possible
@@ -420,7 +437,7 @@ void launch_k(const Launch& L, dim3 grd, int parity, int coll, bool xch, bool fx
     constexpr int P = decltype(par_c)::value, C = decltype(coll_c)::value;
     constexpr bool X = decltype(xch_c)::value, FXv = decltype(fx_c)::value;
     hipLaunchKernelGGL((k_sweep<ST, D, MODEL, P, BODY, C, INJ, X, FXv>), grd, dim3(L.block_x), 0, L.stream, g, ph,
-                       cd, b, dq, flag, in);
+                       cd, b, dq, flag, in, mo);
   };
   using I0 = std::integral_constant<int, 0>;
   using I1 = std::integral_constant<int, 1>;
@@ -454,13 +471,13 @@ hipError_t sweep_t(const Launch& L, const Grid& g, const Phys& ph, const Codec& 
 
 template <int ST>
 hipError_t sweep_inj_t(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
-                       const float* dq, const int* flag) {
+                       const float* dq, const int* flag, const MomentsOut& mo) {
   if (L.dim == 2)
     launch_k<ST, 2, 0, 0, true>(L, cell_grid(g, L.block_x), parity, 0, lane_exchange(g, L.block_x, 0), false, g, ph,
-                                cd, Body{}, dq, flag, Inflow{});
+                                cd, Body{}, dq, flag, Inflow{}, mo);
   else
     launch_k<ST, 3, 0, 0, true>(L, cell_grid(g, L.block_x), parity, 0, lane_exchange(g, L.block_x, 0), false, g, ph,
-                                cd, Body{}, dq, flag, Inflow{});
+                                cd, Body{}, dq, flag, Inflow{}, mo);
   return hipGetLastError();
 }
 
@@ -501,14 +518,14 @@ hipError_t launch_sweep(const Launch& L, const Grid& g, const Phys& ph, const Co
 }
 
 hipError_t launch_sweep_inj(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
-                            const float* dq, const int* flag) {
+                            const float* dq, const int* flag, const MomentsOut& mo) {
   if ((L.dim != 2 && L.dim != 3) || L.model != 0 || ph.collision != 0) return hipErrorInvalidValue;
   if (L.dim == 3 && (g.bc[0] || g.bc[2] || g.bc[4] || g.mask)) return hipErrorInvalidValue;  // periodic, no body
   switch (L.storage) {
-    case ST_F64: return sweep_inj_t<ST_F64>(L, g, ph, cd, parity, dq, flag);
-    case ST_F32: return sweep_inj_t<ST_F32>(L, g, ph, cd, parity, dq, flag);
-    case ST_F16: return sweep_inj_t<ST_F16>(L, g, ph, cd, parity, dq, flag);
-    case ST_BF16: return sweep_inj_t<ST_BF16>(L, g, ph, cd, parity, dq, flag);
+    case ST_F64: return sweep_inj_t<ST_F64>(L, g, ph, cd, parity, dq, flag, mo);
+    case ST_F32: return sweep_inj_t<ST_F32>(L, g, ph, cd, parity, dq, flag, mo);
+    case ST_F16: return sweep_inj_t<ST_F16>(L, g, ph, cd, parity, dq, flag, mo);
+    case ST_BF16: return sweep_inj_t<ST_BF16>(L, g, ph, cd, parity, dq, flag, mo);
     default: return hipErrorInvalidValue;
   }
 }
