@@ -15,6 +15,10 @@ taps -- no blocking or fusion -- so it can be checked by eye:
 * Adam:   m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
           p -= lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps)
 * restriction R: r x r block mean of a moment field (conserves totals)
+* projection P: from every channel of every lattice of a batch its mean over that
+  lattice is removed -- the orthogonal projection onto corrections with zero lattice
+  totals (the totals that the fine run, its restriction and the coarse VLBM all keep,
+  up to the Powell source)
 * gate: the correction is dropped when a per-variable L2 norm exceeds its bound, when
   it raises the central-difference div B norm of the state by more than a relative
   amount plus an absolute amount (a fraction of the field's own L2 norm), or when it
@@ -187,6 +191,17 @@ def restrict(Q, r):
     K, nz, ny, nx = Q.shape
     rz = r if nz > 1 else 1
     return Q.reshape(K, nz // rz, rz, ny // r, r, nx // r, r).mean(axis=(2, 4, 6))
+
+
+def project(dQ, nlat):
+    """Projection onto zero lattice totals of a correction dQ [K, nz, ny, nx] whose nz
+    slices hold nlat lattices of nz / nlat slices each (a batch of 2D lattices:
+    nlat = nz; one 3D lattice: nlat = 1): channel by channel, each lattice loses its
+    own mean."""
+    K = dQ.shape[0]
+    per = dQ.reshape(K, nlat, -1)
+    mean = per.sum(axis=2, keepdims=True) / per.shape[2]
+    return (per - mean).reshape(dQ.shape)
 
 
 def b_l2(Q, dim=2):

@@ -257,7 +257,44 @@ def test_gate_cases():
     assert not C.gate(Q, div_only, big, 0.1, bound_divb_abs=0.01)
 
 
+def chk_projection(mod=C):
+    """The projection onto zero lattice totals, pinned by what defines it rather than
+    by its formula: P d has zero total in every channel of every lattice, and d - P d
+    is constant over each lattice in each channel (it lies in the orthogonal
+    complement of the zero-total fields), which fixes P d uniquely; P is idempotent
+    and self-adjoint.  Returns the largest violation, relative to the field's size."""
+    rng = np.random.default_rng(17)
+    worst = 0.0
+    for shape, nlat in (((8, 3, 16, 16), 3), ((8, 4, 8, 16), 1), ((8, 4, 8, 8), 2)):
+        d = rng.normal(size=shape) + rng.normal(size=(8, 1, 1, 1))  # nonzero means
+        e = rng.normal(size=shape)
+        Pd, Pe = mod.project(d, nlat), mod.project(e, nlat)
+        per = lambda a: a.reshape(8, nlat, -1)
+        scale = np.abs(d).max()
+        worst = max(worst,
+                    np.abs(per(Pd).sum(axis=2)).max() / (scale * per(Pd).shape[2]),
+                    np.ptp(per(d - Pd), axis=2).max() / scale,
+                    np.abs(mod.project(Pd, nlat) - Pd).max() / scale,
+                    abs((Pd * e).sum() - (d * Pe).sum()) / (np.abs(d).sum() * np.abs(e).max()))
+    return worst
+
+
+def test_projection_onto_zero_lattice_totals():
+    assert chk_projection() < 1e-13
+    # a uniform correction vanishes; a zero-total one is kept
+    u = np.ones((8, 2, 4, 4)) * np.arange(8)[:, None, None, None]
+    assert np.abs(C.project(u, 2)).max() < 1e-15
+    z = np.zeros((8, 2, 4, 4))
+    z[:, :, 0, 0], z[:, :, 1, 1] = 1.0, -1.0
+    assert np.array_equal(C.project(z, 2), z)
+
+
 MUTATIONS = {
+    "project_whole_batch": ("per = dQ.reshape(K, nlat, -1)", "per = dQ.reshape(K, 1, -1)"),
+    "project_all_channels": ("mean = per.sum(axis=2, keepdims=True) / per.shape[2]",
+                             "mean = per.sum(axis=(0, 2), keepdims=True) / (K * per.shape[2])"),
+    "project_mean_of_a_slice": ("mean = per.sum(axis=2, keepdims=True) / per.shape[2]",
+                                "mean = per.sum(axis=2, keepdims=True) / dQ.shape[-1]"),
     "conv_shift_sign": ("shifted = np.roll(a, shift=(-(ky - 1), -(kx - 1)), axis=(2, 3))  # a[y+ky-1, x+kx-1]",
                         "shifted = np.roll(a, shift=((ky - 1), (kx - 1)), axis=(2, 3))  # a[y+ky-1, x+kx-1]"),
     "backward_scatter_sign": ("da += np.roll(back, shift=(ky - 1, kx - 1), axis=(2, 3))",
@@ -292,5 +329,6 @@ def test_conv_pins_catch_planted_mistake(name):
     failed = (chk_conv_vs_scipy(mod) > 1e-12 or chk_conv_vs_torch(mod) > 1e-12
               or chk_conv3_vs_scipy(mod) > 1e-12 or chk_conv3_vs_torch(mod) > 1e-12
               or chk_gradients_fd(mod) > 1e-7 or chk_gradients3_fd(mod) > 1e-7
-              or chk_gelu_vs_torch(mod) > 1e-12 or chk_adam_vs_torch(mod) > 1e-12)
+              or chk_gelu_vs_torch(mod) > 1e-12 or chk_adam_vs_torch(mod) > 1e-12
+              or chk_projection(mod) > 1e-13)
     assert failed, name

@@ -21,7 +21,10 @@ Facts used (none of them re-calls or retypes the oracle's own routine):
   their identities with BGK on these first-order lattices;
 * translation invariance and the x<->y mirror symmetry;
 * resistive model: G relaxes to tau_M grad B, magnetic and viscous diffusion rates,
-  and the sign of the resistive energy flux (Sec. 2.2.1, Sec. 2.3).
+  the sign of the resistive energy flux, the viscous work -u . tau_v in the energy
+  flux (local energy change of a shear wave), and the Powell source fed by
+  tr G / tau_M: it cancels the monopole force of a non-solenoidal field and carries
+  div B with the flow (Sec. 2.2.1, Sec. 2.3).
 """
 import json
 import os
@@ -637,9 +640,18 @@ def test_mirror_symmetry_xy():
 # resistive model (Sec. 2.2.1, Sec. 2.3)
 # ----------------------------------------------------------------------------
 
+def _ddx(a, L):
+    """Spectral x-derivative of periodic samples over [0, L) (exact for the
+    band-limited fields used here)."""
+    k = 2 * np.pi * np.fft.fftfreq(a.shape[-1], d=L / a.shape[-1])
+    return np.real(np.fft.ifft(1j * k * np.fft.fft(a, axis=-1), axis=-1))
+
+
 def resistive_line(N, B_fn=None, u_fn=None, dt_over_tau=0.49, eta=0.0, mu=0.0, tau_lb=0.6,
-                   nsteps=100, s=0.2, L=2 * np.pi):
-    """Resistive model on an N x 1 x 1 D3Q7 line over [0, L); returns (Q0, Qn, params dict)."""
+                   nsteps=100, s=0.2, L=2 * np.pi, powell=1, relaxed=False):
+    """Resistive model on an N x 1 x 1 D3Q7 line over [0, L); returns (Q0, Qn, params dict).
+    relaxed: start G and H at their relaxed values tau_M d_x B, tau_H d_x u (the only
+    nonzero gradients of a field that varies along x), else at zero."""
     dx = L / N
     dt = s * dx
     tau_M = dt / dt_over_tau
@@ -648,8 +660,12 @@ def resistive_line(N, B_fn=None, u_fn=None, dt_over_tau=0.49, eta=0.0, mu=0.0, t
     u = np.zeros((3, N)) if u_fn is None else u_fn(x)
     Q = np.zeros((26, 1, 1, N))
     Q[:8] = line_state(np.ones(N), u, 0.6, B)
+    if relaxed:
+        for b in range(3):  # G[3a+b] ~ tau_M d_a B_b, H[3a+b] ~ tau_H d_a u_b, a = x
+            Q[8 + b, 0, 0] = tau_M * _ddx(B[b], L)
+            Q[17 + b, 0, 0] = tau_M * _ddx(u[b], L)
     P = oracle.make_params(dim=3, shape=(N, 1, 1), model=1, s=s, tau=tau_lb, dt=dt, mu=mu,
-                           eta0=eta, tau_M=tau_M, tau_H=tau_M, divb_mode=1)
+                           eta0=eta, tau_M=tau_M, tau_H=tau_M, divb_mode=1, powell=powell)
     f = oracle.init(P, Q)
     oracle.run(P, f, nsteps)
     Qn, _, _ = oracle.moments(P, f)
@@ -729,6 +745,73 @@ def chk_ohmic_energy_flux():
     return np.abs(dE - want).max() / np.abs(want).max()
 
 
+def chk_resistive_powell_monopole():
+    """Static plasma with a non-solenoidal B_x(x) in the resistive model, whose Powell
+    source takes div B from the transported gradient, tr G / tau_M (Sec. 2.3: Powell
+    correction; Sec. 2.2.1: G ~ tau_M grad B).  The magnetic force on the x-momentum
+    is d_x(B_x^2/2) = B_x dB_x/dx; Powell's -B_x div B cancels it, so with the source
+    the fluid stays at rest to leading order.  Returns max|m_x| with Powell / without."""
+    fn = dict(B_fn=lambda x: np.stack([0.3 + 0.05 * np.sin(x), 0 * x, 0 * x]))
+    _, Q1, _ = resistive_line(64, nsteps=10, powell=1, relaxed=True, **fn)
+    _, Q0, _ = resistive_line(64, nsteps=10, powell=0, relaxed=True, **fn)
+    return np.abs(Q1[1]).max() / np.abs(Q0[1]).max()
+
+
+def chk_resistive_powell_advection(nsteps=100):
+    """Uniform flow u0 along x with a non-solenoidal B_x bump in the resistive model.
+    The ideal induction flux moves nothing along x (Phi[B_x][x] = u_x B_x - B_x u_x =
+    0); Powell's -u div B makes B_x obey d_t B_x + u0 d_x B_x = 0, so the bump is
+    carried at u0 (u0 s cells per step), and its energy part -(u.B) div B keeps the
+    pressure uniform.  Returns (bump shift error in cells, max|p - p0| with Powell,
+    bump shift without Powell)."""
+    N = 64
+    L = 2 * np.pi
+    u0 = 0.1
+    bump = lambda x: np.stack([0.3 + 0.05 * np.exp(-((x - L / 2) ** 2) / (2 * (4 * L / N) ** 2)), 0 * x, 0 * x])
+    flow = lambda x: np.stack([u0 + 0 * x, 0 * x, 0 * x])
+    out = {}
+    for powell in (1, 0):
+        _, Qn, d = resistive_line(N, B_fn=bump, u_fn=flow, nsteps=nsteps, powell=powell, relaxed=True)
+        b = Qn[5] - 0.3
+        cells = np.arange(N)
+        out[powell] = ((b * cells).sum() / b.sum() - N / 2, np.abs(pressure(Qn) - 0.6).max())
+    want = nsteps * 0.2 * u0
+    return abs(out[1][0] - want), out[1][1], abs(out[0][0])
+
+
+def chk_viscous_work():
+    """Shear wave u = eps (0, sin x, 0) at B = 0 with viscosity mu: the energy flux
+    gains -u . tau_v (Sec. 2.3, resistive model), here -u_y mu d_x u_y =
+    -mu eps^2 sin(2x) / 2 along x, so the total energy changes locally by
+    d_t E = mu eps^2 cos(2x) (k = 1) at leading order, against the same run without
+    viscosity (the flux (E + p) u carries nothing along x, since u_x = 0).  H starts
+    relaxed, so the rate holds from the first step.  Returns the relative error of
+    (E_mu - E_0) against that rate times t over a short time."""
+    eps, mu, n = 0.1, 0.02, 10
+    fn = dict(u_fn=lambda x: eps * np.stack([0 * x, np.sin(x), 0 * x]), relaxed=True)
+    _, Q1, d = resistive_line(64, mu=mu, nsteps=n, **fn)
+    _, Q0, _ = resistive_line(64, mu=0.0, nsteps=n, **fn)
+    t = n * d["dt"]
+    want = mu * eps ** 2 * np.cos(2 * d["x"]) * t
+    dE = Q1[4] - Q0[4]
+    return np.abs(dE - want).max() / np.abs(want).max()
+
+
+def test_resistive_powell_cancels_monopole_force():
+    assert chk_resistive_powell_monopole() < 0.1
+
+
+def test_resistive_powell_advects_divergence():
+    shift_err, dp, shift_off = chk_resistive_powell_advection()
+    assert shift_err < 0.05
+    assert dp < 3e-4
+    assert shift_off < 0.05  # without the source the bump stays where it was
+
+
+def test_resistive_viscous_work():
+    assert chk_viscous_work() < 0.05
+
+
 def test_resistive_G_relaxes_to_gradient():
     assert chk_G_relaxes_to_gradient() < 0.03
 
@@ -769,6 +852,11 @@ MUTATIONS = {
     "resistive_G_flux_sign": ("- (c == a ? B[b] : 0.0);", "+ (c == a ? B[b] : 0.0);"),
     "ohmic_flux_sign": ("Phi[3 * 4 + b] += -utv + eta * jxB[b];", "Phi[3 * 4 + b] += -utv - eta * jxB[b];"),
     "viscous_transpose_dropped": ("p->mu * (du[a][b] + du[b][a])", "p->mu * (du[a][b] + du[a][b])"),
+    "viscous_work_dropped": ("Phi[3 * 4 + b] += -utv + eta * jxB[b];", "Phi[3 * 4 + b] += eta * jxB[b];"),
+    "viscous_work_sign": ("Phi[3 * 4 + b] += -utv + eta * jxB[b];", "Phi[3 * 4 + b] += utv + eta * jxB[b];"),
+    "powell_trG_dt_over_s_dropped": ("divB_lat = tr * (p->dt / p->s);", "divB_lat = tr;"),
+    "powell_trG_sign": ("divB_lat = tr * (p->dt / p->s);", "divB_lat = -tr * (p->dt / p->s);"),
+    "powell_trG_from_H": ("for (int a = 0; a < d; ++a) tr += dB[a][a];", "for (int a = 0; a < d; ++a) tr += du[a][a];"),
     "trt_rates_swapped": ("- om_s * (fp - ep) - om_a * (fm - em)", "- om_a * (fp - ep) - om_s * (fm - em)"),
     "trt_magic_inverted": ("1.0 / (0.5 + p->trt_magic / (p->tau[k] - 0.5))", "1.0 / (0.5 + (p->tau[k] - 0.5) / p->trt_magic)"),
     "rlb_projection_scale": ("const double fneq = weight(p, i) * eJ / c2;", "const double fneq = weight(p, i) * eJ;"),
@@ -791,6 +879,11 @@ def _fails(name):
         return chk_ohmic_energy_flux() > 0.05
     if name == "viscous_transpose_dropped":
         return chk_viscous_diffusion() > 0.03
+    if name.startswith("viscous_work"):
+        return chk_viscous_work() > 0.05
+    if name.startswith("powell_trG"):
+        shift_err, dp, shift_off = chk_resistive_powell_advection()
+        return chk_resistive_powell_monopole() > 0.1 or shift_err > 0.05 or dp > 3e-4
     if name == "powell_energy_dropped":
         _, dp_on, dp_off = chk_powell_advection()
         return dp_on > 3e-4
