@@ -279,6 +279,46 @@ def test_weight_gradient_exact_on_bf16_exact_operands(env, dim):
     assert rel_l2(gp[0][1], ograds[0][1]) < 1e-5
 
 
+@pytest.mark.parametrize("dim,shape,layers", [(2, (3, 8, 256, 256), 3), (3, (1, 8, 40, 64, 64), 2)])
+def test_gradients_match_oracle_many_tiles(env, dim, shape, layers):
+    """More 16 x 16 tiles than weight-gradient workgroups (768 and 640 against 512), so
+    every workgroup walks several tiles and reuses its LDS across the loop's barrier:
+    loss and every layer's gradients against the oracle at the BF16 tolerance."""
+    torch = env[0]
+    rng = np.random.default_rng(50 + dim)
+    params = rand_params(rng, layers, dim=dim)
+    X = rng.normal(size=shape)
+    T = rng.normal(size=shape)
+    net = make_net(env, layers, params, dim=dim)
+    loss, g = net.vlbm_nn_loss_grad(cm(torch, X), cm(torch, T))
+    oloss, ograds = C.Net(params, layers=layers, quantize=True, dim=dim).loss_and_grads(X, T)
+    assert abs(loss - oloss) <= 1e-2 * oloss
+    gp = unflat(g, layers, dim=dim)
+    for l in range(layers):
+        assert rel_l2(gp[l][0], ograds[l][0]) < 3e-2, (l, "W")
+        assert rel_l2(gp[l][1], ograds[l][1]) < 3e-2, (l, "b")
+
+
+@pytest.mark.parametrize("dim,shape", [(2, (3, 8, 256, 256)), (3, (1, 8, 40, 64, 64))])
+def test_weight_gradient_exact_many_tiles(env, dim, shape):
+    """The exact weight-gradient case (zero layer, BF16-exact operands: agreement up to
+    FP32 accumulation) with several tiles per workgroup (768 / 640 tiles, 512
+    workgroups)."""
+    torch = env[0]
+    rng = np.random.default_rng(57 + dim)
+    params = [(np.zeros(Ws), np.zeros(bs)) for Ws, bs in C.Net.shapes(8, 32, 1, dim=dim)]
+    X = C.bf16_round(rng.normal(size=shape))
+    n = int(np.prod(shape))
+    T = C.bf16_round(rng.normal(size=shape)) * (n / 2.0) * 2.0 ** -16
+    net = make_net(env, 1, params, dim=dim)
+    loss, g = net.vlbm_nn_loss_grad(cm(torch, X), cm(torch, T))
+    oloss, ograds = C.Net(params, layers=1, dim=dim).loss_and_grads(X, T)
+    assert abs(loss - oloss) <= 1e-6 * oloss
+    gp = unflat(g, 1, dim=dim)
+    assert rel_l2(gp[0][0], ograds[0][0]) < 1e-5
+    assert rel_l2(gp[0][1], ograds[0][1]) < 1e-5
+
+
 def test_conv3_training_reduces_loss(env):
     torch = env[0]
     rng = np.random.default_rng(36)
@@ -647,3 +687,129 @@ def test_3d_inject_matches_oracle(env):
     nn.vlbm_inject(sim, torch.tensor(dQ, dtype=torch.float32, device="cuda"))
     Q1, _ = sim.vlbm_moments()
     assert np.abs(Q1 - Q0 - dQ.astype(np.float32)).max() <= 1e-12
+
+
+# --- a random network's corrected steps against the oracle's composition ---------
+
+def _oracle_corrected(op_list, f_list, net_o, steps, bounds, norm, dim):
+    """The corrected coarse run composed from the oracle's parts: per step X = the
+    moments of the populations, dQ = P(out_mean + out_std * Net((X - in_mean) /
+    in_std)) (the quantised Net rounds its input to BF16; P the projection onto zero
+    lattice totals), the gate on (X, dQ) with bounds = (bound_corr, rel, abs), one
+    plain VLBM step, then f_{k,i} += w_i dQ_k if the gate accepted.  op_list / f_list:
+    one oracle lattice per batch entry (advanced in place).  Returns the applied
+    corrections (zero where rejected) and the decisions."""
+    in_mean, in_std, out_mean, out_std = (np.asarray(a, np.float64)[:, None, None, None] for a in norm)
+    nlat = len(f_list)
+    applied, decisions = [], []
+    for _ in range(steps):
+        X = np.concatenate([oracle.moments(op, f)[0].reshape(8, -1, op.ny, op.nx)
+                            for op, f in zip(op_list, f_list)], axis=1)  # [8, nz, ny, nx]
+        xs = (X - in_mean) / in_std
+        y = np.swapaxes(net_o.forward(np.swapaxes(xs, 0, 1)), 0, 1) if dim == 2 else net_o.forward(xs[None])[0]
+        dQ = C.project(out_mean + out_std * y, nlat)
+        ok = C.gate(X, dQ, bounds[0], bounds[1], bounds[2], dim=dim)
+        per = dQ.shape[1] // nlat
+        for j, (op, f) in enumerate(zip(op_list, f_list)):
+            oracle.run(op, f, 1)
+            if ok:
+                NQ = oracle.ndirs(op)
+                wts = np.array([op.w0] + [(1.0 - op.w0) / (NQ - 1)] * (NQ - 1))
+                f += wts[None, :, None] * dQ[:, j * per:(j + 1) * per].reshape(8, 1, -1)
+        applied.append(dQ if ok else np.zeros_like(dQ))
+        decisions.append(ok)
+    return applied, decisions
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_random_network_corrected_steps_match_oracle(env, dim):
+    """A random 4-layer network drives vlbm_step_corrected (FP64 populations, so the
+    network is the only low-precision part): one accepted step, two more accepted steps
+    in one call, then one step whose correction norm exceeds its bound.  Against the
+    oracle's composition (moments -> standardised BF16 input -> quantised Net ->
+    de-standardisation -> projection -> gate -> plain step -> injection): the first
+    applied correction agrees per channel to the network's BF16 precision (rel-L2 <=
+    1e-2, as the forward pass) and has zero lattice totals up to its FP32 rounding; the
+    state after three steps agrees to the FP32 bar, 1e-5 of its size (the corrections
+    are below 7e-4 of it, their BF16 error below 1e-2 of that), and its departure
+    from the plain run to 1e-2; the rejected step is bitwise the plain VLBM step."""
+    from test_gpu_parity import oracle_params
+    torch, vlbm, nn = env
+    rng = np.random.default_rng(70 + dim)
+    params = rand_params(rng, 4, dim=dim)
+    net = make_net(env, 4, params, dim=dim)
+    if dim == 2:
+        n, B = 32, 2
+        w = synth.workload_fourier_2d(n=n)
+        Qs = [synth.fourier_2d(n, seed=60 + j) for j in range(B)]
+        shape, lat_shape = (n, n, B), (n, n, 1)
+    else:
+        w = synth.workload_slab_3d()
+        Qs = [state3(seed=3)]
+        shape = lat_shape = SHAPE3
+    Q0 = np.concatenate(Qs, axis=1)
+    nlat = len(Qs)
+
+    def oracle_lattices():
+        ops = [oracle_params(w, shape=lat_shape) for _ in Qs]
+        return ops, [oracle.init(op, Q) for op, Q in zip(ops, Qs)]
+
+    def oracle_Q(ops, fs):
+        return np.concatenate([oracle.moments(op, f)[0].reshape(8, -1, op.ny, op.nx) for op, f in zip(ops, fs)],
+                              axis=1)
+
+    in_mean = Q0.reshape(8, -1).mean(axis=1)
+    in_std = Q0.reshape(8, -1).std(axis=1) + 1e-3
+    norm = (in_mean, in_std, np.zeros(8), np.full(8, 5e-5))
+    net.vlbm_nn_set_norm(*norm)
+    net_o = C.Net(params, layers=4, quantize=True, dim=dim)
+
+    def fresh():
+        sim = vlbm.Vlbm(gpu_params(vlbm, w, "f64", shape=shape))
+        sim.vlbm_init_fields(Q0)
+        return sim
+
+    a, plain = fresh(), fresh()
+    ops, fs = oracle_lattices()
+    opl, fpl = oracle_lattices()
+    big = np.full(8, 1e30)
+    # one step: the applied correction itself
+    applied, ok = _oracle_corrected(ops, fs, net_o, 1, (big, 10.0, 1.0), norm, dim)
+    assert ok == [True]
+    assert nn.vlbm_step_corrected(a, net, 1, big, 10.0, 1.0) == 0
+    plain.vlbm_step(1)
+    for op, f in zip(opl, fpl):
+        oracle.run(op, f, 1)
+    Qa, Qp = a.vlbm_moments()[0].reshape(Q0.shape), plain.vlbm_moments()[0].reshape(Q0.shape)
+    assert np.abs(Qp - oracle_Q(opl, fpl)).max() <= 1e-10 * np.abs(Q0).max()
+    dq = Qa - Qp
+    for k in range(8):
+        assert rel_l2(dq[k], applied[0][k]) <= 1e-2, k
+    per = dq.reshape(8, nlat, -1)
+    assert np.abs(per.sum(axis=2)).max() <= 1e-6 * np.abs(per).sum(axis=2).max()
+    # two more accepted steps in one call
+    _, ok = _oracle_corrected(ops, fs, net_o, 2, (big, 10.0, 1.0), norm, dim)
+    assert ok == [True, True]
+    assert nn.vlbm_step_corrected(a, net, 2, big, 10.0, 1.0) == 0
+    plain.vlbm_step(2)
+    for op, f in zip(opl, fpl):
+        oracle.run(op, f, 2)
+    Qa, Qp = a.vlbm_moments()[0].reshape(Q0.shape), plain.vlbm_moments()[0].reshape(Q0.shape)
+    Qo, Qpo = oracle_Q(ops, fs), oracle_Q(opl, fpl)
+    assert np.abs(Qa - Qo).max() <= 1e-5 * np.abs(Qo).max()
+    for k in range(8):
+        assert rel_l2((Qa - Qp)[k], (Qo - Qpo)[k]) <= 1e-2, k
+    # a step whose correction is over its bound in E: the oracle's gate rejects it,
+    # and the GPU takes the plain step
+    probe = [f.copy() for f in fs]
+    nxt, _ = _oracle_corrected(ops, probe, net_o, 1, (big, 10.0, 1.0), norm, dim)
+    bound = big.copy()
+    bound[4] = 0.5 * np.linalg.norm(nxt[0][4])
+    _, ok = _oracle_corrected(ops, fs, net_o, 1, (bound, 10.0, 1.0), norm, dim)
+    assert ok == [False]
+    buf, par, step = a.vlbm_get_populations()
+    b = fresh()
+    b.vlbm_set_populations(buf, par, step)
+    assert nn.vlbm_step_corrected(a, net, 1, bound, 10.0, 1.0) == 1
+    b.vlbm_step(1)
+    assert np.array_equal(a.vlbm_get_populations()[0], b.vlbm_get_populations()[0])

@@ -294,8 +294,9 @@ def test_d3q7_slab_at_rest_fp32(vb):
     assert np.abs(Qg[1:4] - Qo[1:4]).max() <= steps * 7 * fmax * 2.0 ** -23, err
 
 
-@pytest.mark.parametrize("storage,tol", [("f64", 1e-10), ("f32", 1e-5)])
-def test_d3q7_resistive_parity(vb, storage, tol):
+@pytest.mark.parametrize("storage,tol,steps", [("f64", 1e-10, 40), ("f32", 1e-5, 40), ("f64", 1e-10, 200),
+                                              ("f32", 1e-5, 200)])
+def test_d3q7_resistive_parity(vb, storage, tol, steps):
     """FP32: every field within 1e-5, except where the method's own formulas evaluated
     in FP32 arithmetic (the oracle compiled with float) already miss it -- the small
     transported gradients G, H ride on populations carrying an O(u) flux term, so
@@ -304,10 +305,11 @@ def test_d3q7_resistive_parity(vb, storage, tol):
     w = synth.workload_resistive_3d(n=16, dt_over_tau_M=0.49)
     w["shape"] = (12, 10, 8)
     Q0 = small_resistive()
-    steps = 40
-    _, Qg, _ = run_gpu(vb, w, Q0, steps, storage)
+    print(f"case resistive {storage} {steps} steps", flush=True)
+    _, Qg, tg = run_gpu(vb, w, Q0, steps, storage)
     Qo, _ = run_oracle(w, Q0, steps)
     err = rel_l2(Qg, Qo, 26)
+    assert tg[26 + 4] == 0  # the state stays physical (rho > 0, p >= 0, finite)
     if storage == "f64":
         assert max(err.values()) <= tol, err
         return
@@ -315,6 +317,47 @@ def test_d3q7_resistive_parity(vb, storage, tol):
     for name, e in err.items():
         assert e <= max(tol, 1.5 * yard[name]), (name, e, yard[name])
     assert max(err[k] for k in ("rho", "m", "E", "B")) <= tol, err
+
+
+# --- FP64 diagnostics against the oracle on the same populations ---------------
+
+@pytest.mark.parametrize("case", ["ideal", "resistive"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+def test_diagnostics_match_oracle_on_the_same_populations(vb, case, storage):
+    """Every FP64 diagnostic of vlbm_moments -- the K totals, sum d, sum d^2, max |d|
+    (d the div B estimate of the Powell source), the sum of the squared central
+    div B of the moment field and the count of unphysical cells -- against the
+    oracle's moments of the GPU's own decoded populations (gathered at every cell),
+    after an odd number of steps (the in-place pattern's odd parity) on a ragged D3Q7
+    box, for every storage form: the reductions agree to FP64 rounding, whatever the
+    storage (rounding of the populations themselves is not tested here)."""
+    if case == "ideal":
+        w = synth.workload_slab_3d()
+        w["shape"] = (20, 12, 10)
+        Q0, _ = synth.planar_discontinuity_3d(seed=2, shape=(10, 12, 20))
+        Q0 = boosted(Q0, (0.3, -0.2, 0.25))
+        K = 8
+    else:
+        w = synth.workload_resistive_3d(n=16, dt_over_tau_M=0.49)
+        w["shape"] = (12, 10, 8)
+        Q0 = small_resistive()
+        K = 26
+    print(f"case diagnostics {case} {storage}", flush=True)
+    sim, Qg, tg = run_gpu(vb, w, Q0, 7, storage)
+    N = int(np.prod(w["shape"]))
+    f = sim.vlbm_gather_cells(np.arange(N, dtype=np.int64))  # [N, K, Q]
+    f = np.ascontiguousarray(np.transpose(f, (1, 2, 0)))
+    Qo, do, to = oracle.moments(oracle_params(w), f)
+    scale = np.abs(Qo).max(axis=1)
+    assert np.all(np.abs(Qg.reshape(K, N) - Qo) <= 1e-14 * scale[:, None] + 1e-300)
+    assert np.all(np.abs(tg[:K] - to[:K]) <= 1e-13 * N * scale), (tg[:K], to[:K])
+    dsum = np.abs(do).sum()
+    assert abs(tg[K] - to[K]) <= 1e-13 * dsum
+    assert abs(tg[K + 1] - to[K + 1]) <= 1e-12 * to[K + 1]
+    assert abs(tg[K + 2] - to[K + 2]) <= 1e-12 * to[K + 2]
+    assert to[K + 1] > 0 and to[K + 3] > 0
+    assert abs(tg[K + 3] - to[K + 3]) <= 1e-12 * to[K + 3]
+    assert tg[K + 4] == to[K + 4] == 0
 
 
 # --- FP16 / BF16 deviation storage: one step at a time vs the oracle ------------
