@@ -185,6 +185,23 @@ vlbm_status vlbm_step(vlbm_ctx* c, int32_t n);
 vlbm_status vlbm_moments(vlbm_ctx* c, void* Q_out, int out_on_device, int out_is_f32,
                          double* totals);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): vlbm_moments without any device
+ * allocation.  Q_out: device FP64 moment field [K][nz][ny][nx] (required: the central
+ * div B pass reads the field from it; the caller owns it).  totals: host, K + 5
+ * doubles as in vlbm_moments, or NULL.  The FP64 partial sums live in a static array
+ * of VLBM_MOMENTS_NOALLOC_SCRATCH_BYTES bytes per GPU (1024 workgroups x (KMAX + 5)
+ * partials, 1024 more, and the totals), which each GPU the library runs on holds
+ * until the process ends; every lattice this library accepts fits in it.  All calls
+ * on one GPU share that array and overwrite it completely before reading it, so calls
+ * that overlap on one GPU (from two host threads or on two streams) race.  The
+ * device current at the call must be the one current at vlbm_create.  Synchronises
+ * the context's stream.  Errors: VLBM_ERR_ARG (NULL Q_out, another device current,
+ * a lattice whose partials would not fit), VLBM_ERR_STATE before vlbm_init_fields,
+ * VLBM_ERR_NONFINITE as vlbm_moments. */
+#define VLBM_MOMENTS_NOALLOC_SCRATCH_BYTES ((1024 * (VLBM_KMAX + 5) + 1024 + (VLBM_KMAX + 5)) * 8)
+vlbm_status vlbm_moments_noalloc(vlbm_ctx* c, double* Q_out, double* totals);
+
 /* Decoded pre-collision populations f_{k,i} at the given cells (host arrays):
  * cells[n] linear indices x + nx (y + ny z); out[n][K][Q] FP64.  Synchronises. */
 vlbm_status vlbm_gather_cells(vlbm_ctx* c, const int64_t* cells, int64_t n, double* out);

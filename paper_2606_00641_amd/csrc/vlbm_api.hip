@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -278,6 +279,10 @@ vlbm_status vlbm_create(const vlbm_params* p, vlbm_ctx** out) {
   c->stride = plane_stride(c->N, c->esize);
   c->pop_bytes = (size_t)c->K * c->NQ * c->stride * c->esize;
   c->stream = static_cast<hipStream_t>(p->stream);
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return fail(nullptr, VLBM_ERR_HIP, "hipGetDevice failed");
+  }
   if (p->rest_Q) {
     for (int k = 0; k < c->K; ++k) c->rest_Q[k] = p->rest_Q[k];
     c->rest_given = true;
@@ -545,6 +550,82 @@ vlbm_status vlbm_moments(vlbm_ctx* c, void* Q_out, int out_on_device, int out_is
     }
   }
   VLBM_HIP(c, hipStreamSynchronize(c->stream));
+  if (totals) std::memcpy(totals, tot, sizeof(double) * NT);
+  bool finite = true;
+  for (int j = 0; j < NT; ++j) finite = finite && std::isfinite(tot[j]);
+  if (!finite || tot[c->K + 4] > 0.0)
+    return fail(c, VLBM_ERR_NONFINITE, "%g unphysical cells (rho <= 0, p < 0 or non-finite)", tot[c->K + 4]);
+  return VLBM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Scratch of vlbm_moments_noalloc: the per-workgroup FP64 partials of the moments pass
+// (at most 1024 workgroups x (K + 5) values), those of the central div B pass (1024)
+// and the reduced totals (K + 5).  One copy per GPU the library runs on, held until
+// the process ends.  In host code `scratch` only names the symbol: its device address
+// comes from hipGetSymbolAddress, once per device.
+constexpr size_t kNoallocBlocks = 1024;
+constexpr size_t kScratchDoubles = kNoallocBlocks * (KMAX + 5) + kNoallocBlocks + (KMAX + 5);
+static_assert(kScratchDoubles * sizeof(double) == VLBM_MOMENTS_NOALLOC_SCRATCH_BYTES,
+              "scratch size and its public statement differ");
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array (the device must be current).
+hipError_t scratch_address(int dev, double** out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+vlbm_status vlbm_moments_noalloc(vlbm_ctx* c, double* Q_out, double* totals) {
+  if (!c) return VLBM_ERR_ARG;
+  if (!c->initialized) return fail(c, VLBM_ERR_STATE, "vlbm_moments_noalloc before vlbm_init_fields");
+  if (!Q_out) return fail(c, VLBM_ERR_ARG, "vlbm_moments_noalloc needs a device FP64 moment field");
+  const int NT = c->K + 5;
+  const size_t need = (size_t)c->nblk * NT + (size_t)c->nblk + NT;
+  if ((size_t)c->nblk > kNoallocBlocks || need > kScratchDoubles)
+    return fail(c, VLBM_ERR_ARG, "vlbm_moments_noalloc: %zu scratch doubles needed, %zu available", need,
+                kScratchDoubles);
+  int dev = -1;
+  VLBM_HIP(c, hipGetDevice(&dev));
+  if (dev != c->device)
+    return fail(c, VLBM_ERR_ARG, "vlbm_moments_noalloc: device %d is current, the context lives on device %d", dev,
+                c->device);
+  double* base = nullptr;
+  VLBM_HIP(c, scratch_address(dev, &base));
+  // every partial and total is written before it is read: nothing to clear
+  double* partial = base;
+  double* partial2 = base + (size_t)c->nblk * NT;
+  double* tot_d = partial2 + c->nblk;
+  double* Qd = static_cast<double*>(Q_out);
+  const int par = (int)(c->step & 1);
+  VLBM_HIP(c, launch_moments(c->L, c->g, c->ph, c->cd, par, Qd, partial, c->nblk));
+  const bool has_B = c->p.model == VLBM_IDEAL || c->p.model == VLBM_RESISTIVE;
+  if (has_B) VLBM_HIP(c, launch_divc(c->L, c->g, Qd, partial2, c->nblk));
+  VLBM_HIP(c, launch_reduce(c->L, NT, partial, c->nblk, 1u << (c->K + 2), tot_d));
+  if (has_B) VLBM_HIP(c, launch_reduce(c->L, 1, partial2, c->nblk, 0u, tot_d + c->K + 3));
+  double tot[KMAX + 5];
+  VLBM_HIP(c, hipMemcpyAsync(tot, tot_d, sizeof(double) * NT, hipMemcpyDeviceToHost, c->stream));
+  VLBM_HIP(c, hipStreamSynchronize(c->stream));
+  if (!has_B) tot[c->K + 3] = 0.0;
   if (totals) std::memcpy(totals, tot, sizeof(double) * NT);
   bool finite = true;
   for (int j = 0; j < NT; ++j) finite = finite && std::isfinite(tot[j]);

@@ -17,6 +17,7 @@ struct vlbm_ctx {
   void* f = nullptr;
   bool owned = false;
   hipStream_t stream = nullptr;
+  int device = 0;                 // the device current at vlbm_create
   vlbm::Phys ph{};
   vlbm::Codec cd{};
   vlbm::Grid g{};

@@ -98,6 +98,7 @@ def load_library(path: str = LIB_PATH):
         "vlbm_init_fields": [vp, vp, ctypes.c_int, ctypes.c_int],
         "vlbm_step": [vp, ctypes.c_int32],
         "vlbm_moments": [vp, vp, ctypes.c_int, ctypes.c_int, dp],
+        "vlbm_moments_noalloc": [vp, vp, dp],
         "vlbm_gather_cells": [vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, dp],
         "vlbm_get_populations": [vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int32),
                                  ctypes.POINTER(ctypes.c_int64)],
@@ -252,6 +253,15 @@ class Vlbm:
         if st != VLBM_OK and not (st == VLBM_ERR_NONFINITE and not raise_nonfinite):
             _check(st, self.ctx)
         return Q, totals
+
+    def vlbm_moments_noalloc(self, out):
+        """vlbm_moments without device allocations: out is a torch FP64 device tensor
+        of K x N values; returns (out, totals [K+5])."""
+        assert _is_torch(out) and str(out.dtype) == "torch.float64" and out.is_cuda and out.is_contiguous()
+        assert out.numel() == self.K * self.N
+        totals = np.zeros(self.K + 5, np.float64)
+        _check(_lib.vlbm_moments_noalloc(self.ctx, ctypes.c_void_p(out.data_ptr()), _dptr(totals)), self.ctx)
+        return out, totals
 
     def vlbm_gather_cells(self, cells):
         cells = np.ascontiguousarray(cells, np.int64)
