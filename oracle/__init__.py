@@ -193,7 +193,7 @@ def make_params(dim=2, shape=(64, 64, 1), model=0, gamma=5.0 / 3.0, s=0.2, w0=No
 
 
 def nvars(p):
-    return {1: 26, 2: 5, 3: 9}.get(p.model, 8)
+    return {1: 26, 2: 5, 3: 9, 4: 13}.get(p.model, 8)
 
 
 def ndirs(p):

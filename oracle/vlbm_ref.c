@@ -25,8 +25,10 @@ int vref_num_threads(void) {
 }
 
 int vref_nvars(const vref_params* p) {
-  return p->model == 1 ? 26 : (p->model == 2 ? 5 : (p->model == 3 ? 9 : 8));
+  return p->model == 1 ? 26 : (p->model == 2 ? 5 : (p->model == 3 ? 9 : (p->model == 4 ? 13 : 8)));
 }
+/* index of B_x in the state vector: 4 in the 13-component 2D system, else 5 */
+static int bx_index(const vref_params* p) { return p->model == 4 ? 4 : 5; }
 int vref_ndirs(const vref_params* p) { return 2 * p->dim + 1; }
 
 /* Lattice (Sec. 2.2; the paper's lattice table is not printed).
@@ -111,10 +113,91 @@ static int elastic_flux(const vref_params* p, const double* Q, double* Phi, doub
   return bad;
 }
 
+/* The 13-component 2D system of the Brio-Wu test (model 4; Sec. 3.1 names its 13
+ * components, Sec. 2.3 defines them): the in-plane state rho, rho u_x, rho u_y, e_tot,
+ * B_x, B_y, the transported viscous stress tau (symmetric: xx, xy, yy) and the
+ * transported field gradient G (G[2a+b] ~ tau_M d_a B_b: xx, xy, yx, yy), on D2Q5.
+ * Fluxes as in the full system of Sec. 2.3 (viscous stress tau_v in the momentum and
+ * energy fluxes, -eta grad B in the induction flux, eta j x B in the energy flux,
+ * with j = d_x B_y - d_y B_x out of the plane and grad B = G / tau_M); G is carried
+ * with G (x) u - I (x) B and relaxed by -G / tau_M (Sec. 2.2.1).
+ * READING ("a similar expansion logic is applied to the viscous stress tensor"): the
+ * transported stress T_ab is carried with T_ab u_c - mu (delta_ca u_b + delta_cb u_a)
+ * and relaxed by -T / tau_H, so that it settles at tau_H mu (d_a u_b + d_b u_a), the
+ * stress the 3D system builds from its transported velocity gradient H, and
+ * tau_v = T / tau_H.  Powell's source takes div B = tr G / tau_M (divb_mode 1) or the
+ * local estimate from the first moments of the B sets (divb_mode 0). */
+static int resistive2d_flux(const vref_params* p, const double* Q, const double* J, double* Phi, double* S,
+                            double* dlat) {
+  const double rho = Q[0], E = Q[3];
+  const double u[2] = {Q[1] / rho, Q[2] / rho};
+  const double B[2] = {Q[4], Q[5]};
+  const double* T = Q + 6; /* xx, xy, yy */
+  const double* G = Q + 9; /* xx, xy, yx, yy */
+  const double uu = u[0] * u[0] + u[1] * u[1], BB = B[0] * B[0] + B[1] * B[1];
+  const double uB = u[0] * B[0] + u[1] * B[1];
+  const double pres = (p->gamma - 1.0) * (E - 0.5 * rho * uu - 0.5 * BB);
+  const double ptot = pres + 0.5 * BB;
+  double dB[2][2], tv[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) dB[a][b] = G[2 * a + b] / p->tau_M;
+  const int tidx[2][2] = {{0, 1}, {1, 2}};
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) tv[a][b] = T[tidx[a][b]] / p->tau_H;
+  const double j = dB[0][1] - dB[1][0];
+  double eta = p->eta0;
+  if (p->j_c > 0.0) eta = p->eta0 * (1.0 + j * j / (p->j_c * p->j_c));
+  const double jxB[2] = {-j * B[1], j * B[0]};
+  for (int k = 0; k < 13; ++k) {
+    S[k] = 0.0;
+    for (int c = 0; c < 3; ++c) Phi[3 * k + c] = 0.0;
+  }
+  for (int c = 0; c < 2; ++c) {
+    Phi[3 * 0 + c] = Q[1 + c];
+    double utv = 0.0;
+    for (int a = 0; a < 2; ++a) {
+      Phi[3 * (1 + a) + c] = Q[1 + a] * u[c] + (a == c ? ptot : 0.0) - B[a] * B[c] - tv[a][c];
+      utv += u[a] * tv[a][c];
+      Phi[3 * (4 + a) + c] = u[c] * B[a] - B[c] * u[a] - eta * dB[c][a];
+    }
+    Phi[3 * 3 + c] = (E + ptot) * u[c] - B[c] * uB - utv + eta * jxB[c];
+    for (int a = 0; a < 2; ++a)
+      for (int b = a; b < 2; ++b)
+        Phi[3 * (6 + tidx[a][b]) + c] =
+            T[tidx[a][b]] * u[c] - p->mu * ((c == a ? u[b] : 0.0) + (c == b ? u[a] : 0.0));
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) Phi[3 * (9 + 2 * a + b) + c] = G[2 * a + b] * u[c] - (c == a ? B[b] : 0.0);
+  }
+  for (int q = 0; q < 3; ++q) S[6 + q] = -T[q] * p->dt / p->tau_H;
+  for (int q = 0; q < 4; ++q) S[9 + q] = -G[q] * p->dt / p->tau_M;
+  double divB_lat;
+  if (p->divb_mode == 1) {
+    divB_lat = (dB[0][0] + dB[1][1]) * (p->dt / p->s);
+  } else {
+    divB_lat = 0.0;
+    for (int a = 0; a < 2; ++a) divB_lat += J[3 * (4 + a) + a] / p->tau[4 + a];
+    divB_lat *= -1.0 / cs2(p);
+  }
+  *dlat = divB_lat;
+  if (p->powell) {
+    const double cp = -p->s * divB_lat;
+    for (int a = 0; a < 2; ++a) {
+      S[1 + a] += cp * B[a];
+      S[4 + a] += cp * u[a];
+    }
+    S[3] += cp * uB;
+  }
+  int bad = !(rho > 0.0) || !(pres >= 0.0);
+  for (int k = 0; k < 13; ++k)
+    if (!isfinite(Q[k])) bad = 1;
+  return bad;
+}
+
 int vref_flux_source(const vref_params* p, const double* Q, const double* J,
                      double* Phi, double* S, double* dlat) {
   if (p->model == 2) return euler_flux(p, Q, Phi, S, dlat);
   if (p->model == 3) return elastic_flux(p, Q, Phi, S, dlat);
+  if (p->model == 4) return resistive2d_flux(p, Q, J, Phi, S, dlat);
   const int K = vref_nvars(p);
   const int d = p->dim;
   const double g = p->gamma;
@@ -428,7 +511,7 @@ int vref_moments(const vref_params* p, const double* f, double* Q_out, double* d
           for (int a = 0; a < d; ++a) {
             const long cp = neighbour(p, x, y, z, 2 * a + 1);
             const long cm = neighbour(p, x, y, z, 2 * a + 2);
-            dv += 0.5 * (Qall[(long)(5 + a) * N + cp] - Qall[(long)(5 + a) * N + cm]);
+            dv += 0.5 * (Qall[(long)(bx_index(p) + a) * N + cp] - Qall[(long)(bx_index(p) + a) * N + cm]);
           }
           totals[K + 3] += dv * dv;
         }

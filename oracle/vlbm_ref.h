@@ -31,7 +31,10 @@ typedef struct {
   int32_t nx, ny, nz; /* nz must be 1 when dim == 2 */
   int32_t model;      /* 0: ideal MHD (K = 8); 1: resistive MHD with G, H (K = 26);
                          2: compressible Euler (K = 5); 3: linear elastodynamics
-                         (Navier-Cauchy) in velocity-stress form (K = 9) */
+                         (Navier-Cauchy) in velocity-stress form (K = 9); 4: the
+                         13-component 2D resistive system (rho, rho u_x, rho u_y,
+                         e_tot, B_x, B_y, transported stress xx xy yy relaxed with
+                         tau_H, G xx xy yx yy relaxed with tau_M; D2Q5 only) */
   int32_t powell;     /* 1: Powell source injected, 0: off */
   int32_t divb_mode;  /* 0: local non-equilibrium estimate of div B; 1: trace of G / tau_M */
   int32_t reserved;

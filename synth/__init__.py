@@ -21,6 +21,12 @@ dataset is involved):
   tau_M grad B, tau_H grad u (spectral derivatives).
 * ``planar_discontinuity_3d``: a slab with a seeded periodic normal separating
   seeded left/right states, tanh-smoothed over 2 cells.
+* ``resistive_2d_state`` / ``brio_wu_2d``: states of the 13-component 2D system
+  [13, 1, ny, nx] (rho, rho u_x, rho u_y, e_tot, B_x, B_y, the transported stress
+  T_xx, T_xy, T_yy, the transported gradient G_xx, G_xy, G_yx, G_yy): smooth seeded
+  Fourier fields with T, G at their relaxed values tau_H mu (grad u + grad u^T),
+  tau_M grad B (spectral derivatives); the Brio-Wu left/right states of the paper's
+  Sec. 3.1 in a periodic slab.
 """
 from __future__ import annotations
 
@@ -414,3 +420,87 @@ def workload_orszag_tang_2d(n=4000, tau=None):
     return dict(dim=2, shape=(n, n, 1), model=0, s=s, gamma=5.0 / 3.0, tau=tau, powell=1, divb_mode=0,
                 steps=int(round(0.5 / (s / n))), dt=0.0, mu=0.0, eta0=0.0, tau_M=1.0, tau_H=1.0)
 
+
+
+def _spectral_grad_2d(f, dx):
+    """d/dx and d/dy of a periodic field f [ny, nx] with cells of size dx."""
+    ny, nx = f.shape
+    kx = 2 * np.pi * np.fft.fftfreq(nx, d=dx)[None, :]
+    ky = 2 * np.pi * np.fft.fftfreq(ny, d=dx)[:, None]
+    F = np.fft.fft2(f)
+    return np.real(np.fft.ifft2(1j * kx * F)), np.real(np.fft.ifft2(1j * ky * F))
+
+
+def resistive_2d_state(shape, seed=0, kmax=3, u_amp=0.05, b_amp=0.05, B0=0.3, rho0=1.0, p0=0.6,
+                       gamma=5.0 / 3.0, tau_M=0.01, tau_H=0.01, mu=1e-3, dx=None):
+    """13-component 2D state [13, 1, ny, nx] on cells of size dx (default 2 pi / nx):
+    u and a vector potential A_z sums of seeded Fourier modes 1 <= |k| <= kmax scaled
+    to max |u| = u_amp, max |B - B0 x| = b_amp, B = B0 x + (d_y A_z, -d_x A_z); rho and
+    p uniform; T = tau_H mu (grad u + grad u^T), G = tau_M grad B (spectral)."""
+    ny, nx = shape
+    dx = 2.0 * np.pi / nx if dx is None else dx
+    rng = np.random.default_rng(seed)
+    u = _random_mode_field(rng, (ny, nx), kmax, 2)
+    u *= u_amp / np.sqrt((u * u).sum(0)).max()
+    A = _random_mode_field(rng, (ny, nx), kmax, 1)[0]
+    Ax, Ay = _spectral_grad_2d(A, dx)
+    B = np.stack([Ay, -Ax])
+    B *= b_amp / np.sqrt((B * B).sum(0)).max()
+    B[0] += B0
+    rho = np.full((ny, nx), rho0)
+    Q = np.zeros((13, 1, ny, nx))
+    Q[0, 0] = rho
+    Q[1, 0], Q[2, 0] = rho * u[0], rho * u[1]
+    Q[3, 0] = p0 / (gamma - 1.0) + 0.5 * rho * (u * u).sum(0) + 0.5 * (B * B).sum(0)
+    Q[4, 0], Q[5, 0] = B[0], B[1]
+    du = [_spectral_grad_2d(u[b], dx) for b in range(2)]  # du[b][a] = d_a u_b
+    dB = [_spectral_grad_2d(B[b], dx) for b in range(2)]
+    Q[6, 0] = tau_H * mu * 2.0 * du[0][0]
+    Q[7, 0] = tau_H * mu * (du[1][0] + du[0][1])
+    Q[8, 0] = tau_H * mu * 2.0 * du[1][1]
+    for a in range(2):
+        for b in range(2):
+            Q[9 + 2 * a + b, 0] = tau_M * dB[b][a]
+    return Q
+
+
+def brio_wu_2d(nx, ny, width=2.0, gamma=2.0, dtype=np.float64):
+    """The Brio-Wu shock-tube states of the paper's Sec. 3.1 as a 13-component 2D
+    state [13, 1, ny, nx]: (rho, p, u, v, B_x, B_y) = (1, 1, 0, 0, 0.75, 1) in the middle
+    half of the periodic x range and (0.125, 0.1, 0, 0, 0.75, -1) outside, blended by
+    1/2 (1 + tanh(distance / width)) at both interfaces; T = G = 0."""
+    x = np.arange(nx) + 0.5
+    d = np.minimum(x - nx / 4.0, 3.0 * nx / 4.0 - x)  # > 0 inside the left-state slab
+    wgt = 0.5 * (1.0 + np.tanh(d / width))
+    mix = lambda left, right: right + (left - right) * wgt
+    rho, p, By = mix(1.0, 0.125), mix(1.0, 0.1), mix(1.0, -1.0)
+    Bx = np.full(nx, 0.75)
+    Q = np.zeros((13, 1, ny, nx), dtype)
+    Q[0, 0] = rho[None, :]
+    Q[3, 0] = (p / (gamma - 1.0) + 0.5 * (Bx * Bx + By * By))[None, :]
+    Q[4, 0] = Bx[None, :]
+    Q[5, 0] = By[None, :]
+    return Q
+
+
+def workload_resistive_2d(n=64, ny=None, s=0.1, tau=0.6, dt_over_tau=0.49, mu=1e-3, eta0=1e-3, j_c=0.5):
+    """13-component 2D system on n x ny cells of size 2 pi / n: flux scale s, the
+    transported stress and gradient relaxed at dt / tau_M = dt / tau_H = dt_over_tau."""
+    dx = 2.0 * np.pi / n
+    dt = s * dx
+    tau_M = dt / dt_over_tau
+    return dict(dim=2, shape=(n, ny or n, 1), model=4, s=s, gamma=5.0 / 3.0, tau=tau, powell=1, divb_mode=1,
+                steps=200, dt=dt, mu=mu, eta0=eta0, j_c=j_c, tau_M=tau_M, tau_H=tau_M)
+
+
+def workload_brio_wu_2d(n=4096, ny=None, s=0.05):
+    """The paper's Brio-Wu test (Sec. 3.1) on the 13-component 2D system: [0, 1) in x
+    with n cells, gamma = 2 (Brio and Wu's value), ideal (mu = eta = 0) with the
+    constant artificial diffusivity 0.75e-4 as the stabilisation of the lattice
+    relaxation time, tau = 1/2 + D s / (c_s^2 dx); flux scale s = 0.05 keeps
+    s (|u| + c_fast) below c_s^2 = 1/3 (c_fast <= 3.8 in the right state);
+    tau_M = tau_H = 0.01 (the paper's tau_M)."""
+    dx = 1.0 / n
+    tau = 0.5 + 0.75e-4 * s / ((1.0 / 3.0) * dx)
+    return dict(dim=2, shape=(n, ny or n, 1), model=4, s=s, gamma=2.0, tau=tau, powell=1, divb_mode=1,
+                steps=int(round(0.1 / (s * dx))), dt=s * dx, mu=0.0, eta0=0.0, j_c=0.0, tau_M=0.01, tau_H=0.01)

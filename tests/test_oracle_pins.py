@@ -829,6 +829,109 @@ def test_resistive_ohmic_energy_flux_sign():
 
 
 # ----------------------------------------------------------------------------
+# the 13-component 2D system (Sec. 3.1, Sec. 2.3)
+# ----------------------------------------------------------------------------
+
+def _plane_states(nx=24, ny=20, seed=11, mu=0.01):
+    """A smooth in-plane state and its two forms: the 13-component 2D state and the
+    26-variable 3D resistive state of an nx x ny x 1 lattice (u_z = B_z = 0, no z
+    gradients), with arbitrary transported gradients G and H and the transported
+    stress T = mu (H + H^T) of the 2D system."""
+    rng = np.random.default_rng(seed)
+    y, x = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+
+    def smooth(amp):
+        f = np.zeros((ny, nx))
+        for _ in range(3):
+            kx, ky = rng.integers(-2, 3), rng.integers(-2, 3)
+            f += amp * rng.uniform(0.3, 1.0) * np.cos(2 * np.pi * (kx * x / nx + ky * y / ny) + rng.uniform(0, 6.3))
+        return f
+
+    rho = 1.0 + smooth(0.05)
+    u = [smooth(0.05), smooth(0.05)]
+    B = [0.3 + smooth(0.05), smooth(0.05)]
+    p = 0.6 + smooth(0.02)
+    E = p / (G53 - 1.0) + 0.5 * rho * (u[0] ** 2 + u[1] ** 2) + 0.5 * (B[0] ** 2 + B[1] ** 2)
+    G = [smooth(0.002) for _ in range(4)]  # G[2a+b]
+    H = [smooth(0.002) for _ in range(4)]  # H[2a+b]
+    Q3 = np.zeros((26, 1, ny, nx))
+    Q3[0], Q3[1], Q3[2], Q3[4], Q3[5], Q3[6] = rho, rho * u[0], rho * u[1], E, B[0], B[1]
+    for a in range(2):
+        for b in range(2):
+            Q3[8 + 3 * a + b] = G[2 * a + b]
+            Q3[17 + 3 * a + b] = H[2 * a + b]
+    Q2 = np.zeros((13, 1, ny, nx))
+    Q2[0], Q2[1], Q2[2], Q2[3], Q2[4], Q2[5] = rho, rho * u[0], rho * u[1], E, B[0], B[1]
+    Q2[6], Q2[7], Q2[8] = 2 * mu * H[0], mu * (H[1] + H[2]), 2 * mu * H[3]
+    Q2[9:13] = np.array(G)[:, None]
+    return Q2, Q3
+
+
+def chk_13_equals_3d_resistive(nsteps=30):
+    """The 13-component D2Q5 system against the 26-variable D3Q7 resistive system on an
+    nx x ny x 1 lattice with rest weight 0 (whose +-z pair then acts as the D2Q5 rest
+    population of weight 1/3 at the same c_s^2 = 1/3): both are linear in each
+    variable's populations given the fluxes, the 2D stress T obeys what mu (H + H^T)
+    obeys, and G_z*, H_z*, u_z, B_z stay zero, so the two runs agree in every in-plane
+    variable and T = mu (H + H^T), with viscosity, current-dependent resistivity and
+    Powell's source (from tr G / tau_M) all active.  Returns the largest difference
+    relative to each variable's size."""
+    nx, ny, mu = 24, 20, 0.01
+    Q2, Q3 = _plane_states(nx, ny, mu=mu)
+    kw = dict(s=0.2, tau=0.6, dt=0.01, mu=mu, eta0=0.02, j_c=0.5, tau_M=0.02, tau_H=0.02, divb_mode=1)
+    P2 = oracle.make_params(dim=2, shape=(nx, ny, 1), model=4, **kw)
+    P3 = oracle.make_params(dim=3, shape=(nx, ny, 1), model=1, w0=0.0, **kw)
+    f2, f3 = oracle.init(P2, Q2), oracle.init(P3, Q3)
+    oracle.run(P2, f2, nsteps)
+    oracle.run(P3, f3, nsteps)
+    A, _, _ = oracle.moments(P2, f2)
+    C, _, _ = oracle.moments(P3, f3)
+    H = lambda a, b: C[17 + 3 * a + b]
+    want = [C[0], C[1], C[2], C[4], C[5], C[6], mu * 2 * H(0, 0), mu * (H(0, 1) + H(1, 0)), mu * 2 * H(1, 1),
+            C[8], C[9], C[11], C[12]]
+    err = max(np.abs(A[k] - want[k]).max() / max(np.abs(want[k]).max(), 1e-300) for k in range(13))
+    stay = max(np.abs(C[k]).max() for k in (3, 7, 10, 13, 14, 15, 16, 19, 22, 23, 24, 25))
+    return err, stay
+
+
+def chk_13_stress_relaxes():
+    """The transported stress of a steady shear u = eps (0, sin x) settles at
+    tau_H mu (d_a u_b + d_b u_a): T_xy -> tau_H mu eps cos x (Sec. 2.2.1 relaxation
+    balance, reading P27).  Relative error after 60 steps (the shear itself decays
+    at mu k^2 only slowly)."""
+    N, eps, mu = 64, 0.05, 0.01
+    L = 2 * np.pi
+    dx = L / N
+    s = 0.2
+    dt = s * dx
+    tau_H = dt / 0.49
+    x = np.arange(N) * dx
+    Q = np.zeros((13, 1, 1, N))
+    u_y = eps * np.sin(x)
+    Q[0] = 1.0
+    Q[2] = u_y
+    Q[3] = 0.6 / (G53 - 1.0) + 0.5 * u_y ** 2
+    P = oracle.make_params(dim=2, shape=(N, 1, 1), model=4, s=s, tau=0.6, dt=dt, mu=mu, tau_M=tau_H, tau_H=tau_H,
+                           divb_mode=1)
+    f = oracle.init(P, Q)
+    oracle.run(P, f, 60)
+    Qn, _, _ = oracle.moments(P, f)
+    amp = 2 * (Qn[2] * np.sin(x)).mean()  # the shear's amplitude now
+    want = tau_H * mu * amp * np.cos(x)
+    return np.abs(Qn[7] - want).max() / np.abs(want).max()
+
+
+def test_13_component_system_equals_3d_resistive_plane():
+    err, stay = chk_13_equals_3d_resistive()
+    assert err < 1e-11, err
+    assert stay < 1e-13, stay
+
+
+def test_13_component_stress_relaxes_to_viscous_stress():
+    assert chk_13_stress_relaxes() < 0.03
+
+
+# ----------------------------------------------------------------------------
 # planted mistakes: each one must make at least one check fail
 # ----------------------------------------------------------------------------
 
@@ -867,6 +970,13 @@ MUTATIONS = {
     "elastic_stress_sign": ("for (int b = 0; b < 3; ++b) Phi[3 * b + a] = -Q[kSigIdx[b][a]];",
                             "for (int b = 0; b < 3; ++b) Phi[3 * b + a] = Q[kSigIdx[b][a]];"),
     "elastic_lambda_dropped": ("-((b == c ? lam * v[a] : 0.0) +", "-((b == c ? 0.0 * v[a] : 0.0) +"),
+    "r2d_stress_flux_half": ("p->mu * ((c == a ? u[b] : 0.0) + (c == b ? u[a] : 0.0))", "p->mu * ((c == a ? u[b] : 0.0))"),
+    "r2d_viscous_momentum_sign": ("- B[a] * B[c] - tv[a][c];", "- B[a] * B[c] + tv[a][c];"),
+    "r2d_ohmic_sign": ("- utv + eta * jxB[c];", "- utv - eta * jxB[c];"),
+    "r2d_G_flux_transposed": ("G[2 * a + b] * u[c] - (c == a ? B[b] : 0.0);", "G[2 * a + b] * u[c] - (c == b ? B[a] : 0.0);"),
+    "r2d_powell_trace": ("divB_lat = (dB[0][0] + dB[1][1]) * (p->dt / p->s);", "divB_lat = (dB[0][1] + dB[1][0]) * (p->dt / p->s);"),
+    "r2d_resistive_induction_transposed": ("- eta * dB[c][a];", "- eta * dB[a][c];"),
+    "r2d_current_sign": ("const double j = dB[0][1] - dB[1][0];", "const double j = dB[1][0] - dB[0][1];"),
     "elastic_shear_half": ("mu * ((a == b ? v[c] : 0.0) + (a == c ? v[b] : 0.0))", "mu * ((a == b ? v[c] : 0.0))"),
 }
 
@@ -889,6 +999,8 @@ def _fails(name):
         return dp_on > 3e-4
     if name == "divb_estimate_scale":
         return chk_divb_estimator_tau1() > 1e-12
+    if name.startswith("r2d_"):
+        return not (chk_13_equals_3d_resistive()[0] < 1e-11) or not (chk_13_stress_relaxes() < 0.03)
     if name.startswith("elastic"):
         return chk_elastic_speeds()[0] > 1e-4 or chk_elastic_lateral_stress() > 1e-9
     if name.startswith("euler"):
