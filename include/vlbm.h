@@ -22,7 +22,7 @@
  *     by the physical dt (Powell: by s times the lattice divergence).
  *   - Moment fields are SoA [K][nz][ny][nx] (x fastest).  Variable order k:
  *     0 rho; 1-3 rho u; 4 e_tot; 5-7 B; resistive only: 8-16 G (G[3a+b] ~ tau_M d_a B_b),
- *     17-25 H (H[3a+b] ~ tau_H d_a u_b).
+ *     17-25 H (H[3a+b] ~ tau_H d_a u_b); the other models list their own order below.
  *   - Direction order i: 0 rest, then +x, -x, +y, -y (, +z, -z).
  *   - Device pointers are HIP device addresses on the current device; host
  *     pointers are ordinary memory.  The caller owns every buffer it passes,
@@ -66,7 +66,23 @@ typedef enum { VLBM_D2Q5 = 0, VLBM_D3Q7 = 1 } vlbm_lattice;
  * Phi[sigma_bc][a] = -(lame_lambda delta_bc v_a + lame_mu (delta_ab v_c + delta_ac v_b)),
  * no source.  P and S waves travel at sqrt((lambda + 2 mu) / rho0) and sqrt(mu / rho0);
  * s times the P speed must stay below c_s^2. */
-typedef enum { VLBM_IDEAL = 0, VLBM_RESISTIVE = 1, VLBM_EULER = 2, VLBM_NAVIER_CAUCHY = 3 } vlbm_model;
+/* RESISTIVE_2D: the 13-component 2D system of the paper's Brio-Wu test (Sec. 3.1 names
+ * it; Sec. 2.3 and 2.2.1 define its parts), D2Q5 only: rho, rho u_x, rho u_y, e_tot,
+ * B_x, B_y (k = 0..5), the transported viscous stress T_xx, T_xy, T_yy (k = 6..8) and
+ * the transported field gradient G_xx, G_xy, G_yx, G_yy (k = 9..12, G[2a+b] ~ tau_M
+ * d_a B_b).  Fluxes of the full system of Sec. 2.3 with tau_v = T / tau_H and grad B =
+ * G / tau_M; T is carried with T_ab u_c - mu (delta_ca u_b + delta_cb u_a) and relaxed
+ * by -T dt / tau_H, so that it settles at tau_H mu (d_a u_b + d_b u_a); G with
+ * G (x) u - I (x) B, relaxed by -G dt / tau_M; eta(j) with j = d_x B_y - d_y B_x.  Takes
+ * dt, mu, eta0, j_c, tau_M, tau_H as the 3D resistive model; divb_mode 1: div B =
+ * tr G / tau_M. */
+typedef enum {
+  VLBM_IDEAL = 0,
+  VLBM_RESISTIVE = 1,
+  VLBM_EULER = 2,
+  VLBM_NAVIER_CAUCHY = 3,
+  VLBM_RESISTIVE_2D = 4
+} vlbm_model;
 
 /* Population storage in HBM.  F64 and F32 store f itself (F64 computes in FP64,
  * F32 in FP32).  F16DEV and BF16DEV store h = (f - f_rest[k][i]) / (w_i sigma_k),

@@ -48,7 +48,8 @@ vlbm_status hip_fail(vlbm_ctx* c, hipError_t e, const char* what) {
 
 int dim_of(int lattice) { return lattice == VLBM_D3Q7 ? 3 : 2; }
 int nvars_of(int model) {
-  return model == VLBM_RESISTIVE ? 26 : (model == VLBM_EULER ? 5 : (model == VLBM_NAVIER_CAUCHY ? 9 : 8));
+  return model == VLBM_RESISTIVE ? 26
+         : (model == VLBM_EULER ? 5 : (model == VLBM_NAVIER_CAUCHY ? 9 : (model == VLBM_RESISTIVE_2D ? 13 : 8)));
 }
 int esize_of(int storage) {
   switch (storage) {
@@ -81,7 +82,7 @@ vlbm_status validate(const vlbm_params* p) {
   if (plane_stride(N, esize_of(p->storage)) * esize_of(p->storage) >= (1LL << 32))
     return fail(nullptr, VLBM_ERR_ARG, "one population plane would exceed 4 GiB");
   if (p->model != VLBM_IDEAL && p->model != VLBM_RESISTIVE && p->model != VLBM_EULER &&
-      p->model != VLBM_NAVIER_CAUCHY)
+      p->model != VLBM_NAVIER_CAUCHY && p->model != VLBM_RESISTIVE_2D)
     return fail(nullptr, VLBM_ERR_ARG, "unknown model %d", p->model);
   if (p->model == VLBM_NAVIER_CAUCHY &&
       (!(p->lame_mu > 0.0) || !(p->rho0 > 0.0) || !(p->lame_lambda + 2.0 * p->lame_mu > 0.0) ||
@@ -89,6 +90,8 @@ vlbm_status validate(const vlbm_params* p) {
     return fail(nullptr, VLBM_ERR_ARG, "Navier-Cauchy needs lame_mu > 0, rho0 > 0, lame_lambda + 2 lame_mu > 0");
   if (p->model == VLBM_RESISTIVE && p->lattice != VLBM_D3Q7)
     return fail(nullptr, VLBM_ERR_ARG, "the resistive model needs D3Q7");
+  if (p->model == VLBM_RESISTIVE_2D && p->lattice != VLBM_D2Q5)
+    return fail(nullptr, VLBM_ERR_ARG, "the 13-component resistive model needs D2Q5");
   if (p->storage < VLBM_F64 || p->storage > VLBM_BF16DEV)
     return fail(nullptr, VLBM_ERR_ARG, "unknown storage %d", p->storage);
   if (!(p->gamma > 1.0) || !std::isfinite(p->gamma)) return fail(nullptr, VLBM_ERR_ARG, "gamma must be > 1");
@@ -100,9 +103,10 @@ vlbm_status validate(const vlbm_params* p) {
     if (!(p->tau[k] > 0.5) || !std::isfinite(p->tau[k]))
       return fail(nullptr, VLBM_ERR_ARG, "tau[%d] = %g must be > 0.5", k, p->tau[k]);
   if (p->powell != 0 && p->powell != 1) return fail(nullptr, VLBM_ERR_ARG, "powell must be 0 or 1");
-  if (p->divb_mode != 0 && !(p->divb_mode == 1 && p->model == VLBM_RESISTIVE))
+  const bool resistive = p->model == VLBM_RESISTIVE || p->model == VLBM_RESISTIVE_2D;
+  if (p->divb_mode != 0 && !(p->divb_mode == 1 && resistive))
     return fail(nullptr, VLBM_ERR_ARG, "divb_mode %d not valid for this model", p->divb_mode);
-  if (p->model == VLBM_RESISTIVE) {
+  if (resistive) {
     if (!(p->tau_M > 0.0) || !(p->tau_H > 0.0) || !(p->dt > 0.0))
       return fail(nullptr, VLBM_ERR_ARG, "resistive model needs dt, tau_M, tau_H > 0");
     if (!(p->mu >= 0.0) || !(p->eta0 >= 0.0)) return fail(nullptr, VLBM_ERR_ARG, "mu, eta0 must be >= 0");
@@ -209,6 +213,8 @@ void build_codec(vlbm_ctx* c) {
     flux_source<double, 2, 2>(c->rest_Q, Jb, c->ph, P, S, dl);
   else if (c->p.model == VLBM_EULER)
     flux_source<double, 3, 2>(c->rest_Q, Jb, c->ph, P, S, dl);
+  else if (c->p.model == VLBM_RESISTIVE_2D)
+    flux_source<double, 2, 4>(c->rest_Q, Jb, c->ph, P, S, dl);
   else if (c->D == 2)
     flux_source<double, 2, 0>(c->rest_Q, Jb, c->ph, P, S, dl);
   else if (c->p.model == VLBM_RESISTIVE)
@@ -297,8 +303,9 @@ vlbm_status vlbm_create(const vlbm_params* p, vlbm_ctx** out) {
   ph.w0 = w0;
   ph.wi = (1.0 - w0) / (2.0 * c->D);
   for (int k = 0; k < KMAX; ++k) ph.omega[k] = k < c->K ? 1.0 / p->tau[k] : 0.0;
-  for (int a = 0; a < 3; ++a) ph.inv_tauB[a] = 1.0 / p->tau[5 + a];
-  if (p->model == VLBM_RESISTIVE) {
+  const int bx = p->model == VLBM_RESISTIVE_2D ? 4 : 5;
+  for (int a = 0; a < 3; ++a) ph.inv_tauB[a] = 1.0 / p->tau[bx + a];
+  if (p->model == VLBM_RESISTIVE || p->model == VLBM_RESISTIVE_2D) {
     ph.dt_over_tauM = p->dt / p->tau_M;
     ph.dt_over_tauH = p->dt / p->tau_H;
     ph.inv_tauM = 1.0 / p->tau_M;
@@ -437,7 +444,9 @@ vlbm_status vlbm_init_fields(vlbm_ctx* c, const void* Q, int q_on_device, int q_
         for (int k = 0; k < c->K; ++k)
           c->rest_Q[k] = c->p.model == VLBM_NAVIER_CAUCHY
                              ? (k <= 2 ? 0.0 : mean[k] / (double)c->N)  // momentum at rest, mean stress
-                             : ((k >= 1 && k <= 3) || k >= 8 ? 0.0 : mean[k] / (double)c->N);
+                             : c->p.model == VLBM_RESISTIVE_2D
+                                   ? ((k >= 1 && k <= 2) || k >= 6 ? 0.0 : mean[k] / (double)c->N)
+                                   : ((k >= 1 && k <= 3) || k >= 8 ? 0.0 : mean[k] / (double)c->N);
     }
     bool need_scale = false;
     for (int k = 0; k < c->K; ++k) need_scale |= !(c->p.scale[k] > 0.0);
@@ -525,7 +534,7 @@ vlbm_status vlbm_moments(vlbm_ctx* c, void* Q_out, int out_on_device, int out_is
   const int NT = c->K + 5;
   const int par = (int)(c->step & 1);
   VLBM_HIP(c, launch_moments(c->L, c->g, c->ph, c->cd, par, Qd, c->d_partial, c->nblk));
-  const bool has_B = c->p.model == VLBM_IDEAL || c->p.model == VLBM_RESISTIVE;
+  const bool has_B = c->p.model == VLBM_IDEAL || c->p.model == VLBM_RESISTIVE || c->p.model == VLBM_RESISTIVE_2D;
   if (has_B) VLBM_HIP(c, launch_divc(c->L, c->g, Qd, c->d_partial2, c->nblk));
   VLBM_HIP(c, launch_reduce(c->L, NT, c->d_partial, c->nblk, 1u << (c->K + 2), c->d_totals));
   if (has_B) VLBM_HIP(c, launch_reduce(c->L, 1, c->d_partial2, c->nblk, 0u, c->d_totals + c->K + 3));
@@ -618,7 +627,7 @@ vlbm_status vlbm_moments_noalloc(vlbm_ctx* c, double* Q_out, double* totals) {
   double* Qd = static_cast<double*>(Q_out);
   const int par = (int)(c->step & 1);
   VLBM_HIP(c, launch_moments(c->L, c->g, c->ph, c->cd, par, Qd, partial, c->nblk));
-  const bool has_B = c->p.model == VLBM_IDEAL || c->p.model == VLBM_RESISTIVE;
+  const bool has_B = c->p.model == VLBM_IDEAL || c->p.model == VLBM_RESISTIVE || c->p.model == VLBM_RESISTIVE_2D;
   if (has_B) VLBM_HIP(c, launch_divc(c->L, c->g, Qd, partial2, c->nblk));
   VLBM_HIP(c, launch_reduce(c->L, NT, partial, c->nblk, 1u << (c->K + 2), tot_d));
   if (has_B) VLBM_HIP(c, launch_reduce(c->L, 1, partial2, c->nblk, 0u, tot_d + c->K + 3));

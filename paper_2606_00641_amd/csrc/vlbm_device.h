@@ -262,6 +262,7 @@ hipError_t dispatch(const Launch& L, A&&... args) {
     VLBM_CASE(3, 2, 0) VLBM_CASE(3, 3, 0) VLBM_CASE(3, 3, 1) VLBM_CASE(3, 2, 2) VLBM_CASE(3, 3, 2)
     VLBM_CASE(0, 2, 3) VLBM_CASE(0, 3, 3) VLBM_CASE(1, 2, 3) VLBM_CASE(1, 3, 3)
     VLBM_CASE(2, 2, 3) VLBM_CASE(2, 3, 3) VLBM_CASE(3, 2, 3) VLBM_CASE(3, 3, 3)
+    VLBM_CASE(0, 2, 4) VLBM_CASE(1, 2, 4) VLBM_CASE(2, 2, 4) VLBM_CASE(3, 2, 4)
 #undef VLBM_CASE
     default: return hipErrorInvalidValue;
   }

@@ -274,7 +274,8 @@ __global__ __launch_bounds__(kReduceThreads) void k_moments(const Grid g, const 
         const int slot = parity == 0 ? i : opposite(i);
         const double v = S::dec64(F[(size_t)(k * NQ + slot) * g.stride + src], cd, k * NQ + i);
         q += v;
-        if (k >= 5 && k < 5 + D && i > 0 && ((i - 1) >> 1) == k - 5) Jb[k - 5] += (i & 1) ? v : -v;
+        constexpr int bx = kBx<MODEL>;
+        if (k >= bx && k < bx + D && i > 0 && ((i - 1) >> 1) == k - bx) Jb[k - bx] += (i & 1) ? v : -v;
       }
       Q[k] = q;
       Qout[(size_t)k * N + c] = q;
@@ -334,8 +335,9 @@ __global__ __launch_bounds__(kReduceThreads) void k_body_loads(const Grid g, con
   block_reduce<8>(acc, 8, 0u, partial + (size_t)blockIdx.x * 8);
 }
 
+// bx: index of B_x in the moment field
 template <int D>
-__global__ __launch_bounds__(kReduceThreads) void k_divc(const Grid g, const double* __restrict__ Qm,
+__global__ __launch_bounds__(kReduceThreads) void k_divc(const Grid g, const double* __restrict__ Qm, int bx,
                                                          double* __restrict__ partial) {
   const size_t N = (size_t)g.nx * g.ny * g.nz;
   double acc[1] = {0.0};
@@ -348,7 +350,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_divc(const Grid g, const dou
     neighbours<D>(g, x, y, z, (unsigned)c, np, nm);
     double dv = 0.0;
 #pragma unroll
-    for (int a = 0; a < D; ++a) dv += 0.5 * (Qm[(size_t)(5 + a) * N + np[a]] - Qm[(size_t)(5 + a) * N + nm[a]]);
+    for (int a = 0; a < D; ++a) dv += 0.5 * (Qm[(size_t)(bx + a) * N + np[a]] - Qm[(size_t)(bx + a) * N + nm[a]]);
     acc[0] += dv * dv;
   }
   block_reduce<1>(acc, 1, 0u, partial + blockIdx.x);
@@ -535,10 +537,11 @@ hipError_t launch_moments(const Launch& L, const Grid& g, const Phys& ph, const 
 }
 
 hipError_t launch_divc(const Launch& L, const Grid& g, const double* Qout, double* partial, int nblk) {
+  const int bx = L.model == 4 ? kBx<4> : kBx<0>;
   if (L.dim == 2)
-    hipLaunchKernelGGL((k_divc<2>), dim3(nblk), dim3(kReduceThreads), 0, L.stream, g, Qout, partial);
+    hipLaunchKernelGGL((k_divc<2>), dim3(nblk), dim3(kReduceThreads), 0, L.stream, g, Qout, bx, partial);
   else
-    hipLaunchKernelGGL((k_divc<3>), dim3(nblk), dim3(kReduceThreads), 0, L.stream, g, Qout, partial);
+    hipLaunchKernelGGL((k_divc<3>), dim3(nblk), dim3(kReduceThreads), 0, L.stream, g, Qout, bx, partial);
   return hipGetLastError();
 }
 

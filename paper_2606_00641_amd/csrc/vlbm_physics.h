@@ -39,8 +39,13 @@ struct Phys {
 // Number of conserved variables of a model: 8 ideal MHD (rho, rho u, E, B), 26
 // resistive MHD (+ G, H), 5 compressible Euler (rho, rho u, E), 9 Navier-Cauchy
 // (rho0 v, sigma_xx, yy, zz, xy, xz, yz).
+// 13 for the 2D resistive system of Sec. 3.1 (rho, rho u_x, rho u_y, E, B_x, B_y, the
+// transported stress xx xy yy and G xx xy yx yy).
 template <int MODEL>
-inline constexpr int kNVars = MODEL == 1 ? 26 : (MODEL == 2 ? 5 : (MODEL == 3 ? 9 : 8));
+inline constexpr int kNVars = MODEL == 1 ? 26 : (MODEL == 2 ? 5 : (MODEL == 3 ? 9 : (MODEL == 4 ? 13 : 8)));
+// Index of B_x in the state (models with a field).
+template <int MODEL>
+inline constexpr int kBx = MODEL == 4 ? 4 : 5;
 
 // Index of sigma_bc in the Navier-Cauchy variables (symmetric, xx yy zz xy xz yz).
 __host__ __device__ constexpr int sigma_index(int b, int c) {
@@ -55,7 +60,85 @@ template <typename R, int D, int MODEL>
 __host__ __device__ inline bool flux_source(const R* Q, const R* Jb, const Phys& ph,
                                             R (*P)[3], R* S, R& dlat, R* pt_out = nullptr) {
   constexpr int K = kNVars<MODEL>;
-  if constexpr (MODEL == 3) {
+  if constexpr (MODEL == 4) {
+    // The 13-component 2D system of Sec. 3.1 on D2Q5: the full flux of Sec. 2.3 with
+    // the viscous stress carried as a transported stress T (xx, xy, yy) that settles
+    // at tau_H mu (d_a u_b + d_b u_a) (its flux T u_c - mu (delta_ca u_b + delta_cb
+    // u_a), its source -T dt / tau_H; tau_v = T / tau_H) and grad B as G / tau_M (G
+    // xx, xy, yx, yy, flux G u_c - delta_ca B_b, source -G dt / tau_M); j = d_x B_y -
+    // d_y B_x out of the plane.
+    static_assert(D == 2, "the 13-component system is two-dimensional");
+    const R rho = Q[0];
+    const R ir = R(1) / rho;
+    const R E = Q[3];
+    const R u[2] = {Q[1] * ir, Q[2] * ir};
+    const R B[2] = {Q[4], Q[5]};
+    const R uu = u[0] * Q[1] + u[1] * Q[2];  // rho |u|^2
+    const R bb = B[0] * B[0] + B[1] * B[1];
+    const R ub = u[0] * B[0] + u[1] * B[1];
+    const R pres = R(ph.gm1) * (E - R(0.5) * uu - R(0.5) * bb);
+    const R pt = pres + R(0.5) * bb;
+    if (pt_out) *pt_out = pt;
+    const R itm = R(ph.inv_tauM), ith = R(ph.inv_tauH), muv = R(ph.mu);
+    const R dB[2][2] = {{Q[9] * itm, Q[10] * itm}, {Q[11] * itm, Q[12] * itm}};
+    const R tv[2][2] = {{Q[6] * ith, Q[7] * ith}, {Q[7] * ith, Q[8] * ith}};
+    const R j = dB[0][1] - dB[1][0];
+    R eta = R(ph.eta0);
+    if (ph.inv_jc2 > 0.0) eta = eta * (R(1) + j * j * R(ph.inv_jc2));
+    const R jxb[2] = {-j * B[1], j * B[0]};
+    const R Ept = E + pt;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      P[0][c] = Q[1 + c];
+      R utv = R(0);
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        P[1 + a][c] = Q[1 + a] * u[c] - B[a] * B[c] - tv[a][c] + (a == c ? pt : R(0));
+        utv += u[a] * tv[a][c];
+        P[4 + a][c] = u[c] * B[a] - B[c] * u[a] - eta * dB[c][a];
+      }
+      P[3][c] = Ept * u[c] - B[c] * ub - utv + eta * jxb[c];
+      P[6][c] = Q[6] * u[c] - muv * (c == 0 ? R(2) * u[0] : R(0));                 // xx
+      P[7][c] = Q[7] * u[c] - muv * (c == 0 ? u[1] : u[0]);                        // xy
+      P[8][c] = Q[8] * u[c] - muv * (c == 1 ? R(2) * u[1] : R(0));                 // yy
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) P[9 + 2 * a + b][c] = Q[9 + 2 * a + b] * u[c] - (a == c ? B[b] : R(0));
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) S[k] = R(0);
+    const R sh = R(-ph.dt_over_tauH), sg = R(-ph.dt_over_tauM);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) S[6 + q] = Q[6 + q] * sh;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) S[9 + q] = Q[9 + q] * sg;
+    R divb;
+    if (ph.divb_mode == 1) {
+      divb = (dB[0][0] + dB[1][1]) * R(ph.divb_scale);
+    } else {
+      divb = -(Jb[0] * R(ph.inv_tauB[0]) + Jb[1] * R(ph.inv_tauB[1])) * R(ph.inv_cs2);
+    }
+    dlat = divb;
+    if (ph.powell) {
+      const R cp = -R(ph.s) * divb;
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        S[1 + b] += cp * B[b];
+        S[4 + b] += cp * u[b];
+      }
+      S[3] += cp * ub;
+    }
+    const R c = R(ph.s * ph.inv_cs2);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) P[k][a] *= c;
+    bool bad = !(rho > R(0)) || !(pres >= R(0));
+#pragma unroll
+    for (int k = 0; k < K; ++k) bad = bad || !(Q[k] - Q[k] == R(0));
+    return bad;
+  } else if constexpr (MODEL == 3) {
     // linear Navier-Cauchy in velocity-stress form: the momentum flux is minus the
     // stress, the stress flux minus the isotropic (lambda) and shear (mu) rates of v
     (void)Jb;
@@ -270,9 +353,10 @@ __device__ __forceinline__ bool collide(R (*f)[2 * D + 1], const Phys& ph, R& dl
     Q[k] = acc;
   }
   R Jb[3] = {R(0), R(0), R(0)};
-  if constexpr (MODEL == 0 || MODEL == 1) {
+  if constexpr (MODEL == 0 || MODEL == 1 || MODEL == 4) {
+    constexpr int bx = kBx<MODEL>;
 #pragma unroll
-    for (int a = 0; a < D; ++a) Jb[a] = f[5 + a][2 * a + 1] - f[5 + a][2 * a + 2];
+    for (int a = 0; a < D; ++a) Jb[a] = f[bx + a][2 * a + 1] - f[bx + a][2 * a + 2];
   }
   R Qt[K];
 #pragma unroll

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libvlbm.so")
 KMAX = 26
 VLBM_OK, VLBM_ERR_ARG, VLBM_ERR_OOM, VLBM_ERR_HIP, VLBM_ERR_STATE, VLBM_ERR_NONFINITE = 0, -1, -2, -3, -4, -5
 VLBM_D2Q5, VLBM_D3Q7 = 0, 1
-VLBM_IDEAL, VLBM_RESISTIVE, VLBM_EULER, VLBM_NAVIER_CAUCHY = 0, 1, 2, 3
+VLBM_IDEAL, VLBM_RESISTIVE, VLBM_EULER, VLBM_NAVIER_CAUCHY, VLBM_RESISTIVE_2D = 0, 1, 2, 3, 4
 VLBM_F64, VLBM_F32, VLBM_F16DEV, VLBM_BF16DEV = 0, 1, 2, 3
 VLBM_BC_PERIODIC, VLBM_BC_INFLOW_EQ, VLBM_BC_ZERO_GRAD = 0, 1, 2
 STORAGE = {"f64": VLBM_F64, "f32": VLBM_F32, "f16": VLBM_F16DEV, "bf16": VLBM_BF16DEV}
@@ -151,7 +151,8 @@ def make_params(lattice="D2Q5", shape=(64, 64, 1), model="ideal", storage="f32",
     p.lattice = VLBM_D3Q7 if str(lattice).upper() == "D3Q7" else VLBM_D2Q5
     p.nx, p.ny, p.nz = (int(v) for v in shape)
     p.model = {"ideal": VLBM_IDEAL, "resistive": VLBM_RESISTIVE, "euler": VLBM_EULER,
-               "navier_cauchy": VLBM_NAVIER_CAUCHY}[model] if isinstance(model, str) \
+               "navier_cauchy": VLBM_NAVIER_CAUCHY, "resistive_2d": VLBM_RESISTIVE_2D}[model] \
+            if isinstance(model, str) \
         else int(model)
     p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
     p.gamma = gamma
@@ -207,7 +208,7 @@ class Vlbm:
         if pop_tensor is not None:
             params.pop_buffer = pop_tensor.data_ptr()
             params.pop_bytes = pop_tensor.numel() * pop_tensor.element_size()
-        self.K = {VLBM_RESISTIVE: 26, VLBM_EULER: 5, VLBM_NAVIER_CAUCHY: 9}.get(params.model, 8)
+        self.K = {VLBM_RESISTIVE: 26, VLBM_EULER: 5, VLBM_NAVIER_CAUCHY: 9, VLBM_RESISTIVE_2D: 13}.get(params.model, 8)
         self.dim = 3 if params.lattice == VLBM_D3Q7 else 2
         self.Q = 2 * self.dim + 1
         self.shape = (params.nx, params.ny, params.nz)

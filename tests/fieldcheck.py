@@ -8,10 +8,11 @@ FAMILIES_26 = dict(FAMILIES_8, G=list(range(8, 17)), H=list(range(17, 26)))
 
 FAMILIES_5 = {"rho": [0], "m": [1, 2, 3], "E": [4]}
 FAMILIES_9 = {"m": [0, 1, 2], "sigma_normal": [3, 4, 5], "sigma_shear": [6, 7, 8]}
+FAMILIES_13 = {"rho": [0], "m": [1, 2], "E": [3], "B": [4, 5], "T": [6, 7, 8], "G": [9, 10, 11, 12]}
 
 
 def families(K):
-    return {26: FAMILIES_26, 5: FAMILIES_5, 9: FAMILIES_9}.get(K, FAMILIES_8)
+    return {26: FAMILIES_26, 5: FAMILIES_5, 9: FAMILIES_9, 13: FAMILIES_13}.get(K, FAMILIES_8)
 
 
 def rel_l2(a, b, K):

@@ -33,10 +33,11 @@ def _stream():
 def gpu_params(vb, w, storage, block_x=0, shape=None):
     shape = shape or w["shape"]
     return vb.make_params(lattice="D3Q7" if w["dim"] == 3 else "D2Q5", shape=shape,
-                          model={0: "ideal", 1: "resistive", 2: "euler", 3: "navier_cauchy"}[w["model"]],
+                          model={0: "ideal", 1: "resistive", 2: "euler", 3: "navier_cauchy",
+                                 4: "resistive_2d"}[w["model"]],
                           storage=storage,
                           gamma=w["gamma"], flux_scale=w["s"], tau=w["tau"], powell=w["powell"],
-                          divb_mode=w["divb_mode"], dt=w["dt"], mu=w["mu"], eta0=w["eta0"],
+                          divb_mode=w["divb_mode"], dt=w["dt"], mu=w["mu"], eta0=w["eta0"], j_c=w.get("j_c", 0.0),
                           tau_M=w["tau_M"], tau_H=w["tau_H"], stream=_stream(), block_x=block_x)
 
 
@@ -44,7 +45,8 @@ def oracle_params(w, shape=None):
     shape = shape or w["shape"]
     return oracle.make_params(dim=w["dim"], shape=shape, model=w["model"], gamma=w["gamma"], s=w["s"],
                               tau=w["tau"], powell=w["powell"], divb_mode=w["divb_mode"], dt=w["dt"],
-                              mu=w["mu"], eta0=w["eta0"], tau_M=w["tau_M"], tau_H=w["tau_H"])
+                              mu=w["mu"], eta0=w["eta0"], j_c=w.get("j_c", 0.0), tau_M=w["tau_M"],
+                              tau_H=w["tau_H"])
 
 
 def run_gpu(vb, w, Q0, steps, storage, block_x=0):
@@ -321,7 +323,7 @@ def test_d3q7_resistive_parity(vb, storage, tol, steps):
 
 # --- FP64 diagnostics against the oracle on the same populations ---------------
 
-@pytest.mark.parametrize("case", ["ideal", "resistive"])
+@pytest.mark.parametrize("case", ["ideal", "resistive", "resistive_2d"])
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
 def test_diagnostics_match_oracle_on_the_same_populations(vb, case, storage):
     """Every FP64 diagnostic of vlbm_moments -- the K totals, sum d, sum d^2, max |d|
@@ -337,11 +339,14 @@ def test_diagnostics_match_oracle_on_the_same_populations(vb, case, storage):
         Q0, _ = synth.planar_discontinuity_3d(seed=2, shape=(10, 12, 20))
         Q0 = boosted(Q0, (0.3, -0.2, 0.25))
         K = 8
-    else:
+    elif case == "resistive":
         w = synth.workload_resistive_3d(n=16, dt_over_tau_M=0.49)
         w["shape"] = (12, 10, 8)
         Q0 = small_resistive()
         K = 26
+    else:
+        w, Q0 = small_resistive_2d()
+        K = 13
     print(f"case diagnostics {case} {storage}", flush=True)
     sim, Qg, tg = run_gpu(vb, w, Q0, 7, storage)
     N = int(np.prod(w["shape"]))
@@ -358,6 +363,89 @@ def test_diagnostics_match_oracle_on_the_same_populations(vb, case, storage):
     assert to[K + 1] > 0 and to[K + 3] > 0
     assert abs(tg[K + 3] - to[K + 3]) <= 1e-12 * to[K + 3]
     assert tg[K + 4] == to[K + 4] == 0
+
+
+# --- the 13-component 2D system (Sec. 3.1) ---------------------------------------
+
+def small_resistive_2d(shape=(70, 36), seed=7):
+    """A smooth 13-component state on a ragged 2D box with viscosity, current-dependent
+    resistivity and Powell's source from tr G / tau_M."""
+    nx, ny = shape
+    w = synth.workload_resistive_2d(n=nx, ny=ny)
+    Q0 = synth.resistive_2d_state((ny, nx), seed=seed, tau_M=w["tau_M"], tau_H=w["tau_H"], mu=w["mu"])
+    return w, Q0
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-10), ("f32", 1e-5)])
+def test_resistive_2d_parity_200_steps(vb, storage, tol):
+    """FP64: every field family within 1e-10 after 200 steps; FP32: within 1e-5, or,
+    for the small transported T and G, within 2x what the oracle evaluated in FP32
+    reaches (the rule of the 3D resistive system)."""
+    w, Q0 = small_resistive_2d()
+    print(f"case resistive_2d {storage}", flush=True)
+    _, Qg, tg = run_gpu(vb, w, Q0, 200, storage)
+    Qo, to = run_oracle(w, Q0, 200)
+    err = rel_l2(Qg, Qo, 13)
+    assert tg[13 + 4] == 0
+    if storage == "f64":
+        assert max(err.values()) <= tol, err
+        assert np.allclose(tg[:13], to[:13], rtol=1e-11, atol=1e-11)
+        return
+    yard = rel_l2(oracle.run_fp32(oracle_params(w), Q0, 200), Qo, 13)
+    for name, e in err.items():
+        assert e <= max(tol, 2.0 * yard[name]), (name, e, yard[name])
+    assert max(err[k] for k in ("rho", "m", "E", "B")) <= tol, err
+
+
+def test_brio_wu_fp64_parity(vb):
+    """The paper's Brio-Wu shock tube (Sec. 3.1) on the 13-component system, 256 x 4
+    cells to t = 0.1 (512 steps): FP64 within 1e-10 of the oracle, and physical."""
+    n = 256
+    w = synth.workload_brio_wu_2d(n=n, ny=4)
+    Q0 = synth.brio_wu_2d(n, 4)
+    _, Qg, tg = run_gpu(vb, w, Q0, w["steps"], "f64")
+    Qo, to = run_oracle(w, Q0, w["steps"])
+    err = rel_l2(Qg, Qo, 13)
+    assert max(err[k] for k in ("rho", "m", "E", "B")) <= 1e-10, err
+    assert tg[13 + 4] == 0 and to[13 + 4] == 0
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+def test_resistive_2d_block_sizes_bitwise_equal(vb, storage):
+    """Every tiling of the rows (64, 128, 256 threads, the lane exchange with 4, 2, 1
+    workgroups per 256-cell row) gives bitwise the same populations."""
+    w, Q0 = small_resistive_2d(shape=(256, 12))
+    out = []
+    for bx in (64, 128, 256):
+        sim, _, _ = run_gpu(vb, w, Q0, 7, storage, block_x=bx)
+        out.append(sim.vlbm_get_populations()[0])
+    assert all(np.array_equal(out[0], o) for o in out[1:])
+
+
+@pytest.mark.parametrize("storage,ulp", [("f16", 2.0 ** -11), ("bf16", 2.0 ** -8)])
+@pytest.mark.parametrize("parity", [0, 1])
+def test_resistive_2d_low_precision_one_step(vb, storage, ulp, parity):
+    """FP16/BF16 storage of the 13-component system: one step from the GPU's own
+    pre-step populations against the oracle's collision, up to one rounding of the
+    stored deviation (plus FP32 arithmetic)."""
+    w, Q0 = small_resistive_2d(shape=(64, 20))
+    shape = w["shape"]
+    sim = vb.Vlbm(gpu_params(vb, w, storage))
+    sim.vlbm_init_fields(Q0)
+    sim.vlbm_step(3 + parity)
+    cells = np.arange(int(np.prod(shape)))
+    op = oracle_params(w)
+    want = oracle_one_step(oracle, op, sim.vlbm_gather_cells, cells, shape, 2)
+    sim.vlbm_step(1)
+    got = sim.vlbm_gather_cells(cells)
+    rest_Q, sigma = sim.vlbm_get_codec()
+    f_rest = oracle.equilibrium(op, rest_Q)
+    wts = np.array([1.0 / 3.0] + [1.0 / 6.0] * 4)
+    sc = sigma[:, None] * wts[None, :]
+    h_want = np.abs(want - f_rest[None]) / sc[None]
+    bound = sc[None] * (2.0 * ulp * h_want + 2.0 ** -24) + 4e-6 * (1.0 + np.abs(want))
+    err = np.abs(got - want)
+    assert np.all(err <= bound), float((err / bound).max())
 
 
 # --- FP16 / BF16 deviation storage: one step at a time vs the oracle ------------
