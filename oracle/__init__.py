@@ -118,6 +118,8 @@ def lib():
         L.vref_solid.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double]
         L.vref_porosity.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double]
         L.vref_porosity.restype = ctypes.c_double
+        L.vref_set_threads.argtypes = [ctypes.c_int]
+        L.vref_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -333,6 +335,11 @@ def flux_source(p, Qcell, J=None):
 
 def num_threads():
     return lib().vref_num_threads()
+
+
+def set_threads(n):
+    """Number of OpenMP threads of the oracle's loops from now on."""
+    lib().vref_set_threads(int(n))
 
 
 def _as_f32(t):

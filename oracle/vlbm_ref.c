@@ -24,6 +24,14 @@ int vref_num_threads(void) {
 #endif
 }
 
+void vref_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 int vref_nvars(const vref_params* p) {
   return p->model == 1 ? 26 : (p->model == 2 ? 5 : (p->model == 3 ? 9 : (p->model == 4 ? 13 : 8)));
 }
@@ -137,7 +145,7 @@ static int resistive2d_flux(const vref_params* p, const double* Q, const double*
   const double uu = u[0] * u[0] + u[1] * u[1], BB = B[0] * B[0] + B[1] * B[1];
   const double uB = u[0] * B[0] + u[1] * B[1];
   const double pres = (p->gamma - 1.0) * (E - 0.5 * rho * uu - 0.5 * BB);
-  const double ptot = pres + 0.5 * BB;
+  const double ptot = 0.5 * BB + pres; /* total pressure */
   double dB[2][2], tv[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) dB[a][b] = G[2 * a + b] / p->tau_M;
@@ -166,7 +174,7 @@ static int resistive2d_flux(const vref_params* p, const double* Q, const double*
         Phi[3 * (6 + tidx[a][b]) + c] =
             T[tidx[a][b]] * u[c] - p->mu * ((c == a ? u[b] : 0.0) + (c == b ? u[a] : 0.0));
     for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b) Phi[3 * (9 + 2 * a + b) + c] = G[2 * a + b] * u[c] - (c == a ? B[b] : 0.0);
+      for (int b = 0; b < 2; ++b) Phi[3 * (9 + 2 * a + b) + c] = G[2 * a + b] * u[c] - (a == c ? B[b] : 0.0);
   }
   for (int q = 0; q < 3; ++q) S[6 + q] = -T[q] * p->dt / p->tau_H;
   for (int q = 0; q < 4; ++q) S[9 + q] = -G[q] * p->dt / p->tau_M;
@@ -175,8 +183,8 @@ static int resistive2d_flux(const vref_params* p, const double* Q, const double*
     divB_lat = (dB[0][0] + dB[1][1]) * (p->dt / p->s);
   } else {
     divB_lat = 0.0;
-    for (int a = 0; a < 2; ++a) divB_lat += J[3 * (4 + a) + a] / p->tau[4 + a];
-    divB_lat *= -1.0 / cs2(p);
+    for (int a = 0; a < 2; ++a) divB_lat -= J[3 * (4 + a) + a] / p->tau[4 + a];
+    divB_lat /= cs2(p);
   }
   *dlat = divB_lat;
   if (p->powell) {

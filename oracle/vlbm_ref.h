@@ -122,6 +122,8 @@ int vref_solid(const vref_params* p, int x, int y, int z, double t);
 double vref_porosity(const vref_params* p, int x, int y, int z, double t);
 
 int vref_num_threads(void);
+/* Set the number of OpenMP threads the oracle uses (n >= 1). */
+void vref_set_threads(int n);
 
 #ifdef __cplusplus
 }

@@ -973,7 +973,7 @@ MUTATIONS = {
     "r2d_stress_flux_half": ("p->mu * ((c == a ? u[b] : 0.0) + (c == b ? u[a] : 0.0))", "p->mu * ((c == a ? u[b] : 0.0))"),
     "r2d_viscous_momentum_sign": ("- B[a] * B[c] - tv[a][c];", "- B[a] * B[c] + tv[a][c];"),
     "r2d_ohmic_sign": ("- utv + eta * jxB[c];", "- utv - eta * jxB[c];"),
-    "r2d_G_flux_transposed": ("G[2 * a + b] * u[c] - (c == a ? B[b] : 0.0);", "G[2 * a + b] * u[c] - (c == b ? B[a] : 0.0);"),
+    "r2d_G_flux_transposed": ("G[2 * a + b] * u[c] - (a == c ? B[b] : 0.0);", "G[2 * a + b] * u[c] - (b == c ? B[a] : 0.0);"),
     "r2d_powell_trace": ("divB_lat = (dB[0][0] + dB[1][1]) * (p->dt / p->s);", "divB_lat = (dB[0][1] + dB[1][0]) * (p->dt / p->s);"),
     "r2d_resistive_induction_transposed": ("- eta * dB[c][a];", "- eta * dB[a][c];"),
     "r2d_current_sign": ("const double j = dB[0][1] - dB[1][0];", "const double j = dB[1][0] - dB[0][1];"),
