@@ -37,46 +37,53 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-MODEL_NAMES = {0: "ideal", 1: "resistive", 2: "euler", 3: "navier_cauchy"}
-MODEL_K = {0: 8, 1: 26, 2: 5, 3: 9}
+MODEL_NAMES = {0: "ideal", 1: "resistive", 2: "euler", 3: "navier_cauchy", 4: "resistive_2d"}
+MODEL_K = {0: 8, 1: 26, 2: 5, 3: 9, 4: 13}
 
 
 def params_for(vlbm, w, storage, stream):
     return vlbm.make_params(lattice="D3Q7" if w["dim"] == 3 else "D2Q5", shape=w["shape"],
                             model=MODEL_NAMES[w["model"]], storage=storage,
                             gamma=w["gamma"], flux_scale=w["s"], tau=w["tau"], powell=w["powell"],
-                            divb_mode=w["divb_mode"], dt=w["dt"], mu=w["mu"], eta0=w["eta0"],
+                            divb_mode=w["divb_mode"], dt=w["dt"], mu=w["mu"], eta0=w["eta0"], j_c=w.get("j_c", 0.0),
                             tau_M=w["tau_M"], tau_H=w["tau_H"], bc=w.get("bc"), inflow_Q=w.get("inflow_Q"),
                             body=w.get("body"), stream=stream)
 
 
-def time_sweep(vlbm, torch, w, Q_dev, storage, steps, warmup):
-    """Returns dict(wall_s, kernel_ms, ncell, bytes_per_cell)."""
+def time_sweep(vlbm, torch, w, Q_dev, storage, steps, warmup, segments=10):
+    """Returns dict(wall_s, kernel_ms, kernel_ms_std, ncell, bytes_per_cell, finite):
+    the timed steps run as `segments` equal segments bracketed by HIP events on the
+    library's stream (kernel_ms: mean per step; kernel_ms_std: spread of the segment
+    means), the wall clock around all of them."""
     stream = torch.cuda.current_stream()
     sim = vlbm.Vlbm(params_for(vlbm, w, storage, stream.cuda_stream))
     sim.vlbm_init_fields(Q_dev)
     sim.vlbm_step(warmup)
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    segments = max(1, min(segments, steps))
+    bounds = [round(steps * j / segments) for j in range(segments + 1)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(segments + 1)]
     t0 = time.perf_counter()
-    e0.record(stream)
-    sim.vlbm_step(steps)
-    e1.record(stream)
+    ev[0].record(stream)
+    for j in range(segments):
+        sim.vlbm_step(bounds[j + 1] - bounds[j])
+        ev[j + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kernel_ms = e0.elapsed_time(e1) / steps
+    seg_ms = [ev[j].elapsed_time(ev[j + 1]) / (bounds[j + 1] - bounds[j]) for j in range(segments)]
+    kernel_ms = ev[0].elapsed_time(ev[-1]) / steps
     _, tot = sim.vlbm_moments(with_field=False, raise_nonfinite=False)
     ncell = int(np.prod(w["shape"]))
     K = MODEL_K[w["model"]]
     Qd = 2 * w["dim"] + 1
     esize = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[storage]
     sim.vlbm_destroy()
-    return dict(wall_s=wall, kernel_ms=kernel_ms, ncell=ncell, bytes_per_cell=2 * K * Qd * esize,
-                finite=bool(np.all(np.isfinite(tot)) and tot[K + 4] == 0))
+    return dict(wall_s=wall, kernel_ms=kernel_ms, kernel_ms_std=float(np.std(seg_ms)), ncell=ncell,
+                bytes_per_cell=2 * K * Qd * esize, finite=bool(np.all(np.isfinite(tot)) and tot[K + 4] == 0))
 
 
 def copy_bandwidth(vlbm, torch, nbytes=4 << 30, reps=10):
+    """GB/s (read + write) of the library's streaming copy kernel on nbytes."""
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
     stream = torch.cuda.current_stream()
@@ -95,11 +102,69 @@ def copy_bandwidth(vlbm, torch, nbytes=4 << 30, reps=10):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(target_s=15.0):
-    """The FP64 oracle (as it stands) on a bounded sample of the same workload: the
-    resistive D3Q7 x 26 recipe on a 48^3 lattice."""
+def copy_ceiling(vlbm, torch, reps=10):
+    """The practical HBM ceiling from several copies: the library's streaming copy
+    kernel (16 bytes per lane) at 1, 4 and 16 GiB, and the runtime's device-to-device
+    copy (torch copy_, a hipMemcpyAsync) at 4 and 16 GiB; GB/s counting read + write."""
+    out = {}
+    for gib in (1, 4, 16):
+        out[f"library_copy_kernel_{gib}GiB"] = round(copy_bandwidth(vlbm, torch, gib << 30, reps), 1)
+    stream = torch.cuda.current_stream()
+    for gib in (4, 16):
+        src = torch.empty((gib << 30) // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            dst.copy_(src)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[f"device_to_device_memcpy_{gib}GiB"] = round(2.0 * (gib << 30) / (ms * 1e-3) / 1e9, 1)
+        del src, dst
+        torch.cuda.empty_cache()
+    out["max"] = max(out.values())
+    return out
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _oracle_rate(oracle, op, Q0, ncell, target_s, max_steps=None):
+    """MLUPS of the oracle on one workload: one step to size the run, then as many
+    steps as fit in target_s (at least 2)."""
+    f = oracle.init(op, Q0)
+    t0 = time.perf_counter()
+    oracle.run(op, f, 1)
+    per = time.perf_counter() - t0
+    steps = max(2, int(target_s / max(per, 1e-6)))
+    if max_steps:
+        steps = min(steps, max_steps)
+    t0 = time.perf_counter()
+    oracle.run(op, f, steps)
+    el = time.perf_counter() - t0
+    return dict(mlups=round(ncell * steps / el / 1e6, 4), steps=steps, seconds=round(el, 2))
+
+
+def cpu_baseline(target_s=10.0):
+    """The FP64 oracle (as it stands, OpenMP) timed on the host: the resistive D3Q7 x 26
+    recipe on a 48^3 lattice (a bounded sample of the benchmark's workload) on all the
+    threads the oracle runs with and on one; the 2D ideal-MHD workload (64^2, D2Q5 x 8,
+    200 steps) in full; a 128^3 slice of the slab workload (D3Q7 x 8)."""
     import oracle
     import synth
+    threads = oracle.num_threads()
     n = 48
     # the same lattice parameters as the 256^3 workload (dt / tau_M = 0.49)
     w = synth.workload_resistive_3d(n=n, dt_over_tau_M=0.49)
@@ -107,18 +172,29 @@ def cpu_baseline(target_s=15.0):
     op = oracle.make_params(dim=3, shape=w["shape"], model=1, gamma=w["gamma"], s=w["s"], tau=w["tau"],
                             powell=w["powell"], divb_mode=w["divb_mode"], dt=w["dt"], mu=w["mu"],
                             eta0=w["eta0"], tau_M=w["tau_M"], tau_H=w["tau_H"])
-    f = oracle.init(op, Q0)
-    t0 = time.perf_counter()
-    oracle.run(op, f, 2)
-    per = (time.perf_counter() - t0) / 2
-    steps = max(2, int(target_s / max(per, 1e-6)))
-    t0 = time.perf_counter()
-    oracle.run(op, f, steps)
-    el = time.perf_counter() - t0
-    return dict(value=round(n ** 3 * steps / el / 1e6, 4), unit="MLUPS", cores=oracle.num_threads(),
-                kind="oracle",
-                sample=f"FP64 oracle, resistive MHD D3Q7 x 26 variables, {n}^3 lattice (same recipe "
-                       f"and lattice parameters scaled to {n}^3), {steps} steps, {el:.1f} s")
+    res_all = _oracle_rate(oracle, op, Q0, n ** 3, target_s)
+    w0 = synth.workload_fourier_2d()
+    Q2 = synth.fourier_2d(64, seed=0)
+    op2 = oracle.make_params(dim=2, shape=(64, 64, 1), tau=w0["tau"], s=w0["s"])
+    ws = synth.workload_slab_3d()
+    Qs, _ = synth.planar_discontinuity_3d(n=128, seed=2)
+    ops = oracle.make_params(dim=3, shape=(128, 128, 128), tau=ws["tau"], s=ws["s"])
+    samples = {}
+    try:
+        for label, nt in (("all_threads", threads), ("one_thread", 1)):
+            oracle.set_threads(nt)
+            res = res_all if nt == threads else _oracle_rate(oracle, op, Q0, n ** 3, target_s / 2)
+            c0 = _oracle_rate(oracle, op2, Q2, 64 * 64, 1e9, max_steps=200)  # config 0 in full: 200 steps
+            sl = _oracle_rate(oracle, ops, Qs, 128 ** 3, 1e9, max_steps=10 if nt > 1 else 2)
+            samples[label] = {"threads": nt, "resistive_48_d3q7x26": res, "fourier_64_d2q5x8_200_steps": c0,
+                              "slab_128_d3q7x8": sl}
+    finally:
+        oracle.set_threads(threads)
+    return dict(value=res_all["mlups"], unit="MLUPS", cores=threads, kind="oracle",
+                sample=f"FP64 oracle, resistive MHD D3Q7 x 26 variables, {n}^3 lattice (same recipe and lattice "
+                       f"parameters scaled to {n}^3), {res_all['steps']} steps, {res_all['seconds']:.1f} s, "
+                       f"{threads} threads",
+                cpu_model=_cpu_model(), host_cpus=len(os.sched_getaffinity(0)), samples=samples)
 
 
 def traffic_for(workload_key, storage):
@@ -208,6 +284,80 @@ def run_body(vlbm, torch, synth, form_steps):
     return body_forms
 
 
+# The paper's own figures for its 13-component 2D kernel (Sec. 4 table), context only:
+# another GPU, kernel and code generator.
+PAPER_2D_KERNEL = {"mlups": 1077, "bytes_per_cell": 624, "frac_of_measured_bandwidth": 0.989,
+                   "hardware": "NVIDIA RTX A5000, 680 GB/s measured (BabelStream)", "precision": "FP32 (inferred)"}
+
+
+def run_resistive_2d(vlbm, torch, synth, form_steps):
+    """The paper's 13-component 2D system (its Brio-Wu test, Sec. 3.1, and the 2D kernel
+    of its Sec. 4 table) on a 4096^2 periodic Brio-Wu slab, FP32 / FP16 / BF16 storage;
+    bytes per cell update 13 x 5 populations read and written."""
+    out = {}
+    n = 4096
+    w = synth.workload_brio_wu_2d(n=n)
+    log("generating the 4096^2 Brio-Wu state")
+    Q = torch.from_numpy(synth.brio_wu_2d(n, n, dtype=np.float32)).cuda()
+    for st in ("f32", "f16", "bf16"):
+        rr = time_sweep(vlbm, torch, w, Q, st, form_steps, 5)
+        m = rr["ncell"] * form_steps / rr["wall_s"] / 1e6
+        gb = rr["bytes_per_cell"] * rr["ncell"] / (rr["kernel_ms"] * 1e-3) / 1e9
+        out[st] = dict(mlups=round(m, 1), kernel_ms=round(rr["kernel_ms"], 4),
+                       kernel_ms_std=round(rr["kernel_ms_std"], 4), bytes_per_cell=rr["bytes_per_cell"],
+                       achieved_GBps=round(gb, 1), frac_of_peak=round(gb / HBM_PEAK_GBPS, 4), finite=rr["finite"])
+        log(f"13-component 2D 4096^2 {st}: {m:.1f} MLUPS, {gb:.0f} GB/s")
+    for st in ("f16", "bf16"):
+        out[st]["speedup_vs_f32"] = round(out[st]["mlups"] / out["f32"]["mlups"], 3)
+    out["paper_2d_kernel_context"] = PAPER_2D_KERNEL
+    del Q
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_learned(synth):
+    """The learned coarse correction measured in this run (2D, fine 1024^2 -> coarse
+    256^2, r = 4, Fourier modes k <= 16): teacher-forced pairs from 8 training seeds,
+    1500 Adam iterations of the 4-layer 3x3 network, then the corrected and the plain
+    coarse runs on 2 held-out seeds over 1000 coarse steps, scored against the restricted
+    FP64 fine run, and the wall time of the corrected coarse run against the plain FP32
+    fine run over the same physical time."""
+    import torch
+    from paper_2606_00641_amd import learned as Lr
+    from paper_2606_00641_amd import nn as N
+    n_fine, r, kmax = 1024, 4, 16
+    seeds, pairs, eval_seeds, steps, iters = list(range(100, 108)), 250, [900, 901], 1000, 1500
+    w = synth.workload_fourier_2d()
+    t0 = time.perf_counter()
+    X, Y = Lr.generate_pairs(seeds, n_fine, r, pairs, w, synth.fourier_2d, kmax=kmax)
+    t_pairs = time.perf_counter() - t0
+    in_mean, in_std, out_mean, out_std, y_l2, drift = Lr.normalisation(X, Y)
+    net = N.Net(8, 32, 4, stream=torch.cuda.current_stream().cuda_stream)
+    net.vlbm_nn_set_weights(Lr.init_weights(seed=0))
+    net.vlbm_nn_set_norm(in_mean, in_std, out_mean, out_std)
+    losses, t_train = Lr.train(net, X, Y, iters, 1e-3, seed=0)
+    del X, Y
+    torch.cuda.empty_cache()
+    b_abs = 5.0 * drift
+    hist, nfb = Lr.evaluate(net, eval_seeds, n_fine, r, steps, w, synth.fourier_2d,
+                            5.0 * y_l2 * np.sqrt(len(eval_seeds)), 0.1, b_abs, kmax=kmax, checkpoints=2,
+                            fine_storage="f64")
+    t_fine, t_learned, nfb_t = Lr.time_runs(net, n_fine, r, steps, w, synth.fourier_2d, 5.0 * y_l2, 0.1, b_abs,
+                                            kmax=kmax)
+    net.vlbm_nn_destroy()
+    last = hist[-1]
+    log(f"learned 2D: {t_fine / t_learned:.2f}x the FP32 fine run; errors vs FP64 fine: plain {last['plain']}, "
+        f"learned {last['learned']}")
+    return {"workload": "2D ideal MHD D2Q5 x 8, fine 1024^2 -> coarse 256^2 (r = 4), Fourier modes k <= 16, "
+                        "FP32 coarse runs", "training": f"{pairs * len(seeds)} teacher-forced pairs from seeds "
+                        f"{seeds[0]}-{seeds[-1]}, {iters} Adam iterations", "eval_seeds": eval_seeds,
+            "coarse_steps": steps, "rel_l2_vs_restricted_fp64_fine": {"plain_coarse": last["plain"],
+                                                                      "learned_coarse": last["learned"]},
+            "fallbacks": nfb, "wall_fine_fp32_s": round(t_fine, 4), "wall_learned_coarse_s": round(t_learned, 4),
+            "speedup_vs_fine_fp32": round(t_fine / t_learned, 3), "time_pairs_s": round(t_pairs, 2),
+            "time_train_s": round(t_train, 2)}
+
+
 def run_network():
     """The learned correction's networks (4 layers, 8-32-32-32-8, BF16 MFMA with FP32
     accumulation): 3x3 on its coarse 2D training batch (40 lattices of 256^2) and
@@ -260,7 +410,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the slab and body forms and the network timing")
     ap.add_argument("--form-steps", type=int, default=50)
-    ap.add_argument("--only", choices=("slab", "body", "models", "network"), default=None,
+    ap.add_argument("--only", choices=("slab", "body", "models", "resistive_2d", "learned", "copy", "network"),
+                    default=None,
                     help="run one secondary part alone and print its result (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -278,6 +429,9 @@ def main():
         part = {"slab": lambda: run_slab(vlbm, torch, synth, args.form_steps),
                 "body": lambda: run_body(vlbm, torch, synth, args.form_steps),
                 "models": lambda: run_models(vlbm, torch, synth, args.form_steps),
+                "resistive_2d": lambda: run_resistive_2d(vlbm, torch, synth, args.form_steps),
+                "learned": lambda: run_learned(synth),
+                "copy": lambda: copy_ceiling(vlbm, torch),
                 "network": run_network}[args.only]()
         print(json.dumps({args.only: part}), flush=True)
         return
@@ -296,11 +450,16 @@ def main():
 
     copy_gbps = copy_bandwidth(vlbm, torch)
     log(f"copy kernel: {copy_gbps:.0f} GB/s")
+    copies = copy_ceiling(vlbm, torch) if not args.no_forms else None
+    if copies:
+        log(f"copy ceiling: {copies}")
 
     forms = run_slab(vlbm, torch, synth, args.form_steps) if not args.no_forms else {}
     body_forms = run_body(vlbm, torch, synth, args.form_steps) if not args.no_forms else {}
     models = run_models(vlbm, torch, synth, args.form_steps) if not args.no_forms else {}
+    r2d = run_resistive_2d(vlbm, torch, synth, args.form_steps) if not args.no_forms else {}
     network = run_network() if not args.no_forms else None
+    learned_run = run_learned(synth) if not args.no_forms else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -336,14 +495,18 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": traffic,
             "kernel_ms": round(r["kernel_ms"], 4),
+            "kernel_ms_std": round(r["kernel_ms_std"], 4),
             "measured_copy_GBps": round(copy_gbps, 1),
             "frac_of_copy": round(achieved / copy_gbps, 4),
+            "copy_ceiling_GBps": copies,
         },
         "cpu_baseline": cpu,
         "forms_slab_512": forms or None,
         "forms_body_768x384x384": body_forms or None,
         "forms_other_models_256": models or None,
+        "forms_13_component_2d_4096": r2d or None,
         "learned_network": network,
+        "learned_coarse_2d_measured": learned_run,
         "recorded_studies": recorded_studies(),
         "finite": r["finite"],
     }

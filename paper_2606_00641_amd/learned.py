@@ -182,13 +182,14 @@ def field_errors(Q, R):
 
 
 def evaluate(net, seeds, n_fine, r, coarse_steps, workload, make_state, bound_corr, bound_divb_rel, bound_divb_abs,
-             kmax=16, checkpoints=5, storage="f32", log=None, project=True):
+             kmax=16, checkpoints=5, storage="f32", log=None, project=True, fine_storage=None):
     """Coarse plain VLBM vs the corrected coarse run, both scored against the restricted
-    fine run."""
+    fine run (in `fine_storage`, default the coarse runs' storage; "f64" scores both
+    against the FP64 fine reference)."""
     torch = _torch()
     s = torch.cuda.current_stream().cuda_stream
     B, nc = len(seeds), n_fine // r
-    fine = make_context((n_fine, n_fine), B, storage, workload, s)
+    fine = make_context((n_fine, n_fine), B, fine_storage or storage, workload, s)
     plain = make_context((nc, nc), B, storage, workload, s)
     learned = make_context((nc, nc), B, storage, workload, s)
     fine.vlbm_init_fields(torch.from_numpy(initial_batch(seeds, n_fine, kmax, make_state)).cuda())
