@@ -89,6 +89,8 @@ class Params(ctypes.Structure):
         ("lame_lambda", ctypes.c_double),
         ("lame_mu", ctypes.c_double),
         ("rho0", ctypes.c_double),
+        ("mrt_tau_e", ctypes.c_double),
+        ("mrt_tau_d", ctypes.c_double),
     ]
 
 
@@ -170,7 +172,7 @@ def _ptr(a):
 def make_params(dim=2, shape=(64, 64, 1), model=0, gamma=5.0 / 3.0, s=0.2, w0=None,
                 tau=0.6, powell=1, divb_mode=0, dt=0.0, mu=0.0, eta0=0.0, j_c=0.0,
                 tau_M=1.0, tau_H=1.0, collision=0, trt_magic=0.25, lame_lambda=1.0, lame_mu=1.0,
-                rho0=1.0) -> Params:
+                rho0=1.0, mrt_tau_e=1.0, mrt_tau_d=1.0) -> Params:
     p = Params()
     p.dim = dim
     p.nx, p.ny, p.nz = shape
@@ -191,6 +193,7 @@ def make_params(dim=2, shape=(64, 64, 1), model=0, gamma=5.0 / 3.0, s=0.2, w0=No
     p.collision = int(collision)
     p.trt_magic = float(trt_magic)
     p.lame_lambda, p.lame_mu, p.rho0 = float(lame_lambda), float(lame_mu), float(rho0)
+    p.mrt_tau_e, p.mrt_tau_d = float(mrt_tau_e), float(mrt_tau_d)
     return p
 
 

@@ -338,6 +338,48 @@ void vref_equilibrium(const vref_params* p, const double* Q, double* feq) {
  * f*_{k,i} = f_{k,i} - (f_{k,i} - f^eq_{k,i}) / tau_k + w_i S~_k. */
 static void homogenize(const vref_params* p, const int cell[3], double t, double* Q);
 
+/* Moment matrix of the MRT collision (rows: 1, e_a, |e|^2, deviatoric second moments)
+ * for the lattice, and its inverse by Gauss-Jordan elimination with partial pivoting. */
+static void mrt_matrices(const vref_params* p, double Mm[7][7], double Mi[7][7]) {
+  const int NQ = vref_ndirs(p), d = p->dim;
+  for (int j = 0; j < 7; ++j)
+    for (int i = 0; i < 7; ++i) Mm[j][i] = 0.0;
+  for (int i = 0; i < NQ; ++i) {
+    double e2[3] = {0.0, 0.0, 0.0}, ee = 0.0;
+    for (int a = 0; a < d; ++a) {
+      e2[a] = (double)(edir(i, a) * edir(i, a));
+      ee += e2[a];
+      Mm[1 + a][i] = edir(i, a);
+    }
+    Mm[0][i] = 1.0;
+    Mm[1 + d][i] = ee;
+    Mm[2 + d][i] = e2[0] - e2[1];
+    if (d == 3) Mm[3 + d][i] = e2[0] + e2[1] - 2.0 * e2[2];
+  }
+  double A[7][14];
+  for (int r = 0; r < NQ; ++r)
+    for (int c = 0; c < 2 * NQ; ++c) A[r][c] = c < NQ ? Mm[r][c] : (c - NQ == r ? 1.0 : 0.0);
+  for (int c = 0; c < NQ; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < NQ; ++r)
+      if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+    for (int j = 0; j < 2 * NQ; ++j) {
+      const double t = A[c][j];
+      A[c][j] = A[piv][j];
+      A[piv][j] = t;
+    }
+    const double inv = 1.0 / A[c][c];
+    for (int j = 0; j < 2 * NQ; ++j) A[c][j] *= inv;
+    for (int r = 0; r < NQ; ++r) {
+      if (r == c) continue;
+      const double fac = A[r][c];
+      for (int j = 0; j < 2 * NQ; ++j) A[r][j] -= fac * A[c][j];
+    }
+  }
+  for (int r = 0; r < NQ; ++r)
+    for (int c = 0; c < NQ; ++c) Mi[r][c] = A[r][NQ + c];
+}
+
 /* cell == NULL: plain collision; else the cell's coordinates, and the target state
  * of the collision is homogenized with the body (Sec. 2.4) at time t. */
 static int collide_cell(const vref_params* p, const double* f, double* fstar, double* dlat,
@@ -379,6 +421,34 @@ static int collide_cell(const vref_params* p, const double* f, double* fstar, do
         const double ep = 0.5 * (feq[k * NQ + i] + feq[k * NQ + ib]);
         const double em = 0.5 * (feq[k * NQ + i] - feq[k * NQ + ib]);
         fstar[k * NQ + i] = f[k * NQ + i] - om_s * (fp - ep) - om_a * (fm - em) + weight(p, i) * S[k];
+      }
+    }
+  } else if (p->collision == 3) {
+    /* Sec. 2.2 names MRT among the admissible collisions.  READING: the moments of
+     * each variable's set are m = M f with the rows 1 (zeroth), e_a (first, one per
+     * axis), |e|^2 (trace of the second moments) and the deviatoric second moments
+     * e_x^2 - e_y^2 (and e_x^2 + e_y^2 - 2 e_z^2 in 3D); they relax toward
+     * m^eq = M f^eq, the first moments at 1/tau_k (transport, as in BGK), the zeroth
+     * moment and the trace at 1/mrt_tau_e, the deviatoric ones at 1/mrt_tau_d:
+     * f* = f - M^-1 S M (f - f^eq) + w_i S~_k. */
+    double Mm[7][7], Mi[7][7], rate[7];
+    mrt_matrices(p, Mm, Mi);
+    for (int j = 0; j < NQ; ++j) rate[j] = 0.0;
+    for (int k = 0; k < K; ++k) {
+      rate[0] = 1.0 / p->mrt_tau_e;
+      for (int a = 0; a < d; ++a) rate[1 + a] = 1.0 / p->tau[k];
+      rate[1 + d] = 1.0 / p->mrt_tau_e;
+      for (int j = 2 + d; j < NQ; ++j) rate[j] = 1.0 / p->mrt_tau_d;
+      double dm[7];
+      for (int j = 0; j < NQ; ++j) {
+        dm[j] = 0.0;
+        for (int i = 0; i < NQ; ++i) dm[j] += Mm[j][i] * (f[k * NQ + i] - feq[k * NQ + i]);
+        dm[j] *= rate[j];
+      }
+      for (int i = 0; i < NQ; ++i) {
+        double df = 0.0;
+        for (int j = 0; j < NQ; ++j) df += Mi[i][j] * dm[j];
+        fstar[k * NQ + i] = f[k * NQ + i] - df + weight(p, i) * S[k];
       }
     }
   } else {

@@ -58,12 +58,15 @@ typedef struct {
   double body_a[4], body_d[4][3], body_b[4], body_e[4][3];
   double body_m[3];
   /* collision (Sec. 2.2 admits several): 0 BGK, 1 TRT with magic parameter
-   * trt_magic, 2 regularized BGK */
+   * trt_magic, 2 regularized BGK, 3 MRT (first moments at 1/tau_k, the zeroth moment
+   * and the trace of the second moments at 1/mrt_tau_e, their deviatoric part at
+   * 1/mrt_tau_d) */
   int32_t collision;
   int32_t reserved2;
   double trt_magic;
   /* model 3: Lame constants and density of the elastic medium */
   double lame_lambda, lame_mu, rho0;
+  double mrt_tau_e, mrt_tau_d;
 } vref_params;
 
 /* number of variables K and of directions Q */

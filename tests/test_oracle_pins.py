@@ -101,7 +101,7 @@ def chk_flux_textbook():
     return err
 
 
-def chk_pulse_fourier(nsteps=40, collision=0, magic=0.25):
+def chk_pulse_fourier(nsteps=40, collision=0, magic=0.25, tau_e=0.8, tau_d=1.3):
     """Density pulse on a uniform (u0, p0, B0) background.  The rho set then obeys
     the linear scalar scheme f(x + e_i, t+1) = M0 f, solved exactly per Fourier mode,
     with M0 built by hand from the collision's definition (W_i = w_i (1 + s e_i.u0 /
@@ -110,7 +110,13 @@ def chk_pulse_fourier(nsteps=40, collision=0, magic=0.25):
     TRT  M0 = I - w+ P+ (I - W 1^T) - w- P- (I - W 1^T), P+/P- the symmetric and
          antisymmetric halves over opposite directions, w- = 1/tau,
          w+ = 1/(1/2 + Lambda/(tau - 1/2));
-    RLB  M0 = W 1^T + (1 - w) R (I - W 1^T), R_ij = w_i e_i.e_j / c_s^2."""
+    RLB  M0 = W 1^T + (1 - w) R (I - W 1^T), R_ij = w_i e_i.e_j / c_s^2;
+    MRT  M0 = I - (w P- + w_e P_iso + w_d P_dev) (I - W 1^T), with the orthogonal
+         projectors onto the odd subspace (P-), onto the deviatoric even vector
+         (1_{+x} + 1_{-x} - 1_{+y} - 1_{-y}) (P_dev) and onto the rest of the even
+         subspace (P_iso = P+ - P_dev): the moment basis of the MRT definition splits
+         the populations into these mutually orthogonal subspaces, each relaxing at
+         its own rate."""
     nx, ny = 32, 16
     s, tau = 0.2, 0.6
     u0 = np.array([0.05, -0.03, 0.02])
@@ -120,7 +126,8 @@ def chk_pulse_fourier(nsteps=40, collision=0, magic=0.25):
                         + 0.3 * np.sin(2 * np.pi * 3 * y / ny + 0.4))
     Q = synth.conserved_from_primitive(rho, u0[:, None, None] * np.ones_like(rho), 0.6,
                                        B0[:, None, None] * np.ones_like(rho), G53)[:, None]
-    p = oracle.make_params(dim=2, shape=(nx, ny, 1), s=s, tau=tau, collision=collision, trt_magic=magic)
+    p = oracle.make_params(dim=2, shape=(nx, ny, 1), s=s, tau=tau, collision=collision, trt_magic=magic,
+                           mrt_tau_e=tau_e, mrt_tau_d=tau_d)
     f = oracle.init(p, Q)
     oracle.run(p, f, nsteps)
     Qn, _, _ = oracle.moments(p, f)
@@ -140,6 +147,14 @@ def chk_pulse_fourier(nsteps=40, collision=0, magic=0.25):
     elif collision == 2:
         Rg = w[:, None] * (e @ e.T) / cs2
         M0 = np.outer(W, np.ones(5)) + (1 - om) * Rg @ A
+    elif collision == 3:
+        opp = [0, 2, 1, 4, 3]
+        Pb = np.eye(5)[opp]
+        Pp, Pm = 0.5 * (np.eye(5) + Pb), 0.5 * (np.eye(5) - Pb)
+        v = np.array([0.0, 1.0, 1.0, -1.0, -1.0])
+        Pdev = np.outer(v, v) / (v @ v)
+        Piso = Pp - Pdev
+        M0 = np.eye(5) - (om * Pm + Piso / tau_e + Pdev / tau_d) @ A
     else:
         M0 = (1 - om) * np.eye(5) + om * np.outer(W, np.ones(5))
     kx = 2 * np.pi * np.fft.fftfreq(nx)
@@ -531,8 +546,8 @@ def test_pulse_exact_fourier_evolution():
     assert chk_pulse_fourier() < 1e-13
 
 
-@pytest.mark.parametrize("collision,magic", [(1, 0.25), (1, 1.0 / 12.0), (2, 0.25)])
-def test_pulse_exact_fourier_evolution_trt_rlb(collision, magic):
+@pytest.mark.parametrize("collision,magic", [(1, 0.25), (1, 1.0 / 12.0), (2, 0.25), (3, 0.25)])
+def test_pulse_exact_fourier_evolution_two_rate_and_mrt(collision, magic):
     assert chk_pulse_fourier(collision=collision, magic=magic) < 1e-13
 
 
@@ -547,13 +562,19 @@ def chk_collision_identities(nsteps=6):
                           (3, (10, 9, 8), synth.smooth_box_state((8, 9, 10), seed=2))):
         tau = 0.7
         runs = {}
-        for name, coll, magic in (("bgk", 0, 0.0), ("trt_bgk", 1, (tau - 0.5) ** 2), ("rlb", 2, 0.0),
-                                  ("trt_rlb", 1, 0.5 * (tau - 0.5))):
-            p = oracle.make_params(dim=dim, shape=shape, tau=tau, collision=coll, trt_magic=magic, s=0.1)
+        tau_p = 0.5 + 0.25 / (tau - 0.5)  # TRT's symmetric relaxation time at Lambda = 1/4
+        for name, coll, magic, te, td in (("bgk", 0, 0.0, 1.0, 1.0), ("trt_bgk", 1, (tau - 0.5) ** 2, 1.0, 1.0),
+                                          ("rlb", 2, 0.0, 1.0, 1.0), ("trt_rlb", 1, 0.5 * (tau - 0.5), 1.0, 1.0),
+                                          ("mrt_bgk", 3, 0.0, tau, tau), ("trt", 1, 0.25, 1.0, 1.0),
+                                          ("mrt_trt", 3, 0.0, tau_p, tau_p), ("mrt", 3, 0.0, 0.8, 1.3)):
+            p = oracle.make_params(dim=dim, shape=shape, tau=tau, collision=coll, trt_magic=magic, s=0.1,
+                                   mrt_tau_e=te, mrt_tau_d=td)
             f = oracle.init(p, Q)
             oracle.run(p, f, nsteps)
             runs[name] = f
-        err = max(err, np.abs(runs["bgk"] - runs["trt_bgk"]).max(), np.abs(runs["rlb"] - runs["trt_rlb"]).max())
+        err = max(err, np.abs(runs["bgk"] - runs["trt_bgk"]).max(), np.abs(runs["rlb"] - runs["trt_rlb"]).max(),
+                  np.abs(runs["bgk"] - runs["mrt_bgk"]).max(), np.abs(runs["trt"] - runs["mrt_trt"]).max())
+        assert np.abs(runs["mrt"] - runs["trt"]).max() > 1e-8  # distinct even rates: another scheme
         assert np.abs(runs["bgk"] - runs["rlb"]).max() > 1e-8  # the two are different schemes
     return err
 
@@ -962,6 +983,11 @@ MUTATIONS = {
     "powell_trG_from_H": ("for (int a = 0; a < d; ++a) tr += dB[a][a];", "for (int a = 0; a < d; ++a) tr += du[a][a];"),
     "trt_rates_swapped": ("- om_s * (fp - ep) - om_a * (fm - em)", "- om_a * (fp - ep) - om_s * (fm - em)"),
     "trt_magic_inverted": ("1.0 / (0.5 + p->trt_magic / (p->tau[k] - 0.5))", "1.0 / (0.5 + (p->tau[k] - 0.5) / p->trt_magic)"),
+    "mrt_deviatoric_row": ("Mm[2 + d][i] = e2[0] - e2[1];", "Mm[2 + d][i] = e2[0] + e2[1];"),
+    "mrt_rates_swapped": ("for (int j = 2 + d; j < NQ; ++j) rate[j] = 1.0 / p->mrt_tau_d;",
+                          "for (int j = 2 + d; j < NQ; ++j) rate[j] = 1.0 / p->mrt_tau_e;"),
+    "mrt_first_moment_rate": ("for (int a = 0; a < d; ++a) rate[1 + a] = 1.0 / p->tau[k];",
+                              "for (int a = 0; a < d; ++a) rate[1 + a] = 1.0 / p->mrt_tau_e;"),
     "rlb_projection_scale": ("const double fneq = weight(p, i) * eJ / c2;", "const double fneq = weight(p, i) * eJ;"),
     "rlb_relaxation": ("feq[k * NQ + i] + (1.0 - 1.0 / p->tau[k]) * fneq", "feq[k * NQ + i] + (1.0 / p->tau[k]) * fneq"),
     "euler_pressure_dropped": ("Phi[3 * (1 + a) + b] = Q[1 + a] * u[b] + (a == b ? pres : 0.0);",
@@ -1005,9 +1031,10 @@ def _fails(name):
         return chk_elastic_speeds()[0] > 1e-4 or chk_elastic_lateral_stress() > 1e-9
     if name.startswith("euler"):
         return chk_euler_vs_mhd(2)[0] > 1e-14 or chk_euler_sound()[0] > 2e-3
-    if name.startswith("trt") or name.startswith("rlb"):
+    if name.startswith("trt") or name.startswith("rlb") or name.startswith("mrt"):
         return (chk_pulse_fourier(collision=1, magic=1.0 / 12.0) > 1e-13
-                or chk_pulse_fourier(collision=2) > 1e-13 or chk_collision_identities() > 1e-14)
+                or chk_pulse_fourier(collision=2) > 1e-13 or not (chk_pulse_fourier(collision=3) < 1e-13)
+                or not (chk_collision_identities() < 1e-14))
     checks = [
         lambda: chk_equilibrium_moments() > 1e-14,
         lambda: chk_flux_textbook() > 1e-14,
