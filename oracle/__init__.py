@@ -91,6 +91,8 @@ class Params(ctypes.Structure):
         ("rho0", ctypes.c_double),
         ("mrt_tau_e", ctypes.c_double),
         ("mrt_tau_d", ctypes.c_double),
+        ("source", ctypes.c_int32),
+        ("reserved3", ctypes.c_int32),
     ]
 
 
@@ -115,6 +117,8 @@ def lib():
         L.vref_collide_at.argtypes = [P, ctypes.c_long, dp, ctypes.POINTER(ctypes.c_int32), ctypes.c_double, dp]
         L.vref_init.argtypes = [P, dp, dp]
         L.vref_run.argtypes = [P, dp, dp, ctypes.c_int]
+        L.vref_run_src.argtypes = [P, dp, dp, dp, ctypes.c_int]
+        L.vref_source_field.argtypes = [P, dp, dp]
         L.vref_moments.argtypes = [P, dp, dp, dp, dp]
         L.vref_run_bc.argtypes = [P, dp, dp, ctypes.c_int, ctypes.c_int]
         L.vref_solid.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double]
@@ -172,7 +176,7 @@ def _ptr(a):
 def make_params(dim=2, shape=(64, 64, 1), model=0, gamma=5.0 / 3.0, s=0.2, w0=None,
                 tau=0.6, powell=1, divb_mode=0, dt=0.0, mu=0.0, eta0=0.0, j_c=0.0,
                 tau_M=1.0, tau_H=1.0, collision=0, trt_magic=0.25, lame_lambda=1.0, lame_mu=1.0,
-                rho0=1.0, mrt_tau_e=1.0, mrt_tau_d=1.0) -> Params:
+                rho0=1.0, mrt_tau_e=1.0, mrt_tau_d=1.0, source=0) -> Params:
     p = Params()
     p.dim = dim
     p.nx, p.ny, p.nz = shape
@@ -194,6 +198,7 @@ def make_params(dim=2, shape=(64, 64, 1), model=0, gamma=5.0 / 3.0, s=0.2, w0=No
     p.trt_magic = float(trt_magic)
     p.lame_lambda, p.lame_mu, p.rho0 = float(lame_lambda), float(lame_mu), float(rho0)
     p.mrt_tau_e, p.mrt_tau_d = float(mrt_tau_e), float(mrt_tau_d)
+    p.source = {"direct": 0, "guo": 1, "chai": 2}[source] if isinstance(source, str) else int(source)
     return p
 
 
@@ -218,11 +223,22 @@ def init(p, Q):
     return f
 
 
-def run(p, f, nsteps):
-    """Advance populations f [K, Q, N] in place by nsteps; returns #unphysical cell-steps."""
+def run(p, f, nsteps, sprev=None):
+    """Advance populations f [K, Q, N] in place by nsteps; returns #unphysical cell-steps.
+    sprev [K, N]: the Chai source's previous-step source (required for p.source == 2,
+    updated in place; start it with source_field)."""
     assert f.dtype == np.float64 and f.flags["C_CONTIGUOUS"]
     work = np.empty_like(f)
-    return lib().vref_run(ctypes.byref(p), _ptr(f), _ptr(work), int(nsteps))
+    if p.source == 2:
+        assert sprev is not None and sprev.dtype == np.float64 and sprev.flags["C_CONTIGUOUS"]
+    return lib().vref_run_src(ctypes.byref(p), _ptr(f), _ptr(work), _ptr(sprev), int(nsteps))
+
+
+def source_field(p, f):
+    """The source S~ [K, N] of the state held by f (the Chai scheme's starting sprev)."""
+    out = np.empty((nvars(p), ncells(p)), np.float64)
+    lib().vref_source_field(ctypes.byref(p), _ptr(np.ascontiguousarray(f)), _ptr(out))
+    return out
 
 
 def set_boundaries(p, bc=None, inflow_Q=None, body=None, body_mode=1):

@@ -382,8 +382,32 @@ static void mrt_matrices(const vref_params* p, double Mm[7][7], double Mi[7][7])
 
 /* cell == NULL: plain collision; else the cell's coordinates, and the target state
  * of the collision is homogenized with the body (Sec. 2.4) at time t. */
+/* Relaxation rate of the zeroth moment of variable k under the collision in use. */
+static double zeroth_rate(const vref_params* p, int k) {
+  switch (p->collision) {
+    case 1: return 1.0 / (0.5 + p->trt_magic / (p->tau[k] - 0.5));
+    case 2: return 1.0;
+    case 3: return 1.0 / p->mrt_tau_e;
+    default: return 1.0 / p->tau[k];
+  }
+}
+
+/* Guo's state (Sec. 2.2 names the Guo source scheme; READING): Q = m + S~(Q)/2 with
+ * m = sum_i f, solved by two fixed-point iterations Q0 = m + S~(m)/2,
+ * Q = m + S~(Q0)/2 (second order in time for the source). */
+static void guo_state(const vref_params* p, const double* m, const double* J, double* Q) {
+  const int K = vref_nvars(p);
+  double Phi[VREF_KMAX * 3], S[VREF_KMAX], dl, Q0[VREF_KMAX];
+  vref_flux_source(p, m, J, Phi, S, &dl);
+  for (int k = 0; k < K; ++k) Q0[k] = m[k] + 0.5 * S[k];
+  vref_flux_source(p, Q0, J, Phi, S, &dl);
+  for (int k = 0; k < K; ++k) Q[k] = m[k] + 0.5 * S[k];
+}
+
+/* sprev (K values, Chai source only): the cell's source of the previous step, replaced
+ * by this step's. */
 static int collide_cell(const vref_params* p, const double* f, double* fstar, double* dlat,
-                        const int* cell, double t) {
+                        const int* cell, double t, double* sprev) {
   const int K = vref_nvars(p), NQ = vref_ndirs(p), d = p->dim;
   double Q[VREF_KMAX], J[VREF_KMAX * 3], Phi[VREF_KMAX * 3], S[VREF_KMAX];
   double feq[VREF_KMAX * 7];
@@ -395,10 +419,27 @@ static int collide_cell(const vref_params* p, const double* f, double* fstar, do
       for (int a = 0; a < d; ++a) J[3 * k + a] += edir(i, a) * f[k * NQ + i];
     }
   }
+  if (p->source == 1) {
+    double m[VREF_KMAX];
+    for (int k = 0; k < K; ++k) m[k] = Q[k];
+    guo_state(p, m, J, Q);
+  }
   if (cell) homogenize(p, cell, t, Q);
   double dl;
   const int bad = vref_flux_source(p, Q, J, Phi, S, &dl);
   equilibrium_from_flux(p, Q, Phi, feq);
+  /* the source as it enters the populations (w_i times this) */
+  for (int k = 0; k < K; ++k) {
+    if (p->source == 1) {
+      S[k] *= 1.0 - 0.5 * zeroth_rate(p, k);
+    } else if (p->source == 2) {
+      /* without a stored previous source (a lone collision) the previous one is taken
+       * equal to the current one, as at the start of a run */
+      const double now = S[k];
+      S[k] = now + 0.5 * (now - (sprev ? sprev[k] : now));
+      if (sprev) sprev[k] = now;
+    }
+  }
   if (p->collision == 0) {
     for (int k = 0; k < K; ++k)
       for (int i = 0; i < NQ; ++i) {
@@ -474,7 +515,7 @@ static int collide_cell(const vref_params* p, const double* f, double* fstar, do
 }
 
 int vref_collide(const vref_params* p, const double* f, double* fstar, double* dlat) {
-  return collide_cell(p, f, fstar, dlat, NULL, 0.0);
+  return collide_cell(p, f, fstar, dlat, NULL, 0.0, NULL);
 }
 
 /* vref_collide on n independent cells: f and fstar are [n][K][Q]. */
@@ -491,7 +532,7 @@ int vref_collide_at(const vref_params* p, long n, const double* f, const int* xy
   int nbad = 0;
 #pragma omp parallel for schedule(static) reduction(+ : nbad)
   for (long j = 0; j < n; ++j)
-    nbad += collide_cell(p, f + j * KQ, fstar + j * KQ, NULL, p->body == 2 ? xyz + 3 * j : NULL, t);
+    nbad += collide_cell(p, f + j * KQ, fstar + j * KQ, NULL, p->body == 2 ? xyz + 3 * j : NULL, t, NULL);
   return nbad;
 }
 
@@ -505,14 +546,23 @@ static long neighbour(const vref_params* p, int x, int y, int z, int i) {
   return (long)c[0] + (long)p->nx * ((long)c[1] + (long)p->ny * c[2]);
 }
 
+/* READING (initial populations, P7): f = f^eq(Q); with Guo's source the populations'
+ * sum is the state minus half its source, sum_i f = Q - S~(Q)/2, the inverse of Guo's
+ * half-source shift: f = f^eq(Q) - w_i S~(Q)/2. */
 int vref_init(const vref_params* p, const double* Q, double* f) {
   const int K = vref_nvars(p), NQ = vref_ndirs(p);
   const long N = ncells(p);
 #pragma omp parallel for schedule(static)
   for (long c = 0; c < N; ++c) {
-    double q[VREF_KMAX], feq[VREF_KMAX * 7];
+    double q[VREF_KMAX], feq[VREF_KMAX * 7], Phi[VREF_KMAX * 3], S[VREF_KMAX], J[VREF_KMAX * 3], dl;
     for (int k = 0; k < K; ++k) q[k] = Q[k * N + c];
     vref_equilibrium(p, q, feq);
+    if (p->source == 1) {
+      memset(J, 0, sizeof J);
+      vref_flux_source(p, q, J, Phi, S, &dl);
+      for (int k = 0; k < K; ++k)
+        for (int i = 0; i < NQ; ++i) feq[k * NQ + i] -= 0.5 * weight(p, i) * S[k];
+    }
     for (int k = 0; k < K; ++k)
       for (int i = 0; i < NQ; ++i) f[((long)k * NQ + i) * N + c] = feq[k * NQ + i];
   }
@@ -521,8 +571,13 @@ int vref_init(const vref_params* p, const double* Q, double* f) {
 
 /* Sec. 2.2 update: collide every cell, then push f*_{k,i}(x) to x + e_i (periodic). */
 int vref_run(const vref_params* p, double* f, double* work, int nsteps) {
+  return vref_run_src(p, f, work, NULL, nsteps);
+}
+
+int vref_run_src(const vref_params* p, double* f, double* work, double* sprev, int nsteps) {
   const int K = vref_nvars(p), NQ = vref_ndirs(p);
   const long N = ncells(p);
+  if (p->source == 2 && !sprev) return -1;
   int nbad = 0;
   for (int step = 0; step < nsteps; ++step) {
 #pragma omp parallel for collapse(2) schedule(static) reduction(+ : nbad)
@@ -533,7 +588,12 @@ int vref_run(const vref_params* p, double* f, double* work, int nsteps) {
           double fc[VREF_KMAX * 7], fs[VREF_KMAX * 7];
           for (int k = 0; k < K; ++k)
             for (int i = 0; i < NQ; ++i) fc[k * NQ + i] = f[((long)k * NQ + i) * N + c];
-          nbad += vref_collide(p, fc, fs, NULL);
+          double sp[VREF_KMAX];
+          if (sprev)
+            for (int k = 0; k < K; ++k) sp[k] = sprev[(long)k * N + c];
+          nbad += collide_cell(p, fc, fs, NULL, NULL, 0.0, sprev ? sp : NULL);
+          if (sprev)
+            for (int k = 0; k < K; ++k) sprev[(long)k * N + c] = sp[k];
           for (int i = 0; i < NQ; ++i) {
             const long t = neighbour(p, x, y, z, i);
             for (int k = 0; k < K; ++k) work[((long)k * NQ + i) * N + t] = fs[k * NQ + i];
@@ -542,6 +602,32 @@ int vref_run(const vref_params* p, double* f, double* work, int nsteps) {
     memcpy(f, work, sizeof(double) * (size_t)K * NQ * N);
   }
   return nbad;
+}
+
+int vref_source_field(const vref_params* p, const double* f, double* S_out) {
+  const int K = vref_nvars(p), NQ = vref_ndirs(p), d = p->dim;
+  const long N = ncells(p);
+#pragma omp parallel for schedule(static)
+  for (long c = 0; c < N; ++c) {
+    double q[VREF_KMAX], J[VREF_KMAX * 3], Phi[VREF_KMAX * 3], S[VREF_KMAX], dl;
+    for (int k = 0; k < K; ++k) {
+      q[k] = 0.0;
+      for (int a = 0; a < 3; ++a) J[3 * k + a] = 0.0;
+      for (int i = 0; i < NQ; ++i) {
+        const double v = f[((long)k * NQ + i) * N + c];
+        q[k] += v;
+        for (int a = 0; a < d; ++a) J[3 * k + a] += edir(i, a) * v;
+      }
+    }
+    if (p->source == 1) {
+      double m[VREF_KMAX];
+      for (int k = 0; k < K; ++k) m[k] = q[k];
+      guo_state(p, m, J, q);
+    }
+    vref_flux_source(p, q, J, Phi, S, &dl);
+    for (int k = 0; k < K; ++k) S_out[(long)k * N + c] = S[k];
+  }
+  return 0;
 }
 
 int vref_moments(const vref_params* p, const double* f, double* Q_out, double* dlat,
@@ -567,8 +653,13 @@ int vref_moments(const vref_params* p, const double* f, double* Q_out, double* d
         q[k] += v;
         for (int a = 0; a < d; ++a) J[3 * k + a] += edir(i, a) * v;
       }
-      Qall[(long)k * N + c] = q[k];
     }
+    if (p->source == 1) {
+      double m[VREF_KMAX];
+      for (int k = 0; k < K; ++k) m[k] = q[k];
+      guo_state(p, m, J, q);
+    }
+    for (int k = 0; k < K; ++k) Qall[(long)k * N + c] = q[k];
     nbad += vref_flux_source(p, q, J, Phi, S, &dl);
     dall[c] = dl;
   }
@@ -802,7 +893,7 @@ int vref_run_bc(const vref_params* p, double* f, double* work, int nsteps, int t
       double fc[VREF_KMAX * 7], fs[VREF_KMAX * 7], Q[VREF_KMAX];
       for (int k = 0; k < K; ++k)
         for (int i = 0; i < NQ; ++i) fc[k * NQ + i] = f[((long)k * NQ + i) * N + cell];
-      nbad += collide_cell(p, fc, fs, NULL, p->body == 2 ? cc : NULL, t);
+      nbad += collide_cell(p, fc, fs, NULL, p->body == 2 ? cc : NULL, t, NULL);
       cell_moments(p, f, N, cell, Q);
       for (int k = 0; k < K; ++k) work[((long)k * NQ + 0) * N + cell] = fs[k * NQ + 0];
       for (int i = 1; i < NQ; ++i) {

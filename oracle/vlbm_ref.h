@@ -67,6 +67,14 @@ typedef struct {
   /* model 3: Lame constants and density of the elastic medium */
   double lame_lambda, lame_mu, rho0;
   double mrt_tau_e, mrt_tau_d;
+  /* source operator (Sec. 2.2 names direct injection, Guo's and Chai's): 0 direct
+   * injection, w_i S~(Q), Q = sum_i f; 1 Guo -- the state is Q = sum_i f + S~(Q)/2
+   * (solved by two fixed-point iterations from sum_i f) and the source enters as
+   * (1 - omega_0/2) w_i S~(Q), omega_0 the relaxation rate of the zeroth moment;
+   * 2 Chai -- Q = sum_i f and the source enters as w_i (S~ + (S~ - S~_prev)/2), S~_prev
+   * the cell's source of the previous step (the backward difference of dt^2/2 d_t S) */
+  int32_t source;
+  int32_t reserved3;
 } vref_params;
 
 /* number of variables K and of directions Q */
@@ -98,8 +106,15 @@ int vref_collide_at(const vref_params* p, long n, const double* f, const int* xy
 /* f := f^eq(Q) everywhere. Q is [K][N], f is [K][Q][N]. */
 int vref_init(const vref_params* p, const double* Q, double* f);
 
-/* nsteps collide + push-stream steps (periodic). work has the size of f. */
+/* nsteps collide + push-stream steps (periodic). work has the size of f.  Not for
+ * the Chai source (source 2), which needs vref_run_src. */
 int vref_run(const vref_params* p, double* f, double* work, int nsteps);
+/* As vref_run, with the previous-step source sprev [K][N] of the Chai scheme (read
+ * and updated; may be NULL for the other source operators). */
+int vref_run_src(const vref_params* p, double* f, double* work, double* sprev, int nsteps);
+/* The source S~ [K][N] of the state in f (Guo: of Q = sum f + S~/2): the Chai scheme's
+ * sprev at the start of a run. */
+int vref_source_field(const vref_params* p, const double* f, double* S_out);
 
 /* Moments of f: Q_out [K][N] (may be NULL), dlat [N] (may be NULL), totals (may be
  * NULL): [0..K-1] sum_x Q_k, [K] sum d, [K+1] sum d^2, [K+2] max |d|,

@@ -850,6 +850,90 @@ def test_resistive_ohmic_energy_flux_sign():
 
 
 # ----------------------------------------------------------------------------
+# source operators (Sec. 2.2: direct injection, Guo's, Chai's)
+# ----------------------------------------------------------------------------
+
+def _decay_run(source, h, nsteps, g0=0.01, collision=0, tau=0.6):
+    """A uniform resistive state at rest with a uniform field B = 0.2 x and one
+    off-diagonal transported gradient G_xy = g0: nothing moves, and G_xy only relaxes,
+    d_t G = -G / tau_M, with dt / tau_M = h (Powell's source is zero: tr G = 0).
+    Returns the reported G_xy after each step."""
+    shape = (4, 3, 2)
+    Q = synth.uniform_state(shape[::-1], rho=1.0, p=0.6, B=(0.2, 0.0, 0.0), K=26)
+    Q[8 + 1] = g0
+    P = oracle.make_params(dim=3, shape=shape, model=1, s=0.2, tau=tau, dt=h, tau_M=1.0, tau_H=1.0, divb_mode=1,
+                           source=source, collision=collision, trt_magic=0.25)
+    f = oracle.init(P, Q)
+    sp = oracle.source_field(P, f) if source == 2 else None
+    out = []
+    for _ in range(nsteps):
+        oracle.run(P, f, 1, sprev=sp)
+        Qn, _, _ = oracle.moments(P, f)
+        out.append(Qn[9].mean())
+    return np.array(out)
+
+
+def chk_source_recurrences(h=0.3, n=12, g0=0.01):
+    """Each source operator on the uniform relaxing state reduces to a scalar recurrence
+    for the populations' sum m (every population stays w_i times it), derived here from
+    the operators' definitions; S~(q) = -h q, omega = 1/tau:
+    direct  m' = m - h m                                    (reported: m)
+    Guo     q0 = m (1 - h/2), q = m - h q0 / 2, m' = m - omega (m - q) - (1 - omega/2) h q,
+            m_0 = g0 (1 + h/2)                              (reported: q)
+    Chai    m' = m - h m - (h m - h m_prev) / 2, m_prev = m at the start (reported: m).
+    Returns the largest relative deviation of the oracle's G_xy from these."""
+    om = 1.0 / 0.6
+    err = 0.0
+    # direct
+    want = g0 * (1 - h) ** np.arange(1, n + 1)
+    err = max(err, np.abs(_decay_run(0, h, n, g0) / want - 1).max())
+    # Guo
+    m, got = g0 * (1 + h / 2), []
+    for _ in range(n):
+        q0 = m * (1 - h / 2)
+        q = m - h * q0 / 2
+        m = m - om * (m - q) - (1 - om / 2) * h * q
+        q0 = m * (1 - h / 2)
+        got.append(m - h * q0 / 2)
+    err = max(err, np.abs(_decay_run(1, h, n, g0) / np.array(got) - 1).max())
+    # Chai
+    m, mp, got = g0, g0, []
+    for _ in range(n):
+        m, mp = m - h * m - 0.5 * (h * m - h * mp), m
+        got.append(m)
+    err = max(err, np.abs(_decay_run(2, h, n, g0) / np.array(got) - 1).max())
+    return err
+
+
+def chk_source_orders(T=2.0):
+    """Error of the relaxing G_xy at time T against g0 exp(-T / tau_M), halving dt:
+    the error ratio is about 2 for direct injection (first order in time) and about 4
+    for the Guo and Chai operators (second order); BGK and TRT.  Returns
+    {(source, collision): ratio}."""
+    out = {}
+    for coll in (0, 1):
+        for src in (0, 1, 2):
+            errs = []
+            for n in (12, 24, 48):
+                h = T / n
+                errs.append(abs(_decay_run(src, h, n, collision=coll)[-1] / (0.01 * np.exp(-T)) - 1))
+            out[(src, coll)] = errs[1] / errs[2]
+    return out
+
+
+def test_source_operators_reduce_to_their_recurrences():
+    assert chk_source_recurrences() < 1e-13
+
+
+def test_source_operators_orders_in_time():
+    r = chk_source_orders()
+    for coll in (0, 1):
+        assert 1.8 < r[(0, coll)] < 2.2, r
+        assert 3.6 < r[(1, coll)] < 4.4, r
+        assert 3.6 < r[(2, coll)] < 4.4, r
+
+
+# ----------------------------------------------------------------------------
 # the 13-component 2D system (Sec. 3.1, Sec. 2.3)
 # ----------------------------------------------------------------------------
 
@@ -996,6 +1080,10 @@ MUTATIONS = {
     "elastic_stress_sign": ("for (int b = 0; b < 3; ++b) Phi[3 * b + a] = -Q[kSigIdx[b][a]];",
                             "for (int b = 0; b < 3; ++b) Phi[3 * b + a] = Q[kSigIdx[b][a]];"),
     "elastic_lambda_dropped": ("-((b == c ? lam * v[a] : 0.0) +", "-((b == c ? 0.0 * v[a] : 0.0) +"),
+    "guo_factor_dropped": ("S[k] *= 1.0 - 0.5 * zeroth_rate(p, k);", "S[k] *= 1.0;"),
+    "guo_full_shift": ("for (int k = 0; k < K; ++k) Q[k] = m[k] + 0.5 * S[k];", "for (int k = 0; k < K; ++k) Q[k] = m[k] + S[k];"),
+    "chai_difference_sign": ("S[k] = now + 0.5 * (now - (sprev ? sprev[k] : now));",
+                             "S[k] = now - 0.5 * (now - (sprev ? sprev[k] : now));"),
     "r2d_stress_flux_half": ("p->mu * ((c == a ? u[b] : 0.0) + (c == b ? u[a] : 0.0))", "p->mu * ((c == a ? u[b] : 0.0))"),
     "r2d_viscous_momentum_sign": ("- B[a] * B[c] - tv[a][c];", "- B[a] * B[c] + tv[a][c];"),
     "r2d_ohmic_sign": ("- utv + eta * jxB[c];", "- utv - eta * jxB[c];"),
@@ -1025,6 +1113,8 @@ def _fails(name):
         return dp_on > 3e-4
     if name == "divb_estimate_scale":
         return chk_divb_estimator_tau1() > 1e-12
+    if name.startswith("guo") or name.startswith("chai"):
+        return not (chk_source_recurrences() < 1e-13)
     if name.startswith("r2d_"):
         return not (chk_13_equals_3d_resistive()[0] < 1e-11) or not (chk_13_stress_relaxes() < 0.03)
     if name.startswith("elastic"):
