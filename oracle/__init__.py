@@ -405,8 +405,15 @@ def run_fp32(p, Q, nsteps):
     f = np.empty((K, NQ, N), np.float32)
     work = np.empty_like(f)
     L.vref_init(ctypes.byref(q), Q32.ctypes.data_as(fp), f.ctypes.data_as(fp))
-    L.vref_run(ctypes.byref(q), f.ctypes.data_as(fp), work.ctypes.data_as(fp), int(nsteps))
-    return f.astype(np.float64).sum(axis=1)
+    sp = None
+    if p.source == 2:
+        sp = np.empty((K, N), np.float32)
+        L.vref_source_field(ctypes.byref(q), f.ctypes.data_as(fp), sp.ctypes.data_as(fp))
+    L.vref_run_src(ctypes.byref(q), f.ctypes.data_as(fp), work.ctypes.data_as(fp),
+                   sp.ctypes.data_as(fp) if sp is not None else None, int(nsteps))
+    out = np.empty((K, N), np.float32)
+    L.vref_moments(ctypes.byref(q), f.ctypes.data_as(fp), out.ctypes.data_as(fp), None, None)
+    return out.astype(np.float64)
 
 
 def body_loads(p, f, t):

@@ -380,9 +380,8 @@ static void mrt_matrices(const vref_params* p, double Mm[7][7], double Mi[7][7])
     for (int c = 0; c < NQ; ++c) Mi[r][c] = A[r][NQ + c];
 }
 
-/* cell == NULL: plain collision; else the cell's coordinates, and the target state
- * of the collision is homogenized with the body (Sec. 2.4) at time t. */
-/* Relaxation rate of the zeroth moment of variable k under the collision in use. */
+/* Relaxation rate of the zeroth moment of variable k under the collision in use (TRT:
+ * the symmetric rate 1/tau+_k, tau+ fixed by the magic parameter). */
 static double zeroth_rate(const vref_params* p, int k) {
   switch (p->collision) {
     case 1: return 1.0 / (0.5 + p->trt_magic / (p->tau[k] - 0.5));
@@ -404,8 +403,9 @@ static void guo_state(const vref_params* p, const double* m, const double* J, do
   for (int k = 0; k < K; ++k) Q[k] = m[k] + 0.5 * S[k];
 }
 
-/* sprev (K values, Chai source only): the cell's source of the previous step, replaced
- * by this step's. */
+/* cell == NULL: plain collision; else the cell's coordinates, and the target state
+ * of the collision is homogenized with the body (Sec. 2.4) at time t.  sprev (K values,
+ * Chai source only): the cell's source of the previous step, replaced by this step's. */
 static int collide_cell(const vref_params* p, const double* f, double* fstar, double* dlat,
                         const int* cell, double t, double* sprev) {
   const int K = vref_nvars(p), NQ = vref_ndirs(p), d = p->dim;
@@ -454,7 +454,7 @@ static int collide_cell(const vref_params* p, const double* f, double* fstar, do
      * Lambda = (tau+ - 1/2)(tau_k - 1/2). */
     for (int k = 0; k < K; ++k) {
       const double om_a = 1.0 / p->tau[k];
-      const double om_s = 1.0 / (0.5 + p->trt_magic / (p->tau[k] - 0.5));
+      const double om_s = zeroth_rate(p, k);
       for (int i = 0; i < NQ; ++i) {
         const int ib = i == 0 ? 0 : ((i % 2 == 1) ? i + 1 : i - 1);
         const double fp = 0.5 * (f[k * NQ + i] + f[k * NQ + ib]);
