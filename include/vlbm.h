@@ -161,12 +161,27 @@ typedef struct {
   /* Collision (Sec. 2.2 admits several): 0 BGK; 1 TRT -- the antisymmetric halves
    * (f_i - f_ibar)/2, which carry the first moment, relax with 1/tau_k and the
    * symmetric halves with 1/tau+_k, (tau+_k - 1/2)(tau_k - 1/2) = trt_magic (> 0);
-   * 2 regularized BGK -- f* = f^eq + (1 - 1/tau_k) w_i e_i . J^neq / c_s^2 + w_i S~. */
+   * 2 regularized BGK -- f* = f^eq + (1 - 1/tau_k) w_i e_i . J^neq / c_s^2 + w_i S~;
+   * 3 MRT -- each set's moments (1, e_a, |e|^2 and the deviatoric second moments
+   * e_x^2 - e_y^2 [, e_x^2 + e_y^2 - 2 e_z^2]) relax toward those of f^eq: the first
+   * moments with 1/tau_k, the zeroth moment and the trace with 1/mrt_tau_e, the
+   * deviatoric ones with 1/mrt_tau_d (each > 0.5); then + w_i S~. */
   int32_t collision;
   double trt_magic;
   /* NAVIER_CAUCHY only: Lame constants (lame_mu > 0, lame_lambda + 2 lame_mu > 0) and
    * density (rho0 > 0) of the elastic medium; defaults 1, 1, 1. */
   double lame_lambda, lame_mu, rho0;
+  double mrt_tau_e, mrt_tau_d; /* MRT relaxation times (collision 3); defaults 1 */
+  /* Source operator (Sec. 2.2 names direct injection, the Guo and the Chai scheme):
+   * 0 direct injection, w_i S~(Q) with Q = sum_i f; 1 Guo -- the state is Q = sum_i f +
+   * S~(Q)/2 (two fixed-point iterations from the populations' sum; vlbm_moments
+   * reports it, and vlbm_init_fields sets sum_i f = Q - S~(Q)/2), the source entering as
+   * (1 - omega_0/2) w_i S~ with omega_0 the zeroth moment's relaxation rate; 2 Chai --
+   * the source enters as w_i (S~ + (S~ - S~_prev)/2), S~_prev the cell's source of the
+   * previous step, kept by the context (K x N values, started at S~ of the initial
+   * state; not part of vlbm_get/set_populations).  1 and 2: FP64/FP32 storage, the ideal,
+   * resistive and 13-component models, periodic lattices without a body. */
+  int32_t source;
 } vlbm_params;
 
 /* Fill *p with defaults (periodic, F32, gamma 5/3, s 0.2, tau 0.6, Powell on, BGK,

@@ -124,7 +124,18 @@ vlbm_status validate(const vlbm_params* p) {
     }
   }
   if (p->body < 0 || p->body > 2) return fail(nullptr, VLBM_ERR_ARG, "body must be 0, 1 or 2");
-  if (p->collision < 0 || p->collision > 2) return fail(nullptr, VLBM_ERR_ARG, "collision must be 0, 1 or 2");
+  if (p->collision < 0 || p->collision > 3) return fail(nullptr, VLBM_ERR_ARG, "collision must be 0, 1, 2 or 3");
+  if (p->source < 0 || p->source > 2) return fail(nullptr, VLBM_ERR_ARG, "source must be 0, 1 or 2");
+  if (p->source != 0) {
+    if (p->storage != VLBM_F64 && p->storage != VLBM_F32)
+      return fail(nullptr, VLBM_ERR_ARG, "the Guo and Chai source operators need FP64 or FP32 storage");
+    if (p->model != VLBM_IDEAL && p->model != VLBM_RESISTIVE && p->model != VLBM_RESISTIVE_2D)
+      return fail(nullptr, VLBM_ERR_ARG, "the Guo and Chai source operators apply to the models with a source");
+    if (faces || p->body) return fail(nullptr, VLBM_ERR_ARG, "the Guo and Chai source operators need a periodic lattice");
+  }
+  if (p->collision == 3 && (!(p->mrt_tau_e > 0.5) || !(p->mrt_tau_d > 0.5) || !std::isfinite(p->mrt_tau_e) ||
+                            !std::isfinite(p->mrt_tau_d)))
+    return fail(nullptr, VLBM_ERR_ARG, "MRT needs mrt_tau_e, mrt_tau_d > 0.5");
   if (p->collision == 1 && !(p->trt_magic > 0.0 && std::isfinite(p->trt_magic)))
     return fail(nullptr, VLBM_ERR_ARG, "trt_magic must be > 0");
   if ((faces || p->body) && (p->lattice != VLBM_D3Q7 || p->model != VLBM_IDEAL))
@@ -255,6 +266,7 @@ vlbm_status vlbm_params_default(vlbm_params* p) {
   p->tau_M = p->tau_H = 1.0;
   p->trt_magic = 0.25;
   p->lame_lambda = p->lame_mu = p->rho0 = 1.0;
+  p->mrt_tau_e = p->mrt_tau_d = 1.0;
   return VLBM_OK;
 }
 
@@ -321,11 +333,14 @@ vlbm_status vlbm_create(const vlbm_params* p, vlbm_ctx** out) {
   ph.powell = p->powell;
   ph.divb_mode = p->divb_mode;
   ph.collision = p->collision;
+  ph.source = p->source;
   for (int k = 0; k < KMAX; ++k) {
     const double tau = k < c->K ? p->tau[k] : 1.0;
     ph.omega_s[k] = p->collision == 1 ? 1.0 / (0.5 + p->trt_magic / (tau - 0.5))
                     : p->collision == 2 ? 1.0
+                    : p->collision == 3 ? 1.0 / p->mrt_tau_e
                                         : ph.omega[k];
+    ph.omega_d[k] = p->collision == 3 ? 1.0 / p->mrt_tau_d : ph.omega_s[k];
   }
 
   if (p->pop_buffer) {
@@ -403,6 +418,14 @@ vlbm_status vlbm_create(const vlbm_params* p, vlbm_ctx** out) {
       }
       c->g.mask = c->d_mask;
     }
+  }
+  if (p->source == 2) {  // Chai's source keeps each cell's previous source
+    const size_t bytes = (size_t)c->K * (size_t)c->N * (p->storage == VLBM_F64 ? sizeof(double) : sizeof(float));
+    if (hipMalloc(&c->d_sprev, bytes) != hipSuccess) {
+      vlbm_destroy(c);
+      return fail(nullptr, VLBM_ERR_OOM, "allocation of the previous-source field failed");
+    }
+    c->g.sprev = c->d_sprev;
   }
   c->L.storage = p->storage;
   c->L.dim = c->D;
@@ -728,6 +751,7 @@ void vlbm_destroy(vlbm_ctx* c) {
   if (c->d_totals) (void)hipFree(c->d_totals);
   if (c->d_Q) (void)hipFree(c->d_Q);
   if (c->d_mask) (void)hipFree(c->d_mask);
+  if (c->d_sprev) (void)hipFree(c->d_sprev);
   delete c;
 }
 

@@ -35,6 +35,7 @@ struct vlbm_ctx {
   vlbm::Body body{};              // geometry; t and box set per launch
   double body_rmax = 0.0;         // bound of the body's surface radius
   unsigned char* d_mask = nullptr;  // [N] body mask (body only)
+  void* d_sprev = nullptr;          // [K][N] previous-step source (Chai's source operator only)
   long long step = 0;
   bool initialized = false;
   std::string err;

@@ -17,6 +17,8 @@ struct Grid {
   int nx, ny, nz;
   int bc[6];            // per face: 0 periodic, 1 inflow, 2 zero gradient
   unsigned char* mask;  // body mask per cell (NULL: no body), bits below
+  void* sprev;          // Chai source operator: the previous step's source [K][N] in the
+                        // compute type (double for FP64 storage, else float); else NULL
 };
 
 // Body mask bits: solid now, solid before the last move, and for i = 1..6 the

@@ -200,11 +200,19 @@ __global__ __launch_bounds__(256) void k_init(const Grid g, const Phys ph, const
   flux_source<R, D, MODEL>(Q, Jb, ph, P, Sv, dl);
   const R wi = R(ph.wi);
   const R w0 = rest_weight<R, D>(wi);
+  // Guo's source: the populations' sum is the state minus half its source (the inverse
+  // of the sweep's half-source shift); Chai's: the previous source starts as S~(Q)
+  const R gs = ph.source == 1 ? R(0.5) : R(0);
 #pragma unroll
   for (int k = 0; k < K; ++k)
 #pragma unroll
     for (int i = 0; i < NQ; ++i)
-      F[(size_t)(k * NQ + i) * g.stride + c] = S::enc(feq_dir<R, D>(Q[k], P[k], i, w0, wi), cd, k * NQ + i);
+      F[(size_t)(k * NQ + i) * g.stride + c] =
+          S::enc(feq_dir<R, D>(Q[k], P[k], i, w0, wi) - gs * (i == 0 ? w0 : wi) * Sv[k], cd, k * NQ + i);
+  if (ph.source == 2 && g.sprev) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) static_cast<R*>(g.sprev)[(size_t)k * N + c] = Sv[k];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -281,6 +289,19 @@ __global__ __launch_bounds__(kReduceThreads) void k_moments(const Grid g, const 
       Qout[(size_t)k * N + c] = q;
     }
     double P[K][3], Sv[K], dl;
+    if (ph.source == 1) {
+      // Guo's state: sum f + S~/2 by the sweep's two fixed-point iterations
+      double q[K];
+      flux_source<double, D, MODEL>(Q, Jb, ph, P, Sv, dl);
+#pragma unroll
+      for (int k = 0; k < K; ++k) q[k] = Q[k] + 0.5 * Sv[k];
+      flux_source<double, D, MODEL>(q, Jb, ph, P, Sv, dl);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        Q[k] += 0.5 * Sv[k];
+        Qout[(size_t)k * N + c] = Q[k];
+      }
+    }
     const bool bad = flux_source<double, D, MODEL>(Q, Jb, ph, P, Sv, dl);
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] += Q[k];

@@ -1089,7 +1089,7 @@ vlbm_status vlbm_restrict(const float* Qf, int32_t K, int32_t nx, int32_t ny, in
 namespace {
 // a periodic ideal-MHD context (2D batch or 3D lattice, any storage form)
 bool correctable(const vlbm_ctx* c) {
-  return c->K == 8 && c->p.model == VLBM_IDEAL && !c->has_faces && c->p.body == 0;
+  return c->K == 8 && c->p.model == VLBM_IDEAL && !c->has_faces && c->p.body == 0 && c->p.source == 0;
 }
 
 // The launchers below index by storage * 2 + (dimension - 2): the storage codes of

@@ -31,8 +31,13 @@ struct Phys {
   double mu, eta0, inv_jc2, inv_tauM, inv_tauH;
   double divb_scale; // divb_mode 1: dx = dt / s (lattice units of tr G / tau_M)
   int powell, divb_mode;
-  int collision;     // 0 BGK; else two rates: antisymmetric halves at omega, symmetric at omega_s
+  int collision;     // 0 BGK; else the first moments (antisymmetric halves) at omega, the
+                     // zeroth moment and the trace of the second moments at omega_s, their
+                     // deviatoric part at omega_d (TRT and RLB: omega_d = omega_s; MRT apart)
   double omega_s[KMAX];
+  double omega_d[KMAX];
+  int source;        // 0 direct injection; 1 Guo (state = sum f + S/2, source times
+                     // 1 - omega_0/2); 2 Chai (source + half its change since the last step)
   double lame_lambda, lame_mu, inv_rho0;  // Navier-Cauchy medium
 };
 
@@ -337,9 +342,16 @@ struct NoTarget {
 // estimate, the pre-collision moments Q and the total pressure pt of Q'.
 // COLL 0: BGK; 1: two relaxation rates (TRT, and the regularized BGK as its case
 // omega_s = 1) -- a template parameter, so that the BGK sweep keeps its registers.
-template <typename R, int D, int MODEL, int COLL = 0, typename Tgt = NoTarget>
+// SRC: the source operator (Sec. 2.2 names direct injection, Guo's and Chai's): 0 direct
+// injection of w_i S~(Q); 1 Guo -- the state is Q = sum f + S~(Q)/2, found by two
+// fixed-point iterations from the populations' sum, and the source enters as
+// (1 - omega_0/2) w_i S~ with omega_0 the zeroth moment's rate; 2 Chai -- the source
+// enters as w_i (S~ + (S~ - S~_prev)/2), sp holding the cell's S~_prev on entry and
+// this step's S~ on return.
+template <typename R, int D, int MODEL, int COLL = 0, typename Tgt = NoTarget, int SRC = 0>
 __device__ __forceinline__ bool collide(R (*f)[2 * D + 1], const Phys& ph, R& dlat,
-                                        R (&Q)[kNVars<MODEL>], R& pt, const Tgt& tgt = Tgt{}) {
+                                        R (&Q)[kNVars<MODEL>], R& pt, const Tgt& tgt = Tgt{},
+                                        R* sp = nullptr) {
   constexpr int K = kNVars<MODEL>;
   // Zeroth moments, opposite directions paired first: f_{+a} + f_{-a} cancels the
   // flux part c_a . Phi / c_s^2 the two carry with opposite signs before it is
@@ -361,10 +373,30 @@ __device__ __forceinline__ bool collide(R (*f)[2 * D + 1], const Phys& ph, R& dl
   R Qt[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) Qt[k] = Q[k];
+  if constexpr (SRC == 1) {
+    R P0[K][3], S0[K], d0;
+    flux_source<R, D, MODEL>(Q, Jb, ph, P0, S0, d0);
+#pragma unroll
+    for (int k = 0; k < K; ++k) Qt[k] = Q[k] + R(0.5) * S0[k];
+    flux_source<R, D, MODEL>(Qt, Jb, ph, P0, S0, d0);
+#pragma unroll
+    for (int k = 0; k < K; ++k) Qt[k] = Q[k] + R(0.5) * S0[k];
+  }
   tgt(Qt);
   R P[K][3];
   R S[K];
   const bool bad = flux_source<R, D, MODEL>(Qt, Jb, ph, P, S, dlat, &pt);
+  if constexpr (SRC == 1) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) S[k] *= R(1) - R(0.5) * R(COLL == 0 ? ph.omega[k] : ph.omega_s[k]);
+  } else if constexpr (SRC == 2) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const R now = S[k];
+      S[k] = now + R(0.5) * (now - sp[k]);
+      sp[k] = now;
+    }
+  }
   const R wi = R(ph.wi);
   const R w0 = rest_weight<R, D>(wi);
   if constexpr (COLL == 0) {
@@ -382,19 +414,28 @@ __device__ __forceinline__ bool collide(R (*f)[2 * D + 1], const Phys& ph, R& dl
       }
     }
   } else {
-    // two relaxation rates over each opposite pair: the symmetric half (f_+ + f_-)/2
-    // toward w_i Q at omega_s, the antisymmetric half (f_+ - f_-)/2 toward w_i P at
-    // omega; the rest population is symmetric.  The regularized BGK of these
-    // first-order lattices is the case omega_s = 1.
+    // moment relaxation over each opposite pair: the antisymmetric half (f_+ - f_-)/2
+    // (the first moment) toward w_i P at omega; the symmetric halves' non-equilibrium
+    // parts h_a = (f_+ + f_-)/2 - w_i Q split into their mean over the axes (the trace
+    // of the second moments), relaxed with the rest population at omega_s, and their
+    // deviations from it, relaxed at omega_d.  omega_d = omega_s: TRT (and the
+    // regularized BGK of these first-order lattices, omega_s = 1); else MRT.
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const R oa = R(ph.omega[k]), os = R(ph.omega_s[k]);
+      const R oa = R(ph.omega[k]), os = R(ph.omega_s[k]), od = R(ph.omega_d[k]);
       const R sw0 = w0 * S[k], swi = wi * S[k];
       f[k][0] += os * (w0 * Qt[k] - f[k][0]) + sw0;
+      R h[D], hm = R(0);
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        h[a] = R(0.5) * (f[k][2 * a + 1] + f[k][2 * a + 2]) - wi * Qt[k];
+        hm += h[a];
+      }
+      hm *= R(1.0 / D);
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         const R fp = f[k][2 * a + 1], fm = f[k][2 * a + 2];
-        const R ds = os * (R(0.5) * (fp + fm) - wi * Qt[k]);
+        const R ds = os * hm + od * (h[a] - hm);
         const R da = oa * (R(0.5) * (fp - fm) - wi * P[k][a]);
         f[k][2 * a + 1] = fp - ds - da + swi;
         f[k][2 * a + 2] = fm - ds + da + swi;

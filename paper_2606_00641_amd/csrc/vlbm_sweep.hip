@@ -80,7 +80,7 @@ struct XchLds<T, K, false> {};
 // one wavefront per SIMD; bounding it to two per SIMD costs 48 B of scratch per lane
 // and was measured 4-5 % faster (at parity 1 the bound spills more and is slower).
 template <int ST, int D, int MODEL, int PAR, int BODY = 0, int COLL = 0, bool INJ = false, bool XCH = false,
-          bool FX = false>
+          bool FX = false, int SRC = 0>
 __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COLL == 0) ? 2 : 1) void k_sweep(
     const Grid g, const Phys ph, const Codec cd, const Body bd, const float* __restrict__ dq,
     const int* __restrict__ dqflag, const Inflow in, const MomentsOut mo) {
@@ -291,6 +291,19 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
         *reinterpret_cast<uint4*>(mo.act + (size_t)c * K) =
             make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
       }
+    } else if constexpr (SRC == 2) {
+      // Chai's source: the cell's previous source in, this step's out (own cell, any parity)
+      const size_t N = (size_t)g.nx * g.ny * g.nz;
+      R* __restrict__ sprev = static_cast<R*>(g.sprev);
+      R sp[K], Q[K], pt;
+#pragma unroll
+      for (int k = 0; k < K; ++k) sp[k] = sprev[(size_t)k * N + c];
+      collide<R, D, MODEL, COLL, NoTarget, SRC>(f, ph, dl, Q, pt, NoTarget{}, sp);
+#pragma unroll
+      for (int k = 0; k < K; ++k) sprev[(size_t)k * N + c] = sp[k];
+    } else if constexpr (SRC == 1) {
+      R Q[K], pt;
+      collide<R, D, MODEL, COLL, NoTarget, SRC>(f, ph, dl, Q, pt);
     } else {
       collide<R, D, MODEL, COLL>(f, ph, dl);
     }
@@ -462,8 +475,35 @@ void launch_k(const Launch& L, dim3 grd, int parity, int coll, bool xch, bool fx
   with_coll(I1{}, BF{});
 }
 
+// Sweeps with the Guo or Chai source operator: the plain periodic sweep (direct +-x
+// accesses at parity 1), BGK or the moment-rate collisions, FP64/FP32 storage and the
+// models with sources (ideal, resistive, 13-component); the library refuses the rest.
+template <int ST, int D, int MODEL>
+hipError_t sweep_src_t(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity) {
+  if constexpr ((ST == ST_F64 || ST == ST_F32) && (MODEL == 0 || MODEL == 1 || MODEL == 4)) {
+    const dim3 grd = cell_grid(g, L.block_x), blk(L.block_x);
+    const int key = (parity ? 4 : 0) + (ph.collision ? 2 : 0) + (ph.source == 2 ? 1 : 0);
+    switch (key) {
+#define SRC_CASE(P, C, SR)                                                                                    \
+  case (P ? 4 : 0) + (C ? 2 : 0) + (SR == 2 ? 1 : 0):                                                          \
+    hipLaunchKernelGGL((k_sweep<ST, D, MODEL, P, 0, C, false, false, false, SR>), grd, blk, 0, L.stream, g, ph, cd, \
+                       Body{}, nullptr, nullptr, Inflow{}, MomentsOut{});                                        \
+    break;
+      SRC_CASE(0, 0, 1) SRC_CASE(0, 0, 2) SRC_CASE(0, 1, 1) SRC_CASE(0, 1, 2)
+      SRC_CASE(1, 0, 1) SRC_CASE(1, 0, 2) SRC_CASE(1, 1, 1) SRC_CASE(1, 1, 2)
+#undef SRC_CASE
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  } else {
+    (void)L, (void)g, (void)ph, (void)cd, (void)parity;
+    return hipErrorInvalidValue;
+  }
+}
+
 template <int ST, int D, int MODEL>
 hipError_t sweep_t(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity, const Inflow& in) {
+  if (ph.source != 0) return sweep_src_t<ST, D, MODEL>(L, g, ph, cd, parity);
   launch_k<ST, D, MODEL, 0, false>(L, cell_grid(g, L.block_x), parity, ph.collision, lane_exchange(g, L.block_x, MODEL),
                                    fuse_x_faces(g), g, ph, cd, Body{}, nullptr, nullptr, in);
   return hipGetLastError();

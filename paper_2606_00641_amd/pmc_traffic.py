@@ -43,7 +43,7 @@ def read_counter(path, counter):
     return rows
 
 
-SWEEP_RE = re.compile(r"k_sweep<(\d+), (\d+), (\d+), (\d+), (\d+), (\d+)((?:, (?:true|false))*)>")
+SWEEP_RE = re.compile(r"k_sweep<(\d+), (\d+), (\d+), (\d+), (\d+), (\d+)((?:, (?:true|false|\d+))*)>")
 
 
 def per_parity(rows, st, d, model):
@@ -55,7 +55,8 @@ def per_parity(rows, st, d, model):
         if not m:
             continue
         ST, D, MODEL, PAR, BODY, COLL, flags = m.groups()
-        if (int(ST), int(D), int(MODEL), int(BODY), int(COLL)) != (st, d, model, 0, 0) or "true" in flags:
+        if (int(ST), int(D), int(MODEL), int(BODY), int(COLL)) != (st, d, model, 0, 0) or "true" in flags \
+                or re.search(r", [1-9]", flags):
             continue
         acc.setdefault(int(PAR), []).append(v)
     return {p: sum(v) / len(v) for p, v in sorted(acc.items())}

@@ -75,6 +75,9 @@ class vlbm_params(ctypes.Structure):
         ("lame_lambda", ctypes.c_double),
         ("lame_mu", ctypes.c_double),
         ("rho0", ctypes.c_double),
+        ("mrt_tau_e", ctypes.c_double),
+        ("mrt_tau_d", ctypes.c_double),
+        ("source", ctypes.c_int32),
     ]
 
 
@@ -145,7 +148,7 @@ def make_params(lattice="D2Q5", shape=(64, 64, 1), model="ideal", storage="f32",
                 flux_scale=0.2, tau=0.6, powell=True, divb_mode=0, dt=0.0, mu=0.0, eta0=0.0,
                 j_c=0.0, tau_M=1.0, tau_H=1.0, w0=0.0, bc=None, inflow_Q=None, scale=None,
                 stream=None, block_x=0, body=None, collision="bgk", trt_magic=0.25, lame_lambda=1.0, lame_mu=1.0,
-                rho0=1.0):
+                rho0=1.0, mrt_tau_e=1.0, mrt_tau_d=1.0, source="direct"):
     p = vlbm_params()
     _check(_lib.vlbm_params_default(ctypes.byref(p)))
     p.lattice = VLBM_D3Q7 if str(lattice).upper() == "D3Q7" else VLBM_D2Q5
@@ -176,7 +179,9 @@ def make_params(lattice="D2Q5", shape=(64, 64, 1), model="ideal", storage="f32",
             p.scale[k] = float(v)
     p.stream = stream
     p.block_x = int(block_x)
-    p.collision = {"bgk": 0, "trt": 1, "rlb": 2}[collision] if isinstance(collision, str) else int(collision)
+    p.collision = {"bgk": 0, "trt": 1, "rlb": 2, "mrt": 3}[collision] if isinstance(collision, str) else int(collision)
+    p.mrt_tau_e, p.mrt_tau_d = float(mrt_tau_e), float(mrt_tau_d)
+    p.source = {"direct": 0, "guo": 1, "chai": 2}[source] if isinstance(source, str) else int(source)
     p.trt_magic = float(trt_magic)
     p.lame_lambda, p.lame_mu, p.rho0 = float(lame_lambda), float(lame_mu), float(rho0)
     if body is not None:

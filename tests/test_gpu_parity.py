@@ -96,24 +96,28 @@ def test_fourier2d_fp32_parity_200_steps(vb):
     assert max(err.values()) <= 1e-5, err
 
 
-@pytest.mark.parametrize("collision,magic", [("trt", 0.25), ("trt", 1.0 / 12.0), ("rlb", 0.25)])
+MRT_TAUS = (0.8, 1.3)  # mrt_tau_e, mrt_tau_d of the MRT cases
+
+
+@pytest.mark.parametrize("collision,magic", [("trt", 0.25), ("trt", 1.0 / 12.0), ("rlb", 0.25), ("mrt", 0.25)])
 @pytest.mark.parametrize("storage,tol", [("f64", 1e-10), ("f32", 1e-5)])
 def test_two_rate_collisions_parity(vb, collision, magic, storage, tol):
-    """TRT and the regularized BGK (Sec. 2.2 names both): 2D Fourier workload, 200
-    steps; the GPU applies both as two relaxation rates per opposite pair, the oracle
-    follows each definition literally."""
+    """TRT, the regularized BGK and MRT (Sec. 2.2 names all three): 2D Fourier
+    workload, 200 steps; the GPU relaxes each opposite pair's antisymmetric half and the
+    trace and deviatoric parts of the symmetric halves at their rates, the oracle
+    follows each definition literally (MRT through its moment matrix)."""
     w = synth.workload_fourier_2d()
     Q0 = synth.fourier_2d(64, seed=1)
-    code = {"trt": 1, "rlb": 2}[collision]
+    code = {"trt": 1, "rlb": 2, "mrt": 3}[collision]
     print(f"case {collision} magic={magic} {storage}", flush=True)
     sim = vb.Vlbm(vb.make_params(lattice="D2Q5", shape=(64, 64, 1), storage=storage, gamma=w["gamma"],
                                  flux_scale=w["s"], tau=w["tau"], powell=w["powell"], collision=collision,
-                                 trt_magic=magic, stream=_stream()))
+                                 trt_magic=magic, mrt_tau_e=MRT_TAUS[0], mrt_tau_d=MRT_TAUS[1], stream=_stream()))
     sim.vlbm_init_fields(Q0)
     sim.vlbm_step(200)
     Qg, _ = sim.vlbm_moments()
     op = oracle.make_params(dim=2, shape=(64, 64, 1), s=w["s"], tau=w["tau"], powell=w["powell"], collision=code,
-                            trt_magic=magic)
+                            trt_magic=magic, mrt_tau_e=MRT_TAUS[0], mrt_tau_d=MRT_TAUS[1])
     f = oracle.init(op, Q0)
     oracle.run(op, f, 200)
     Qo, _, _ = oracle.moments(op, f)
@@ -127,20 +131,22 @@ def test_two_rate_collisions_parity(vb, collision, magic, storage, tol):
         assert e <= max(tol, 1.5 * yard[name]), (name, e, yard[name])
 
 
-@pytest.mark.parametrize("collision", ["trt", "rlb"])
+@pytest.mark.parametrize("collision", ["trt", "rlb", "mrt"])
 def test_two_rate_collisions_3d_resistive_fp64(vb, collision):
     w = synth.workload_resistive_3d(n=16, dt_over_tau_M=0.49)
     w["shape"] = (12, 10, 8)
     Q0 = small_resistive()
-    code = {"trt": 1, "rlb": 2}[collision]
+    code = {"trt": 1, "rlb": 2, "mrt": 3}[collision]
     p = gpu_params(vb, w, "f64")
     p.collision, p.trt_magic = code, 0.25
+    p.mrt_tau_e, p.mrt_tau_d = MRT_TAUS
     sim = vb.Vlbm(p)
     sim.vlbm_init_fields(Q0)
     sim.vlbm_step(30)
     Qg, _ = sim.vlbm_moments()
     op = oracle_params(w)
     op.collision, op.trt_magic = code, 0.25
+    op.mrt_tau_e, op.mrt_tau_d = MRT_TAUS
     f = oracle.init(op, Q0)
     oracle.run(op, f, 30)
     Qo, _, _ = oracle.moments(op, f)
@@ -363,6 +369,71 @@ def test_diagnostics_match_oracle_on_the_same_populations(vb, case, storage):
     assert to[K + 1] > 0 and to[K + 3] > 0
     assert abs(tg[K + 3] - to[K + 3]) <= 1e-12 * to[K + 3]
     assert tg[K + 4] == to[K + 4] == 0
+
+
+# --- source operators: Guo and Chai (Sec. 2.2) ------------------------------------
+
+def _source_case(case):
+    if case == "fourier_2d":
+        w = synth.workload_fourier_2d()
+        return w, synth.fourier_2d(64, seed=2), 200, 8
+    if case == "resistive_3d":
+        w = synth.workload_resistive_3d(n=16, dt_over_tau_M=0.49)
+        w["shape"] = (12, 10, 8)
+        return w, small_resistive(), 60, 26
+    w, Q0 = small_resistive_2d()
+    return w, Q0, 200, 13
+
+
+@pytest.mark.parametrize("source", ["guo", "chai"])
+@pytest.mark.parametrize("case", ["fourier_2d", "resistive_3d", "resistive_2d"])
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-10), ("f32", 1e-5)])
+def test_source_operators_parity(vb, source, case, storage, tol):
+    """The Guo and Chai source operators on the models with sources (Powell's source,
+    and the relaxation of the transported gradients and stress): GPU against the
+    oracle, FP64 within 1e-10 and FP32 within 1e-5 (or 2x the oracle evaluated in FP32
+    where the FP32 formulas themselves miss it, the rule of the resistive system)."""
+    w, Q0, steps, K = _source_case(case)
+    print(f"case source {source} {case} {storage}", flush=True)
+    p = gpu_params(vb, w, storage)
+    p.source = {"guo": 1, "chai": 2}[source]
+    sim = vb.Vlbm(p)
+    sim.vlbm_init_fields(Q0)
+    sim.vlbm_step(steps)
+    Qg, tg = sim.vlbm_moments()
+    op = oracle_params(w)
+    op.source = p.source
+    f = oracle.init(op, Q0)
+    sp = oracle.source_field(op, f) if source == "chai" else None
+    oracle.run(op, f, steps, sprev=sp)
+    Qo, _, to = oracle.moments(op, f)
+    err = rel_l2(Qg, Qo, K)
+    assert tg[K + 4] == 0
+    if storage == "f64":
+        assert max(err.values()) <= tol, err
+        return
+    yard = rel_l2(oracle.run_fp32(op, Q0, steps), Qo, K)
+    for name, e in err.items():
+        assert e <= max(tol, 2.0 * yard[name]), (name, e, yard[name])
+
+
+def test_source_operators_refused_where_not_built(vb):
+    """The Guo and Chai operators need FP64/FP32 storage, a model with a source and a
+    periodic lattice without a body: anything else is refused at creation."""
+    w = synth.workload_fourier_2d()
+    for storage in ("f16", "bf16"):
+        p = gpu_params(vb, w, storage)
+        p.source = 1
+        with pytest.raises(vb.VlbmError):
+            vb.Vlbm(p)
+    p = vb.make_params(lattice="D3Q7", shape=(16, 8, 8), model="euler", storage="f64", source="chai",
+                       stream=_stream())
+    with pytest.raises(vb.VlbmError):
+        vb.Vlbm(p)
+    p = vb.make_params(lattice="D3Q7", shape=(16, 8, 8), storage="f64", source="guo", bc=(1, 2, 2, 2, 2, 2),
+                       inflow_Q=[1.0, 0.1, 0, 0, 1.0, 0, 0, 0], stream=_stream())
+    with pytest.raises(vb.VlbmError):
+        vb.Vlbm(p)
 
 
 # --- the 13-component 2D system (Sec. 3.1) ---------------------------------------
