@@ -20,6 +20,15 @@ constexpr int kReduceThreads = 256;
 // ---------------------------------------------------------------------------
 // storage codecs
 // ---------------------------------------------------------------------------
+// A scalar the compiler must treat as new at each use.  The FP64 decode converts the
+// codec's FP32 constants to double; inside a grid-stride loop the compiler would
+// otherwise hoist all 2 x K x Q converted constants out of the loop and keep them in
+// VGPRs (over 300 for 26 variables: one wave per SIMD, and scratch spills).
+__device__ __forceinline__ float opaque(float v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 template <int ST>
 struct Store;
 
@@ -55,7 +64,7 @@ struct Store<ST_F16> {
     return __half_as_ushort(__float2half_rn(h));
   }
   static __device__ __forceinline__ double dec64(T v, const Codec& cd, int j) {
-    return (double)cd.rest[j] + (double)cd.sc[j] * (double)h2f(v);
+    return (double)opaque(cd.rest[j]) + (double)opaque(cd.sc[j]) * (double)h2f(v);
   }
 };
 
@@ -74,7 +83,7 @@ struct Store<ST_BF16> {
     return (T)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
   }
   static __device__ __forceinline__ double dec64(T v, const Codec& cd, int j) {
-    return (double)cd.rest[j] + (double)cd.sc[j] * (double)b2f(v);
+    return (double)opaque(cd.rest[j]) + (double)opaque(cd.sc[j]) * (double)b2f(v);
   }
 };
 
