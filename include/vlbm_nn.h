@@ -123,7 +123,12 @@ vlbm_status vlbm_inject(vlbm_ctx* c, const float* dQ);
  * extent the network supports: 2D (nz = batch of independent lattices, gated
  * together and projected one by one) with a dim-2 network, or 3D (one lattice) with a
  * dim-3 network.  bound_corr: host, K doubles.  *n_fallback (host, may be NULL)
- * receives the number of fallbacks in this call.  Synchronises. */
+ * receives the number of fallbacks in this call.  Synchronises.  The handle keeps the
+ * step's buffers (about 128 N + N / 4 bytes for N cells, grown for a larger context), a stream,
+ * an event and the graph of a pair of steps from call to call, until vlbm_nn_destroy;
+ * the graph is captured again after the context is initialised or restored, for the
+ * other starting parity, the other projection setting or another context.  Calls on one
+ * network handle must not overlap. */
 vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const double* bound_corr,
                                 double bound_divb_rel, double bound_divb_abs, int32_t project_totals,
                                 int64_t* n_fallback);

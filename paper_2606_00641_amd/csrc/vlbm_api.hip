@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -213,6 +214,7 @@ hipError_t body_mask_full(vlbm_ctx* c) {
 }
 
 void build_codec(vlbm_ctx* c) {
+  ++c->gen;
   std::memset(&c->cd, 0, sizeof c->cd);
   if (c->p.storage != VLBM_F16DEV && c->p.storage != VLBM_BF16DEV) return;
   double P[KMAX][3], S[KMAX], dl, Jb[3] = {0, 0, 0};
@@ -297,6 +299,8 @@ vlbm_status vlbm_create(const vlbm_params* p, vlbm_ctx** out) {
   c->stride = plane_stride(c->N, c->esize);
   c->pop_bytes = (size_t)c->K * c->NQ * c->stride * c->esize;
   c->stream = static_cast<hipStream_t>(p->stream);
+  static std::atomic<long long> next_uid{1};
+  c->uid = next_uid++;
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
     return fail(nullptr, VLBM_ERR_HIP, "hipGetDevice failed");

@@ -37,6 +37,10 @@ struct vlbm_ctx {
   unsigned char* d_mask = nullptr;  // [N] body mask (body only)
   void* d_sprev = nullptr;          // [K][N] previous-step source (Chai's source operator only)
   long long step = 0;
+  // identity of this context (unique in the process) and the generation of what kernel
+  // launches take by value (the codec changes at init and restore); a graph captured
+  // from this context is valid while both are unchanged
+  long long uid = 0, gen = 0;
   bool initialized = false;
   std::string err;
 };

@@ -97,10 +97,18 @@ hipError_t launch_refill(const Launch& L, const Grid& g, const Phys& ph, const C
 hipError_t launch_sweep_body(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
                              const Body& b, int mode, const Inflow& in);
 
+// Control block of a pending learned correction (device, 32-bit words): ctl[0] nonzero
+// means "add it"; ctl[1 + 8 b + k] holds, as an FP32 bit pattern, the mean that channel k
+// of lattice b loses (its projection onto zero lattice totals; 0 without projection).
+// Lattice b is the slice z for a batch of 2D lattices and 0 for a 3D lattice.  The
+// correction added is w_i (dq[k][c] - mean[b][k]), the difference taken in FP32.
+__host__ __device__ inline int inj_lattice(int dim, int z) { return dim == 2 ? z : 0; }
+
 // Sweep of a periodic 2D or 3D ideal-MHD BGK lattice (any storage form) that first
-// adds *flag * w_i dq[k][c] to the gathered, decoded populations (dq FP32 [K][N], device).
+// adds the pending correction of control block ctl (above) to the gathered, decoded
+// populations (dq FP32 [K][N], device).
 hipError_t launch_sweep_inj(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
-                            const float* dq, const int* flag, const MomentsOut& mo);
+                            const float* dq, const int* ctl, const MomentsOut& mo);
 
 // f := f^eq(Q) in natural layout.  Q is device SoA [K][N], FP64 or FP32.
 hipError_t launch_init(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd,

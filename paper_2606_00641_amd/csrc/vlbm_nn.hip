@@ -47,6 +47,25 @@ constexpr int kConvThreads = 64 * (TILE / kConvRows);
 constexpr int kMaxLayers = 8;
 constexpr int kGateThreads = 256;
 
+// Sum of a double over the 64 lanes of a wavefront, in every lane.  The four levels
+// inside each row of 16 lanes use DPP row rotations (by 8, 4, 2, 1; VALU only, every
+// lane of a row ends with the row's sum), the two levels across rows lane shuffles.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_f64<0x128>(v);  // row_ror:8
+  v += dpp_f64<0x124>(v);  // row_ror:4
+  v += dpp_f64<0x122>(v);  // row_ror:2
+  v += dpp_f64<0x121>(v);  // row_ror:1
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  return v;
+}
+
 enum { MODE_HIDDEN = 0, MODE_LAST = 1, MODE_BWD = 2 };
 
 __host__ __device__ inline int ksteps(int cin) { return (9 * cin + 31) / 32; }
@@ -117,12 +136,11 @@ __global__ __launch_bounds__(kConvThreads) void k_conv(const bf16_t* __restrict_
                                                    bf16_t* __restrict__ out_act, float* __restrict__ out_z,
                                                    const float* __restrict__ zprev,
                                                    const float* __restrict__ oscale,
-                                                   const float* __restrict__ oshift, double* __restrict__ tsum) {
+                                                   const float* __restrict__ oshift) {
   constexpr int KS = (9 * CIN + 31) / 32;
   constexpr int NT = (COUT + 15) / 16;
   constexpr int CH = CIN / 8;
   constexpr int MR = kConvRows;     // rows of the 16 x 16 tile per wavefront
-  constexpr int NW = TILE / MR;     // wavefronts per workgroup
   constexpr int NTH = kConvThreads;
   // The input halo, and after the products the FP32 results of the tile (HIDDEN and
   // BWD), share one LDS buffer.  Result rows are padded by 4 floats so that the four
@@ -201,9 +219,6 @@ __global__ __launch_bounds__(kConvThreads) void k_conv(const bf16_t* __restrict_
 
   if constexpr (MODE == MODE_LAST) {
     // channel-major output: a lane's four results are four consecutive x of one channel
-    double ts[NT];  // FP64 sums of this lane's outputs per channel (tsum != NULL)
-#pragma unroll
-    for (int t = 0; t < NT; ++t) ts[t] = 0.0;
 #pragma unroll
     for (int m = 0; m < MR; ++m) {
       const int y = ty0 + MR * wv + m;
@@ -218,30 +233,6 @@ __global__ __launch_bounds__(kConvThreads) void k_conv(const bf16_t* __restrict_
         o.z = (acc[m][t][2] + b) * sc + sh;
         o.w = (acc[m][t][3] + b) * sc + sh;
         *reinterpret_cast<float4*>(out_z + (((size_t)co * gridDim.z + sl) * H + y) * W + tx0 + 4 * g) = o;
-        ts[t] += ((double)o.x + (double)o.y) + ((double)o.z + (double)o.w);
-      }
-    }
-    if (tsum) {
-      // per-channel sum of the tile, tsum[co][tile] (tiles in launch order, so the
-      // tiles of one lattice are contiguous); a fixed order, so every run agrees
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {  // lanes l, l ^ 16, l ^ 32, l ^ 48 share a channel
-        ts[t] += __shfl_xor(ts[t], 16);
-        ts[t] += __shfl_xor(ts[t], 32);
-      }
-      double* wsum = reinterpret_cast<double*>(lds);  // [wavefront][16 NT]
-      __syncthreads();  // every wavefront is done with the halo
-      if (lane < 16)
-#pragma unroll
-        for (int t = 0; t < NT; ++t) wsum[wv * 16 * NT + 16 * t + lane] = ts[t];
-      __syncthreads();
-      if ((int)threadIdx.x < COUT) {
-        const int co = threadIdx.x;
-        double tot = 0.0;
-        for (int w = 0; w < NW; ++w) tot += wsum[w * 16 * NT + co];
-        const size_t ntile = (size_t)gridDim.x * gridDim.y * gridDim.z;
-        const size_t tile = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-        tsum[(size_t)co * ntile + tile] = tot;
       }
     }
   } else {
@@ -518,26 +509,29 @@ __device__ inline void upwind_cells(const vlbm::Grid& g, size_t c, size_t* up) {
   }
 }
 
-// add w_i dQ_k to every population at the given parity, if *flag (or flag is NULL);
-// FP16/BF16 deviations are decoded, incremented in FP32 and encoded again
+// add w_i dQ_k to every population at the given parity; ctl NULL: dQ_k = dq[k][c];
+// else only if ctl[0], with dQ_k = dq[k][c] - mean[b][k] of control block ctl (the
+// layout launch_sweep_inj describes).  FP16/BF16 deviations are decoded, incremented in
+// FP32 and encoded again
 template <int ST, int D>
 __global__ void k_inject(const vlbm::Grid g, const vlbm::Codec cd, int parity, const float* __restrict__ dq,
-                         const int* __restrict__ flag, double wi_d) {
+                         const int* __restrict__ ctl, double wi_d) {
   using S = vlbm::Store<ST>;
   using T = typename S::T;
   using R = typename S::R;
   constexpr int K = 8, NQ = 2 * D + 1;
   const size_t N = (size_t)g.nx * g.ny * g.nz;
   const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= N || (flag && !*flag)) return;
+  if (c >= N || (ctl && !ctl[0])) return;
   size_t up[NQ];
   upwind_cells<D>(g, c, up);
+  const int* mean = ctl ? ctl + 1 + 8 * vlbm::inj_lattice(D, (int)(c / ((size_t)g.nx * g.ny))) : nullptr;
   T* F = static_cast<T*>(g.f);
   // same weights, in the same type, as the injecting sweep
   const R wi = (R)wi_d;
   const R w0 = vlbm::rest_weight<R, D>(wi);
   for (int k = 0; k < K; ++k) {
-    const R d = (R)dq[(size_t)k * N + c];
+    const R d = (R)(mean ? dq[(size_t)k * N + c] - __int_as_float(mean[k]) : dq[(size_t)k * N + c]);
     if (d == R(0)) continue;  // nothing to add: the stored values stay as they are
     for (int i = 0; i < NQ; ++i) {
       const int slot = parity == 0 ? i : vlbm::opposite(i);
@@ -553,84 +547,67 @@ struct GateBounds {
   double divb_rel, divb_abs;
 };
 
-// Gate statistics of the network's correction, after its projection onto zero lattice
-// totals.  The fine run, its restriction and the coarse VLBM all keep each lattice's
-// totals of rho, rho u, E and B (up to the Powell source), so the correction they
-// define has zero total; projecting the prediction onto that keeps a small bias of the
-// network from accumulating in the totals over many steps.
-// raw: the network's output; tsum (NULL: no projection): its per-channel tile sums
-// from the last convolution, tsum[k][tile], the ntl tiles of lattice b at
-// [b ntl, (b + 1) ntl).  Every workgroup works inside one lattice (blockIdx.y): it sums
-// that lattice's tile sums in a fixed order (all its workgroups get the same means),
-// writes dq = raw - mean (FP32, as stored) and accumulates over its cells the FP64
-// partials: [0..7] sum dQ_k^2, [8] sum divc(X)^2, [9] sum divc(X + dQ)^2,
-// [10] non-finite count, [11] sum |B(X)|^2 (the D components the divergence sees).
-// D = 2: nz lattices of nx x ny (divergence of the in-plane field); D = 3: one
-// nx x ny x nz lattice.  raw and dq are distinct buffers (neighbours are read from raw
-// and projected on the fly).
+// Gate statistics of the network's raw correction.  The fine run, its restriction and
+// the coarse VLBM all keep each lattice's totals of rho, rho u, E and B (up to the Powell
+// source), so the correction they define has zero total; projecting the prediction onto
+// that (each lattice's mean removed, channel by channel) keeps a small bias of the
+// network from accumulating in the totals over many steps.  The projection is not
+// applied here: k_gate_final forms the means from these sums and the injection
+// subtracts them, and since a constant has no central difference and
+// sum (r - m)^2 = sum r^2 - 2 m sum r + n m^2, the gate's statistics of the projected
+// correction follow from those of the raw one.
+// Every workgroup works inside one lattice (blockIdx.y) and accumulates over its cells
+// the FP64 partials: [0..7] sum r_k^2, [8..15] sum r_k, [16] sum divc(X)^2,
+// [17] sum divc(X + r)^2, [18] non-finite count, [19] sum |B(X)|^2 (the D components
+// the divergence sees); r = raw, the network's output.  D = 2: nz lattices of nx x ny
+// (divergence of the in-plane field); D = 3: one nx x ny x nz lattice.
+constexpr int kGateNP = 20;
+
 template <int D>
 __global__ __launch_bounds__(kGateThreads) void k_gate_partials(const float* __restrict__ X, const float* __restrict__ raw,
-                                                                float* __restrict__ dq, const double* __restrict__ tsum,
-                                                                int ntl, int nx, int ny, int nz,
-                                                                double* __restrict__ partial) {
-  constexpr int NP = 12;
+                                                                int nx, int ny, int nz, double* __restrict__ partial) {
+  constexpr int NP = kGateNP;
   __shared__ double sh[kGateThreads / 64][NP];
-  __shared__ float mean[8];
-  const size_t N = (size_t)nx * ny * nz;
   const int nb = gridDim.y, b = blockIdx.y;
-  const size_t ncl = N / (size_t)nb;  // cells per lattice
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int k = wv; k < 8; k += kGateThreads / 64) {
-    double t = 0.0;
-    if (tsum) {
-      const double* q = tsum + (size_t)k * nb * ntl + (size_t)b * ntl;
-      for (int j = lane; j < ntl; j += 64) t += q[j];
-      for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
-    }
-    if (lane == 0) mean[k] = (float)(t / (double)ncl);
-  }
-  __syncthreads();
-  float mk[8];
-  for (int k = 0; k < 8; ++k) mk[k] = mean[k];
   double acc[NP];
   for (int j = 0; j < NP; ++j) acc[j] = 0.0;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < ncl; i += (size_t)gridDim.x * blockDim.x) {
-    const size_t c = (size_t)b * ncl + i;
-    const size_t sl = (c / ((size_t)nx * ny)) * nx * ny;  // z-slice
-    const int x = (int)(c % nx), y = (int)((c / nx) % ny);
-    const size_t xp = sl + (size_t)y * nx + (x + 1 == nx ? 0 : x + 1), xm = sl + (size_t)y * nx + (x == 0 ? nx - 1 : x - 1);
-    const size_t yp = sl + (size_t)(y + 1 == ny ? 0 : y + 1) * nx + x, ym = sl + (size_t)(y == 0 ? ny - 1 : y - 1) * nx + x;
+  // 32-bit cell arithmetic: a corrected context has at most 2^28 cells
+  const unsigned nxy = (unsigned)nx * (unsigned)ny, N32 = nxy * (unsigned)nz, ncl = N32 / (unsigned)nb;
+  for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < ncl; i += gridDim.x * blockDim.x) {
+    const unsigned c = (unsigned)b * ncl + i;
+    const unsigned z = c / nxy, r = c - z * nxy, y = r / (unsigned)nx, x = r - y * (unsigned)nx;
+    const unsigned sl = z * nxy;  // z-slice
+    const unsigned xp = sl + y * nx + (x + 1 == (unsigned)nx ? 0 : x + 1), xm = sl + y * nx + (x == 0 ? nx - 1 : x - 1);
+    const unsigned yp = sl + (y + 1 == (unsigned)ny ? 0 : y + 1) * nx + x, ym = sl + (y == 0 ? ny - 1 : y - 1) * nx + x;
     for (int k = 0; k < 8; ++k) {
-      const float v = raw[(size_t)k * N + c] - mk[k];
-      dq[(size_t)k * N + c] = v;
-      const double d = v;
+      const double d = raw[k * N32 + c];
       acc[k] += d * d;
-      if (!(d - d == 0.0)) acc[10] += 1.0;
+      acc[8 + k] += d;
+      if (!(d - d == 0.0)) acc[18] += 1.0;
     }
-    const float* Bx = X + 5 * N;
-    const float* By = X + 6 * N;
-    const float* rBx = raw + 5 * N;
-    const float* rBy = raw + 6 * N;
+    const float* Bx = X + 5 * N32;
+    const float* By = X + 6 * N32;
+    const float* rBx = raw + 5 * N32;
+    const float* rBy = raw + 6 * N32;
     double dv = 0.5 * ((double)Bx[xp] - Bx[xm]) + 0.5 * ((double)By[yp] - By[ym]);
-    double ddv = 0.5 * ((double)(rBx[xp] - mk[5]) - (double)(rBx[xm] - mk[5])) +
-                 0.5 * ((double)(rBy[yp] - mk[6]) - (double)(rBy[ym] - mk[6]));
+    double ddv = 0.5 * ((double)rBx[xp] - rBx[xm]) + 0.5 * ((double)rBy[yp] - rBy[ym]);
     double b2 = (double)Bx[c] * Bx[c] + (double)By[c] * By[c];
     if constexpr (D == 3) {
-      const size_t nxy = (size_t)nx * ny, r = c - sl, z = c / nxy;
-      const size_t zp = (z + 1 == (size_t)nz ? 0 : z + 1) * nxy + r, zm = (z == 0 ? nz - 1 : z - 1) * nxy + r;
-      const float* Bz = X + 7 * N;
-      const float* rBz = raw + 7 * N;
+      const unsigned zp = (z + 1 == (unsigned)nz ? 0 : z + 1) * nxy + r, zm = (z == 0 ? nz - 1 : z - 1) * nxy + r;
+      const float* Bz = X + 7 * N32;
+      const float* rBz = raw + 7 * N32;
       dv += 0.5 * ((double)Bz[zp] - Bz[zm]);
-      ddv += 0.5 * ((double)(rBz[zp] - mk[7]) - (double)(rBz[zm] - mk[7]));
+      ddv += 0.5 * ((double)rBz[zp] - rBz[zm]);
       b2 += (double)Bz[c] * Bz[c];
     }
     const double dv2 = dv + ddv;
-    acc[8] += dv * dv;
-    acc[9] += dv2 * dv2;
-    acc[11] += b2;
+    acc[16] += dv * dv;
+    acc[17] += dv2 * dv2;
+    acc[19] += b2;
   }
   for (int j = 0; j < NP; ++j) {
-    for (int off = 32; off > 0; off >>= 1) acc[j] += __shfl_xor(acc[j], off);
+    acc[j] = wave_sum(acc[j]);
     if (lane == 0) sh[wv][j] = acc[j];
   }
   __syncthreads();
@@ -641,22 +618,88 @@ __global__ __launch_bounds__(kGateThreads) void k_gate_partials(const float* __r
   }
 }
 
-// One wavefront: lane l sums the partials of blocks l, l + 64, ...; a shuffle tree
-// combines the lanes, and lane 0 decides.
-__global__ __launch_bounds__(64) void k_gate_final(const double* __restrict__ partial, int nblk, GateBounds gb,
-                                                   int* __restrict__ flag, long long* __restrict__ fallbacks) {
-  constexpr int NP = 12;
-  double t[NP];
-  for (int j = 0; j < NP; ++j) t[j] = 0.0;
-  for (int b = (int)threadIdx.x; b < nblk; b += 64)
-    for (int j = 0; j < NP; ++j) t[j] += partial[(size_t)b * NP + j];
-  for (int j = 0; j < NP; ++j)
-    for (int off = 32; off > 0; off >>= 1) t[j] += __shfl_xor(t[j], off);
+// The decision and the projection's means, one workgroup.  partial: nb lattices x gbpl
+// workgroups x kGateNP sums (k_gate_partials); ncl cells per lattice.
+// With project: mean m[b][k] = (float)(sum over lattice b of r_k / ncl), written to the
+// control block ctl (layout of launch_sweep_inj) -- for one lattice from the batch-wide
+// sums; for a batch the (lattice, channel) pairs are taken by groups of G threads (a
+// power of two, fixed by nb), each thread summing the lattice's workgroup sums w = r,
+// r + G, ... in that order, a lane-shuffle tree over the group; without it the means
+// stay 0.  The correction passes when it is finite, every
+// ||dQ_k||_2 <= gb->corr[k] (||dQ_k||^2 = sum r_k^2 + sum over lattices of
+// (ncl m^2 - 2 m sum r_k)) and ||divc(X + dQ)||_2 <= (1 + gb->divb_rel) ||divc(X)||_2 +
+// gb->divb_abs ||B(X)||_2: ctl[0] = 1, else ctl[0] = 0 and *fallbacks += 1.  Batch-wide
+// sums: thread t takes workgroups t, t + 256, ... in that order, wave_sum per
+// wavefront, thread 0 adds the four wavefronts in order.  (A separate launch: deciding
+// in the last workgroup of the partials kernel needs a device-scope release fence in
+// every workgroup, which on this chip writes back L2; measured at 2D 256^2 and 3D 64^3,
+// that one kernel took longer than the two.)
+constexpr int kFinalThreads = 256;
+__global__ __launch_bounds__(kFinalThreads) void k_gate_final(const double* __restrict__ partial, int nb, int gbpl,
+                                                              double ncl, int project,
+                                                              const GateBounds* __restrict__ gb,
+                                                              int* __restrict__ ctl,
+                                                              long long* __restrict__ fallbacks) {
+  constexpr int NP = kGateNP, NR = NP + 8;  // the sums, then the projection's terms
+  __shared__ double sh[kFinalThreads / 64][NR];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nblk = nb * gbpl;
+  double t[NR];
+  for (int j = 0; j < NR; ++j) t[j] = 0.0;
+#pragma unroll 4
+  for (int w = (int)threadIdx.x; w < nblk; w += kFinalThreads)
+    for (int j = 0; j < NP; ++j) t[j] += partial[(size_t)w * NP + j];
+  // per-lattice sums of a batch (one lattice: the batch-wide sums serve, below)
+  if (project && nb > 1) {
+    const int P = 8 * nb;
+    int G = 1;
+    while (G < 32 && 2 * G * P <= kFinalThreads) G *= 2;
+    const int per = kFinalThreads / G, g = (int)threadIdx.x / G, r = (int)threadIdx.x % G;
+    for (int p0 = 0; p0 < P; p0 += per) {  // the same trip count in every thread
+      const int p = p0 + g;
+      double s1 = 0.0;
+      if (p < P) {
+        const double* q = partial + (size_t)(p >> 3) * gbpl * NP + 8 + (p & 7);
+#pragma unroll 8
+        for (int w = r; w < gbpl; w += G) s1 += q[(size_t)w * NP];
+      }
+      for (int off = G / 2; off > 0; off >>= 1) s1 += __shfl_xor(s1, off);
+      if (p < P && r == 0) {
+        const float m = (float)(s1 / ncl);
+        ctl[1 + p] = __float_as_int(m);
+        const double md = m, d = ncl * md * md - 2.0 * md * s1;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)  // constant indices keep t in registers
+          if (k == (p & 7)) t[NP + k] += d;
+      }
+    }
+  }
+  const bool batch_terms = project && nb > 1;
+#pragma unroll
+  for (int j = 0; j < NR; ++j)
+    if (j < NP || batch_terms) {
+      t[j] = wave_sum(t[j]);
+      if (lane == 0) sh[wv][j] = t[j];
+    }
+  __syncthreads();
   if (threadIdx.x != 0) return;
-  bool ok = t[10] == 0.0;
-  for (int k = 0; k < 8; ++k) ok = ok && sqrt(t[k]) <= gb.corr[k];
-  ok = ok && sqrt(t[9]) <= (1.0 + gb.divb_rel) * sqrt(t[8]) + gb.divb_abs * sqrt(t[11]);
-  *flag = ok ? 1 : 0;
+#pragma unroll
+  for (int j = 0; j < NR; ++j)
+    if (j < NP || batch_terms) {
+      t[j] = sh[0][j];
+      for (int w = 1; w < kFinalThreads / 64; ++w) t[j] += sh[w][j];
+    }
+  if (project && nb == 1)
+    for (int k = 0; k < 8; ++k) {
+      const float m = (float)(t[8 + k] / ncl);
+      ctl[1 + k] = __float_as_int(m);
+      const double md = m;
+      t[NP + k] = ncl * md * md - 2.0 * md * t[8 + k];
+    }
+  bool ok = t[18] == 0.0;
+  for (int k = 0; k < 8; ++k) ok = ok && sqrt(fmax(t[k] + t[NP + k], 0.0)) <= gb->corr[k];
+  ok = ok && sqrt(t[17]) <= (1.0 + gb->divb_rel) * sqrt(t[16]) + gb->divb_abs * sqrt(t[19]);
+  ctl[0] = ok ? 1 : 0;
   if (!ok) *fallbacks += 1;
 }
 
@@ -692,6 +735,27 @@ struct vlbm_nn {
   double* d_part_loss = nullptr;
   double* d_loss = nullptr;
   int bw_blocks = 0;
+  long long ws_gen = 0;  // incremented whenever the activation workspace is reallocated
+  // corrected stepping: buffers kept from call to call (grown on demand), the stream and
+  // event the steps run with, and the instantiated graph of a pair of steps together with
+  // what it was captured for (context identity and generation, workspace generation,
+  // parity at its start, projection on or off)
+  struct Corr {
+    size_t n = 0;
+    int gblk = 0, nbatch = 0;
+    float* X = nullptr;
+    float* raw[2] = {nullptr, nullptr};  // the network's output, ping-pong
+    int* ctl = nullptr;                  // two control blocks of 1 + 8 nbatch words
+    long long* fb = nullptr;
+    double* gpart = nullptr;
+    GateBounds* gb = nullptr;
+    GateBounds gb_host{};
+    hipStream_t cs = nullptr;
+    hipEvent_t ev = nullptr;
+    hipGraphExec_t exec = nullptr;
+    long long uid = -1, gen = -1, ws_gen = -1;
+    int par = -1, project = -1;
+  } corr;
   std::string err;
 };
 
@@ -725,13 +789,12 @@ size_t packed_elems(int cin, int cout, int nzt) { return (size_t)nzt * ksteps(ci
 // S slices of D-slice lattices (D = 1 for 2D lattices); nzt = 1 (3x3) or 3 (3x3x3)
 hipError_t launch_conv(int cin, int cout, int mode, int nzt, const bf16_t* act, const bf16_t* wpack,
                        const float* bias, int S, int D, int H, int W, bf16_t* out_act, float* out_z,
-                       const float* zprev, const float* oscale, const float* oshift, hipStream_t s,
-                       double* tsum = nullptr) {
+                       const float* zprev, const float* oscale, const float* oshift, hipStream_t s) {
   const dim3 grd(W / TILE, H / TILE, S), blk(kConvThreads);
 #define CONV_CASE(CI, CO, M, Z)                                                                          \
   if (cin == CI && cout == CO && mode == M && nzt == Z) {                                               \
     hipLaunchKernelGGL((k_conv<CI, CO, M, Z>), grd, blk, 0, s, act, wpack, bias, D, H, W, out_act, out_z, \
-                       zprev, oscale, oshift, tsum);                                                   \
+                       zprev, oscale, oshift);                                                         \
     return hipGetLastError();                                                                          \
   }
 #define CONV_CASES(Z)             \
@@ -803,6 +866,7 @@ vlbm_status ensure_workspace(vlbm_nn* nn, size_t positions) {
   for (int j = 0; j < 2; ++j)
     if (nn->d_dz[j]) (void)hipFree(nn->d_dz[j]), nn->d_dz[j] = nullptr;
   nn->ws_positions = 0;
+  ++nn->ws_gen;
   NN_HIP(nn, hipMalloc(&nn->d_act[0], positions * nn->cin * sizeof(bf16_t)));
   for (int l = 0; l < nn->layers; ++l) {
     NN_HIP(nn, hipMalloc(&nn->d_act[l + 1], positions * nn->co[l] * sizeof(bf16_t)));
@@ -816,10 +880,9 @@ vlbm_status ensure_workspace(vlbm_nn* nn, size_t positions) {
 
 // forward pass; mode_train keeps the pre-activations.  Writes nn->d_y (NCHW FP32),
 // scaled by oscale/oshift.
-// X == NULL: the first layer's input is already in nn->d_act[0].  tsum != NULL: the
-// last layer also writes its per-channel tile sums there (k_conv).
+// X == NULL: the first layer's input is already in nn->d_act[0].
 vlbm_status forward(vlbm_nn* nn, const float* X, int B, int nx, int ny, int nz, bool train, const float* oscale,
-                    const float* oshift, float* yout, hipStream_t s, double* tsum = nullptr) {
+                    const float* oshift, float* yout, hipStream_t s) {
   const int S = B * nz;  // slices
   const size_t P = (size_t)S * nx * ny;
   vlbm_status st = ensure_workspace(nn, P);
@@ -835,9 +898,65 @@ vlbm_status forward(vlbm_nn* nn, const float* X, int B, int nx, int ny, int nz, 
     NN_HIP(nn, launch_conv(nn->ci[l], nn->co[l], last ? MODE_LAST : MODE_HIDDEN, nn->nzt, nn->d_act[l],
                            nn->d_wf[l], nn->d_param + nn->boff[l], S, nz, ny, nx,
                            last ? nullptr : nn->d_act[l + 1], last ? yout : (train ? nn->d_z[l] : nullptr),
-                           nullptr, oscale, oshift, s, last ? tsum : nullptr));
+                           nullptr, oscale, oshift, s));
   }
   return VLBM_OK;
+}
+
+// The corrected step's persistent state: its graph (drop_graph), and with all = true
+// also its buffers, event and stream.
+void corr_release(vlbm_nn* nn, bool all) {
+  auto& q = nn->corr;
+  if (q.exec) (void)hipGraphExecDestroy(q.exec);
+  q.exec = nullptr;
+  q.uid = -1;
+  if (!all) return;
+  void* bufs[] = {q.X, q.raw[0], q.raw[1], q.ctl, q.fb, q.gpart, q.gb};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  q.X = q.raw[0] = q.raw[1] = nullptr;
+  q.ctl = nullptr;
+  q.fb = nullptr;
+  q.gpart = nullptr;
+  q.gb = nullptr;
+  q.n = 0;
+  q.gblk = q.nbatch = 0;
+  if (q.ev) (void)hipEventDestroy(q.ev);
+  if (q.cs) (void)hipStreamDestroy(q.cs);
+  q.ev = nullptr;
+  q.cs = nullptr;
+}
+
+// Buffers for N cells, gblk gate workgroups and nbatch lattices; the stream and event
+// on first use.  Growing the buffers drops the graph (it holds their addresses).
+hipError_t corr_reserve(vlbm_nn* nn, size_t N, int gblk, int nbatch) {
+  auto& q = nn->corr;
+  hipError_t e = hipSuccess;
+  if (!q.cs) e = hipStreamCreateWithFlags(&q.cs, hipStreamNonBlocking);
+  if (e == hipSuccess && !q.ev) e = hipEventCreateWithFlags(&q.ev, hipEventDisableTiming);
+  if (e != hipSuccess || (N <= q.n && gblk <= q.gblk && nbatch <= q.nbatch && q.X)) return e;
+  hipStream_t cs = q.cs;
+  hipEvent_t ev = q.ev;
+  q.cs = nullptr;
+  q.ev = nullptr;
+  corr_release(nn, true);  // keeps the stream and event (taken out above)
+  q.cs = cs;
+  q.ev = ev;
+  e = hipMalloc(&q.X, 8 * N * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&q.raw[0], 8 * N * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&q.raw[1], 8 * N * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&q.ctl, 2 * (1 + 8 * (size_t)nbatch) * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&q.fb, sizeof(long long));
+  if (e == hipSuccess) e = hipMalloc(&q.gpart, (size_t)gblk * kGateNP * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&q.gb, sizeof(GateBounds));
+  if (e != hipSuccess) {
+    corr_release(nn, true);
+    return e;
+  }
+  q.n = N;
+  q.gblk = gblk;
+  q.nbatch = nbatch;
+  return hipSuccess;
 }
 
 }  // namespace
@@ -935,6 +1054,7 @@ void vlbm_nn_destroy(vlbm_nn* nn) {
     if (nn->d_dz[j]) (void)hipFree(nn->d_dz[j]);
   if (nn->d_part_loss) (void)hipFree(nn->d_part_loss);
   if (nn->d_loss) (void)hipFree(nn->d_loss);
+  corr_release(nn, true);
   delete nn;
 }
 
@@ -1094,12 +1214,12 @@ bool correctable(const vlbm_ctx* c) {
 
 // The launchers below index by storage * 2 + (dimension - 2): the storage codes of
 // vlbm.h and of the kernels agree.
-void launch_inject(const vlbm_ctx* c, int par, const float* dq, const int* flag, hipStream_t s) {
+void launch_inject(const vlbm_ctx* c, int par, const float* dq, const int* ctl, hipStream_t s) {
   const dim3 cgrid((unsigned)(((size_t)c->N + 255) / 256)), cblk(256);
   switch (c->p.storage * 2 + (c->D - 2)) {
 #define INJ_CASE(ST, D)                                                                                   \
   case ST * 2 + (D - 2):                                                                                  \
-    hipLaunchKernelGGL((k_inject<ST, D>), cgrid, cblk, 0, s, c->g, c->cd, par, dq, flag, c->ph.wi);       \
+    hipLaunchKernelGGL((k_inject<ST, D>), cgrid, cblk, 0, s, c->g, c->cd, par, dq, ctl, c->ph.wi);        \
     break;
     INJ_CASE(vlbm::ST_F64, 2) INJ_CASE(vlbm::ST_F64, 3) INJ_CASE(vlbm::ST_F32, 2) INJ_CASE(vlbm::ST_F32, 3)
     INJ_CASE(vlbm::ST_F16, 2) INJ_CASE(vlbm::ST_F16, 3) INJ_CASE(vlbm::ST_BF16, 2) INJ_CASE(vlbm::ST_BF16, 3)
@@ -1144,82 +1264,56 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
   gb.divb_abs = bound_divb_abs;
   const size_t N = (size_t)c->N;
   hipStream_t s = c->stream;
-  float *X = nullptr, *dq[2] = {nullptr, nullptr};
-  int* flag = nullptr;  // flag[0..1] ping-pong
-  long long* fb = nullptr;
-  double* gpart = nullptr;
-  float* raw = nullptr;     // the network's output before the projection
-  double* ctsum = nullptr;  // its per-channel tile sums
-  // cells per lattice (the projection's unit)
-  // cells per lattice, conv tiles (16 x 16 cells of one slice) in all and per lattice
-  const size_t ncl = N / (size_t)nbatch, ntile = N / (TILE * TILE);
-  const int ntl = (int)(ntile / (size_t)nbatch);
-  hipStream_t cs = nullptr;  // the loop runs on its own stream, ordered after and before s
-  hipEvent_t ev = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  const size_t ncl = N / (size_t)nbatch;  // cells per lattice (the projection's unit)
   // gate workgroups per lattice, about 1024 in all
   const int gbpl = (int)std::max<size_t>(
       1, std::min<size_t>((ncl + kGateThreads - 1) / kGateThreads, std::max<size_t>(1, 1024 / (size_t)nbatch)));
   const int gblk = gbpl * nbatch;
-  auto cleanup = [&]() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (X) (void)hipFree(X);
-    for (int j = 0; j < 2; ++j)
-      if (dq[j]) (void)hipFree(dq[j]);
-    if (flag) (void)hipFree(flag);
-    if (fb) (void)hipFree(fb);
-    if (gpart) (void)hipFree(gpart);
-    if (raw) (void)hipFree(raw);
-    if (ctsum) (void)hipFree(ctsum);
-    if (ev) (void)hipEventDestroy(ev);
-    if (cs) (void)hipStreamDestroy(cs);
-  };
-  hipError_t e = hipMalloc(&X, 8 * N * sizeof(float));
-  if (e == hipSuccess) e = hipMalloc(&dq[0], 8 * N * sizeof(float));
-  if (e == hipSuccess) e = hipMalloc(&dq[1], 8 * N * sizeof(float));
-  if (e == hipSuccess) e = hipMalloc(&flag, 2 * sizeof(int));
-  if (e == hipSuccess) e = hipMalloc(&fb, sizeof(long long));
-  if (e == hipSuccess) e = hipMalloc(&gpart, (size_t)gblk * 12 * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc(&raw, 8 * N * sizeof(float));
-  if (e == hipSuccess) e = hipMalloc(&ctsum, 8 * ntile * sizeof(double));
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventRecord(ev, s);
-  if (e == hipSuccess) e = hipStreamWaitEvent(cs, ev, 0);
-  if (e == hipSuccess) e = hipMemsetAsync(flag, 0, 2 * sizeof(int), cs);
-  if (e == hipSuccess) e = hipMemsetAsync(fb, 0, sizeof(long long), cs);
+  // the network's workspace first: its (re)allocation must not happen under capture
+  st = ensure_workspace(nn, N);
+  if (st != VLBM_OK) return st;
+  hipError_t e = corr_reserve(nn, N, gblk, nbatch);
+  if (e != hipSuccess)
+    return nfail(nn, e == hipErrorOutOfMemory ? VLBM_ERR_OOM : VLBM_ERR_HIP, "corrected step: %s",
+                 hipGetErrorString(e));
+  auto& q = nn->corr;
+  hipStream_t cs = q.cs;  // the steps run on the handle's own stream, ordered after s
+  q.gb_host = gb;         // lives in the handle: the copy below may read it after returning
+  e = hipEventRecord(q.ev, s);
+  if (e == hipSuccess) e = hipStreamWaitEvent(cs, q.ev, 0);
+  if (e == hipSuccess) e = hipMemcpyAsync(q.gb, &q.gb_host, sizeof(GateBounds), hipMemcpyHostToDevice, cs);
+  // both control blocks cleared: nothing pending, means 0
+  int* ctl[2] = {q.ctl, q.ctl + 1 + 8 * nbatch};
+  if (e == hipSuccess) e = hipMemsetAsync(q.ctl, 0, 2 * (1 + 8 * (size_t)nbatch) * sizeof(int), cs);
+  if (e == hipSuccess) e = hipMemsetAsync(q.fb, 0, sizeof(long long), cs);
   vlbm::Launch L = c->L;
   L.stream = cs;
-  int cur = 0;  // dq[cur], flag[cur]: the pending correction (not yet in the populations)
+  int cur = 0;  // raw[cur], ctl[cur]: the pending correction (not yet in the populations)
   // one corrected step: the sweep injecting the pending correction (it also writes the
-  // moments it collides with), the network on those moments, projection and gate of
-  // its correction (pending until the next sweep).  Kernels only, so that it can be
-  // captured.
+  // moments it collides with), the network on those moments, the gate of its
+  // correction and its projection's means (pending until the next sweep).  Kernels
+  // only, so that it can be captured.
   auto step = [&]() -> vlbm_status {
     const int par = (int)(c->step & 1);
-    // the network's workspace is sized by the first (eager) step, never under capture
-    vlbm_status fs = ensure_workspace(nn, N);
-    if (fs != VLBM_OK) return fs;
     // the sweep injects the pending correction and writes the moments it collides with
     // (this step's network input, X and its standardised BF16 form); the network's
     // correction for them is injected by the next sweep
-    const vlbm::MomentsOut mo{X, nn->d_act[0], nn->d_norm + 0, nn->d_norm + 8};
-    e = vlbm::launch_sweep_inj(L, c->g, c->ph, c->cd, par, dq[cur], flag + cur, mo);
+    const vlbm::MomentsOut mo{q.X, nn->d_act[0], nn->d_norm + 0, nn->d_norm + 8};
+    e = vlbm::launch_sweep_inj(L, c->g, c->ph, c->cd, par, q.raw[cur], ctl[cur], mo);
     if (e != hipSuccess) return VLBM_ERR_HIP;
-    fs = forward(nn, nullptr, nbatch, c->p.nx, c->p.ny, nzl, false, nn->d_norm + 24, nn->d_norm + 16, raw, cs,
-                 project_totals ? ctsum : nullptr);
+    vlbm_status fs = forward(nn, nullptr, nbatch, c->p.nx, c->p.ny, nzl, false, nn->d_norm + 24, nn->d_norm + 16,
+                             q.raw[1 - cur], cs);
     if (fs != VLBM_OK) return fs;
-    // projection (when asked for) and gate statistics; the projected correction lands in dq
+    // gate statistics, then the decision and (when asked for) the projection's means
     const dim3 ggrid((unsigned)gbpl, (unsigned)nbatch);
     if (c->D == 2)
-      hipLaunchKernelGGL(k_gate_partials<2>, ggrid, dim3(kGateThreads), 0, cs, X, raw, dq[1 - cur],
-                         project_totals ? ctsum : nullptr, ntl, c->p.nx, c->p.ny, c->p.nz, gpart);
+      hipLaunchKernelGGL(k_gate_partials<2>, ggrid, dim3(kGateThreads), 0, cs, q.X, q.raw[1 - cur], c->p.nx,
+                         c->p.ny, c->p.nz, q.gpart);
     else
-      hipLaunchKernelGGL(k_gate_partials<3>, ggrid, dim3(kGateThreads), 0, cs, X, raw, dq[1 - cur],
-                         project_totals ? ctsum : nullptr, ntl, c->p.nx, c->p.ny, c->p.nz, gpart);
-    hipLaunchKernelGGL(k_gate_final, dim3(1), dim3(64), 0, cs, gpart, gblk, gb, flag + (1 - cur), fb);
+      hipLaunchKernelGGL(k_gate_partials<3>, ggrid, dim3(kGateThreads), 0, cs, q.X, q.raw[1 - cur], c->p.nx,
+                         c->p.ny, c->p.nz, q.gpart);
+    hipLaunchKernelGGL(k_gate_final, dim3(1), dim3(kFinalThreads), 0, cs, q.gpart, nbatch, gbpl, (double)ncl,
+                       project_totals ? 1 : 0, q.gb, ctl[1 - cur], q.fb);
     e = hipGetLastError();
     if (e != hipSuccess) return VLBM_ERR_HIP;
     ++c->step;
@@ -1227,16 +1321,22 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
     return VLBM_OK;
   };
   int32_t done = 0;
-  // two steps eagerly (they also size the network's workspace), then pairs of steps
-  // replayed from a captured graph: a pair returns parity and ping-pong slot to where
-  // they started, so one captured pair serves every later pair
+  // two steps eagerly, then pairs of steps replayed from a graph: a pair returns parity
+  // and ping-pong slot to where they started, so one captured pair serves every later
+  // pair, in this call and in later calls on the same context while nothing it took by
+  // value or by address has changed
   for (; done < n && done < 2 && e == hipSuccess; ++done) {
     st = step();
     if (st != VLBM_OK) break;
   }
-  if (st == VLBM_OK && e == hipSuccess && n - done >= 4) {
+  const int par0 = (int)(c->step & 1);
+  const bool cached = q.exec && q.uid == c->uid && q.gen == c->gen && q.ws_gen == nn->ws_gen &&
+                      q.par == par0 && q.project == (project_totals ? 1 : 0);
+  if (st == VLBM_OK && e == hipSuccess && !cached && n - done >= 4) {
+    corr_release(nn, false);
     const long long step0 = c->step;
     const int cur0 = cur;
+    hipGraph_t graph = nullptr;
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
       const vlbm_status s1 = step();
       const vlbm_status s2 = s1 == VLBM_OK ? step() : s1;
@@ -1244,32 +1344,39 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
       c->step = step0;  // the captured steps have not run
       cur = cur0;
       if (s2 == VLBM_OK && ce == hipSuccess && graph &&
-          hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
-        exec = nullptr;
+          hipGraphInstantiate(&q.exec, graph, nullptr, nullptr, 0) != hipSuccess)
+        q.exec = nullptr;
+      if (graph) (void)hipGraphDestroy(graph);
       (void)hipGetLastError();  // a failed capture leaves the eager path below
       e = hipSuccess;
-    }
-    if (exec)
-      for (; n - done >= 2; done += 2) {
-        e = hipGraphLaunch(exec, cs);
-        if (e != hipSuccess) break;
-        c->step += 2;
+      if (q.exec) {
+        q.uid = c->uid;
+        q.gen = c->gen;
+        q.ws_gen = nn->ws_gen;
+        q.par = par0;
+        q.project = project_totals ? 1 : 0;
       }
+    }
   }
+  const bool use_graph = q.exec && q.uid == c->uid && q.gen == c->gen && q.ws_gen == nn->ws_gen &&
+                         q.par == par0 && q.project == (project_totals ? 1 : 0);
+  if (st == VLBM_OK && e == hipSuccess && use_graph)
+    for (; n - done >= 2; done += 2) {
+      e = hipGraphLaunch(q.exec, cs);
+      if (e != hipSuccess) break;
+      c->step += 2;
+    }
   for (; st == VLBM_OK && done < n && e == hipSuccess; ++done) st = step();
-  if (st != VLBM_OK && e == hipSuccess) {
-    cleanup();
-    return st;
-  }
-  if (e == hipSuccess && n > 0) {
+  if (st == VLBM_OK && e == hipSuccess && n > 0) {
     // the last accepted correction goes into the populations
-    launch_inject(c, (int)(c->step & 1), dq[cur], flag + cur, cs);
+    launch_inject(c, (int)(c->step & 1), q.raw[cur], ctl[cur], cs);
     e = hipGetLastError();
   }
   long long nfb = 0;
-  if (e == hipSuccess) e = hipMemcpyAsync(&nfb, fb, sizeof nfb, hipMemcpyDeviceToHost, cs);
-  if (e == hipSuccess) e = hipStreamSynchronize(cs);
-  cleanup();
+  const hipError_t ce = hipMemcpyAsync(&nfb, q.fb, sizeof nfb, hipMemcpyDeviceToHost, cs);
+  const hipError_t se = hipStreamSynchronize(cs);  // also when a step failed: nothing stays in flight
+  if (e == hipSuccess) e = ce != hipSuccess ? ce : se;
+  if (st != VLBM_OK) return st;
   if (e != hipSuccess)
     return nfail(nn, e == hipErrorOutOfMemory ? VLBM_ERR_OOM : VLBM_ERR_HIP, "corrected step: %s", hipGetErrorString(e));
   if (n_fallback) *n_fallback = nfb;

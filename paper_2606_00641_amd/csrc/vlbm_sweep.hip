@@ -74,8 +74,9 @@ struct XchLds<T, K, false> {};
 // rho u and B.  In the AA layout that population belongs at slot i of cell x + e_i
 // after a parity-0 step and at slot opposite(i) of x after a parity-1 step, places
 // no other thread writes because the solid cell runs no update.
-// INJ: before the collision add *dqflag * w_i dq[k][c] to f_{k,i} (the pending learned
-// coarse correction, which shifts the zeroth moments by dq); dq is FP32 [K][N].
+// INJ: before the collision add w_i (dq[k][c] - mean[b][k]) to f_{k,i} when dqctl[0] is
+// nonzero (the pending learned coarse correction, projected, which shifts the zeroth
+// moments; dq FP32 [K][N], control block dqctl as launch_sweep_inj describes).
 // Occupancy: the FP32 26-variable sweep needs 256 VGPRs + 26 AGPRs at parity 0,
 // one wavefront per SIMD; bounding it to two per SIMD costs 48 B of scratch per lane
 // and was measured 4-5 % faster (at parity 1 the bound spills more and is slower).
@@ -83,7 +84,7 @@ template <int ST, int D, int MODEL, int PAR, int BODY = 0, int COLL = 0, bool IN
           bool FX = false, int SRC = 0>
 __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COLL == 0) ? 2 : 1) void k_sweep(
     const Grid g, const Phys ph, const Codec cd, const Body bd, const float* __restrict__ dq,
-    const int* __restrict__ dqflag, const Inflow in, const MomentsOut mo) {
+    const int* __restrict__ dqctl, const Inflow in, const MomentsOut mo) {
   using S = Store<ST>;
   using T = typename S::T;
   using R = typename S::R;
@@ -255,13 +256,14 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
   }
 
   if constexpr (INJ) {
-    if (*dqflag) {
+    if (dqctl[0]) {
       const size_t N = (size_t)g.nx * g.ny * g.nz;
       const R wi = R(ph.wi);
       const R w0 = rest_weight<R, D>(wi);
+      const int* __restrict__ mean = dqctl + 1 + 8 * inj_lattice(D, z);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const R d = (R)dq[(size_t)k * N + c];
+        const R d = (R)(dq[(size_t)k * N + c] - __int_as_float(mean[k]));
 #pragma unroll
         for (int i = 0; i < NQ; ++i) f[k][i] += (i == 0 ? w0 : wi) * d;
       }
@@ -511,13 +513,13 @@ hipError_t sweep_t(const Launch& L, const Grid& g, const Phys& ph, const Codec& 
 
 template <int ST>
 hipError_t sweep_inj_t(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
-                       const float* dq, const int* flag, const MomentsOut& mo) {
+                       const float* dq, const int* ctl, const MomentsOut& mo) {
   if (L.dim == 2)
     launch_k<ST, 2, 0, 0, true>(L, cell_grid(g, L.block_x), parity, 0, lane_exchange(g, L.block_x, 0), false, g, ph,
-                                cd, Body{}, dq, flag, Inflow{}, mo);
+                                cd, Body{}, dq, ctl, Inflow{}, mo);
   else
     launch_k<ST, 3, 0, 0, true>(L, cell_grid(g, L.block_x), parity, 0, lane_exchange(g, L.block_x, 0), false, g, ph,
-                                cd, Body{}, dq, flag, Inflow{}, mo);
+                                cd, Body{}, dq, ctl, Inflow{}, mo);
   return hipGetLastError();
 }
 
@@ -558,14 +560,14 @@ hipError_t launch_sweep(const Launch& L, const Grid& g, const Phys& ph, const Co
 }
 
 hipError_t launch_sweep_inj(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
-                            const float* dq, const int* flag, const MomentsOut& mo) {
+                            const float* dq, const int* ctl, const MomentsOut& mo) {
   if ((L.dim != 2 && L.dim != 3) || L.model != 0 || ph.collision != 0) return hipErrorInvalidValue;
   if (L.dim == 3 && (g.bc[0] || g.bc[2] || g.bc[4] || g.mask)) return hipErrorInvalidValue;  // periodic, no body
   switch (L.storage) {
-    case ST_F64: return sweep_inj_t<ST_F64>(L, g, ph, cd, parity, dq, flag, mo);
-    case ST_F32: return sweep_inj_t<ST_F32>(L, g, ph, cd, parity, dq, flag, mo);
-    case ST_F16: return sweep_inj_t<ST_F16>(L, g, ph, cd, parity, dq, flag, mo);
-    case ST_BF16: return sweep_inj_t<ST_BF16>(L, g, ph, cd, parity, dq, flag, mo);
+    case ST_F64: return sweep_inj_t<ST_F64>(L, g, ph, cd, parity, dq, ctl, mo);
+    case ST_F32: return sweep_inj_t<ST_F32>(L, g, ph, cd, parity, dq, ctl, mo);
+    case ST_F16: return sweep_inj_t<ST_F16>(L, g, ph, cd, parity, dq, ctl, mo);
+    case ST_BF16: return sweep_inj_t<ST_BF16>(L, g, ph, cd, parity, dq, ctl, mo);
     default: return hipErrorInvalidValue;
   }
 }

@@ -487,6 +487,73 @@ def test_replayed_steps_equal_single_steps(env):
     assert np.abs(qa - qb).max() <= 1e-5 * np.abs(qb).max()
 
 
+def _moderate_net(env, seed):
+    rng = np.random.default_rng(seed)
+    return make_net(env, 4, [(W * 0.05, b * 0.01) for W, b in rand_params(rng, 4)])
+
+
+def test_graph_kept_between_calls_equals_fresh_handles(env):
+    """The handle keeps the captured pair of steps from call to call.  Calls 2 and 3 on
+    one handle (its graph replayed, also after another context used the handle in
+    between, which makes it capture again) give bitwise the populations of the same
+    calls made each with a fresh handle of the same weights (fresh capture)."""
+    torch, vlbm, nn = env
+    bound = np.full(8, 0.02)
+    a = coarse_sim(env, "f32", n=32, seed=4)
+    other = coarse_sim(env, "f32", n=32, seed=5)
+    ref = coarse_sim(env, "f32", n=32, seed=4)
+    net = _moderate_net(env, 21)
+    nfa = nfr = 0
+    for call in range(3):
+        nfa += nn.vlbm_step_corrected(a, net, 8, bound, 0.1, 1e-6)
+        if call == 1:
+            nn.vlbm_step_corrected(other, net, 6, bound, 0.1, 1e-6)
+        nfr += nn.vlbm_step_corrected(ref, _moderate_net(env, 21), 8, bound, 0.1, 1e-6)
+    assert a.vlbm_get_step() == ref.vlbm_get_step() == 24
+    assert nfa == nfr
+    assert np.array_equal(a.vlbm_get_populations()[0], ref.vlbm_get_populations()[0])
+
+
+def test_graph_captured_again_after_reinit(env):
+    """FP16 storage: initialising the context again changes its codec (rest state and
+    scales), which the sweep takes by value; the handle's graph must not be replayed
+    with the old one.  Result bitwise that of a fresh context and handle."""
+    torch, vlbm, nn = env
+    bound = np.full(8, 1e30)
+    a = coarse_sim(env, "f16", n=32, seed=4)
+    net = _moderate_net(env, 22)
+    nn.vlbm_step_corrected(a, net, 8, bound, 10.0, 1.0)
+    q2 = synth.fourier_2d(32, seed=9)
+    q2[0] *= 1.5  # another density level: another rest state
+    a.vlbm_init_fields(q2)
+    nfa = nn.vlbm_step_corrected(a, net, 8, bound, 10.0, 1.0)
+    b = coarse_sim(env, "f16", n=32, seed=4)
+    b.vlbm_init_fields(q2)
+    nfb = nn.vlbm_step_corrected(b, _moderate_net(env, 22), 8, bound, 10.0, 1.0)
+    assert nfa == nfb == 0
+    assert a.vlbm_get_step() == b.vlbm_get_step() == 8
+    assert np.array_equal(a.vlbm_get_populations()[0], b.vlbm_get_populations()[0])
+
+
+def test_gate_bounds_change_under_a_kept_graph(env):
+    """The gate reads its bounds from device memory written at each call, so a graph
+    kept from an earlier call applies the bounds of the current one."""
+    torch, vlbm, nn = env
+    a = coarse_sim(env, "f32", n=32, seed=6)
+    net = _moderate_net(env, 23)
+    assert nn.vlbm_step_corrected(a, net, 8, np.full(8, 1e30), 10.0, 1.0) == 0
+    assert nn.vlbm_step_corrected(a, net, 8, np.zeros(8), 10.0, 1.0) == 8
+    assert nn.vlbm_step_corrected(a, net, 8, np.full(8, 1e30), 10.0, 1.0) == 0
+    # a step with the gate closed is the plain step: compare a closed-gate call with
+    # the plain sweep from the same populations
+    f, par, step = a.vlbm_get_populations()
+    b = coarse_sim(env, "f32", n=32, seed=6)
+    b.vlbm_set_populations(f, par, step)
+    assert nn.vlbm_step_corrected(a, net, 10, np.zeros(8), 10.0, 1.0) == 10
+    b.vlbm_step(10)
+    assert np.array_equal(a.vlbm_get_populations()[0], b.vlbm_get_populations()[0])
+
+
 # --- corrected stepping of a 3D lattice (3x3x3 network) --------------------------
 
 SHAPE3 = (32, 16, 8)  # nx, ny, nz
