@@ -429,6 +429,176 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
   }
 }
 
+// Two cells per lane (FP16/BF16 storage, plain sweep of a periodic lattice without a
+// body): lane l of a workgroup takes cells x0 = 2 (b B + l) and x0 + 1 of its row (B
+// threads per workgroup, 2 B cells), so every plane access moves the 32-bit word of the
+// pair -- the low half is cell x0.  A wavefront instruction that moves 2 bytes per lane
+// runs far below HBM bandwidth on gfx950 (a streaming copy measured about 3 TB/s at 16
+// bits per lane against 5 TB/s at 32).  Each cell is decoded, collided and encoded as
+// in k_sweep (the same arithmetic, so the results are bitwise those of k_sweep).
+// Parity 1 reads f_{+x}(x) from slot(-x) of x - 1 and f_{-x}(x) from slot(+x) of x + 1:
+// a lane loads its own words of those slots, A = slot(-x)[x0, x0 + 1] and
+// W = slot(+x)[x0, x0 + 1], and forms its pairs from the neighbour lanes' words,
+// f_{+x} = (A of lane l - 1).hi : A.lo and f_{-x} = W.hi : (W of lane l + 1).lo; the
+// post-collision f_{+x} pair goes to slot(+x) of x0 + 1, x0 + 2 and the f_{-x} pair to
+// slot(-x) of x0 - 1, x0, so a lane stores at its own word (left lane's f_{+x}).hi :
+// f_{+x}.lo and f_{-x}.hi : (right lane's f_{-x}).lo.  Between wavefronts the edge words
+// go through LDS; at the ends of a workgroup that spans its row they wrap around the
+// row, else the end lanes read the neighbouring workgroup's boundary element, and
+// write the half that belongs to it, with 16-bit accesses (as k_sweep's lane exchange).
+template <int ST, int D, int MODEL, int PAR, int COLL>
+__global__ __launch_bounds__(256) void k_sweep2(const Grid g, const Phys ph, const Codec cd) {
+  static_assert(ST == ST_F16 || ST == ST_BF16, "two cells per lane: 16-bit storage");
+  using S = Store<ST>;
+  using R = typename S::R;
+  using H = typename S::T;
+  constexpr int NQ = 2 * D + 1;
+  constexpr int K = kNVars<MODEL>;
+  __shared__ XchLds<unsigned, K, true> xl;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = (int)(blockDim.x >> 6);
+  const int y = blockIdx.y, z = blockIdx.z;
+  const int x0 = 2 * ((int)blockIdx.x * (int)blockDim.x + t);
+  const bool row = 2 * (int)blockDim.x == g.nx;
+  const unsigned rowc = (unsigned)g.nx * ((unsigned)y + (unsigned)g.ny * (unsigned)z);
+  const unsigned c = rowc + (unsigned)x0;
+  void* const F = g.f;
+  const size_t pb = (size_t)g.stride * sizeof(H);
+  const unsigned co = c * (unsigned)sizeof(H);
+  unsigned np[3], nm[3];
+  if constexpr (PAR == 1) {
+    neighbours<D>(g, x0, y, z, c, np, nm);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      np[a] *= (unsigned)sizeof(H);
+      nm[a] *= (unsigned)sizeof(H);
+    }
+  }
+  // byte offsets of the elements just outside this workgroup's stretch of the row
+  const unsigned xa = (unsigned)(2 * (int)blockIdx.x * (int)blockDim.x), xb = xa + 2 * blockDim.x;
+  const unsigned cl = (rowc + (xa == 0 ? (unsigned)g.nx - 1u : xa - 1u)) * (unsigned)sizeof(H);
+  const unsigned cr = (rowc + (xb == (unsigned)g.nx ? 0u : xb)) * (unsigned)sizeof(H);
+
+  unsigned P[K][NQ];  // the pair's words: low half cell x0, high half x0 + 1
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      if constexpr (PAR == 0) {
+        P[k][i] = ld<unsigned>(F, pb, k * NQ + i, co);
+      } else {
+        // i = 1, 2: this pair's own slot opposite(i), combined with a neighbour lane's below
+        const unsigned src = (i <= 2) ? co : ((i & 1) ? nm[(i - 1) >> 1] : np[(i - 1) >> 1]);
+        P[k][i] = ld<unsigned>(F, pb, k * NQ + opposite(i), src);
+      }
+    }
+  if constexpr (PAR == 1) {
+    if (lane == 63) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) xl.hi[0][w][k] = P[k][1];
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) xl.lo[0][w][k] = P[k][2];
+    }
+    __syncthreads();
+    unsigned el[K], er[K];  // lane 0's left word (its high half used), lane 63's right word (low half)
+    if (w > 0 || row) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) el[k] = xl.hi[0][w > 0 ? w - 1 : nw - 1][k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) el[k] = (unsigned)ld<H>(F, pb, k * NQ + 2, cl) << 16;
+    }
+    if (w < nw - 1 || row) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) er[k] = xl.lo[0][w < nw - 1 ? w + 1 : 0][k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) er[k] = (unsigned)ld<H>(F, pb, k * NQ + 1, cr);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const unsigned left = lane_shift<true>(el[k], P[k][1]), right = lane_shift<false>(er[k], P[k][2]);
+      P[k][1] = __builtin_amdgcn_alignbyte(P[k][1], left, 2);   // left.hi : A.lo
+      P[k][2] = __builtin_amdgcn_alignbyte(right, P[k][2], 2);  // W.hi : right.lo
+    }
+  }
+
+  // the two cells, one after the other; each result replaces the half it came from
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    R f[K][NQ];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) f[k][i] = S::dec((H)(P[k][i] >> (16 * j)), cd, k * NQ + i);
+    R dl;
+    collide<R, D, MODEL, COLL>(f, ph, dl);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) {
+        const unsigned h = (unsigned)S::enc(f[k][i], cd, k * NQ + i);
+        P[k][i] = j == 0 ? (P[k][i] & 0xffff0000u) | h : (P[k][i] & 0xffffu) | (h << 16);
+      }
+  }
+
+  if constexpr (PAR == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) st<unsigned>(F, pb, k * NQ + opposite(i), co, P[k][i]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) {
+        if (i == 1 || i == 2) continue;
+        const unsigned dst = (i == 0) ? co : ((i & 1) ? np[(i - 1) >> 1] : nm[(i - 1) >> 1]);
+        st<unsigned>(F, pb, k * NQ + i, dst, P[k][i]);
+      }
+    if (lane == 63) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) xl.hi[1][w][k] = P[k][1];
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) xl.lo[1][w][k] = P[k][2];
+    }
+    __syncthreads();
+    const int wl = w > 0 ? w - 1 : nw - 1, wr = w < nw - 1 ? w + 1 : 0;
+    // the lane shifts read every lane, so they run with all lanes active
+    unsigned left[K], right[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      left[k] = lane_shift<true>(xl.hi[1][wl][k], P[k][1]);
+      right[k] = lane_shift<false>(xl.lo[1][wr][k], P[k][2]);
+    }
+    const bool first = !row && t == 0, last = !row && t == (int)blockDim.x - 1;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const unsigned vp = __builtin_amdgcn_alignbyte(P[k][1], left[k], 2);   // slot(+x) of x0, x0 + 1
+      const unsigned vm = __builtin_amdgcn_alignbyte(right[k], P[k][2], 2);  // slot(-x) of x0, x0 + 1
+      if (first) {
+        // x0 - 1 is the previous workgroup's: it writes slot(+x) of x0; this lane writes
+        // x0 + 1's, and slot(-x) of x0 - 1 (its own f_{-x}(x0))
+        st_shifted<H>(F, pb, k * NQ + 1, co + (unsigned)sizeof(H), (H)(vp >> 16));
+        st_shifted<H>(F, pb, k * NQ + 2, cl, (H)P[k][2]);
+      } else {
+        st<unsigned>(F, pb, k * NQ + 1, co, vp);
+      }
+      if (last) {
+        // x0 + 2 is the next workgroup's: this lane writes slot(-x) of x0 only, and
+        // slot(+x) of x0 + 2 (its own f_{+x}(x0 + 1))
+        st_shifted<H>(F, pb, k * NQ + 2, co, (H)vm);
+        st_shifted<H>(F, pb, k * NQ + 1, cr, (H)(P[k][1] >> 16));
+      } else {
+        st<unsigned>(F, pb, k * NQ + 2, co, vm);
+      }
+    }
+  }
+}
+
 // The parity-1 lane exchange needs every workgroup to cover whole wavefronts of one
 // x row (no partial workgroup, so that every lane reaches the barriers).  It is used
 // for the 8-variable (and 5-variable) sweeps (measured on 512^3: parity 1 11-20 % faster in FP32,
@@ -503,9 +673,45 @@ hipError_t sweep_src_t(const Launch& L, const Grid& g, const Phys& ph, const Cod
   }
 }
 
+// k_sweep2 serves FP16/BF16 storage of the 8-, 5- and 9-variable models (the 26-variable
+// one's 182 packed words per lane do not fit the registers; the 13-component one's
+// pair sweep needs about 300 VGPRs at parity 1, one wavefront per SIMD, and measured
+// slower than its one-cell sweep: 3.7 against 4.5 TB/s) on periodic lattices without
+// a body, with the direct source.  Its workgroup width: the first of block_x,
+// block_x / 2, block_x / 4 that is a multiple of 64 and whose 2 x width cells tile
+// every x row; 0 if none does (the one-cell sweep runs).
+inline int pair_width(const Grid& g, int block_x) {
+  for (int f = 0; f < 6; ++f)
+    if (g.bc[f]) return 0;
+  if (g.mask) return 0;
+  for (int b = block_x, n = 0; n < 3 && b >= 64; b /= 2, ++n)
+    if (b % 64 == 0 && g.nx % (2 * b) == 0) return b;
+  return 0;
+}
+
+template <int ST, int D, int MODEL>
+hipError_t sweep2_t(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity, int bw) {
+  const dim3 grd((unsigned)(g.nx / (2 * bw)), (unsigned)g.ny, (unsigned)g.nz), blk((unsigned)bw);
+  if (parity == 0) {
+    if (ph.collision)
+      hipLaunchKernelGGL((k_sweep2<ST, D, MODEL, 0, 1>), grd, blk, 0, L.stream, g, ph, cd);
+    else
+      hipLaunchKernelGGL((k_sweep2<ST, D, MODEL, 0, 0>), grd, blk, 0, L.stream, g, ph, cd);
+  } else {
+    if (ph.collision)
+      hipLaunchKernelGGL((k_sweep2<ST, D, MODEL, 1, 1>), grd, blk, 0, L.stream, g, ph, cd);
+    else
+      hipLaunchKernelGGL((k_sweep2<ST, D, MODEL, 1, 0>), grd, blk, 0, L.stream, g, ph, cd);
+  }
+  return hipGetLastError();
+}
+
 template <int ST, int D, int MODEL>
 hipError_t sweep_t(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity, const Inflow& in) {
   if (ph.source != 0) return sweep_src_t<ST, D, MODEL>(L, g, ph, cd, parity);
+  if constexpr ((ST == ST_F16 || ST == ST_BF16) && MODEL != 1 && MODEL != 4) {
+    if (const int bw = pair_width(g, L.block_x)) return sweep2_t<ST, D, MODEL>(L, g, ph, cd, parity, bw);
+  }
   launch_k<ST, D, MODEL, 0, false>(L, cell_grid(g, L.block_x), parity, ph.collision, lane_exchange(g, L.block_x, MODEL),
                                    fuse_x_faces(g), g, ph, cd, Body{}, nullptr, nullptr, in);
   return hipGetLastError();

@@ -575,6 +575,64 @@ def test_low_precision_one_step(vb, storage, ulp, parity):
     assert np.all(err <= bound), float((err / bound).max())
 
 
+# --- two cells per lane (FP16/BF16 storage) --------------------------------------
+
+def _pair_case(case):
+    """Workloads on 256-cell rows, which FP16/BF16 storage sweeps two cells per lane."""
+    if case == "ideal_2d":
+        w = synth.workload_fourier_2d()
+        w["shape"] = (256, 8, 2)
+        Q0 = np.concatenate([synth.fourier_2d(256, seed=s)[:, :, :8, :] for s in (3, 4)], axis=1)
+    elif case == "ideal_3d":
+        w = synth.workload_slab_3d()
+        w["shape"] = (256, 6, 4)
+        Q0, _ = synth.planar_discontinuity_3d(seed=5, shape=(4, 6, 256))
+        Q0 = boosted(Q0, (0.3, -0.2, 0.25))
+    elif case == "euler_3d":
+        w = _euler(synth.workload_slab_3d())
+        w["shape"] = (256, 6, 4)
+        Qm, _ = synth.planar_discontinuity_3d(seed=6, shape=(4, 6, 256))
+        Q0 = synth.without_field(boosted(Qm, (0.3, -0.2, 0.25)))
+    elif case == "navier_cauchy_3d":
+        w = synth.workload_elastic(dim=3, shape=(256, 6, 4))
+        Q0 = synth.elastic_state((256, 6, 4), seed=7)
+    else:
+        w, Q0 = small_resistive_2d(shape=(256, 10), seed=8)
+    return w, np.ascontiguousarray(Q0)
+
+
+@pytest.mark.parametrize("storage,ulp", [("f16", 2.0 ** -11), ("bf16", 2.0 ** -8)])
+@pytest.mark.parametrize("parity", [0, 1])
+@pytest.mark.parametrize("block_x", [64, 128])
+@pytest.mark.parametrize("case", ["ideal_2d", "ideal_3d", "euler_3d", "navier_cauchy_3d", "resistive_2d"])
+def test_pair_sweep_one_step(vb, case, block_x, storage, ulp, parity):
+    """Two cells per lane: 256-cell rows tiled by two workgroups of 64 threads (the
+    workgroups' end lanes read and write their neighbours' boundary elements) or by one
+    of 128 threads (the row wraps inside the workgroup).  One step from the GPU's own
+    pre-step populations against the oracle's collision of every cell, up to one
+    rounding of the stored deviation (plus FP32 arithmetic)."""
+    w, Q0 = _pair_case(case)
+    shape, dim = w["shape"], w["dim"]
+    print("case pair sweep", case, block_x, storage, parity, flush=True)
+    sim = vb.Vlbm(gpu_params(vb, w, storage, block_x=block_x))
+    sim.vlbm_init_fields(Q0)
+    sim.vlbm_step(3 + parity)
+    cells = np.arange(int(np.prod(shape)))
+    op = oracle_params(w)
+    want = oracle_one_step(oracle, op, sim.vlbm_gather_cells, cells, shape, dim)
+    sim.vlbm_step(1)
+    got = sim.vlbm_gather_cells(cells)
+    rest_Q, sigma = sim.vlbm_get_codec()
+    f_rest = oracle.equilibrium(op, rest_Q)
+    w0 = 1.0 / 3.0 if dim == 2 else 0.25
+    wts = np.array([w0] + [(1.0 - w0) / (2 * dim)] * (2 * dim))
+    sc = sigma[:, None] * wts[None, :]
+    h_want = np.abs(want - f_rest[None]) / sc[None]
+    bound = sc[None] * (2.0 * ulp * h_want + 2.0 ** -24) + 4e-6 * (1.0 + np.abs(want))
+    err = np.abs(got - want)
+    assert np.all(err <= bound), float((err / bound).max())
+
+
 # --- invariants -----------------------------------------------------------------
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
