@@ -100,9 +100,11 @@ vlbm_status vlbm_restrict(const float* Qf, int32_t K, int32_t nx, int32_t ny, in
 
 /* f_{k,i} += w_i dQ_k at the context's current step (shifts the zeroth moments by
  * dQ): the teacher-forced coarse run of the training pairs takes each target this
- * way.  dQ: device FP32 [8][N] in the context's moment layout.  Periodic ideal-MHD
- * context (2D or 3D, no body), any storage form (FP16/BF16 deviations are decoded,
- * incremented in FP32 and encoded again).  Stream-ordered, no synchronisation. */
+ * way.  dQ: device FP32 [8][N] in the context's moment layout.  Ideal-MHD context with
+ * the direct source (2D or 3D, periodic or with static faces, no body or the
+ * homogenized one; not the bounce-back body, whose solid cells hold no fluid), any
+ * storage form (FP16/BF16 deviations are decoded, incremented in FP32 and encoded
+ * again).  Stream-ordered, no synchronisation. */
 vlbm_status vlbm_inject(vlbm_ctx* c, const float* dQ);
 
 /* n coarse steps with the learned correction.  Per step: the moments X of the
@@ -118,11 +120,16 @@ vlbm_status vlbm_inject(vlbm_ctx* c, const float* dQ);
  * dQ := 0, i.e. the plain coarse VLBM step, and the fallback counter is incremented),
  * then the sweep, with the previous step's accepted dQ added as w_i dQ_k to the
  * populations before the collision.  After the last step the pending dQ is added to
- * the populations, so vlbm_moments sees the corrected state.  The context must be a
- * periodic ideal-MHD BGK context (K = cin = 8, any storage form, no body) whose
- * extent the network supports: 2D (nz = batch of independent lattices, gated
- * together and projected one by one) with a dim-2 network, or 3D (one lattice) with a
- * dim-3 network.  bound_corr: host, K doubles.  *n_fallback (host, may be NULL)
+ * the populations, so vlbm_moments sees the corrected state.  The context must be an
+ * ideal-MHD BGK context (K = cin = 8, any storage form) whose extent the network
+ * supports: periodic without a body, 2D (nz = batch of independent lattices, gated
+ * together and projected one by one) with a dim-2 network or 3D (one lattice) with a
+ * dim-3 network; or 3D with static faces and/or the homogenized body (Sec. 2.4) with a
+ * dim-3 network and project_totals = 0 (faces and the body change the totals): there
+ * each step adds the pending dQ to the populations, takes their moments as X, runs the
+ * plain step (faces, sweep, body) and then the network and the gate, eagerly (the
+ * body's box is recomputed on the host each step); the gate's central differences
+ * wrap around the lattice as on a periodic one.  bound_corr: host, K doubles.  *n_fallback (host, may be NULL)
  * receives the number of fallbacks in this call.  Synchronises.  The handle keeps the
  * step's buffers (about 128 N + N / 4 bytes for N cells, grown for a larger context), a stream,
  * an event and the graph of a pair of steps from call to call, until vlbm_nn_destroy;

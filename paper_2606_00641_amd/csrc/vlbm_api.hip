@@ -250,6 +250,36 @@ void build_codec(vlbm_ctx* c) {
 
 }  // namespace
 
+// One step on the context's stream: faces, sweep (with the body, and its move), step + 1.
+vlbm_status vlbm_step_one(vlbm_ctx* c) {
+  const int par = (int)(c->step & 1);
+  if (c->has_faces) {
+    const hipError_t e = launch_faces(c->L, c->g, c->ph, c->cd, par, c->inflow);
+    if (e != hipSuccess) return hip_fail(c, e, "face launch");
+  }
+  if (!c->p.body) {
+    const hipError_t e = launch_sweep(c->L, c->g, c->ph, c->cd, par, c->inflow);
+    if (e != hipSuccess) return hip_fail(c, e, "sweep launch");
+    ++c->step;
+    return VLBM_OK;
+  }
+  Body b = c->body;
+  b.t = (double)c->step;
+  if (c->p.body == 2) hlbm_box(c, b.t, b.box);
+  hipError_t e = launch_sweep_body(c->L, c->g, c->ph, c->cd, par, b, c->p.body, c->inflow);
+  if (e != hipSuccess) return hip_fail(c, e, "sweep launch");
+  ++c->step;
+  if (c->p.body == 2) return VLBM_OK;  // the homogenized body needs no mask
+  // the body moves to its position at the new step; uncovered cells are refilled
+  body_box(c, b.t, (double)c->step, b.box);
+  b.t = (double)c->step;
+  e = launch_mask(c->L, c->g, b, 0, 0);
+  if (e == hipSuccess) e = launch_mask(c->L, c->g, b, 1, 0);
+  if (e == hipSuccess) e = launch_refill(c->L, c->g, c->ph, c->cd, (int)(c->step & 1), b, c->inflow);
+  if (e != hipSuccess) return hip_fail(c, e, "body update");
+  return VLBM_OK;
+}
+
 extern "C" {
 
 vlbm_status vlbm_params_default(vlbm_params* p) {
@@ -518,31 +548,8 @@ vlbm_status vlbm_step(vlbm_ctx* c, int32_t n) {
   if (n < 0) return fail(c, VLBM_ERR_ARG, "n = %d < 0", n);
   if (!c->initialized) return fail(c, VLBM_ERR_STATE, "vlbm_step before vlbm_init_fields");
   for (int32_t j = 0; j < n; ++j) {
-    const int par = (int)(c->step & 1);
-    if (c->has_faces) {
-      const hipError_t e = launch_faces(c->L, c->g, c->ph, c->cd, par, c->inflow);
-      if (e != hipSuccess) return hip_fail(c, e, "face launch");
-    }
-    if (!c->p.body) {
-      const hipError_t e = launch_sweep(c->L, c->g, c->ph, c->cd, par, c->inflow);
-      if (e != hipSuccess) return hip_fail(c, e, "sweep launch");
-      ++c->step;
-      continue;
-    }
-    Body b = c->body;
-    b.t = (double)c->step;
-    if (c->p.body == 2) hlbm_box(c, b.t, b.box);
-    hipError_t e = launch_sweep_body(c->L, c->g, c->ph, c->cd, par, b, c->p.body, c->inflow);
-    if (e != hipSuccess) return hip_fail(c, e, "sweep launch");
-    ++c->step;
-    if (c->p.body == 2) continue;  // the homogenized body needs no mask
-    // the body moves to its position at the new step; uncovered cells are refilled
-    body_box(c, b.t, (double)c->step, b.box);
-    b.t = (double)c->step;
-    e = launch_mask(c->L, c->g, b, 0, 0);
-    if (e == hipSuccess) e = launch_mask(c->L, c->g, b, 1, 0);
-    if (e == hipSuccess) e = launch_refill(c->L, c->g, c->ph, c->cd, (int)(c->step & 1), b, c->inflow);
-    if (e != hipSuccess) return hip_fail(c, e, "body update");
+    const vlbm_status s = vlbm_step_one(c);
+    if (s != VLBM_OK) return s;
   }
   return VLBM_OK;
 }

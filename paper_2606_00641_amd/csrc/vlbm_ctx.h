@@ -44,3 +44,7 @@ struct vlbm_ctx {
   bool initialized = false;
   std::string err;
 };
+
+// One step of an initialised context on its stream (vlbm_step's body): static faces,
+// the sweep (with the body and its move), step + 1.  Errors are recorded in c->err.
+vlbm_status vlbm_step_one(vlbm_ctx* c);

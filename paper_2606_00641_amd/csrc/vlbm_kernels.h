@@ -110,6 +110,11 @@ __host__ __device__ inline int inj_lattice(int dim, int z) { return dim == 2 ? z
 hipError_t launch_sweep_inj(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity,
                             const float* dq, const int* ctl, const MomentsOut& mo);
 
+// The learned correction's network input from the populations at the given parity
+// (8-variable ideal model): the moments of every cell, FP32 in mo.x, and their
+// standardised BF16 form in mo.act (as MomentsOut describes).
+hipError_t launch_net_input(const Launch& L, const Grid& g, const Codec& cd, int parity, const MomentsOut& mo);
+
 // f := f^eq(Q) in natural layout.  Q is device SoA [K][N], FP64 or FP32.
 hipError_t launch_init(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd,
                        const void* Q, int q_is_f32);

@@ -313,6 +313,41 @@ __global__ __launch_bounds__(kReduceThreads) void k_moments(const Grid g, const 
   block_reduce<NT>(acc, NT, 1u << (K + 2), partial + (size_t)blockIdx.x * NT);
 }
 
+// Network input of the learned correction (8-variable ideal model): the moments of
+// each cell in the storage's compute type, summed over i in order, then as FP32 and
+// standardised BF16 (round to nearest even), one cell per thread.
+template <int ST, int D>
+__global__ __launch_bounds__(256) void k_net_input(const Grid g, const Codec cd, int parity, const MomentsOut mo) {
+  using S = Store<ST>;
+  using T = typename S::T;
+  using R = typename S::R;
+  constexpr int NQ = 2 * D + 1, K = 8;
+  const T* __restrict__ F = static_cast<const T*>(g.f);
+  const size_t N = (size_t)g.nx * g.ny * g.nz;
+  const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  const int x = (int)(c % g.nx), y = (int)((c / g.nx) % g.ny), z = (int)(c / ((size_t)g.nx * g.ny));
+  unsigned np[3], nm[3];
+  neighbours<D>(g, x, y, z, (unsigned)c, np, nm);
+  unsigned h[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    R q = R(0);
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const unsigned src = (parity == 0 || i == 0) ? (unsigned)c : ((i & 1) ? nm[(i - 1) >> 1] : np[(i - 1) >> 1]);
+      const int slot = parity == 0 ? i : opposite(i);
+      q += S::dec(F[(size_t)(k * NQ + slot) * g.stride + src], cd, k * NQ + i);
+    }
+    const float xq = (float)q;
+    mo.x[(size_t)k * N + c] = xq;
+    const unsigned u = __float_as_uint((xq - mo.mean[k]) * mo.istd[k]);
+    h[k] = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+  }
+  *reinterpret_cast<uint4*>(mo.act + c * K) =
+      make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+}
+
 // Per-step loads on the homogenized body at time b.t (cells of b.box): what the
 // homogenized collision moves from the fluid to the body -- force (momentum), torque
 // about the body's centre, energy -- and the magnetic flux through its surface,
@@ -527,6 +562,21 @@ struct MomentsFn {
 };
 
 }  // namespace
+
+hipError_t launch_net_input(const Launch& L, const Grid& g, const Codec& cd, int parity, const MomentsOut& mo) {
+  const size_t N = (size_t)g.nx * g.ny * g.nz;
+  const dim3 grd((unsigned)((N + 255) / 256)), blk(256);
+  switch (L.storage * 2 + (L.dim - 2)) {
+#define NI_CASE(ST, D)                                                                               \
+  case ST * 2 + (D - 2):                                                                             \
+    hipLaunchKernelGGL((k_net_input<ST, D>), grd, blk, 0, L.stream, g, cd, parity, mo);              \
+    return hipGetLastError();
+    NI_CASE(ST_F64, 2) NI_CASE(ST_F64, 3) NI_CASE(ST_F32, 2) NI_CASE(ST_F32, 3)
+    NI_CASE(ST_F16, 2) NI_CASE(ST_F16, 3) NI_CASE(ST_BF16, 2) NI_CASE(ST_BF16, 3)
+#undef NI_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_init(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd,
                        const void* Q, int q_is_f32) {

@@ -1211,6 +1211,15 @@ namespace {
 bool correctable(const vlbm_ctx* c) {
   return c->K == 8 && c->p.model == VLBM_IDEAL && !c->has_faces && c->p.body == 0 && c->p.source == 0;
 }
+// Contexts a correction can be added to: the 8-variable ideal model with the direct
+// source, any faces, no body or the homogenized one (every cell is fluid there).
+// Open-lattice corrected stepping: the slot of the correction pending before step j
+// (ping-pong: step j's network writes slot 1 - cur_open(j)).
+inline int cur_open(int32_t j) { return (int)(j & 1); }
+
+bool injectable(const vlbm_ctx* c) {
+  return c->K == 8 && c->p.model == VLBM_IDEAL && c->p.body != 1 && c->p.source == 0;
+}
 
 // The launchers below index by storage * 2 + (dimension - 2): the storage codes of
 // vlbm.h and of the kernels agree.
@@ -1233,7 +1242,7 @@ void launch_inject(const vlbm_ctx* c, int par, const float* dq, const int* ctl, 
 vlbm_status vlbm_inject(vlbm_ctx* c, const float* dQ) {
   if (!c || !dQ) return VLBM_ERR_ARG;
   if (!c->initialized) return VLBM_ERR_STATE;
-  if (!correctable(c)) return VLBM_ERR_ARG;
+  if (!injectable(c)) return VLBM_ERR_ARG;
   launch_inject(c, (int)(c->step & 1), dQ, nullptr, c->stream);
   return hipGetLastError() == hipSuccess ? VLBM_OK : VLBM_ERR_HIP;
 }
@@ -1244,9 +1253,17 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
   if (!c || !nn) return VLBM_ERR_ARG;
   if (!c->initialized) return VLBM_ERR_STATE;
   if (n < 0 || !bound_corr) return nfail(nn, VLBM_ERR_ARG, "n >= 0 and bound_corr required");
-  if (!correctable(c) || c->N > (1LL << 28) || c->p.collision != 0)
+  // periodic lattices: the fused path (the sweep injects); a 3D lattice with faces or
+  // the homogenized body: the open path (a separate injection and moments pass)
+  const bool open = !correctable(c);
+  if ((open && (!injectable(c) || c->D != 3)) || c->N > (1LL << 28) || c->p.collision != 0)
     return nfail(nn, VLBM_ERR_ARG,
-                 "corrected stepping needs a periodic ideal-MHD BGK context without a body");
+                 "corrected stepping needs an ideal-MHD BGK context: periodic (2D or 3D) without a body, or "
+                 "3D with static faces and/or the homogenized body");
+  if (open && project_totals)
+    return nfail(nn, VLBM_ERR_ARG,
+                 "the projection onto zero lattice totals needs a periodic lattice without a body: with faces or a "
+                 "body the totals change (pass project_totals = 0)");
   if (nn->dim != c->D)
     return nfail(nn, VLBM_ERR_ARG, "a %dD context needs a network of dim %d (got %d)", c->D, c->D, nn->dim);
   // 2D: the context's nz is a batch of lattices; 3D: one lattice of nz slices
@@ -1277,15 +1294,61 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
     return nfail(nn, e == hipErrorOutOfMemory ? VLBM_ERR_OOM : VLBM_ERR_HIP, "corrected step: %s",
                  hipGetErrorString(e));
   auto& q = nn->corr;
-  hipStream_t cs = q.cs;  // the steps run on the handle's own stream, ordered after s
-  q.gb_host = gb;         // lives in the handle: the copy below may read it after returning
-  e = hipEventRecord(q.ev, s);
-  if (e == hipSuccess) e = hipStreamWaitEvent(cs, q.ev, 0);
+  // the periodic path runs on the handle's own stream, ordered after s; the open path
+  // on the context's stream, where its plain step runs
+  hipStream_t cs = open ? s : q.cs;
+  q.gb_host = gb;  // lives in the handle: the copy below may read it after returning
+  if (!open) {
+    e = hipEventRecord(q.ev, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(cs, q.ev, 0);
+  }
   if (e == hipSuccess) e = hipMemcpyAsync(q.gb, &q.gb_host, sizeof(GateBounds), hipMemcpyHostToDevice, cs);
   // both control blocks cleared: nothing pending, means 0
   int* ctl[2] = {q.ctl, q.ctl + 1 + 8 * nbatch};
   if (e == hipSuccess) e = hipMemsetAsync(q.ctl, 0, 2 * (1 + 8 * (size_t)nbatch) * sizeof(int), cs);
   if (e == hipSuccess) e = hipMemsetAsync(q.fb, 0, sizeof(long long), cs);
+  if (e == hipSuccess && open) {
+    // Open lattice (static faces, homogenized body), eager: the body's box changes every
+    // step.  Per step: the pending correction goes into the populations, their moments
+    // are this step's network input, the plain step (faces, sweep, body) runs, then the
+    // network and the gate of its correction (pending until the next step).
+    const int gb3 = gbpl;
+    for (int32_t j = 0; j < n && st == VLBM_OK && e == hipSuccess; ++j) {
+      launch_inject(c, (int)(c->step & 1), q.raw[cur_open(j)], ctl[cur_open(j)], cs);
+      const vlbm::MomentsOut mo{q.X, nn->d_act[0], nn->d_norm + 0, nn->d_norm + 8};
+      e = vlbm::launch_net_input(c->L, c->g, c->cd, (int)(c->step & 1), mo);
+      if (e != hipSuccess) break;
+      st = vlbm_step_one(c);
+      if (st != VLBM_OK) {
+        (void)hipStreamSynchronize(cs);
+        return nfail(nn, st, "corrected step: %s", c->err.c_str());
+      }
+      const int nxt = 1 - cur_open(j);
+      st = forward(nn, nullptr, 1, c->p.nx, c->p.ny, c->p.nz, false, nn->d_norm + 24, nn->d_norm + 16, q.raw[nxt],
+                   cs);
+      if (st != VLBM_OK) break;
+      hipLaunchKernelGGL(k_gate_partials<3>, dim3((unsigned)gb3, 1u), dim3(kGateThreads), 0, cs, q.X, q.raw[nxt],
+                         c->p.nx, c->p.ny, c->p.nz, q.gpart);
+      hipLaunchKernelGGL(k_gate_final, dim3(1), dim3(kFinalThreads), 0, cs, q.gpart, 1, gb3, (double)ncl, 0, q.gb,
+                         ctl[nxt], q.fb);
+      e = hipGetLastError();
+    }
+    if (st == VLBM_OK && e == hipSuccess && n > 0) {
+      // the last accepted correction goes into the populations
+      launch_inject(c, (int)(c->step & 1), q.raw[cur_open(n)], ctl[cur_open(n)], cs);
+      e = hipGetLastError();
+    }
+    long long nfb = 0;
+    const hipError_t ce = hipMemcpyAsync(&nfb, q.fb, sizeof nfb, hipMemcpyDeviceToHost, cs);
+    const hipError_t se = hipStreamSynchronize(cs);
+    if (e == hipSuccess) e = ce != hipSuccess ? ce : se;
+    if (st != VLBM_OK) return st;
+    if (e != hipSuccess)
+      return nfail(nn, e == hipErrorOutOfMemory ? VLBM_ERR_OOM : VLBM_ERR_HIP, "corrected step: %s",
+                   hipGetErrorString(e));
+    if (n_fallback) *n_fallback = nfb;
+    return VLBM_OK;
+  }
   vlbm::Launch L = c->L;
   L.stream = cs;
   int cur = 0;  // raw[cur], ctl[cur]: the pending correction (not yet in the populations)

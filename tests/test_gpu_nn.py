@@ -658,9 +658,10 @@ def test_3d_gate_sees_the_z_divergence(env):
     assert nn.vlbm_step_corrected(sim2, net, 1, big, 0.1, bound_divb_abs=1e3) == 0
 
 
-def test_3d_corrected_step_rejects_open_lattices_and_2d_networks(env):
-    """The corrected 3D step needs a periodic lattice without a body and a dim-3
-    network; vlbm_inject likewise refuses a lattice with faces."""
+def test_3d_corrected_step_refusals(env):
+    """On a lattice with faces the corrected step refuses the projection onto zero
+    totals (faces change the totals); the bounce-back body (solid cells) is refused by
+    the corrected step and by vlbm_inject; a 3D context refuses a 2D network."""
     torch, vlbm, nn = env
     w = synth.workload_slab_3d()
     Q = state3()
@@ -671,12 +672,153 @@ def test_3d_corrected_step_rejects_open_lattices_and_2d_networks(env):
     opened.vlbm_init_fields(Q)
     net3 = nn.Net(8, 32, 1, stream=torch.cuda.current_stream().cuda_stream, dim=3)
     with pytest.raises(vlbm.VlbmError):
-        nn.vlbm_step_corrected(opened, net3, 1, np.full(8, 1e30), 0.1)
+        nn.vlbm_step_corrected(opened, net3, 1, np.full(8, 1e30), 0.1, project_totals=True)
+    bb = open_sim(env, "f32", mode=1)
     with pytest.raises(vlbm.VlbmError):
-        nn.vlbm_inject(opened, torch.zeros((8, int(np.prod(SHAPE3))), dtype=torch.float32, device="cuda"))
+        nn.vlbm_step_corrected(bb, nn.Net(8, 32, 1, stream=torch.cuda.current_stream().cuda_stream, dim=3), 1,
+                               np.full(8, 1e30), 0.1, project_totals=False)
+    with pytest.raises(vlbm.VlbmError):
+        nn.vlbm_inject(bb, torch.zeros((8, int(np.prod(OPEN_SHAPE))), dtype=torch.float32, device="cuda"))
     net2 = nn.Net(8, 32, 1, stream=torch.cuda.current_stream().cuda_stream)
     with pytest.raises(vlbm.VlbmError):
         nn.vlbm_step_corrected(sim3(env, "f32"), net2, 1, np.full(8, 1e30), 0.1)
+
+
+# --- corrected stepping of an open 3D lattice (faces, homogenized body) -----------
+
+OPEN_SHAPE = (32, 32, 16)  # nx, ny, nz
+OPEN_BC = (1, 2, 2, 2, 2, 2)
+
+
+def open_case(mode=2):
+    """Inflow at x-, zero gradient elsewhere, a moving rough magnetised body (mode 2
+    homogenized, 1 bounce-back) in a perturbed Mach-0.8 inflow state."""
+    Qin, _ = synth.inflow_state(mach=0.8, alfven_mach=4.0)
+    Q0 = np.broadcast_to(Qin[:, None, None, None], (8,) + OPEN_SHAPE[::-1]).copy()
+    Q0 += 0.3 * synth.smooth_box_state(OPEN_SHAPE[::-1], seed=13, amp=0.05, rho=0.0, p=0.0, B0=0.0)
+    body = synth.rough_body((12.3, 15.1, 7.7), (0.06, 0.03, 0.0), 5.0, m=(3.0, -2.0, 1.5), rough=0.12, seed=5)
+    body["mode"] = mode
+    return Q0, Qin, body
+
+
+def open_sim(env, storage, mode=2):
+    torch, vlbm, nn = env
+    Q0, Qin, body = open_case(mode)
+    sim = vlbm.Vlbm(vlbm.make_params(lattice="D3Q7", shape=OPEN_SHAPE, model="ideal", storage=storage, flux_scale=0.1,
+                                     tau=0.7, bc=OPEN_BC, inflow_Q=Qin, body=body,
+                                     stream=torch.cuda.current_stream().cuda_stream))
+    sim.vlbm_init_fields(Q0)
+    return sim
+
+
+def test_open_zero_weights_corrected_run_is_the_plain_run(env):
+    """Zero network on the open lattice: every correction is zero and accepted, and the
+    corrected run (injection, moments pass, plain step) is bitwise the plain run."""
+    torch, vlbm, nn = env
+    a, b = open_sim(env, "f32"), open_sim(env, "f32")
+    net = nn.Net(8, 32, 4, stream=torch.cuda.current_stream().cuda_stream, dim=3)
+    assert nn.vlbm_step_corrected(a, net, 9, np.full(8, 1e30), 10.0, 1.0, project_totals=False) == 0
+    b.vlbm_step(9)
+    assert np.array_equal(a.vlbm_get_populations()[0], b.vlbm_get_populations()[0])
+
+
+def test_open_zero_bound_falls_back_every_step(env):
+    torch, vlbm, nn = env
+    rng = np.random.default_rng(31)
+    a, b = open_sim(env, "f32"), open_sim(env, "f32")
+    net = make_net(env, 4, rand_params(rng, 4, dim=3), dim=3)
+    assert nn.vlbm_step_corrected(a, net, 7, np.zeros(8), 10.0, 1.0, project_totals=False) == 7
+    b.vlbm_step(7)
+    assert np.array_equal(a.vlbm_get_populations()[0], b.vlbm_get_populations()[0])
+
+
+def _oracle_corrected_open(op, f, net_o, steps, t0, bounds, norm):
+    """The open-lattice corrected run from the oracle's parts: per step X = the moments
+    of the populations, dQ = out_mean + out_std * Net((X - in_mean) / in_std) (no
+    projection), the gate on (X, dQ), one step with the faces and the body (run_bc at
+    time t0 + j), then f_{k,i} += w_i dQ_k if the gate accepted.  Returns the applied
+    corrections and the decisions."""
+    in_mean, in_std, out_mean, out_std = (np.asarray(a, np.float64)[:, None, None, None] for a in norm)
+    wts = np.array([op.w0] + [(1.0 - op.w0) / 6.0] * 6)
+    applied, decisions = [], []
+    for j in range(steps):
+        X = oracle.moments(op, f)[0].reshape(8, op.nz, op.ny, op.nx)
+        dQ = out_mean + out_std * net_o.forward(((X - in_mean) / in_std)[None])[0]
+        ok = C.gate(X, dQ, bounds[0], bounds[1], bounds[2], dim=3)
+        oracle.run_bc(op, f, 1, t0 + j)
+        if ok:
+            f += wts[None, :, None] * dQ.reshape(8, 1, -1)
+        applied.append(dQ if ok else np.zeros_like(dQ))
+        decisions.append(ok)
+    return applied, decisions
+
+
+def test_open_random_network_corrected_steps_match_oracle(env):
+    """A random 4-layer 3x3x3 network drives the corrected step on the open lattice
+    (FP64 populations): against the oracle's composition with its own face and body
+    step, the first applied correction agrees per channel to the network's BF16
+    precision (rel-L2 <= 1e-2); after three steps the departure from the plain run
+    agrees per channel to 1e-2, and the state to 1e-2 of that departure (the network's
+    BF16 rounding is the only difference; near the body the random network's
+    corrections reach about 2 % of the state, so the bound scales with them rather
+    than with the state); a step whose correction exceeds its bound is bitwise the
+    plain step."""
+    torch, vlbm, nn = env
+    rng = np.random.default_rng(75)
+    params = rand_params(rng, 4, dim=3)
+    net = make_net(env, 4, params, dim=3)
+    Q0, Qin, body = open_case(2)
+    in_mean = Q0.reshape(8, -1).mean(axis=1)
+    in_std = Q0.reshape(8, -1).std(axis=1) + 1e-3
+    norm = (in_mean, in_std, np.zeros(8), np.full(8, 5e-5))
+    net.vlbm_nn_set_norm(*norm)
+    net_o = C.Net(params, layers=4, quantize=True, dim=3)
+
+    def oracle_state():
+        op = oracle.make_params(dim=3, shape=OPEN_SHAPE, s=0.1, tau=0.7)
+        oracle.set_boundaries(op, bc=OPEN_BC, inflow_Q=Qin, body=body, body_mode=2)
+        return op, oracle.init(op, Q0)
+
+    a, plain = open_sim(env, "f64"), open_sim(env, "f64")
+    op, f = oracle_state()
+    opl, fpl = oracle_state()
+    big = np.full(8, 1e30)
+    applied, ok = _oracle_corrected_open(op, f, net_o, 1, 0, (big, 10.0, 1.0), norm)
+    assert ok == [True]
+    assert nn.vlbm_step_corrected(a, net, 1, big, 10.0, 1.0, project_totals=False) == 0
+    plain.vlbm_step(1)
+    oracle.run_bc(opl, fpl, 1, 0)
+    shape4 = (8,) + OPEN_SHAPE[::-1]
+    Qa, Qp = a.vlbm_moments()[0].reshape(shape4), plain.vlbm_moments()[0].reshape(shape4)
+    Qpo = oracle.moments(opl, fpl)[0].reshape(shape4)
+    assert np.abs(Qp - Qpo).max() <= 1e-10 * np.abs(Q0).max()
+    dq = Qa - Qp
+    for k in range(8):
+        assert rel_l2(dq[k], applied[0][k]) <= 1e-2, k
+    _, ok = _oracle_corrected_open(op, f, net_o, 2, 1, (big, 10.0, 1.0), norm)
+    assert ok == [True, True]
+    assert nn.vlbm_step_corrected(a, net, 2, big, 10.0, 1.0, project_totals=False) == 0
+    plain.vlbm_step(2)
+    oracle.run_bc(opl, fpl, 2, 1)
+    Qa, Qp = a.vlbm_moments()[0].reshape(shape4), plain.vlbm_moments()[0].reshape(shape4)
+    Qo, Qpo = oracle.moments(op, f)[0].reshape(shape4), oracle.moments(opl, fpl)[0].reshape(shape4)
+    assert np.abs(Qa - Qo).max() <= 1e-2 * np.abs(Qo - Qpo).max()
+    for k in range(8):
+        assert rel_l2((Qa - Qp)[k], (Qo - Qpo)[k]) <= 1e-2, k
+    # a correction over its bound in E: rejected, the plain step
+    probe = f.copy()
+    applied, _ = _oracle_corrected_open(op, probe, net_o, 1, 3, (big, 10.0, 1.0), norm)
+    e_norm = float(np.sqrt((applied[0][4] ** 2).sum()))
+    tight = big.copy()
+    tight[4] = 0.5 * e_norm
+    _, ok = _oracle_corrected_open(op, f, net_o, 1, 3, (tight, 10.0, 1.0), norm)
+    assert ok == [False]
+    before, par, step = a.vlbm_get_populations()
+    ref = open_sim(env, "f64")
+    ref.vlbm_set_populations(before, par, step)
+    assert nn.vlbm_step_corrected(a, net, 1, tight, 10.0, 1.0, project_totals=False) == 1
+    ref.vlbm_step(1)
+    assert np.array_equal(a.vlbm_get_populations()[0], ref.vlbm_get_populations()[0])
 
 
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
