@@ -116,7 +116,8 @@ vlbm_status vlbm_inject(vlbm_ctx* c, const float* dQ);
  * (FP64 over the whole lattice or batch: every ||dQ_k||_2 <= bound_corr[k]; the
  * central-difference div B drift ||div(B + dB)||_2 <= (1 + bound_divb_rel) ||div B||_2
  * + bound_divb_abs ||B||_2 with B the in-plane field of X in 2D, all three components
- * in 3D; all finite -- otherwise
+ * in 3D; all finite; without the projection also X + dQ physical in every cell,
+ * rho > 0 and p >= 0 -- otherwise
  * dQ := 0, i.e. the plain coarse VLBM step, and the fallback counter is incremented),
  * then the sweep, with the previous step's accepted dQ added as w_i dQ_k to the
  * populations before the collision.  After the last step the pending dQ is added to

@@ -21,8 +21,9 @@ taps -- no blocking or fusion -- so it can be checked by eye:
   up to the Powell source)
 * gate: the correction is dropped when a per-variable L2 norm exceeds its bound, when
   it raises the central-difference div B norm of the state by more than a relative
-  amount plus an absolute amount (a fraction of the field's own L2 norm), or when it
-  is not finite.
+  amount plus an absolute amount (a fraction of the field's own L2 norm), when it
+  is not finite, or (optionally, gamma given) when it leaves a cell with rho <= 0 or
+  a negative pressure.
 """
 from __future__ import annotations
 
@@ -218,10 +219,22 @@ def central_divb_l2(Q, dim=2):
     return float(np.sqrt((div * div).sum()))
 
 
-def gate(Q, dQ, bound_corr, bound_divb_rel, bound_divb_abs=0.0, dim=2):
+def physical(Q, gamma):
+    """True if every cell of the ideal-MHD state Q [8, ...] has rho > 0 and
+    p = (gamma - 1)(E - |rho u|^2 / (2 rho) - |B|^2 / 2) >= 0."""
+    rho = Q[0]
+    if not np.all(rho > 0):
+        return False
+    kinetic = 0.5 * (Q[1] ** 2 + Q[2] ** 2 + Q[3] ** 2) / rho
+    magnetic = 0.5 * (Q[5] ** 2 + Q[6] ** 2 + Q[7] ** 2)
+    return bool(np.all((gamma - 1.0) * (Q[4] - kinetic - magnetic) >= 0))
+
+
+def gate(Q, dQ, bound_corr, bound_divb_rel, bound_divb_abs=0.0, dim=2, gamma=None):
     """True if the correction dQ may be applied to state Q: finite, every
-    ||dQ_k||_2 <= bound_corr[k], and the central div B norm after the correction at
-    most (1 + rel) times the one before plus abs times ||B||_2."""
+    ||dQ_k||_2 <= bound_corr[k], the central div B norm after the correction at
+    most (1 + rel) times the one before plus abs times ||B||_2, and (gamma given)
+    Q + dQ physical in every cell."""
     if not np.all(np.isfinite(dQ)):
         return False
     K = dQ.shape[0]
@@ -230,4 +243,6 @@ def gate(Q, dQ, bound_corr, bound_divb_rel, bound_divb_abs=0.0, dim=2):
         return False
     before = central_divb_l2(Q, dim)
     after = central_divb_l2(Q + dQ, dim)
-    return after <= (1.0 + bound_divb_rel) * before + bound_divb_abs * b_l2(Q, dim)
+    if after > (1.0 + bound_divb_rel) * before + bound_divb_abs * b_l2(Q, dim):
+        return False
+    return gamma is None or physical(Q + dQ, gamma)

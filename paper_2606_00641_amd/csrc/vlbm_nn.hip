@@ -559,13 +559,17 @@ struct GateBounds {
 // Every workgroup works inside one lattice (blockIdx.y) and accumulates over its cells
 // the FP64 partials: [0..7] sum r_k^2, [8..15] sum r_k, [16] sum divc(X)^2,
 // [17] sum divc(X + r)^2, [18] non-finite count, [19] sum |B(X)|^2 (the D components
-// the divergence sees); r = raw, the network's output.  D = 2: nz lattices of nx x ny
-// (divergence of the in-plane field); D = 3: one nx x ny x nz lattice.
-constexpr int kGateNP = 20;
+// the divergence sees), [20] (gm1 > 0) count of cells X + r leaves with rho <= 0 or a
+// negative pressure (gm1 = gamma - 1; meaningful where the correction is not
+// projected, so that X + r is the corrected state); r = raw, the network's output.
+// D = 2: nz lattices of nx x ny (divergence of the in-plane field); D = 3: one
+// nx x ny x nz lattice.
+constexpr int kGateNP = 21;
 
 template <int D>
 __global__ __launch_bounds__(kGateThreads) void k_gate_partials(const float* __restrict__ X, const float* __restrict__ raw,
-                                                                int nx, int ny, int nz, double* __restrict__ partial) {
+                                                                int nx, int ny, int nz, double gm1,
+                                                                double* __restrict__ partial) {
   constexpr int NP = kGateNP;
   __shared__ double sh[kGateThreads / 64][NP];
   const int nb = gridDim.y, b = blockIdx.y;
@@ -605,6 +609,13 @@ __global__ __launch_bounds__(kGateThreads) void k_gate_partials(const float* __r
     acc[16] += dv * dv;
     acc[17] += dv2 * dv2;
     acc[19] += b2;
+    if (gm1 > 0.0) {
+      double q[8];
+      for (int k = 0; k < 8; ++k) q[k] = (double)X[k * N32 + c] + (double)raw[k * N32 + c];
+      const double kin = 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0];
+      const double mag = 0.5 * (q[5] * q[5] + q[6] * q[6] + q[7] * q[7]);
+      if (!(q[0] > 0.0) || !(gm1 * (q[4] - kin - mag) >= 0.0)) acc[20] += 1.0;
+    }
   }
   for (int j = 0; j < NP; ++j) {
     acc[j] = wave_sum(acc[j]);
@@ -627,8 +638,9 @@ __global__ __launch_bounds__(kGateThreads) void k_gate_partials(const float* __r
 // r + G, ... in that order, a lane-shuffle tree over the group; without it the means
 // stay 0.  The correction passes when it is finite, every
 // ||dQ_k||_2 <= gb->corr[k] (||dQ_k||^2 = sum r_k^2 + sum over lattices of
-// (ncl m^2 - 2 m sum r_k)) and ||divc(X + dQ)||_2 <= (1 + gb->divb_rel) ||divc(X)||_2 +
-// gb->divb_abs ||B(X)||_2: ctl[0] = 1, else ctl[0] = 0 and *fallbacks += 1.  Batch-wide
+// (ncl m^2 - 2 m sum r_k)), ||divc(X + dQ)||_2 <= (1 + gb->divb_rel) ||divc(X)||_2 +
+// gb->divb_abs ||B(X)||_2 and no cell is left unphysical (partial [20]): ctl[0] = 1, else
+// ctl[0] = 0 and *fallbacks += 1.  Batch-wide
 // sums: thread t takes workgroups t, t + 256, ... in that order, wave_sum per
 // wavefront, thread 0 adds the four wavefronts in order.  (A separate launch: deciding
 // in the last workgroup of the partials kernel needs a device-scope release fence in
@@ -696,7 +708,7 @@ __global__ __launch_bounds__(kFinalThreads) void k_gate_final(const double* __re
       const double md = m;
       t[NP + k] = ncl * md * md - 2.0 * md * t[8 + k];
     }
-  bool ok = t[18] == 0.0;
+  bool ok = t[18] == 0.0 && t[20] == 0.0;
   for (int k = 0; k < 8; ++k) ok = ok && sqrt(fmax(t[k] + t[NP + k], 0.0)) <= gb->corr[k];
   ok = ok && sqrt(t[17]) <= (1.0 + gb->divb_rel) * sqrt(t[16]) + gb->divb_abs * sqrt(t[19]);
   ctl[0] = ok ? 1 : 0;
@@ -1279,6 +1291,8 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
     return nfail(nn, VLBM_ERR_ARG, "div B bounds must be >= 0");
   gb.divb_rel = bound_divb_rel;
   gb.divb_abs = bound_divb_abs;
+  // positivity of the corrected state, where it is X + raw (no projection)
+  const double gm1_gate = project_totals ? 0.0 : c->ph.gm1;
   const size_t N = (size_t)c->N;
   hipStream_t s = c->stream;
   const size_t ncl = N / (size_t)nbatch;  // cells per lattice (the projection's unit)
@@ -1328,7 +1342,7 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
                    cs);
       if (st != VLBM_OK) break;
       hipLaunchKernelGGL(k_gate_partials<3>, dim3((unsigned)gb3, 1u), dim3(kGateThreads), 0, cs, q.X, q.raw[nxt],
-                         c->p.nx, c->p.ny, c->p.nz, q.gpart);
+                         c->p.nx, c->p.ny, c->p.nz, gm1_gate, q.gpart);
       hipLaunchKernelGGL(k_gate_final, dim3(1), dim3(kFinalThreads), 0, cs, q.gpart, 1, gb3, (double)ncl, 0, q.gb,
                          ctl[nxt], q.fb);
       e = hipGetLastError();
@@ -1371,10 +1385,10 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
     const dim3 ggrid((unsigned)gbpl, (unsigned)nbatch);
     if (c->D == 2)
       hipLaunchKernelGGL(k_gate_partials<2>, ggrid, dim3(kGateThreads), 0, cs, q.X, q.raw[1 - cur], c->p.nx,
-                         c->p.ny, c->p.nz, q.gpart);
+                         c->p.ny, c->p.nz, gm1_gate, q.gpart);
     else
       hipLaunchKernelGGL(k_gate_partials<3>, ggrid, dim3(kGateThreads), 0, cs, q.X, q.raw[1 - cur], c->p.nx,
-                         c->p.ny, c->p.nz, q.gpart);
+                         c->p.ny, c->p.nz, gm1_gate, q.gpart);
     hipLaunchKernelGGL(k_gate_final, dim3(1), dim3(kFinalThreads), 0, cs, q.gpart, nbatch, gbpl, (double)ncl,
                        project_totals ? 1 : 0, q.gb, ctl[1 - cur], q.fb);
     e = hipGetLastError();

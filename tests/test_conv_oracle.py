@@ -257,6 +257,32 @@ def test_gate_cases():
     assert not C.gate(Q, div_only, big, 0.1, bound_divb_abs=0.01)
 
 
+def chk_positivity(mod=C):
+    """The gate's positivity condition against pressures worked out by hand: rho = 1,
+    rho u = (1, 0, 0), B = (0, 1, 0), p = 0.6, gamma = 5/3, so E = 0.9 + 0.5 + 0.5 =
+    1.9; lowering E by 1 leaves p = (2/3)(0.9 - 1) < 0 (rejected), by 0.8 leaves
+    p = (2/3)(0.1) > 0 (accepted) -- either without the kinetic or without the magnetic
+    energy the first would pass; a correction to rho = -0.1 in one cell is rejected;
+    without gamma the condition is off.  Returns the number of wrong decisions."""
+    Q = np.zeros((8, 1, 4, 4))
+    Q[0], Q[1], Q[6], Q[4] = 1.0, 1.0, 1.0, 1.9
+    big = np.full(8, 1e9)
+    wrong = 0
+    for dE, want in ((-1.0, False), (-0.8, True)):
+        dQ = np.zeros_like(Q)
+        dQ[4, 0, 2, 1] = dE
+        wrong += mod.gate(Q, dQ, big, 10.0, 1.0, gamma=5.0 / 3.0) != want
+        wrong += mod.gate(Q, dQ, big, 10.0, 1.0) is not True
+    dQ = np.zeros_like(Q)
+    dQ[0, 0, 1, 3] = -1.1
+    wrong += mod.gate(Q, dQ, big, 10.0, 1.0, gamma=5.0 / 3.0) is not False
+    return int(wrong)
+
+
+def test_gate_positivity():
+    assert chk_positivity() == 0
+
+
 def chk_projection(mod=C):
     """The projection onto zero lattice totals, pinned by what defines it rather than
     by its formula: P d has zero total in every channel of every lattice, and d - P d
@@ -311,6 +337,11 @@ MUTATIONS = {
     "loss_scale": ("dz = 2.0 * (y - t) / n", "dz = 1.0 * (y - t) / n"),
     "adam_bias_correction": ("new.append(p - self.lr * (m / c1) / (np.sqrt(v / c2) + self.eps))",
                              "new.append(p - self.lr * m / (np.sqrt(v) + self.eps))"),
+    "positivity_kinetic_dropped": ("return bool(np.all((gamma - 1.0) * (Q[4] - kinetic - magnetic) >= 0))",
+                                   "return bool(np.all((gamma - 1.0) * (Q[4] - magnetic) >= 0))"),
+    "positivity_magnetic_dropped": ("return bool(np.all((gamma - 1.0) * (Q[4] - kinetic - magnetic) >= 0))",
+                                    "return bool(np.all((gamma - 1.0) * (Q[4] - kinetic) >= 0))"),
+    "positivity_rho_ignored": ("    if not np.all(rho > 0):\n        return False\n", ""),
 }
 
 
@@ -330,5 +361,5 @@ def test_conv_pins_catch_planted_mistake(name):
               or chk_conv3_vs_scipy(mod) > 1e-12 or chk_conv3_vs_torch(mod) > 1e-12
               or chk_gradients_fd(mod) > 1e-7 or chk_gradients3_fd(mod) > 1e-7
               or chk_gelu_vs_torch(mod) > 1e-12 or chk_adam_vs_torch(mod) > 1e-12
-              or chk_projection(mod) > 1e-13)
+              or chk_projection(mod) > 1e-13 or chk_positivity(mod) > 0)
     assert failed, name

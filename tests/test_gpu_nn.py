@@ -732,11 +732,38 @@ def test_open_zero_bound_falls_back_every_step(env):
     assert np.array_equal(a.vlbm_get_populations()[0], b.vlbm_get_populations()[0])
 
 
+def test_open_gate_rejects_an_unphysical_correction(env):
+    """Without the projection the gate also holds the corrected state physical: a
+    network whose only nonzero parameter is the last layer's bias in E applies a
+    uniform change of the energy; lowering E by 1.5 times the smallest internal-energy
+    margin of the state (E - |rho u|^2 / (2 rho) - |B|^2 / 2, its minimum over the cells)
+    leaves cells with a negative pressure and falls back, by half of it is accepted --
+    the oracle's gate (conv_ref.physical) decides the same."""
+    torch, vlbm, nn = env
+    sim = open_sim(env, "f64")
+    Q = sim.vlbm_moments()[0].reshape((8,) + OPEN_SHAPE[::-1])
+    margin = float((Q[4] - 0.5 * (Q[1] ** 2 + Q[2] ** 2 + Q[3] ** 2) / Q[0]
+                    - 0.5 * (Q[5] ** 2 + Q[6] ** 2 + Q[7] ** 2)).min())
+    assert margin > 0
+    big = np.full(8, 1e30)
+    for frac, want in ((1.5, 1), (0.5, 0)):
+        params = [(np.zeros(Ws), np.zeros(bs)) for Ws, bs in C.Net.shapes(8, 32, 4, dim=3)]
+        params[-1][1][4] = -frac * margin
+        net = make_net(env, 4, params, dim=3)
+        net.vlbm_nn_set_norm(np.zeros(8), np.ones(8), np.zeros(8), np.ones(8))
+        dQ = np.zeros_like(Q)
+        dQ[4] = np.float32(-frac * margin)
+        assert C.gate(Q, dQ, big, 10.0, 1.0, dim=3, gamma=5.0 / 3.0) == (want == 0)
+        a = open_sim(env, "f64")
+        assert nn.vlbm_step_corrected(a, net, 1, big, 10.0, 1.0, project_totals=False) == want, frac
+
+
 def _oracle_corrected_open(op, f, net_o, steps, t0, bounds, norm):
     """The open-lattice corrected run from the oracle's parts: per step X = the moments
     of the populations, dQ = out_mean + out_std * Net((X - in_mean) / in_std) (no
-    projection), the gate on (X, dQ), one step with the faces and the body (run_bc at
-    time t0 + j), then f_{k,i} += w_i dQ_k if the gate accepted.  Returns the applied
+    projection), the gate on (X, dQ) with the positivity condition, one step with the
+    faces and the body (run_bc at time t0 + j), then f_{k,i} += w_i dQ_k if the gate
+    accepted.  Returns the applied
     corrections and the decisions."""
     in_mean, in_std, out_mean, out_std = (np.asarray(a, np.float64)[:, None, None, None] for a in norm)
     wts = np.array([op.w0] + [(1.0 - op.w0) / 6.0] * 6)
@@ -744,7 +771,7 @@ def _oracle_corrected_open(op, f, net_o, steps, t0, bounds, norm):
     for j in range(steps):
         X = oracle.moments(op, f)[0].reshape(8, op.nz, op.ny, op.nx)
         dQ = out_mean + out_std * net_o.forward(((X - in_mean) / in_std)[None])[0]
-        ok = C.gate(X, dQ, bounds[0], bounds[1], bounds[2], dim=3)
+        ok = C.gate(X, dQ, bounds[0], bounds[1], bounds[2], dim=3, gamma=5.0 / 3.0)
         oracle.run_bc(op, f, 1, t0 + j)
         if ok:
             f += wts[None, :, None] * dQ.reshape(8, 1, -1)
