@@ -146,7 +146,12 @@ __global__ __launch_bounds__(kConvThreads) void k_conv(const bf16_t* __restrict_
   // BWD), share one LDS buffer.  Result rows are padded by 4 floats so that the four
   // lane groups of a store land in distinct banks.
   constexpr int OS = COUT + 4;
-  constexpr int kTileBytes = NZT * HALO * HALO * CIN * 2;
+  // Halo positions are stored unpadded, 2 CIN bytes apart.  (Padding the 32-channel
+  // positions to 40 channels, meant to spread the A-fragment reads over the banks,
+  // was measured with SQ_LDS_BANK_CONFLICT to raise the conflict cycles by a third
+  // and left the time unchanged.)
+  constexpr int PS = CIN;
+  constexpr int kTileBytes = NZT * HALO * HALO * PS * 2;
   constexpr int kOutBytes = MODE == MODE_LAST ? 0 : TILE * TILE * OS * 4;
   __shared__ __attribute__((aligned(16))) unsigned char lds[kTileBytes > kOutBytes ? kTileBytes : kOutBytes];
   bf16_t* tile = reinterpret_cast<bf16_t*>(lds);
@@ -164,7 +169,7 @@ __global__ __launch_bounds__(kConvThreads) void k_conv(const bf16_t* __restrict_
     gx = gx < 0 ? gx + W : (gx >= W ? gx - W : gx);
     const uint4 v =
         *reinterpret_cast<const uint4*>(act + (((size_t)(zbase + gz) * H + gy) * W + gx) * CIN + ch * 8);
-    *reinterpret_cast<uint4*>(tile + (zs * HALO * HALO + pix) * CIN + ch * 8) = v;
+    *reinterpret_cast<uint4*>(tile + (zs * HALO * HALO + pix) * PS + ch * 8) = v;
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   bf16x8 bw[KS][NT];
@@ -191,7 +196,7 @@ __global__ __launch_bounds__(kConvThreads) void k_conv(const bf16_t* __restrict_
         for (int t = 0; t < NT; ++t)
           bw[s][t] = *reinterpret_cast<const bf16x8*>(wpack + ((size_t)((zs * KS + s) * NT + t) * 64 + lane) * 8);
     }
-    const bf16_t* tz = tile + zs * HALO * HALO * CIN;
+    const bf16_t* tz = tile + zs * HALO * HALO * PS;
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
 #pragma unroll
@@ -200,12 +205,12 @@ __global__ __launch_bounds__(kConvThreads) void k_conv(const bf16_t* __restrict_
         bf16x8 a;
         if constexpr (CIN == 32) {
           const int dy = s / 3, dx = s % 3;
-          a = *reinterpret_cast<const bf16x8*>(tz + ((py + dy) * HALO + px + dx) * CIN + 8 * g);
+          a = *reinterpret_cast<const bf16x8*>(tz + ((py + dy) * HALO + px + dx) * PS + 8 * g);
         } else {
           const int tap = 4 * s + g;  // 8 input channels: 4 taps per K step
           if (tap < 9) {
             const int dy = tap / 3, dx = tap % 3;
-            a = *reinterpret_cast<const bf16x8*>(tz + ((py + dy) * HALO + px + dx) * CIN);
+            a = *reinterpret_cast<const bf16x8*>(tz + ((py + dy) * HALO + px + dx) * PS);
           } else {
             a = bf16x8{};  // zero padding of K
           }
@@ -293,8 +298,14 @@ __global__ __launch_bounds__(kThreads) void k_conv_bw(const bf16_t* __restrict__
   constexpr int NTJ = (NJ + 15) / 16;
   constexpr int MT = (COUT + 15) / 16;
   constexpr int NTW = (NTJ + 3) / 4;  // N tiles per wavefront
-  __shared__ __attribute__((aligned(16))) bf16_t aT[CIN * HALO * HALO];
-  __shared__ __attribute__((aligned(16))) bf16_t dzT[MT * 16 * TILE * TILE];
+  // LDS rows padded against bank conflicts: a channel's halo (324 elements) to 326, an
+  // odd number of dwords, so that the 16 channels a lane group reads fall in distinct
+  // banks; a row of dZ (256 positions, 512 bytes: every lane of a group in one bank) by
+  // 8 elements, 33 16-byte groups.
+  constexpr int AS = HALO * HALO + 2;
+  constexpr int DZS = TILE * TILE + 8;
+  __shared__ __attribute__((aligned(16))) bf16_t aT[CIN * AS];
+  __shared__ __attribute__((aligned(16))) bf16_t dzT[MT * 16 * DZS];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4;
   f32x4 acc[MT][NTW];
 #pragma unroll
@@ -324,17 +335,17 @@ __global__ __launch_bounds__(kThreads) void k_conv_bw(const bf16_t* __restrict__
       const uint4 v = *reinterpret_cast<const uint4*>(act + (((size_t)asl * H + gy) * W + gx) * CIN + ch * 8);
       const bf16_t* e = reinterpret_cast<const bf16_t*>(&v);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) aT[((ch * 8 + j) * HALO + hy) * HALO + hx] = e[j];
+      for (int j = 0; j < 8; ++j) aT[(ch * 8 + j) * AS + hy * HALO + hx] = e[j];
     }
     for (int q = threadIdx.x; q < MT * 16 * TILE * TILE; q += kThreads) {
       const int o = q / (TILE * TILE), p = q % (TILE * TILE);
       const int y = ty0 + p / TILE, x = tx0 + p % TILE;
-      dzT[q] = o < COUT ? dz[(((size_t)sl * H + y) * W + x) * COUT + o] : (bf16_t)0;
+      dzT[o * DZS + p] = o < COUT ? dz[(((size_t)sl * H + y) * W + x) * COUT + o] : (bf16_t)0;
     }
     __syncthreads();
     if (slab == 0 && (int)threadIdx.x < COUT) {
       float sacc = 0.0f;
-      for (int p = 0; p < TILE * TILE; ++p) sacc += bf2f(dzT[threadIdx.x * TILE * TILE + p]);
+      for (int p = 0; p < TILE * TILE; ++p) sacc += bf2f(dzT[threadIdx.x * DZS + p]);
       db += sacc;
     }
 #pragma unroll
@@ -342,7 +353,7 @@ __global__ __launch_bounds__(kThreads) void k_conv_bw(const bf16_t* __restrict__
       bf16x8 afr[MT];
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
-        afr[mt] = *reinterpret_cast<const bf16x8*>(dzT + (16 * mt + (lane & 15)) * TILE * TILE + 32 * s + 8 * g);
+        afr[mt] = *reinterpret_cast<const bf16x8*>(dzT + (16 * mt + (lane & 15)) * DZS + 32 * s + 8 * g);
       const int pos0 = 32 * s + 8 * g;  // 8 consecutive positions of one tile row
       const int py = pos0 / TILE, px0 = pos0 % TILE;
 #pragma unroll
@@ -354,7 +365,7 @@ __global__ __launch_bounds__(kThreads) void k_conv_bw(const bf16_t* __restrict__
         if (j < NJ) {
           const int tap = j / CIN, c = j % CIN;
           const int dy = tap / 3, dx = tap % 3;
-          const bf16_t* src = aT + (c * HALO + py + dy) * HALO + px0 + dx;  // 8 positions, unaligned
+          const bf16_t* src = aT + c * AS + (py + dy) * HALO + px0 + dx;  // 8 positions, unaligned
 #pragma unroll
           for (int e = 0; e < 8; ++e) bfr[e] = __builtin_bit_cast(__bf16, src[e]);
         }

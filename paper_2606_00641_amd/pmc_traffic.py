@@ -10,6 +10,10 @@ taken on the kernel as it now stands.
 
 Usage: python -m paper_2606_00641_amd.pmc_traffic --fetch F.csv --write W.csv
        --key resistive_256/f32 --cells N --bytes-per-cell B --out traffic.json
+       [--kernel sweep|pair] [--merge]
+--kernel pair takes the FP16/BF16 two-cells-per-lane sweep (k_sweep2) instead of the
+plain one-cell sweep; --merge adds the record to an existing file taken on the same
+sources.
 """
 import argparse
 import csv
@@ -62,6 +66,23 @@ def per_parity(rows, st, d, model):
     return {p: sum(v) / len(v) for p, v in sorted(acc.items())}
 
 
+PAIR_RE = re.compile(r"k_sweep2<(\d+), (\d+), (\d+), (\d+), (\d+)>")
+
+
+def per_parity_pair(rows, st, d, model):
+    """Mean KiB per dispatch of the two-cells-per-lane BGK sweep for each parity."""
+    acc = {}
+    for name, v in rows:
+        m = PAIR_RE.search(name)
+        if not m:
+            continue
+        ST, D, MODEL, PAR, COLL = (int(x) for x in m.groups())
+        if (ST, D, MODEL, COLL) != (st, d, model, 0):
+            continue
+        acc.setdefault(PAR, []).append(v)
+    return {p: sum(v) / len(v) for p, v in sorted(acc.items())}
+
+
 def copy_kib(rows):
     vals = [v for name, v in rows if name.startswith("k_copy") or " k_copy(" in name or "::k_copy(" in name]
     if not vals:
@@ -80,6 +101,8 @@ def main():
     ap.add_argument("--cells", type=int, required=True)
     ap.add_argument("--bytes-per-cell", type=int, required=True)
     ap.add_argument("--commands", nargs="*", default=[])
+    ap.add_argument("--kernel", choices=("sweep", "pair"), default="sweep")
+    ap.add_argument("--merge", action="store_true", help="add the record to an existing --out file")
     ap.add_argument("--out", required=True)
     args = ap.parse_args()
 
@@ -88,15 +111,17 @@ def main():
     cf, cw = copy_kib(fr), copy_kib(wr)
     fetch_factor = COPY_BYTES / (cf * 1024.0)
     write_factor = COPY_BYTES / (cw * 1024.0)
-    pf = per_parity(fr, args.storage, args.dim_code, args.model)
-    pw = per_parity(wr, args.storage, args.dim_code, args.model)
+    select = per_parity if args.kernel == "sweep" else per_parity_pair
+    pf = select(fr, args.storage, args.dim_code, args.model)
+    pw = select(wr, args.storage, args.dim_code, args.model)
     if not pf or set(pf) != set(pw):
         raise SystemExit(f"sweep dispatches missing: fetch parities {sorted(pf)}, write parities {sorted(pw)}")
     fetch_b = sum(pf.values()) / len(pf) * 1024.0 * fetch_factor
     write_b = sum(pw.values()) / len(pw) * 1024.0 * write_factor
     algo = args.cells * args.bytes_per_cell
+    kname = "k_sweep" if args.kernel == "sweep" else "k_sweep2 (two cells per lane)"
     rec = {
-        "kernel": f"k_sweep<storage {args.storage}, lattice {args.dim_code}, model {args.model}, parity, no body, BGK>",
+        "kernel": f"{kname}<storage {args.storage}, lattice {args.dim_code}, model {args.model}, parity, no body, BGK>",
         "per_parity_raw_kib": {str(p): {"fetch_kib": pf[p], "write_kib": pw[p]} for p in pf},
         "fetch_bytes_per_launch": round(fetch_b),
         "write_bytes_per_launch": round(write_b),
@@ -104,6 +129,19 @@ def main():
         "algorithmic_bytes_per_launch": algo,
         "ratio_to_algorithmic": round((fetch_b + write_b) / algo, 4),
     }
+    rec["copy_kernel"] = {"FETCH_SIZE_kib": cf, "WRITE_SIZE_kib": cw, "fetch_factor": round(fetch_factor, 5),
+                          "write_factor": round(write_factor, 5)}
+    rec["commands"] = args.commands
+    if args.merge:
+        with open(args.out) as fh:
+            out = json.load(fh)
+        if out.get("kernel_hash") != kernel_source_hash():
+            raise SystemExit("--merge: the existing file was taken on other sources")
+        out["records"][args.key] = rec
+        with open(args.out, "w") as fh:
+            json.dump(out, fh, indent=1)
+        print(json.dumps(rec))
+        return
     out = {
         "description": "HBM traffic of the benchmark's dominant kernel from two rocprofv3 --pmc runs "
                        "(FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by the ratio of the known "
