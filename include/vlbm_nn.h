@@ -127,10 +127,11 @@ vlbm_status vlbm_inject(vlbm_ctx* c, const float* dQ);
  * together and projected one by one) with a dim-2 network or 3D (one lattice) with a
  * dim-3 network; or 3D with static faces and/or the homogenized body (Sec. 2.4) with a
  * dim-3 network and project_totals = 0 (faces and the body change the totals): there
- * each step adds the pending dQ to the populations, takes their moments as X, runs the
- * plain step (faces, sweep, body) and then the network and the gate, eagerly (the
- * body's box is recomputed on the host each step); the gate's central differences
- * wrap around the lattice as on a periodic one.  bound_corr: host, K doubles.  *n_fallback (host, may be NULL)
+ * each step evaluates the network on X, runs the plain step (faces, sweep, body), takes
+ * the moments X' of its result and gates X' + dQ -- the state the correction would make
+ * -- instead of X + dQ; an accepted dQ is added to the populations at once and X' + dQ
+ * is the next step's X (eager: the body's box is recomputed on the host each step); the
+ * gate's central differences wrap around the lattice as on a periodic one.  bound_corr: host, K doubles.  *n_fallback (host, may be NULL)
  * receives the number of fallbacks in this call.  Synchronises.  The handle keeps the
  * step's buffers (about 128 N + N / 4 bytes for N cells, grown for a larger context), a stream,
  * an event and the graph of a pair of steps from call to call, until vlbm_nn_destroy;

@@ -728,6 +728,25 @@ __global__ __launch_bounds__(kFinalThreads) void k_gate_final(const double* __re
 
 }  // namespace
 
+// Open-lattice corrected stepping: if the gate accepted (ctl[0]), the correction joins the
+// network's next input, X += dQ, and its standardised BF16 form is recomputed.
+__global__ __launch_bounds__(256) void k_net_accept(float* __restrict__ X, bf16_t* __restrict__ act,
+                                                    const float* __restrict__ dq, const int* __restrict__ ctl,
+                                                    const float* __restrict__ mean, const float* __restrict__ istd,
+                                                    size_t N) {
+  const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N || !ctl[0]) return;
+  unsigned h[8];
+  for (int k = 0; k < 8; ++k) {
+    const float x = X[(size_t)k * N + c] + dq[(size_t)k * N + c];
+    X[(size_t)k * N + c] = x;
+    const unsigned u = __float_as_uint((x - mean[k]) * istd[k]);
+    h[k] = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;  // BF16, nearest even
+  }
+  *reinterpret_cast<uint4*>(act + c * 8) =
+      make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+}
+
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
@@ -1236,10 +1255,6 @@ bool correctable(const vlbm_ctx* c) {
 }
 // Contexts a correction can be added to: the 8-variable ideal model with the direct
 // source, any faces, no body or the homogenized one (every cell is fluid there).
-// Open-lattice corrected stepping: the slot of the correction pending before step j
-// (ping-pong: step j's network writes slot 1 - cur_open(j)).
-inline int cur_open(int32_t j) { return (int)(j & 1); }
-
 bool injectable(const vlbm_ctx* c) {
   return c->K == 8 && c->p.model == VLBM_IDEAL && c->p.body != 1 && c->p.source == 0;
 }
@@ -1334,33 +1349,33 @@ vlbm_status vlbm_step_corrected(vlbm_ctx* c, vlbm_nn* nn, int32_t n, const doubl
   if (e == hipSuccess) e = hipMemsetAsync(q.fb, 0, sizeof(long long), cs);
   if (e == hipSuccess && open) {
     // Open lattice (static faces, homogenized body), eager: the body's box changes every
-    // step.  Per step: the pending correction goes into the populations, their moments
-    // are this step's network input, the plain step (faces, sweep, body) runs, then the
-    // network and the gate of its correction (pending until the next step).
+    // step.  X holds the network's input, the moments of the state at a step's start.
+    // Per step: the network on X; the plain step (faces, sweep, body); the moments X' of
+    // its result; the gate on X' + dQ, the state the correction would make (its norms,
+    // div B and positivity); an accepted correction goes into the populations at once,
+    // and X := X' + dQ (with its standardised form) is the next step's input.
     const int gb3 = gbpl;
+    const vlbm::MomentsOut mo{q.X, nn->d_act[0], nn->d_norm + 0, nn->d_norm + 8};
+    const size_t Nc = (size_t)c->N;
+    if (n > 0) e = vlbm::launch_net_input(c->L, c->g, c->cd, (int)(c->step & 1), mo);
     for (int32_t j = 0; j < n && st == VLBM_OK && e == hipSuccess; ++j) {
-      launch_inject(c, (int)(c->step & 1), q.raw[cur_open(j)], ctl[cur_open(j)], cs);
-      const vlbm::MomentsOut mo{q.X, nn->d_act[0], nn->d_norm + 0, nn->d_norm + 8};
-      e = vlbm::launch_net_input(c->L, c->g, c->cd, (int)(c->step & 1), mo);
-      if (e != hipSuccess) break;
+      st = forward(nn, nullptr, 1, c->p.nx, c->p.ny, c->p.nz, false, nn->d_norm + 24, nn->d_norm + 16, q.raw[0],
+                   cs);
+      if (st != VLBM_OK) break;
       st = vlbm_step_one(c);
       if (st != VLBM_OK) {
         (void)hipStreamSynchronize(cs);
         return nfail(nn, st, "corrected step: %s", c->err.c_str());
       }
-      const int nxt = 1 - cur_open(j);
-      st = forward(nn, nullptr, 1, c->p.nx, c->p.ny, c->p.nz, false, nn->d_norm + 24, nn->d_norm + 16, q.raw[nxt],
-                   cs);
-      if (st != VLBM_OK) break;
-      hipLaunchKernelGGL(k_gate_partials<3>, dim3((unsigned)gb3, 1u), dim3(kGateThreads), 0, cs, q.X, q.raw[nxt],
+      e = vlbm::launch_net_input(c->L, c->g, c->cd, (int)(c->step & 1), mo);
+      if (e != hipSuccess) break;
+      hipLaunchKernelGGL(k_gate_partials<3>, dim3((unsigned)gb3, 1u), dim3(kGateThreads), 0, cs, q.X, q.raw[0],
                          c->p.nx, c->p.ny, c->p.nz, gm1_gate, q.gpart);
       hipLaunchKernelGGL(k_gate_final, dim3(1), dim3(kFinalThreads), 0, cs, q.gpart, 1, gb3, (double)ncl, 0, q.gb,
-                         ctl[nxt], q.fb);
-      e = hipGetLastError();
-    }
-    if (st == VLBM_OK && e == hipSuccess && n > 0) {
-      // the last accepted correction goes into the populations
-      launch_inject(c, (int)(c->step & 1), q.raw[cur_open(n)], ctl[cur_open(n)], cs);
+                         ctl[0], q.fb);
+      launch_inject(c, (int)(c->step & 1), q.raw[0], ctl[0], cs);
+      hipLaunchKernelGGL(k_net_accept, dim3((unsigned)((Nc + 255) / 256)), dim3(256), 0, cs, q.X, nn->d_act[0],
+                         q.raw[0], ctl[0], nn->d_norm + 0, nn->d_norm + 8, Nc);
       e = hipGetLastError();
     }
     long long nfb = 0;

@@ -736,11 +736,13 @@ def test_open_gate_rejects_an_unphysical_correction(env):
     """Without the projection the gate also holds the corrected state physical: a
     network whose only nonzero parameter is the last layer's bias in E applies a
     uniform change of the energy; lowering E by 1.5 times the smallest internal-energy
-    margin of the state (E - |rho u|^2 / (2 rho) - |B|^2 / 2, its minimum over the cells)
-    leaves cells with a negative pressure and falls back, by half of it is accepted --
-    the oracle's gate (conv_ref.physical) decides the same."""
+    margin of the state the correction is added to -- the state after the plain step
+    (E - |rho u|^2 / (2 rho) - |B|^2 / 2, its minimum over the cells) -- leaves cells with
+    a negative pressure and falls back, by half of it is accepted; the oracle's gate
+    (conv_ref.physical) decides the same."""
     torch, vlbm, nn = env
     sim = open_sim(env, "f64")
+    sim.vlbm_step(1)  # the gate judges the state after the plain step
     Q = sim.vlbm_moments()[0].reshape((8,) + OPEN_SHAPE[::-1])
     margin = float((Q[4] - 0.5 * (Q[1] ** 2 + Q[2] ** 2 + Q[3] ** 2) / Q[0]
                     - 0.5 * (Q[5] ** 2 + Q[6] ** 2 + Q[7] ** 2)).min())
@@ -761,18 +763,19 @@ def test_open_gate_rejects_an_unphysical_correction(env):
 def _oracle_corrected_open(op, f, net_o, steps, t0, bounds, norm):
     """The open-lattice corrected run from the oracle's parts: per step X = the moments
     of the populations, dQ = out_mean + out_std * Net((X - in_mean) / in_std) (no
-    projection), the gate on (X, dQ) with the positivity condition, one step with the
-    faces and the body (run_bc at time t0 + j), then f_{k,i} += w_i dQ_k if the gate
-    accepted.  Returns the applied
-    corrections and the decisions."""
+    projection), one step with the faces and the body (run_bc at time t0 + j), the gate
+    on (X', dQ) with X' the moments after that step and the positivity condition, then
+    f_{k,i} += w_i dQ_k if the gate accepted.  Returns the applied corrections and the
+    decisions."""
     in_mean, in_std, out_mean, out_std = (np.asarray(a, np.float64)[:, None, None, None] for a in norm)
     wts = np.array([op.w0] + [(1.0 - op.w0) / 6.0] * 6)
     applied, decisions = [], []
     for j in range(steps):
         X = oracle.moments(op, f)[0].reshape(8, op.nz, op.ny, op.nx)
         dQ = out_mean + out_std * net_o.forward(((X - in_mean) / in_std)[None])[0]
-        ok = C.gate(X, dQ, bounds[0], bounds[1], bounds[2], dim=3, gamma=5.0 / 3.0)
         oracle.run_bc(op, f, 1, t0 + j)
+        Xp = oracle.moments(op, f)[0].reshape(8, op.nz, op.ny, op.nx)
+        ok = C.gate(Xp, dQ, bounds[0], bounds[1], bounds[2], dim=3, gamma=5.0 / 3.0)
         if ok:
             f += wts[None, :, None] * dQ.reshape(8, 1, -1)
         applied.append(dQ if ok else np.zeros_like(dQ))
