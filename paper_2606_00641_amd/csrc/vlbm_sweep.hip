@@ -429,13 +429,16 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
   }
 }
 
-// Two cells per lane (FP16/BF16 storage, plain sweep of a periodic lattice without a
-// body): lane l of a workgroup takes cells x0 = 2 (b B + l) and x0 + 1 of its row (B
-// threads per workgroup, 2 B cells), so every plane access moves the 32-bit word of the
+// Two cells per lane (FP16/BF16 storage; the plain sweep, or with the BOX and FX forms
+// below the open D3Q7 lattice of the homogenized body): lane l of the workgroup that takes
+// segment b of a row takes cells x0 = 2 (b B + l) and x0 + 1 (B threads per workgroup,
+// 2 B cells per segment), so every plane access moves the 32-bit word of the
 // pair -- the low half is cell x0.  A wavefront instruction that moves 2 bytes per lane
 // runs far below HBM bandwidth on gfx950 (a streaming copy measured about 3 TB/s at 16
 // bits per lane against 5 TB/s at 32).  Each cell is decoded, collided and encoded as
-// in k_sweep (the same arithmetic, so the results are bitwise those of k_sweep).
+// in k_sweep: the same arithmetic, which the compiler may contract into fused
+// multiply-adds differently in the two kernels, so they agree to one rounding of the
+// stored value; the tilings of k_sweep2 agree bitwise.
 // Parity 1 reads f_{+x}(x) from slot(-x) of x - 1 and f_{-x}(x) from slot(+x) of x + 1:
 // a lane loads its own words of those slots, A = slot(-x)[x0, x0 + 1] and
 // W = slot(+x)[x0, x0 + 1], and forms its pairs from the neighbour lanes' words,
@@ -446,9 +449,35 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
 // go through LDS; at the ends of a workgroup that spans its row they wrap around the
 // row, else the end lanes read the neighbouring workgroup's boundary element, and
 // write the half that belongs to it, with 16-bit accesses (as k_sweep's lane exchange).
-template <int ST, int D, int MODEL, int PAR, int COLL>
-__global__ __launch_bounds__(256) void k_sweep2(const Grid g, const Phys ph, const Codec cd) {
+// BOX: the sweep of every cell outside the body's box (k_sweep's BODY 3); a cell of the
+// box still loads and relays its words but stores nothing of its own.
+// FX: the non-periodic x faces re-set inside the sweep as in k_sweep; x = 0 is the low
+// cell of its lane and x = nx - 1 the high one, so the zero-gradient neighbour is the
+// lane's other cell.
+//
+// Workgroups are numbered along a 1-D grid and dispatched to the eight XCDs in turn by
+// that number.  When several workgroups share a row (segments s = 0..S-1), the row's
+// segments take numbers eight apart, 8 S q + 8 s + j for row 8 q + j, so they run on
+// one XCD: the boundary words two neighbouring segments both load and each half-store
+// then meet in that XCD's L2 instead of being fetched from HBM by two of them.
+__device__ __forceinline__ void xcd_row_tile(int nseg, int nrows, int& seg, int& row) {
+  const int L = (int)blockIdx.x;
+  if (nseg == 1) {
+    seg = 0;
+    row = L;
+    return;
+  }
+  const int q = L / (8 * nseg), rem = L - q * 8 * nseg;
+  const int gsz = min(8, nrows - 8 * q);  // rows in this group (fewer in the last one)
+  seg = rem / gsz;
+  row = 8 * q + (rem - seg * gsz);
+}
+
+template <int ST, int D, int MODEL, int PAR, int COLL, bool BOX = false, bool FX = false>
+__global__ __launch_bounds__(256) void k_sweep2(const Grid g, const Phys ph, const Codec cd, const Body bd,
+                                                const Inflow in) {
   static_assert(ST == ST_F16 || ST == ST_BF16, "two cells per lane: 16-bit storage");
+  static_assert(!(BOX || FX) || (D == 3 && MODEL == 0), "body box, x faces: D3Q7 ideal MHD");
   using S = Store<ST>;
   using R = typename S::R;
   using H = typename S::T;
@@ -456,8 +485,10 @@ __global__ __launch_bounds__(256) void k_sweep2(const Grid g, const Phys ph, con
   constexpr int K = kNVars<MODEL>;
   __shared__ XchLds<unsigned, K, true> xl;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = (int)(blockDim.x >> 6);
-  const int y = blockIdx.y, z = blockIdx.z;
-  const int x0 = 2 * ((int)blockIdx.x * (int)blockDim.x + t);
+  int seg, rw;
+  xcd_row_tile(g.nx / (2 * (int)blockDim.x), g.ny * g.nz, seg, rw);
+  const int y = rw % g.ny, z = rw / g.ny;
+  const int x0 = 2 * (seg * (int)blockDim.x + t);
   const bool row = 2 * (int)blockDim.x == g.nx;
   const unsigned rowc = (unsigned)g.nx * ((unsigned)y + (unsigned)g.ny * (unsigned)z);
   const unsigned c = rowc + (unsigned)x0;
@@ -474,7 +505,7 @@ __global__ __launch_bounds__(256) void k_sweep2(const Grid g, const Phys ph, con
     }
   }
   // byte offsets of the elements just outside this workgroup's stretch of the row
-  const unsigned xa = (unsigned)(2 * (int)blockIdx.x * (int)blockDim.x), xb = xa + 2 * blockDim.x;
+  const unsigned xa = (unsigned)(2 * seg * (int)blockDim.x), xb = xa + 2 * blockDim.x;
   const unsigned cl = (rowc + (xa == 0 ? (unsigned)g.nx - 1u : xa - 1u)) * (unsigned)sizeof(H);
   const unsigned cr = (rowc + (xb == (unsigned)g.nx ? 0u : xb)) * (unsigned)sizeof(H);
 
@@ -524,6 +555,32 @@ __global__ __launch_bounds__(256) void k_sweep2(const Grid g, const Phys ph, con
     }
   }
 
+  bool inb[2] = {false, false};  // the cell lies in the body's box
+  if constexpr (BOX) {
+    const bool yz = y >= bd.box[2] && y < bd.box[3] && z >= bd.box[4] && z < bd.box[5];
+    inb[0] = yz && x0 >= bd.box[0] && x0 < bd.box[1];
+    inb[1] = yz && x0 + 1 >= bd.box[0] && x0 + 1 < bd.box[1];
+  }
+  bool face[2] = {false, false};  // x-face node on no other non-periodic face
+  R qn[FX ? 8 : 1];               // zero gradient: the moments of the lane's other cell
+  (void)qn;
+  if constexpr (FX) {
+    const bool yin = g.bc[2] == 0 || (y > 0 && y < g.ny - 1);
+    const bool zin = g.bc[4] == 0 || (z > 0 && z < g.nz - 1);
+    face[0] = x0 == 0 && g.bc[0] != 0 && yin && zin;
+    face[1] = x0 + 1 == g.nx - 1 && g.bc[1] != 0 && yin && zin;
+    if (face[0] || face[1]) {
+      const int sh = face[0] ? 16 : 0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        R a = R(0);
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) a += S::dec((H)(P[k][i] >> sh), cd, k * NQ + i);
+        qn[k] = a;
+      }
+    }
+  }
+
   // the two cells, one after the other; each result replaces the half it came from
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
@@ -532,6 +589,24 @@ __global__ __launch_bounds__(256) void k_sweep2(const Grid g, const Phys ph, con
     for (int k = 0; k < K; ++k)
 #pragma unroll
       for (int i = 0; i < NQ; ++i) f[k][i] = S::dec((H)(P[k][i] >> (16 * j)), cd, k * NQ + i);
+    if constexpr (FX) {
+      if (face[j]) {
+        const int side = j;  // x = 0 is always a low cell, x = nx - 1 a high one
+        R Qb[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) Qb[k] = g.bc[side] == 1 ? R(in.q[k]) : qn[k];
+        R Jb[3] = {R(0), R(0), R(0)};
+        R Pf[8][3], Sv[8], dlb;
+        flux_source<R, 3, 0>(Qb, Jb, ph, Pf, Sv, dlb);
+        const R wi = R(ph.wi);
+        const R w0 = rest_weight<R, 3>(wi);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+#pragma unroll
+          for (int i = 0; i < NQ; ++i)
+            f[k][i] = S::dec(S::enc(feq_dir<R, 3>(Qb[k], Pf[k], i, w0, wi), cd, k * NQ + i), cd, k * NQ + i);
+      }
+    }
     R dl;
     collide<R, D, MODEL, COLL>(f, ph, dl);
 #pragma unroll
@@ -543,20 +618,66 @@ __global__ __launch_bounds__(256) void k_sweep2(const Grid g, const Phys ph, con
       }
   }
 
-  if constexpr (PAR == 0) {
+  // BOX: a slot whose owner -- the cell whose outgoing population it receives -- lies in
+  // the box is not written (the box sweep that follows reads and writes it), so a word
+  // with one such half is stored as its other half.  own0/own1: cells x0, x0 + 1;
+  // ownl/ownr: the cells x0 - 1 and x0 + 2 whose populations the x-exchange words also
+  // carry.  The choice between the two store sequences is made once per wavefront:
+  // wavefronts that touch no box cell run the plain word stores as one straight block
+  // (a test per store split them into blocks of their own and made the sweep 30-50 % slower).
+  bool own0 = true, own1 = true, ownl = true, ownr = true, careful = false;
+  if constexpr (BOX) {
+    const bool yz = y >= bd.box[2] && y < bd.box[3] && z >= bd.box[4] && z < bd.box[5];
+    const int xl = x0 == 0 ? g.nx - 1 : x0 - 1, xr = x0 + 2 == g.nx ? 0 : x0 + 2;
+    own0 = !inb[0];
+    own1 = !inb[1];
+    ownl = !(yz && xl >= bd.box[0] && xl < bd.box[1]);
+    ownr = !(yz && xr >= bd.box[0] && xr < bd.box[1]);
+    careful = __builtin_amdgcn_ballot_w64(!(own0 && own1 && ownl && ownr)) != 0;
+  }
+  (void)ownl;
+  (void)ownr;
+  (void)careful;
+  auto put = [&](auto cf, int plane, unsigned off, unsigned v, bool lo, bool hi) {
+    if constexpr (decltype(cf)::value) {
+      if (lo && hi)
+        st<unsigned>(F, pb, plane, off, v);
+      else if (lo)
+        st_shifted<H>(F, pb, plane, off, (H)v);
+      else if (hi)
+        st_shifted<H>(F, pb, plane, off + (unsigned)sizeof(H), (H)(v >> 16));
+    } else {
+      st<unsigned>(F, pb, plane, off, v);
+    }
+  };
+  // every store but the parity-1 x slots
+  auto own_stores = [&](auto cf) {
+    if constexpr (PAR == 0) {
 #pragma unroll
-    for (int k = 0; k < K; ++k)
+      for (int k = 0; k < K; ++k)
 #pragma unroll
-      for (int i = 0; i < NQ; ++i) st<unsigned>(F, pb, k * NQ + opposite(i), co, P[k][i]);
+        for (int i = 0; i < NQ; ++i) put(cf, k * NQ + opposite(i), co, P[k][i], own0, own1);
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+          if (i == 1 || i == 2) continue;
+          const unsigned dst = (i == 0) ? co : ((i & 1) ? np[(i - 1) >> 1] : nm[(i - 1) >> 1]);
+          put(cf, k * NQ + i, dst, P[k][i], own0, own1);
+        }
+    }
+  };
+  if constexpr (BOX) {
+    if (careful)
+      own_stores(std::true_type{});
+    else
+      own_stores(std::false_type{});
   } else {
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-      for (int i = 0; i < NQ; ++i) {
-        if (i == 1 || i == 2) continue;
-        const unsigned dst = (i == 0) ? co : ((i & 1) ? np[(i - 1) >> 1] : nm[(i - 1) >> 1]);
-        st<unsigned>(F, pb, k * NQ + i, dst, P[k][i]);
-      }
+    own_stores(std::false_type{});
+  }
+
+  if constexpr (PAR == 1) {
     if (lane == 63) {
 #pragma unroll
       for (int k = 0; k < K; ++k) xl.hi[1][w][k] = P[k][1];
@@ -575,26 +696,40 @@ __global__ __launch_bounds__(256) void k_sweep2(const Grid g, const Phys ph, con
       right[k] = lane_shift<false>(xl.lo[1][wr][k], P[k][2]);
     }
     const bool first = !row && t == 0, last = !row && t == (int)blockDim.x - 1;
+    auto x_stores = [&](auto cf) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const unsigned vp = __builtin_amdgcn_alignbyte(P[k][1], left[k], 2);   // slot(+x) of x0, x0 + 1
-      const unsigned vm = __builtin_amdgcn_alignbyte(right[k], P[k][2], 2);  // slot(-x) of x0, x0 + 1
-      if (first) {
-        // x0 - 1 is the previous workgroup's: it writes slot(+x) of x0; this lane writes
-        // x0 + 1's, and slot(-x) of x0 - 1 (its own f_{-x}(x0))
-        st_shifted<H>(F, pb, k * NQ + 1, co + (unsigned)sizeof(H), (H)(vp >> 16));
-        st_shifted<H>(F, pb, k * NQ + 2, cl, (H)P[k][2]);
-      } else {
-        st<unsigned>(F, pb, k * NQ + 1, co, vp);
+      for (int k = 0; k < K; ++k) {
+        const unsigned vp = __builtin_amdgcn_alignbyte(P[k][1], left[k], 2);   // slot(+x) of x0, x0 + 1
+        const unsigned vm = __builtin_amdgcn_alignbyte(right[k], P[k][2], 2);  // slot(-x) of x0, x0 + 1
+        if (first) {
+          // x0 - 1 is the previous workgroup's: it writes slot(+x) of x0; this lane writes
+          // x0 + 1's, and slot(-x) of x0 - 1 (its own f_{-x}(x0))
+          if (own0) {
+            st_shifted<H>(F, pb, k * NQ + 1, co + (unsigned)sizeof(H), (H)(vp >> 16));
+            st_shifted<H>(F, pb, k * NQ + 2, cl, (H)P[k][2]);
+          }
+        } else {
+          put(cf, k * NQ + 1, co, vp, ownl, own0);
+        }
+        if (last) {
+          // x0 + 2 is the next workgroup's: this lane writes slot(-x) of x0 only, and
+          // slot(+x) of x0 + 2 (its own f_{+x}(x0 + 1))
+          if (own1) {
+            st_shifted<H>(F, pb, k * NQ + 2, co, (H)vm);
+            st_shifted<H>(F, pb, k * NQ + 1, cr, (H)(P[k][1] >> 16));
+          }
+        } else {
+          put(cf, k * NQ + 2, co, vm, own1, ownr);
+        }
       }
-      if (last) {
-        // x0 + 2 is the next workgroup's: this lane writes slot(-x) of x0 only, and
-        // slot(+x) of x0 + 2 (its own f_{+x}(x0 + 1))
-        st_shifted<H>(F, pb, k * NQ + 2, co, (H)vm);
-        st_shifted<H>(F, pb, k * NQ + 1, cr, (H)(P[k][1] >> 16));
-      } else {
-        st<unsigned>(F, pb, k * NQ + 2, co, vm);
-      }
+    };
+    if constexpr (BOX) {
+      if (careful)
+        x_stores(std::true_type{});
+      else
+        x_stores(std::false_type{});
+    } else {
+      x_stores(std::false_type{});
     }
   }
 }
@@ -676,33 +811,48 @@ hipError_t sweep_src_t(const Launch& L, const Grid& g, const Phys& ph, const Cod
 // k_sweep2 serves FP16/BF16 storage of the 8-, 5- and 9-variable models (the 26-variable
 // one's 182 packed words per lane do not fit the registers; the 13-component one's
 // pair sweep needs about 300 VGPRs at parity 1, one wavefront per SIMD, and measured
-// slower than its one-cell sweep: 3.7 against 4.5 TB/s) on periodic lattices without
-// a body, with the direct source.  Its workgroup width: the first of block_x,
-// block_x / 2, block_x / 4 that is a multiple of 64 and whose 2 x width cells tile
-// every x row; 0 if none does (the one-cell sweep runs).
-inline int pair_width(const Grid& g, int block_x) {
-  for (int f = 0; f < 6; ++f)
-    if (g.bc[f]) return 0;
+// slower than its one-cell sweep: 3.7 against 4.5 TB/s) with the direct source, on
+// lattices without a bounce-back mask: periodic ones, and D3Q7 ideal lattices with
+// static faces (x faces in the sweep, y and z faces in the face pass) and the
+// homogenized body (the sweep outside its box).  Its workgroup width: the first of
+// block_x, block_x / 2, block_x / 4 that is a multiple of 64 and whose 2 x width cells
+// tile every x row; 0 if none does (the one-cell sweep runs).
+inline int pair_width(const Grid& g, int block_x, bool faces) {
   if (g.mask) return 0;
+  for (int f = 0; f < 6; ++f)
+    if (g.bc[f] && !faces) return 0;
+  if (g.bc[0] && !fuse_x_faces(g)) return 0;
   for (int b = block_x, n = 0; n < 3 && b >= 64; b /= 2, ++n)
     if (b % 64 == 0 && g.nx % (2 * b) == 0) return b;
   return 0;
 }
 
-template <int ST, int D, int MODEL>
-hipError_t sweep2_t(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity, int bw) {
-  const dim3 grd((unsigned)(g.nx / (2 * bw)), (unsigned)g.ny, (unsigned)g.nz), blk((unsigned)bw);
-  if (parity == 0) {
-    if (ph.collision)
-      hipLaunchKernelGGL((k_sweep2<ST, D, MODEL, 0, 1>), grd, blk, 0, L.stream, g, ph, cd);
-    else
-      hipLaunchKernelGGL((k_sweep2<ST, D, MODEL, 0, 0>), grd, blk, 0, L.stream, g, ph, cd);
-  } else {
-    if (ph.collision)
-      hipLaunchKernelGGL((k_sweep2<ST, D, MODEL, 1, 1>), grd, blk, 0, L.stream, g, ph, cd);
-    else
-      hipLaunchKernelGGL((k_sweep2<ST, D, MODEL, 1, 0>), grd, blk, 0, L.stream, g, ph, cd);
-  }
+template <int ST, int D, int MODEL, bool BOX = false>
+hipError_t sweep2_t(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity, int bw,
+                    const Body& b = Body{}, const Inflow& in = Inflow{}) {
+  const dim3 grd((unsigned)((long long)(g.nx / (2 * bw)) * g.ny * g.nz)), blk((unsigned)bw);
+  constexpr bool kF = D == 3 && MODEL == 0;  // x faces possible
+  auto go = [&](auto par_c, auto coll_c, auto fx_c) {
+    constexpr int P = decltype(par_c)::value, C = decltype(coll_c)::value;
+    constexpr bool FXv = decltype(fx_c)::value;
+    hipLaunchKernelGGL((k_sweep2<ST, D, MODEL, P, C, BOX, FXv>), grd, blk, 0, L.stream, g, ph, cd, b, in);
+  };
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  auto with_fx = [&](auto par_c, auto coll_c) {
+    if constexpr (kF) {
+      if (g.bc[0]) return go(par_c, coll_c, std::true_type{});
+    }
+    go(par_c, coll_c, std::false_type{});
+  };
+  auto with_coll = [&](auto par_c) {
+    if (ph.collision) return with_fx(par_c, I1{});
+    with_fx(par_c, I0{});
+  };
+  if (parity == 0)
+    with_coll(I0{});
+  else
+    with_coll(I1{});
   return hipGetLastError();
 }
 
@@ -710,7 +860,8 @@ template <int ST, int D, int MODEL>
 hipError_t sweep_t(const Launch& L, const Grid& g, const Phys& ph, const Codec& cd, int parity, const Inflow& in) {
   if (ph.source != 0) return sweep_src_t<ST, D, MODEL>(L, g, ph, cd, parity);
   if constexpr ((ST == ST_F16 || ST == ST_BF16) && MODEL != 1 && MODEL != 4) {
-    if (const int bw = pair_width(g, L.block_x)) return sweep2_t<ST, D, MODEL>(L, g, ph, cd, parity, bw);
+    if (const int bw = pair_width(g, L.block_x, D == 3 && MODEL == 0))
+      return sweep2_t<ST, D, MODEL>(L, g, ph, cd, parity, bw, Body{}, in);
   }
   launch_k<ST, D, MODEL, 0, false>(L, cell_grid(g, L.block_x), parity, ph.collision, lane_exchange(g, L.block_x, MODEL),
                                    fuse_x_faces(g), g, ph, cd, Body{}, nullptr, nullptr, in);
@@ -741,8 +892,17 @@ hipError_t sweep_body_t(const Launch& L, const Grid& g, const Phys& ph, const Co
     // homogenized body: the plain sweep outside the body's box, then the homogenized
     // sweep of the box; the two update disjoint cells, each cell exactly once
     const int bx = b->box[1] - b->box[0], by = b->box[3] - b->box[2], bz = b->box[5] - b->box[4];
-    launch_k<ST, 3, 0, 3, false>(L, grd, parity, ph.collision, lane_exchange(g, L.block_x, 0), fx, g, ph, cd, *b,
-                                 nullptr, nullptr, in);
+    bool pair = false;
+    if constexpr (ST == ST_F16 || ST == ST_BF16) {
+      if (const int bw = pair_width(g, L.block_x, true)) {
+        const hipError_t e = sweep2_t<ST, 3, 0, true>(L, g, ph, cd, parity, bw, *b, in);
+        if (e != hipSuccess) return e;
+        pair = true;
+      }
+    }
+    if (!pair)
+      launch_k<ST, 3, 0, 3, false>(L, grd, parity, ph.collision, lane_exchange(g, L.block_x, 0), fx, g, ph, cd, *b,
+                                   nullptr, nullptr, in);
     if (bx > 0 && by > 0 && bz > 0) {
       const dim3 bgrd((unsigned)((bx + L.block_x - 1) / L.block_x), (unsigned)by, (unsigned)bz);
       launch_k<ST, 3, 0, 2, false>(L, bgrd, parity, ph.collision, false, false, g, ph, cd, *b, nullptr, nullptr, in);

@@ -10,10 +10,12 @@ taken on the kernel as it now stands.
 
 Usage: python -m paper_2606_00641_amd.pmc_traffic --fetch F.csv --write W.csv
        --key resistive_256/f32 --cells N --bytes-per-cell B --out traffic.json
-       [--kernel sweep|pair] [--merge]
---kernel pair takes the FP16/BF16 two-cells-per-lane sweep (k_sweep2) instead of the
-plain one-cell sweep; --merge adds the record to an existing file taken on the same
-sources.
+       [--kernel sweep|pair|pair_body] [--store-cells M] [--merge]
+--kernel pair takes the FP16/BF16 two-cells-per-lane sweep (k_sweep2) of a periodic
+lattice instead of the plain one-cell sweep, pair_body its form on the open lattice
+with the homogenized body, which loads every cell but stores nothing for the cells of
+the body's box (--store-cells: the cells it stores); --merge adds the record to an
+existing file taken on the same sources.
 """
 import argparse
 import csv
@@ -27,13 +29,18 @@ SWEEP_SOURCES = ("vlbm_device.h", "vlbm_kernels.h", "vlbm_physics.h", "vlbm_swee
 COPY_BYTES = 4 << 30
 
 
+_COMMENT = re.compile(r"//[^\n]*|/\*.*?\*/", re.S)
+
+
 def kernel_source_hash():
-    """Hash of the sources the sweep kernel is built from."""
+    """Hash of the code the sweep kernel is built from: its sources with the comments
+    taken out and the whitespace collapsed, so that a change of a comment leaves it."""
     h = hashlib.sha256()
     for name in SWEEP_SOURCES:
-        with open(os.path.join(CSRC, name), "rb") as fh:
-            h.update(name.encode())
-            h.update(fh.read())
+        with open(os.path.join(CSRC, name), encoding="utf-8") as fh:
+            code = " ".join(_COMMENT.sub(" ", fh.read()).split())
+        h.update(name.encode())
+        h.update(code.encode())
     return h.hexdigest()[:16]
 
 
@@ -66,18 +73,21 @@ def per_parity(rows, st, d, model):
     return {p: sum(v) / len(v) for p, v in sorted(acc.items())}
 
 
-PAIR_RE = re.compile(r"k_sweep2<(\d+), (\d+), (\d+), (\d+), (\d+)>")
+PAIR_RE = re.compile(r"k_sweep2<(\d+), (\d+), (\d+), (\d+), (\d+), (true|false), (true|false)>")
 
 
-def per_parity_pair(rows, st, d, model):
-    """Mean KiB per dispatch of the two-cells-per-lane BGK sweep for each parity."""
+def per_parity_pair(rows, st, d, model, body=False):
+    """Mean KiB per dispatch of the two-cells-per-lane BGK sweep for each parity: the
+    plain periodic one, or (body) the one of an open lattice with the homogenized body
+    (x faces in the sweep, the body's box left to the box sweep)."""
     acc = {}
     for name, v in rows:
         m = PAIR_RE.search(name)
         if not m:
             continue
-        ST, D, MODEL, PAR, COLL = (int(x) for x in m.groups())
-        if (ST, D, MODEL, COLL) != (st, d, model, 0):
+        ST, D, MODEL, PAR, COLL = (int(x) for x in m.groups()[:5])
+        flags = m.groups()[5:]
+        if (ST, D, MODEL, COLL) != (st, d, model, 0) or flags != (("true", "true") if body else ("false", "false")):
             continue
         acc.setdefault(PAR, []).append(v)
     return {p: sum(v) / len(v) for p, v in sorted(acc.items())}
@@ -101,7 +111,10 @@ def main():
     ap.add_argument("--cells", type=int, required=True)
     ap.add_argument("--bytes-per-cell", type=int, required=True)
     ap.add_argument("--commands", nargs="*", default=[])
-    ap.add_argument("--kernel", choices=("sweep", "pair"), default="sweep")
+    ap.add_argument("--store-cells", type=int, default=None,
+                    help="cells whose populations the kernel stores (default --cells; the body form stores "
+                         "nothing for the cells of the body's box)")
+    ap.add_argument("--kernel", choices=("sweep", "pair", "pair_body"), default="sweep")
     ap.add_argument("--merge", action="store_true", help="add the record to an existing --out file")
     ap.add_argument("--out", required=True)
     args = ap.parse_args()
@@ -111,22 +124,30 @@ def main():
     cf, cw = copy_kib(fr), copy_kib(wr)
     fetch_factor = COPY_BYTES / (cf * 1024.0)
     write_factor = COPY_BYTES / (cw * 1024.0)
-    select = per_parity if args.kernel == "sweep" else per_parity_pair
+    if args.kernel == "sweep":
+        select = per_parity
+    else:
+        def select(rows, st, d, model):
+            return per_parity_pair(rows, st, d, model, body=args.kernel == "pair_body")
     pf = select(fr, args.storage, args.dim_code, args.model)
     pw = select(wr, args.storage, args.dim_code, args.model)
     if not pf or set(pf) != set(pw):
         raise SystemExit(f"sweep dispatches missing: fetch parities {sorted(pf)}, write parities {sorted(pw)}")
     fetch_b = sum(pf.values()) / len(pf) * 1024.0 * fetch_factor
     write_b = sum(pw.values()) / len(pw) * 1024.0 * write_factor
-    algo = args.cells * args.bytes_per_cell
+    store_cells = args.cells if args.store_cells is None else args.store_cells
+    algo = (args.cells + store_cells) * args.bytes_per_cell // 2
     kname = "k_sweep" if args.kernel == "sweep" else "k_sweep2 (two cells per lane)"
+    form = "homogenized body outside its box, x faces" if args.kernel == "pair_body" else "no body"
     rec = {
-        "kernel": f"{kname}<storage {args.storage}, lattice {args.dim_code}, model {args.model}, parity, no body, BGK>",
+        "kernel": f"{kname}<storage {args.storage}, lattice {args.dim_code}, model {args.model}, parity, {form}, BGK>",
         "per_parity_raw_kib": {str(p): {"fetch_kib": pf[p], "write_kib": pw[p]} for p in pf},
         "fetch_bytes_per_launch": round(fetch_b),
         "write_bytes_per_launch": round(write_b),
         "bytes_per_launch": round(fetch_b + write_b),
         "algorithmic_bytes_per_launch": algo,
+        "cells_loaded": args.cells,
+        "cells_stored": store_cells,
         "ratio_to_algorithmic": round((fetch_b + write_b) / algo, 4),
     }
     rec["copy_kernel"] = {"FETCH_SIZE_kib": cf, "WRITE_SIZE_kib": cw, "fetch_factor": round(fetch_factor, 5),

@@ -178,6 +178,86 @@ def test_homogenized_body_lane_exchange(vb, block_x):
     assert max(d.values()) < 1e-6, d
 
 
+@pytest.mark.parametrize("storage,ulp", [("f16", 2.0 ** -11), ("bf16", 2.0 ** -8)])
+@pytest.mark.parametrize("body_x", [9.3, 127.6, None])
+def test_pair_sweep_faces_and_body(vb, storage, ulp, body_x):
+    """FP16/BF16 storage sweeps two cells per lane on the open lattice too: x faces in
+    the sweep (x = 0 the low cell of its lane, x = nx - 1 the high one) and the
+    homogenized body's box left to the box sweep (a lane with one cell in the box stores
+    only the other half of its words).  256 x 22 x 20, inflow and zero-gradient faces;
+    the body inside the first wavefront (its box x = 3..16 at steps 5-6: both edges
+    split a lane), across the boundary at x = 128 between two 64-thread workgroups
+    (box 121..135), or no body.  Workgroups of 64 threads (two per row, the end lanes'
+    16-bit accesses) and 128 (one per row) take the pair sweep.  After 5 steps, one step
+    of each parity from the GPU's own pre-step populations: every population that comes
+    from a cell off the faces equals the oracle's boundary step (homogenized body) up to
+    one rounding of the stored deviation; every population, the face nodes' outputs
+    included (their input is f^eq rounded to the storage, as the oracle does not round
+    it), equals to that rounding the one-cell sweep (192-thread workgroups, which the
+    pair sweep cannot tile) of the same pre-step populations.  The two pair tilings give
+    identical bits."""
+    import torch
+    shape = (256, 22, 20)
+    nx, ny, nz = shape
+    Qin, _ = synth.inflow_state(mach=0.8, alfven_mach=4.0)
+    Q0 = np.broadcast_to(Qin[:, None, None, None], (8,) + shape[::-1]).copy()
+    Q0 += 0.3 * (synth.smooth_box_state(shape[::-1], seed=12, amp=0.05, rho=0.0, p=0.0, B0=0.0))
+    body = None
+    if body_x is not None:
+        body = synth.rough_body((body_x, 10.1, 9.7), (0.08, 0.04, 0.02), 4.6, m=(3.0, -2.0, 1.5), rough=0.12, seed=5)
+        body["mode"] = 2
+    bc = (1, 2, 2, 2, 2, 2)
+    op = oracle.make_params(dim=3, shape=shape, s=0.1, tau=0.7)
+    oracle.set_boundaries(op, bc=bc, inflow_Q=Qin, body=body, body_mode=2)
+    cells = np.arange(nx * ny * nz)
+    x, y, z = cells % nx, (cells // nx) % ny, cells // (nx * ny)
+    face = (x == 0) | (x == nx - 1) | (y == 0) | (y == ny - 1) | (z == 0) | (z == nz - 1)
+    # population i of cell c after the step is the output of its upstream cell c - e_i
+    from_face = np.empty((len(cells), 7), bool)
+    from_face[:, 0] = face
+    for i, (dx, dy, dz) in enumerate(((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)), 1):
+        from_face[:, i] = face[(x - dx) % nx + nx * ((y - dy) % ny + ny * ((z - dz) % nz))]
+    interior = np.broadcast_to(~from_face[:, None, :], (len(cells), 8, 7))
+    wts = np.array([0.25] + [0.125] * 6)
+
+    def make(block_x):
+        return vb.Vlbm(vb.make_params(lattice="D3Q7", shape=shape, model="ideal", storage=storage, flux_scale=0.1,
+                                      tau=0.7, bc=bc, inflow_Q=Qin, body=body, stream=_stream(), block_x=block_x))
+
+    one = make(192)
+    one.vlbm_init_fields(Q0)  # the same initial state fixes the same FP16/BF16 codec
+    bufs = []
+    for block_x in (64, 128):
+        print("case pair faces/body", storage, body_x, block_x, flush=True)
+        sim = make(block_x)
+        sim.vlbm_init_fields(Q0)
+        sim.vlbm_step(5)
+        rest_Q, sigma = sim.vlbm_get_codec()
+        f_rest = oracle.equilibrium(op, rest_Q)
+        sc = sigma[:, None] * wts[None, :]
+        for _ in range(2):
+            t = sim.vlbm_get_step()
+            one.vlbm_set_populations(*sim.vlbm_get_populations())
+            pre = sim.vlbm_gather_cells(cells)
+            f = np.ascontiguousarray(np.transpose(pre, (1, 2, 0)))
+            oracle.run_bc(op, f, 1, t)
+            sim.vlbm_step(1)
+            one.vlbm_step(1)
+            torch.cuda.synchronize()
+            got = sim.vlbm_gather_cells(cells)
+            want = np.transpose(f, (2, 0, 1))
+            bound = sc[None] * (2 * ulp * np.abs(want - f_rest[None]) / sc[None] + 2.0 ** -24) \
+                + 4e-6 + 2e-6 * np.abs(want)
+            err = np.where(interior, np.abs(got - want), 0.0)
+            assert np.all(err <= bound), (block_x, t % 2, float((err / bound).max()))
+            d = np.abs(got - one.vlbm_gather_cells(cells))
+            assert np.all(d <= bound), (block_x, t % 2, float((d / bound).max()))
+        bufs.append(sim.vlbm_get_populations()[0])
+        sim.vlbm_destroy()
+    one.vlbm_destroy()
+    assert np.array_equal(bufs[0], bufs[1]), int(np.count_nonzero(bufs[0] != bufs[1]))
+
+
 @pytest.mark.parametrize("storage,tol", [("f64", 1e-10), ("f32", 1e-5)])
 @pytest.mark.parametrize("steps", [13, 14])
 def test_body_loads_parity(vb, storage, tol, steps):
