@@ -56,6 +56,26 @@ struct XchLds {
 template <typename T, int K>
 struct XchLds<T, K, false> {};
 
+// Workgroups that share x rows (the lane exchanges of k_sweep and k_sweep2) are numbered
+// along a 1-D grid, and the hardware deals them to the eight XCDs in turn by that
+// number.  When several workgroups share a row (segments s = 0..S-1), the row's segments
+// take numbers eight apart, 8 S q + 8 s + j for row 8 q + j, so they run on one XCD: the
+// boundary elements two neighbouring segments both touch then meet in that XCD's L2
+// instead of being fetched from HBM by two of them.
+__device__ __forceinline__ void xcd_row_tile(int nseg, int nrows, int& seg, int& row) {
+  const int L = (int)blockIdx.x;
+  if (nseg == 1) {
+    seg = 0;
+    row = L;
+    return;
+  }
+  const int q = L / (8 * nseg), rem = L - q * 8 * nseg;
+  const int gsz = min(8, nrows - 8 * q);  // rows in this group (fewer in the last one)
+  seg = rem / gsz;
+  row = 8 * q + (rem - seg * gsz);
+}
+
+
 // XCH (parity 1, plain sweep, workgroups tiling every x row exactly): the +-x
 // populations are read and written at the cell's own, aligned slots and passed
 // between neighbouring lanes instead of being accessed one element off the
@@ -96,7 +116,18 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
   __shared__ XchLds<T, K, XCH> xl;
   // BODY 2 runs over the body's box only (grid = box extent, offset by its corner);
   // BODY 3 is the plain sweep of every other cell.
-  int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+  int x, y, z;
+  if constexpr (XCH) {
+    int seg, rw;
+    xcd_row_tile(g.nx / (int)blockDim.x, g.ny * g.nz, seg, rw);
+    x = seg * (int)blockDim.x + (int)threadIdx.x;
+    y = rw % g.ny;
+    z = rw / g.ny;
+  } else {
+    x = blockIdx.x * blockDim.x + threadIdx.x;
+    y = blockIdx.y;
+    z = blockIdx.z;
+  }
   if constexpr (BODY == 2) {
     x += bd.box[0];
     y += bd.box[2];
@@ -189,7 +220,7 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
     // edge value, or (ends of a workgroup that does not span the row) the
     // neighbouring workgroup's cell, at a wavefront-uniform address
     const unsigned rowc = (unsigned)g.nx * ((unsigned)y + (unsigned)g.ny * (unsigned)z);
-    const unsigned x0 = blockIdx.x * blockDim.x, x1 = x0 + blockDim.x;
+    const unsigned x0 = (unsigned)(x - t), x1 = x0 + blockDim.x;
     const unsigned cl = (rowc + (x0 == 0 ? (unsigned)g.nx - 1u : x0 - 1u)) * ES;
     const unsigned cr = (rowc + (x1 == (unsigned)g.nx ? 0u : x1)) * ES;
     T el[K], er[K];
@@ -453,26 +484,7 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
 // box still loads and relays its words but stores nothing of its own.
 // FX: the non-periodic x faces re-set inside the sweep as in k_sweep; x = 0 is the low
 // cell of its lane and x = nx - 1 the high one, so the zero-gradient neighbour is the
-// lane's other cell.
-//
-// Workgroups are numbered along a 1-D grid and dispatched to the eight XCDs in turn by
-// that number.  When several workgroups share a row (segments s = 0..S-1), the row's
-// segments take numbers eight apart, 8 S q + 8 s + j for row 8 q + j, so they run on
-// one XCD: the boundary words two neighbouring segments both load and each half-store
-// then meet in that XCD's L2 instead of being fetched from HBM by two of them.
-__device__ __forceinline__ void xcd_row_tile(int nseg, int nrows, int& seg, int& row) {
-  const int L = (int)blockIdx.x;
-  if (nseg == 1) {
-    seg = 0;
-    row = L;
-    return;
-  }
-  const int q = L / (8 * nseg), rem = L - q * 8 * nseg;
-  const int gsz = min(8, nrows - 8 * q);  // rows in this group (fewer in the last one)
-  seg = rem / gsz;
-  row = 8 * q + (rem - seg * gsz);
-}
-
+// lane's other cell.  The workgroups are numbered by xcd_row_tile.
 template <int ST, int D, int MODEL, int PAR, int COLL, bool BOX = false, bool FX = false>
 __global__ __launch_bounds__(256) void k_sweep2(const Grid g, const Phys ph, const Codec cd, const Body bd,
                                                 const Inflow in) {
@@ -756,7 +768,9 @@ void launch_k(const Launch& L, dim3 grd, int parity, int coll, bool xch, bool fx
   auto go = [&](auto par_c, auto coll_c, auto xch_c, auto fx_c) {
     constexpr int P = decltype(par_c)::value, C = decltype(coll_c)::value;
     constexpr bool X = decltype(xch_c)::value, FXv = decltype(fx_c)::value;
-    hipLaunchKernelGGL((k_sweep<ST, D, MODEL, P, BODY, C, INJ, X, FXv>), grd, dim3(L.block_x), 0, L.stream, g, ph,
+    // the lane exchange numbers its workgroups along a 1-D grid (xcd_row_tile)
+    const dim3 grid = X ? dim3((unsigned)((long long)(g.nx / L.block_x) * g.ny * g.nz)) : grd;
+    hipLaunchKernelGGL((k_sweep<ST, D, MODEL, P, BODY, C, INJ, X, FXv>), grid, dim3(L.block_x), 0, L.stream, g, ph,
                        cd, b, dq, flag, in, mo);
   };
   using I0 = std::integral_constant<int, 0>;
