@@ -266,6 +266,9 @@ vlbm_status vlbm_step_one(vlbm_ctx* c) {
   Body b = c->body;
   b.t = (double)c->step;
   if (c->p.body == 2) hlbm_box(c, b.t, b.box);
+  // bounce-back: every solid cell and every cut link lies in the box of the body's
+  // position at this step (the FP16/BF16 sweep leaves that box to the one-cell sweep)
+  if (c->p.body == 1) body_box(c, b.t, b.t, b.box);
   hipError_t e = launch_sweep_body(c->L, c->g, c->ph, c->cd, par, b, c->p.body, c->inflow);
   if (e != hipSuccess) return hip_fail(c, e, "sweep launch");
   ++c->step;

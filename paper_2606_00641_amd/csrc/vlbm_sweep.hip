@@ -87,8 +87,9 @@ __device__ __forceinline__ void xcd_row_tile(int nseg, int nrows, int& seg, int&
 // LDS; at the ends of a workgroup that spans a whole row they wrap around the row
 // (periodic), else the end lanes read and write the neighbouring workgroup's cell
 // directly, one element each.
-// BODY (D3Q7 ideal): solid cells are skipped; a link i whose neighbour x + e_i is
-// solid returns the post-collision population into direction opposite(i) of the
+// BODY 1 (D3Q7 ideal, every cell) and BODY 4 (the same over the body's box only, the
+// grid offset by its corner as for BODY 2): solid cells are skipped; a link i whose
+// neighbour x + e_i is solid returns the post-collision population into direction opposite(i) of the
 // same cell -- halfway bounce-back with the moving-wall flux correction for rho and
 // E, anti-bounce-back to rho u_w and to the dipole field at the link midpoint for
 // rho u and B.  In the AA layout that population belongs at slot i of cell x + e_i
@@ -112,7 +113,9 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
   constexpr int K = kNVars<MODEL>;
   constexpr unsigned ES = sizeof(T);
   static_assert(!XCH || (PAR == 1 && (BODY == 0 || BODY == 3)), "lane exchange: plain sweep at parity 1");
-  static_assert(!FX || (D == 3 && MODEL == 0 && BODY != 2 && !INJ), "x faces: D3Q7 ideal MHD");
+  static_assert(!FX || (D == 3 && MODEL == 0 && BODY != 2 && BODY != 4 && !INJ), "x faces: D3Q7 ideal MHD");
+  constexpr bool kBB = BODY == 1 || BODY == 4;     // link-wise bounce-back (mask)
+  constexpr bool kInBox = BODY == 2 || BODY == 4;  // grid over the body's box
   __shared__ XchLds<T, K, XCH> xl;
   // BODY 2 runs over the body's box only (grid = box extent, offset by its corner);
   // BODY 3 is the plain sweep of every other cell.
@@ -128,7 +131,7 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
     y = blockIdx.y;
     z = blockIdx.z;
   }
-  if constexpr (BODY == 2) {
+  if constexpr (kInBox) {
     x += bd.box[0];
     y += bd.box[2];
     z += bd.box[4];
@@ -158,14 +161,14 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
   void* const F = g.f;
   const size_t pb = (size_t)g.stride * ES;
   unsigned mk = 0;
-  if constexpr (BODY == 1) {
+  if constexpr (kBB) {
     mk = g.mask[c];
     if (mk & kSolid) return;
   }
 
   // byte offsets of this cell and of its neighbours x + e_a (np), x - e_a (nm)
   unsigned np[3], nm[3];
-  if constexpr (PAR == 1 || BODY == 1) {
+  if constexpr (PAR == 1 || kBB) {
     neighbours<D>(g, x, y, z, c, np, nm);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -302,7 +305,7 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
   }
 
   R dl;
-  if constexpr (BODY != 1) {
+  if constexpr (!kBB) {
     if constexpr (BODY == 2) {
       static_assert(D == 3 && MODEL == 0, "homogenized body: D3Q7 ideal MHD");
       R Q[K], pt;
@@ -763,7 +766,7 @@ void launch_k(const Launch& L, dim3 grd, int parity, int coll, bool xch, bool fx
               const Codec& cd, const Body& b, const float* dq, const int* flag, const Inflow& in,
               const MomentsOut& mo = MomentsOut{}) {
   constexpr bool kX = MODEL != 1 && (BODY == 0 || BODY == 3);  // exchange possible
-  constexpr bool kF = D == 3 && MODEL == 0 && BODY != 2 && !INJ;  // x faces possible
+  constexpr bool kF = D == 3 && MODEL == 0 && BODY != 2 && BODY != 4 && !INJ;  // x faces possible
   constexpr bool kC = !INJ;                                      // two-rate collisions possible
   auto go = [&](auto par_c, auto coll_c, auto xch_c, auto fx_c) {
     constexpr int P = decltype(par_c)::value, C = decltype(coll_c)::value;
@@ -826,13 +829,14 @@ hipError_t sweep_src_t(const Launch& L, const Grid& g, const Phys& ph, const Cod
 // one's 182 packed words per lane do not fit the registers; the 13-component one's
 // pair sweep needs about 300 VGPRs at parity 1, one wavefront per SIMD, and measured
 // slower than its one-cell sweep: 3.7 against 4.5 TB/s) with the direct source, on
-// lattices without a bounce-back mask: periodic ones, and D3Q7 ideal lattices with
-// static faces (x faces in the sweep, y and z faces in the face pass) and the
-// homogenized body (the sweep outside its box).  Its workgroup width: the first of
-// block_x, block_x / 2, block_x / 4 that is a multiple of 64 and whose 2 x width cells
-// tile every x row; 0 if none does (the one-cell sweep runs).
-inline int pair_width(const Grid& g, int block_x, bool faces) {
-  if (g.mask) return 0;
+// periodic lattices, and D3Q7 ideal lattices with static faces (x faces in the sweep, y
+// and z faces in the face pass) and a body -- the sweep outside the body's box, the box
+// left to a one-cell sweep (mask_ok: the caller handles the bounce-back mask that way).
+// Its workgroup width: the first of block_x, block_x / 2, block_x / 4 that is a multiple
+// of 64 and whose 2 x width cells tile every x row; 0 if none does (the one-cell sweep
+// runs).
+inline int pair_width(const Grid& g, int block_x, bool faces, bool mask_ok = false) {
+  if (g.mask && !mask_ok) return 0;
   for (int f = 0; f < 6; ++f)
     if (g.bc[f] && !faces) return 0;
   if (g.bc[0] && !fuse_x_faces(g)) return 0;
@@ -900,12 +904,29 @@ hipError_t sweep_body_t(const Launch& L, const Grid& g, const Phys& ph, const Co
                         const Body* b, int what, const Inflow& in) {
   const dim3 grd = cell_grid(g, L.block_x);
   const bool fx = fuse_x_faces(g);
+  const int bx = b->box[1] - b->box[0], by = b->box[3] - b->box[2], bz = b->box[5] - b->box[4];
   if (what == 1) {
+    // FP16/BF16: the two-cell sweep outside the body's box, which holds every solid cell
+    // and every cut link, and the one-cell bounce-back sweep of the box (the two update
+    // disjoint cells); the box must keep clear of the x faces the pair sweep re-sets and
+    // of the cells next to them, whose moments a zero-gradient face takes
+    if constexpr (ST == ST_F16 || ST == ST_BF16) {
+      const int bw = pair_width(g, L.block_x, true, true);
+      if (bw && b->box[0] > 1 && b->box[1] < g.nx - 1) {
+        const hipError_t e = sweep2_t<ST, 3, 0, true>(L, g, ph, cd, parity, bw, *b, in);
+        if (e != hipSuccess) return e;
+        if (bx > 0 && by > 0 && bz > 0) {
+          const dim3 bgrd((unsigned)((bx + L.block_x - 1) / L.block_x), (unsigned)by, (unsigned)bz);
+          launch_k<ST, 3, 0, 4, false>(L, bgrd, parity, ph.collision, false, false, g, ph, cd, *b, nullptr, nullptr,
+                                       in);
+        }
+        return hipGetLastError();
+      }
+    }
     launch_k<ST, 3, 0, 1, false>(L, grd, parity, ph.collision, false, fx, g, ph, cd, *b, nullptr, nullptr, in);
   } else {
     // homogenized body: the plain sweep outside the body's box, then the homogenized
     // sweep of the box; the two update disjoint cells, each cell exactly once
-    const int bx = b->box[1] - b->box[0], by = b->box[3] - b->box[2], bz = b->box[5] - b->box[4];
     bool pair = false;
     if constexpr (ST == ST_F16 || ST == ST_BF16) {
       if (const int bw = pair_width(g, L.block_x, true)) {
