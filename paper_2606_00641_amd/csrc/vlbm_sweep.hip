@@ -906,22 +906,28 @@ hipError_t sweep_body_t(const Launch& L, const Grid& g, const Phys& ph, const Co
   const bool fx = fuse_x_faces(g);
   const int bx = b->box[1] - b->box[0], by = b->box[3] - b->box[2], bz = b->box[5] - b->box[4];
   if (what == 1) {
-    // FP16/BF16: the two-cell sweep outside the body's box, which holds every solid cell
-    // and every cut link, and the one-cell bounce-back sweep of the box (the two update
-    // disjoint cells); the box must keep clear of the x faces the pair sweep re-sets and
-    // of the cells next to them, whose moments a zero-gradient face takes
-    if constexpr (ST == ST_F16 || ST == ST_BF16) {
-      const int bw = pair_width(g, L.block_x, true, true);
-      if (bw && b->box[0] > 1 && b->box[1] < g.nx - 1) {
-        const hipError_t e = sweep2_t<ST, 3, 0, true>(L, g, ph, cd, parity, bw, *b, in);
-        if (e != hipSuccess) return e;
-        if (bx > 0 && by > 0 && bz > 0) {
-          const dim3 bgrd((unsigned)((bx + L.block_x - 1) / L.block_x), (unsigned)by, (unsigned)bz);
-          launch_k<ST, 3, 0, 4, false>(L, bgrd, parity, ph.collision, false, false, g, ph, cd, *b, nullptr, nullptr,
-                                       in);
+    // the plain sweep outside the body's box, which holds every solid cell and every cut
+    // link (two cells per lane in FP16/BF16, else one with the lane exchange), and the
+    // one-cell bounce-back sweep of the box; the two update disjoint cells.  The box must
+    // keep clear of the x faces the outside sweep re-sets and of the cells next to them,
+    // whose moments a zero-gradient face takes; else the bounce-back sweep takes every cell.
+    if (b->box[0] > 1 && b->box[1] < g.nx - 1) {
+      bool pair = false;
+      if constexpr (ST == ST_F16 || ST == ST_BF16) {
+        if (const int bw = pair_width(g, L.block_x, true, true)) {
+          const hipError_t e = sweep2_t<ST, 3, 0, true>(L, g, ph, cd, parity, bw, *b, in);
+          if (e != hipSuccess) return e;
+          pair = true;
         }
-        return hipGetLastError();
       }
+      if (!pair)
+        launch_k<ST, 3, 0, 3, false>(L, grd, parity, ph.collision, lane_exchange(g, L.block_x, 0), fx, g, ph, cd, *b,
+                                     nullptr, nullptr, in);
+      if (bx > 0 && by > 0 && bz > 0) {
+        const dim3 bgrd((unsigned)((bx + L.block_x - 1) / L.block_x), (unsigned)by, (unsigned)bz);
+        launch_k<ST, 3, 0, 4, false>(L, bgrd, parity, ph.collision, false, false, g, ph, cd, *b, nullptr, nullptr, in);
+      }
+      return hipGetLastError();
     }
     launch_k<ST, 3, 0, 1, false>(L, grd, parity, ph.collision, false, fx, g, ph, cd, *b, nullptr, nullptr, in);
   } else {
