@@ -100,10 +100,17 @@ __device__ __forceinline__ void xcd_row_tile(int nseg, int nrows, int& seg, int&
 // moments; dq FP32 [K][N], control block dqctl as launch_sweep_inj describes).
 // Occupancy: the FP32 26-variable sweep needs 256 VGPRs + 26 AGPRs at parity 0,
 // one wavefront per SIMD; bounding it to two per SIMD costs 48 B of scratch per lane
-// and was measured 4-5 % faster (at parity 1 the bound spills more and is slower).
+// and was measured 4-5 % faster (at parity 1 the bound spills more and is slower).  The
+// FP16/BF16 13-component sweep at parity 1 is bounded to three wavefronts per SIMD (FP16
+// 173 -> 151 VGPRs, no spill): with the XCD-grouped workgroup order of the lane exchange
+// it then runs 12 % (FP16) and 14 % (BF16) faster on 4096^2 than with the row grid, where
+// at two wavefronts per SIMD the same order had made FP16 19 % slower.
 template <int ST, int D, int MODEL, int PAR, int BODY = 0, int COLL = 0, bool INJ = false, bool XCH = false,
           bool FX = false, int SRC = 0>
-__global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COLL == 0) ? 2 : 1) void k_sweep(
+__global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COLL == 0)
+                                      ? 2
+                                      : ((MODEL == 4 && (ST == ST_F16 || ST == ST_BF16) && PAR == 1 && COLL == 0) ? 3 : 1))
+    void k_sweep(
     const Grid g, const Phys ph, const Codec cd, const Body bd, const float* __restrict__ dq,
     const int* __restrict__ dqctl, const Inflow in, const MomentsOut mo) {
   using S = Store<ST>;
@@ -120,7 +127,7 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
   // BODY 2 runs over the body's box only (grid = box extent, offset by its corner);
   // BODY 3 is the plain sweep of every other cell.
   int x, y, z;
-  if constexpr (XCH && D == 3) {  // 2D lattices keep the row grid (see launch_k)
+  if constexpr (XCH) {
     int seg, rw;
     xcd_row_tile(g.nx / (int)blockDim.x, g.ny * g.nz, seg, rw);
     x = seg * (int)blockDim.x + (int)threadIdx.x;
@@ -771,11 +778,8 @@ void launch_k(const Launch& L, dim3 grd, int parity, int coll, bool xch, bool fx
   auto go = [&](auto par_c, auto coll_c, auto xch_c, auto fx_c) {
     constexpr int P = decltype(par_c)::value, C = decltype(coll_c)::value;
     constexpr bool X = decltype(xch_c)::value, FXv = decltype(fx_c)::value;
-    // the lane exchange on 3D lattices numbers its workgroups along a 1-D grid
-    // (xcd_row_tile).  On the 13-component 2D lattice (4096^2, sixteen workgroups per
-    // row) that order measured -19 % in FP16 storage, +14 % in BF16 and -1 % in FP32,
-    // reproducibly and with the same registers, so 2D lattices keep the row grid.
-    const dim3 grid = (X && D == 3) ? dim3((unsigned)((long long)(g.nx / L.block_x) * g.ny * g.nz)) : grd;
+    // the lane exchange numbers its workgroups along a 1-D grid (xcd_row_tile)
+    const dim3 grid = X ? dim3((unsigned)((long long)(g.nx / L.block_x) * g.ny * g.nz)) : grd;
     hipLaunchKernelGGL((k_sweep<ST, D, MODEL, P, BODY, C, INJ, X, FXv>), grid, dim3(L.block_x), 0, L.stream, g, ph,
                        cd, b, dq, flag, in, mo);
   };
