@@ -636,12 +636,14 @@ __global__ __launch_bounds__(kGateThreads) void k_gate_partials(const float* __r
   if ((int)threadIdx.x < NP) {
     double sum = 0.0;
     for (int w = 0; w < kGateThreads / 64; ++w) sum += sh[w][threadIdx.x];
-    partial[((size_t)b * gridDim.x + blockIdx.x) * NP + threadIdx.x] = sum;
+    // sum-major, [kGateNP][all workgroups]: the decision kernel reads each sum's
+    // workgroup values with whole-line loads
+    partial[(size_t)threadIdx.x * gridDim.x * gridDim.y + (size_t)b * gridDim.x + blockIdx.x] = sum;
   }
 }
 
-// The decision and the projection's means, one workgroup.  partial: nb lattices x gbpl
-// workgroups x kGateNP sums (k_gate_partials); ncl cells per lattice.
+// The decision and the projection's means, one workgroup.  partial: kGateNP sums x (nb
+// lattices x gbpl workgroups), sum-major (k_gate_partials); ncl cells per lattice.
 // With project: mean m[b][k] = (float)(sum over lattice b of r_k / ncl), written to the
 // control block ctl (layout of launch_sweep_inj) -- for one lattice from the batch-wide
 // sums; for a batch the (lattice, channel) pairs are taken by groups of G threads (a
@@ -671,7 +673,7 @@ __global__ __launch_bounds__(kFinalThreads) void k_gate_final(const double* __re
   for (int j = 0; j < NR; ++j) t[j] = 0.0;
 #pragma unroll 4
   for (int w = (int)threadIdx.x; w < nblk; w += kFinalThreads)
-    for (int j = 0; j < NP; ++j) t[j] += partial[(size_t)w * NP + j];
+    for (int j = 0; j < NP; ++j) t[j] += partial[(size_t)j * nblk + w];
   // per-lattice sums of a batch (one lattice: the batch-wide sums serve, below)
   if (project && nb > 1) {
     const int P = 8 * nb;
@@ -682,9 +684,9 @@ __global__ __launch_bounds__(kFinalThreads) void k_gate_final(const double* __re
       const int p = p0 + g;
       double s1 = 0.0;
       if (p < P) {
-        const double* q = partial + (size_t)(p >> 3) * gbpl * NP + 8 + (p & 7);
+        const double* q = partial + (size_t)(8 + (p & 7)) * nblk + (size_t)(p >> 3) * gbpl;
 #pragma unroll 8
-        for (int w = r; w < gbpl; w += G) s1 += q[(size_t)w * NP];
+        for (int w = r; w < gbpl; w += G) s1 += q[w];
       }
       for (int off = G / 2; off > 0; off >>= 1) s1 += __shfl_xor(s1, off);
       if (p < P && r == 0) {
