@@ -100,7 +100,8 @@ __device__ __forceinline__ void xcd_row_tile(int nseg, int nrows, int& seg, int&
 // moments; dq FP32 [K][N], control block dqctl as launch_sweep_inj describes).
 // Occupancy: the FP32 26-variable sweep needs 256 VGPRs + 26 AGPRs at parity 0,
 // one wavefront per SIMD; bounding it to two per SIMD costs 48 B of scratch per lane
-// and was measured 4-5 % faster (at parity 1 the bound spills more and is slower).  The
+// and was measured 4-5 % faster (at parity 1 it spills 72 B per lane and, re-measured on
+// the current kernel, changes nothing: 4.685-4.692 against 4.685-4.687 ms per step).  The
 // FP16/BF16 13-component sweep at parity 1 is bounded to three wavefronts per SIMD (FP16
 // 173 -> 151 VGPRs, no spill): with the XCD-grouped workgroup order of the lane exchange
 // it then runs 12 % (FP16) and 14 % (BF16) faster on 4096^2 than with the row grid, where
