@@ -253,23 +253,31 @@ void build_codec(vlbm_ctx* c) {
 // One step on the context's stream: faces, sweep (with the body, and its move), step + 1.
 vlbm_status vlbm_step_one(vlbm_ctx* c) {
   const int par = (int)(c->step & 1);
+  Grid g = c->g;
+  Body b = c->body;
+  b.t = (double)c->step;
+  if (c->p.body == 2) {
+    hlbm_box(c, b.t, b.box);
+    // the box sweep re-sets no face: a box that reaches the x faces (or the cells whose
+    // moments a zero-gradient x face takes) leaves them to the face pass this step
+    const bool nonempty = b.box[1] > b.box[0] && b.box[3] > b.box[2] && b.box[5] > b.box[4];
+    if (g.bc[0] && nonempty && (b.box[0] <= 1 || b.box[1] >= g.nx - 1)) g.xf_pass = 1;
+  }
+  // bounce-back: every solid cell and every cut link lies in the box of the body's
+  // position at this step (the sweep leaves that box to the bounce-back sweep, unless
+  // it reaches the x faces)
+  if (c->p.body == 1) body_box(c, b.t, b.t, b.box);
   if (c->has_faces) {
-    const hipError_t e = launch_faces(c->L, c->g, c->ph, c->cd, par, c->inflow);
+    const hipError_t e = launch_faces(c->L, g, c->ph, c->cd, par, c->inflow);
     if (e != hipSuccess) return hip_fail(c, e, "face launch");
   }
   if (!c->p.body) {
-    const hipError_t e = launch_sweep(c->L, c->g, c->ph, c->cd, par, c->inflow);
+    const hipError_t e = launch_sweep(c->L, g, c->ph, c->cd, par, c->inflow);
     if (e != hipSuccess) return hip_fail(c, e, "sweep launch");
     ++c->step;
     return VLBM_OK;
   }
-  Body b = c->body;
-  b.t = (double)c->step;
-  if (c->p.body == 2) hlbm_box(c, b.t, b.box);
-  // bounce-back: every solid cell and every cut link lies in the box of the body's
-  // position at this step (the FP16/BF16 sweep leaves that box to the one-cell sweep)
-  if (c->p.body == 1) body_box(c, b.t, b.t, b.box);
-  hipError_t e = launch_sweep_body(c->L, c->g, c->ph, c->cd, par, b, c->p.body, c->inflow);
+  hipError_t e = launch_sweep_body(c->L, g, c->ph, c->cd, par, b, c->p.body, c->inflow);
   if (e != hipSuccess) return hip_fail(c, e, "sweep launch");
   ++c->step;
   if (c->p.body == 2) return VLBM_OK;  // the homogenized body needs no mask

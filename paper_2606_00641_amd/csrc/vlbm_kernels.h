@@ -19,6 +19,7 @@ struct Grid {
   unsigned char* mask;  // body mask per cell (NULL: no body), bits below
   void* sprev;          // Chai source operator: the previous step's source [K][N] in the
                         // compute type (double for FP64 storage, else float); else NULL
+  int xf_pass = 0;      // 1: this step the face pass re-sets the x faces too (fuse_x_faces)
 };
 
 // Body mask bits: solid now, solid before the last move, and for i = 1..6 the
@@ -80,8 +81,12 @@ hipError_t launch_faces(const Launch& L, const Grid& g, const Phys& ph, const Co
 // The sweep itself re-sets the nodes of non-periodic x faces that lie on no other
 // non-periodic face (D3Q7 ideal); it takes the zero-gradient state from the
 // neighbouring lane, which holds cell x = 1 (x = nx - 2) unless nx - 1 starts a new
-// wavefront.  The face pass then handles the y and z faces only.
-__host__ __device__ inline bool fuse_x_faces(const Grid& g) { return g.bc[0] != 0 && g.nx % 64 != 1; }
+// wavefront.  The face pass then handles the y and z faces only.  A step whose body box
+// reaches x <= 1 or x >= nx - 2 sets xf_pass: the cells of the box skip the outside
+// sweep and the box sweep re-sets no face, so the face pass takes the x faces as well.
+__host__ __device__ inline bool fuse_x_faces(const Grid& g) {
+  return g.bc[0] != 0 && g.nx % 64 != 1 && !g.xf_pass;
+}
 
 // Body mask in b.box at time b.t: pass 0 sets the solid bit (and keeps the old one
 // as kWasSolid unless `fresh`), pass 1 the link bits.
