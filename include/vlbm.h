@@ -154,7 +154,9 @@ typedef struct {
    * flux and the Powell source, rho and the pressure are kept (e_tot follows);
    * B_b is the dipole field outside R0 and the uniform 2 m / R0^3 inside (a
    * uniformly magnetised sphere).  No mask, no refill; all cells report moments.
-   * The body must stay clear of the domain faces (it does not wrap). */
+   * The body must stay clear of the domain faces (it does not wrap); with body = 1 a
+   * step whose box of possibly solid or cut cells (the surface-radius bound plus two
+   * cells below and three above) reaches a non-periodic face returns VLBM_ERR_STATE. */
   double body_c0[3], body_v[3], body_R0;
   double body_a[4], body_d[4][3], body_b[4], body_e[4][3];
   double body_m[3];

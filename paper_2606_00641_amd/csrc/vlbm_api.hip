@@ -266,7 +266,17 @@ vlbm_status vlbm_step_one(vlbm_ctx* c) {
   // bounce-back: every solid cell and every cut link lies in the box of the body's
   // position at this step (the sweep leaves that box to the bounce-back sweep, unless
   // it reaches the x faces)
-  if (c->p.body == 1) body_box(c, b.t, b.t, b.box);
+  if (c->p.body == 1) {
+    body_box(c, b.t, b.t, b.box);
+    // the body must stay clear of the non-periodic faces: a face node inside the box
+    // could be solid or have a cut link, which the faces' re-set does not define
+    const int n[3] = {c->p.nx, c->p.ny, c->p.nz};
+    for (int a = 0; a < 3; ++a)
+      if ((g.bc[2 * a] && b.box[2 * a] <= 0) || (g.bc[2 * a + 1] && b.box[2 * a + 1] >= n[a]))
+        return fail(c, VLBM_ERR_STATE,
+                    "step %lld: the bounce-back body's box [%d,%d) x [%d,%d) x [%d,%d) reaches a non-periodic face",
+                    (long long)c->step, b.box[0], b.box[1], b.box[2], b.box[3], b.box[4], b.box[5]);
+  }
   if (c->has_faces) {
     const hipError_t e = launch_faces(c->L, g, c->ph, c->cd, par, c->inflow);
     if (e != hipSuccess) return hip_fail(c, e, "face launch");

@@ -277,20 +277,25 @@ def test_pair_sweep_faces_and_body(vb, storage, ulp, body_x, mode):
     assert np.array_equal(bufs[0], bufs[1]), int(np.count_nonzero(bufs[0] != bufs[1]))
 
 
-@pytest.mark.parametrize("storage,tol,nx", [("f64", 1e-10, 30), ("f32", 1e-5, 30), ("f16", 2e-3, 256)])
-def test_homogenized_body_reaching_the_x_face(vb, storage, tol, nx):
-    """A homogenized body whose box reaches the inflow face (centre x = 3.5): the box's cells
-    skip the outside sweep and the box sweep re-sets no face, so for such steps the face
-    pass takes the x faces.  Every cell against the oracle after 40 steps (FP16 on 256-cell
-    rows, where the two-cell sweep would otherwise run)."""
+@pytest.mark.parametrize("storage,tol,nx,centre", [("f64", 1e-10, 30, (3.5, 10.1, 9.7)),
+                                                   ("f32", 1e-5, 30, (3.5, 10.1, 9.7)),
+                                                   ("f16", 2e-3, 256, (3.5, 10.1, 9.7)),
+                                                   ("f64", 1e-10, 30, (9.3, 2.5, 9.7)),
+                                                   ("f64", 1e-10, 30, (9.3, 10.1, 17.0))])
+def test_homogenized_body_at_the_faces(vb, storage, tol, nx, centre):
+    """A homogenized body whose box reaches the inflow face (centre x = 3.5), or that
+    crosses a zero-gradient y or z face: at the x face the box's cells skip the outside
+    sweep and the box sweep re-sets no face, so for such steps the face pass takes the x
+    faces.  Every cell against the oracle after 40 steps (FP16 on 256-cell rows, where
+    the two-cell sweep would otherwise run)."""
     shape = (nx, 22, 20)
     Qin, _ = synth.inflow_state(mach=0.8, alfven_mach=4.0)
     Q0 = np.broadcast_to(Qin[:, None, None, None], (8,) + shape[::-1]).copy()
     Q0 += 0.3 * (synth.smooth_box_state(shape[::-1], seed=12, amp=0.05, rho=0.0, p=0.0, B0=0.0))
-    body = synth.rough_body((3.5, 10.1, 9.7), (0.08, 0.04, 0.02), 4.6, m=(3.0, -2.0, 1.5), rough=0.12, seed=5)
+    body = synth.rough_body(centre, (0.08, 0.04, 0.02), 4.6, m=(3.0, -2.0, 1.5), rough=0.12, seed=5)
     body["mode"] = 2
     bc = (1, 2, 2, 2, 2, 2)
-    print("case homogenized body at the x face", storage, nx, flush=True)
+    print("case homogenized body at the faces", storage, nx, centre, flush=True)
     sim = vb.Vlbm(vb.make_params(lattice="D3Q7", shape=shape, model="ideal", storage=storage, flux_scale=0.1,
                                  tau=0.7, bc=bc, inflow_Q=Qin, body=body, stream=_stream()))
     sim.vlbm_init_fields(Q0)
@@ -304,6 +309,25 @@ def test_homogenized_body_reaching_the_x_face(vb, storage, tol, nx):
     Qo, _, _ = oracle.moments(op, f)
     err = rel_l2(np.asarray(Qg).reshape(8, -1), Qo, 8)
     assert max(err.values()) < tol, err
+
+
+@pytest.mark.parametrize("centre", [(9.3, 2.5, 9.7), (9.3, 10.1, 17.0), (3.5, 10.1, 9.7)])
+def test_bounce_back_body_at_a_face_is_refused(vb, centre):
+    """The body must stay clear of the non-periodic faces; a bounce-back step whose box of
+    possibly solid or cut cells reaches one (here a y face, a z face, the inflow face)
+    returns VLBM_ERR_STATE instead of stepping."""
+    shape = (30, 22, 20)
+    Qin, _ = synth.inflow_state(mach=0.8, alfven_mach=4.0)
+    Q0 = np.broadcast_to(Qin[:, None, None, None], (8,) + shape[::-1]).copy()
+    body = synth.rough_body(centre, (0.08, 0.04, 0.02), 4.6, m=(3.0, -2.0, 1.5), rough=0.12, seed=5)
+    body["mode"] = 1
+    sim = vb.Vlbm(vb.make_params(lattice="D3Q7", shape=shape, model="ideal", storage="f64", flux_scale=0.1,
+                                 tau=0.7, bc=(1, 2, 2, 2, 2, 2), inflow_Q=Qin, body=body, stream=_stream()))
+    sim.vlbm_init_fields(Q0)
+    with pytest.raises(vb.VlbmError) as ei:
+        sim.vlbm_step(1)
+    assert ei.value.status == -4 and "non-periodic face" in str(ei.value)
+    sim.vlbm_destroy()
 
 
 @pytest.mark.parametrize("storage,tol", [("f64", 1e-10), ("f32", 1e-5)])
