@@ -236,6 +236,55 @@ def run_slab(vlbm, torch, synth, form_steps, only=False):
     return forms
 
 
+RESISTIVE_FAMILIES = {"rho": [0], "m": [1, 2, 3], "E": [4], "B": [5, 6, 7], "G": list(range(8, 17)),
+                      "H": list(range(17, 26))}
+
+
+def run_resistive_storage(vlbm, torch, w, Q, r32, form_steps, err_steps=200):
+    """The benchmark's own workload (resistive 256^3, D3Q7 x 26) in FP16 and BF16 deviation
+    storage: the sweep's MLUPS and GB/s against the FP32 form timed just before (r32), and
+    the error of each field family after err_steps steps against the same run in FP64
+    storage (the GPU's FP64 path, held to the oracle at 1e-10): ||Q - Q_64|| / ||Q_64|| per
+    family (vector families as vectors), FP64 norms on the host of the FP32 moment fields."""
+    stream = torch.cuda.current_stream()
+
+    def moments_after(storage):
+        sim = vlbm.Vlbm(params_for(vlbm, w, storage, stream.cuda_stream))
+        sim.vlbm_init_fields(Q)
+        sim.vlbm_step(err_steps)
+        q, tot = sim.vlbm_moments(f32=True, raise_nonfinite=False)
+        sim.vlbm_destroy()
+        torch.cuda.empty_cache()
+        return q, tot
+
+    log(f"resistive 256^3: FP64 reference run of {err_steps} steps")
+    ref, _ = moments_after("f64")
+    den = {f: float(np.sqrt(sum(np.sum(ref[k].astype(np.float64) ** 2) for k in ks)))
+           for f, ks in RESISTIVE_FAMILIES.items()}
+    out = {"error_steps": err_steps}
+    for st in ("f32", "f16", "bf16"):
+        q, tot = moments_after(st)
+        err = {}
+        for f, ks in RESISTIVE_FAMILIES.items():
+            num = np.sqrt(sum(np.sum((q[k].astype(np.float64) - ref[k]) ** 2) for k in ks))
+            err[f] = float(num / den[f]) if den[f] > 0 else float(num)
+        del q
+        entry = {"rel_l2_vs_fp64": err, "finite": bool(np.all(np.isfinite(tot)) and tot[26 + 4] == 0)}
+        if st != "f32":
+            rr = time_sweep(vlbm, torch, w, Q, st, form_steps, 5)
+            m = rr["ncell"] * form_steps / rr["wall_s"] / 1e6
+            gb = rr["bytes_per_cell"] * rr["ncell"] / (rr["kernel_ms"] * 1e-3) / 1e9
+            entry.update(mlups=round(m, 1), kernel_ms=round(rr["kernel_ms"], 4), bytes_per_cell=rr["bytes_per_cell"],
+                         achieved_GBps=round(gb, 1), frac_of_peak=round(gb / HBM_PEAK_GBPS, 4),
+                         speedup_vs_f32=round(r32["kernel_ms"] / rr["kernel_ms"], 3))
+            log(f"resistive 256^3 {st}: {m:.1f} MLUPS, {gb:.0f} GB/s, error vs FP64 {err}")
+        else:
+            log(f"resistive 256^3 f32: error vs FP64 {err}")
+        out[st] = entry
+    del ref
+    return out
+
+
 def run_models(vlbm, torch, synth, form_steps):
     """The other PDEs through the same sweep, 256^3 periodic, FP32: compressible Euler
     (K = 5, the resistive workload's state without its field) and linear Navier-Cauchy
@@ -463,6 +512,7 @@ def main():
     Q = torch.from_numpy(synth.turbulence_3d(n=256, seed=1, dtype=np.float32)).cuda()
     log("timing", args.steps, "sweeps after", args.warmup, "warmup")
     r = time_sweep(vlbm, torch, w, Q, "f32", args.steps, args.warmup)
+    res_forms = run_resistive_storage(vlbm, torch, w, Q, r, args.form_steps) if not args.no_forms else {}
     del Q
     torch.cuda.empty_cache()
     mlups = r["ncell"] * args.steps / r["wall_s"] / 1e6
@@ -522,6 +572,7 @@ def main():
             "copy_ceiling_GBps": copies,
         },
         "cpu_baseline": cpu,
+        "forms_resistive_256": res_forms or None,
         "forms_slab_512": forms or None,
         "forms_body_768x384x384": body_forms or None,
         "forms_other_models_256": models or None,
