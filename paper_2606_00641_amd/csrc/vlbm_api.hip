@@ -433,6 +433,8 @@ vlbm_status vlbm_create(const vlbm_params* p, vlbm_ctx** out) {
   }
   c->g.f = c->f;
   c->g.stride = c->stride;
+  // 16-bit storage of the 26-variable model: variable pairs share 32-bit elements
+  c->g.pk = (p->model == VLBM_RESISTIVE && (p->storage == VLBM_F16DEV || p->storage == VLBM_BF16DEV)) ? 1 : 0;
   c->g.nx = p->nx;
   c->g.ny = p->ny;
   c->g.nz = p->nz;

@@ -20,7 +20,17 @@ struct Grid {
   void* sprev;          // Chai source operator: the previous step's source [K][N] in the
                         // compute type (double for FP64 storage, else float); else NULL
   int xf_pass = 0;      // 1: this step the face pass re-sets the x faces too (fuse_x_faces)
+  int pk = 0;           // 1: variable pairs packed (16-bit storage of the 26-variable model):
+                        // variables 2p and 2p + 1 of one slot share the 32-bit element of
+                        // plane (p*Q + slot) -- `stride` words per plane, low half 2p
 };
+
+// 16-bit element index of population (variable k, slot, cell): planes (k*Q + slot) of
+// `stride` elements, or with packed pairs planes (k/2*Q + slot) of `stride` 32-bit words.
+__host__ __device__ inline size_t pop_index(const Grid& g, int nq, int k, int slot, unsigned cell) {
+  return g.pk ? ((size_t)((k >> 1) * nq + slot) * (size_t)g.stride + cell) * 2 + (k & 1)
+              : (size_t)(k * nq + slot) * (size_t)g.stride + cell;
+}
 
 // Body mask bits: solid now, solid before the last move, and for i = 1..6 the
 // neighbour x + e_i is solid now (the link i is cut).

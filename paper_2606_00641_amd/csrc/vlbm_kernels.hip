@@ -207,7 +207,7 @@ __global__ __launch_bounds__(256) void k_init(const Grid g, const Phys ph, const
   for (int k = 0; k < K; ++k)
 #pragma unroll
     for (int i = 0; i < NQ; ++i)
-      F[(size_t)(k * NQ + i) * g.stride + c] =
+      F[pop_index(g, NQ, k, i, c)] =
           S::enc(feq_dir<R, D>(Q[k], P[k], i, w0, wi) - gs * (i == 0 ? w0 : wi) * Sv[k], cd, k * NQ + i);
   if (ph.source == 2 && g.sprev) {
 #pragma unroll
@@ -280,7 +280,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_moments(const Grid g, const 
         const unsigned src = (parity == 0 || i == 0) ? (unsigned)c
                              : ((i & 1) ? nm[(i - 1) >> 1] : np[(i - 1) >> 1]);
         const int slot = parity == 0 ? i : opposite(i);
-        const double v = S::dec64(F[(size_t)(k * NQ + slot) * g.stride + src], cd, k * NQ + i);
+        const double v = S::dec64(F[pop_index(g, NQ, k, slot, src)], cd, k * NQ + i);
         q += v;
         constexpr int bx = kBx<MODEL>;
         if (k >= bx && k < bx + D && i > 0 && ((i - 1) >> 1) == k - bx) Jb[k - bx] += (i & 1) ? v : -v;
@@ -464,7 +464,7 @@ __global__ void k_gather(const Grid g, const Codec cd, int parity, int K,
   const unsigned src = (parity == 0 || i == 0) ? (unsigned)c : ((i & 1) ? nm[(i - 1) >> 1] : np[(i - 1) >> 1]);
   const int slot = parity == 0 ? i : opposite(i);
   const T* F = static_cast<const T*>(g.f);
-  out[t] = S::dec64(F[(size_t)(k * NQ + slot) * g.stride + src], cd, k * NQ + i);
+  out[t] = S::dec64(F[pop_index(g, NQ, k, slot, src)], cd, k * NQ + i);
 }
 
 __global__ void k_to_f32(const double* __restrict__ in, float* __restrict__ out, long long n) {

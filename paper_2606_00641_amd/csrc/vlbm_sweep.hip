@@ -167,7 +167,12 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
   (void)own_r;
   const unsigned c = (unsigned)x + (unsigned)g.nx * ((unsigned)y + (unsigned)g.ny * (unsigned)z);
   void* const F = g.f;
-  const size_t pb = (size_t)g.stride * ES;
+  // PK: 16-bit storage of the 26-variable model keeps variables 2p and 2p + 1 of a slot in
+  // one 32-bit element (Grid::pk), so every access moves 4 bytes per lane; both halves
+  // stream in the same direction, so the in-place pattern is unchanged
+  constexpr bool PK = MODEL == 1 && (ST == ST_F16 || ST == ST_BF16) && !XCH;
+  constexpr unsigned EA = PK ? 4u : ES;  // bytes per addressed element
+  const size_t pb = (size_t)g.stride * EA;
   unsigned mk = 0;
   if constexpr (kBB) {
     mk = g.mask[c];
@@ -180,17 +185,33 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
     neighbours<D>(g, x, y, z, c, np, nm);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      np[a] *= ES;
-      nm[a] *= ES;
+      np[a] *= EA;
+      nm[a] *= EA;
     }
   }
-  const unsigned co = c * ES;
+  const unsigned co = c * EA;
 
   R f[K][NQ];
   T raw[XCH ? K : 1][2];
   (void)raw;
+  if constexpr (PK) {
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
+    for (int p = 0; p < K / 2; ++p)
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) {
+        unsigned w;
+        if constexpr (PAR == 0) {
+          w = ld<unsigned>(F, pb, p * NQ + i, co);
+        } else {
+          const unsigned src = (i == 0) ? co : ((i & 1) ? nm[(i - 1) >> 1] : np[(i - 1) >> 1]);
+          w = ld<unsigned>(F, pb, p * NQ + opposite(i), src);
+        }
+        f[2 * p][i] = S::dec((T)(w & 0xffffu), cd, 2 * p * NQ + i);
+        f[2 * p + 1][i] = S::dec((T)(w >> 16), cd, (2 * p + 1) * NQ + i);
+      }
+  }
+#pragma unroll
+  for (int k = 0; k < (PK ? 0 : K); ++k) {
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
       T v;
@@ -351,8 +372,26 @@ __global__ __launch_bounds__(256, (MODEL == 1 && ST == ST_F32 && PAR == 0 && COL
     } else {
       collide<R, D, MODEL, COLL>(f, ph, dl);
     }
+    if constexpr (PK) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
+      for (int p = 0; p < K / 2; ++p)
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+          const unsigned w = (unsigned)S::enc(f[2 * p][i], cd, 2 * p * NQ + i) |
+                             ((unsigned)S::enc(f[2 * p + 1][i], cd, (2 * p + 1) * NQ + i) << 16);
+          if constexpr (PAR == 0) {
+            st<unsigned>(F, pb, p * NQ + opposite(i), co, w);
+          } else {
+            const unsigned dst = (i == 0) ? co : ((i & 1) ? np[(i - 1) >> 1] : nm[(i - 1) >> 1]);
+            if (i == 1 || i == 2)
+              st_shifted<unsigned>(F, pb, p * NQ + i, dst, w);
+            else
+              st<unsigned>(F, pb, p * NQ + i, dst, w);
+          }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < (PK ? 0 : K); ++k) {
 #pragma unroll
       for (int i = 0; i < NQ; ++i) {
         if constexpr (XCH) {

@@ -349,8 +349,14 @@ def test_body_loads_parity(vb, storage, tol, steps):
     oracle.run_bc(op, f, steps)
     o = oracle.body_loads(op, f, steps)
     print(storage, steps, g, o)
-    for a, b in ((g["force"], o["force"]), (g["torque"], o["torque"])):
-        assert np.abs(a - b).max() <= tol * np.abs(b).max(), (a, b)
+    fmax = np.abs(o["force"]).max()
+    assert np.abs(g["force"] - o["force"]).max() <= tol * fmax, (g["force"], o["force"])
+    # the torque is the moment of the surface forces about the centre: it cancels to a
+    # small value, but its rounding is at most the lever arm (the surface-radius bound,
+    # R0 (1 + rough) < 1.2 R0) times the forces' rounding
+    lever = 1.2 * body["R0"]
+    assert np.abs(g["torque"] - o["torque"]).max() <= tol * max(np.abs(o["torque"]).max(), lever * fmax), \
+        (g["torque"], o["torque"])
     assert abs(g["energy"] - o["work"]) <= tol * abs(o["work"])
     assert abs(g["flux"] - o["flux"]) <= tol * o["flux"]
 

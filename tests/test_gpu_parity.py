@@ -495,6 +495,36 @@ def test_resistive_2d_block_sizes_bitwise_equal(vb, storage):
 
 @pytest.mark.parametrize("storage,ulp", [("f16", 2.0 ** -11), ("bf16", 2.0 ** -8)])
 @pytest.mark.parametrize("parity", [0, 1])
+def test_resistive_3d_low_precision_one_step(vb, storage, ulp, parity):
+    """FP16/BF16 storage of the 26-variable system, whose variable pairs share 32-bit
+    elements: one step from the GPU's own pre-step populations against the oracle's
+    collision, every population of a ragged 70 x 10 x 6 box, up to one rounding of the
+    stored deviation (plus FP32 arithmetic)."""
+    w = synth.workload_resistive_3d(n=16, dt_over_tau_M=0.49)
+    shape = (70, 10, 6)
+    w["shape"] = shape
+    Q0 = small_resistive(shape=shape, seed=9)
+    print("case resistive 3D one step", storage, parity, flush=True)
+    sim = vb.Vlbm(gpu_params(vb, w, storage))
+    sim.vlbm_init_fields(Q0)
+    sim.vlbm_step(3 + parity)
+    cells = np.arange(int(np.prod(shape)))
+    op = oracle_params(w)
+    want = oracle_one_step(oracle, op, sim.vlbm_gather_cells, cells, shape, 3)
+    sim.vlbm_step(1)
+    got = sim.vlbm_gather_cells(cells)
+    rest_Q, sigma = sim.vlbm_get_codec()
+    f_rest = oracle.equilibrium(op, rest_Q)
+    wts = np.array([0.25] + [0.125] * 6)
+    sc = sigma[:, None] * wts[None, :]
+    h_want = np.abs(want - f_rest[None]) / sc[None]
+    bound = sc[None] * (2.0 * ulp * h_want + 2.0 ** -24) + 4e-6 * (1.0 + np.abs(want))
+    err = np.abs(got - want)
+    assert np.all(err <= bound), float((err / bound).max())
+
+
+@pytest.mark.parametrize("storage,ulp", [("f16", 2.0 ** -11), ("bf16", 2.0 ** -8)])
+@pytest.mark.parametrize("parity", [0, 1])
 def test_resistive_2d_low_precision_one_step(vb, storage, ulp, parity):
     """FP16/BF16 storage of the 13-component system: one step from the GPU's own
     pre-step populations against the oracle's collision, up to one rounding of the
